@@ -1,0 +1,348 @@
+/*
+ * ncf_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, FP64 CPU implementation of the kernel-weighted
+ * auto/cross-correlation estimator for irregularly sampled series
+ * (the "real-space" estimator of the paper's Appendix B, Algorithms
+ * "CorrSum" and "PairCount", assembled as in "ACF via real-space
+ * kernel-weighted summation" and "CCF via real-space kernel-weighted
+ * summation"; the estimator itself is eq. kernel_estimator of Sec. 2.3).
+ *
+ * It exists to check the GPU library. Only the test suite, the smoke
+ * entry point and the benchmark's CPU-baseline leg may load it. It shares
+ * no code, header or constant with the GPU library: the status codes below
+ * are redefined here on purpose and only mirror the public interface.
+ *
+ * What it computes (series 1 = (t_i, x_i), series 2 = (s_j, y_j)):
+ *   d = (t_i) - (s_j + eps*tau)       (eps = +1 ACF, -1 CCF; Appendix A.2)
+ *   Gaussian kernel  (eq. Gaussian_kernel): weight phi(d) on the window
+ *       t_i >= centre - 6h  and  t_i < centre + 6h   (PairCount, Gaussian)
+ *   Rectangle kernel (PairCount, rectangle): weight 1 on the closed window
+ *       t_i >= centre - h  and  t_i <= centre + h     (h = half-width)
+ *   C(tau) = sum over window pairs of weight * v_i * v_j
+ *   B(tau) = sum over window pairs of weight * w_i * w_j
+ *   b(tau) = sum over window pairs of weight          (effective pair count)
+ *   count  = number of window pairs                   (rectangle only)
+ * with v = w * (x - mean)/sd the standardized values and w the per-sample
+ * weight (1 without errors; 1/err^2 with errors, an extension the paper does
+ * not define -- "parity unpinned" beyond the invariances the tests check).
+ *
+ *   r(tau) = C(tau) / max(B(tau), 1e-16)       (floor of PairCount)
+ *   ACF: c_k = r(tau_k) / r(0)                 (lag-0 normalization, Alg. ACF via NUFFT)
+ *   CCF: c_k = r_xy(tau_k) / sqrt(scale_x * scale_y),
+ *        scale_x = C_xx(0)/max(B_xx(0),1e-16) on (t,x) with eps=+1, same for y
+ *        (Algorithm "CCF via real-space kernel-weighted summation").
+ *
+ * The two-pointer scan follows the paper's PairCount / CorrSum loops: for
+ * each lag the window [lo, hi) only advances as the centre increases. The
+ * rectangle numerator is summed directly over the window (not by prefix
+ * sums), so this file never uses the prefix-sum form the GPU path relies on.
+ * A brute-force all-pairs mode evaluates the same predicates without any
+ * scan.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_OK 0
+#define ORC_E_INVALID_ARG (-1)
+#define ORC_E_UNSORTED (-2)
+#define ORC_E_DEGENERATE (-3)
+#define ORC_E_NOMEM (-4)
+
+#define ORC_GAUSSIAN 0
+#define ORC_RECTANGLE 1
+
+static const double ORC_FLOOR = 1e-16;
+
+/* ---------------------------------------------------------------- checks */
+
+static int check_series(int64_t n, const double* t, const double* x, const double* err) {
+    if (n < 2 || !t || !x) return ORC_E_INVALID_ARG;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!isfinite(t[i]) || !isfinite(x[i])) return ORC_E_INVALID_ARG;
+        if (err && (!isfinite(err[i]) || !(err[i] > 0.0))) return ORC_E_INVALID_ARG;
+    }
+    for (int64_t i = 1; i < n; ++i)
+        if (t[i] < t[i - 1]) return ORC_E_UNSORTED;
+    return ORC_OK;
+}
+
+static int check_lags(int64_t K, const double* lags, double h) {
+    if (K < 0 || (K > 0 && !lags)) return ORC_E_INVALID_ARG;
+    if (!isfinite(h) || !(h > 0.0)) return ORC_E_INVALID_ARG;
+    for (int64_t k = 0; k < K; ++k)
+        if (!isfinite(lags[k])) return ORC_E_INVALID_ARG;
+    return ORC_OK;
+}
+
+/* ----------------------------------------------------- standardization */
+
+/* Mean and standard deviation (ddof 0), weighted by w = 1/err^2 when err is
+ * given; v = w * (x - mean) / sd, w written alongside (all ones without err).
+ * Plain left-to-right FP64 sums. */
+int oracle_standardize(int64_t n, const double* x, const double* err, double* v, double* w) {
+    double sw = 0.0, swx = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double wi = err ? 1.0 / (err[i] * err[i]) : 1.0;
+        w[i] = wi;
+        sw += wi;
+        swx += wi * x[i];
+    }
+    double mean = swx / sw;
+    double swd = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double d = x[i] - mean;
+        swd += w[i] * d * d;
+    }
+    double sd = sqrt(swd / sw);
+    if (!(sd > 0.0) || !isfinite(sd)) return ORC_E_DEGENERATE;
+    for (int64_t i = 0; i < n; ++i) v[i] = w[i] * ((x[i] - mean) / sd);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------ kernel weights */
+
+static double gauss_weight(double d, double h) {
+    /* eq. Gaussian_kernel */
+    return exp(-(d * d) / (2.0 * h * h)) / (h * sqrt(2.0 * M_PI));
+}
+
+/* ------------------------------------------------- scan over one lag */
+
+typedef struct {
+    int kernel, eps;
+    int64_t n_out;
+    const double *s, *v_out, *w_out;
+    int64_t n_win;
+    const double *t, *v_win, *w_win;
+    double h;
+} scan_args;
+
+/* Two-pointer window scan for one lag (PairCount / CorrSum loop body). */
+static void scan_one_lag(const scan_args* a, double tau, double* C, double* B, double* b,
+                         int64_t* count) {
+    double c_acc = 0.0, B_acc = 0.0, b_acc = 0.0;
+    int64_t n_acc = 0;
+    int64_t lo = 0, hi = 0;
+    const double e = (double)a->eps;
+    if (a->kernel == ORC_GAUSSIAN) {
+        const double W = 6.0 * a->h;
+        for (int64_t j = 0; j < a->n_out; ++j) {
+            double centre = a->s[j] + e * tau;
+            while (lo < a->n_win && a->t[lo] < centre - W) lo++;
+            while (hi < a->n_win && a->t[hi] < centre + W) hi++;
+            for (int64_t i = lo; i < hi; ++i) {
+                double wt = gauss_weight(a->t[i] - centre, a->h);
+                c_acc += wt * a->v_win[i] * a->v_out[j];
+                B_acc += wt * a->w_win[i] * a->w_out[j];
+                b_acc += wt;
+                n_acc += 1;
+            }
+        }
+    } else {
+        const double hw = a->h;
+        for (int64_t j = 0; j < a->n_out; ++j) {
+            double centre = a->s[j] + e * tau;
+            while (lo < a->n_win && a->t[lo] < centre - hw) lo++;
+            if (hi < lo) hi = lo;
+            while (hi < a->n_win && a->t[hi] <= centre + hw) hi++;
+            for (int64_t i = lo; i < hi; ++i) {
+                c_acc += a->v_win[i] * a->v_out[j];
+                B_acc += a->w_win[i] * a->w_out[j];
+                b_acc += 1.0;
+                n_acc += 1;
+            }
+        }
+    }
+    *C = c_acc;
+    *B = B_acc;
+    *b = b_acc;
+    *count = n_acc;
+}
+
+/* All-pairs evaluation of the same window predicates (no scan). */
+static void brute_one_lag(const scan_args* a, double tau, double* C, double* B, double* b,
+                          int64_t* count) {
+    double c_acc = 0.0, B_acc = 0.0, b_acc = 0.0;
+    int64_t n_acc = 0;
+    const double e = (double)a->eps;
+    for (int64_t j = 0; j < a->n_out; ++j) {
+        double centre = a->s[j] + e * tau;
+        for (int64_t i = 0; i < a->n_win; ++i) {
+            double ti = a->t[i];
+            double wt;
+            if (a->kernel == ORC_GAUSSIAN) {
+                const double W = 6.0 * a->h;
+                if (ti < centre - W || !(ti < centre + W)) continue;
+                wt = gauss_weight(ti - centre, a->h);
+            } else {
+                if (ti < centre - a->h || !(ti <= centre + a->h)) continue;
+                wt = 1.0;
+            }
+            c_acc += wt * a->v_win[i] * a->v_out[j];
+            B_acc += wt * a->w_win[i] * a->w_out[j];
+            b_acc += wt;
+            n_acc += 1;
+        }
+    }
+    *C = c_acc;
+    *B = B_acc;
+    *b = b_acc;
+    *count = n_acc;
+}
+
+/* Window sums for every lag; lags distributed over threads as the paper's
+ * parallel-for over k. Outputs are raw (not floored). */
+int oracle_window_sums(int kernel, int eps, int64_t n_out, const double* s, const double* v_out,
+                       const double* w_out, int64_t n_win, const double* t, const double* v_win,
+                       const double* w_win, int64_t K, const double* lags, double h, double* C,
+                       double* B, double* b, int64_t* count, int nthreads, int brute) {
+    if (kernel != ORC_GAUSSIAN && kernel != ORC_RECTANGLE) return ORC_E_INVALID_ARG;
+    if (eps != 1 && eps != -1) return ORC_E_INVALID_ARG;
+    scan_args a = {kernel, eps, n_out, s, v_out, w_out, n_win, t, v_win, w_win, h};
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t k = 0; k < K; ++k) {
+        if (brute)
+            brute_one_lag(&a, lags[k], &C[k], &B[k], &b[k], &count[k]);
+        else
+            scan_one_lag(&a, lags[k], &C[k], &B[k], &b[k], &count[k]);
+    }
+    (void)nthreads;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------ estimators */
+
+static double floor_b(double v) { return v > ORC_FLOOR ? v : ORC_FLOOR; }
+
+int oracle_acf(int64_t n, const double* t, const double* x, const double* err, int64_t K,
+               const double* lags, int kernel, double h, double* c, double* b_out,
+               int64_t* count_out, int nthreads, int brute) {
+    int st = check_series(n, t, x, err);
+    if (st) return st;
+    st = check_lags(K, lags, h);
+    if (st) return st;
+    if (kernel != ORC_GAUSSIAN && kernel != ORC_RECTANGLE) return ORC_E_INVALID_ARG;
+
+    double* v = malloc(sizeof(double) * n);
+    double* w = malloc(sizeof(double) * n);
+    double* ev = malloc(sizeof(double) * (K + 1));
+    double* C = malloc(sizeof(double) * (K + 1));
+    double* B = malloc(sizeof(double) * (K + 1));
+    double* bb = malloc(sizeof(double) * (K + 1));
+    int64_t* cnt = malloc(sizeof(int64_t) * (K + 1));
+    if (!v || !w || !ev || !C || !B || !bb || !cnt) {
+        st = ORC_E_NOMEM;
+        goto done;
+    }
+    st = oracle_standardize(n, x, err, v, w);
+    if (st) goto done;
+    /* evaluation lags (0, tau_1, ..., tau_K): lag 0 is prepended */
+    ev[0] = 0.0;
+    for (int64_t k = 0; k < K; ++k) ev[k + 1] = lags[k];
+    oracle_window_sums(kernel, +1, n, t, v, w, n, t, v, w, K + 1, ev, h, C, B, bb, cnt, nthreads,
+                       brute);
+    double r0 = C[0] / floor_b(B[0]);
+    if (!(r0 > 0.0) || !isfinite(r0)) {
+        for (int64_t k = 0; k < K; ++k) {
+            c[k] = NAN;
+            if (b_out) b_out[k] = floor_b(bb[k + 1]);
+            if (count_out) count_out[k] = cnt[k + 1];
+        }
+        st = ORC_E_DEGENERATE;
+        goto done;
+    }
+    for (int64_t k = 0; k < K; ++k) {
+        double r = C[k + 1] / floor_b(B[k + 1]);
+        c[k] = r / r0;
+        if (b_out) b_out[k] = floor_b(bb[k + 1]);
+        if (count_out) count_out[k] = cnt[k + 1];
+    }
+done:
+    free(v);
+    free(w);
+    free(ev);
+    free(C);
+    free(B);
+    free(bb);
+    free(cnt);
+    return st;
+}
+
+int oracle_ccf(int64_t nx, const double* t, const double* x, const double* ex, int64_t ny,
+               const double* s, const double* y, const double* ey, int64_t K, const double* lags,
+               int kernel, double h, double* c, double* b_out, int64_t* count_out, int nthreads,
+               int brute) {
+    int st = check_series(nx, t, x, ex);
+    if (st) return st;
+    st = check_series(ny, s, y, ey);
+    if (st) return st;
+    st = check_lags(K, lags, h);
+    if (st) return st;
+    if (kernel != ORC_GAUSSIAN && kernel != ORC_RECTANGLE) return ORC_E_INVALID_ARG;
+
+    double *vx = malloc(sizeof(double) * nx), *wx = malloc(sizeof(double) * nx);
+    double *vy = malloc(sizeof(double) * ny), *wy = malloc(sizeof(double) * ny);
+    double* C = malloc(sizeof(double) * (K + 1));
+    double* B = malloc(sizeof(double) * (K + 1));
+    double* bb = malloc(sizeof(double) * (K + 1));
+    int64_t* cnt = malloc(sizeof(int64_t) * (K + 1));
+    if (!vx || !wx || !vy || !wy || !C || !B || !bb || !cnt) {
+        st = ORC_E_NOMEM;
+        goto done;
+    }
+    st = oracle_standardize(nx, x, ex, vx, wx);
+    if (st) goto done;
+    st = oracle_standardize(ny, y, ey, vy, wy);
+    if (st) goto done;
+
+    /* cross sums: outer array = series 2 (s), window array = series 1 (t), eps = -1 */
+    if (K > 0)
+        oracle_window_sums(kernel, -1, ny, s, vy, wy, nx, t, vx, wx, K, lags, h, C, B, bb, cnt,
+                           nthreads, brute);
+    /* lag-0 scales of each series on itself, eps = +1 */
+    double zero = 0.0, Cs, Bs, bs;
+    int64_t ns;
+    oracle_window_sums(kernel, +1, nx, t, vx, wx, nx, t, vx, wx, 1, &zero, h, &Cs, &Bs, &bs, &ns,
+                       nthreads, brute);
+    double scale_x = Cs / floor_b(Bs);
+    oracle_window_sums(kernel, +1, ny, s, vy, wy, ny, s, vy, wy, 1, &zero, h, &Cs, &Bs, &bs, &ns,
+                       nthreads, brute);
+    double scale_y = Cs / floor_b(Bs);
+    double prod = scale_x * scale_y;
+    int degenerate = !(prod > 0.0) || !isfinite(prod);
+    double scale = degenerate ? NAN : sqrt(prod);
+    for (int64_t k = 0; k < K; ++k) {
+        double r = C[k] / floor_b(B[k]);
+        c[k] = degenerate ? NAN : r / scale;
+        if (b_out) b_out[k] = floor_b(bb[k]);
+        if (count_out) count_out[k] = cnt[k];
+    }
+    if (degenerate) st = ORC_E_DEGENERATE;
+done:
+    free(vx);
+    free(wx);
+    free(vy);
+    free(wy);
+    free(C);
+    free(B);
+    free(bb);
+    free(cnt);
+    return st;
+}
+
+int oracle_max_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

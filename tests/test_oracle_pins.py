@@ -1,0 +1,356 @@
+"""Pins for the FP64 CPU oracle (no GPU).
+
+Each test fixes the oracle against something other than itself: brute force
+on tiny inputs, the textbook regular-grid estimator (eq. acf_regular), exact
+pair counts n - |k|, closed-form sums, hand-evaluated cases, identities and
+invariances of the estimator (eq. kernel_estimator), and statistical truths
+of processes with known correlation functions (Sec. 3.1).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2609_03866_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _phi(d, h):
+    return math.exp(-d * d / (2 * h * h)) / (h * math.sqrt(2 * math.pi))
+
+
+def _std(x):
+    x = np.asarray(x, float)
+    return (x - x.mean()) / x.std()
+
+
+# ------------------------------------------------------------ P1 brute force
+
+def _random_series(rng, n, dup_frac=0.2, scale=1.0):
+    t = np.sort(np.round(rng.exponential(scale, n).cumsum() * 4) / 4)  # quarter grid -> ties
+    # force exact duplicates
+    k = int(dup_frac * n)
+    idx = rng.integers(1, n, size=k)
+    t[idx] = t[idx - 1]
+    t = np.sort(t)
+    x = rng.normal(size=n)
+    return t, x
+
+
+@pytest.mark.parametrize("kernel", ["gaussian", "rectangle"])
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_scan_equals_brute_force_acf(kernel, seed):
+    rng = np.random.default_rng(seed)
+    t, x = _random_series(rng, 250)
+    lags = np.concatenate([[0.0, 0.25, -0.25, 1.0, -1.0, 2.5, 7.75], rng.uniform(-20, 20, 20)])
+    h = 0.5 if kernel == "rectangle" else 0.3
+    st1, c1, b1, n1 = O.acf(t, x, lags, kernel, h)
+    st2, c2, b2, n2 = O.acf(t, x, lags, kernel, h, brute=True)
+    assert st1 == st2 == 0
+    np.testing.assert_array_equal(n1, n2)
+    np.testing.assert_allclose(b1, b2, rtol=1e-13, atol=0)
+    np.testing.assert_allclose(c1, c2, rtol=1e-12, atol=1e-13)
+
+
+@pytest.mark.parametrize("kernel", ["gaussian", "rectangle"])
+@pytest.mark.parametrize("seed", [3, 4])
+def test_scan_equals_brute_force_ccf(kernel, seed):
+    rng = np.random.default_rng(seed)
+    t, x = _random_series(rng, 200)
+    s, y = _random_series(rng, 300, scale=0.7)
+    lags = np.concatenate([[0.0, 0.5, -0.5, 3.0], rng.uniform(-30, 30, 20)])
+    h = 0.5 if kernel == "rectangle" else 0.4
+    st1, c1, b1, n1 = O.ccf(t, x, s, y, lags, kernel, h)
+    st2, c2, b2, n2 = O.ccf(t, x, s, y, lags, kernel, h, brute=True)
+    assert st1 == st2 == 0
+    np.testing.assert_array_equal(n1, n2)
+    np.testing.assert_allclose(b1, b2, rtol=1e-13, atol=0)
+    np.testing.assert_allclose(c1, c2, rtol=1e-12, atol=1e-13)
+
+
+# ----------------------------------------- P2 regular grid vs textbook ACF
+
+def _textbook_acf(x, k):
+    """eq. acf_regular with the unbiased pair-count normalization that the
+    kernel estimator reaches on a regular grid: sum_t x_t x_{t+k} / (n - k)
+    over sum_t x_t^2 / n, x standardized."""
+    v = _std(x)
+    n = v.size
+    k = abs(k)
+    return (np.dot(v[: n - k], v[k:]) / (n - k)) / (np.dot(v, v) / n)
+
+
+@pytest.mark.parametrize("kernel,h", [("rectangle", 0.5), ("gaussian", 0.15)])
+def test_regular_grid_matches_textbook(kernel, h):
+    rng = np.random.default_rng(11)
+    n = 500
+    t = np.arange(n, dtype=float)
+    x = rng.normal(size=n).cumsum() * 0.1 + rng.normal(size=n)
+    lags = np.arange(-40.0, 41.0)
+    st, c, b, cnt = O.acf(t, x, lags, kernel, h)
+    assert st == 0
+    want = np.array([_textbook_acf(x, int(k)) for k in lags])
+    np.testing.assert_allclose(c, want, rtol=1e-12, atol=1e-13)
+    exp_count = n - np.abs(lags).astype(int)
+    np.testing.assert_array_equal(cnt, exp_count)
+    if kernel == "gaussian":
+        np.testing.assert_allclose(b, exp_count * _phi(0.0, h), rtol=1e-13)
+    else:
+        np.testing.assert_array_equal(b, exp_count.astype(float))
+
+
+# --------------------------------------------- P3 Gaussian b closed form
+
+def test_gaussian_pair_count_closed_form_regular_grid():
+    n, h = 300, 0.7
+    t = np.arange(n, dtype=float)
+    x = np.random.default_rng(5).normal(size=n)
+    lags = np.array([0.0, 0.3, 1.37, -2.6, 10.1, 55.55])
+    st, c, b, cnt = O.acf(t, x, lags, "gaussian", h)
+    assert st == 0
+    for k, tau in enumerate(lags):
+        want = 0.0
+        for m in range(-n + 1, n):
+            d = m - tau
+            if -6 * h <= d < 6 * h:
+                want += (n - abs(m)) * _phi(d, h)
+        assert b[k] == pytest.approx(want, rel=1e-13)
+
+
+# ------------------------------------------------ P4 identities
+
+def test_identities():
+    rng = np.random.default_rng(7)
+    t = np.sort(rng.uniform(0, 400, 600))
+    x = rng.normal(size=600).cumsum()
+    s = np.sort(rng.uniform(0, 400, 500))
+    y = rng.normal(size=500).cumsum()
+    lags = rng.uniform(-30, 30, 25)
+    for kern, h in (("gaussian", 0.6), ("rectangle", 0.6)):
+        st, c0, _, _ = O.acf(t, x, np.array([0.0]), kern, h)
+        assert st == 0 and c0[0] == pytest.approx(1.0, abs=1e-15)
+        _, cp, bp, np_ = O.acf(t, x, lags, kern, h)
+        _, cm, bm, nm = O.acf(t, x, -lags, kern, h)
+        np.testing.assert_allclose(cp, cm, rtol=1e-11, atol=1e-12)
+        np.testing.assert_array_equal(np_, nm)
+        _, cxy, bxy, nxy = O.ccf(t, x, s, y, lags, kern, h)
+        _, cyx, byx, nyx = O.ccf(s, y, t, x, -lags, kern, h)
+        np.testing.assert_allclose(cxy, cyx, rtol=1e-11, atol=1e-12)
+        np.testing.assert_allclose(bxy, byx, rtol=1e-12)
+        np.testing.assert_array_equal(nxy, nyx)
+        _, cxx, bxx, nxx = O.ccf(t, x, t, x, lags, kern, h)
+        _, cacf, bacf, nacf = O.acf(t, x, lags, kern, h)
+        np.testing.assert_allclose(cxx, cacf, rtol=1e-11, atol=1e-12)
+        np.testing.assert_array_equal(nxx, nacf)
+
+
+# ----------------------------------------------- P5 invariances
+
+@pytest.mark.parametrize("kernel", ["gaussian", "rectangle"])
+def test_affine_value_invariance(kernel):
+    rng = np.random.default_rng(8)
+    t = np.sort(rng.uniform(0, 300, 400))
+    x = rng.normal(size=400).cumsum()
+    lags = np.linspace(-20, 20, 33)
+    _, c1, b1, n1 = O.acf(t, x, lags, kernel, 0.8)
+    _, c2, b2, n2 = O.acf(t, 3.7 * x - 12.5, lags, kernel, 0.8)
+    np.testing.assert_allclose(c1, c2, rtol=1e-11, atol=1e-12)
+    np.testing.assert_array_equal(b1, b2)
+
+
+@pytest.mark.parametrize("kernel", ["gaussian", "rectangle"])
+@pytest.mark.parametrize("p", [-3, 5])
+def test_power_of_two_time_scaling_is_bitwise(kernel, p):
+    rng = np.random.default_rng(9)
+    t = np.sort(rng.uniform(0, 300, 400))
+    x = rng.normal(size=400)
+    s = np.sort(rng.uniform(0, 300, 350))
+    y = rng.normal(size=350)
+    lags = rng.uniform(-25, 25, 30)
+    h = 0.9
+    f = 2.0 ** p
+    _, c1, b1, n1 = O.ccf(t, x, s, y, lags, kernel, h)
+    _, c2, b2, n2 = O.ccf(t * f, x, s * f, y, lags * f, kernel, h * f)
+    np.testing.assert_array_equal(n1, n2)
+    np.testing.assert_array_equal(c1, c2)
+    if kernel == "gaussian":
+        np.testing.assert_array_equal(b1 / f, b2)
+
+
+def test_integer_time_shift_is_bitwise():
+    rng = np.random.default_rng(10)
+    t = np.sort(rng.integers(0, 2000, 500)).astype(float) / 4.0  # dyadic times
+    x = rng.normal(size=500)
+    lags = np.arange(-16, 17) / 4.0
+    for kern in ("gaussian", "rectangle"):
+        _, c1, b1, n1 = O.acf(t, x, lags, kern, 0.75)
+        _, c2, b2, n2 = O.acf(t + 4096.0, x, lags, kern, 0.75)
+        np.testing.assert_array_equal(c1, c2)
+        np.testing.assert_array_equal(b1, b2)
+        np.testing.assert_array_equal(n1, n2)
+
+
+# ----------------------------------------------- P6 tiny closed forms
+
+def test_golden_tiny_rectangle():
+    rows = []
+    with open(os.path.join(GOLDEN, "tiny_acf_rectangle.txt")) as f:
+        for line in f:
+            if line.startswith("#") or line.startswith("lag"):
+                continue
+            lag, num, den, cnt = line.strip().split(",")
+            rows.append((float(lag), float(num) / float(den), int(cnt)))
+    t = np.array([0.0, 1.0, 3.0])
+    x = np.array([1.0, -1.0, 2.0])
+    lags = np.array([r[0] for r in rows])
+    st, c, b, cnt = O.acf(t, x, lags, "rectangle", 0.5)
+    assert st == 0
+    np.testing.assert_allclose(c, [r[1] for r in rows], rtol=1e-14, atol=1e-15)
+    np.testing.assert_array_equal(cnt, [r[2] for r in rows])
+    assert b[-1] == 1e-16  # empty window: floored pair count
+
+
+def test_tiny_gaussian_hand_sum():
+    # two samples, t = (0, 1), x = (1, -1): standardized v = (1, -1)
+    h = 0.8
+    t = np.array([0.0, 1.0])
+    x = np.array([1.0, -1.0])
+    tau = 0.4
+    st, c, b, _ = O.acf(t, x, np.array([tau]), "gaussian", h)
+    assert st == 0
+    # pairs (i, j) with d = t_i - t_j - tau, all within 6h
+    pairs = [(0, 0), (1, 1), (0, 1), (1, 0)]
+    v = [1.0, -1.0]
+    num = sum(_phi(t[i] - t[j] - tau, h) * v[i] * v[j] for i, j in pairs)
+    den = sum(_phi(t[i] - t[j] - tau, h) for i, j in pairs)
+    r0 = (2 * _phi(0, h) - 2 * _phi(1, h)) / (2 * _phi(0, h) + 2 * _phi(1, h))
+    assert b[0] == pytest.approx(den, rel=1e-14)
+    assert c[0] == pytest.approx((num / den) / r0, rel=1e-13)
+
+
+# ----------------------------------------------- P7 regular sinusoid
+
+def _sum_cos(m, a, b):
+    """sum_{t=0}^{m-1} cos(a t + b), closed form."""
+    if m <= 0:
+        return 0.0
+    return math.sin(m * a / 2) * math.cos(b + (m - 1) * a / 2) / math.sin(a / 2)
+
+
+def test_regular_sinusoid_exact():
+    n, P, ph = 400, 37.3, 0.9
+    a = 2 * math.pi / P
+    t = np.arange(n, dtype=float)
+    x = np.cos(a * t + ph)
+    mu = _sum_cos(n, a, ph) / n
+    sxx = 0.5 * n + 0.5 * _sum_cos(n, 2 * a, 2 * ph)
+    var = sxx / n - mu * mu
+    lags = np.arange(0.0, 60.0)
+    st, c, _, _ = O.acf(t, x, lags, "rectangle", 0.5)
+    assert st == 0
+    for k in range(60):
+        m = n - k
+        # sum_{t<m} cos(at+b) cos(a(t+k)+b) = 1/2 sum [cos(ak) + cos(2at + ak + 2b)]
+        sxy = 0.5 * m * math.cos(a * k) + 0.5 * _sum_cos(m, 2 * a, a * k + 2 * ph)
+        s_lo = _sum_cos(m, a, ph)
+        s_hi = _sum_cos(m, a, ph + a * k)
+        cov = (sxy - mu * (s_lo + s_hi) + m * mu * mu) / m
+        assert c[k] == pytest.approx(cov / var, rel=1e-10, abs=1e-11)
+
+
+# ----------------------------------------------- P8 statistical truths
+
+def test_statistical_sinusoid_and_ou():
+    taus = np.array([5.0, 10.0, 20.0, 40.0])
+    P = 36.5
+    cs, co = [], []
+    for seed in range(12):
+        rng = np.random.default_rng(100 + seed)
+        t = synth.exp_gap_times(rng, 3000, 1.0)
+        xs = np.cos(2 * math.pi * t / P + rng.uniform(0, 2 * math.pi))
+        cs.append(O.acf(t, xs, taus, "gaussian", 0.25)[1])
+        xo = synth.ou_at_times(rng, t, 10.0)
+        co.append(O.acf(t, xo, taus, "gaussian", 0.25)[1])
+    cs, co = np.mean(cs, 0), np.mean(co, 0)
+    np.testing.assert_allclose(cs, np.cos(2 * math.pi * taus / P), atol=0.03)
+    np.testing.assert_allclose(co, np.exp(-taus / 10.0), atol=0.05)
+
+
+def test_ccf_sign_convention_peak_at_delay():
+    # y lags x by +40 d: the CCF peaks at +40 (Appendix A, sign convention)
+    d = synth.c2(seed=21, n=6000)
+    lags = np.arange(-100.0, 101.0, 2.0)
+    st, c, _, _ = O.ccf(d["t"], d["x"], d["s"], d["y"], lags, "gaussian", 0.5)
+    assert st == 0
+    assert abs(lags[np.argmax(c)] - 40.0) <= 4.0
+    assert c.max() > 0.7
+
+
+# ----------------------------------------------- P9 weighted mode
+
+def test_weighted_constant_errors_equal_unweighted():
+    rng = np.random.default_rng(12)
+    t = np.sort(rng.uniform(0, 200, 300))
+    x = rng.normal(size=300)
+    lags = np.linspace(-10, 10, 21)
+    for kern in ("gaussian", "rectangle"):
+        _, c1, b1, n1 = O.acf(t, x, lags, kern, 0.7)
+        _, c2, b2, n2 = O.acf(t, x, lags, kern, 0.7, err=np.full(300, 0.37))
+        np.testing.assert_allclose(c1, c2, rtol=1e-12, atol=1e-13)
+        np.testing.assert_allclose(b1, b2, rtol=1e-14)
+
+
+def test_weighted_integer_weights_equal_duplicated_samples():
+    rng = np.random.default_rng(13)
+    n = 150
+    t = np.sort(rng.uniform(0, 100, n))
+    x = rng.normal(size=n)
+    m = rng.integers(1, 4, size=n)  # multiplicities
+    err = 1.0 / np.sqrt(m)  # w = 1/err^2 = m
+    td = np.repeat(t, m)
+    xd = np.repeat(x, m)
+    s = np.sort(rng.uniform(0, 100, 120))
+    y = rng.normal(size=120)
+    lags = np.linspace(-8, 8, 17)
+    for kern in ("gaussian", "rectangle"):
+        _, cw, _, _ = O.acf(t, x, lags, kern, 0.9, err=err)
+        _, cd, _, _ = O.acf(td, xd, lags, kern, 0.9)
+        np.testing.assert_allclose(cw, cd, rtol=1e-11, atol=1e-12)
+        _, cw2, _, _ = O.ccf(t, x, s, y, lags, kern, 0.9, ex=err)
+        _, cd2, _, _ = O.ccf(td, xd, s, y, lags, kern, 0.9)
+        np.testing.assert_allclose(cw2, cd2, rtol=1e-11, atol=1e-12)
+
+
+def test_weighted_tiny_weight_drops_sample():
+    rng = np.random.default_rng(14)
+    n = 120
+    t = np.sort(rng.uniform(0, 80, n))
+    x = rng.normal(size=n)
+    err = np.ones(n)
+    err[37] = 1e7  # weight 1e-14
+    keep = np.arange(n) != 37
+    lags = np.linspace(-6, 6, 13)
+    _, cw, _, _ = O.acf(t, x, lags, "gaussian", 0.8, err=err)
+    _, cd, _, _ = O.acf(t[keep], x[keep], lags, "gaussian", 0.8)
+    np.testing.assert_allclose(cw, cd, atol=1e-9)
+
+
+# ----------------------------------------------- status codes
+
+def test_status_codes():
+    t = np.arange(10.0)
+    x = np.arange(10.0) % 3
+    lags = np.arange(3.0)
+    assert O.acf(t[::-1].copy(), x, lags, "g", 0.5)[0] == O.E_UNSORTED
+    xb = x.copy()
+    xb[3] = np.nan
+    assert O.acf(t, xb, lags, "g", 0.5)[0] == O.E_INVALID_ARG
+    assert O.acf(t, np.ones(10), lags, "g", 0.5)[0] == O.E_DEGENERATE
+    assert O.acf(t, x, lags, "g", 0.0)[0] == O.E_INVALID_ARG
+    assert O.acf(t, x, lags, "g", 0.5, err=np.zeros(10))[0] == O.E_INVALID_ARG
+    tt = t.copy()
+    tt[4] = tt[3]  # ties are allowed
+    assert O.acf(tt, x, lags, "r", 0.5)[0] == 0
