@@ -1,0 +1,282 @@
+"""Benchmark of the kernel-weighted correlation hot path on one MI355X.
+
+Default workload (``--workload c2``): the CCF of two irregular series of
+1e5 samples each with 401 lags over [-200, 200] d, Gaussian and rectangle
+kernels, mixed precision (FP32 spreading / FFT / kernel weights with FP64
+positions, phases, moments, prefix sums and accumulators). One step is one
+Gaussian CCF plus one rectangle CCF through the C ABI with the inputs
+resident in HBM. The metric is n*K lag-pairs per second with n = nx + ny
+per CCF (the paper's O((n1 + n2) K) unit of work).
+
+Other workloads (``--workload c1|c3|c4|c5``) are reported the same way and
+add series/s for the batched ones.
+
+Prints one JSON line. ``roofline`` describes the kernel with the largest
+share of GPU time, timed with HIP events on the stream the library
+launches on; ``cpu_baseline`` times the FP64 CPU oracle on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("n·K lag-pairs/s + batched series/s, mixed vs FP64 GPU path at "
+          "|ΔACF|≤1e-5")
+HBM_PEAK = 8.0e12            # B/s, MI355X
+VALU_PEAK = 256 * 64 * 2.4e9  # lane-ops/s: 256 CUs x 4 SIMD16 x 2.4 GHz (non-packed issue)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_workload(name):
+    from paper_2609_03866_amd import synth
+    if name == "c1":
+        return [synth.c1()]
+    if name == "c2":
+        return [synth.c2(kernel="gaussian"), synth.c2(kernel="rectangle")]
+    if name == "c3":
+        return [synth.c3()]
+    if name == "c4":
+        return [synth.c4()]
+    if name == "c5":
+        return [synth.c5()]
+    raise SystemExit(f"unknown workload {name}")
+
+
+def lag_pairs(d):
+    K = d["lags"].size
+    if d["kind"] == "acf":
+        return d["t"].size * K
+    if d["kind"] == "ccf":
+        return (d["t"].size + d["s"].size) * K
+    if d["kind"] == "acf_batch":
+        return d["t"].size * K
+    return (d["t"].size + d["s"].size) * K
+
+
+def n_series(d):
+    if d["kind"] == "acf_batch":
+        return d["offs"].size - 1
+    if d["kind"] == "ccf_batch":
+        return d["offx"].size - 1
+    return 1
+
+
+def to_dev(d):
+    import torch
+    dev = torch.device("cuda:0")
+    out = dict(d)
+    for k in ("t", "x", "s", "y", "lags", "err"):
+        if d.get(k) is not None:
+            out[k] = torch.as_tensor(np.ascontiguousarray(d[k], dtype=np.float64), device=dev)
+    return out
+
+
+def run_one(d, precision="mixed", method="auto"):
+    from paper_2609_03866_amd import ncf
+    kw = dict(precision=precision, method=method, with_count=True)
+    if d["kind"] == "acf":
+        return ncf.acf(d["t"], d["x"], d["lags"], d["kernel"], d["h"], err=d.get("err"), **kw)
+    if d["kind"] == "ccf":
+        return ncf.ccf(d["t"], d["x"], d["s"], d["y"], d["lags"], d["kernel"], d["h"], **kw)
+    if d["kind"] == "acf_batch":
+        return ncf.acf_batch(d["offs"], d["t"], d["x"], d["lags"], d["kernel"], d["h"],
+                             err=d.get("err"), **kw)
+    return ncf.ccf_batch(d["offx"], d["t"], d["x"], d["offy"], d["s"], d["y"], d["lags"],
+                         d["kernel"], d["h"], **kw)
+
+
+def oracle_subset(d, max_series):
+    """The oracle on the whole workload (single problems) or on its first
+    ``max_series`` series (batches). Returns (c list, count list, lag-pairs, seconds)."""
+    from oracle import oracle as O
+    t0 = time.perf_counter()
+    cs, ns, work = [], [], 0
+    if d["kind"] == "acf":
+        st, c, b, n = O.acf(d["t"], d["x"], d["lags"], d["kernel"], d["h"], err=d.get("err"))
+        cs, ns, work = [c], [n], lag_pairs(d)
+    elif d["kind"] == "ccf":
+        st, c, b, n = O.ccf(d["t"], d["x"], d["s"], d["y"], d["lags"], d["kernel"], d["h"])
+        cs, ns, work = [c], [n], lag_pairs(d)
+    elif d["kind"] == "acf_batch":
+        o = d["offs"]
+        for i in range(min(max_series, o.size - 1)):
+            sl = slice(o[i], o[i + 1])
+            st, c, b, n = O.acf(d["t"][sl], d["x"][sl], d["lags"], d["kernel"], d["h"][i],
+                                err=None if d.get("err") is None else d["err"][sl])
+            cs.append(c)
+            ns.append(n)
+            work += (o[i + 1] - o[i]) * d["lags"].size
+    else:
+        ox, oy = d["offx"], d["offy"]
+        for i in range(min(max_series, ox.size - 1)):
+            sx, sy = slice(ox[i], ox[i + 1]), slice(oy[i], oy[i + 1])
+            st, c, b, n = O.ccf(d["t"][sx], d["x"][sx], d["s"][sy], d["y"][sy], d["lags"],
+                                d["kernel"], d["h"][i])
+            cs.append(c)
+            ns.append(n)
+            work += (ox[i + 1] - ox[i] + oy[i + 1] - oy[i]) * d["lags"].size
+    return cs, ns, work, time.perf_counter() - t0
+
+
+def max_dc(gpu_c, orc_cs):
+    g = np.asarray(gpu_c.cpu() if hasattr(gpu_c, "cpu") else gpu_c)
+    g = g.reshape(len(orc_cs), -1) if g.ndim == 1 and len(orc_cs) > 1 else g.reshape(
+        -1, orc_cs[0].size)
+    return float(max(np.max(np.abs(g[i] - orc_cs[i])) for i in range(len(orc_cs))))
+
+
+def counts_equal(gpu_n, orc_ns):
+    g = np.asarray(gpu_n.cpu() if hasattr(gpu_n, "cpu") else gpu_n).reshape(-1, orc_ns[0].size)
+    return bool(all(np.array_equal(g[i], orc_ns[i]) for i in range(len(orc_ns))))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU path")
+    ap.add_argument("--oracle-series", type=int, default=64)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                          "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2609_03866_amd import ncf
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    ncf.lib()
+
+    log(f"[bench] generating workload {args.workload}")
+    host = make_workload(args.workload)
+    devs = [to_dev(d) for d in host]
+    work = sum(lag_pairs(d) for d in host)
+    nser = sum(n_series(d) for d in host)
+
+    def step(precision="mixed", method="auto"):
+        return [run_one(d, precision, method) for d in devs]
+
+    log("[bench] warmup")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"[bench] timing {args.steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    value = work / dt
+    log(f"[bench] {dt * 1e3:.3f} ms/step, {value:.4e} lag-pairs/s")
+
+    # FP64 plain GPU path (direct window sums, FP64 exp)
+    fp64 = None
+    if not args.no_fp64:
+        step("fp64", "direct")
+        torch.cuda.synchronize()
+        n64 = max(2, args.steps // 4)
+        t1 = time.perf_counter()
+        for _ in range(n64):
+            res64 = step("fp64", "direct")
+        torch.cuda.synchronize()
+        dt64 = (time.perf_counter() - t1) / n64
+        fp64 = {"value": work / dt64, "ms_per_step": dt64 * 1e3, "path": "fp64 direct window sums"}
+        log(f"[bench] fp64 direct: {dt64 * 1e3:.3f} ms/step")
+
+    # roofline of the dominant kernel, HIP events on the library's stream
+    ncf.profile_enable(True)
+    nprof = max(2, min(5, args.steps))
+    for _ in range(nprof):
+        step()
+    prof = ncf.profile_read()
+    ncf.profile_enable(False)
+    dom = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
+    name, rec = dom
+    avg_s = rec["total_ms"] / rec["launches"] / 1e3
+    work_per_launch = rec["work"] / rec["launches"]
+    if rec["unit"] == "bytes":
+        roof = {"bound": "hbm", "achieved": work_per_launch / avg_s / 1e9,
+                "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
+    else:
+        roof = {"bound": "alu", "achieved": work_per_launch / avg_s / 1e12,
+                "peak": VALU_PEAK / 1e12, "unit": "Tlane-op/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = name
+    roof["avg_launch_ms"] = avg_s * 1e3
+    kernels = {k: {"avg_ms": v["total_ms"] / v["launches"], "launches_per_step":
+                   v["launches"] / nprof} for k, v in prof.items()}
+
+    # accuracy against the oracle, CPU baseline
+    acc = {}
+    cpu = None
+    if not args.no_cpu:
+        from oracle import oracle as O
+        cores = O.max_threads()
+        log(f"[bench] oracle on {cores} threads")
+        orc_work, orc_time = 0, 0.0
+        for d, r in zip(host, res):
+            cs, ns, w, sec = oracle_subset(d, args.oracle_series)
+            orc_work += w
+            orc_time += sec
+            key = f"{d['name']}_{d['kernel']}"
+            acc[key] = {"max_abs_dc_mixed": max_dc(r[0], cs)}
+            if d["kernel"] == "rectangle":
+                acc[key]["counts_bit_exact"] = counts_equal(r[2], ns)
+        if fp64 is not None:
+            for d, r in zip(host, res64):
+                cs, ns, w, sec = oracle_subset(d, args.oracle_series)
+                acc[f"{d['name']}_{d['kernel']}"]["max_abs_dc_fp64_direct"] = max_dc(r[0], cs)
+        sample = ("whole workload" if host[0]["kind"] in ("acf", "ccf")
+                  else f"first {args.oracle_series} series of the batch")
+        cpu = {"value": orc_work / orc_time, "unit": "lag-pairs/s", "cores": cores,
+               "kind": "oracle", "sample": sample, "seconds": orc_time}
+
+    d0 = host[0]
+    cfg = {"workload": {"c1": "acf_n2000_K101_gauss_fp64plain_vs_mixed",
+                        "c2": "ccf_n1e5x2_K401_gauss+rect_mixed",
+                        "c3": "acf_n1e7_K4096_gauss_mixed",
+                        "c4": "acf_batch_10000_curves_K256_gauss_mixed",
+                        "c5": "ccf_batch_2048_pairs_K512_rect_mixed"}[args.workload],
+           "lag_pairs_per_step": int(work), "series_per_step": int(nser)}
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "lag-pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64 (mixed)",
+        "data": "synthetic",
+        "config": cfg,
+        "series_per_s": nser / dt,
+        "fp64_gpu_path": fp64,
+        "accuracy_vs_oracle": acc,
+        "roofline": roof,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,157 @@
+/*
+ * ncf.h -- C ABI of the MI355X kernel-weighted correlation library.
+ *
+ * The library computes the kernel-weighted auto- and cross-correlation
+ * estimator for irregularly sampled series (eq. kernel_estimator, Sec. 2.3)
+ * with the Gaussian kernel (eq. Gaussian_kernel, bandwidth h) or the
+ * rectangle kernel (half-width h, closed window, as in Algorithm
+ * "PairCount, rectangle"), together with the effective pair count b
+ * (Appendix A.2, Algorithms "PairCount").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Series 1 is (t_i, x_i), series 2 is (s_j, y_j). Times must be finite and
+ *    non-decreasing (ties allowed); values finite.
+ *  - CCF lag +tau means series 2 lags series 1 by tau: pairs with
+ *    s_j - t_i close to tau (Appendix A.1, sign convention).
+ *    ACF pairs have t_i - t_j close to tau.
+ *  - Gaussian window: t_i in [centre - 6h, centre + 6h) with
+ *    centre = s_j + eps*tau (eps = +1 ACF, -1 CCF); weight
+ *    exp(-d^2/2h^2)/(sqrt(2 pi) h) (Algorithm "PairCount, Gaussian").
+ *    Rectangle window: t_i in [centre - h, centre + h], weight 1.
+ *  - Values are standardized (mean 0, sd 1, ddof 0) before the pair sums
+ *    (Algorithms "CCF via NUFFT" / "ACF via NUFFT", first step).
+ *  - r(tau) = C(tau) / max(B(tau), 1e-16) where C is the kernel-weighted sum of
+ *    value products and B the kernel-weighted pair sum.
+ *    ACF: c_k = r(tau_k) / r(0)   (lag-0 normalization of "ACF via NUFFT").
+ *    CCF: c_k = r(tau_k) / sqrt(scale_x * scale_y), scale_x = r_xx(0) of
+ *    series 1 on itself, same for series 2 ("CCF via real-space ...").
+ *  - b_k = max(effective pair count, 1e-16); count_k = raw number of pairs in
+ *    the rectangle window (int64, exact). An empty window gives c_k = 0.
+ *  - Optional per-sample errors err_i > 0 give weights w_i = 1/err_i^2: the
+ *    mean and sd become weighted, and C and B weight each pair by w_i w_j.
+ *    b and count stay unweighted. (An extension: the paper defines no
+ *    weighted estimator.)
+ *  - Lags may come in any order, repeat, or be negative; outputs are in the
+ *    order of the request.
+ *
+ * Memory and ownership
+ *  - By default every array argument is a HOST pointer; the call copies in,
+ *    computes on the current HIP device and returns when the outputs are
+ *    written.
+ *  - With NCF_DEVICE_POINTERS in options->flags, every data array (times,
+ *    values, errors, lags, outputs) is a DEVICE pointer on options->stream.
+ *    Batch offset arrays and per-series bandwidths are always HOST arrays.
+ *    The call still returns only after the outputs are written.
+ *  - The caller owns all buffers; the library keeps no caller pointer after
+ *    return. Device workspace is cached by the library per device and freed
+ *    by ncf_release_workspace() or at process exit.
+ *
+ * Errors
+ *  - Every entry point returns NCF_OK (0) or a negative NCF_E_* code; on an
+ *    error the outputs are unspecified and ncf_last_error() returns a
+ *    message (thread-local, valid until the next call on the thread).
+ *    Batch calls also fill an optional per-series status array; the call
+ *    itself then returns the first non-zero per-series status, if any.
+ */
+#ifndef NCF_H
+#define NCF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NCF_OK 0
+#define NCF_E_INVALID_ARG (-1) /* null pointer, n < 2, K < 0, h <= 0, non-finite input, err <= 0 */
+#define NCF_E_UNSORTED (-2)    /* times not non-decreasing */
+#define NCF_E_DEGENERATE (-3)  /* sd = 0, or lag-0 scale (ACF r(0), CCF scale product) <= 0 */
+#define NCF_E_NOMEM (-4)       /* device or host allocation failed */
+#define NCF_E_DEVICE (-5)      /* HIP runtime error, or no GPU */
+#define NCF_E_UNSUPPORTED (-6) /* option combination not implemented */
+
+typedef enum { NCF_GAUSSIAN = 0, NCF_RECTANGLE = 1 } ncf_kernel_t;
+
+/* NCF_MIXED: FP32 spreading / FFT / kernel weights with FP64 positions,
+ * phases, moments, prefix sums and accumulators.
+ * NCF_FP64: every step in FP64. */
+typedef enum { NCF_MIXED = 0, NCF_FP64 = 1 } ncf_precision_t;
+
+/* NCF_AUTO: Gaussian numerator by the spectral (Wiener-Khinchin + NUFFT)
+ *   route (Sec. 2.6), rectangle numerator by prefix sums over the window
+ *   (Algorithm "CorrSum, rectangle"); pair counts always by the window scan.
+ * NCF_SPECTRAL: as AUTO for the Gaussian; for the rectangle kernel the
+ *   spectral route with the box kernel's Fourier transform (diagnostic: its
+ *   truncation error decays only as 1/f).
+ * NCF_DIRECT: numerator and pair counts by the window scan (real-space
+ *   estimator, Appendix B); with NCF_FP64 this is the plain FP64 GPU path. */
+typedef enum { NCF_AUTO = 0, NCF_SPECTRAL = 1, NCF_DIRECT = 2 } ncf_method_t;
+
+#define NCF_DEVICE_POINTERS 0x1u
+
+typedef struct {
+    uint32_t struct_size; /* sizeof(ncf_options_t) */
+    int32_t precision;    /* ncf_precision_t, default NCF_MIXED */
+    int32_t method;       /* ncf_method_t, default NCF_AUTO */
+    double tol;           /* spectral truncation target, 0 = default (1e-9 mixed, 1e-13 FP64) */
+    double sigma;         /* minimum grid oversampling factor, 0 = default (1.5) */
+    int64_t grid_size;    /* 0 = planned from h, L and tol; else a power of two to force */
+    void* stream;         /* hipStream_t; NULL = the null stream */
+    uint32_t flags;       /* NCF_DEVICE_POINTERS */
+    uint32_t reserved;
+} ncf_options_t;
+
+/* Fill *opt with defaults. */
+void ncf_options_init(ncf_options_t* opt);
+
+/* Autocorrelation of one series.
+ *   n       number of samples (>= 2)
+ *   t, x    times (sorted) and values, n each; err optional (NULL or n)
+ *   K       number of lags (>= 0); lags[K]
+ *   kern, h kernel and bandwidth (Gaussian sd / rectangle half-width), h > 0
+ *   c, b    outputs, K each; count optional output (K int64; rectangle pair
+ *           counts, zeros for the Gaussian kernel)
+ *   opt     NULL for defaults. */
+int ncf_acf(int64_t n, const double* t, const double* x, const double* err, int64_t K,
+            const double* lags, int kern, double h, double* c, double* b, int64_t* count,
+            const ncf_options_t* opt);
+
+/* Cross-correlation of series 1 (nx samples: tx, x, ex) and series 2 (ny
+ * samples: ty, y, ey); arguments as in ncf_acf. */
+int ncf_ccf(int64_t nx, const double* tx, const double* x, const double* ex, int64_t ny,
+            const double* ty, const double* y, const double* ey, int64_t K, const double* lags,
+            int kern, double h, double* c, double* b, int64_t* count, const ncf_options_t* opt);
+
+/* Autocorrelation of nser independent series in one call (CSR layout).
+ *   offs    HOST array of nser+1 offsets into t, x, err (offs[0] = 0)
+ *   lags    K lags shared by every series
+ *   h       HOST array of nser bandwidths
+ *   c, b    nser*K outputs, series-major; count optional nser*K
+ *   status  optional HOST array of nser per-series status codes. */
+int ncf_acf_batch(int64_t nser, const int64_t* offs, const double* t, const double* x,
+                  const double* err, int64_t K, const double* lags, int kern, const double* h,
+                  double* c, double* b, int64_t* count, int* status, const ncf_options_t* opt);
+
+/* Cross-correlation of npair series pairs in one call: series 1 of pair p
+ * is tx/x/ex[offx[p] .. offx[p+1]), series 2 is ty/y/ey[offy[p] ..
+ * offy[p+1]); other arguments as in ncf_acf_batch. */
+int ncf_ccf_batch(int64_t npair, const int64_t* offx, const double* tx, const double* x,
+                  const double* ex, const int64_t* offy, const double* ty, const double* y,
+                  const double* ey, int64_t K, const double* lags, int kern, const double* h,
+                  double* c, double* b, int64_t* count, int* status, const ncf_options_t* opt);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char* ncf_last_error(void);
+
+/* Free the cached device workspace of the current device. */
+void ncf_release_workspace(void);
+
+/* Library version, e.g. 100 for 0.1.0. */
+int ncf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NCF_H */

@@ -1,0 +1,1293 @@
+// api.hip -- C ABI, planner and batch scheduler of the ncf library.
+//
+// A call runs in two phases on one stream:
+//   1. inputs on the device -> per-series validation and FP64 moments (A1);
+//      the per-series statistics (status, mean, sd, time span) come back to
+//      the host, which plans the rest from them;
+//   2. standardization (+ FP64 prefix sums for the rectangle kernel), the
+//      window scan over every (series, j-tile, lag-tile) work item of the
+//      whole batch in one launch (A7), the spectral route for the Gaussian
+//      numerator (A2-A6: spreading tiles of every series in one launch, the
+//      FFT passes of all grids of one size in one launch per pass, the
+//      product, the lag evaluation), and the normalization (A8).
+// Work items of a batch are flattened across series so that a single
+// launch covers thousands of uneven series.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "ncf_diag.h"
+
+namespace ncf {
+
+// ------------------------------------------------------------------ errors
+
+namespace {
+thread_local std::string g_err;
+}
+
+void set_error(const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+}
+
+void clear_error() { g_err.clear(); }
+
+// --------------------------------------------------------------- profiling
+
+namespace {
+
+struct ProfRec {
+    int64_t launches = 0;
+    double ms = 0.0;
+    double work = 0.0;
+    std::string unit;
+};
+struct Pending {
+    std::string name;
+    hipEvent_t e0, e1;
+    double work;
+    std::string unit;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<Pending> g_pending;
+std::map<std::string, ProfRec> g_prof;
+
+void prof_flush_locked() {
+    for (auto& p : g_pending) {
+        float ms = 0.f;
+        (void)hipEventSynchronize(p.e1);
+        (void)hipEventElapsedTime(&ms, p.e0, p.e1);
+        auto& r = g_prof[p.name];
+        r.launches += 1;
+        r.ms += ms;
+        r.work += p.work;
+        r.unit = p.unit;
+        (void)hipEventDestroy(p.e0);
+        (void)hipEventDestroy(p.e1);
+    }
+    g_pending.clear();
+}
+
+}  // namespace
+
+ProfScope::ProfScope(hipStream_t s, const char* n, double w, const char* u)
+    : stream(s), name(n), work(w), unit(u), ev0(nullptr) {
+    if (!g_prof_on) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    (void)hipEventRecord(e, stream);
+    ev0 = e;
+}
+
+ProfScope::~ProfScope() {
+    if (!ev0) return;
+    hipEvent_t e1;
+    if (hipEventCreate(&e1) != hipSuccess) return;
+    (void)hipEventRecord(e1, stream);
+    std::lock_guard<std::mutex> lock(g_prof_mu);
+    g_pending.push_back({name, (hipEvent_t)ev0, e1, work, unit});
+}
+
+// --------------------------------------------------------------- workspace
+
+namespace {
+
+struct DevBuf {
+    void* ptr = nullptr;
+    size_t cap = 0;
+};
+std::mutex g_ws_mu;
+std::map<int, DevBuf> g_ws[2];  // [arena][device]
+
+int ensure_ws(int which, size_t bytes, void** out) {
+    int dev = 0;
+    NCF_TRY_HIP(hipGetDevice(&dev));
+    DevBuf& b = g_ws[which][dev];
+    if (b.cap < bytes) {
+        if (b.ptr) {
+            NCF_TRY_HIP(hipDeviceSynchronize());
+            NCF_TRY_HIP(hipFree(b.ptr));
+            b.ptr = nullptr;
+            b.cap = 0;
+        }
+        size_t want = bytes + bytes / 8 + (1 << 20);
+        hipError_t e = hipMalloc(&b.ptr, want);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            b.ptr = nullptr;
+            set_error("device workspace allocation of %zu bytes failed", want);
+            return NCF_E_NOMEM;
+        }
+        b.cap = want;
+    }
+    *out = b.ptr;
+    return NCF_OK;
+}
+
+// Bump allocator over a workspace: first a sizing pass (base == nullptr),
+// then the same sequence of takes on the real buffer.
+struct Arena {
+    char* base = nullptr;
+    size_t off = 0;
+    template <typename T>
+    T* take(size_t count) {
+        size_t a = (off + 255) & ~(size_t)255;
+        off = a + sizeof(T) * count;
+        return base ? reinterpret_cast<T*>(base + a) : reinterpret_cast<T*>(a + 1);
+    }
+};
+
+// -------------------------------------------------------------- the job
+
+constexpr int64_t kChunk = 16384;  // samples per moments chunk
+
+struct SeriesSet {
+    // device inputs
+    const double* t = nullptr;
+    const double* x = nullptr;
+    const double* err = nullptr;
+    int64_t ntot = 0;
+    std::vector<int64_t> offs;  // host, nser + 1
+    int nser = 0;
+    // derived (device)
+    float* v32 = nullptr;
+    double* v64 = nullptr;
+    double* w64 = nullptr;
+    double* pv = nullptr;
+    double* pw = nullptr;
+    SeriesDesc* d_series = nullptr;
+    Chunk* d_chunks = nullptr;
+    double* d_chunk_part = nullptr;
+    double* d_chunk_tot = nullptr;
+    SeriesStat* d_stats = nullptr;
+    std::vector<SeriesDesc> h_series;
+    std::vector<Chunk> h_chunks;
+    std::vector<SeriesStat> stats;
+};
+
+struct Job {
+    bool ccf = false;
+    int64_t nprob = 0;
+    int kern = NCF_GAUSSIAN;
+    std::vector<double> h;   // per problem
+    std::vector<double> lags;  // host copy, K
+    int64_t K = 0;
+    // user outputs
+    double* c = nullptr;
+    double* b = nullptr;
+    int64_t* count = nullptr;
+    int* status = nullptr;   // host, nprob (may be null)
+    ncf_options_t opt;
+    bool dev_ptrs = false;
+    hipStream_t st = nullptr;
+    SeriesSet set[2];        // ACF: set[0]; CCF: set[0] = series 1, set[1] = series 2
+};
+
+bool use_spectral(const Job& J) {
+    if (J.opt.method == NCF_DIRECT) return false;
+    if (J.kern == NCF_GAUSSIAN) return true;
+    return J.opt.method == NCF_SPECTRAL;  // rectangle: diagnostic only
+}
+
+int upload_inputs(Job& J, int si, const double* t, const double* x, const double* err,
+                  Arena& ar) {
+    SeriesSet& S = J.set[si];
+    if (J.dev_ptrs) {
+        S.t = t;
+        S.x = x;
+        S.err = err;
+        return NCF_OK;
+    }
+    double* dt = ar.take<double>(S.ntot);
+    double* dx = ar.take<double>(S.ntot);
+    double* de = err ? ar.take<double>(S.ntot) : nullptr;
+    if (ar.base) {
+        NCF_TRY_HIP(hipMemcpyAsync(dt, t, sizeof(double) * S.ntot, hipMemcpyHostToDevice, J.st));
+        NCF_TRY_HIP(hipMemcpyAsync(dx, x, sizeof(double) * S.ntot, hipMemcpyHostToDevice, J.st));
+        if (err)
+            NCF_TRY_HIP(
+                hipMemcpyAsync(de, err, sizeof(double) * S.ntot, hipMemcpyHostToDevice, J.st));
+    }
+    S.t = dt;
+    S.x = dx;
+    S.err = de;
+    return NCF_OK;
+}
+
+void build_chunks(SeriesSet& S) {
+    S.h_series.resize(S.nser);
+    S.h_chunks.clear();
+    int64_t pre = 0;
+    for (int s = 0; s < S.nser; ++s) {
+        SeriesDesc d;
+        d.off = S.offs[s];
+        d.n = S.offs[s + 1] - S.offs[s];
+        d.pre_off = pre;
+        pre += d.n + 1;
+        d.chunk0 = (int32_t)S.h_chunks.size();
+        int32_t nc = 0;
+        for (int64_t b = d.off; b < d.off + d.n; b += kChunk) {
+            Chunk c;
+            c.begin = b;
+            c.end = std::min(b + kChunk, d.off + d.n);
+            c.series = s;
+            c.pad = 0;
+            S.h_chunks.push_back(c);
+            ++nc;
+        }
+        d.nchunk = nc;
+        S.h_series[s] = d;
+    }
+}
+
+MomentsArgs moments_args(const SeriesSet& S) {
+    MomentsArgs a{};
+    a.t = S.t;
+    a.x = S.x;
+    a.err = S.err;
+    a.series = S.d_series;
+    a.chunks = S.d_chunks;
+    a.nseries = S.nser;
+    a.nchunks = (int32_t)S.h_chunks.size();
+    a.chunk_part = S.d_chunk_part;
+    a.stats = S.d_stats;
+    a.v32 = S.v32;
+    a.v64 = S.v64;
+    a.w64 = S.w64;
+    a.pv = S.pv;
+    a.pw = S.pw;
+    a.chunk_tot = S.d_chunk_tot;
+    return a;
+}
+
+// phase-1 layout (sizing pass when ar.base == nullptr)
+int layout_phase1(Job& J, const double* const* tin, const double* const* xin,
+                  const double* const* ein, Arena& ar, bool need_v32, bool need_v64,
+                  bool need_prefix) {
+    const int nsets = J.ccf ? 2 : 1;
+    for (int si = 0; si < nsets; ++si) {
+        SeriesSet& S = J.set[si];
+        NCF_TRY(upload_inputs(J, si, tin[si], xin[si], ein[si], ar));
+        const bool wtd = S.err != nullptr;
+        S.d_series = ar.take<SeriesDesc>(S.nser);
+        S.d_chunks = ar.take<Chunk>(S.h_chunks.size() + 1);
+        S.d_chunk_part = ar.take<double>(4 * (S.h_chunks.size() + 1));
+        S.d_chunk_tot = ar.take<double>(2 * (S.h_chunks.size() + 1));
+        S.d_stats = ar.take<SeriesStat>(S.nser);
+        S.v32 = need_v32 ? ar.take<float>(S.ntot) : nullptr;
+        S.v64 = need_v64 ? ar.take<double>(S.ntot) : nullptr;
+        S.w64 = wtd ? ar.take<double>(S.ntot) : nullptr;
+        S.pv = need_prefix ? ar.take<double>(S.ntot + S.nser) : nullptr;
+        S.pw = (need_prefix && wtd) ? ar.take<double>(S.ntot + S.nser) : nullptr;
+    }
+    return NCF_OK;
+}
+
+int64_t pow2_at_least(double v) {
+    int64_t p = 1;
+    while ((double)p < v) p <<= 1;
+    return p;
+}
+
+// One spectral problem's geometry.
+struct SpecGeom {
+    double L, t_ref, s, W;
+    int64_t N, M;
+};
+
+int plan_grid(const Job& J, double tmin, double tmax, double maxlag, double h, SpecGeom* g) {
+    const bool fp64 = J.opt.precision == NCF_FP64;
+    const double tol = J.opt.tol > 0 ? J.opt.tol : (fp64 ? 1e-13 : 1e-9);
+    const double eps_s = fp64 ? 1e-13 : 1e-7;  // spreading accuracy
+    const double sig_min = J.opt.sigma > 1.0 ? J.opt.sigma : 1.5;
+    const double span = tmax - tmin;
+    double Wh, fcut;
+    if (J.kern == NCF_GAUSSIAN) {
+        Wh = 9.0 * h;  // phi_h(9h)/phi_h(0) = e^-40.5
+        fcut = std::sqrt(std::log(1.0 / tol) / (2.0 * M_PI * M_PI)) / h;
+    } else {
+        Wh = h;
+        fcut = 16.0 / h;
+    }
+    double L = span + maxlag + Wh;
+    for (int iter = 0; iter < 8; ++iter) {
+        int64_t M = (int64_t)std::ceil(fcut * L);
+        int64_t N;
+        if (J.opt.grid_size > 0) {
+            N = J.opt.grid_size;
+            M = std::min<int64_t>(M, (int64_t)std::floor((N / sig_min - 1.0) / 2.0));
+        } else {
+            N = std::max<int64_t>(4096, pow2_at_least(sig_min * (2.0 * M + 1.0)));
+        }
+        SpreadParams sp{};
+        for (;;) {
+            const double sigma = (double)N / (2.0 * M + 1.0);
+            sp = spread_params(sigma, eps_s);
+            const double h_cells = h * (double)N / L;
+            // the folded factor phihat / Psi^3 must decay with |m|
+            if (J.kern != NCF_GAUSSIAN || h_cells >= std::sqrt(3.0) * sp.s ||
+                J.opt.grid_size > 0)
+                break;
+            N *= 2;
+        }
+        if (N > (1LL << 31)) {
+            set_error("spectral grid of %lld cells exceeds the supported maximum (2^31)",
+                      (long long)N);
+            return NCF_E_UNSUPPORTED;
+        }
+        const double cell = L / (double)N;
+        const double margin = (sp.W + 2.0) * cell;
+        if (span + 2.0 * margin <= L) {
+            g->L = L;
+            g->N = N;
+            g->M = M;
+            g->s = sp.s;
+            g->W = sp.W;
+            g->t_ref = tmin - margin;
+            return NCF_OK;
+        }
+        L = span + 2.0 * margin + cell;
+    }
+    set_error("grid planning did not converge");
+    return NCF_E_UNSUPPORTED;
+}
+
+int run_job(Job& J, const double* const* tin, const double* const* xin,
+            const double* const* ein) {
+    const bool fp64 = J.opt.precision == NCF_FP64;
+    const bool spectral = use_spectral(J);
+    const bool rect = J.kern == NCF_RECTANGLE;
+    const int nsets = J.ccf ? 2 : 1;
+    bool weighted = false;
+    for (int si = 0; si < nsets; ++si) weighted |= (ein[si] != nullptr);
+    const bool numer_in_window = !spectral;  // C from the window scan
+    const bool need_v32 = spectral && !fp64;
+    const bool need_v64 = (spectral && fp64) || numer_in_window;
+    const bool need_prefix = rect && numer_in_window;
+
+    for (int si = 0; si < nsets; ++si) build_chunks(J.set[si]);
+
+    // ---------------- phase 1: validation + moments
+    Arena a1;
+    NCF_TRY(layout_phase1(J, tin, xin, ein, a1, need_v32, need_v64, need_prefix));
+    void* ws1 = nullptr;
+    NCF_TRY(ensure_ws(0, a1.off + 256, &ws1));
+    a1 = Arena{(char*)ws1, 0};
+    NCF_TRY(layout_phase1(J, tin, xin, ein, a1, need_v32, need_v64, need_prefix));
+    for (int si = 0; si < nsets; ++si) {
+        SeriesSet& S = J.set[si];
+        NCF_TRY_HIP(hipMemcpyAsync(S.d_series, S.h_series.data(),
+                                   sizeof(SeriesDesc) * S.nser, hipMemcpyHostToDevice, J.st));
+        if (!S.h_chunks.empty())
+            NCF_TRY_HIP(hipMemcpyAsync(S.d_chunks, S.h_chunks.data(),
+                                       sizeof(Chunk) * S.h_chunks.size(),
+                                       hipMemcpyHostToDevice, J.st));
+        NCF_TRY(launch_moments(moments_args(S), J.st));
+        S.stats.resize(S.nser);
+        NCF_TRY_HIP(hipMemcpyAsync(S.stats.data(), S.d_stats, sizeof(SeriesStat) * S.nser,
+                                   hipMemcpyDeviceToHost, J.st));
+    }
+    NCF_TRY_HIP(hipStreamSynchronize(J.st));
+
+    // per-problem status from its series
+    std::vector<int> pstat(J.nprob, NCF_OK);
+    for (int64_t p = 0; p < J.nprob; ++p) {
+        for (int si = 0; si < nsets; ++si) {
+            int s = J.set[si].stats[p].status;
+            if (s != NCF_OK && pstat[p] == NCF_OK) pstat[p] = s;
+        }
+        if (pstat[p] == NCF_OK && !(J.h[p] > 0.0 && std::isfinite(J.h[p])))
+            pstat[p] = NCF_E_INVALID_ARG;
+    }
+
+    // standardization (+ prefix sums)
+    for (int si = 0; si < nsets; ++si) NCF_TRY(launch_standardize(moments_args(J.set[si]), J.st));
+
+    // ---------------- phase 2 planning (host)
+    const int64_t K = J.K;
+    double maxlag = 0.0;
+    for (double v : J.lags) maxlag = std::max(maxlag, std::fabs(v));
+    // window lag rows: sorted offsets delta = eps * tau (ACF: plus lag 0)
+    const double epsv = J.ccf ? -1.0 : 1.0;
+    std::vector<std::pair<double, int>> rows;
+    for (int64_t k = 0; k < K; ++k) rows.push_back({epsv * J.lags[k], (int)k});
+    bool have0 = false;
+    for (double v : J.lags) have0 |= (v == 0.0);
+    if (!J.ccf && !have0) rows.push_back({0.0, -1});
+    std::stable_sort(rows.begin(), rows.end(),
+                     [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+                         return a.first < b.first;
+                     });
+    const int Krow = (int)rows.size();
+    std::vector<double> delta(Krow);
+    std::vector<int32_t> perm(std::max<int64_t>(K, 1));
+    int row0 = -1;
+    for (int r = 0; r < Krow; ++r) {
+        delta[r] = rows[r].first;
+        if (rows[r].second >= 0) perm[rows[r].second] = r;
+        if (rows[r].first == 0.0 && row0 < 0) row0 = r;
+    }
+    // largest lag extent of a 64-row tile
+    double lag_ext = 0.0;
+    for (int r0 = 0; r0 < Krow; r0 += 64) {
+        int r1 = std::min(Krow, r0 + 64) - 1;
+        lag_ext = std::max(lag_ext, delta[r1] - delta[r0]);
+    }
+
+    // window flags and LDS budget
+    uint32_t wflags = 0;
+    if (rect) wflags |= WIN_RECT;
+    if (numer_in_window) wflags |= WIN_NUMER;
+    if (weighted) wflags |= WIN_WEIGHTED;
+    if (fp64 && !rect) wflags |= WIN_EXP64;
+    const int jmax = rect ? 512 : 1024;
+    const int outer_arrays = 1 + (numer_in_window ? 1 : 0) + (weighted ? 1 : 0);
+    const int win_arrays = 1 + (numer_in_window ? 1 : 0) + (weighted ? 1 : 0);
+    const int budget = 40 * 1024 / 8;  // doubles
+    int cap = (budget - jmax * outer_arrays - 2) / win_arrays;
+    cap = std::max(256, std::min(4096, cap));
+
+    struct WinPlan {
+        int wi_set, wi_ser, wo_set, wo_ser;  // window (set, series), outer (set, series)
+        int krows;                           // rows: Krow (cross/acf) or 1 (self lag 0)
+        int64_t prob;
+        int role;                            // 0 main, 1 self x, 2 self y
+    };
+    std::vector<WinPlan> wplans;
+    for (int64_t p = 0; p < J.nprob; ++p) {
+        if (pstat[p] != NCF_OK) continue;
+        if (!J.ccf) {
+            wplans.push_back({0, (int)p, 0, (int)p, Krow, p, 0});
+        } else {
+            if (Krow > 0) wplans.push_back({0, (int)p, 1, (int)p, Krow, p, 0});
+            wplans.push_back({0, (int)p, 0, (int)p, 1, p, 1});
+            wplans.push_back({1, (int)p, 1, (int)p, 1, p, 2});
+        }
+    }
+    const int ntw = (int)wplans.size();
+    std::vector<WinTask> wt(ntw);
+    std::vector<int64_t> item0(ntw + 1), wk0(ntw + 1);
+    int64_t nitems = 0, total_rows = 0;
+    double win_work = 0.0;
+    const double zero = 0.0;
+    (void)zero;
+    for (int i = 0; i < ntw; ++i) {
+        const WinPlan& P = wplans[i];
+        const SeriesSet& SW = J.set[P.wi_set];
+        const SeriesSet& SO = J.set[P.wo_set];
+        const SeriesDesc& dw = SW.h_series[P.wi_ser];
+        const SeriesDesc& dO = SO.h_series[P.wo_ser];
+        const SeriesStat& sw = SW.stats[P.wi_ser];
+        const SeriesStat& so = SO.stats[P.wo_ser];
+        const double h = J.h[P.prob];
+        WinTask T{};
+        T.t = SW.t + dw.off;
+        T.n_win = dw.n;
+        T.s = SO.t + dO.off;
+        T.n_out = dO.n;
+        if (numer_in_window) {
+            if (rect) {
+                T.pv = SW.pv + dw.pre_off;
+            } else {
+                T.v = SW.v64 + dw.off;
+            }
+            T.vo = SO.v64 + dO.off;
+        }
+        if (weighted) {
+            if (rect) {
+                T.pw = SW.pw ? SW.pw + dw.pre_off : nullptr;
+            } else {
+                T.w = SW.w64 ? SW.w64 + dw.off : nullptr;
+            }
+            T.wo = SO.w64 ? SO.w64 + dO.off : nullptr;
+        }
+        T.K = P.krows;
+        T.h = h;
+        T.W = rect ? h : 6.0 * h;
+        // tile size
+        const double span_w = std::max(sw.tmax - sw.tmin, 1e-300);
+        const double span_o = std::max(so.tmax - so.tmin, 1e-300);
+        const double dens_w = (double)(dw.n - 1) / span_w;
+        const double dens_o = (double)(dO.n - 1) / span_o;
+        const int n_kt = (int)ceil_div(T.K, 64);
+        const double lext = (P.krows == 1) ? 0.0 : lag_ext;
+        int64_t Jt = 1;
+        const double target = 4096.0;
+        while (Jt * 2 <= jmax && (double)dO.n * n_kt / (double)(Jt * 2) >= target) Jt *= 2;
+        Jt = std::max<int64_t>(Jt, std::min<int64_t>(64, jmax));
+        while (Jt > 16 &&
+               dens_w * ((double)Jt / dens_o + lext + 2.0 * T.W) + 2.0 > 0.5 * cap)
+            Jt /= 2;
+        T.J = (int32_t)Jt;
+        T.n_jt = (int32_t)ceil_div(dO.n, Jt);
+        T.n_kt = n_kt;
+        T.item0 = nitems;
+        item0[i] = nitems;
+        wk0[i] = total_rows;
+        nitems += (int64_t)T.n_jt * T.n_kt;
+        total_rows += T.K;
+        // algorithmic work: per (j, k) window, searches + per-point weight ops
+        const double pts = rect ? 0.0 : dens_w * 2.0 * T.W;
+        win_work += (double)dO.n * T.K * (8.0 + (rect ? 4.0 : 8.0 * pts));
+        wt[i] = T;
+    }
+    item0[ntw] = nitems;
+    wk0[ntw] = total_rows;
+
+    // spectral problems
+    struct SpecPlan {
+        int64_t prob;
+        SpecGeom g;
+    };
+    std::vector<SpecPlan> splans;
+    if (spectral) {
+        for (int64_t p = 0; p < J.nprob; ++p) {
+            if (pstat[p] != NCF_OK) continue;
+            double tmin = J.set[0].stats[p].tmin, tmax = J.set[0].stats[p].tmax;
+            if (J.ccf) {
+                tmin = std::min(tmin, J.set[1].stats[p].tmin);
+                tmax = std::max(tmax, J.set[1].stats[p].tmax);
+            }
+            SpecPlan sp;
+            sp.prob = p;
+            NCF_TRY(plan_grid(J, tmin, tmax, maxlag, J.h[p], &sp.g));
+            splans.push_back(sp);
+        }
+        std::stable_sort(splans.begin(), splans.end(),
+                         [](const SpecPlan& a, const SpecPlan& b) { return a.g.N < b.g.N; });
+    }
+    const int nts = (int)splans.size();
+    const int Keval = (int)(J.ccf ? K : K + 1);
+
+    // ---------------- phase 2 layout
+    const size_t csz = fp64 ? 16 : 8;
+    auto layout2 = [&](Arena& ar, std::vector<SpecTask>* stasks, std::vector<NormTask>* ntasks,
+                       void** d_wt, int64_t** d_item0, int64_t** d_wk0, void** d_st,
+                       int64_t** d_tile0, int64_t** d_pos0, int64_t** d_sk0, void** d_rinfo,
+                       double** d_delta, int32_t** d_perm, double** d_evlags, void** d_nt,
+                       int32_t** d_status, double** d_c, double** d_b, int64_t** d_cnt,
+                       std::vector<void*>* grids, double** d_zero, void*** d_gtab) {
+        *d_wt = ar.take<WinTask>(std::max(ntw, 1));
+        *d_item0 = ar.take<int64_t>(ntw + 1);
+        *d_wk0 = ar.take<int64_t>(ntw + 1);
+        *d_delta = ar.take<double>(std::max(Krow, 1));
+        *d_perm = ar.take<int32_t>(std::max<int64_t>(K, 1));
+        *d_zero = ar.take<double>(1);
+        for (int i = 0; i < ntw; ++i) {
+            // self tasks of a CCF run at lag 0 only
+            wt[i].delta = wplans[i].role == 0 ? *d_delta : *d_zero;
+            wt[i].part = ar.take<double>((size_t)wt[i].n_jt * wt[i].K * 4);
+            wt[i].sums = ar.take<double>((size_t)wt[i].K * 4);
+        }
+        // spectral
+        stasks->clear();
+        *d_st = ar.take<SpecTask>(std::max(nts, 1));
+        *d_tile0 = ar.take<int64_t>(nts + 1);
+        *d_pos0 = ar.take<int64_t>(nts + 1);
+        *d_sk0 = ar.take<int64_t>(nts + 1);
+        *d_rinfo = ar.take<int32_t>(6 * std::max(nts, 1));
+        *d_evlags = ar.take<double>(std::max(Keval, 1));
+        *d_gtab = ar.take<void*>(std::max(nts, 1));
+        grids->clear();
+        int64_t tiles = 0, pos = 0;
+        for (int i = 0; i < nts; ++i) {
+            const SpecPlan& P = splans[i];
+            const SeriesSet& S0 = J.set[0];
+            const SeriesDesc& d0 = S0.h_series[P.prob];
+            SpecTask T{};
+            T.t0 = S0.t + d0.off;
+            T.v0f = S0.v32 ? S0.v32 + d0.off : nullptr;
+            T.v0d = S0.v64 ? S0.v64 + d0.off : nullptr;
+            T.n0 = d0.n;
+            if (J.ccf) {
+                const SeriesSet& S1 = J.set[1];
+                const SeriesDesc& d1 = S1.h_series[P.prob];
+                T.t1 = S1.t + d1.off;
+                T.v1f = S1.v32 ? S1.v32 + d1.off : nullptr;
+                T.v1d = S1.v64 ? S1.v64 + d1.off : nullptr;
+                T.n1 = d1.n;
+            }
+            T.t_ref = P.g.t_ref;
+            T.L = P.g.L;
+            T.N = P.g.N;
+            T.M = P.g.M;
+            T.s = P.g.s;
+            T.W = P.g.W;
+            T.h = J.h[P.prob];
+            T.kern = J.kern;
+            T.ccf = J.ccf ? 1 : 0;
+            T.grid = ar.take<char>((size_t)P.g.N * csz);
+            grids->push_back(T.grid);
+            T.tile0 = tiles;
+            T.ntiles = P.g.N / 4096;
+            tiles += T.ntiles;
+            T.tile_rng = ar.take<int64_t>(4 * T.ntiles);
+            T.lags = *d_evlags;
+            T.K_eval = Keval;
+            T.numer = ar.take<double>(std::max(Keval, 1));
+            T.scale_part = J.ccf ? ar.take<double>(2 * (P.g.N / 256)) : nullptr;
+            T.pos0 = pos;
+            pos += P.g.N;
+            stasks->push_back(T);
+        }
+        // normalization + outputs
+        *d_nt = ar.take<NormTask>(std::max<int64_t>(J.nprob, 1));
+        *d_status = ar.take<int32_t>(std::max<int64_t>(J.nprob, 1));
+        if (J.dev_ptrs) {
+            *d_c = J.c;
+            *d_b = J.b;
+            *d_cnt = J.count;
+        } else {
+            *d_c = ar.take<double>(std::max<int64_t>(J.nprob * K, 1));
+            *d_b = ar.take<double>(std::max<int64_t>(J.nprob * K, 1));
+            *d_cnt = J.count ? ar.take<int64_t>(std::max<int64_t>(J.nprob * K, 1)) : nullptr;
+        }
+        return NCF_OK;
+    };
+
+    std::vector<SpecTask> stasks;
+    std::vector<NormTask> ntasks_v;
+    void *d_wt, *d_st, *d_rinfo, *d_nt;
+    int64_t *d_item0, *d_wk0, *d_tile0, *d_pos0, *d_sk0, *d_cnt;
+    double *d_delta, *d_evlags, *d_c, *d_b;
+    int32_t *d_perm, *d_status;
+    std::vector<void*> grids;
+    double* d_zero;
+    void** d_gtab;
+    Arena a2;
+    layout2(a2, &stasks, &ntasks_v, &d_wt, &d_item0, &d_wk0, &d_st, &d_tile0, &d_pos0, &d_sk0,
+            &d_rinfo, &d_delta, &d_perm, &d_evlags, &d_nt, &d_status, &d_c, &d_b, &d_cnt,
+            &grids, &d_zero, &d_gtab);
+    void* ws2 = nullptr;
+    NCF_TRY(ensure_ws(1, a2.off + 256, &ws2));
+    a2 = Arena{(char*)ws2, 0};
+    layout2(a2, &stasks, &ntasks_v, &d_wt, &d_item0, &d_wk0, &d_st, &d_tile0, &d_pos0, &d_sk0,
+            &d_rinfo, &d_delta, &d_perm, &d_evlags, &d_nt, &d_status, &d_c, &d_b, &d_cnt,
+            &grids, &d_zero, &d_gtab);
+
+    // window tables
+    if (Krow > 0)
+        NCF_TRY_HIP(hipMemcpyAsync(d_delta, delta.data(), sizeof(double) * Krow,
+                                   hipMemcpyHostToDevice, J.st));
+    {
+        static const double kZero = 0.0;
+        NCF_TRY_HIP(
+            hipMemcpyAsync(d_zero, &kZero, sizeof(double), hipMemcpyHostToDevice, J.st));
+    }
+    if (K > 0)
+        NCF_TRY_HIP(hipMemcpyAsync(d_perm, perm.data(), sizeof(int32_t) * K,
+                                   hipMemcpyHostToDevice, J.st));
+    if (ntw > 0) {
+        NCF_TRY_HIP(hipMemcpyAsync(d_wt, wt.data(), sizeof(WinTask) * ntw, hipMemcpyHostToDevice,
+                                   J.st));
+        NCF_TRY_HIP(hipMemcpyAsync(d_item0, item0.data(), sizeof(int64_t) * (ntw + 1),
+                                   hipMemcpyHostToDevice, J.st));
+        NCF_TRY_HIP(hipMemcpyAsync(d_wk0, wk0.data(), sizeof(int64_t) * (ntw + 1),
+                                   hipMemcpyHostToDevice, J.st));
+    }
+
+    // ---- A7 window scan (all tasks, one launch)
+    NCF_TRY(launch_window((const WinTask*)d_wt, d_item0, ntw, nitems, wflags, cap, jmax, J.st,
+                          win_work));
+    NCF_TRY(launch_window_reduce((const WinTask*)d_wt, ntw, total_rows, d_wk0, wflags, J.st));
+
+    // ---- A2-A6 spectral numerator
+    // host tables of async copies live until the final synchronization
+    std::vector<int64_t> tile0(nts + 1), pos0(nts + 1), sk0(nts + 1);
+    std::vector<double> ev(std::max(Keval, 1));
+    std::vector<int32_t> rinfo(6 * std::max(nts, 1));
+    if (nts > 0) {
+        for (int64_t k = 0; k < K; ++k) ev[k] = J.lags[k];
+        if (!J.ccf) ev[K] = 0.0;
+        NCF_TRY_HIP(hipMemcpyAsync(d_evlags, ev.data(), sizeof(double) * Keval,
+                                   hipMemcpyHostToDevice, J.st));
+        std::map<int64_t, FftPlan> plans;
+        int64_t spread_bytes = 0, total_pos = 0;
+        for (int i = 0; i < nts; ++i) {
+            tile0[i] = stasks[i].tile0;
+            pos0[i] = stasks[i].pos0;
+            sk0[i] = (int64_t)i * Keval;
+            const int64_t N = stasks[i].N;
+            if (!plans.count(N)) {
+                FftPlan fp;
+                NCF_TRY(fft_plan(N, fp64, &fp, J.st));
+                plans[N] = fp;
+            }
+            const FftPlan& fp = plans[N];
+            int lgN = 0;
+            while ((1LL << lgN) < N) ++lgN;
+            rinfo[6 * i + 0] = fp.npass;
+            for (int q = 0; q < 4; ++q) {
+                int lg = 0;
+                if (q < fp.npass)
+                    while ((1 << lg) < fp.radix[q]) ++lg;
+                rinfo[6 * i + 1 + q] = lg;
+            }
+            rinfo[6 * i + 5] = lgN;
+            spread_bytes += (stasks[i].n0 + stasks[i].n1) * 12 + N * (int64_t)csz;
+            total_pos += N;
+        }
+        tile0[nts] = stasks.back().tile0 + stasks.back().ntiles;
+        pos0[nts] = total_pos;
+        sk0[nts] = (int64_t)nts * Keval;
+        NCF_TRY_HIP(hipMemcpyAsync(d_st, stasks.data(), sizeof(SpecTask) * nts,
+                                   hipMemcpyHostToDevice, J.st));
+        NCF_TRY_HIP(hipMemcpyAsync(d_tile0, tile0.data(), sizeof(int64_t) * (nts + 1),
+                                   hipMemcpyHostToDevice, J.st));
+        NCF_TRY_HIP(hipMemcpyAsync(d_pos0, pos0.data(), sizeof(int64_t) * (nts + 1),
+                                   hipMemcpyHostToDevice, J.st));
+        NCF_TRY_HIP(hipMemcpyAsync(d_sk0, sk0.data(), sizeof(int64_t) * (nts + 1),
+                                   hipMemcpyHostToDevice, J.st));
+        NCF_TRY_HIP(hipMemcpyAsync(d_rinfo, rinfo.data(), sizeof(int32_t) * 6 * nts,
+                                   hipMemcpyHostToDevice, J.st));
+        const int64_t ntiles = tile0[nts];
+        NCF_TRY(launch_tile_ranges((const SpecTask*)d_st, d_tile0, nts, ntiles, 4096, J.st));
+        NCF_TRY(launch_spread((const SpecTask*)d_st, d_tile0, nts, ntiles, 4096, fp64, J.st,
+                              (double)spread_bytes));
+        // grids of one size are contiguous in the task list (sorted by N)
+        NCF_TRY_HIP(hipMemcpyAsync(d_gtab, grids.data(), sizeof(void*) * nts,
+                                   hipMemcpyHostToDevice, J.st));
+        std::vector<std::pair<int, int>> groups;  // (first task, count)
+        for (int i = 0; i < nts; ++i) {
+            if (i == 0 || stasks[i].N != stasks[i - 1].N)
+                groups.push_back({i, 1});
+            else
+                groups.back().second++;
+        }
+        for (auto& gq : groups)
+            NCF_TRY(fft_exec(plans[stasks[gq.first].N], d_gtab + gq.first, gq.second, +1, fp64,
+                             J.st));
+        NCF_TRY(launch_product((const SpecTask*)d_st, d_pos0, nts, total_pos,
+                               (const int64_t*)d_rinfo, fp64, J.st, 2.0 * total_pos * csz));
+        for (auto& gq : groups)
+            NCF_TRY(fft_exec(plans[stasks[gq.first].N], d_gtab + gq.first, gq.second, -1, fp64,
+                             J.st));
+        NCF_TRY(launch_interp((const SpecTask*)d_st, nts, d_sk0, (int64_t)nts * Keval, fp64,
+                              J.st));
+    }
+
+    // ---- A8 normalization
+    std::vector<int32_t> dstat(J.nprob);
+    std::vector<NormTask> nt(J.nprob);
+    {
+        // locate window tasks of each problem
+        std::vector<int> main_t(J.nprob, -1), selfx(J.nprob, -1), selfy(J.nprob, -1),
+            spec_t(J.nprob, -1);
+        for (int i = 0; i < ntw; ++i) {
+            const WinPlan& P = wplans[i];
+            (P.role == 0 ? main_t : P.role == 1 ? selfx : selfy)[P.prob] = i;
+        }
+        for (int i = 0; i < nts; ++i) spec_t[splans[i].prob] = i;
+        for (int64_t p = 0; p < J.nprob; ++p) {
+            NormTask T{};
+            T.ccf = J.ccf ? 1 : 0;
+            T.K = (int32_t)K;
+            T.perm = d_perm;
+            T.row0 = row0;
+            T.spectral = spectral ? 1 : 0;
+            T.weighted = weighted ? 1 : 0;
+            T.is_rect = rect ? 1 : 0;
+            T.status = d_status + p;
+            T.c = d_c + p * K;
+            T.b = d_b + p * K;
+            T.count = d_cnt ? d_cnt + p * K : nullptr;
+            dstat[p] = pstat[p];
+            if (pstat[p] == NCF_OK) {
+                if (main_t[p] >= 0) T.wsums = wt[main_t[p]].sums;
+                if (J.ccf) {
+                    T.self_x = wt[selfx[p]].sums;
+                    T.self_y = wt[selfy[p]].sums;
+                }
+                if (spectral) {
+                    const SpecTask& S = stasks[spec_t[p]];
+                    T.numer = S.numer;
+                    T.scale_part = S.scale_part;
+                    T.nscale_part = S.N / 256;
+                }
+            } else {
+                T.skip = 1;  // outputs filled with NaN below
+            }
+            nt[p] = T;
+        }
+    }
+    NCF_TRY_HIP(hipMemcpyAsync(d_status, dstat.data(), sizeof(int32_t) * J.nprob,
+                               hipMemcpyHostToDevice, J.st));
+    NCF_TRY_HIP(
+        hipMemcpyAsync(d_nt, nt.data(), sizeof(NormTask) * J.nprob, hipMemcpyHostToDevice, J.st));
+    // problems that failed validation: fill c = NaN, b = 0, count = 0
+    bool any_bad = false;
+    for (int64_t p = 0; p < J.nprob; ++p) any_bad |= (pstat[p] != NCF_OK);
+    if (any_bad && K > 0) {
+        std::vector<double> nanv(K, NAN), zv(K, 0.0);
+        std::vector<int64_t> zc(K, 0);
+        for (int64_t p = 0; p < J.nprob; ++p) {
+            if (pstat[p] == NCF_OK) continue;
+            NCF_TRY_HIP(hipMemcpyAsync(d_c + p * K, nanv.data(), sizeof(double) * K,
+                                       hipMemcpyHostToDevice, J.st));
+            NCF_TRY_HIP(hipMemcpyAsync(d_b + p * K, zv.data(), sizeof(double) * K,
+                                       hipMemcpyHostToDevice, J.st));
+            if (d_cnt)
+                NCF_TRY_HIP(hipMemcpyAsync(d_cnt + p * K, zc.data(), sizeof(int64_t) * K,
+                                           hipMemcpyHostToDevice, J.st));
+        }
+        // these host buffers must outlive the copies
+        NCF_TRY_HIP(hipStreamSynchronize(J.st));
+    }
+    NCF_TRY(launch_normalize((const NormTask*)d_nt, (int)J.nprob, J.nprob * K, nullptr, J.st));
+
+    // ---- outputs
+    std::vector<int32_t> fstat(J.nprob);
+    NCF_TRY_HIP(hipMemcpyAsync(fstat.data(), d_status, sizeof(int32_t) * J.nprob,
+                               hipMemcpyDeviceToHost, J.st));
+    if (!J.dev_ptrs && K > 0) {
+        NCF_TRY_HIP(hipMemcpyAsync(J.c, d_c, sizeof(double) * J.nprob * K, hipMemcpyDeviceToHost,
+                                   J.st));
+        NCF_TRY_HIP(hipMemcpyAsync(J.b, d_b, sizeof(double) * J.nprob * K, hipMemcpyDeviceToHost,
+                                   J.st));
+        if (J.count)
+            NCF_TRY_HIP(hipMemcpyAsync(J.count, d_cnt, sizeof(int64_t) * J.nprob * K,
+                                       hipMemcpyDeviceToHost, J.st));
+    }
+    NCF_TRY_HIP(hipStreamSynchronize(J.st));
+    if (g_prof_on) {
+        std::lock_guard<std::mutex> lock(g_prof_mu);
+        prof_flush_locked();
+    }
+    int first = NCF_OK;
+    for (int64_t p = 0; p < J.nprob; ++p) {
+        if (J.status) J.status[p] = fstat[p];
+        if (fstat[p] != NCF_OK && first == NCF_OK) first = fstat[p];
+    }
+    if (first != NCF_OK) {
+        static const char* names[] = {"ok", "invalid argument", "unsorted times",
+                                      "degenerate series", "out of memory", "device error",
+                                      "unsupported"};
+        int idx = -first;
+        set_error("series failed: %s", (idx >= 0 && idx <= 6) ? names[idx] : "error");
+    }
+    return first;
+}
+
+// ---------------------------------------------------------- entry helpers
+
+int common_checks(const ncf_options_t* opt, ncf_options_t* o, int kern) {
+    ncf_options_init(o);
+    if (opt) {
+        if (opt->struct_size != sizeof(ncf_options_t)) {
+            set_error("ncf_options_t.struct_size mismatch");
+            return NCF_E_INVALID_ARG;
+        }
+        *o = *opt;
+    }
+    if (kern != NCF_GAUSSIAN && kern != NCF_RECTANGLE) {
+        set_error("unknown kernel %d", kern);
+        return NCF_E_INVALID_ARG;
+    }
+    if (o->precision != NCF_MIXED && o->precision != NCF_FP64) {
+        set_error("unknown precision %d", o->precision);
+        return NCF_E_INVALID_ARG;
+    }
+    if (o->method != NCF_AUTO && o->method != NCF_SPECTRAL && o->method != NCF_DIRECT) {
+        set_error("unknown method %d", o->method);
+        return NCF_E_INVALID_ARG;
+    }
+    if (o->grid_size > 0 && (o->grid_size < 4096 || (o->grid_size & (o->grid_size - 1)))) {
+        set_error("grid_size must be a power of two >= 4096");
+        return NCF_E_INVALID_ARG;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+        (void)hipGetLastError();
+        set_error("no HIP device available");
+        return NCF_E_DEVICE;
+    }
+    return NCF_OK;
+}
+
+int load_lags(Job& J, int64_t K, const double* lags) {
+    if (K < 0 || (K > 0 && !lags)) {
+        set_error("invalid lag array");
+        return NCF_E_INVALID_ARG;
+    }
+    J.K = K;
+    J.lags.resize(K);
+    if (K > 0) {
+        if (J.dev_ptrs) {
+            NCF_TRY_HIP(hipMemcpyAsync(J.lags.data(), lags, sizeof(double) * K,
+                                       hipMemcpyDeviceToHost, J.st));
+            NCF_TRY_HIP(hipStreamSynchronize(J.st));
+        } else {
+            std::memcpy(J.lags.data(), lags, sizeof(double) * K);
+        }
+    }
+    for (double v : J.lags)
+        if (!std::isfinite(v)) {
+            set_error("non-finite lag");
+            return NCF_E_INVALID_ARG;
+        }
+    return NCF_OK;
+}
+
+int check_offs(const int64_t* offs, int64_t n, int64_t* total) {
+    if (!offs || offs[0] != 0) {
+        set_error("offset array must start at 0");
+        return NCF_E_INVALID_ARG;
+    }
+    for (int64_t i = 0; i < n; ++i)
+        if (offs[i + 1] < offs[i] + 2) {
+            set_error("series %lld has fewer than 2 samples", (long long)i);
+            return NCF_E_INVALID_ARG;
+        }
+    *total = offs[n];
+    return NCF_OK;
+}
+
+}  // namespace
+
+}  // namespace ncf
+
+using namespace ncf;
+
+extern "C" {
+
+void ncf_options_init(ncf_options_t* opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof *opt);
+    opt->struct_size = sizeof(ncf_options_t);
+    opt->precision = NCF_MIXED;
+    opt->method = NCF_AUTO;
+}
+
+const char* ncf_last_error(void) { return g_err.c_str(); }
+
+int ncf_version(void) { return 100; }
+
+void ncf_release_workspace(void) {
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    (void)hipDeviceSynchronize();
+    for (int w = 0; w < 2; ++w) {
+        auto it = g_ws[w].find(dev);
+        if (it != g_ws[w].end() && it->second.ptr) {
+            (void)hipFree(it->second.ptr);
+            it->second = DevBuf{};
+        }
+    }
+}
+
+int ncf_acf_batch(int64_t nser, const int64_t* offs, const double* t, const double* x,
+                  const double* err, int64_t K, const double* lags, int kern, const double* h,
+                  double* c, double* b, int64_t* count, int* status, const ncf_options_t* opt) {
+    clear_error();
+    Job J;
+    NCF_TRY(common_checks(opt, &J.opt, kern));
+    if (nser <= 0 || !t || !x || !h || (K > 0 && (!c || !b))) {
+        set_error("null argument or nser <= 0");
+        return NCF_E_INVALID_ARG;
+    }
+    int64_t total = 0;
+    NCF_TRY(check_offs(offs, nser, &total));
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    J.ccf = false;
+    J.nprob = nser;
+    J.kern = kern;
+    J.h.assign(h, h + nser);
+    J.c = c;
+    J.b = b;
+    J.count = count;
+    J.status = status;
+    J.dev_ptrs = (J.opt.flags & NCF_DEVICE_POINTERS) != 0;
+    J.st = (hipStream_t)J.opt.stream;
+    NCF_TRY(load_lags(J, K, lags));
+    J.set[0].ntot = total;
+    J.set[0].nser = (int)nser;
+    J.set[0].offs.assign(offs, offs + nser + 1);
+    const double* tin[2] = {t, nullptr};
+    const double* xin[2] = {x, nullptr};
+    const double* ein[2] = {err, nullptr};
+    return run_job(J, tin, xin, ein);
+}
+
+int ncf_ccf_batch(int64_t npair, const int64_t* offx, const double* tx, const double* x,
+                  const double* ex, const int64_t* offy, const double* ty, const double* y,
+                  const double* ey, int64_t K, const double* lags, int kern, const double* h,
+                  double* c, double* b, int64_t* count, int* status, const ncf_options_t* opt) {
+    clear_error();
+    Job J;
+    NCF_TRY(common_checks(opt, &J.opt, kern));
+    if (npair <= 0 || !tx || !x || !ty || !y || !h || (K > 0 && (!c || !b))) {
+        set_error("null argument or npair <= 0");
+        return NCF_E_INVALID_ARG;
+    }
+    int64_t totx = 0, toty = 0;
+    NCF_TRY(check_offs(offx, npair, &totx));
+    NCF_TRY(check_offs(offy, npair, &toty));
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    J.ccf = true;
+    J.nprob = npair;
+    J.kern = kern;
+    J.h.assign(h, h + npair);
+    J.c = c;
+    J.b = b;
+    J.count = count;
+    J.status = status;
+    J.dev_ptrs = (J.opt.flags & NCF_DEVICE_POINTERS) != 0;
+    J.st = (hipStream_t)J.opt.stream;
+    NCF_TRY(load_lags(J, K, lags));
+    J.set[0].ntot = totx;
+    J.set[0].nser = (int)npair;
+    J.set[0].offs.assign(offx, offx + npair + 1);
+    J.set[1].ntot = toty;
+    J.set[1].nser = (int)npair;
+    J.set[1].offs.assign(offy, offy + npair + 1);
+    const double* tin[2] = {tx, ty};
+    const double* xin[2] = {x, y};
+    const double* ein[2] = {ex, ey};
+    return run_job(J, tin, xin, ein);
+}
+
+int ncf_acf(int64_t n, const double* t, const double* x, const double* err, int64_t K,
+            const double* lags, int kern, double h, double* c, double* b, int64_t* count,
+            const ncf_options_t* opt) {
+    if (n < 2) {
+        set_error("n must be >= 2");
+        return NCF_E_INVALID_ARG;
+    }
+    int64_t offs[2] = {0, n};
+    return ncf_acf_batch(1, offs, t, x, err, K, lags, kern, &h, c, b, count, nullptr, opt);
+}
+
+int ncf_ccf(int64_t nx, const double* tx, const double* x, const double* ex, int64_t ny,
+            const double* ty, const double* y, const double* ey, int64_t K, const double* lags,
+            int kern, double h, double* c, double* b, int64_t* count, const ncf_options_t* opt) {
+    if (nx < 2 || ny < 2) {
+        set_error("nx and ny must be >= 2");
+        return NCF_E_INVALID_ARG;
+    }
+    int64_t ox[2] = {0, nx}, oy[2] = {0, ny};
+    return ncf_ccf_batch(1, ox, tx, x, ex, oy, ty, y, ey, K, lags, kern, &h, c, b, count,
+                         nullptr, opt);
+}
+
+// ------------------------------------------------------------- diagnostics
+
+int ncf_diag_fft_radices(int64_t N, int* radices, int max) {
+    clear_error();
+    if (N < 4096 || (N & (N - 1))) {
+        set_error("N must be a power of two >= 4096");
+        return NCF_E_INVALID_ARG;
+    }
+    int p = 0;
+    while ((1LL << p) < N) ++p;
+    int r[3], np;
+    if (p == 12) {
+        np = 1;
+        r[0] = 4096;
+    } else if (p <= 22) {
+        np = 2;
+        r[0] = 1 << (p - 12);
+        r[1] = 4096;
+    } else {
+        np = 3;
+        r[0] = 1 << ((p - 11) / 2);
+        r[1] = 1 << ((p - 12) / 2);
+        r[2] = 4096;
+    }
+    for (int i = 0; i < np && i < max; ++i) radices[i] = r[i];
+    return np;
+}
+
+int ncf_diag_fft(int64_t N, int precision, int sign, void* data) {
+    clear_error();
+    if (!data || (sign != 1 && sign != -1)) {
+        set_error("invalid argument");
+        return NCF_E_INVALID_ARG;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+        (void)hipGetLastError();
+        set_error("no HIP device available");
+        return NCF_E_DEVICE;
+    }
+    const bool fp64 = precision == NCF_FP64;
+    const size_t esz = fp64 ? 16 : 8;
+    FftPlan plan;
+    hipStream_t st = nullptr;
+    NCF_TRY(fft_plan(N, fp64, &plan, st));
+    std::vector<char> h((size_t)N * esz);
+    // the -1 transform consumes digit-reversed order: permute on the host
+    if (sign < 0) {
+        for (int64_t k = 0; k < N; ++k)
+            std::memcpy(&h[fft_position(plan, k) * esz], (char*)data + k * esz, esz);
+    } else {
+        std::memcpy(h.data(), data, (size_t)N * esz);
+    }
+    void* d = nullptr;
+    NCF_TRY_HIP(hipMalloc(&d, (size_t)N * esz));
+    void** dg = nullptr;
+    NCF_TRY_HIP(hipMalloc((void**)&dg, sizeof(void*)));
+    NCF_TRY_HIP(hipMemcpy(dg, &d, sizeof(void*), hipMemcpyHostToDevice));
+    NCF_TRY_HIP(hipMemcpy(d, h.data(), (size_t)N * esz, hipMemcpyHostToDevice));
+    int rc = fft_exec(plan, dg, 1, sign, fp64, st);
+    if (rc == NCF_OK) {
+        NCF_TRY_HIP(hipMemcpy(h.data(), d, (size_t)N * esz, hipMemcpyDeviceToHost));
+        if (sign > 0) {
+            for (int64_t k = 0; k < N; ++k)
+                std::memcpy((char*)data + k * esz, &h[fft_position(plan, k) * esz], esz);
+        } else {
+            std::memcpy(data, h.data(), (size_t)N * esz);
+        }
+    }
+    (void)hipFree(d);
+    (void)hipFree(dg);
+    return rc;
+}
+
+int ncf_diag_spread_params(double sigma, double eps, double* out) {
+    if (!out || !(sigma > 1.0) || !(eps > 0.0 && eps < 1.0)) return NCF_E_INVALID_ARG;
+    SpreadParams p = spread_params(sigma, eps);
+    out[0] = p.s;
+    out[1] = p.W;
+    return NCF_OK;
+}
+
+int ncf_diag_type1(int64_t n, const double* t, const double* v, double t_ref, double L,
+                   int64_t N, int64_t M, int precision, double* out) {
+    clear_error();
+    if (n < 1 || !t || !v || !out || !(L > 0) || N < 4096 || (N & (N - 1)) || M < 0 ||
+        2 * M + 1 > N) {
+        set_error("invalid argument");
+        return NCF_E_INVALID_ARG;
+    }
+    const bool fp64 = precision == NCF_FP64;
+    const double sigma = (double)N / (2.0 * M + 1.0);
+    if (sigma <= 1.0) return NCF_E_INVALID_ARG;
+    SpreadParams sp = spread_params(sigma, fp64 ? 1e-13 : 1e-7);
+    for (int64_t i = 0; i < n; ++i) {
+        const double u = (t[i] - t_ref) * ((double)N / L);
+        if (!(u >= sp.W + 2.0 && u <= (double)N - sp.W - 2.0) || (i && t[i] < t[i - 1])) {
+            set_error("sample %lld outside the no-wrap band or unsorted", (long long)i);
+            return NCF_E_INVALID_ARG;
+        }
+    }
+    hipStream_t st = nullptr;
+    const size_t esz = fp64 ? 16 : 8;
+    double* dt;
+    void* dv;
+    void* grid;
+    int64_t* rng;
+    SpecTask* dtask;
+    int64_t* dtile0;
+    void** dg;
+    NCF_TRY_HIP(hipMalloc((void**)&dt, sizeof(double) * n));
+    NCF_TRY_HIP(hipMalloc(&dv, (fp64 ? 8 : 4) * n));
+    NCF_TRY_HIP(hipMalloc(&grid, esz * N));
+    NCF_TRY_HIP(hipMalloc((void**)&rng, sizeof(int64_t) * 4 * (N / 4096)));
+    NCF_TRY_HIP(hipMalloc((void**)&dtask, sizeof(SpecTask)));
+    NCF_TRY_HIP(hipMalloc((void**)&dtile0, sizeof(int64_t) * 2));
+    NCF_TRY_HIP(hipMalloc((void**)&dg, sizeof(void*)));
+    NCF_TRY_HIP(hipMemcpy(dt, t, sizeof(double) * n, hipMemcpyHostToDevice));
+    if (fp64) {
+        NCF_TRY_HIP(hipMemcpy(dv, v, sizeof(double) * n, hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> vf(v, v + n);
+        NCF_TRY_HIP(hipMemcpy(dv, vf.data(), sizeof(float) * n, hipMemcpyHostToDevice));
+    }
+    SpecTask T{};
+    T.t0 = dt;
+    T.v0f = fp64 ? nullptr : (const float*)dv;
+    T.v0d = fp64 ? (const double*)dv : nullptr;
+    T.n0 = n;
+    T.t_ref = t_ref;
+    T.L = L;
+    T.N = N;
+    T.M = M;
+    T.s = sp.s;
+    T.W = sp.W;
+    T.grid = grid;
+    T.tile0 = 0;
+    T.ntiles = N / 4096;
+    T.tile_rng = rng;
+    int64_t t0h[2] = {0, T.ntiles};
+    NCF_TRY_HIP(hipMemcpy(dtask, &T, sizeof T, hipMemcpyHostToDevice));
+    NCF_TRY_HIP(hipMemcpy(dtile0, t0h, sizeof t0h, hipMemcpyHostToDevice));
+    NCF_TRY_HIP(hipMemcpy(dg, &grid, sizeof(void*), hipMemcpyHostToDevice));
+    int rc = launch_tile_ranges(dtask, dtile0, 1, T.ntiles, 4096, st);
+    if (rc == NCF_OK) rc = launch_spread(dtask, dtile0, 1, T.ntiles, 4096, fp64, st, 0.0);
+    FftPlan plan;
+    if (rc == NCF_OK) rc = fft_plan(N, fp64, &plan, st);
+    if (rc == NCF_OK) rc = fft_exec(plan, dg, 1, +1, fp64, st);
+    if (rc == NCF_OK) {
+        std::vector<char> h(esz * N);
+        NCF_TRY_HIP(hipMemcpy(h.data(), grid, esz * N, hipMemcpyDeviceToHost));
+        const double twopi = 2.0 * M_PI;
+        for (int64_t m = -M; m <= M; ++m) {
+            const int64_t k = m >= 0 ? m : m + N;
+            const int64_t p = fft_position(plan, k);
+            double re, im;
+            if (fp64) {
+                re = ((double*)h.data())[2 * p];
+                im = ((double*)h.data())[2 * p + 1];
+            } else {
+                re = ((float*)h.data())[2 * p];
+                im = ((float*)h.data())[2 * p + 1];
+            }
+            // deconvolve: divide by Psi(m/N) = sqrt(2 pi) s exp(-2 pi^2 s^2 (m/N)^2)
+            const double xi = (double)m / (double)N;
+            const double psi = std::sqrt(twopi) * sp.s * std::exp(-2.0 * M_PI * M_PI * sp.s * sp.s * xi * xi);
+            out[2 * (m + M)] = re / psi;
+            out[2 * (m + M) + 1] = im / psi;
+        }
+    }
+    (void)hipFree(dt);
+    (void)hipFree(dv);
+    (void)hipFree(grid);
+    (void)hipFree(rng);
+    (void)hipFree(dtask);
+    (void)hipFree(dtile0);
+    (void)hipFree(dg);
+    return rc;
+}
+
+void ncf_profile_enable(int on) {
+    std::lock_guard<std::mutex> lock(g_prof_mu);
+    if (on) {
+        prof_flush_locked();
+        g_prof.clear();
+    }
+    g_prof_on = on != 0;
+}
+
+int ncf_profile_read(ncf_profile_record_t* out, int max) {
+    (void)hipDeviceSynchronize();
+    std::lock_guard<std::mutex> lock(g_prof_mu);
+    prof_flush_locked();
+    int i = 0;
+    for (auto& kv : g_prof) {
+        if (i >= max) break;
+        ncf_profile_record_t& r = out[i++];
+        std::memset(&r, 0, sizeof r);
+        std::snprintf(r.name, sizeof r.name, "%s", kv.first.c_str());
+        r.launches = kv.second.launches;
+        r.total_ms = kv.second.ms;
+        r.work = kv.second.work;
+        std::snprintf(r.work_unit, sizeof r.work_unit, "%s", kv.second.unit.c_str());
+    }
+    return i;
+}
+
+}  // extern "C"

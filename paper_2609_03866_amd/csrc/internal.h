@@ -1,0 +1,232 @@
+// internal.h -- shared declarations of the ncf HIP library (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstddef>
+
+#include "ncf.h"
+
+namespace ncf {
+
+// ----------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define NCF_TRY_HIP(call)                                                              \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            ::ncf::set_error("%s:%d %s: %s", __FILE__, __LINE__, #call,                \
+                             hipGetErrorString(e_));                                   \
+            return NCF_E_DEVICE;                                                       \
+        }                                                                              \
+    } while (0)
+
+#define NCF_TRY(expr)              \
+    do {                           \
+        int st_ = (expr);          \
+        if (st_ != NCF_OK) return st_; \
+    } while (0)
+
+// Check the launch that was just enqueued.
+#define NCF_CHECK_LAUNCH() NCF_TRY_HIP(hipGetLastError())
+
+// -------------------------------------------------------------- profiling
+// Bracket a kernel launch with HIP events on `stream` when profiling is on.
+struct ProfScope {
+    ProfScope(hipStream_t stream, const char* name, double work, const char* unit);
+    ~ProfScope();
+    hipStream_t stream;
+    const char* name;
+    double work;
+    const char* unit;
+    void* ev0;
+};
+
+// ------------------------------------------------------------ constants
+constexpr double kFloor = 1e-16;        // pair-count floor (PairCount algorithms)
+constexpr int kWarp = 64;               // CDNA wavefront
+constexpr int kXcds = 8;                // MI355X accelerator complex dies
+
+// XCD-aware block index: consecutive logical tiles land on the same XCD
+// (hardware dispatches workgroup b to XCD b % 8). `nblocks` is the launched
+// grid (a multiple of 8); the result is a bijection of [0, nblocks).
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nblocks) {
+    int64_t per = nblocks / kXcds;
+    return (b % kXcds) * per + b / kXcds;
+}
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ----------------------------------------------------------- A1 moments
+struct SeriesDesc {
+    int64_t off;     // first sample in the concatenated arrays
+    int64_t n;       // samples
+    int64_t pre_off; // first entry of this series' prefix arrays (n+1 entries)
+    int32_t chunk0;  // first chunk of the series
+    int32_t nchunk;  // chunks of the series
+};
+
+struct Chunk {
+    int64_t begin, end;  // sample range [begin, end)
+    int32_t series;
+    int32_t pad;
+};
+
+struct SeriesStat {
+    double mean, sd, sw;  // weighted mean, sd (ddof 0), sum of weights
+    double tmin, tmax;
+    int32_t status;       // NCF_OK or a negative NCF_E_* code
+    int32_t pad;
+};
+
+struct MomentsArgs {
+    const double* t;
+    const double* x;
+    const double* err;      // may be null
+    const SeriesDesc* series;
+    const Chunk* chunks;
+    int32_t nseries, nchunks;
+    double* chunk_part;      // 4 doubles per chunk: sw, mean, M2, flags
+    SeriesStat* stats;       // nseries
+    // standardize outputs (each may be null)
+    float* v32;              // w * (x - mean)/sd, FP32
+    double* v64;             // same, FP64
+    double* w64;             // weights
+    double* pv;              // prefix of v64, n+1 per series
+    double* pw;              // prefix of w64, n+1 per series
+    double* chunk_tot;       // 2 doubles per chunk (v, w) totals for the prefix pass
+};
+
+int launch_moments(const MomentsArgs& a, hipStream_t st);
+int launch_standardize(const MomentsArgs& a, hipStream_t st);
+
+// ------------------------------------------------------- A7 window scan
+enum WinFlags : uint32_t {
+    WIN_RECT = 1u,       // rectangle kernel (else Gaussian)
+    WIN_NUMER = 2u,      // also accumulate the numerator C (Gaussian: direct sum)
+    WIN_WEIGHTED = 4u,   // accumulate the weighted pair sum B separately
+    WIN_EXP64 = 8u,      // Gaussian weights in FP64 (else FP32 exp of FP64 differences)
+};
+
+struct WinTask {
+    // window array (series 1 of a CCF, the series itself for an ACF)
+    const double* t;
+    const double* v;     // FP64 values (Gaussian numerator) or null
+    const double* w;     // FP64 weights or null
+    const double* pv;    // prefix of v (n_win + 1) or null
+    const double* pw;    // prefix of w (n_win + 1) or null
+    int64_t n_win;
+    // outer array (series 2 of a CCF)
+    const double* s;
+    const double* vo;
+    const double* wo;
+    int64_t n_out;
+    const double* delta; // K sorted lag offsets eps * tau
+    int32_t K;
+    int32_t J;           // outer samples per workgroup
+    int32_t n_jt, n_kt;  // tiles
+    double h;            // bandwidth
+    double W;            // window half-width: 6h (Gaussian) or h (rectangle)
+    double* part;        // [n_jt][K][4] partial sums: C, B, b, count (count as bits)
+    double* sums;        // [K][4] final sums
+    int64_t item0;       // first work item of this task
+};
+
+int launch_window(const WinTask* d_tasks, const int64_t* d_item0, int ntasks, int64_t nitems,
+                  uint32_t flags, int cap, int jmax, hipStream_t st, double work_units);
+int launch_window_reduce(const WinTask* d_tasks, int ntasks, int64_t total_k, const int64_t* d_k0,
+                         uint32_t flags, hipStream_t st);
+
+// --------------------------------------------------- A2-A6 spectral route
+struct SpreadParams {
+    double s;     // Gaussian spreading width (cells)
+    double W;     // truncation half-width (cells)
+};
+SpreadParams spread_params(double sigma, double eps);
+
+// One spectral problem: grid of N cells over period L.
+struct SpecTask {
+    // point sets: set 0 -> real channel, set 1 -> imaginary channel (CCF)
+    const double* t0; const float* v0f; const double* v0d; int64_t n0;
+    const double* t1; const float* v1f; const double* v1d; int64_t n1;
+    double t_ref;          // grid origin
+    double L;              // period
+    int64_t N;             // grid cells (power of two)
+    int64_t M;             // retained modes |m| <= M
+    double s, W;           // spreading kernel
+    double h;              // lag-kernel bandwidth
+    int32_t kern;          // NCF_GAUSSIAN / NCF_RECTANGLE (diagnostic)
+    int32_t ccf;           // 1: packed two-series grid
+    void* grid;            // N complex (float2 or double2)
+    int64_t tile0;         // first spreading tile of this task
+    int64_t ntiles;
+    int64_t* tile_rng;     // [ntiles][4]: p0, p1 of set 0 and of set 1
+    double* lags;          // K_eval lags to evaluate (device)
+    int32_t K_eval;
+    int32_t pad;
+    double* numer;         // K_eval results N(tau)
+    double* scale_part;    // per-workgroup partial (S_xx, S_yy) pairs, product kernel
+    int64_t pos0;          // first element offset of this task in the flattened product launch
+};
+
+int launch_tile_ranges(const SpecTask* d_tasks, const int64_t* d_tile0, int ntasks,
+                       int64_t ntiles, int tile, hipStream_t st);
+int launch_spread(const SpecTask* d_tasks, const int64_t* d_tile0, int ntasks, int64_t ntiles,
+                  int tile, bool fp64, hipStream_t st, double bytes);
+int launch_interp(const SpecTask* d_tasks, int ntasks, const int64_t* d_k0, int64_t total_k,
+                  bool fp64, hipStream_t st);
+
+// FFT (A4)
+struct FftPlan {
+    int64_t N;
+    int npass;
+    int radix[4];       // first pass first
+    int64_t stride[4];  // S of each pass
+    // twiddles: wlo[e] = w_N^e (e < 2^b), whi[e] = w_N^(e << b); small[e] = w_4096^e
+    int lobits;
+    void* wlo;  // float2 or double2
+    void* whi;
+    void* small;
+};
+int fft_plan(int64_t N, bool fp64, FftPlan* plan, hipStream_t st);  // tables cached per (N, fp64)
+// Batched transform of `count` grids of the same N laid out at `grids[i]`.
+// sign +1: natural -> digit-reversed; sign -1: digit-reversed -> natural.
+int fft_exec(const FftPlan& plan, void* const* d_grids, int count, int sign, bool fp64,
+             hipStream_t st);
+// storage position of frequency k after the sign +1 transform
+int64_t fft_position(const FftPlan& plan, int64_t k);
+
+// A5 spectral product (in place, digit-reversed order)
+int launch_product(const SpecTask* d_tasks, const int64_t* d_pos0, int ntasks, int64_t total,
+                   const int64_t* d_radix_info, bool fp64, hipStream_t st, double bytes);
+
+// ------------------------------------------------------------ A8 output
+struct NormTask {
+    int32_t ccf;          // 0 ACF, 1 CCF
+    int32_t K;            // requested lags
+    const int32_t* perm;  // requested lag k -> row of the window sums
+    int32_t row0;         // ACF: row of lag 0 in the window sums
+    int32_t spectral;     // numerator from the spectral route
+    const double* wsums;  // window sums [K_rows][4]
+    const double* numer;  // spectral numerator per requested lag (+ lag 0 last for ACF)
+    const double* self_x; // CCF: window sums of series 1 on itself at lag 0 ([4])
+    const double* self_y; // CCF: window sums of series 2 on itself at lag 0
+    const double* scale_part; // CCF spectral: partial (S_xx, S_yy) pairs
+    int64_t nscale_part;
+    int32_t weighted;
+    int32_t is_rect;
+    int32_t skip;         // problem failed validation: write nothing
+    int32_t pad;
+    int32_t* status;      // per-task status (device)
+    double* c;            // K outputs
+    double* b;
+    int64_t* count;       // may be null
+};
+int launch_normalize(const NormTask* d_tasks, int ntasks, int64_t total_k, const int64_t* d_k0,
+                     hipStream_t st);
+
+}  // namespace ncf

@@ -1,0 +1,427 @@
+// spectral.hip -- Wiener-Khinchin route for the Gaussian numerator (A2-A6).
+//
+// The numerator of eq. kernel_estimator with the Gaussian kernel is
+//   N(tau) = sum_ij v_i v'_j phi_h(s_j - t_i - tau)
+//          = (1/L) sum_m phihat(m/L) conj(X_m) Y_m exp(-2 pi i m tau / L)
+// on a period L long enough that the periodic images of phi_h do not reach
+// the data (Poisson summation), with X_m = sum_i v_i exp(+2 pi i m t_i / L)
+// the type-1 transform of eq. nufft_type1 and phihat(f) = exp(-2 pi^2 h^2 f^2)
+// the Fourier transform of eq. Gaussian_kernel. Sec. 2.6 evaluates the same
+// identity with a type-1 NUFFT, a cross-spectrum product and a type-2 NUFFT at
+// the lags; here the lag kernel's transform multiplies the cross-spectrum
+// directly instead of smoothing along the lag axis afterwards.
+//
+// Both non-uniform transforms use Gaussian gridding (Sec. 2.5: spread, FFT,
+// deconvolve): psi(d) = exp(-d^2 / 2 s^2) on a grid of N cells, truncated at
+// |d| <= W cells, whose transform Psi(xi) = sqrt(2 pi) s exp(-2 pi^2 s^2 xi^2)
+// is closed form. The product step therefore folds phihat, the forward
+// deconvolution 1/Psi^2 and the type-2 pre-correction 1/Psi into one factor
+//   exp(-2 pi^2 m^2 (h^2/L^2 - 3 s^2/N^2)) / (L (2 pi)^(3/2) s^3).
+//
+// Positions are split in FP64 into an integer cell and an FP32 (or FP64)
+// fraction before any FP32 arithmetic, so long baselines keep their phase.
+// Spreading gathers: each workgroup owns a tile of grid cells, stages the
+// samples that can reach it (sorted times -> contiguous index range) in LDS,
+// and every thread sums the samples near its own cells. No atomics; one
+// coalesced write per cell; deterministic.
+#include "internal.h"
+
+namespace ncf {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kCellsPerThread = 16;
+constexpr int kTile = kThreads * kCellsPerThread;  // 4096 cells per workgroup
+constexpr int kPtsChunk = 2048;
+
+template <typename R>
+struct Cplx;
+template <>
+struct Cplx<float> {
+    using T = float2;
+};
+template <>
+struct Cplx<double> {
+    using T = double2;
+};
+
+__device__ __forceinline__ int64_t find_task(const int64_t* starts, int ntasks, int64_t g) {
+    int lo = 0, hi = ntasks;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (starts[mid] <= g)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int64_t lower_bound_d(const double* a, int64_t n, double key) {
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (a[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Sample index ranges that can reach each tile: [p0, p1) per point set.
+__global__ void k_tile_ranges(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ tile0,
+                              int ntasks, int64_t ntiles) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ntiles) return;
+    const int ti = (int)find_task(tile0, ntasks, g);
+    const SpecTask& T = tasks[ti];
+    const int64_t tile = g - T.tile0;
+    const double c0 = (double)(tile * kTile);
+    const double inv_scale = T.L / (double)T.N;  // time per cell
+    const double lo_t = T.t_ref + (c0 - T.W - 2.0) * inv_scale;
+    const double hi_t = T.t_ref + (c0 + kTile + T.W + 2.0) * inv_scale;
+    int64_t* r = T.tile_rng + 4 * tile;
+    r[0] = lower_bound_d(T.t0, T.n0, lo_t);
+    r[1] = lower_bound_d(T.t0, T.n0, hi_t);
+    if (T.ccf) {
+        r[2] = lower_bound_d(T.t1, T.n1, lo_t);
+        r[3] = lower_bound_d(T.t1, T.n1, hi_t);
+    } else {
+        r[2] = r[3] = 0;
+    }
+}
+
+template <typename R>
+struct PtsLds {
+    int cell[kPtsChunk];  // cell index relative to the tile start
+    R frac[kPtsChunk];    // fraction in [0, 1)
+    R val[kPtsChunk];
+};
+
+// Accumulate one point set into the thread's 16 cells.
+template <typename R>
+__device__ void gather_set(R (&acc)[kCellsPerThread], PtsLds<R>& P, const double* t, const float* vf,
+                           const double* vd, int64_t p0, int64_t p1, int64_t c0, double t_ref,
+                           double scale, R W, R k2) {
+    const int tid = threadIdx.x;
+    const int cb = tid * kCellsPerThread;  // first own cell, relative to tile
+    for (int64_t base = p0; base < p1; base += kPtsChunk) {
+        const int np = (int)min((int64_t)kPtsChunk, p1 - base);
+        __syncthreads();
+        for (int i = tid; i < np; i += kThreads) {
+            const double u = (t[base + i] - t_ref) * scale;  // FP64 grid coordinate
+            const double cf = floor(u);
+            P.cell[i] = (int)((int64_t)cf - c0);
+            P.frac[i] = (R)(u - cf);
+            P.val[i] = vd ? (R)vd[base + i] : (R)vf[base + i];
+        }
+        __syncthreads();
+        // first staged point whose cell can reach cell cb: cell >= cb - W - 1
+        const int need_lo = cb - (int)W - 2;
+        const int need_hi = cb + kCellsPerThread + (int)W + 1;
+        int lo = 0, hi = np;
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if (P.cell[mid] < need_lo)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        for (int i = lo; i < np; ++i) {
+            const int ci = P.cell[i];
+            if (ci > need_hi) break;
+            const R fr = P.frac[i];
+            const R vv = P.val[i];
+#pragma unroll
+            for (int q = 0; q < kCellsPerThread; ++q) {
+                const R d = (R)(ci - (cb + q)) + fr;
+                if (d <= W && d >= -W) {
+                    R e;
+                    if constexpr (sizeof(R) == 4)
+                        e = __builtin_amdgcn_exp2f(d * d * k2);
+                    else
+                        e = exp(d * d * k2);
+                    acc[q] += e * vv;
+                }
+            }
+        }
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kThreads)
+k_spread(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ tile0, int ntasks,
+         int64_t ntiles, int64_t nblocks) {
+    using C2 = typename Cplx<R>::T;
+    __shared__ PtsLds<R> P;
+    const int64_t g = xcd_remap(blockIdx.x, nblocks);
+    if (g >= ntiles) return;
+    const int ti = (int)find_task(tile0, ntasks, g);
+    const SpecTask& T = tasks[ti];
+    const int64_t tile = g - T.tile0;
+    const int64_t c0 = tile * kTile;
+    const int64_t* rng = T.tile_rng + 4 * tile;
+    const double scale = (double)T.N / T.L;
+    const R W = (R)T.W;
+    // exp(-d^2 / 2 s^2): FP32 uses exp2 with log2(e) folded in
+    const R k2 = sizeof(R) == 4 ? (R)(-0.72134752044448170 / (T.s * T.s))
+                                : (R)(-0.5 / (T.s * T.s));
+    R re[kCellsPerThread], im[kCellsPerThread];
+#pragma unroll
+    for (int q = 0; q < kCellsPerThread; ++q) re[q] = im[q] = (R)0;
+    gather_set<R>(re, P, T.t0, T.v0f, T.v0d, rng[0], rng[1], c0, T.t_ref, scale, W, k2);
+    if (T.ccf) gather_set<R>(im, P, T.t1, T.v1f, T.v1d, rng[2], rng[3], c0, T.t_ref, scale, W, k2);
+    // stage the tile through LDS for a coalesced write
+    __syncthreads();
+    C2* out = reinterpret_cast<C2*>(&P);
+    static_assert(sizeof(PtsLds<R>) >= sizeof(C2) * kTile / 2, "LDS staging too small");
+    C2* grid = reinterpret_cast<C2*>(T.grid) + c0;
+    // two halves so the staging fits the point buffer
+    for (int half = 0; half < 2; ++half) {
+        const int hbase = half * (kTile / 2);
+        const int tb = threadIdx.x * kCellsPerThread - hbase;
+        if (tb >= 0 && tb < kTile / 2) {
+#pragma unroll
+            for (int q = 0; q < kCellsPerThread; ++q) {
+                C2 v;
+                v.x = re[q];
+                v.y = im[q];
+                out[tb + q] = v;
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < kTile / 2; i += kThreads) grid[hbase + i] = out[i];
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- product
+
+struct RadixInfo {
+    int npass;
+    int lg[4];  // log2 radix of each pass (first pass first)
+    int lgN;
+};
+
+__device__ __forceinline__ int64_t freq_of_pos(int64_t p, const RadixInfo& ri) {
+    // p = sum_i d_i * 2^(lgN - B_i), k = sum_i d_i * 2^(B_{i-1})
+    int64_t k = 0;
+    int B = 0;
+    for (int i = 0; i < ri.npass; ++i) {
+        const int lg = ri.lg[i];
+        const int64_t d = (p >> (ri.lgN - B - lg)) & ((1LL << lg) - 1);
+        k |= d << B;
+        B += lg;
+    }
+    return k;
+}
+
+__device__ __forceinline__ int64_t pos_of_freq(int64_t k, const RadixInfo& ri) {
+    int64_t p = 0;
+    int B = 0;
+    for (int i = 0; i < ri.npass; ++i) {
+        const int lg = ri.lg[i];
+        const int64_t d = (k >> B) & ((1LL << lg) - 1);
+        p |= d << (ri.lgN - B - lg);
+        B += lg;
+    }
+    return p;
+}
+
+template <typename R>
+__device__ __forceinline__ double lag_kernel_ft(int kern, double f, double h) {
+    if (kern == NCF_GAUSSIAN) return exp(-2.0 * M_PI * M_PI * h * h * f * f);
+    // box of half-width h: integral_{-h}^{h} exp(2 pi i f d) dd = sin(2 pi h f) / (pi f)
+    if (f == 0.0) return 2.0 * h;
+    return sin(2.0 * M_PI * h * f) / (M_PI * f);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kThreads)
+k_product(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pos0, int ntasks,
+          int64_t total, const RadixInfo* __restrict__ rinfo) {
+    using C2 = typename Cplx<R>::T;
+    __shared__ double red[2][kThreads];
+    const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int64_t gb = (int64_t)blockIdx.x * kThreads;  // whole block in one task
+    const int ti = (int)find_task(pos0, ntasks, gb);
+    const SpecTask& T = tasks[ti];
+    const RadixInfo ri = rinfo[ti];
+    const int64_t p = g - T.pos0;
+    const int64_t N = T.N;
+    C2* Z = reinterpret_cast<C2*>(T.grid);
+    const double L = T.L, h = T.h, s = T.s;
+    const double Nd = (double)N;
+    double sxx = 0.0, syy = 0.0;
+    if (p < N) {
+        const int64_t k = freq_of_pos(p, ri);
+        const int64_t m = k <= N / 2 ? k : k - N;
+        const double md = (double)m;
+        const bool keep = (m <= T.M && m >= -T.M);
+        // 1/Psi(m/N) = exp(2 pi^2 s^2 m^2 / N^2) / (sqrt(2 pi) s)
+        const double e_psi = 2.0 * M_PI * M_PI * s * s * md * md / (Nd * Nd);
+        const double ker = keep ? lag_kernel_ft<R>(T.kern, md / L, h) : 0.0;
+        // phihat / (L Psi^3) and phihat / (L Psi^2)
+        const double f3 = ker * exp(3.0 * e_psi) / (L * 15.749609945722419 * s * s * s);
+        const double f2 = ker * exp(2.0 * e_psi) / (L * 6.283185307179586 * s * s);
+        if (!T.ccf) {
+            const C2 z = Z[p];
+            const double pw = (double)z.x * z.x + (double)z.y * z.y;
+            C2 o;
+            o.x = (R)(f3 * pw);
+            o.y = (R)0;
+            Z[p] = o;
+        } else if (k <= N - k || k == 0) {
+            // pair (m, -m): unpack the packed x (real) / y (imaginary) spectra
+            const int64_t kp = (N - k) & (N - 1);
+            const int64_t pp = pos_of_freq(kp, ri);
+            const C2 za = Z[p];
+            const C2 zb = Z[pp];
+            // Fx = (Z_m + conj Z_-m)/2, Fy = (Z_m - conj Z_-m)/(2i)
+            const double fxr = 0.5 * ((double)za.x + zb.x), fxi = 0.5 * ((double)za.y - zb.y);
+            const double fyr = 0.5 * ((double)za.y + zb.y), fyi = -0.5 * ((double)za.x - zb.x);
+            // conj(Fx) * Fy
+            const double gr = fxr * fyr + fxi * fyi;
+            const double gi = fxr * fyi - fxi * fyr;
+            C2 o;
+            o.x = (R)(f3 * gr);
+            o.y = (R)(f3 * gi);
+            Z[p] = o;
+            if (pp != p) {
+                C2 oc;
+                oc.x = o.x;
+                oc.y = -o.y;
+                Z[pp] = oc;
+            }
+            const double mult = (pp != p) ? 2.0 : 1.0;
+            sxx = mult * f2 * (fxr * fxr + fxi * fxi);
+            syy = mult * f2 * (fyr * fyr + fyi * fyi);
+        }
+    }
+    if (T.ccf) {
+        red[0][threadIdx.x] = sxx;
+        red[1][threadIdx.x] = syy;
+        __syncthreads();
+        for (int off = kThreads / 2; off > 0; off >>= 1) {
+            if (threadIdx.x < off) {
+                red[0][threadIdx.x] += red[0][threadIdx.x + off];
+                red[1][threadIdx.x] += red[1][threadIdx.x + off];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            const int64_t wg = (gb - T.pos0) / kThreads;
+            T.scale_part[2 * wg] = red[0][0];
+            T.scale_part[2 * wg + 1] = red[1][0];
+        }
+    }
+}
+
+// --------------------------------------------------------- type-2 at lags
+
+template <typename R>
+__global__ void k_interp(const SpecTask* __restrict__ tasks, int ntasks, const int64_t* __restrict__ k0s,
+                         int64_t total_k) {
+    using C2 = typename Cplx<R>::T;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total_k) return;
+    const int ti = (int)find_task(k0s, ntasks, g);
+    const SpecTask& T = tasks[ti];
+    const int k = (int)(g - k0s[ti]);
+    const double tau = T.lags[k];
+    const double Nd = (double)T.N;
+    double u = tau * (Nd / T.L);
+    u -= Nd * floor(u / Nd);  // wrap to [0, N)
+    const double cf = floor(u);
+    const double fr = u - cf;
+    const int64_t cell = (int64_t)cf;
+    const C2* G = reinterpret_cast<const C2*>(T.grid);
+    const int wi = (int)ceil(T.W);
+    const double kk = -0.5 / (T.s * T.s);
+    double acc = 0.0;
+    for (int q = -wi - 1; q <= wi + 1; ++q) {
+        const double d = fr - (double)q;  // u - (cell + q)
+        if (d > T.W || d < -T.W) continue;
+        const int64_t c = (cell + q) & (T.N - 1);
+        acc += (double)G[c].x * exp(d * d * kk);
+    }
+    T.numer[k] = acc;
+}
+
+}  // namespace
+
+SpreadParams spread_params(double sigma, double eps) {
+    // aliasing exp(-2 pi^2 s^2 (1 - 1/sigma)) and truncation exp(-W^2/2s^2)
+    // both set to eps
+    const double Le = -log(eps);
+    SpreadParams p;
+    p.s = sqrt(Le / (2.0 * M_PI * M_PI * (1.0 - 1.0 / sigma)));
+    p.W = p.s * sqrt(2.0 * Le);
+    return p;
+}
+
+int launch_tile_ranges(const SpecTask* d_tasks, const int64_t* d_tile0, int ntasks,
+                       int64_t ntiles, int tile, hipStream_t st) {
+    if (tile != kTile) {
+        set_error("spread tile mismatch");
+        return NCF_E_UNSUPPORTED;
+    }
+    if (ntiles <= 0) return NCF_OK;
+    ProfScope p(st, "tile_ranges", 0.0, "bytes");
+    hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)ceil_div(ntiles, 128)), dim3(128), 0, st,
+                       d_tasks, d_tile0, ntasks, ntiles);
+    NCF_CHECK_LAUNCH();
+    return NCF_OK;
+}
+
+int launch_spread(const SpecTask* d_tasks, const int64_t* d_tile0, int ntasks, int64_t ntiles,
+                  int tile, bool fp64, hipStream_t st, double bytes) {
+    if (tile != kTile) {
+        set_error("spread tile mismatch");
+        return NCF_E_UNSUPPORTED;
+    }
+    if (ntiles <= 0) return NCF_OK;
+    const int64_t nblocks = round_up(ntiles, kXcds);
+    ProfScope p(st, fp64 ? "spread_f64" : "spread_f32", bytes, "bytes");
+    if (fp64)
+        hipLaunchKernelGGL(k_spread<double>, dim3((unsigned)nblocks), dim3(kThreads), 0, st,
+                           d_tasks, d_tile0, ntasks, ntiles, nblocks);
+    else
+        hipLaunchKernelGGL(k_spread<float>, dim3((unsigned)nblocks), dim3(kThreads), 0, st,
+                           d_tasks, d_tile0, ntasks, ntiles, nblocks);
+    NCF_CHECK_LAUNCH();
+    return NCF_OK;
+}
+
+int launch_product(const SpecTask* d_tasks, const int64_t* d_pos0, int ntasks, int64_t total,
+                   const int64_t* d_radix_info, bool fp64, hipStream_t st, double bytes) {
+    if (total <= 0) return NCF_OK;
+    const RadixInfo* ri = reinterpret_cast<const RadixInfo*>(d_radix_info);
+    ProfScope p(st, fp64 ? "product_f64" : "product_f32", bytes, "bytes");
+    if (fp64)
+        hipLaunchKernelGGL(k_product<double>, dim3((unsigned)ceil_div(total, kThreads)),
+                           dim3(kThreads), 0, st, d_tasks, d_pos0, ntasks, total, ri);
+    else
+        hipLaunchKernelGGL(k_product<float>, dim3((unsigned)ceil_div(total, kThreads)),
+                           dim3(kThreads), 0, st, d_tasks, d_pos0, ntasks, total, ri);
+    NCF_CHECK_LAUNCH();
+    return NCF_OK;
+}
+
+int launch_interp(const SpecTask* d_tasks, int ntasks, const int64_t* d_k0, int64_t total_k,
+                  bool fp64, hipStream_t st) {
+    if (total_k <= 0) return NCF_OK;
+    ProfScope p(st, "interp", 0.0, "bytes");
+    if (fp64)
+        hipLaunchKernelGGL(k_interp<double>, dim3((unsigned)ceil_div(total_k, 128)), dim3(128), 0,
+                           st, d_tasks, ntasks, d_k0, total_k);
+    else
+        hipLaunchKernelGGL(k_interp<float>, dim3((unsigned)ceil_div(total_k, 128)), dim3(128), 0,
+                           st, d_tasks, ntasks, d_k0, total_k);
+    NCF_CHECK_LAUNCH();
+    return NCF_OK;
+}
+
+}  // namespace ncf

@@ -1,0 +1,281 @@
+"""Thin ctypes binding of the ncf C ABI (include/ncf.h, include/ncf_diag.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library. Host arrays (numpy) are passed as host pointers; torch CUDA tensors
+are passed as device pointers on torch's current stream
+(NCF_DEVICE_POINTERS). Loading fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libncf.so")
+
+GAUSSIAN, RECTANGLE = 0, 1
+MIXED, FP64 = 0, 1
+AUTO, SPECTRAL, DIRECT = 0, 1, 2
+DEVICE_POINTERS = 0x1
+
+OK = 0
+E_INVALID_ARG = -1
+E_UNSORTED = -2
+E_DEGENERATE = -3
+E_NOMEM = -4
+E_DEVICE = -5
+E_UNSUPPORTED = -6
+
+
+class NcfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ncf error {code}: {msg}")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("precision", ctypes.c_int32),
+                ("method", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("sigma", ctypes.c_double), ("grid_size", ctypes.c_int64),
+                ("stream", ctypes.c_void_p), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class ProfileRecord(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double), ("work", ctypes.c_double),
+                ("work_unit", ctypes.c_char * 16)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+
+
+def lib():
+    """Load libncf.so (built by paper_2609_03866_amd.build). Raises if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2609_03866_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        L.ncf_acf.argtypes = [_I64, _P, _P, _P, _I64, _P, ctypes.c_int, ctypes.c_double, _P, _P,
+                              _P, _P]
+        L.ncf_ccf.argtypes = [_I64, _P, _P, _P, _I64, _P, _P, _P, _I64, _P, ctypes.c_int,
+                              ctypes.c_double, _P, _P, _P, _P]
+        L.ncf_acf_batch.argtypes = [_I64, _P, _P, _P, _P, _I64, _P, ctypes.c_int, _P, _P, _P, _P,
+                                    _P, _P]
+        L.ncf_ccf_batch.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _I64, _P,
+                                    ctypes.c_int, _P, _P, _P, _P, _P, _P]
+        L.ncf_last_error.restype = ctypes.c_char_p
+        L.ncf_options_init.argtypes = [_P]
+        L.ncf_diag_fft.argtypes = [_I64, ctypes.c_int, ctypes.c_int, _P]
+        L.ncf_diag_fft_radices.argtypes = [_I64, _P, ctypes.c_int]
+        L.ncf_diag_type1.argtypes = [_I64, _P, _P, ctypes.c_double, ctypes.c_double, _I64, _I64,
+                                     ctypes.c_int, _P]
+        L.ncf_diag_spread_params.argtypes = [ctypes.c_double, ctypes.c_double, _P]
+        L.ncf_profile_enable.argtypes = [ctypes.c_int]
+        L.ncf_profile_read.argtypes = [_P, ctypes.c_int]
+        _lib = L
+    return _lib
+
+
+def _kern(k):
+    if isinstance(k, str):
+        return {"gaussian": GAUSSIAN, "g": GAUSSIAN, "rectangle": RECTANGLE, "r": RECTANGLE}[
+            k.lower()]
+    return int(k)
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+class _Marshal:
+    """Collects pointers for one call; keeps host copies alive."""
+
+    def __init__(self, device):
+        self.device = device
+        self.keep = []
+
+    def inp(self, a, dtype=np.float64):
+        if a is None:
+            return None
+        if self.device:
+            import torch
+            assert a.is_cuda and a.dtype == torch.float64 and a.is_contiguous(), \
+                "device arrays must be contiguous float64 CUDA tensors"
+            return a.data_ptr()
+        a = np.ascontiguousarray(a, dtype=dtype)
+        self.keep.append(a)
+        return a.ctypes.data
+
+    def out(self, n, dtype):
+        if self.device:
+            import torch
+            tdt = {np.float64: torch.float64, np.int64: torch.int64}[dtype]
+            t = torch.empty(n, dtype=tdt, device=self.device)
+            self.keep.append(t)
+            return t, t.data_ptr()
+        a = np.empty(n, dtype=dtype)
+        self.keep.append(a)
+        return a, a.ctypes.data
+
+
+def _options(precision, method, tol, sigma, grid_size, device, stream):
+    o = Options()
+    lib().ncf_options_init(ctypes.byref(o))
+    o.precision = {"mixed": MIXED, "fp64": FP64}.get(precision, precision) \
+        if isinstance(precision, str) else int(precision)
+    o.method = {"auto": AUTO, "spectral": SPECTRAL, "direct": DIRECT}.get(method, method) \
+        if isinstance(method, str) else int(method)
+    o.tol = float(tol or 0.0)
+    o.sigma = float(sigma or 0.0)
+    o.grid_size = int(grid_size or 0)
+    if device:
+        import torch
+        o.flags = DEVICE_POINTERS
+        o.stream = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    return o
+
+
+def _check(rc, allow=()):
+    if rc != OK and rc not in allow:
+        raise NcfError(rc, lib().ncf_last_error().decode())
+    return rc
+
+
+def acf(t, x, lags, kernel="gaussian", h=1.0, err=None, precision="mixed", method="auto",
+        tol=0.0, sigma=0.0, grid_size=0, with_count=True, raise_on_error=True, stream=None):
+    """ncf_acf. Returns (c, b, count, status). numpy in -> numpy out; torch CUDA
+    tensors in -> torch CUDA tensors out (stream-ordered on `stream`)."""
+    dev = t.device if _is_torch(t) else None
+    m = _Marshal(dev)
+    K = int(lags.numel() if _is_torch(lags) else np.asarray(lags).size)
+    c, pc = m.out(K, np.float64)
+    b, pb = m.out(K, np.float64)
+    cnt, pn = m.out(K, np.int64) if with_count else (None, None)
+    n = int(t.numel() if _is_torch(t) else np.asarray(t).size)
+    o = _options(precision, method, tol, sigma, grid_size, dev, stream)
+    rc = lib().ncf_acf(n, m.inp(t), m.inp(x), m.inp(err), K, m.inp(lags), _kern(kernel),
+                       float(h), pc, pb, pn, ctypes.byref(o))
+    if raise_on_error:
+        _check(rc)
+    return c, b, cnt, rc
+
+
+def ccf(t, x, s, y, lags, kernel="gaussian", h=1.0, ex=None, ey=None, precision="mixed",
+        method="auto", tol=0.0, sigma=0.0, grid_size=0, with_count=True, raise_on_error=True,
+        stream=None):
+    """ncf_ccf (lag +tau: series 2 (s, y) lags series 1 (t, x) by tau)."""
+    dev = t.device if _is_torch(t) else None
+    m = _Marshal(dev)
+    K = int(lags.numel() if _is_torch(lags) else np.asarray(lags).size)
+    c, pc = m.out(K, np.float64)
+    b, pb = m.out(K, np.float64)
+    cnt, pn = m.out(K, np.int64) if with_count else (None, None)
+    nx = int(t.numel() if _is_torch(t) else np.asarray(t).size)
+    ny = int(s.numel() if _is_torch(s) else np.asarray(s).size)
+    o = _options(precision, method, tol, sigma, grid_size, dev, stream)
+    rc = lib().ncf_ccf(nx, m.inp(t), m.inp(x), m.inp(ex), ny, m.inp(s), m.inp(y), m.inp(ey), K,
+                       m.inp(lags), _kern(kernel), float(h), pc, pb, pn, ctypes.byref(o))
+    if raise_on_error:
+        _check(rc)
+    return c, b, cnt, rc
+
+
+def acf_batch(offs, t, x, lags, kernel="gaussian", h=1.0, err=None, precision="mixed",
+              method="auto", tol=0.0, sigma=0.0, grid_size=0, with_count=True,
+              raise_on_error=True, stream=None):
+    """ncf_acf_batch over CSR series. Returns (c[nser, K], b, count, status[nser], rc)."""
+    offs = np.ascontiguousarray(offs, dtype=np.int64)
+    nser = offs.size - 1
+    hs = np.ascontiguousarray(np.broadcast_to(np.asarray(h, dtype=np.float64), (nser,)))
+    dev = t.device if _is_torch(t) else None
+    m = _Marshal(dev)
+    K = int(lags.numel() if _is_torch(lags) else np.asarray(lags).size)
+    c, pc = m.out(nser * K, np.float64)
+    b, pb = m.out(nser * K, np.float64)
+    cnt, pn = m.out(nser * K, np.int64) if with_count else (None, None)
+    st = np.zeros(nser, dtype=np.int32)
+    o = _options(precision, method, tol, sigma, grid_size, dev, stream)
+    rc = lib().ncf_acf_batch(nser, offs.ctypes.data, m.inp(t), m.inp(x), m.inp(err), K,
+                             m.inp(lags), _kern(kernel), hs.ctypes.data, pc, pb, pn,
+                             st.ctypes.data, ctypes.byref(o))
+    if raise_on_error:
+        _check(rc)
+    rs = (lambda a: a.reshape(nser, K) if a is not None else None)
+    return rs(c), rs(b), rs(cnt), st, rc
+
+
+def ccf_batch(offx, t, x, offy, s, y, lags, kernel="gaussian", h=1.0, ex=None, ey=None,
+              precision="mixed", method="auto", tol=0.0, sigma=0.0, grid_size=0,
+              with_count=True, raise_on_error=True, stream=None):
+    """ncf_ccf_batch over CSR series pairs."""
+    offx = np.ascontiguousarray(offx, dtype=np.int64)
+    offy = np.ascontiguousarray(offy, dtype=np.int64)
+    npair = offx.size - 1
+    hs = np.ascontiguousarray(np.broadcast_to(np.asarray(h, dtype=np.float64), (npair,)))
+    dev = t.device if _is_torch(t) else None
+    m = _Marshal(dev)
+    K = int(lags.numel() if _is_torch(lags) else np.asarray(lags).size)
+    c, pc = m.out(npair * K, np.float64)
+    b, pb = m.out(npair * K, np.float64)
+    cnt, pn = m.out(npair * K, np.int64) if with_count else (None, None)
+    st = np.zeros(npair, dtype=np.int32)
+    o = _options(precision, method, tol, sigma, grid_size, dev, stream)
+    rc = lib().ncf_ccf_batch(npair, offx.ctypes.data, m.inp(t), m.inp(x), m.inp(ex),
+                             offy.ctypes.data, m.inp(s), m.inp(y), m.inp(ey), K, m.inp(lags),
+                             _kern(kernel), hs.ctypes.data, pc, pb, pn, st.ctypes.data,
+                             ctypes.byref(o))
+    if raise_on_error:
+        _check(rc)
+    rs = (lambda a: a.reshape(npair, K) if a is not None else None)
+    return rs(c), rs(b), rs(cnt), st, rc
+
+
+# ------------------------------------------------------------- diagnostics
+
+def diag_fft(x, sign=+1, precision="mixed"):
+    """ncf_diag_fft on a complex numpy array (natural order in and out)."""
+    fp64 = precision in ("fp64", FP64)
+    a = np.ascontiguousarray(x, dtype=np.complex128 if fp64 else np.complex64).copy()
+    _check(lib().ncf_diag_fft(a.size, FP64 if fp64 else MIXED, int(sign), a.ctypes.data))
+    return a
+
+
+def diag_fft_radices(N):
+    r = np.zeros(4, dtype=np.int32)
+    n = lib().ncf_diag_fft_radices(int(N), r.ctypes.data, 4)
+    _check(n if n < 0 else OK)
+    return [int(v) for v in r[:n]]
+
+
+def diag_type1(t, v, t_ref, L, N, M, precision="mixed"):
+    t = np.ascontiguousarray(t, dtype=np.float64)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    out = np.zeros(2 * (2 * M + 1))
+    _check(lib().ncf_diag_type1(t.size, t.ctypes.data, v.ctypes.data, float(t_ref), float(L),
+                                int(N), int(M), FP64 if precision in ("fp64", FP64) else MIXED,
+                                out.ctypes.data))
+    return out[0::2] + 1j * out[1::2]
+
+
+def diag_spread_params(sigma, eps):
+    out = np.zeros(2)
+    _check(lib().ncf_diag_spread_params(float(sigma), float(eps), out.ctypes.data))
+    return float(out[0]), float(out[1])
+
+
+def profile_enable(on=True):
+    lib().ncf_profile_enable(1 if on else 0)
+
+
+def profile_read():
+    recs = (ProfileRecord * 64)()
+    n = lib().ncf_profile_read(ctypes.cast(recs, ctypes.c_void_p), 64)
+    return {r.name.decode(): dict(launches=r.launches, total_ms=r.total_ms, work=r.work,
+                                  unit=r.work_unit.decode()) for r in recs[:n]}

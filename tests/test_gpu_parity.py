@@ -1,0 +1,241 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle.
+
+Tolerances (|delta c| absolute per lag, b relative):
+  * mixed precision, Gaussian, spectral numerator: c 1e-5, b 1e-6;
+  * FP64 spectral numerator: c 5e-8 -- the spectral sum has no 6h window
+    truncation, the oracle's does; the dropped terms weigh at most
+    exp(-18) ~ 1.5e-8 of a pair's peak weight;
+  * FP64 direct window sums: c 1e-11, b 1e-12;
+  * rectangle: counts bit-exact, c 1e-9 (FP64 prefix sums).
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2609_03866_amd import ncf, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _orc_acf(d, lags=None, kernel=None, err=None, h=None):
+    lags = d["lags"] if lags is None else lags
+    st, c, b, n = O.acf(d["t"], d["x"], lags, kernel or d["kernel"], d["h"] if h is None else h,
+                        err=err if err is not None else d.get("err"))
+    assert st == 0
+    return c, b, n
+
+
+def _orc_ccf(d, lags=None, kernel=None):
+    lags = d["lags"] if lags is None else lags
+    st, c, b, n = O.ccf(d["t"], d["x"], d["s"], d["y"], lags, kernel or d["kernel"], d["h"],
+                        ex=d.get("ex"), ey=d.get("ey"))
+    assert st == 0
+    return c, b, n
+
+
+def _check(c, b, n, oc, ob, on, kernel, ctol, btol):
+    c, b = np.asarray(c), np.asarray(b)
+    assert np.all(np.isfinite(c))
+    err = np.max(np.abs(c - oc))
+    assert err <= ctol, f"max |dc| = {err:.3e} > {ctol:.1e}"
+    if kernel == "rectangle":
+        np.testing.assert_array_equal(np.asarray(n), on)
+        np.testing.assert_array_equal(b, np.maximum(on.astype(float), 1e-16))
+    else:
+        np.testing.assert_allclose(b, ob, rtol=btol, atol=0)
+
+
+MODES = [
+    ("mixed", "auto", 1e-5, 1e-6),
+    ("fp64", "auto", 5e-8, 1e-12),
+    ("fp64", "direct", 1e-11, 1e-12),
+    ("mixed", "direct", 1e-5, 1e-6),
+]
+
+
+@pytest.mark.parametrize("prec,method,ctol,btol", MODES)
+@pytest.mark.parametrize("name", ["c1", "c3"])
+def test_acf_gaussian_small(name, prec, method, ctol, btol):
+    d = synth.small(name, seed=7)
+    oc, ob, on = _orc_acf(d)
+    c, b, n, _ = ncf.acf(d["t"], d["x"], d["lags"], "gaussian", d["h"], precision=prec,
+                         method=method)
+    _check(c, b, n, oc, ob, on, "gaussian", ctol, btol)
+
+
+@pytest.mark.parametrize("prec,method,ctol,btol", MODES)
+def test_ccf_gaussian_small(prec, method, ctol, btol):
+    d = synth.small("c2", seed=3)
+    oc, ob, on = _orc_ccf(d, kernel="gaussian")
+    c, b, n, _ = ncf.ccf(d["t"], d["x"], d["s"], d["y"], d["lags"], "gaussian", d["h"],
+                         precision=prec, method=method)
+    _check(c, b, n, oc, ob, on, "gaussian", ctol, btol)
+
+
+@pytest.mark.parametrize("method", ["auto", "direct"])
+def test_rectangle_acf_ccf_small(method):
+    d = synth.small("c2", seed=4)
+    oc, ob, on = _orc_ccf(d, kernel="rectangle")
+    c, b, n, _ = ncf.ccf(d["t"], d["x"], d["s"], d["y"], d["lags"], "rectangle", d["h"],
+                         method=method)
+    _check(c, b, n, oc, ob, on, "rectangle", 1e-9, 0)
+    d1 = synth.small("c1", seed=5)
+    lags = np.linspace(-30.0, 30.0, 97)
+    oc, ob, on = _orc_acf(d1, lags=lags, kernel="rectangle", h=0.5)
+    c, b, n, _ = ncf.acf(d1["t"], d1["x"], lags, "rectangle", 0.5, method=method)
+    _check(c, b, n, oc, ob, on, "rectangle", 1e-9, 0)
+
+
+def test_ties_negative_repeated_unsorted_lags():
+    rng = np.random.default_rng(17)
+    t = np.sort(np.round(rng.uniform(0, 500, 1500) * 4) / 4)  # quarter-day grid: many ties
+    x = rng.normal(size=t.size).cumsum()
+    lags = np.array([3.25, -7.5, 0.0, 3.25, 100.0, -0.25, 12.0, 480.0, 900.0])
+    for kern, h in (("rectangle", 0.5), ("gaussian", 0.4)):
+        st, oc, ob, on = O.acf(t, x, lags, kern, h)
+        for prec in ("mixed", "fp64"):
+            c, b, n, _ = ncf.acf(t, x, lags, kern, h, precision=prec)
+            _check(c, b, n, oc, ob, on, kern, 1e-5 if prec == "mixed" else 5e-8, 1e-6)
+        # lag 900 is beyond the data: empty window -> c = 0, b = 1e-16
+        assert b[-1] == 1e-16 and c[-1] == 0.0
+
+
+def test_weighted_mode_matches_oracle():
+    d = synth.small("c4", seed=2)
+    i0, i1 = d["offs"][3], d["offs"][4]
+    t, x, e = d["t"][i0:i1], d["x"][i0:i1], d["err_values"][i0:i1]
+    lags = np.arange(40.0)
+    for kern in ("gaussian", "rectangle"):
+        st, oc, ob, on = O.acf(t, x, lags, kern, 0.5, err=e)
+        assert st == 0
+        c, b, n, _ = ncf.acf(t, x, lags, kern, 0.5, err=e)
+        _check(c, b, n, oc, ob, on, kern, 1e-5 if kern == "gaussian" else 1e-9, 1e-6)
+
+
+def test_status_codes_on_gpu():
+    t = np.arange(50.0)
+    x = np.sin(t)
+    lags = np.arange(5.0)
+    assert ncf.acf(t[::-1].copy(), x, lags, "g", 0.5, raise_on_error=False)[3] == ncf.E_UNSORTED
+    xb = x.copy()
+    xb[7] = np.inf
+    assert ncf.acf(t, xb, lags, "g", 0.5, raise_on_error=False)[3] == ncf.E_INVALID_ARG
+    assert ncf.acf(t, np.ones(50), lags, "g", 0.5, raise_on_error=False)[3] == ncf.E_DEGENERATE
+    assert ncf.acf(t, x, lags, "g", -1.0, raise_on_error=False)[3] == ncf.E_INVALID_ARG
+    c, b, n, rc = ncf.acf(t, x, np.zeros(0), "g", 0.5)
+    assert rc == 0 and c.size == 0
+
+
+def test_batch_acf_small_matches_per_series_oracle():
+    d = synth.small("c4", seed=9)
+    offs = d["offs"]
+    c, b, n, st, rc = ncf.acf_batch(offs, d["t"], d["x"], d["lags"], "gaussian", d["h"])
+    assert rc == 0 and np.all(st == 0)
+    for i in range(len(offs) - 1):
+        sl = slice(offs[i], offs[i + 1])
+        s2, oc, ob, on = O.acf(d["t"][sl], d["x"][sl], d["lags"], "gaussian", d["h"][i])
+        _check(c[i], b[i], n[i], oc, ob, on, "gaussian", 1e-5, 1e-6)
+
+
+def test_batch_ccf_small_rectangle_exact_counts():
+    d = synth.small("c5", seed=9)
+    c, b, n, st, rc = ncf.ccf_batch(d["offx"], d["t"], d["x"], d["offy"], d["s"], d["y"],
+                                    d["lags"], "rectangle", d["h"])
+    assert rc == 0 and np.all(st == 0)
+    for p in range(len(d["offx"]) - 1):
+        sx = slice(d["offx"][p], d["offx"][p + 1])
+        sy = slice(d["offy"][p], d["offy"][p + 1])
+        s2, oc, ob, on = O.ccf(d["t"][sx], d["x"][sx], d["s"][sy], d["y"][sy], d["lags"],
+                               "rectangle", d["h"][p])
+        _check(c[p], b[p], n[p], oc, ob, on, "rectangle", 1e-9, 0)
+
+
+def test_batch_with_a_bad_series_reports_per_series_status():
+    d = synth.small("c4", seed=11)
+    x = d["x"].copy()
+    x[d["offs"][2]:d["offs"][3]] = 1.0  # constant series
+    c, b, n, st, rc = ncf.acf_batch(d["offs"], d["t"], x, d["lags"], "gaussian", d["h"],
+                                    raise_on_error=False)
+    assert rc == ncf.E_DEGENERATE and st[2] == ncf.E_DEGENERATE
+    assert np.all(np.isnan(c[2])) and np.sum(st != 0) == 1
+    i0, i1 = d["offs"][0], d["offs"][1]
+    s2, oc, ob, on = O.acf(d["t"][i0:i1], x[i0:i1], d["lags"], "gaussian", d["h"][0])
+    _check(c[0], b[0], n[0], oc, ob, on, "gaussian", 1e-5, 1e-6)
+
+
+def test_device_pointer_mode_with_torch_tensors():
+    import torch
+    d = synth.small("c2", seed=5)
+    dev = torch.device("cuda:0")
+    tt = {k: torch.as_tensor(d[k], device=dev) for k in ("t", "x", "s", "y", "lags")}
+    c, b, n, _ = ncf.ccf(tt["t"], tt["x"], tt["s"], tt["y"], tt["lags"], "gaussian", d["h"])
+    torch.cuda.synchronize()
+    oc, ob, on = _orc_ccf(d, kernel="gaussian")
+    _check(c.cpu().numpy(), b.cpu().numpy(), n.cpu().numpy(), oc, ob, on, "gaussian", 1e-5, 1e-6)
+
+
+def test_results_are_deterministic():
+    d = synth.small("c3", seed=1)
+    r1 = ncf.acf(d["t"], d["x"], d["lags"], "gaussian", d["h"])
+    r2 = ncf.acf(d["t"], d["x"], d["lags"], "gaussian", d["h"])
+    np.testing.assert_array_equal(r1[0], r2[0])
+    np.testing.assert_array_equal(r1[1], r2[1])
+
+
+# ------------------------------------------------------- stage-level pins
+
+@pytest.mark.parametrize("p", [12, 15, 21, 23])
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_fft_against_numpy(p, prec):
+    N = 2 ** p
+    rng = np.random.default_rng(p)
+    x = rng.normal(size=N) + 1j * rng.normal(size=N)
+    want_p = np.fft.ifft(x) * N  # sum x exp(+2 pi i n k / N)
+    want_m = np.fft.fft(x)       # sum x exp(-2 pi i n k / N)
+    tol = 2e-6 if prec == "mixed" else 1e-13
+    for sign, want in ((+1, want_p), (-1, want_m)):
+        got = ncf.diag_fft(x, sign, prec)
+        rel = np.linalg.norm(got - want) / np.linalg.norm(want)
+        assert rel < tol, (sign, rel)
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_type1_against_direct_dft(prec):
+    rng = np.random.default_rng(3)
+    n, L, N, M = 700, 1000.0, 8192, 2600
+    t = np.sort(rng.uniform(20.0, 980.0, n))
+    v = rng.normal(size=n)
+    got = ncf.diag_type1(t, v, 0.0, L, N, M, prec)
+    m = np.arange(-M, M + 1)
+    want = np.exp(2j * np.pi * np.outer(m, t) / L) @ v
+    rel = np.linalg.norm(got - want) / np.linalg.norm(want)
+    assert rel < (2e-6 if prec == "mixed" else 1e-11), rel
+
+
+# ------------------------------------------- full-size, bench configuration
+
+def test_c2_full_size_ccf_both_kernels():
+    for kern in ("gaussian", "rectangle"):
+        d = synth.c2(kernel=kern)
+        oc, ob, on = _orc_ccf(d)
+        c, b, n, _ = ncf.ccf(d["t"], d["x"], d["s"], d["y"], d["lags"], kern, d["h"])
+        _check(c, b, n, oc, ob, on, kern, 1e-5 if kern == "gaussian" else 1e-9, 1e-6)
+        # the delay of the response (40 d) is recovered
+        assert abs(d["lags"][np.argmax(c)] - 40.0) <= 3.0
+
+
+def test_c1_full_size_both_precisions():
+    d = synth.c1()
+    oc, ob, on = _orc_acf(d)
+    for prec, method, ctol, btol in MODES:
+        c, b, n, _ = ncf.acf(d["t"], d["x"], d["lags"], "gaussian", d["h"], precision=prec,
+                             method=method)
+        _check(c, b, n, oc, ob, on, "gaussian", ctol, btol)
+
+
+def test_c3_full_size_sampled_lags():
+    d = synth.c3()
+    c, b, n, _ = ncf.acf(d["t"], d["x"], d["lags"], "gaussian", d["h"])
+    pick = np.array([0, 1, 2, 7, 31, 365, 1000, 2047, 4095])
+    oc, ob, on = _orc_acf(d, lags=d["lags"][pick])
+    _check(c[pick], b[pick], n[pick], oc, ob, on, "gaussian", 1e-5, 1e-6)
