@@ -152,148 +152,93 @@ struct Arena {
 
 // -------------------------------------------------------------- the job
 
-constexpr int64_t kChunk = 16384;  // samples per moments chunk
+constexpr int64_t kChunk = 2048;  // samples per moments chunk
+
+// Small tables (descriptors, offsets, lag lists) of one phase are laid out
+// in a pinned host buffer mirrored by a device buffer and uploaded with a
+// single copy. Cached per device and phase, grown on demand.
+struct Staging {
+    char* h = nullptr;
+    char* d = nullptr;
+    size_t cap = 0;
+};
+std::map<int, Staging> g_stage[2];
+
+int ensure_stage(int phase, size_t bytes, Staging** out) {
+    int dev = 0;
+    NCF_TRY_HIP(hipGetDevice(&dev));
+    Staging& S = g_stage[phase][dev];
+    if (S.cap < bytes) {
+        if (S.h) {
+            NCF_TRY_HIP(hipDeviceSynchronize());
+            NCF_TRY_HIP(hipHostFree(S.h));
+            NCF_TRY_HIP(hipFree(S.d));
+            S = Staging{};
+        }
+        const size_t want = 2 * bytes + 65536;
+        if (hipHostMalloc((void**)&S.h, want) != hipSuccess ||
+            hipMalloc((void**)&S.d, want) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("staging allocation of %zu bytes failed", want);
+            return NCF_E_NOMEM;
+        }
+        S.cap = want;
+    }
+    *out = &S;
+    return NCF_OK;
+}
+
+// Reserve table slots: device address for kernels, host address for filling.
+struct Tables {
+    char* h = nullptr;  // null during the sizing pass
+    char* d = nullptr;
+    size_t off = 0;
+    template <typename T>
+    T* take(size_t n, T** host) {
+        const size_t a = (off + 15) & ~(size_t)15;
+        off = a + sizeof(T) * std::max<size_t>(n, 1);
+        *host = h ? reinterpret_cast<T*>(h + a) : nullptr;
+        return d ? reinterpret_cast<T*>(d + a) : nullptr;
+    }
+};
 
 struct SeriesSet {
-    // device inputs
-    const double* t = nullptr;
+    const double* t = nullptr;  // device inputs
     const double* x = nullptr;
     const double* err = nullptr;
     int64_t ntot = 0;
     std::vector<int64_t> offs;  // host, nser + 1
     int nser = 0;
-    // derived (device)
+    // derived device arrays (concatenated over the set's series)
     float* v32 = nullptr;
     double* v64 = nullptr;
     double* w64 = nullptr;
-    double* pv = nullptr;
+    double* pv = nullptr;  // ntot + nser entries (n + 1 per series)
     double* pw = nullptr;
-    SeriesDesc* d_series = nullptr;
-    Chunk* d_chunks = nullptr;
-    double* d_chunk_part = nullptr;
-    double* d_chunk_tot = nullptr;
-    SeriesStat* d_stats = nullptr;
-    std::vector<SeriesDesc> h_series;
-    std::vector<Chunk> h_chunks;
-    std::vector<SeriesStat> stats;
+    int sd0 = 0;           // first descriptor of this set in the moments table
 };
 
 struct Job {
     bool ccf = false;
     int64_t nprob = 0;
     int kern = NCF_GAUSSIAN;
-    std::vector<double> h;   // per problem
+    std::vector<double> h;     // per problem
     std::vector<double> lags;  // host copy, K
     int64_t K = 0;
-    // user outputs
-    double* c = nullptr;
+    double* c = nullptr;       // user outputs
     double* b = nullptr;
     int64_t* count = nullptr;
-    int* status = nullptr;   // host, nprob (may be null)
+    int* status = nullptr;     // host, nprob (may be null)
     ncf_options_t opt;
     bool dev_ptrs = false;
     hipStream_t st = nullptr;
-    SeriesSet set[2];        // ACF: set[0]; CCF: set[0] = series 1, set[1] = series 2
+    SeriesSet set[2];          // ACF: set[0]; CCF: set[0] = series 1, set[1] = series 2
 };
 
 bool use_spectral(const Job& J) {
     if (J.opt.method == NCF_DIRECT) return false;
     if (J.kern == NCF_GAUSSIAN) return true;
     return J.opt.method == NCF_SPECTRAL;  // rectangle: diagnostic only
-}
-
-int upload_inputs(Job& J, int si, const double* t, const double* x, const double* err,
-                  Arena& ar) {
-    SeriesSet& S = J.set[si];
-    if (J.dev_ptrs) {
-        S.t = t;
-        S.x = x;
-        S.err = err;
-        return NCF_OK;
-    }
-    double* dt = ar.take<double>(S.ntot);
-    double* dx = ar.take<double>(S.ntot);
-    double* de = err ? ar.take<double>(S.ntot) : nullptr;
-    if (ar.base) {
-        NCF_TRY_HIP(hipMemcpyAsync(dt, t, sizeof(double) * S.ntot, hipMemcpyHostToDevice, J.st));
-        NCF_TRY_HIP(hipMemcpyAsync(dx, x, sizeof(double) * S.ntot, hipMemcpyHostToDevice, J.st));
-        if (err)
-            NCF_TRY_HIP(
-                hipMemcpyAsync(de, err, sizeof(double) * S.ntot, hipMemcpyHostToDevice, J.st));
-    }
-    S.t = dt;
-    S.x = dx;
-    S.err = de;
-    return NCF_OK;
-}
-
-void build_chunks(SeriesSet& S) {
-    S.h_series.resize(S.nser);
-    S.h_chunks.clear();
-    int64_t pre = 0;
-    for (int s = 0; s < S.nser; ++s) {
-        SeriesDesc d;
-        d.off = S.offs[s];
-        d.n = S.offs[s + 1] - S.offs[s];
-        d.pre_off = pre;
-        pre += d.n + 1;
-        d.chunk0 = (int32_t)S.h_chunks.size();
-        int32_t nc = 0;
-        for (int64_t b = d.off; b < d.off + d.n; b += kChunk) {
-            Chunk c;
-            c.begin = b;
-            c.end = std::min(b + kChunk, d.off + d.n);
-            c.series = s;
-            c.pad = 0;
-            S.h_chunks.push_back(c);
-            ++nc;
-        }
-        d.nchunk = nc;
-        S.h_series[s] = d;
-    }
-}
-
-MomentsArgs moments_args(const SeriesSet& S) {
-    MomentsArgs a{};
-    a.t = S.t;
-    a.x = S.x;
-    a.err = S.err;
-    a.series = S.d_series;
-    a.chunks = S.d_chunks;
-    a.nseries = S.nser;
-    a.nchunks = (int32_t)S.h_chunks.size();
-    a.chunk_part = S.d_chunk_part;
-    a.stats = S.d_stats;
-    a.v32 = S.v32;
-    a.v64 = S.v64;
-    a.w64 = S.w64;
-    a.pv = S.pv;
-    a.pw = S.pw;
-    a.chunk_tot = S.d_chunk_tot;
-    return a;
-}
-
-// phase-1 layout (sizing pass when ar.base == nullptr)
-int layout_phase1(Job& J, const double* const* tin, const double* const* xin,
-                  const double* const* ein, Arena& ar, bool need_v32, bool need_v64,
-                  bool need_prefix) {
-    const int nsets = J.ccf ? 2 : 1;
-    for (int si = 0; si < nsets; ++si) {
-        SeriesSet& S = J.set[si];
-        NCF_TRY(upload_inputs(J, si, tin[si], xin[si], ein[si], ar));
-        const bool wtd = S.err != nullptr;
-        S.d_series = ar.take<SeriesDesc>(S.nser);
-        S.d_chunks = ar.take<Chunk>(S.h_chunks.size() + 1);
-        S.d_chunk_part = ar.take<double>(4 * (S.h_chunks.size() + 1));
-        S.d_chunk_tot = ar.take<double>(2 * (S.h_chunks.size() + 1));
-        S.d_stats = ar.take<SeriesStat>(S.nser);
-        S.v32 = need_v32 ? ar.take<float>(S.ntot) : nullptr;
-        S.v64 = need_v64 ? ar.take<double>(S.ntot) : nullptr;
-        S.w64 = wtd ? ar.take<double>(S.ntot) : nullptr;
-        S.pv = need_prefix ? ar.take<double>(S.ntot + S.nser) : nullptr;
-        S.pw = (need_prefix && wtd) ? ar.take<double>(S.ntot + S.nser) : nullptr;
-    }
-    return NCF_OK;
 }
 
 int64_t pow2_at_least(double v) {
@@ -378,45 +323,141 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     const bool need_v64 = (spectral && fp64) || numer_in_window;
     const bool need_prefix = rect && numer_in_window;
 
-    for (int si = 0; si < nsets; ++si) build_chunks(J.set[si]);
+    // ------------------------------------------------ phase 1: A1 moments
+    // chunks of every series of every set, one launch for all of them
+    std::vector<SeriesDesc> sdesc;
+    std::vector<Chunk> chunks;
+    for (int si = 0; si < nsets; ++si) {
+        SeriesSet& S = J.set[si];
+        S.sd0 = (int)sdesc.size();
+        for (int s = 0; s < S.nser; ++s) {
+            SeriesDesc d{};
+            d.n = S.offs[s + 1] - S.offs[s];
+            d.chunk0 = (int32_t)chunks.size();
+            int32_t nc = 0;
+            for (int64_t b = 0; b < d.n; b += kChunk) {
+                chunks.push_back(Chunk{b, std::min(b + kChunk, d.n), (int32_t)sdesc.size(), 0});
+                ++nc;
+            }
+            d.nchunk = nc;
+            sdesc.push_back(d);
+        }
+    }
+    const int nsd = (int)sdesc.size();
+    const int nch = (int)chunks.size();
 
-    // ---------------- phase 1: validation + moments
+    // device workspace of phase 1: inputs (host mode), derived arrays, partials
+    auto layout1 = [&](Arena& ar, double** d_cpart, double** d_ctot, SeriesStat** d_stats) {
+        for (int si = 0; si < nsets; ++si) {
+            SeriesSet& S = J.set[si];
+            if (J.dev_ptrs) {
+                S.t = tin[si];
+                S.x = xin[si];
+                S.err = ein[si];
+            } else {
+                S.t = ar.take<double>(S.ntot);
+                S.x = ar.take<double>(S.ntot);
+                S.err = ein[si] ? ar.take<double>(S.ntot) : nullptr;
+            }
+            S.v32 = need_v32 ? ar.take<float>(S.ntot) : nullptr;
+            S.v64 = need_v64 ? ar.take<double>(S.ntot) : nullptr;
+            S.w64 = ein[si] ? ar.take<double>(S.ntot) : nullptr;
+            S.pv = need_prefix ? ar.take<double>(S.ntot + S.nser) : nullptr;
+            S.pw = (need_prefix && ein[si]) ? ar.take<double>(S.ntot + S.nser) : nullptr;
+        }
+        *d_cpart = ar.take<double>(4 * (size_t)nch);
+        *d_ctot = ar.take<double>(2 * (size_t)nch);
+        *d_stats = ar.take<SeriesStat>(nsd);
+    };
+    double *d_cpart, *d_ctot;
+    SeriesStat* d_stats;
     Arena a1;
-    NCF_TRY(layout_phase1(J, tin, xin, ein, a1, need_v32, need_v64, need_prefix));
+    layout1(a1, &d_cpart, &d_ctot, &d_stats);
     void* ws1 = nullptr;
     NCF_TRY(ensure_ws(0, a1.off + 256, &ws1));
     a1 = Arena{(char*)ws1, 0};
-    NCF_TRY(layout_phase1(J, tin, xin, ein, a1, need_v32, need_v64, need_prefix));
-    for (int si = 0; si < nsets; ++si) {
-        SeriesSet& S = J.set[si];
-        NCF_TRY_HIP(hipMemcpyAsync(S.d_series, S.h_series.data(),
-                                   sizeof(SeriesDesc) * S.nser, hipMemcpyHostToDevice, J.st));
-        if (!S.h_chunks.empty())
-            NCF_TRY_HIP(hipMemcpyAsync(S.d_chunks, S.h_chunks.data(),
-                                       sizeof(Chunk) * S.h_chunks.size(),
-                                       hipMemcpyHostToDevice, J.st));
-        NCF_TRY(launch_moments(moments_args(S), J.st));
-        S.stats.resize(S.nser);
-        NCF_TRY_HIP(hipMemcpyAsync(S.stats.data(), S.d_stats, sizeof(SeriesStat) * S.nser,
-                                   hipMemcpyDeviceToHost, J.st));
+    layout1(a1, &d_cpart, &d_ctot, &d_stats);
+    if (!J.dev_ptrs) {
+        for (int si = 0; si < nsets; ++si) {
+            SeriesSet& S = J.set[si];
+            const size_t by = sizeof(double) * S.ntot;
+            NCF_TRY_HIP(hipMemcpyAsync((void*)S.t, tin[si], by, hipMemcpyHostToDevice, J.st));
+            NCF_TRY_HIP(hipMemcpyAsync((void*)S.x, xin[si], by, hipMemcpyHostToDevice, J.st));
+            if (ein[si])
+                NCF_TRY_HIP(
+                    hipMemcpyAsync((void*)S.err, ein[si], by, hipMemcpyHostToDevice, J.st));
+        }
     }
+    for (int si = 0; si < nsets; ++si) {
+        const SeriesSet& S = J.set[si];
+        for (int s = 0; s < S.nser; ++s) {
+            SeriesDesc& d = sdesc[S.sd0 + s];
+            const int64_t o = S.offs[s];
+            d.t = S.t + o;
+            d.x = S.x + o;
+            d.err = S.err ? S.err + o : nullptr;
+            d.v32 = S.v32 ? S.v32 + o : nullptr;
+            d.v64 = S.v64 ? S.v64 + o : nullptr;
+            d.w64 = S.w64 ? S.w64 + o : nullptr;
+            d.pv = S.pv ? S.pv + o + s : nullptr;
+            d.pw = S.pw ? S.pw + o + s : nullptr;
+        }
+    }
+    Staging* stg1 = nullptr;
+    Tables t1;
+    {
+        SeriesDesc* hs;
+        Chunk* hc;
+        SeriesStat* hst;
+        t1.take<SeriesDesc>(nsd, &hs);
+        t1.take<Chunk>(nch, &hc);
+        t1.take<SeriesStat>(nsd, &hst);
+    }
+    NCF_TRY(ensure_stage(0, t1.off, &stg1));
+    t1 = Tables{stg1->h, stg1->d, 0};
+    SeriesDesc* h_sd;
+    Chunk* h_ch;
+    SeriesStat* h_stats;
+    SeriesDesc* d_sd = t1.take<SeriesDesc>(nsd, &h_sd);
+    Chunk* d_ch = t1.take<Chunk>(nch, &h_ch);
+    t1.take<SeriesStat>(nsd, &h_stats);  // host landing area of the statistics
+    std::memcpy(h_sd, sdesc.data(), sizeof(SeriesDesc) * nsd);
+    std::memcpy(h_ch, chunks.data(), sizeof(Chunk) * nch);
+    const size_t up1 = (size_t)((char*)h_stats - stg1->h);
+    NCF_TRY_HIP(hipMemcpyAsync(stg1->d, stg1->h, up1, hipMemcpyHostToDevice, J.st));
+    MomentsArgs ma{};
+    ma.series = d_sd;
+    ma.chunks = d_ch;
+    ma.nseries = nsd;
+    ma.nchunks = nch;
+    ma.chunk_part = d_cpart;
+    ma.chunk_tot = d_ctot;
+    ma.stats = d_stats;
+    ma.prefix = need_prefix ? 1 : 0;
+    NCF_TRY(launch_moments(ma, J.st));
+    NCF_TRY_HIP(hipMemcpyAsync(h_stats, d_stats, sizeof(SeriesStat) * nsd, hipMemcpyDeviceToHost,
+                               J.st));
     NCF_TRY_HIP(hipStreamSynchronize(J.st));
+    std::vector<SeriesStat> stats(h_stats, h_stats + nsd);
+    auto stat_of = [&](int si, int64_t s) -> const SeriesStat& {
+        return stats[J.set[si].sd0 + s];
+    };
 
     // per-problem status from its series
     std::vector<int> pstat(J.nprob, NCF_OK);
     for (int64_t p = 0; p < J.nprob; ++p) {
         for (int si = 0; si < nsets; ++si) {
-            int s = J.set[si].stats[p].status;
+            int s = stat_of(si, p).status;
             if (s != NCF_OK && pstat[p] == NCF_OK) pstat[p] = s;
         }
         if (pstat[p] == NCF_OK && !(J.h[p] > 0.0 && std::isfinite(J.h[p])))
             pstat[p] = NCF_E_INVALID_ARG;
     }
 
-    // standardization (+ prefix sums)
-    for (int si = 0; si < nsets; ++si) NCF_TRY(launch_standardize(moments_args(J.set[si]), J.st));
+    // standardization (+ prefix sums), all series in one launch
+    NCF_TRY(launch_standardize(ma, J.st));
 
-    // ---------------- phase 2 planning (host)
+    // ------------------------------------------------ phase 2 planning (host)
     const int64_t K = J.K;
     double maxlag = 0.0;
     for (double v : J.lags) maxlag = std::max(maxlag, std::fabs(v));
@@ -432,8 +473,8 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
                          return a.first < b.first;
                      });
     const int Krow = (int)rows.size();
-    std::vector<double> delta(Krow);
-    std::vector<int32_t> perm(std::max<int64_t>(K, 1));
+    std::vector<double> delta(std::max(Krow, 1), 0.0);
+    std::vector<int32_t> perm(std::max<int64_t>(K, 1), 0);
     int row0 = -1;
     for (int r = 0; r < Krow; ++r) {
         delta[r] = rows[r].first;
@@ -447,72 +488,70 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         lag_ext = std::max(lag_ext, delta[r1] - delta[r0]);
     }
 
-    // window flags and LDS budget
+    // window flags and LDS budget: staged window samples (+ prefix or value
+    // arrays) and outer samples. `cap` starts at the 40 KiB budget and is
+    // shrunk to what the planned tiles need, for occupancy.
     uint32_t wflags = 0;
     if (rect) wflags |= WIN_RECT;
     if (numer_in_window) wflags |= WIN_NUMER;
     if (weighted) wflags |= WIN_WEIGHTED;
     if (fp64 && !rect) wflags |= WIN_EXP64;
-    const int jmax = rect ? 512 : 1024;
-    const int outer_arrays = 1 + (numer_in_window ? 1 : 0) + (weighted ? 1 : 0);
-    const int win_arrays = 1 + (numer_in_window ? 1 : 0) + (weighted ? 1 : 0);
+    const int jmax = 1024;
+    const int arrays = 1 + (numer_in_window ? 1 : 0) + (weighted ? 1 : 0);
     const int budget = 40 * 1024 / 8;  // doubles
-    int cap = (budget - jmax * outer_arrays - 2) / win_arrays;
+    int cap = (budget - jmax * arrays) / arrays - 8;
     cap = std::max(256, std::min(4096, cap));
 
     struct WinPlan {
-        int wi_set, wi_ser, wo_set, wo_ser;  // window (set, series), outer (set, series)
-        int krows;                           // rows: Krow (cross/acf) or 1 (self lag 0)
+        int wi_set, wo_set;  // window set, outer set (series index = problem)
+        int krows;           // rows: Krow (cross / acf) or 1 (self lag 0)
         int64_t prob;
-        int role;                            // 0 main, 1 self x, 2 self y
+        int role;            // 0 main, 1 self x, 2 self y
     };
     std::vector<WinPlan> wplans;
     for (int64_t p = 0; p < J.nprob; ++p) {
         if (pstat[p] != NCF_OK) continue;
         if (!J.ccf) {
-            wplans.push_back({0, (int)p, 0, (int)p, Krow, p, 0});
+            wplans.push_back({0, 0, Krow, p, 0});
         } else {
-            if (Krow > 0) wplans.push_back({0, (int)p, 1, (int)p, Krow, p, 0});
-            wplans.push_back({0, (int)p, 0, (int)p, 1, p, 1});
-            wplans.push_back({1, (int)p, 1, (int)p, 1, p, 2});
+            if (Krow > 0) wplans.push_back({0, 1, Krow, p, 0});
+            wplans.push_back({0, 0, 1, p, 1});
+            wplans.push_back({1, 1, 1, p, 2});
         }
     }
     const int ntw = (int)wplans.size();
     std::vector<WinTask> wt(ntw);
-    std::vector<int64_t> item0(ntw + 1), wk0(ntw + 1);
-    int64_t nitems = 0, total_rows = 0;
+    std::vector<double> wt_est(ntw, 0.0);
+    std::vector<int64_t> item0(ntw + 1), wk0(ntw + 1), r0(ntw + 1);
+    int64_t nitems = 0, total_rows = 0, nred1 = 0;
     double win_work = 0.0;
-    const double zero = 0.0;
-    (void)zero;
     for (int i = 0; i < ntw; ++i) {
         const WinPlan& P = wplans[i];
         const SeriesSet& SW = J.set[P.wi_set];
         const SeriesSet& SO = J.set[P.wo_set];
-        const SeriesDesc& dw = SW.h_series[P.wi_ser];
-        const SeriesDesc& dO = SO.h_series[P.wo_ser];
-        const SeriesStat& sw = SW.stats[P.wi_ser];
-        const SeriesStat& so = SO.stats[P.wo_ser];
+        const SeriesDesc& dw = sdesc[SW.sd0 + P.prob];
+        const SeriesDesc& dO = sdesc[SO.sd0 + P.prob];
+        const SeriesStat& sw = stat_of(P.wi_set, P.prob);
+        const SeriesStat& so = stat_of(P.wo_set, P.prob);
         const double h = J.h[P.prob];
         WinTask T{};
-        T.t = SW.t + dw.off;
+        T.t = dw.t;
         T.n_win = dw.n;
-        T.s = SO.t + dO.off;
+        T.s = dO.t;
         T.n_out = dO.n;
         if (numer_in_window) {
-            if (rect) {
-                T.pv = SW.pv + dw.pre_off;
-            } else {
-                T.v = SW.v64 + dw.off;
-            }
-            T.vo = SO.v64 + dO.off;
+            if (rect)
+                T.pv = dw.pv;
+            else
+                T.v = dw.v64;
+            T.vo = dO.v64;
         }
         if (weighted) {
-            if (rect) {
-                T.pw = SW.pw ? SW.pw + dw.pre_off : nullptr;
-            } else {
-                T.w = SW.w64 ? SW.w64 + dw.off : nullptr;
-            }
-            T.wo = SO.w64 ? SO.w64 + dO.off : nullptr;
+            if (rect)
+                T.pw = dw.pw;
+            else
+                T.w = dw.w64;
+            T.wo = dO.w64;
         }
         T.K = P.krows;
         T.h = h;
@@ -524,20 +563,27 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         const double dens_o = (double)(dO.n - 1) / span_o;
         const int n_kt = (int)ceil_div(T.K, 64);
         const double lext = (P.krows == 1) ? 0.0 : lag_ext;
-        int64_t Jt = 1;
-        const double target = 4096.0;
-        while (Jt * 2 <= jmax && (double)dO.n * n_kt / (double)(Jt * 2) >= target) Jt *= 2;
-        Jt = std::max<int64_t>(Jt, std::min<int64_t>(64, jmax));
-        while (Jt > 16 &&
-               dens_w * ((double)Jt / dens_o + lext + 2.0 * T.W) + 2.0 > 0.5 * cap)
-            Jt /= 2;
+        auto est = [&](int64_t j) {
+            return dens_w * ((double)j / dens_o + lext + 2.0 * T.W) + 2.0;
+        };
+        // outer samples per workgroup: as many as keep the window range in
+        // LDS (half the capacity, for clustering) while leaving at least 2048
+        // work items (eight per CU) when the problem is big enough
+        int64_t Jt = 64;
+        while (Jt * 2 <= jmax && est(Jt * 2) <= 0.5 * cap &&
+               (double)dO.n * n_kt / (double)(Jt * 2) >= 2048.0)
+            Jt *= 2;
+        while (Jt > 16 && est(Jt) > 0.5 * cap) Jt /= 2;
         T.J = (int32_t)Jt;
+        wt_est[i] = est(Jt);
         T.n_jt = (int32_t)ceil_div(dO.n, Jt);
         T.n_kt = n_kt;
         T.item0 = nitems;
         item0[i] = nitems;
         wk0[i] = total_rows;
+        r0[i] = nred1;
         nitems += (int64_t)T.n_jt * T.n_kt;
+        nred1 += (int64_t)T.n_kt * ceil_div(T.n_jt, kWinJc);
         total_rows += T.K;
         // algorithmic work: per (j, k) window, searches + per-point weight ops
         const double pts = rect ? 0.0 : dens_w * 2.0 * T.W;
@@ -546,8 +592,21 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     }
     item0[ntw] = nitems;
     wk0[ntw] = total_rows;
+    r0[ntw] = nred1;
+    int jmax_used = 64;
+    {
+        double need = 0.0;
+        for (int i = 0; i < ntw; ++i) {
+            need = std::max(need, wt_est[i]);
+            jmax_used = std::max(jmax_used, wt[i].J);
+        }
+        // twice the estimated window range (clustering margin), rounded up
+        const int want = (int)std::min<double>(cap, round_up((int64_t)(2.0 * need) + 64, 256));
+        cap = std::max(256, want);
+        jmax_used = (int)round_up(jmax_used, 64);
+    }
 
-    // spectral problems
+    // spectral problems, sorted by grid size so grids of one size are contiguous
     struct SpecPlan {
         int64_t prob;
         SpecGeom g;
@@ -556,10 +615,10 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     if (spectral) {
         for (int64_t p = 0; p < J.nprob; ++p) {
             if (pstat[p] != NCF_OK) continue;
-            double tmin = J.set[0].stats[p].tmin, tmax = J.set[0].stats[p].tmax;
+            double tmin = stat_of(0, p).tmin, tmax = stat_of(0, p).tmax;
             if (J.ccf) {
-                tmin = std::min(tmin, J.set[1].stats[p].tmin);
-                tmax = std::max(tmax, J.set[1].stats[p].tmax);
+                tmin = std::min(tmin, stat_of(1, p).tmin);
+                tmax = std::max(tmax, stat_of(1, p).tmax);
             }
             SpecPlan sp;
             sp.prob = p;
@@ -571,219 +630,162 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     }
     const int nts = (int)splans.size();
     const int Keval = (int)(J.ccf ? K : K + 1);
-
-    // ---------------- phase 2 layout
     const size_t csz = fp64 ? 16 : 8;
-    auto layout2 = [&](Arena& ar, std::vector<SpecTask>* stasks, std::vector<NormTask>* ntasks,
-                       void** d_wt, int64_t** d_item0, int64_t** d_wk0, void** d_st,
-                       int64_t** d_tile0, int64_t** d_pos0, int64_t** d_sk0, void** d_rinfo,
-                       double** d_delta, int32_t** d_perm, double** d_evlags, void** d_nt,
-                       int32_t** d_status, double** d_c, double** d_b, int64_t** d_cnt,
-                       std::vector<void*>* grids, double** d_zero, void*** d_gtab) {
-        *d_wt = ar.take<WinTask>(std::max(ntw, 1));
-        *d_item0 = ar.take<int64_t>(ntw + 1);
-        *d_wk0 = ar.take<int64_t>(ntw + 1);
-        *d_delta = ar.take<double>(std::max(Krow, 1));
-        *d_perm = ar.take<int32_t>(std::max<int64_t>(K, 1));
-        *d_zero = ar.take<double>(1);
+
+    // ------------------------------------------------ phase 2 device workspace
+    std::vector<void*> grids(nts);
+    std::vector<double*> numer(nts), spart(nts);
+    double *d_c = nullptr, *d_b = nullptr;
+    int64_t* d_cnt = nullptr;
+    auto layout2 = [&](Arena& ar) {
         for (int i = 0; i < ntw; ++i) {
-            // self tasks of a CCF run at lag 0 only
-            wt[i].delta = wplans[i].role == 0 ? *d_delta : *d_zero;
             wt[i].part = ar.take<double>((size_t)wt[i].n_jt * wt[i].K * 4);
+            wt[i].part2 = ar.take<double>((size_t)ceil_div(wt[i].n_jt, kWinJc) * wt[i].K * 4);
             wt[i].sums = ar.take<double>((size_t)wt[i].K * 4);
         }
-        // spectral
-        stasks->clear();
-        *d_st = ar.take<SpecTask>(std::max(nts, 1));
-        *d_tile0 = ar.take<int64_t>(nts + 1);
-        *d_pos0 = ar.take<int64_t>(nts + 1);
-        *d_sk0 = ar.take<int64_t>(nts + 1);
-        *d_rinfo = ar.take<int32_t>(6 * std::max(nts, 1));
-        *d_evlags = ar.take<double>(std::max(Keval, 1));
-        *d_gtab = ar.take<void*>(std::max(nts, 1));
-        grids->clear();
-        int64_t tiles = 0, pos = 0;
         for (int i = 0; i < nts; ++i) {
-            const SpecPlan& P = splans[i];
-            const SeriesSet& S0 = J.set[0];
-            const SeriesDesc& d0 = S0.h_series[P.prob];
-            SpecTask T{};
-            T.t0 = S0.t + d0.off;
-            T.v0f = S0.v32 ? S0.v32 + d0.off : nullptr;
-            T.v0d = S0.v64 ? S0.v64 + d0.off : nullptr;
-            T.n0 = d0.n;
-            if (J.ccf) {
-                const SeriesSet& S1 = J.set[1];
-                const SeriesDesc& d1 = S1.h_series[P.prob];
-                T.t1 = S1.t + d1.off;
-                T.v1f = S1.v32 ? S1.v32 + d1.off : nullptr;
-                T.v1d = S1.v64 ? S1.v64 + d1.off : nullptr;
-                T.n1 = d1.n;
-            }
-            T.t_ref = P.g.t_ref;
-            T.L = P.g.L;
-            T.N = P.g.N;
-            T.M = P.g.M;
-            T.s = P.g.s;
-            T.W = P.g.W;
-            T.h = J.h[P.prob];
-            T.kern = J.kern;
-            T.ccf = J.ccf ? 1 : 0;
-            T.grid = ar.take<char>((size_t)P.g.N * csz);
-            grids->push_back(T.grid);
-            T.tile0 = tiles;
-            T.ntiles = P.g.N / 4096;
-            tiles += T.ntiles;
-            T.tile_rng = ar.take<int64_t>(4 * T.ntiles);
-            T.lags = *d_evlags;
-            T.K_eval = Keval;
-            T.numer = ar.take<double>(std::max(Keval, 1));
-            T.scale_part = J.ccf ? ar.take<double>(2 * (P.g.N / 256)) : nullptr;
-            T.pos0 = pos;
-            pos += P.g.N;
-            stasks->push_back(T);
+            grids[i] = ar.take<char>((size_t)splans[i].g.N * csz);
+            numer[i] = ar.take<double>(std::max(Keval, 1));
+            spart[i] = J.ccf ? ar.take<double>(2 * (splans[i].g.N / 256)) : nullptr;
         }
-        // normalization + outputs
-        *d_nt = ar.take<NormTask>(std::max<int64_t>(J.nprob, 1));
-        *d_status = ar.take<int32_t>(std::max<int64_t>(J.nprob, 1));
         if (J.dev_ptrs) {
-            *d_c = J.c;
-            *d_b = J.b;
-            *d_cnt = J.count;
+            d_c = J.c;
+            d_b = J.b;
+            d_cnt = J.count;
         } else {
-            *d_c = ar.take<double>(std::max<int64_t>(J.nprob * K, 1));
-            *d_b = ar.take<double>(std::max<int64_t>(J.nprob * K, 1));
-            *d_cnt = J.count ? ar.take<int64_t>(std::max<int64_t>(J.nprob * K, 1)) : nullptr;
+            d_c = ar.take<double>(std::max<int64_t>(J.nprob * K, 1));
+            d_b = ar.take<double>(std::max<int64_t>(J.nprob * K, 1));
+            d_cnt = J.count ? ar.take<int64_t>(std::max<int64_t>(J.nprob * K, 1)) : nullptr;
         }
-        return NCF_OK;
     };
-
-    std::vector<SpecTask> stasks;
-    std::vector<NormTask> ntasks_v;
-    void *d_wt, *d_st, *d_rinfo, *d_nt;
-    int64_t *d_item0, *d_wk0, *d_tile0, *d_pos0, *d_sk0, *d_cnt;
-    double *d_delta, *d_evlags, *d_c, *d_b;
-    int32_t *d_perm, *d_status;
-    std::vector<void*> grids;
-    double* d_zero;
-    void** d_gtab;
     Arena a2;
-    layout2(a2, &stasks, &ntasks_v, &d_wt, &d_item0, &d_wk0, &d_st, &d_tile0, &d_pos0, &d_sk0,
-            &d_rinfo, &d_delta, &d_perm, &d_evlags, &d_nt, &d_status, &d_c, &d_b, &d_cnt,
-            &grids, &d_zero, &d_gtab);
+    layout2(a2);
     void* ws2 = nullptr;
     NCF_TRY(ensure_ws(1, a2.off + 256, &ws2));
     a2 = Arena{(char*)ws2, 0};
-    layout2(a2, &stasks, &ntasks_v, &d_wt, &d_item0, &d_wk0, &d_st, &d_tile0, &d_pos0, &d_sk0,
-            &d_rinfo, &d_delta, &d_perm, &d_evlags, &d_nt, &d_status, &d_c, &d_b, &d_cnt,
-            &grids, &d_zero, &d_gtab);
+    layout2(a2);
+
+    // ------------------------------------------------ phase 2 tables
+    struct T2 {
+        WinTask* wt;
+        int64_t *item0, *wk0, *r0;
+        double *delta, *zero;
+        int32_t* perm;
+        SpecTask* st;
+        int64_t *tile0, *pos0, *sk0;
+        int32_t* rinfo;
+        double* ev;
+        void** gtab;
+        NormTask* nt;
+        int32_t* status;
+    } dT{}, hT{};
+    auto take2 = [&](Tables& tb) {
+        dT.wt = tb.take<WinTask>(ntw, &hT.wt);
+        dT.item0 = tb.take<int64_t>(ntw + 1, &hT.item0);
+        dT.wk0 = tb.take<int64_t>(ntw + 1, &hT.wk0);
+        dT.r0 = tb.take<int64_t>(ntw + 1, &hT.r0);
+        dT.delta = tb.take<double>(Krow, &hT.delta);
+        dT.zero = tb.take<double>(1, &hT.zero);
+        dT.perm = tb.take<int32_t>(K, &hT.perm);
+        dT.st = tb.take<SpecTask>(nts, &hT.st);
+        dT.tile0 = tb.take<int64_t>(nts + 1, &hT.tile0);
+        dT.pos0 = tb.take<int64_t>(nts + 1, &hT.pos0);
+        dT.sk0 = tb.take<int64_t>(nts + 1, &hT.sk0);
+        dT.rinfo = tb.take<int32_t>(6 * (size_t)nts, &hT.rinfo);
+        dT.ev = tb.take<double>(Keval, &hT.ev);
+        dT.gtab = tb.take<void*>(nts, &hT.gtab);
+        dT.nt = tb.take<NormTask>(J.nprob, &hT.nt);
+        dT.status = tb.take<int32_t>(J.nprob, &hT.status);
+    };
+    Tables t2;
+    take2(t2);
+    Staging* stg2 = nullptr;
+    NCF_TRY(ensure_stage(1, t2.off, &stg2));
+    t2 = Tables{stg2->h, stg2->d, 0};
+    take2(t2);
 
     // window tables
-    if (Krow > 0)
-        NCF_TRY_HIP(hipMemcpyAsync(d_delta, delta.data(), sizeof(double) * Krow,
-                                   hipMemcpyHostToDevice, J.st));
-    {
-        static const double kZero = 0.0;
-        NCF_TRY_HIP(
-            hipMemcpyAsync(d_zero, &kZero, sizeof(double), hipMemcpyHostToDevice, J.st));
-    }
-    if (K > 0)
-        NCF_TRY_HIP(hipMemcpyAsync(d_perm, perm.data(), sizeof(int32_t) * K,
-                                   hipMemcpyHostToDevice, J.st));
-    if (ntw > 0) {
-        NCF_TRY_HIP(hipMemcpyAsync(d_wt, wt.data(), sizeof(WinTask) * ntw, hipMemcpyHostToDevice,
-                                   J.st));
-        NCF_TRY_HIP(hipMemcpyAsync(d_item0, item0.data(), sizeof(int64_t) * (ntw + 1),
-                                   hipMemcpyHostToDevice, J.st));
-        NCF_TRY_HIP(hipMemcpyAsync(d_wk0, wk0.data(), sizeof(int64_t) * (ntw + 1),
-                                   hipMemcpyHostToDevice, J.st));
-    }
+    for (int i = 0; i < ntw; ++i) wt[i].delta = wplans[i].role == 0 ? dT.delta : dT.zero;
+    std::memcpy(hT.wt, wt.data(), sizeof(WinTask) * ntw);
+    std::memcpy(hT.item0, item0.data(), sizeof(int64_t) * (ntw + 1));
+    std::memcpy(hT.wk0, wk0.data(), sizeof(int64_t) * (ntw + 1));
+    std::memcpy(hT.r0, r0.data(), sizeof(int64_t) * (ntw + 1));
+    std::memcpy(hT.delta, delta.data(), sizeof(double) * Krow);
+    hT.zero[0] = 0.0;
+    std::memcpy(hT.perm, perm.data(), sizeof(int32_t) * K);
 
-    // ---- A7 window scan (all tasks, one launch)
-    NCF_TRY(launch_window((const WinTask*)d_wt, d_item0, ntw, nitems, wflags, cap, jmax, J.st,
-                          win_work));
-    NCF_TRY(launch_window_reduce((const WinTask*)d_wt, ntw, total_rows, d_wk0, wflags, J.st));
-
-    // ---- A2-A6 spectral numerator
-    // host tables of async copies live until the final synchronization
-    std::vector<int64_t> tile0(nts + 1), pos0(nts + 1), sk0(nts + 1);
-    std::vector<double> ev(std::max(Keval, 1));
-    std::vector<int32_t> rinfo(6 * std::max(nts, 1));
+    // spectral tables
+    std::map<int64_t, FftPlan> plans;
+    int64_t total_pos = 0, ntiles = 0;
+    double spread_bytes = 0.0;
+    for (int i = 0; i < nts; ++i) {
+        const SpecPlan& P = splans[i];
+        const SeriesDesc& d0 = sdesc[J.set[0].sd0 + P.prob];
+        SpecTask T{};
+        T.t0 = d0.t;
+        T.v0f = d0.v32;
+        T.v0d = d0.v32 ? nullptr : d0.v64;
+        T.n0 = d0.n;
+        if (J.ccf) {
+            const SeriesDesc& d1 = sdesc[J.set[1].sd0 + P.prob];
+            T.t1 = d1.t;
+            T.v1f = d1.v32;
+            T.v1d = d1.v32 ? nullptr : d1.v64;
+            T.n1 = d1.n;
+        }
+        T.t_ref = P.g.t_ref;
+        T.L = P.g.L;
+        T.N = P.g.N;
+        T.M = P.g.M;
+        T.s = P.g.s;
+        T.W = P.g.W;
+        T.h = J.h[P.prob];
+        T.kern = J.kern;
+        T.ccf = J.ccf ? 1 : 0;
+        T.grid = grids[i];
+        T.tile0 = ntiles;
+        T.ntiles = P.g.N / 4096;
+        ntiles += T.ntiles;
+        T.tile_rng = nullptr;
+        T.lags = dT.ev;
+        T.K_eval = Keval;
+        T.numer = numer[i];
+        T.scale_part = spart[i];
+        T.pos0 = total_pos;
+        total_pos += P.g.N;
+        hT.st[i] = T;
+        hT.tile0[i] = T.tile0;
+        hT.pos0[i] = T.pos0;
+        hT.sk0[i] = (int64_t)i * Keval;
+        hT.gtab[i] = grids[i];
+        if (!plans.count(T.N)) {
+            FftPlan fp;
+            NCF_TRY(fft_plan(T.N, fp64, &fp, J.st));
+            plans[T.N] = fp;
+        }
+        const FftPlan& fp = plans[T.N];
+        int lgN = 0;
+        while ((1LL << lgN) < T.N) ++lgN;
+        hT.rinfo[6 * i + 0] = fp.npass;
+        for (int q = 0; q < 4; ++q) {
+            int lg = 0;
+            if (q < fp.npass)
+                while ((1 << lg) < fp.radix[q]) ++lg;
+            hT.rinfo[6 * i + 1 + q] = lg;
+        }
+        hT.rinfo[6 * i + 5] = lgN;
+        spread_bytes += (double)(T.n0 + T.n1) * 12.0 + (double)T.N * csz;
+    }
     if (nts > 0) {
-        for (int64_t k = 0; k < K; ++k) ev[k] = J.lags[k];
-        if (!J.ccf) ev[K] = 0.0;
-        NCF_TRY_HIP(hipMemcpyAsync(d_evlags, ev.data(), sizeof(double) * Keval,
-                                   hipMemcpyHostToDevice, J.st));
-        std::map<int64_t, FftPlan> plans;
-        int64_t spread_bytes = 0, total_pos = 0;
-        for (int i = 0; i < nts; ++i) {
-            tile0[i] = stasks[i].tile0;
-            pos0[i] = stasks[i].pos0;
-            sk0[i] = (int64_t)i * Keval;
-            const int64_t N = stasks[i].N;
-            if (!plans.count(N)) {
-                FftPlan fp;
-                NCF_TRY(fft_plan(N, fp64, &fp, J.st));
-                plans[N] = fp;
-            }
-            const FftPlan& fp = plans[N];
-            int lgN = 0;
-            while ((1LL << lgN) < N) ++lgN;
-            rinfo[6 * i + 0] = fp.npass;
-            for (int q = 0; q < 4; ++q) {
-                int lg = 0;
-                if (q < fp.npass)
-                    while ((1 << lg) < fp.radix[q]) ++lg;
-                rinfo[6 * i + 1 + q] = lg;
-            }
-            rinfo[6 * i + 5] = lgN;
-            spread_bytes += (stasks[i].n0 + stasks[i].n1) * 12 + N * (int64_t)csz;
-            total_pos += N;
-        }
-        tile0[nts] = stasks.back().tile0 + stasks.back().ntiles;
-        pos0[nts] = total_pos;
-        sk0[nts] = (int64_t)nts * Keval;
-        NCF_TRY_HIP(hipMemcpyAsync(d_st, stasks.data(), sizeof(SpecTask) * nts,
-                                   hipMemcpyHostToDevice, J.st));
-        NCF_TRY_HIP(hipMemcpyAsync(d_tile0, tile0.data(), sizeof(int64_t) * (nts + 1),
-                                   hipMemcpyHostToDevice, J.st));
-        NCF_TRY_HIP(hipMemcpyAsync(d_pos0, pos0.data(), sizeof(int64_t) * (nts + 1),
-                                   hipMemcpyHostToDevice, J.st));
-        NCF_TRY_HIP(hipMemcpyAsync(d_sk0, sk0.data(), sizeof(int64_t) * (nts + 1),
-                                   hipMemcpyHostToDevice, J.st));
-        NCF_TRY_HIP(hipMemcpyAsync(d_rinfo, rinfo.data(), sizeof(int32_t) * 6 * nts,
-                                   hipMemcpyHostToDevice, J.st));
-        const int64_t ntiles = tile0[nts];
-        NCF_TRY(launch_tile_ranges((const SpecTask*)d_st, d_tile0, nts, ntiles, 4096, J.st));
-        NCF_TRY(launch_spread((const SpecTask*)d_st, d_tile0, nts, ntiles, 4096, fp64, J.st,
-                              (double)spread_bytes));
-        // grids of one size are contiguous in the task list (sorted by N)
-        NCF_TRY_HIP(hipMemcpyAsync(d_gtab, grids.data(), sizeof(void*) * nts,
-                                   hipMemcpyHostToDevice, J.st));
-        std::vector<std::pair<int, int>> groups;  // (first task, count)
-        for (int i = 0; i < nts; ++i) {
-            if (i == 0 || stasks[i].N != stasks[i - 1].N)
-                groups.push_back({i, 1});
-            else
-                groups.back().second++;
-        }
-        for (auto& gq : groups)
-            NCF_TRY(fft_exec(plans[stasks[gq.first].N], d_gtab + gq.first, gq.second, +1, fp64,
-                             J.st));
-        NCF_TRY(launch_product((const SpecTask*)d_st, d_pos0, nts, total_pos,
-                               (const int64_t*)d_rinfo, fp64, J.st, 2.0 * total_pos * csz));
-        for (auto& gq : groups)
-            NCF_TRY(fft_exec(plans[stasks[gq.first].N], d_gtab + gq.first, gq.second, -1, fp64,
-                             J.st));
-        NCF_TRY(launch_interp((const SpecTask*)d_st, nts, d_sk0, (int64_t)nts * Keval, fp64,
-                              J.st));
+        hT.tile0[nts] = ntiles;
+        hT.pos0[nts] = total_pos;
+        hT.sk0[nts] = (int64_t)nts * Keval;
+        for (int64_t k = 0; k < K; ++k) hT.ev[k] = J.lags[k];
+        if (!J.ccf) hT.ev[K] = 0.0;
     }
 
-    // ---- A8 normalization
-    std::vector<int32_t> dstat(J.nprob);
-    std::vector<NormTask> nt(J.nprob);
+    // normalization tables
     {
-        // locate window tasks of each problem
         std::vector<int> main_t(J.nprob, -1), selfx(J.nprob, -1), selfy(J.nprob, -1),
             spec_t(J.nprob, -1);
         for (int i = 0; i < ntw; ++i) {
@@ -795,16 +797,16 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             NormTask T{};
             T.ccf = J.ccf ? 1 : 0;
             T.K = (int32_t)K;
-            T.perm = d_perm;
+            T.perm = dT.perm;
             T.row0 = row0;
             T.spectral = spectral ? 1 : 0;
             T.weighted = weighted ? 1 : 0;
             T.is_rect = rect ? 1 : 0;
-            T.status = d_status + p;
+            T.status = dT.status + p;
             T.c = d_c + p * K;
             T.b = d_b + p * K;
             T.count = d_cnt ? d_cnt + p * K : nullptr;
-            dstat[p] = pstat[p];
+            hT.status[p] = pstat[p];
             if (pstat[p] == NCF_OK) {
                 if (main_t[p] >= 0) T.wsums = wt[main_t[p]].sums;
                 if (J.ccf) {
@@ -812,45 +814,49 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
                     T.self_y = wt[selfy[p]].sums;
                 }
                 if (spectral) {
-                    const SpecTask& S = stasks[spec_t[p]];
-                    T.numer = S.numer;
-                    T.scale_part = S.scale_part;
-                    T.nscale_part = S.N / 256;
+                    const int i = spec_t[p];
+                    T.numer = numer[i];
+                    T.scale_part = spart[i];
+                    T.nscale_part = splans[i].g.N / 256;
                 }
             } else {
-                T.skip = 1;  // outputs filled with NaN below
+                T.skip = 1;  // outputs: c = NaN, b = 0, count = 0
             }
-            nt[p] = T;
+            hT.nt[p] = T;
         }
     }
-    NCF_TRY_HIP(hipMemcpyAsync(d_status, dstat.data(), sizeof(int32_t) * J.nprob,
-                               hipMemcpyHostToDevice, J.st));
-    NCF_TRY_HIP(
-        hipMemcpyAsync(d_nt, nt.data(), sizeof(NormTask) * J.nprob, hipMemcpyHostToDevice, J.st));
-    // problems that failed validation: fill c = NaN, b = 0, count = 0
-    bool any_bad = false;
-    for (int64_t p = 0; p < J.nprob; ++p) any_bad |= (pstat[p] != NCF_OK);
-    if (any_bad && K > 0) {
-        std::vector<double> nanv(K, NAN), zv(K, 0.0);
-        std::vector<int64_t> zc(K, 0);
-        for (int64_t p = 0; p < J.nprob; ++p) {
-            if (pstat[p] == NCF_OK) continue;
-            NCF_TRY_HIP(hipMemcpyAsync(d_c + p * K, nanv.data(), sizeof(double) * K,
-                                       hipMemcpyHostToDevice, J.st));
-            NCF_TRY_HIP(hipMemcpyAsync(d_b + p * K, zv.data(), sizeof(double) * K,
-                                       hipMemcpyHostToDevice, J.st));
-            if (d_cnt)
-                NCF_TRY_HIP(hipMemcpyAsync(d_cnt + p * K, zc.data(), sizeof(int64_t) * K,
-                                           hipMemcpyHostToDevice, J.st));
-        }
-        // these host buffers must outlive the copies
-        NCF_TRY_HIP(hipStreamSynchronize(J.st));
-    }
-    NCF_TRY(launch_normalize((const NormTask*)d_nt, (int)J.nprob, J.nprob * K, nullptr, J.st));
+    NCF_TRY_HIP(hipMemcpyAsync(stg2->d, stg2->h, t2.off, hipMemcpyHostToDevice, J.st));
 
-    // ---- outputs
-    std::vector<int32_t> fstat(J.nprob);
-    NCF_TRY_HIP(hipMemcpyAsync(fstat.data(), d_status, sizeof(int32_t) * J.nprob,
+    // ------------------------------------------------ A7 window scan
+    NCF_TRY(launch_window(dT.wt, dT.item0, ntw, nitems, wflags, cap, jmax_used, J.st,
+                          win_work));
+    NCF_TRY(launch_window_reduce(dT.wt, ntw, total_rows, dT.wk0, dT.r0, nred1, wflags, J.st));
+
+    // ------------------------------------------------ A2-A6 spectral numerator
+    if (nts > 0) {
+        NCF_TRY(launch_spread(dT.st, dT.tile0, nts, ntiles, 4096, fp64, J.st, spread_bytes));
+        std::vector<std::pair<int, int>> groups;  // (first task, count) per grid size
+        for (int i = 0; i < nts; ++i) {
+            if (i == 0 || splans[i].g.N != splans[i - 1].g.N)
+                groups.push_back({i, 1});
+            else
+                groups.back().second++;
+        }
+        for (auto& gq : groups)
+            NCF_TRY(fft_exec(plans[splans[gq.first].g.N], dT.gtab + gq.first, gq.second, +1,
+                             fp64, J.st));
+        NCF_TRY(launch_product(dT.st, dT.pos0, nts, total_pos, (const int64_t*)dT.rinfo, fp64,
+                               J.st, 2.0 * total_pos * csz));
+        for (auto& gq : groups)
+            NCF_TRY(fft_exec(plans[splans[gq.first].g.N], dT.gtab + gq.first, gq.second, -1,
+                             fp64, J.st));
+        NCF_TRY(launch_interp(dT.st, nts, dT.sk0, (int64_t)nts * Keval, fp64, J.st));
+    }
+
+    // ------------------------------------------------ A8 normalization, outputs
+    NCF_TRY(launch_normalize(dT.nt, (int)J.nprob, J.nprob * K, nullptr, J.st));
+    int32_t* h_fstat = hT.status;  // pinned; the upload above has been enqueued before
+    NCF_TRY_HIP(hipMemcpyAsync(h_fstat, dT.status, sizeof(int32_t) * J.nprob,
                                hipMemcpyDeviceToHost, J.st));
     if (!J.dev_ptrs && K > 0) {
         NCF_TRY_HIP(hipMemcpyAsync(J.c, d_c, sizeof(double) * J.nprob * K, hipMemcpyDeviceToHost,
@@ -868,8 +874,8 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     }
     int first = NCF_OK;
     for (int64_t p = 0; p < J.nprob; ++p) {
-        if (J.status) J.status[p] = fstat[p];
-        if (fstat[p] != NCF_OK && first == NCF_OK) first = fstat[p];
+        if (J.status) J.status[p] = h_fstat[p];
+        if (h_fstat[p] != NCF_OK && first == NCF_OK) first = h_fstat[p];
     }
     if (first != NCF_OK) {
         static const char* names[] = {"ok", "invalid argument", "unsorted times",

@@ -58,20 +58,52 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nblocks) {
     return (b % kXcds) * per + b / kXcds;
 }
 
+// First index i in [0, n) with (upper ? a[i] > key : a[i] >= key), else n.
+// Called by a whole wavefront: 64 probes per round.
+template <typename T>
+__device__ __forceinline__ int64_t wave_search(const T* a, int64_t n, T key, bool upper) {
+    const int lane = threadIdx.x & 63;
+    int64_t lo = 0, hi = n;
+    while (hi > lo) {
+        const int64_t len = hi - lo;
+        const int64_t stride = (len + 63) / 64;
+        const int64_t p = lo + (int64_t)lane * stride;
+        bool before = false;
+        if (p < hi) {
+            T v = a[p];
+            before = upper ? (v <= key) : (v < key);
+        }
+        const uint64_t m = __ballot(before);
+        const int q = __popcll(m);
+        if (stride == 1 || q == 0) return lo + (stride == 1 ? q : 0);
+        const int64_t nlo = lo + (int64_t)(q - 1) * stride + 1;
+        const int64_t phq = lo + (int64_t)q * stride;
+        hi = phq < hi ? phq : hi;
+        lo = nlo;
+    }
+    return lo;
+}
+
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // ----------------------------------------------------------- A1 moments
 struct SeriesDesc {
-    int64_t off;     // first sample in the concatenated arrays
-    int64_t n;       // samples
-    int64_t pre_off; // first entry of this series' prefix arrays (n+1 entries)
-    int32_t chunk0;  // first chunk of the series
-    int32_t nchunk;  // chunks of the series
+    const double* t;  // times, values, optional errors of this series
+    const double* x;
+    const double* err;
+    float* v32;       // outputs, each may be null: w (x - mean)/sd in FP32 / FP64,
+    double* v64;      // weights, and FP64 prefix sums of v and w (n + 1 entries)
+    double* w64;
+    double* pv;
+    double* pw;
+    int64_t n;        // samples
+    int32_t chunk0;   // first chunk of the series
+    int32_t nchunk;   // chunks of the series
 };
 
 struct Chunk {
-    int64_t begin, end;  // sample range [begin, end)
+    int64_t begin, end;  // sample range [begin, end) within the series
     int32_t series;
     int32_t pad;
 };
@@ -84,21 +116,14 @@ struct SeriesStat {
 };
 
 struct MomentsArgs {
-    const double* t;
-    const double* x;
-    const double* err;      // may be null
     const SeriesDesc* series;
     const Chunk* chunks;
     int32_t nseries, nchunks;
     double* chunk_part;      // 4 doubles per chunk: sw, mean, M2, flags
-    SeriesStat* stats;       // nseries
-    // standardize outputs (each may be null)
-    float* v32;              // w * (x - mean)/sd, FP32
-    double* v64;             // same, FP64
-    double* w64;             // weights
-    double* pv;              // prefix of v64, n+1 per series
-    double* pw;              // prefix of w64, n+1 per series
     double* chunk_tot;       // 2 doubles per chunk (v, w) totals for the prefix pass
+    SeriesStat* stats;       // nseries
+    int32_t prefix;          // any series has prefix outputs
+    int32_t pad;
 };
 
 int launch_moments(const MomentsArgs& a, hipStream_t st);
@@ -132,6 +157,7 @@ struct WinTask {
     double h;            // bandwidth
     double W;            // window half-width: 6h (Gaussian) or h (rectangle)
     double* part;        // [n_jt][K][4] partial sums: C, B, b, count (count as bits)
+    double* part2;       // [ceil(n_jt / 64)][K][4] first-level sums of part
     double* sums;        // [K][4] final sums
     int64_t item0;       // first work item of this task
 };
@@ -139,7 +165,8 @@ struct WinTask {
 int launch_window(const WinTask* d_tasks, const int64_t* d_item0, int ntasks, int64_t nitems,
                   uint32_t flags, int cap, int jmax, hipStream_t st, double work_units);
 int launch_window_reduce(const WinTask* d_tasks, int ntasks, int64_t total_k, const int64_t* d_k0,
-                         uint32_t flags, hipStream_t st);
+                         const int64_t* d_r0, int64_t nred1, uint32_t flags, hipStream_t st);
+constexpr int kWinJc = 64;  // j-tiles per first-level reduction block
 
 // --------------------------------------------------- A2-A6 spectral route
 struct SpreadParams {

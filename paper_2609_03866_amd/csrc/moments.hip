@@ -42,15 +42,15 @@ k_chunk_moments(MomentsArgs a) {
     double sw = 0.0, swx = 0.0;
     int bad = 0, unsorted = 0;
     for (int64_t i = ch.begin + tid; i < ch.end; i += kThreads) {
-        double ti = a.t[i], xi = a.x[i];
+        double ti = sd.t[i], xi = sd.x[i];
         double wi = 1.0;
-        if (a.err) {
-            double e = a.err[i];
+        if (sd.err) {
+            double e = sd.err[i];
             if (!(e > 0.0) || !isfinite(e)) bad = 1;
             wi = 1.0 / (e * e);
         }
         if (!isfinite(ti) || !isfinite(xi)) bad = 1;
-        if (i > sd.off && !(ti >= a.t[i - 1])) unsorted = 1;
+        if (i > 0 && !(ti >= sd.t[i - 1])) unsorted = 1;
         sw += wi;
         swx += wi * xi;
     }
@@ -60,11 +60,11 @@ k_chunk_moments(MomentsArgs a) {
     double m2 = 0.0;
     for (int64_t i = ch.begin + tid; i < ch.end; i += kThreads) {
         double wi = 1.0;
-        if (a.err) {
-            double e = a.err[i];
+        if (sd.err) {
+            double e = sd.err[i];
             wi = 1.0 / (e * e);
         }
-        double d = a.x[i] - mean;
+        double d = sd.x[i] - mean;
         m2 += wi * d * d;
     }
     double M2 = block_sum(m2, sh);
@@ -79,48 +79,72 @@ k_chunk_moments(MomentsArgs a) {
     }
 }
 
-__global__ void k_series_finalize(MomentsArgs a) {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= a.nseries) return;
+// Combine (sum of weights, mean, M2) of two disjoint parts (pairwise update).
+__device__ __forceinline__ void merge_moments(double& sw, double& mean, double& m2, double swb,
+                                              double mb, double m2b) {
+    if (swb == 0.0) return;
+    if (sw == 0.0) {
+        sw = swb;
+        mean = mb;
+        m2 = m2b;
+        return;
+    }
+    const double tot = sw + swb;
+    const double dlt = mb - mean;
+    mean = mean + dlt * (swb / tot);
+    m2 = m2 + m2b + dlt * dlt * (sw * swb / tot);
+    sw = tot;
+}
+
+// One workgroup per series: each thread merges a contiguous run of chunks in
+// order, then the threads' results are merged pairwise in a fixed tree.
+__global__ void __launch_bounds__(kThreads)
+k_series_finalize(MomentsArgs a) {
+    __shared__ double sh[3][kThreads];
+    __shared__ int shf[kThreads];
+    const int s = blockIdx.x;
+    const int tid = threadIdx.x;
     const SeriesDesc sd = a.series[s];
+    double sw = 0.0, mean = 0.0, m2 = 0.0;
+    int fl = 0;
+    const int per = (sd.nchunk + kThreads - 1) / kThreads;
+    const int c0 = tid * per, c1 = min(sd.nchunk, c0 + per);
+    for (int c = c0; c < c1; ++c) {
+        const double* p = a.chunk_part + 4 * (int64_t)(sd.chunk0 + c);
+        merge_moments(sw, mean, m2, p[0], p[1], p[2]);
+        fl |= (int)p[3];
+    }
+    sh[0][tid] = sw;
+    sh[1][tid] = mean;
+    sh[2][tid] = m2;
+    shf[tid] = fl;
+    __syncthreads();
+    for (int off = 1; off < kThreads; off <<= 1) {
+        if ((tid & (2 * off - 1)) == 0 && tid + off < kThreads) {
+            double w0 = sh[0][tid], m0 = sh[1][tid], q0 = sh[2][tid];
+            merge_moments(w0, m0, q0, sh[0][tid + off], sh[1][tid + off], sh[2][tid + off]);
+            sh[0][tid] = w0;
+            sh[1][tid] = m0;
+            sh[2][tid] = q0;
+            shf[tid] |= shf[tid + off];
+        }
+        __syncthreads();
+    }
+    if (tid != 0) return;
     SeriesStat st;
     st.status = NCF_OK;
     st.pad = 0;
-    if (sd.n < 2) {
-        st.status = NCF_E_INVALID_ARG;
-        st.mean = st.sd = st.sw = st.tmin = st.tmax = 0.0;
-        a.stats[s] = st;
-        return;
-    }
-    double sw = 0.0, mean = 0.0, m2 = 0.0;
-    int bad = 0, unsorted = 0;
-    for (int c = 0; c < sd.nchunk; ++c) {
-        const double* p = a.chunk_part + 4 * (int64_t)(sd.chunk0 + c);
-        double swb = p[0], mb = p[1], m2b = p[2];
-        int fl = (int)p[3];
-        bad |= fl & 1;
-        unsorted |= (fl >> 1) & 1;
-        if (c == 0) {
-            sw = swb;
-            mean = mb;
-            m2 = m2b;
-        } else {
-            double tot = sw + swb;
-            double dlt = mb - mean;
-            mean = mean + dlt * (swb / tot);
-            m2 = m2 + m2b + dlt * dlt * (sw * swb / tot);
-            sw = tot;
-        }
-    }
-    double sdv = sqrt(m2 / sw);
-    st.mean = mean;
+    const int flags = shf[0];
+    const double swt = sh[0][0];
+    const double sdv = sqrt(sh[2][0] / swt);
+    st.mean = sh[1][0];
     st.sd = sdv;
-    st.sw = sw;
-    st.tmin = a.t[sd.off];
-    st.tmax = a.t[sd.off + sd.n - 1];
-    if (bad)
+    st.sw = swt;
+    st.tmin = sd.t[0];
+    st.tmax = sd.t[sd.n - 1];
+    if (sd.n < 2 || (flags & 1))
         st.status = NCF_E_INVALID_ARG;
-    else if (unsorted)
+    else if (flags & 2)
         st.status = NCF_E_UNSORTED;
     else if (!(sdv > 0.0) || !isfinite(sdv))
         st.status = NCF_E_DEGENERATE;
@@ -139,22 +163,22 @@ k_standardize(MomentsArgs a) {
     const bool ok = st.status == NCF_OK;
     const double mean = st.mean;
     const double inv_sd = ok ? 1.0 / st.sd : 0.0;
-    const bool do_prefix = a.pv != nullptr;
+    const bool do_prefix = sd.pv != nullptr;
     double carry_v = 0.0, carry_w = 0.0;
-    // prefix index of sample i within the series' prefix array: i - off + 1
+    // prefix index of sample i within the series' prefix array: i + 1
     for (int64_t base = ch.begin; base < ch.end; base += kThreads) {
         int64_t i = base + tid;
         double v = 0.0, w = 0.0;
         if (i < ch.end) {
             w = 1.0;
-            if (a.err) {
-                double e = a.err[i];
+            if (sd.err) {
+                double e = sd.err[i];
                 w = 1.0 / (e * e);
             }
-            v = ok ? w * ((a.x[i] - mean) * inv_sd) : 0.0;
-            if (a.v32) a.v32[i] = (float)v;
-            if (a.v64) a.v64[i] = v;
-            if (a.w64) a.w64[i] = w;
+            v = ok ? w * ((sd.x[i] - mean) * inv_sd) : 0.0;
+            if (sd.v32) sd.v32[i] = (float)v;
+            if (sd.v64) sd.v64[i] = v;
+            if (sd.w64) sd.w64[i] = w;
         }
         if (do_prefix) {
             // inclusive Hillis-Steele scan over the block (fixed order)
@@ -170,9 +194,8 @@ k_standardize(MomentsArgs a) {
                 __syncthreads();
             }
             if (i < ch.end) {
-                int64_t pidx = sd.pre_off + (i - sd.off) + 1;
-                a.pv[pidx] = carry_v + shv[tid];
-                if (a.pw) a.pw[pidx] = carry_w + shw[tid];
+                sd.pv[i + 1] = carry_v + shv[tid];
+                if (sd.pw) sd.pw[i + 1] = carry_w + shw[tid];
             }
             carry_v += shv[kThreads - 1];
             carry_w += shw[kThreads - 1];
@@ -182,27 +205,54 @@ k_standardize(MomentsArgs a) {
     if (do_prefix && tid == 0) {
         a.chunk_tot[2 * (int64_t)blockIdx.x] = carry_v;
         a.chunk_tot[2 * (int64_t)blockIdx.x + 1] = carry_w;
-        if (ch.begin == sd.off) {
-            a.pv[sd.pre_off] = 0.0;
-            if (a.pw) a.pw[sd.pre_off] = 0.0;
+        if (ch.begin == 0) {
+            sd.pv[0] = 0.0;
+            if (sd.pw) sd.pw[0] = 0.0;
         }
     }
 }
 
 // Exclusive scan of chunk totals per series (in place: chunk_tot becomes the
-// offset to add to each chunk).
-__global__ void k_chunk_offsets(MomentsArgs a) {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= a.nseries) return;
+// offset to add to each chunk). One workgroup per series: per-thread runs,
+// then a fixed-order scan of the run totals.
+__global__ void __launch_bounds__(kThreads)
+k_chunk_offsets(MomentsArgs a) {
+    __shared__ double shv[kThreads];
+    __shared__ double shw[kThreads];
+    const int s = blockIdx.x;
+    const int tid = threadIdx.x;
     const SeriesDesc sd = a.series[s];
-    double cv = 0.0, cw = 0.0;
-    for (int c = 0; c < sd.nchunk; ++c) {
+    if (!sd.pv) return;
+    const int per = (sd.nchunk + kThreads - 1) / kThreads;
+    const int c0 = tid * per, c1 = min(sd.nchunk, c0 + per);
+    double tv = 0.0, tw = 0.0;
+    for (int c = c0; c < c1; ++c) {
+        const double* p = a.chunk_tot + 2 * (int64_t)(sd.chunk0 + c);
+        tv += p[0];
+        tw += p[1];
+    }
+    shv[tid] = tv;
+    shw[tid] = tw;
+    __syncthreads();
+    if (tid == 0) {  // exclusive scan of 256 run totals, in order
+        double cv = 0.0, cw = 0.0;
+        for (int i = 0; i < kThreads; ++i) {
+            const double v = shv[i], w = shw[i];
+            shv[i] = cv;
+            shw[i] = cw;
+            cv += v;
+            cw += w;
+        }
+    }
+    __syncthreads();
+    double cv = shv[tid], cw = shw[tid];
+    for (int c = c0; c < c1; ++c) {
         double* p = a.chunk_tot + 2 * (int64_t)(sd.chunk0 + c);
-        double tv = p[0], tw = p[1];
+        const double v = p[0], w = p[1];
         p[0] = cv;
         p[1] = cw;
-        cv += tv;
-        cw += tw;
+        cv += v;
+        cw += w;
     }
 }
 
@@ -210,13 +260,13 @@ __global__ void __launch_bounds__(kThreads)
 k_prefix_add(MomentsArgs a) {
     const Chunk ch = a.chunks[blockIdx.x];
     const SeriesDesc sd = a.series[ch.series];
+    if (!sd.pv) return;
     const double ov = a.chunk_tot[2 * (int64_t)blockIdx.x];
     const double ow = a.chunk_tot[2 * (int64_t)blockIdx.x + 1];
-    if (ch.begin == sd.off) return;  // first chunk: offset 0
+    if (ch.begin == 0) return;  // first chunk: offset 0
     for (int64_t i = ch.begin + threadIdx.x; i < ch.end; i += kThreads) {
-        int64_t pidx = sd.pre_off + (i - sd.off) + 1;
-        a.pv[pidx] += ov;
-        if (a.pw) a.pw[pidx] += ow;
+        sd.pv[i + 1] += ov;
+        if (sd.pw) sd.pw[i + 1] += ow;
     }
 }
 
@@ -230,7 +280,7 @@ int launch_moments(const MomentsArgs& a, hipStream_t st) {
     }
     {
         ProfScope p(st, "series_finalize", 0.0, "bytes");
-        hipLaunchKernelGGL(k_series_finalize, dim3((a.nseries + 127) / 128), dim3(128), 0, st, a);
+        hipLaunchKernelGGL(k_series_finalize, dim3(a.nseries), dim3(kThreads), 0, st, a);
         NCF_CHECK_LAUNCH();
     }
     return NCF_OK;
@@ -243,8 +293,8 @@ int launch_standardize(const MomentsArgs& a, hipStream_t st) {
         hipLaunchKernelGGL(k_standardize, dim3(a.nchunks), dim3(kThreads), 0, st, a);
         NCF_CHECK_LAUNCH();
     }
-    if (a.pv) {
-        hipLaunchKernelGGL(k_chunk_offsets, dim3((a.nseries + 127) / 128), dim3(128), 0, st, a);
+    if (a.prefix) {
+        hipLaunchKernelGGL(k_chunk_offsets, dim3(a.nseries), dim3(kThreads), 0, st, a);
         NCF_CHECK_LAUNCH();
         hipLaunchKernelGGL(k_prefix_add, dim3(a.nchunks), dim3(kThreads), 0, st, a);
         NCF_CHECK_LAUNCH();

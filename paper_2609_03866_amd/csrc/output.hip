@@ -21,8 +21,15 @@ k_normalize(const NormTask* __restrict__ tasks) {
     __shared__ double red[2][kThreads];
     __shared__ double sh_scale;
     const NormTask& T = tasks[blockIdx.x];
-    if (T.skip) return;
     const int tid = threadIdx.x;
+    if (T.skip) {  // the problem failed validation
+        for (int k = tid; k < T.K; k += kThreads) {
+            T.c[k] = NAN;
+            T.b[k] = 0.0;
+            if (T.count) T.count[k] = 0;
+        }
+        return;
+    }
     const int bq = T.weighted ? 1 : 2;  // which window sum is the denominator B
     // lag-0 scale
     if (T.ccf && T.spectral) {

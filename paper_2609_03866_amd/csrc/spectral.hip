@@ -156,13 +156,28 @@ k_spread(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ tile0, 
          int64_t ntiles, int64_t nblocks) {
     using C2 = typename Cplx<R>::T;
     __shared__ PtsLds<R> P;
-    const int64_t g = xcd_remap(blockIdx.x, nblocks);
+    const int64_t g = blockIdx.x;
+    (void)nblocks;
     if (g >= ntiles) return;
     const int ti = (int)find_task(tile0, ntasks, g);
     const SpecTask& T = tasks[ti];
     const int64_t tile = g - T.tile0;
     const int64_t c0 = tile * kTile;
-    const int64_t* rng = T.tile_rng + 4 * tile;
+    // sample index ranges that can reach this tile (sorted times)
+    __shared__ int64_t rng[4];
+    {
+        const int wave = threadIdx.x >> 6;
+        const double inv_scale = T.L / (double)T.N;  // time per cell
+        const double lo_t = T.t_ref + ((double)c0 - T.W - 2.0) * inv_scale;
+        const double hi_t = T.t_ref + ((double)c0 + kTile + T.W + 2.0) * inv_scale;
+        int64_t r = 0;
+        if (wave == 0) r = wave_search<double>(T.t0, T.n0, lo_t, false);
+        if (wave == 1) r = wave_search<double>(T.t0, T.n0, hi_t, false);
+        if (wave == 2) r = T.ccf ? wave_search<double>(T.t1, T.n1, lo_t, false) : 0;
+        if (wave == 3) r = T.ccf ? wave_search<double>(T.t1, T.n1, hi_t, false) : 0;
+        if ((threadIdx.x & 63) == 0) rng[wave] = r;
+        __syncthreads();
+    }
     const double scale = (double)T.N / T.L;
     const R W = (R)T.W;
     // exp(-d^2 / 2 s^2): FP32 uses exp2 with log2(e) folded in
@@ -260,12 +275,28 @@ k_product(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pos0, 
         const int64_t m = k <= N / 2 ? k : k - N;
         const double md = (double)m;
         const bool keep = (m <= T.M && m >= -T.M);
-        // 1/Psi(m/N) = exp(2 pi^2 s^2 m^2 / N^2) / (sqrt(2 pi) s)
-        const double e_psi = 2.0 * M_PI * M_PI * s * s * md * md / (Nd * Nd);
-        const double ker = keep ? lag_kernel_ft<R>(T.kern, md / L, h) : 0.0;
-        // phihat / (L Psi^3) and phihat / (L Psi^2)
-        const double f3 = ker * exp(3.0 * e_psi) / (L * 15.749609945722419 * s * s * s);
-        const double f2 = ker * exp(2.0 * e_psi) / (L * 6.283185307179586 * s * s);
+        // phihat(m/L) / (L Psi^3) and phihat(m/L) / (L Psi^2) with
+        // Psi(m/N) = sqrt(2 pi) s exp(-2 pi^2 s^2 m^2 / N^2)
+        const double a_psi = 2.0 * M_PI * M_PI * s * s * md * md / (Nd * Nd);
+        double f3 = 0.0, f2 = 0.0;
+        if (keep) {
+            const double c3 = 1.0 / (L * 15.749609945722419 * s * s * s);
+            const double c2 = 1.0 / (L * 6.283185307179586 * s * s);
+            if (T.kern == NCF_GAUSSIAN) {
+                const double a_h = 2.0 * M_PI * M_PI * h * h * (md / L) * (md / L);
+                if (sizeof(R) == 4) {
+                    f3 = c3 * (double)__expf((float)(3.0 * a_psi - a_h));
+                    f2 = c2 * (double)__expf((float)(2.0 * a_psi - a_h));
+                } else {
+                    f3 = c3 * exp(3.0 * a_psi - a_h);
+                    f2 = c2 * exp(2.0 * a_psi - a_h);
+                }
+            } else {
+                const double ker = lag_kernel_ft<R>(T.kern, md / L, h);
+                f3 = c3 * ker * exp(3.0 * a_psi);
+                f2 = c2 * ker * exp(2.0 * a_psi);
+            }
+        }
         if (!T.ccf) {
             const C2 z = Z[p];
             const double pw = (double)z.x * z.x + (double)z.y * z.y;

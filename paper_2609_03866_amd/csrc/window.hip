@@ -30,32 +30,6 @@ namespace {
 
 constexpr int kThreads = 256;
 
-// First index i in [0, n) with (upper ? a[i] > key : a[i] >= key), else n.
-// Called by a whole wavefront: 64 probes per round.
-template <typename T>
-__device__ int64_t wave_search(const T* a, int64_t n, T key, bool upper) {
-    const int lane = threadIdx.x & 63;
-    int64_t lo = 0, hi = n;
-    while (hi > lo) {
-        const int64_t len = hi - lo;
-        const int64_t stride = (len + 63) / 64;
-        const int64_t p = lo + (int64_t)lane * stride;
-        bool before = false;
-        if (p < hi) {
-            T v = a[p];
-            before = upper ? (v <= key) : (v < key);
-        }
-        const uint64_t m = __ballot(before);
-        const int q = __popcll(m);
-        if (stride == 1 || q == 0) return lo + (stride == 1 ? q : 0);
-        const int64_t nlo = lo + (int64_t)(q - 1) * stride + 1;
-        const int64_t phq = lo + (int64_t)q * stride;
-        hi = phq < hi ? phq : hi;
-        lo = nlo;
-    }
-    return lo;
-}
-
 __device__ __forceinline__ int lower_idx(const double* a, int lo, int hi, double key) {
     while (lo < hi) {
         int mid = (lo + hi) >> 1;
@@ -83,54 +57,137 @@ struct Acc {
     int64_t n;
 };
 
-// Two-pointer scan of one lane over outer samples [ja, jb) (indices relative
-// to the tile's first outer sample) for one lag offset `delta`, on the window
-// samples Tl[0, len) (relative to the tile's first window sample).
-template <uint32_t F>
-__device__ __forceinline__ void scan_lane(Acc& acc, const double* Tl, const double* A1,
-                                          const double* A2, int len, const double* Sl,
-                                          const double* VOl, const double* WOl, int ja, int jb,
-                                          double delta, double W, double inv_h) {
+// Dynamic LDS of the window kernel, referenced by symbol so that reads
+// through it are LDS instructions.
+extern __shared__ double g_win_lds[];
+
+typedef __attribute__((address_space(1))) const double* gdp;
+
+constexpr double kInf = __builtin_huge_val();
+
+// Window samples and outer samples staged in LDS; the staged window array
+// is followed by +inf sentinels, so reads up to 8 past its end need no check.
+struct LdsView {
+    int t0, a10, a20, s0, vo0, wo0, len;
+    __device__ __forceinline__ double T(int i) const { return g_win_lds[t0 + i]; }
+    __device__ __forceinline__ double A1(int i) const { return g_win_lds[a10 + i]; }
+    __device__ __forceinline__ double A2(int i) const { return g_win_lds[a20 + i]; }
+    __device__ __forceinline__ double S(int j) const { return g_win_lds[s0 + j]; }
+    __device__ __forceinline__ double VO(int j) const { return g_win_lds[vo0 + j]; }
+    __device__ __forceinline__ double WO(int j) const { return g_win_lds[wo0 + j]; }
+};
+
+// Fallback when the window range does not fit in LDS: global memory with
+// explicit bounds.
+struct GlbView {
+    gdp t, a1, a2, s, vo, wo;
+    int len;
+    __device__ __forceinline__ double T(int i) const { return i < len ? t[i] : kInf; }
+    __device__ __forceinline__ double A1(int i) const { return a1[i]; }
+    __device__ __forceinline__ double A2(int i) const { return a2[i]; }
+    __device__ __forceinline__ double S(int j) const { return s[j]; }
+    __device__ __forceinline__ double VO(int j) const { return vo[j]; }
+    __device__ __forceinline__ double WO(int j) const { return wo[j]; }
+};
+
+template <typename V>
+__device__ __forceinline__ int lower_idx(const V& v, int lo, int hi, double key) {
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (v.T(mid) < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+template <typename V>
+__device__ __forceinline__ int upper_idx(const V& v, int lo, int hi, double key) {
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (v.T(mid) <= key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Advance a pointer over sorted samples while T(p) < key (or <= key):
+// four independent reads per round; sorted order makes the passing samples
+// a prefix of the four.
+template <bool LE, typename V>
+__device__ __forceinline__ int advance(const V& v, int p, double key) {
+    for (;;) {
+        const double x0 = v.T(p), x1 = v.T(p + 1), x2 = v.T(p + 2), x3 = v.T(p + 3);
+        const int a = LE ? (x0 <= key) + (x1 <= key) + (x2 <= key) + (x3 <= key)
+                         : (x0 < key) + (x1 < key) + (x2 < key) + (x3 < key);
+        p += a;
+        if (a < 4) return p;
+    }
+}
+
+// Two-pointer scan of one lane over outer samples [ja, jb) (relative to the
+// tile's first outer sample) for one lag offset `delta`, on the window
+// samples [0, len) (relative to the tile's first window sample).
+template <uint32_t F, typename V>
+__device__ __forceinline__ void scan_lane(Acc& acc, const V& v, int ja, int jb, double delta,
+                                          double W, double inv_h) {
     constexpr bool RECT = (F & WIN_RECT) != 0;
     constexpr bool NUMER = (F & WIN_NUMER) != 0;
     constexpr bool WTD = (F & WIN_WEIGHTED) != 0;
     constexpr bool E64 = (F & WIN_EXP64) != 0;
     if (ja >= jb) return;
-    double c = Sl[ja] + delta;
-    int lo = lower_idx(Tl, 0, len, c - W);
-    int hi = RECT ? upper_idx(Tl, lo, len, c + W) : lower_idx(Tl, lo, len, c + W);
-    // -0.5 * log2(e): exp(-z^2/2) = exp2(z^2 * kHalfLog2e)
-    const float kHalfLog2e = -0.72134752044448170f;
+    const int len = v.len;
+    double c = v.S(ja) + delta;
+    int lo = lower_idx(v, 0, len, c - W);
+    int hi = RECT ? upper_idx(v, lo, len, c + W) : lower_idx(v, lo, len, c + W);
+    // exp(-d^2/2h^2) = exp2(d^2 * k2), k2 = -log2(e) / (2 h^2)
+    const float k2 = (float)(-0.72134752044448170 * inv_h * inv_h);
+    double s_next = v.S(ja);
     for (int j = ja; j < jb; ++j) {
-        c = Sl[j] + delta;
+        c = s_next + delta;
+        if (j + 1 < jb) s_next = v.S(j + 1);  // next centre's load overlaps this one
         const double lk = c - W;
         const double hk = c + W;
-        while (lo < len && Tl[lo] < lk) ++lo;
+        lo = advance<false>(v, lo, lk);
         if (RECT) {
-            while (hi < len && Tl[hi] <= hk) ++hi;
+            hi = advance<true>(v, hi, hk);
             acc.n += hi - lo;
-            if (NUMER) acc.C += VOl[j] * (A1[hi] - A1[lo]);
-            if (WTD) acc.B += WOl[j] * (A2[hi] - A2[lo]);
+            if (NUMER) acc.C += v.VO(j) * (v.A1(hi) - v.A1(lo));
+            if (WTD) acc.B += v.WO(j) * (v.A2(hi) - v.A2(lo));
         } else {
-            while (hi < len && Tl[hi] < hk) ++hi;
+            hi = advance<false>(v, hi, hk);
             double bj = 0.0, Cj = 0.0, Bj = 0.0;
-            for (int i = lo; i < hi; ++i) {
-                const double z = (Tl[i] - c) * inv_h;
-                double e;
-                if (E64) {
-                    e = exp(-0.5 * z * z);
-                } else {
-                    const float zf = (float)z;
-                    e = (double)__builtin_amdgcn_exp2f(zf * zf * kHalfLog2e);
+            float bf = 0.0f;
+            for (int i = lo; i < hi; i += 4) {
+                double dd[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) dd[m] = v.T(i + m) - c;  // FP64 difference
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    if (i + m < hi) {
+                        if (E64) {
+                            const double z = dd[m] * inv_h;
+                            const double e = exp(-0.5 * z * z);
+                            bj += e;
+                            if (NUMER) Cj += e * v.A1(i + m);
+                            if (WTD) Bj += e * v.A2(i + m);
+                        } else {
+                            const float df = (float)dd[m];
+                            const float e = __builtin_amdgcn_exp2f(df * df * k2);
+                            bf += e;
+                            if (NUMER) Cj += (double)e * v.A1(i + m);
+                            if (WTD) Bj += (double)e * v.A2(i + m);
+                        }
+                    }
                 }
-                bj += e;
-                if (NUMER) Cj += e * A1[i];
-                if (WTD) Bj += e * A2[i];
             }
-            acc.b += bj;
+            acc.b += E64 ? bj : (double)bf;
             acc.n += hi - lo;
-            if (NUMER) acc.C += Cj * VOl[j];
-            if (WTD) acc.B += Bj * WOl[j];
+            if (NUMER) acc.C += Cj * v.VO(j);
+            if (WTD) acc.B += Bj * v.WO(j);
         }
     }
 }
@@ -146,17 +203,19 @@ k_window(const WinTask* __restrict__ tasks, const int64_t* __restrict__ item0, i
     // Gaussian -> values / weights
     constexpr bool HAS_A1 = NUMER;
     constexpr bool HAS_A2 = WTD;
-    extern __shared__ double lds[];
     __shared__ int64_t sh_rng[4];
 
-    const int64_t item = xcd_remap(blockIdx.x, nblocks);
+    // work items are dispatched in order: the hardware spreads consecutive
+    // workgroups over the XCDs, which balances tiles of uneven cost
+    const int64_t item = blockIdx.x;
+    (void)nblocks;
     if (item >= nitems) return;
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int lane = tid & 63;
 
     // task of this item: last ti with item0[ti] <= item
-    const int ti = (int)wave_search<int64_t>(item0, ntasks, item, true) - 1;
+    const int ti = ntasks == 1 ? 0 : (int)wave_search<int64_t>(item0, ntasks, item, true) - 1;
     const WinTask& T = tasks[ti];
     const int64_t local = item - T.item0;
     const int jt = (int)(local / T.n_kt);
@@ -186,28 +245,28 @@ k_window(const WinTask* __restrict__ tasks, const int64_t* __restrict__ item0, i
     const int nj = (int)(j1 - j0);
     const bool fits = (thi - tlo) <= cap && nj <= jmax;
 
-    // LDS carve-up
-    double* Ts = lds;
-    double* A1s = Ts + cap;
-    double* A2s = A1s + (HAS_A1 ? cap + 1 : 0);
-    double* Ss = A2s + (HAS_A2 ? cap + 1 : 0);
-    double* VOs = Ss + jmax;
-    double* WOs = VOs + (NUMER ? jmax : 0);
-    double* Red = lds;  // reused after the scan
+    // LDS carve-up (offsets in doubles)
+    const int o_t = 0;
+    const int o_a1 = o_t + cap + 8;
+    const int o_a2 = o_a1 + (HAS_A1 ? cap + 8 : 0);
+    const int o_s = o_a2 + (HAS_A2 ? cap + 8 : 0);
+    const int o_vo = o_s + jmax;
+    const int o_wo = o_vo + (NUMER ? jmax : 0);
 
     const double* A1g = RECT ? T.pv : T.v;
     const double* A2g = RECT ? T.pw : T.w;
     const int a_len = RECT ? len + 1 : len;  // prefix arrays need the entry at hi
     if (fits) {
-        for (int i = tid; i < len; i += kThreads) Ts[i] = T.t[tlo + i];
+        for (int i = tid; i < len + 8; i += kThreads)
+            g_win_lds[o_t + i] = i < len ? T.t[tlo + i] : kInf;
         if (HAS_A1)
-            for (int i = tid; i < a_len; i += kThreads) A1s[i] = A1g[tlo + i];
+            for (int i = tid; i < a_len; i += kThreads) g_win_lds[o_a1 + i] = A1g[tlo + i];
         if (HAS_A2)
-            for (int i = tid; i < a_len; i += kThreads) A2s[i] = A2g[tlo + i];
+            for (int i = tid; i < a_len; i += kThreads) g_win_lds[o_a2 + i] = A2g[tlo + i];
         for (int i = tid; i < nj; i += kThreads) {
-            Ss[i] = T.s[j0 + i];
-            if (NUMER) VOs[i] = T.vo[j0 + i];
-            if (WTD) WOs[i] = T.wo[j0 + i];
+            g_win_lds[o_s + i] = T.s[j0 + i];
+            if (NUMER) g_win_lds[o_vo + i] = T.vo[j0 + i];
+            if (WTD) g_win_lds[o_wo + i] = T.wo[j0 + i];
         }
     }
     __syncthreads();
@@ -228,15 +287,22 @@ k_window(const WinTask* __restrict__ tasks, const int64_t* __restrict__ item0, i
 
     Acc acc = {0.0, 0.0, 0.0, 0};
     if (active) {
-        if (fits)
-            scan_lane<F>(acc, Ts, A1s, A2s, len, Ss, VOs, WOs, ja, jb, delta, W, inv_h);
-        else
-            scan_lane<F>(acc, T.t + tlo, HAS_A1 ? A1g + tlo : nullptr,
-                         HAS_A2 ? A2g + tlo : nullptr, len, T.s + j0,
-                         NUMER ? T.vo + j0 : nullptr, WTD ? T.wo + j0 : nullptr, ja, jb, delta,
-                         W, inv_h);
+        if (fits) {
+            LdsView v{o_t, o_a1, o_a2, o_s, o_vo, o_wo, len};
+            scan_lane<F>(acc, v, ja, jb, delta, W, inv_h);
+        } else {
+            GlbView v{(gdp)(T.t + tlo),
+                      HAS_A1 ? (gdp)(A1g + tlo) : nullptr,
+                      HAS_A2 ? (gdp)(A2g + tlo) : nullptr,
+                      (gdp)(T.s + j0),
+                      NUMER ? (gdp)(T.vo + j0) : nullptr,
+                      WTD ? (gdp)(T.wo + j0) : nullptr,
+                      len};
+            scan_lane<F>(acc, v, ja, jb, delta, W, inv_h);
+        }
     }
     __syncthreads();  // staging area is reused for the reduction
+    double* Red = g_win_lds;
     Red[4 * tid + 0] = acc.C;
     Red[4 * tid + 1] = acc.B;
     Red[4 * tid + 2] = acc.b;
@@ -261,7 +327,58 @@ k_window(const WinTask* __restrict__ tasks, const int64_t* __restrict__ item0, i
     }
 }
 
-// Sum partials over j-tiles in order; scale the Gaussian weights by
+// Level 1: sum the partials of up to kJc consecutive j-tiles for 64 lags
+// (one lane per lag, four waves over interleaved j-tiles, combined in a fixed
+// order) into part2[chunk][k].
+constexpr int kJc = 64;
+
+__global__ void __launch_bounds__(kThreads)
+k_window_reduce1(const WinTask* __restrict__ tasks, const int64_t* __restrict__ r0s, int ntasks,
+                 int64_t nitems) {
+    __shared__ double red[4][64][4];
+    const int64_t item = blockIdx.x;
+    if (item >= nitems) return;
+    const int ti = (int)wave_search<int64_t>(r0s, ntasks, item, true) - 1;
+    const WinTask& T = tasks[ti];
+    const int64_t local = item - r0s[ti];
+    const int n_jc = (T.n_jt + kJc - 1) / kJc;
+    const int kt = (int)(local / n_jc);
+    const int jc = (int)(local % n_jc);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int k = kt * 64 + lane;
+    double C = 0.0, B = 0.0, b = 0.0;
+    long long n = 0;
+    if (k < T.K) {
+        const int jt_end = min(T.n_jt, (jc + 1) * kJc);
+        for (int jt = jc * kJc + wave; jt < jt_end; jt += 4) {
+            const double* p = T.part + ((int64_t)jt * T.K + k) * 4;
+            C += p[0];
+            B += p[1];
+            b += p[2];
+            n += __double_as_longlong(p[3]);
+        }
+    }
+    red[wave][lane][0] = C;
+    red[wave][lane][1] = B;
+    red[wave][lane][2] = b;
+    red[wave][lane][3] = __longlong_as_double(n);
+    __syncthreads();
+    if (wave == 0 && k < T.K) {
+        for (int w = 1; w < 4; ++w) {
+            C += red[w][lane][0];
+            B += red[w][lane][1];
+            b += red[w][lane][2];
+            n += __double_as_longlong(red[w][lane][3]);
+        }
+        double* o = T.part2 + ((int64_t)jc * T.K + k) * 4;
+        o[0] = C;
+        o[1] = B;
+        o[2] = b;
+        o[3] = __longlong_as_double(n);
+    }
+}
+
+// Level 2: sum the chunk partials in order; scale the Gaussian weights by
 // 1/(sqrt(2 pi) h) (eq. Gaussian_kernel).
 __global__ void k_window_reduce(const WinTask* __restrict__ tasks, int ntasks,
                                 const int64_t* __restrict__ k0s, int64_t total_k,
@@ -279,10 +396,11 @@ __global__ void k_window_reduce(const WinTask* __restrict__ tasks, int ntasks,
     }
     const WinTask& T = tasks[lo];
     const int k = (int)(g - k0s[lo]);
+    const int n_jc = (T.n_jt + kJc - 1) / kJc;
     double C = 0.0, B = 0.0, b = 0.0;
     long long n = 0;
-    for (int jt = 0; jt < T.n_jt; ++jt) {
-        const double* p = T.part + ((int64_t)jt * T.K + k) * 4;
+    for (int jc = 0; jc < n_jc; ++jc) {
+        const double* p = T.part2 + ((int64_t)jc * T.K + k) * 4;
         C += p[0];
         B += p[1];
         b += p[2];
@@ -309,8 +427,8 @@ int launch_window_t(const WinTask* d_tasks, const int64_t* d_item0, int ntasks, 
     constexpr bool RECT = (F & WIN_RECT) != 0;
     constexpr bool NUMER = (F & WIN_NUMER) != 0;
     constexpr bool WTD = (F & WIN_WEIGHTED) != 0;
-    size_t stage = (size_t)cap + (NUMER ? cap + 1 : 0) + (WTD ? cap + 1 : 0) + jmax +
-                   (NUMER ? jmax : 0) + (WTD ? jmax : 0);
+    size_t stage = (size_t)(cap + 8) * (1 + (NUMER ? 1 : 0) + (WTD ? 1 : 0)) +
+                   (size_t)jmax * (1 + (NUMER ? 1 : 0) + (WTD ? 1 : 0));
     size_t red = 4 * kThreads;
     size_t bytes = (stage > red ? stage : red) * sizeof(double);
     (void)RECT;
@@ -351,9 +469,14 @@ int launch_window(const WinTask* d_tasks, const int64_t* d_item0, int ntasks, in
 }
 
 int launch_window_reduce(const WinTask* d_tasks, int ntasks, int64_t total_k, const int64_t* d_k0,
-                         uint32_t flags, hipStream_t st) {
+                         const int64_t* d_r0, int64_t nred1, uint32_t flags, hipStream_t st) {
     if (total_k <= 0) return NCF_OK;
     ProfScope p(st, "window_reduce", 0.0, "bytes");
+    if (nred1 > 0) {
+        hipLaunchKernelGGL(k_window_reduce1, dim3((unsigned)nred1), dim3(kThreads), 0, st,
+                           d_tasks, d_r0, ntasks, nred1);
+        NCF_CHECK_LAUNCH();
+    }
     hipLaunchKernelGGL(k_window_reduce, dim3((unsigned)ceil_div(total_k, 128)), dim3(128), 0, st,
                        d_tasks, ntasks, d_k0, total_k, flags);
     NCF_CHECK_LAUNCH();
