@@ -12,9 +12,12 @@
 //
 // A workgroup transforms one tile of 4096 elements: R_i rows by
 // C_i = 4096 / R_i adjacent columns (C_i * element size contiguous bytes per
-// row in HBM), held in LDS; each column's DFT is a Stockham autosort
-// sequence of radix-4 (and one radix-2) stages. Twiddles come from tables
-// computed in FP64 on the host and rounded once to the working precision.
+// row in HBM). Each column's DFT is a Stockham autosort sequence of radix-16
+// stages (and one radix-8/4/2 stage for the remainder) with 16 elements per
+// thread in registers: the first stage reads HBM directly, the last writes
+// HBM directly, and the stages in between exchange through padded LDS.
+// Twiddles come from tables computed in FP64 on the host and rounded once to
+// the working precision.
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -101,138 +104,276 @@ struct PassArgs {
     const void* wsmall;  // w_4096^e
 };
 
+// Global-memory element access through address-space-1 scalar pointers
+// (global loads and stores rather than flat ones).
+template <typename C2>
+__device__ __forceinline__ C2 gld(const void* base, int64_t idx) {
+    typedef decltype(C2{}.x) R;
+    typedef __attribute__((address_space(1))) const R* P;
+    P p = (P)base;
+    C2 v;
+    v.x = p[2 * idx];
+    v.y = p[2 * idx + 1];
+    return v;
+}
+
+template <typename C2>
+__device__ __forceinline__ void gst(void* base, int64_t idx, C2 v) {
+    typedef decltype(C2{}.x) R;
+    typedef __attribute__((address_space(1))) R* P;
+    P p = (P)base;
+    p[2 * idx] = v.x;
+    p[2 * idx + 1] = v.y;
+}
+
 template <typename C2>
 __device__ __forceinline__ C2 tw_big(const PassArgs& a, int64_t e) {
     // w_N^e for 0 <= e < N, with the sign of the pass
-    const C2* lo = reinterpret_cast<const C2*>(a.wlo);
-    const C2* hi = reinterpret_cast<const C2*>(a.whi);
-    C2 w = cmul(hi[e >> a.lobits], lo[e & ((1LL << a.lobits) - 1)]);
+    C2 w = cmul(gld<C2>(a.whi, e >> a.lobits), gld<C2>(a.wlo, e & ((1LL << a.lobits) - 1)));
     return a.sign > 0 ? w : cconj(w);
 }
 
 template <typename C2>
 __device__ __forceinline__ C2 tw_small(const PassArgs& a, int e) {
-    const C2* sm = reinterpret_cast<const C2*>(a.wsmall);
-    C2 w = sm[e & (kTileElems - 1)];
+    C2 w = gld<C2>(a.wsmall, e & (kTileElems - 1));
     return a.sign > 0 ? w : cconj(w);
 }
 
-template <typename Real>
+// ------------------------------------------------ small DFTs in registers
+// X[k] = sum_n x[n] w_r^(n k), w_r = exp(sign 2 pi i / r), in place.
+
+template <typename C2>
+__device__ __forceinline__ void dft2(C2& a0, C2& a1) {
+    const C2 t = a0;
+    a0 = cadd(t, a1);
+    a1 = csub(t, a1);
+}
+
+template <typename C2>
+__device__ __forceinline__ void dft4(C2& a0, C2& a1, C2& a2, C2& a3, int sign) {
+    const C2 t0 = cadd(a0, a2);
+    const C2 t1 = csub(a0, a2);
+    const C2 t2 = cadd(a1, a3);
+    const C2 t3 = cmul_si(csub(a1, a3), sign);
+    a0 = cadd(t0, t2);
+    a1 = cadd(t1, t3);
+    a2 = csub(t0, t2);
+    a3 = csub(t1, t3);
+}
+
+// multiply by w_16^m (m in 0..15) for the given sign; constants fold
+template <typename C2>
+__device__ __forceinline__ C2 mul_w16(C2 a, int m, int sign) {
+    typedef decltype(a.x) R;
+    const R c1 = (R)0.92387953251128674, s1 = (R)0.38268343236508978;  // pi/8
+    const R c2 = (R)0.70710678118654752;                                // pi/4
+    R wr, wi;
+    switch (m & 15) {
+        case 0: return a;
+        case 1: wr = c1; wi = s1; break;
+        case 2: wr = c2; wi = c2; break;
+        case 3: wr = s1; wi = c1; break;
+        case 4: wr = 0; wi = 1; break;
+        case 5: wr = -s1; wi = c1; break;
+        case 6: wr = -c2; wi = c2; break;
+        case 7: wr = -c1; wi = s1; break;
+        case 8: wr = -1; wi = 0; break;
+        case 9: wr = -c1; wi = -s1; break;
+        default: wr = -c2; wi = -c2; break;  // 10 (larger m do not occur)
+    }
+    if (sign < 0) wi = -wi;
+    C2 w;
+    w.x = wr;
+    w.y = wi;
+    return cmul(a, w);
+}
+
+// DFT of size 8: n = 4 n1 + n2, k = k1 + 2 k2
+template <typename C2>
+__device__ __forceinline__ void dft8(C2* a, int sign) {
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) dft2(a[n2], a[4 + n2]);
+    // twiddle w_8^(n2 k1) = w_16^(2 n2 k1); k1 = 1 lives at a[4 + n2]
+#pragma unroll
+    for (int n2 = 1; n2 < 4; ++n2) a[4 + n2] = mul_w16(a[4 + n2], 2 * n2, sign);
+    dft4(a[0], a[1], a[2], a[3], sign);  // k1 = 0 -> X[2 k2]
+    dft4(a[4], a[5], a[6], a[7], sign);  // k1 = 1 -> X[1 + 2 k2]
+    C2 o[8];
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) {
+        o[2 * k2] = a[k2];
+        o[2 * k2 + 1] = a[4 + k2];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) a[i] = o[i];
+}
+
+// DFT of size 16: n = 4 n1 + n2, k = k1 + 4 k2
+template <typename C2>
+__device__ __forceinline__ void dft16(C2* a, int sign) {
+    // inner DFT4 over n1 for each n2: inputs a[4 n1 + n2]
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) dft4(a[n2], a[4 + n2], a[8 + n2], a[12 + n2], sign);
+    // now a[4 k1 + n2] holds y[n2][k1]; twiddle w_16^(n2 k1)
+#pragma unroll
+    for (int k1 = 1; k1 < 4; ++k1)
+#pragma unroll
+        for (int n2 = 1; n2 < 4; ++n2) a[4 * k1 + n2] = mul_w16(a[4 * k1 + n2], n2 * k1, sign);
+    // outer DFT4 over n2 for each k1: X[k1 + 4 k2]
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) dft4(a[4 * k1], a[4 * k1 + 1], a[4 * k1 + 2], a[4 * k1 + 3], sign);
+    // a[4 k1 + k2] = X[k1 + 4 k2]
+    C2 o[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) o[k1 + 4 * k2] = a[4 * k1 + k2];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) a[i] = o[i];
+}
+
+template <int RADIX, typename C2>
+__device__ __forceinline__ void dft_r(C2* a, int sign) {
+    if constexpr (RADIX == 16) {
+        dft16(a, sign);
+    } else if constexpr (RADIX == 8) {
+        dft8(a, sign);
+    } else if constexpr (RADIX == 4) {
+        dft4(a[0], a[1], a[2], a[3], sign);
+    } else {
+        dft2(a[0], a[1]);
+    }
+}
+
+__device__ __forceinline__ int lds_pad(int e) { return e + (e >> 4); }
+
+// One Stockham stage of radix RADIX over the tile's C columns of length R.
+// Each thread owns 16 / RADIX butterflies (16 elements). Inputs come from
+// `src` (global or LDS view), outputs go to `dst`.
+template <int RADIX, bool FROM_GLOBAL, bool TO_GLOBAL, int LGR, int NS, typename C2>
+__device__ __forceinline__ void stockham_stage(const PassArgs& a, C2* lds, C2* gbase,
+                                               int64_t s0) {
+    constexpr int NB = 16 / RADIX;  // butterflies per thread
+    constexpr int lgC = 12 - LGR;
+    constexpr int R = 1 << LGR;
+    constexpr int C = 1 << lgC;
+    constexpr int Rr = R / RADIX;
+    constexpr int Ns = NS;
+    const int tid = threadIdx.x;
+    C2 v[16];
+    int jj[NB], cc[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        const int beta = tid + u * kThreads;
+        const int c = beta & (C - 1);
+        const int j = beta >> lgC;
+        jj[u] = j;
+        cc[u] = c;
+#pragma unroll
+        for (int i = 0; i < RADIX; ++i) {
+            const int row = j + i * Rr;
+            C2 x;
+            if (FROM_GLOBAL) {
+                x = gld<C2>(gbase, (int64_t)row * a.S + c);
+                if (a.sign < 0) {
+                    // adjoint of the forward pass twiddle, applied before the DFT
+                    const int64_t ex = (s0 + c) * (int64_t)row * (a.N / a.B);
+                    if (ex) x = cmul(x, tw_big<C2>(a, ex));
+                }
+            } else {
+                x = lds[lds_pad(row * C + c)];
+            }
+            v[u * RADIX + i] = x;
+        }
+        // stage twiddles w_{Ns r}^(i k), k = j mod Ns, from the w_4096 table
+        const int k = j & (Ns - 1);
+        if (Ns > 1 && k) {
+            const int step = kTileElems / (Ns * RADIX);
+#pragma unroll
+            for (int i = 1; i < RADIX; ++i)
+                v[u * RADIX + i] = cmul(v[u * RADIX + i], tw_small<C2>(a, i * k * step));
+        }
+        dft_r<RADIX>(v + u * RADIX, a.sign);
+    }
+    // all reads of this stage are done before any write (the tile is
+    // transformed in place, in LDS or in HBM)
+    if (!FROM_GLOBAL || TO_GLOBAL) __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        const int j = jj[u], c = cc[u];
+        const int k = j & (Ns - 1);
+        const int obase = (j / Ns) * Ns * RADIX + k;
+#pragma unroll
+        for (int i = 0; i < RADIX; ++i) {
+            const int row = obase + i * Ns;
+            C2 x = v[u * RADIX + i];
+            if (TO_GLOBAL) {
+                if (a.sign > 0) {
+                    const int64_t ex = (s0 + c) * (int64_t)row * (a.N / a.B);
+                    if (ex) x = cmul(x, tw_big<C2>(a, ex));
+                }
+                gst<C2>(gbase, (int64_t)row * a.S + c, x);
+            } else {
+                lds[lds_pad(row * C + c)] = x;
+            }
+        }
+    }
+    if (!TO_GLOBAL) __syncthreads();  // outputs visible to the next stage
+}
+
+// Radix schedule of a column of length R = 2^LGR: radix-16 stages first, then
+// one stage of 8, 4 or 2 for the remainder; fixed at compile time.
+template <int LGR, int ST, int NS, typename C2>
+__device__ __forceinline__ void run_stages(const PassArgs& a, C2* lds, C2* gbase,
+                                           int64_t s0) {
+    constexpr int n16 = LGR / 4;
+    constexpr int rem = LGR % 4;
+    constexpr int nst = n16 + (rem ? 1 : 0);
+    if constexpr (ST < nst) {
+        constexpr int RX = ST < n16 ? 16 : (1 << rem);
+        stockham_stage<RX, ST == 0, ST == nst - 1, LGR, NS>(a, lds, gbase, s0);
+        run_stages<LGR, ST + 1, NS * RX>(a, lds, gbase, s0);
+    }
+}
+
+template <typename Real, int LGR>
 __global__ void __launch_bounds__(kThreads)
 k_fft_pass(PassArgs a) {
     using C2 = typename C2T<Real>::T;
-    __shared__ C2 buf[kTileElems];
-    const int64_t wg = xcd_remap(blockIdx.x, a.nblocks);
+    constexpr int lgC = 12 - LGR;
+    __shared__ C2 buf[kTileElems + kTileElems / 16];
+    const int64_t wg = blockIdx.x;
     if (wg >= a.ntiles) return;
-    const int tid = threadIdx.x;
     const int64_t gidx = wg / a.tiles_per_grid;
     const int64_t tile = wg % a.tiles_per_grid;
     C2* data = a.grids ? reinterpret_cast<C2*>(const_cast<void*>(a.grids[gidx]))
                        : reinterpret_cast<C2*>(a.data) + gidx * a.grid_stride;
-    const int R = 1 << a.lgR;
-    const int C = 1 << a.lgC;
     // tile -> (block, first column)
-    const int64_t chunks_per_block = a.S >> a.lgC;  // S / C
+    const int64_t chunks_per_block = a.S >> lgC;  // S / C
     const int64_t blk = tile / chunks_per_block;
-    const int64_t s0 = (tile % chunks_per_block) << a.lgC;
+    const int64_t s0 = (tile % chunks_per_block) << lgC;
     C2* base = data + blk * a.B + s0;
+    run_stages<LGR, 0, 1>(a, buf, base, s0);
+}
 
-    // load: element (r, c) at base + r*S + c  ->  buf[c*R + r]
-    for (int e = tid; e < kTileElems; e += kThreads) {
-        const int r = e >> a.lgC;
-        const int c = e & (C - 1);
-        C2 v = base[(int64_t)r * a.S + c];
-        if (a.sign < 0) {
-            // DIT: input index r is the frequency digit k of the forward pass
-            const int64_t ex = (s0 + c) * (int64_t)r * (a.N / a.B);
-            if (ex) v = cmul(v, tw_big<C2>(a, ex));
-        }
-        buf[c * R + r] = v;
-    }
-    __syncthreads();
+template <typename Real>
+using PassKernel = void (*)(PassArgs);
 
-    // Stockham stages on each column (length R): radix-2 first if lgR is odd
-    int Ns = 1;
-    if (a.lgR & 1) {
-        // radix-2: C*R/2 = 2048 butterflies, 8 per thread
-        C2 va[8][2];
-        int dst[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int beta = tid + u * kThreads;
-            const int c = beta >> (a.lgR - 1);
-            const int j = beta & ((R >> 1) - 1);
-            C2* col = buf + c * R;
-            C2 x0 = col[j];
-            C2 x1 = col[j + (R >> 1)];
-            // Ns = 1: no twiddle
-            va[u][0] = cadd(x0, x1);
-            va[u][1] = csub(x0, x1);
-            dst[u] = c * R + j * 2;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            buf[dst[u]] = va[u][0];
-            buf[dst[u] + 1] = va[u][1];
-        }
-        __syncthreads();
-        Ns = 2;
-    }
-    const int lgR4 = a.lgR - 2;  // log2(R/4)
-    for (; Ns < R; Ns <<= 2) {
-        C2 va[4][4];
-        int dst[4];
-        // twiddle step in units of w_4096: w_{4 Ns}^1 = w_4096^(4096 / (4 Ns))
-        const int step = kTileElems / (4 * Ns);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int beta = tid + u * kThreads;
-            const int c = beta >> lgR4;
-            const int j = beta & ((R >> 2) - 1);
-            C2* col = buf + c * R;
-            const int k = j & (Ns - 1);
-            const int q = R >> 2;
-            C2 x0 = col[j];
-            C2 x1 = col[j + q];
-            C2 x2 = col[j + 2 * q];
-            C2 x3 = col[j + 3 * q];
-            if (k) {
-                x1 = cmul(x1, tw_small<C2>(a, k * step));
-                x2 = cmul(x2, tw_small<C2>(a, 2 * k * step));
-                x3 = cmul(x3, tw_small<C2>(a, 3 * k * step));
-            }
-            const C2 t0 = cadd(x0, x2);
-            const C2 t1 = csub(x0, x2);
-            const C2 t2 = cadd(x1, x3);
-            const C2 t3 = cmul_si(csub(x1, x3), a.sign);
-            va[u][0] = cadd(t0, t2);
-            va[u][1] = cadd(t1, t3);
-            va[u][2] = csub(t0, t2);
-            va[u][3] = csub(t1, t3);
-            dst[u] = c * R + (j / Ns) * Ns * 4 + k;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            buf[dst[u]] = va[u][0];
-            buf[dst[u] + Ns] = va[u][1];
-            buf[dst[u] + 2 * Ns] = va[u][2];
-            buf[dst[u] + 3 * Ns] = va[u][3];
-        }
-        __syncthreads();
-    }
-
-    // store: buf[c*R + k] -> base + k*S + c (DIF: twiddle w_B^(s k) first)
-    for (int e = tid; e < kTileElems; e += kThreads) {
-        const int k = e >> a.lgC;
-        const int c = e & (C - 1);
-        C2 v = buf[c * R + k];
-        if (a.sign > 0) {
-            const int64_t ex = (s0 + c) * (int64_t)k * (a.N / a.B);
-            if (ex) v = cmul(v, tw_big<C2>(a, ex));
-        }
-        base[(int64_t)k * a.S + c] = v;
+template <typename Real>
+PassKernel<Real> pass_kernel(int lgR) {
+    switch (lgR) {
+        case 1: return k_fft_pass<Real, 1>;
+        case 2: return k_fft_pass<Real, 2>;
+        case 3: return k_fft_pass<Real, 3>;
+        case 4: return k_fft_pass<Real, 4>;
+        case 5: return k_fft_pass<Real, 5>;
+        case 6: return k_fft_pass<Real, 6>;
+        case 7: return k_fft_pass<Real, 7>;
+        case 8: return k_fft_pass<Real, 8>;
+        case 9: return k_fft_pass<Real, 9>;
+        case 10: return k_fft_pass<Real, 10>;
+        case 11: return k_fft_pass<Real, 11>;
+        default: return k_fft_pass<Real, 12>;
     }
 }
 
@@ -383,11 +524,11 @@ int fft_exec(const FftPlan& plan, void* const* d_grids, int count, int sign, boo
         a.B = a.S * plan.radix[i];
         ProfScope p(st, fp64 ? "fft_pass_f64" : "fft_pass_f32", bytes, "bytes");
         if (fp64)
-            hipLaunchKernelGGL(k_fft_pass<double>, dim3((unsigned)a.nblocks), dim3(kThreads), 0,
-                               st, a);
+            hipLaunchKernelGGL(pass_kernel<double>(a.lgR), dim3((unsigned)a.nblocks),
+                               dim3(kThreads), 0, st, a);
         else
-            hipLaunchKernelGGL(k_fft_pass<float>, dim3((unsigned)a.nblocks), dim3(kThreads), 0,
-                               st, a);
+            hipLaunchKernelGGL(pass_kernel<float>(a.lgR), dim3((unsigned)a.nblocks),
+                               dim3(kThreads), 0, st, a);
         NCF_CHECK_LAUNCH();
     }
     return NCF_OK;
