@@ -96,18 +96,34 @@ def run_one(d, precision="mixed", method="auto"):
                          d["kernel"], d["h"], **kw)
 
 
+def lag_subset(d, max_windows=2.5e9):
+    """Indices of an evenly spaced subset of the lags that bounds the oracle's
+    work on a single large problem to about ``max_windows`` (j, k) windows."""
+    n_out = d["s"].size if d["kind"] == "ccf" else d["t"].size
+    K = d["lags"].size
+    keep = int(min(K, max(8, max_windows // max(n_out, 1))))
+    return np.unique(np.linspace(0, K - 1, keep).round().astype(int))
+
+
 def oracle_subset(d, max_series):
-    """The oracle on the whole workload (single problems) or on its first
-    ``max_series`` series (batches). Returns (c list, count list, lag-pairs, seconds)."""
+    """The oracle on the whole workload (single problems; an evenly spaced
+    subset of lags when the whole would take minutes) or on its first
+    ``max_series`` series (batches). Returns (c list, count list, lag-pairs,
+    seconds, lag indices)."""
     from oracle import oracle as O
     t0 = time.perf_counter()
     cs, ns, work = [], [], 0
+    pick = None
     if d["kind"] == "acf":
-        st, c, b, n = O.acf(d["t"], d["x"], d["lags"], d["kernel"], d["h"], err=d.get("err"))
-        cs, ns, work = [c], [n], lag_pairs(d)
+        pick = lag_subset(d)
+        st, c, b, n = O.acf(d["t"], d["x"], d["lags"][pick], d["kernel"], d["h"],
+                            err=d.get("err"))
+        cs, ns, work = [c], [n], d["t"].size * pick.size
     elif d["kind"] == "ccf":
-        st, c, b, n = O.ccf(d["t"], d["x"], d["s"], d["y"], d["lags"], d["kernel"], d["h"])
-        cs, ns, work = [c], [n], lag_pairs(d)
+        pick = lag_subset(d)
+        st, c, b, n = O.ccf(d["t"], d["x"], d["s"], d["y"], d["lags"][pick], d["kernel"],
+                            d["h"])
+        cs, ns, work = [c], [n], (d["t"].size + d["s"].size) * pick.size
     elif d["kind"] == "acf_batch":
         o = d["offs"]
         for i in range(min(max_series, o.size - 1)):
@@ -126,18 +142,28 @@ def oracle_subset(d, max_series):
             cs.append(c)
             ns.append(n)
             work += (ox[i + 1] - ox[i] + oy[i + 1] - oy[i]) * d["lags"].size
-    return cs, ns, work, time.perf_counter() - t0
+    return cs, ns, work, time.perf_counter() - t0, pick
 
 
-def max_dc(gpu_c, orc_cs):
-    g = np.asarray(gpu_c.cpu() if hasattr(gpu_c, "cpu") else gpu_c)
-    g = g.reshape(len(orc_cs), -1) if g.ndim == 1 and len(orc_cs) > 1 else g.reshape(
-        -1, orc_cs[0].size)
+def _host(a):
+    return np.asarray(a.cpu() if hasattr(a, "cpu") else a)
+
+
+def max_dc(gpu_c, orc_cs, pick=None):
+    g = _host(gpu_c)
+    K = g.shape[-1] if g.ndim > 1 else g.size // max(len(orc_cs), 1)
+    g = g.reshape(-1, K)
+    if pick is not None:
+        g = g[:, pick]
     return float(max(np.max(np.abs(g[i] - orc_cs[i])) for i in range(len(orc_cs))))
 
 
-def counts_equal(gpu_n, orc_ns):
-    g = np.asarray(gpu_n.cpu() if hasattr(gpu_n, "cpu") else gpu_n).reshape(-1, orc_ns[0].size)
+def counts_equal(gpu_n, orc_ns, pick=None):
+    g = _host(gpu_n)
+    K = g.shape[-1] if g.ndim > 1 else g.size // max(len(orc_ns), 1)
+    g = g.reshape(-1, K)
+    if pick is not None:
+        g = g[:, pick]
     return bool(all(np.array_equal(g[i], orc_ns[i]) for i in range(len(orc_ns))))
 
 
@@ -230,20 +256,25 @@ def main():
         cores = O.max_threads()
         log(f"[bench] oracle on {cores} threads")
         orc_work, orc_time = 0, 0.0
-        for d, r in zip(host, res):
-            cs, ns, w, sec = oracle_subset(d, args.oracle_series)
+        picks = []
+        for i, (d, r) in enumerate(zip(host, res)):
+            cs, ns, w, sec, pick = oracle_subset(d, args.oracle_series)
+            picks.append(pick)
             orc_work += w
             orc_time += sec
             key = f"{d['name']}_{d['kernel']}"
-            acc[key] = {"max_abs_dc_mixed": max_dc(r[0], cs)}
+            acc[key] = {"max_abs_dc_mixed": max_dc(r[0], cs, pick)}
             if d["kernel"] == "rectangle":
-                acc[key]["counts_bit_exact"] = counts_equal(r[2], ns)
-        if fp64 is not None:
-            for d, r in zip(host, res64):
-                cs, ns, w, sec = oracle_subset(d, args.oracle_series)
-                acc[f"{d['name']}_{d['kernel']}"]["max_abs_dc_fp64_direct"] = max_dc(r[0], cs)
-        sample = ("whole workload" if host[0]["kind"] in ("acf", "ccf")
-                  else f"first {args.oracle_series} series of the batch")
+                acc[key]["counts_bit_exact"] = counts_equal(r[2], ns, pick)
+            if fp64 is not None:
+                acc[key]["max_abs_dc_fp64_direct"] = max_dc(res64[i][0], cs, pick)
+        d0 = host[0]
+        if d0["kind"] in ("acf", "ccf"):
+            npick = picks[0].size
+            sample = ("whole workload" if npick == d0["lags"].size else
+                      f"all samples, {npick} of {d0['lags'].size} lags (evenly spaced)")
+        else:
+            sample = f"first {args.oracle_series} series of the batch"
         cpu = {"value": orc_work / orc_time, "unit": "lag-pairs/s", "cores": cores,
                "kind": "oracle", "sample": sample, "seconds": orc_time}
 

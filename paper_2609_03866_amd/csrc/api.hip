@@ -110,7 +110,7 @@ struct DevBuf {
     size_t cap = 0;
 };
 std::mutex g_ws_mu;
-std::map<int, DevBuf> g_ws[2];  // [arena][device]
+std::map<int, DevBuf> g_ws[3];  // [arena][device]
 
 int ensure_ws(int which, size_t bytes, void** out) {
     int dev = 0;
@@ -162,7 +162,7 @@ struct Staging {
     char* d = nullptr;
     size_t cap = 0;
 };
-std::map<int, Staging> g_stage[2];
+std::map<int, Staging> g_stage[3];
 
 int ensure_stage(int phase, size_t bytes, Staging** out) {
     int dev = 0;
@@ -320,7 +320,9 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     for (int si = 0; si < nsets; ++si) weighted |= (ein[si] != nullptr);
     const bool numer_in_window = !spectral;  // C from the window scan
     const bool need_v32 = spectral && !fp64;
-    const bool need_v64 = (spectral && fp64) || numer_in_window;
+    // FP64 values: FP64 spreading, and every Gaussian window pass (its direct
+    // numerator backs up the spectral one at lags with few pairs)
+    const bool need_v64 = (spectral && fp64) || numer_in_window || !rect;
     const bool need_prefix = rect && numer_in_window;
 
     // ------------------------------------------------ phase 1: A1 moments
@@ -461,6 +463,11 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     const int64_t K = J.K;
     double maxlag = 0.0;
     for (double v : J.lags) maxlag = std::max(maxlag, std::fabs(v));
+    // Gaussian default: numerator and pair count both by the spectral route
+    // (unit-weight channel); lags whose spectral b is small against the
+    // reference are re-evaluated by the direct window scan.
+    const bool spec_b = spectral && !rect && J.opt.method == NCF_AUTO && !weighted;
+    const double beta = fp64 ? 1e-6 : 1e-2;
     // window lag rows: sorted offsets delta = eps * tau (ACF: plus lag 0)
     const double epsv = J.ccf ? -1.0 : 1.0;
     std::vector<std::pair<double, int>> rows;
@@ -481,130 +488,142 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         if (rows[r].second >= 0) perm[rows[r].second] = r;
         if (rows[r].first == 0.0 && row0 < 0) row0 = r;
     }
-    // largest lag extent of a 64-row tile
-    double lag_ext = 0.0;
-    for (int r0 = 0; r0 < Krow; r0 += 64) {
-        int r1 = std::min(Krow, r0 + 64) - 1;
-        lag_ext = std::max(lag_ext, delta[r1] - delta[r0]);
-    }
 
-    // window flags and LDS budget: staged window samples (+ prefix or value
-    // arrays) and outer samples. `cap` starts at the 40 KiB budget and is
-    // shrunk to what the planned tiles need, for occupancy.
+    // window flags: the rectangle numerator is always the prefix form; the
+    // Gaussian window pass also sums the direct numerator (its weights are
+    // already computed), used where the window b is small
     uint32_t wflags = 0;
     if (rect) wflags |= WIN_RECT;
-    if (numer_in_window) wflags |= WIN_NUMER;
+    if (!rect || numer_in_window) wflags |= WIN_NUMER;
     if (weighted) wflags |= WIN_WEIGHTED;
     if (fp64 && !rect) wflags |= WIN_EXP64;
-    const int jmax = 1024;
-    const int arrays = 1 + (numer_in_window ? 1 : 0) + (weighted ? 1 : 0);
-    const int budget = 40 * 1024 / 8;  // doubles
-    int cap = (budget - jmax * arrays) / arrays - 8;
-    cap = std::max(256, std::min(4096, cap));
+    const bool wnumer = (wflags & WIN_NUMER) != 0;
+
+    // the rectangle prefix arrays exist only when the numerator is in the window
+    if (rect && !numer_in_window) wflags &= ~(uint32_t)WIN_NUMER;
 
     struct WinPlan {
         int wi_set, wo_set;  // window set, outer set (series index = problem)
-        int krows;           // rows: Krow (cross / acf) or 1 (self lag 0)
         int64_t prob;
-        int role;            // 0 main, 1 self x, 2 self y
+        int role;            // 0 main, 1 self x, 2 self y, 3 fallback
+        std::vector<double> dl;  // sorted lag offsets of this task
     };
-    std::vector<WinPlan> wplans;
-    for (int64_t p = 0; p < J.nprob; ++p) {
-        if (pstat[p] != NCF_OK) continue;
-        if (!J.ccf) {
-            wplans.push_back({0, 0, Krow, p, 0});
-        } else {
-            if (Krow > 0) wplans.push_back({0, 1, Krow, p, 0});
-            wplans.push_back({0, 0, 1, p, 1});
-            wplans.push_back({1, 1, 1, p, 2});
-        }
-    }
-    const int ntw = (int)wplans.size();
-    std::vector<WinTask> wt(ntw);
-    std::vector<double> wt_est(ntw, 0.0);
-    std::vector<int64_t> item0(ntw + 1), wk0(ntw + 1), r0(ntw + 1);
-    int64_t nitems = 0, total_rows = 0, nred1 = 0;
-    double win_work = 0.0;
-    for (int i = 0; i < ntw; ++i) {
-        const WinPlan& P = wplans[i];
-        const SeriesSet& SW = J.set[P.wi_set];
-        const SeriesSet& SO = J.set[P.wo_set];
-        const SeriesDesc& dw = sdesc[SW.sd0 + P.prob];
-        const SeriesDesc& dO = sdesc[SO.sd0 + P.prob];
-        const SeriesStat& sw = stat_of(P.wi_set, P.prob);
-        const SeriesStat& so = stat_of(P.wo_set, P.prob);
-        const double h = J.h[P.prob];
-        WinTask T{};
-        T.t = dw.t;
-        T.n_win = dw.n;
-        T.s = dO.t;
-        T.n_out = dO.n;
-        if (numer_in_window) {
-            if (rect)
-                T.pv = dw.pv;
-            else
-                T.v = dw.v64;
-            T.vo = dO.v64;
-        }
-        if (weighted) {
-            if (rect)
-                T.pw = dw.pw;
-            else
-                T.w = dw.w64;
-            T.wo = dO.w64;
-        }
-        T.K = P.krows;
-        T.h = h;
-        T.W = rect ? h : 6.0 * h;
-        // tile size
-        const double span_w = std::max(sw.tmax - sw.tmin, 1e-300);
-        const double span_o = std::max(so.tmax - so.tmin, 1e-300);
-        const double dens_w = (double)(dw.n - 1) / span_w;
-        const double dens_o = (double)(dO.n - 1) / span_o;
-        const int n_kt = (int)ceil_div(T.K, 64);
-        const double lext = (P.krows == 1) ? 0.0 : lag_ext;
-        auto est = [&](int64_t j) {
-            return dens_w * ((double)j / dens_o + lext + 2.0 * T.W) + 2.0;
-        };
-        // outer samples per workgroup: as many as keep the window range in
-        // LDS (half the capacity, for clustering) while leaving at least 2048
-        // work items (eight per CU) when the problem is big enough
-        int64_t Jt = 64;
-        while (Jt * 2 <= jmax && est(Jt * 2) <= 0.5 * cap &&
-               (double)dO.n * n_kt / (double)(Jt * 2) >= 2048.0)
-            Jt *= 2;
-        while (Jt > 16 && est(Jt) > 0.5 * cap) Jt /= 2;
-        T.J = (int32_t)Jt;
-        wt_est[i] = est(Jt);
-        T.n_jt = (int32_t)ceil_div(dO.n, Jt);
-        T.n_kt = n_kt;
-        T.item0 = nitems;
-        item0[i] = nitems;
-        wk0[i] = total_rows;
-        r0[i] = nred1;
-        nitems += (int64_t)T.n_jt * T.n_kt;
-        nred1 += (int64_t)T.n_kt * ceil_div(T.n_jt, kWinJc);
-        total_rows += T.K;
-        // algorithmic work: per (j, k) window, searches + per-point weight ops
-        const double pts = rect ? 0.0 : dens_w * 2.0 * T.W;
-        win_work += (double)dO.n * T.K * (8.0 + (rect ? 4.0 : 8.0 * pts));
-        wt[i] = T;
-    }
-    item0[ntw] = nitems;
-    wk0[ntw] = total_rows;
-    r0[ntw] = nred1;
-    int jmax_used = 64;
-    {
+    // Plan window tasks: tile sizes, LDS size, work items.
+    struct WinLaunch {
+        std::vector<WinPlan> plans;
+        std::vector<WinTask> wt;
+        std::vector<int64_t> item0, wk0, r0;
+        int64_t nitems = 0, total_rows = 0, nred1 = 0;
+        int cap = 256, jmax = 64;
+        double work = 0.0;
+    };
+    auto plan_window = [&](WinLaunch& W) {
+        const int arrays = 1 + ((W.plans.empty() ? false : ((wflags & WIN_NUMER) != 0)) ? 1 : 0) +
+                           (weighted ? 1 : 0);
+        const int jmax = 1024;
+        const int budget = 40 * 1024 / 8;  // doubles
+        int cap = (budget - jmax * arrays) / arrays - 8;
+        cap = std::max(256, std::min(4096, cap));
+        const int ntw = (int)W.plans.size();
+        W.wt.assign(ntw, WinTask{});
+        W.item0.assign(ntw + 1, 0);
+        W.wk0.assign(ntw + 1, 0);
+        W.r0.assign(ntw + 1, 0);
         double need = 0.0;
+        int jneed = 16;
         for (int i = 0; i < ntw; ++i) {
-            need = std::max(need, wt_est[i]);
-            jmax_used = std::max(jmax_used, wt[i].J);
+            const WinPlan& P = W.plans[i];
+            const SeriesSet& SW = J.set[P.wi_set];
+            const SeriesSet& SO = J.set[P.wo_set];
+            const SeriesDesc& dw = sdesc[SW.sd0 + P.prob];
+            const SeriesDesc& dO = sdesc[SO.sd0 + P.prob];
+            const SeriesStat& sw = stat_of(P.wi_set, P.prob);
+            const SeriesStat& so = stat_of(P.wo_set, P.prob);
+            const double h = J.h[P.prob];
+            WinTask T{};
+            T.t = dw.t;
+            T.n_win = dw.n;
+            T.s = dO.t;
+            T.n_out = dO.n;
+            if (wflags & WIN_NUMER) {
+                if (rect)
+                    T.pv = dw.pv;
+                else
+                    T.v = dw.v64;
+                T.vo = dO.v64;
+            }
+            if (weighted) {
+                if (rect)
+                    T.pw = dw.pw;
+                else
+                    T.w = dw.w64;
+                T.wo = dO.w64;
+            }
+            T.K = (int32_t)P.dl.size();
+            T.h = h;
+            T.W = rect ? h : 6.0 * h;
+            double lext = 0.0;
+            for (size_t r = 0; r < P.dl.size(); r += 64) {
+                const size_t r1 = std::min(P.dl.size(), r + 64) - 1;
+                lext = std::max(lext, P.dl[r1] - P.dl[r]);
+            }
+            const double span_w = std::max(sw.tmax - sw.tmin, 1e-300);
+            const double span_o = std::max(so.tmax - so.tmin, 1e-300);
+            const double dens_w = (double)(dw.n - 1) / span_w;
+            const double dens_o = (double)(dO.n - 1) / span_o;
+            const int n_kt = (int)ceil_div(T.K, 64);
+            auto est = [&](int64_t j) {
+                return dens_w * ((double)j / dens_o + lext + 2.0 * T.W) + 2.0;
+            };
+            // outer samples per workgroup: as many as keep the window range in
+            // LDS (half the capacity, for clustering) while leaving at least
+            // 2048 work items (eight per CU) when the problem is big enough
+            int64_t Jt = 64;
+            while (Jt * 2 <= jmax && est(Jt * 2) <= 0.5 * cap &&
+                   (double)dO.n * n_kt / (double)(Jt * 2) >= 2048.0)
+                Jt *= 2;
+            while (Jt > 16 && est(Jt) > 0.5 * cap) Jt /= 2;
+            T.J = (int32_t)Jt;
+            need = std::max(need, est(Jt));
+            jneed = std::max(jneed, (int)Jt);
+            T.n_jt = (int32_t)ceil_div(dO.n, Jt);
+            T.n_kt = n_kt;
+            T.item0 = W.nitems;
+            W.item0[i] = W.nitems;
+            W.wk0[i] = W.total_rows;
+            W.r0[i] = W.nred1;
+            W.nitems += (int64_t)T.n_jt * T.n_kt;
+            W.nred1 += (int64_t)T.n_kt * ceil_div(T.n_jt, kWinJc);
+            W.total_rows += T.K;
+            // algorithmic work: per (j, k) window, searches + per-point weight ops
+            const double pts = rect ? 0.0 : dens_w * 2.0 * T.W;
+            W.work += (double)dO.n * T.K * (8.0 + (rect ? 4.0 : 8.0 * pts));
+            W.wt[i] = T;
         }
-        // twice the estimated window range (clustering margin), rounded up
+        W.item0[ntw] = W.nitems;
+        W.wk0[ntw] = W.total_rows;
+        W.r0[ntw] = W.nred1;
+        // LDS: twice the estimated window range (clustering margin), rounded up
         const int want = (int)std::min<double>(cap, round_up((int64_t)(2.0 * need) + 64, 256));
-        cap = std::max(256, want);
-        jmax_used = (int)round_up(jmax_used, 64);
+        W.cap = std::max(256, want);
+        W.jmax = (int)round_up(jneed, 64);
+    };
+
+    WinLaunch W1;
+    for (int64_t p = 0; p < J.nprob; ++p) {
+        if (pstat[p] != NCF_OK || spec_b) continue;
+        if (!J.ccf) {
+            W1.plans.push_back({0, 0, p, 0, delta});
+        } else {
+            if (Krow > 0) W1.plans.push_back({0, 1, p, 0, delta});
+            W1.plans.push_back({0, 0, p, 1, {0.0}});
+            W1.plans.push_back({1, 1, p, 2, {0.0}});
+        }
     }
+    if (Krow == 0) delta.assign(1, 0.0);
+    plan_window(W1);
+    const int ntw = (int)W1.plans.size();
+    (void)wnumer;
 
     // spectral problems, sorted by grid size so grids of one size are contiguous
     struct SpecPlan {
@@ -631,22 +650,30 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     const int nts = (int)splans.size();
     const int Keval = (int)(J.ccf ? K : K + 1);
     const size_t csz = fp64 ? 16 : 8;
+    const bool two_grids = spec_b && J.ccf;
 
     // ------------------------------------------------ phase 2 device workspace
-    std::vector<void*> grids(nts);
-    std::vector<double*> numer(nts), spart(nts);
+    std::vector<void*> grids(nts), gridbs(nts, nullptr);
+    std::vector<double*> numer(nts), bspec(nts, nullptr), spart(nts, nullptr);
     double *d_c = nullptr, *d_b = nullptr;
     int64_t* d_cnt = nullptr;
     auto layout2 = [&](Arena& ar) {
         for (int i = 0; i < ntw; ++i) {
-            wt[i].part = ar.take<double>((size_t)wt[i].n_jt * wt[i].K * 4);
-            wt[i].part2 = ar.take<double>((size_t)ceil_div(wt[i].n_jt, kWinJc) * wt[i].K * 4);
-            wt[i].sums = ar.take<double>((size_t)wt[i].K * 4);
+            WinTask& T = W1.wt[i];
+            T.part = ar.take<double>((size_t)T.n_jt * T.K * 4);
+            T.part2 = ar.take<double>((size_t)ceil_div(T.n_jt, kWinJc) * T.K * 4);
+            T.sums = ar.take<double>((size_t)T.K * 4);
         }
+        // per-lag spectral results of all problems are contiguous (one readback)
+        double* numer_all = ar.take<double>((size_t)std::max(nts, 1) * std::max(Keval, 1));
+        double* bspec_all =
+            spec_b ? ar.take<double>((size_t)std::max(nts, 1) * std::max(Keval, 1)) : nullptr;
         for (int i = 0; i < nts; ++i) {
             grids[i] = ar.take<char>((size_t)splans[i].g.N * csz);
-            numer[i] = ar.take<double>(std::max(Keval, 1));
-            spart[i] = J.ccf ? ar.take<double>(2 * (splans[i].g.N / 256)) : nullptr;
+            if (two_grids) gridbs[i] = ar.take<char>((size_t)splans[i].g.N * csz);
+            numer[i] = numer_all + (size_t)i * std::max(Keval, 1);
+            if (spec_b) bspec[i] = bspec_all + (size_t)i * std::max(Keval, 1);
+            if (J.ccf) spart[i] = ar.take<double>(4 * (splans[i].g.N / 4096));
         }
         if (J.dev_ptrs) {
             d_c = J.c;
@@ -669,33 +696,30 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     struct T2 {
         WinTask* wt;
         int64_t *item0, *wk0, *r0;
-        double *delta, *zero;
-        int32_t* perm;
+        double* dl;
         SpecTask* st;
         int64_t *tile0, *pos0, *sk0;
         int32_t* rinfo;
         double* ev;
-        void** gtab;
-        NormTask* nt;
-        int32_t* status;
+        void** gfwd;
+        void** ginv;
     } dT{}, hT{};
+    size_t ndl = 0;
+    for (auto& P : W1.plans) ndl += P.dl.size();
     auto take2 = [&](Tables& tb) {
         dT.wt = tb.take<WinTask>(ntw, &hT.wt);
         dT.item0 = tb.take<int64_t>(ntw + 1, &hT.item0);
         dT.wk0 = tb.take<int64_t>(ntw + 1, &hT.wk0);
         dT.r0 = tb.take<int64_t>(ntw + 1, &hT.r0);
-        dT.delta = tb.take<double>(Krow, &hT.delta);
-        dT.zero = tb.take<double>(1, &hT.zero);
-        dT.perm = tb.take<int32_t>(K, &hT.perm);
+        dT.dl = tb.take<double>(ndl, &hT.dl);
         dT.st = tb.take<SpecTask>(nts, &hT.st);
         dT.tile0 = tb.take<int64_t>(nts + 1, &hT.tile0);
         dT.pos0 = tb.take<int64_t>(nts + 1, &hT.pos0);
         dT.sk0 = tb.take<int64_t>(nts + 1, &hT.sk0);
         dT.rinfo = tb.take<int32_t>(6 * (size_t)nts, &hT.rinfo);
         dT.ev = tb.take<double>(Keval, &hT.ev);
-        dT.gtab = tb.take<void*>(nts, &hT.gtab);
-        dT.nt = tb.take<NormTask>(J.nprob, &hT.nt);
-        dT.status = tb.take<int32_t>(J.nprob, &hT.status);
+        dT.gfwd = tb.take<void*>(2 * (size_t)nts, &hT.gfwd);
+        dT.ginv = tb.take<void*>(nts, &hT.ginv);
     };
     Tables t2;
     take2(t2);
@@ -704,20 +728,27 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     t2 = Tables{stg2->h, stg2->d, 0};
     take2(t2);
 
-    // window tables
-    for (int i = 0; i < ntw; ++i) wt[i].delta = wplans[i].role == 0 ? dT.delta : dT.zero;
-    std::memcpy(hT.wt, wt.data(), sizeof(WinTask) * ntw);
-    std::memcpy(hT.item0, item0.data(), sizeof(int64_t) * (ntw + 1));
-    std::memcpy(hT.wk0, wk0.data(), sizeof(int64_t) * (ntw + 1));
-    std::memcpy(hT.r0, r0.data(), sizeof(int64_t) * (ntw + 1));
-    std::memcpy(hT.delta, delta.data(), sizeof(double) * Krow);
-    hT.zero[0] = 0.0;
-    std::memcpy(hT.perm, perm.data(), sizeof(int32_t) * K);
+    // window tables: each task's sorted lag offsets
+    {
+        size_t o = 0;
+        for (int i = 0; i < ntw; ++i) {
+            std::memcpy(hT.dl + o, W1.plans[i].dl.data(), sizeof(double) * W1.plans[i].dl.size());
+            W1.wt[i].delta = dT.dl + o;
+            o += W1.plans[i].dl.size();
+        }
+    }
+    if (ntw) {
+        std::memcpy(hT.wt, W1.wt.data(), sizeof(WinTask) * ntw);
+        std::memcpy(hT.item0, W1.item0.data(), sizeof(int64_t) * (ntw + 1));
+        std::memcpy(hT.wk0, W1.wk0.data(), sizeof(int64_t) * (ntw + 1));
+        std::memcpy(hT.r0, W1.r0.data(), sizeof(int64_t) * (ntw + 1));
+    }
 
     // spectral tables
     std::map<int64_t, FftPlan> plans;
     int64_t total_pos = 0, ntiles = 0;
     double spread_bytes = 0.0;
+    std::vector<std::pair<int, int>> groups;  // (first task, count) per grid size
     for (int i = 0; i < nts; ++i) {
         const SpecPlan& P = splans[i];
         const SeriesDesc& d0 = sdesc[J.set[0].sd0 + P.prob];
@@ -743,6 +774,9 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         T.kern = J.kern;
         T.ccf = J.ccf ? 1 : 0;
         T.grid = grids[i];
+        T.gridb = gridbs[i];
+        T.with_b = spec_b ? 1 : 0;
+        T.bspec = bspec[i];
         T.tile0 = ntiles;
         T.ntiles = P.g.N / 4096;
         ntiles += T.ntiles;
@@ -757,7 +791,10 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         hT.tile0[i] = T.tile0;
         hT.pos0[i] = T.pos0;
         hT.sk0[i] = (int64_t)i * Keval;
-        hT.gtab[i] = grids[i];
+        if (i == 0 || splans[i].g.N != splans[i - 1].g.N)
+            groups.push_back({i, 1});
+        else
+            groups.back().second++;
         if (!plans.count(T.N)) {
             FftPlan fp;
             NCF_TRY(fft_plan(T.N, fp64, &fp, J.st));
@@ -774,7 +811,19 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             hT.rinfo[6 * i + 1 + q] = lg;
         }
         hT.rinfo[6 * i + 5] = lgN;
-        spread_bytes += (double)(T.n0 + T.n1) * 12.0 + (double)T.N * csz;
+        spread_bytes += (double)(T.n0 + T.n1) * 12.0 + (double)T.N * csz * (two_grids ? 2 : 1);
+    }
+    // forward table: per size group, its grids then (CCF with b) its unit grids
+    std::vector<std::pair<int, int>> fwd_groups;
+    {
+        int o = 0;
+        for (auto& gq : groups) {
+            fwd_groups.push_back({o, gq.second * (two_grids ? 2 : 1)});
+            for (int i = gq.first; i < gq.first + gq.second; ++i) hT.gfwd[o++] = grids[i];
+            if (two_grids)
+                for (int i = gq.first; i < gq.first + gq.second; ++i) hT.gfwd[o++] = gridbs[i];
+        }
+        for (int i = 0; i < nts; ++i) hT.ginv[i] = grids[i];
     }
     if (nts > 0) {
         hT.tile0[nts] = ntiles;
@@ -783,80 +832,195 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         for (int64_t k = 0; k < K; ++k) hT.ev[k] = J.lags[k];
         if (!J.ccf) hT.ev[K] = 0.0;
     }
-
-    // normalization tables
-    {
-        std::vector<int> main_t(J.nprob, -1), selfx(J.nprob, -1), selfy(J.nprob, -1),
-            spec_t(J.nprob, -1);
-        for (int i = 0; i < ntw; ++i) {
-            const WinPlan& P = wplans[i];
-            (P.role == 0 ? main_t : P.role == 1 ? selfx : selfy)[P.prob] = i;
-        }
-        for (int i = 0; i < nts; ++i) spec_t[splans[i].prob] = i;
-        for (int64_t p = 0; p < J.nprob; ++p) {
-            NormTask T{};
-            T.ccf = J.ccf ? 1 : 0;
-            T.K = (int32_t)K;
-            T.perm = dT.perm;
-            T.row0 = row0;
-            T.spectral = spectral ? 1 : 0;
-            T.weighted = weighted ? 1 : 0;
-            T.is_rect = rect ? 1 : 0;
-            T.status = dT.status + p;
-            T.c = d_c + p * K;
-            T.b = d_b + p * K;
-            T.count = d_cnt ? d_cnt + p * K : nullptr;
-            hT.status[p] = pstat[p];
-            if (pstat[p] == NCF_OK) {
-                if (main_t[p] >= 0) T.wsums = wt[main_t[p]].sums;
-                if (J.ccf) {
-                    T.self_x = wt[selfx[p]].sums;
-                    T.self_y = wt[selfy[p]].sums;
-                }
-                if (spectral) {
-                    const int i = spec_t[p];
-                    T.numer = numer[i];
-                    T.scale_part = spart[i];
-                    T.nscale_part = splans[i].g.N / 256;
-                }
-            } else {
-                T.skip = 1;  // outputs: c = NaN, b = 0, count = 0
-            }
-            hT.nt[p] = T;
-        }
-    }
     NCF_TRY_HIP(hipMemcpyAsync(stg2->d, stg2->h, t2.off, hipMemcpyHostToDevice, J.st));
 
     // ------------------------------------------------ A7 window scan
-    NCF_TRY(launch_window(dT.wt, dT.item0, ntw, nitems, wflags, cap, jmax_used, J.st,
-                          win_work));
-    NCF_TRY(launch_window_reduce(dT.wt, ntw, total_rows, dT.wk0, dT.r0, nred1, wflags, J.st));
+    NCF_TRY(launch_window(dT.wt, dT.item0, ntw, W1.nitems, wflags, W1.cap, W1.jmax, J.st,
+                          W1.work));
+    NCF_TRY(launch_window_reduce(dT.wt, ntw, W1.total_rows, dT.wk0, dT.r0, W1.nred1, wflags,
+                                 J.st));
 
-    // ------------------------------------------------ A2-A6 spectral numerator
+    // ------------------------------------------------ A2-A6 spectral route
     if (nts > 0) {
         NCF_TRY(launch_spread(dT.st, dT.tile0, nts, ntiles, 4096, fp64, J.st, spread_bytes));
-        std::vector<std::pair<int, int>> groups;  // (first task, count) per grid size
-        for (int i = 0; i < nts; ++i) {
-            if (i == 0 || splans[i].g.N != splans[i - 1].g.N)
-                groups.push_back({i, 1});
-            else
-                groups.back().second++;
-        }
-        for (auto& gq : groups)
-            NCF_TRY(fft_exec(plans[splans[gq.first].g.N], dT.gtab + gq.first, gq.second, +1,
-                             fp64, J.st));
+        for (size_t q = 0; q < groups.size(); ++q)
+            NCF_TRY(fft_exec(plans[splans[groups[q].first].g.N], dT.gfwd + fwd_groups[q].first,
+                             fwd_groups[q].second, +1, fp64, J.st));
         NCF_TRY(launch_product(dT.st, dT.pos0, nts, total_pos, (const int64_t*)dT.rinfo, fp64,
-                               J.st, 2.0 * total_pos * csz));
+                               J.st, (two_grids ? 3.0 : 2.0) * total_pos * csz));
         for (auto& gq : groups)
-            NCF_TRY(fft_exec(plans[splans[gq.first].g.N], dT.gtab + gq.first, gq.second, -1,
+            NCF_TRY(fft_exec(plans[splans[gq.first].g.N], dT.ginv + gq.first, gq.second, -1,
                              fp64, J.st));
         NCF_TRY(launch_interp(dT.st, nts, dT.sk0, (int64_t)nts * Keval, fp64, J.st));
     }
 
+    // ------------------------------------------------ direct fallback (spectral b)
+    // lags whose spectral pair count is below beta times the reference
+    // (lag 0 for the ACF, the largest requested lag for the CCF) are summed
+    // directly: their spectral value is dominated by rounding noise
+    std::vector<int> spec_of(J.nprob, -1);
+    for (int i = 0; i < nts; ++i) spec_of[splans[i].prob] = i;
+    std::vector<std::vector<int>> flagged(J.nprob);  // requested lag indices
+    WinLaunch W2;
+    if (spec_b && nts > 0 && K > 0) {
+        // the spectral b values of all problems are contiguous in the arena
+        std::vector<double> hb((size_t)nts * Keval);
+        NCF_TRY_HIP(hipMemcpyAsync(hb.data(), bspec[0], sizeof(double) * Keval * nts,
+                                   hipMemcpyDeviceToHost, J.st));
+        NCF_TRY_HIP(hipStreamSynchronize(J.st));
+        for (int i = 0; i < nts; ++i) {
+            const int64_t p = splans[i].prob;
+            const double* bb = hb.data() + (size_t)i * Keval;
+            double bref = 0.0;
+            if (!J.ccf)
+                bref = bb[K];
+            else
+                for (int64_t k = 0; k < K; ++k) bref = std::max(bref, bb[k]);
+            std::vector<double> dl;
+            for (int r = 0; r < Krow; ++r) {
+                const int k = rows[r].second;
+                if (k < 0) continue;
+                if (!(bb[k] >= beta * bref) || !(bref > 0.0)) {
+                    flagged[p].push_back(k);
+                    dl.push_back(delta[r]);
+                }
+            }
+            if (!dl.empty())
+                W2.plans.push_back({0, J.ccf ? 1 : 0, p, 3, dl});
+        }
+        plan_window(W2);
+    }
+    const int ntw2 = (int)W2.plans.size();
+    const uint32_t wflags2 = (fp64 ? (uint32_t)WIN_EXP64 : 0u) | (uint32_t)WIN_NUMER;
+
+    // fallback workspace and the output tables
+    auto layout3 = [&](Arena& ar) {
+        for (int i = 0; i < ntw2; ++i) {
+            WinTask& T = W2.wt[i];
+            T.part = ar.take<double>((size_t)T.n_jt * T.K * 4);
+            T.part2 = ar.take<double>((size_t)ceil_div(T.n_jt, kWinJc) * T.K * 4);
+            T.sums = ar.take<double>((size_t)T.K * 4);
+        }
+    };
+    Arena a3;
+    layout3(a3);
+    if (ntw2 > 0) {
+        void* ws3 = nullptr;
+        NCF_TRY(ensure_ws(2, a3.off + 256, &ws3));
+        a3 = Arena{(char*)ws3, 0};
+        layout3(a3);
+    }
+    struct T3 {
+        WinTask* wt;
+        int64_t *item0, *wk0, *r0;
+        double* dl;
+        int32_t* fbrow;
+        int32_t* perm;
+        NormTask* nt;
+        int32_t* status;
+    } dU{}, hU{};
+    size_t ndl2 = 0;
+    for (auto& P : W2.plans) ndl2 += P.dl.size();
+    const bool any_fb = ntw2 > 0;
+    auto take3 = [&](Tables& tb) {
+        dU.wt = tb.take<WinTask>(ntw2, &hU.wt);
+        dU.item0 = tb.take<int64_t>(ntw2 + 1, &hU.item0);
+        dU.wk0 = tb.take<int64_t>(ntw2 + 1, &hU.wk0);
+        dU.r0 = tb.take<int64_t>(ntw2 + 1, &hU.r0);
+        dU.dl = tb.take<double>(ndl2, &hU.dl);
+        dU.fbrow = tb.take<int32_t>(any_fb ? (size_t)J.nprob * K : 1, &hU.fbrow);
+        dU.perm = tb.take<int32_t>(K, &hU.perm);
+        dU.nt = tb.take<NormTask>(J.nprob, &hU.nt);
+        dU.status = tb.take<int32_t>(J.nprob, &hU.status);
+    };
+    Tables t3;
+    take3(t3);
+    Staging* stg3 = nullptr;
+    NCF_TRY(ensure_stage(2, t3.off, &stg3));
+    t3 = Tables{stg3->h, stg3->d, 0};
+    take3(t3);
+    std::vector<int> fb_task(J.nprob, -1);
+    {
+        size_t o = 0;
+        for (int i = 0; i < ntw2; ++i) {
+            std::memcpy(hU.dl + o, W2.plans[i].dl.data(), sizeof(double) * W2.plans[i].dl.size());
+            W2.wt[i].delta = dU.dl + o;
+            o += W2.plans[i].dl.size();
+            fb_task[W2.plans[i].prob] = i;
+        }
+        if (ntw2) {
+            std::memcpy(hU.wt, W2.wt.data(), sizeof(WinTask) * ntw2);
+            std::memcpy(hU.item0, W2.item0.data(), sizeof(int64_t) * (ntw2 + 1));
+            std::memcpy(hU.wk0, W2.wk0.data(), sizeof(int64_t) * (ntw2 + 1));
+            std::memcpy(hU.r0, W2.r0.data(), sizeof(int64_t) * (ntw2 + 1));
+        }
+        if (any_fb) {
+            for (int64_t i = 0; i < J.nprob * K; ++i) hU.fbrow[i] = -1;
+            // flagged lags are in sorted-row order; their fallback row is their rank
+            for (int64_t p = 0; p < J.nprob; ++p)
+                for (size_t q = 0; q < flagged[p].size(); ++q)
+                    hU.fbrow[p * K + flagged[p][q]] = (int32_t)q;
+        }
+    }
+    // normalization tables
+    std::memcpy(hU.perm, perm.data(), sizeof(int32_t) * K);
+    {
+        std::vector<int> main_t(J.nprob, -1), selfx(J.nprob, -1), selfy(J.nprob, -1);
+        for (int i = 0; i < ntw; ++i) {
+            const WinPlan& P = W1.plans[i];
+            (P.role == 0 ? main_t : P.role == 1 ? selfx : selfy)[P.prob] = i;
+        }
+        for (int64_t p = 0; p < J.nprob; ++p) {
+            NormTask T{};
+            T.ccf = J.ccf ? 1 : 0;
+            T.K = (int32_t)K;
+            T.perm = dU.perm;
+            T.row0 = row0;
+            T.spectral = spectral ? 1 : 0;
+            T.spec_b = spec_b ? 1 : 0;
+            T.weighted = weighted ? 1 : 0;
+            T.is_rect = rect ? 1 : 0;
+            T.beta = beta;
+            T.status = dU.status + p;
+            T.c = d_c + p * K;
+            T.b = d_b + p * K;
+            T.count = d_cnt ? d_cnt + p * K : nullptr;
+            hU.status[p] = pstat[p];
+            if (pstat[p] == NCF_OK) {
+                if (main_t[p] >= 0) T.wsums = W1.wt[main_t[p]].sums;
+                if (J.ccf && selfx[p] >= 0) {
+                    T.self_x = W1.wt[selfx[p]].sums;
+                    T.self_y = W1.wt[selfy[p]].sums;
+                }
+                if (spectral) {
+                    const int i = spec_of[p];
+                    T.numer = numer[i];
+                    T.bspec = bspec[i];
+                    T.scale_part = spart[i];
+                    T.nscale_part = splans[i].g.N / 4096;
+                }
+                if (fb_task[p] >= 0) {
+                    T.fb_row = dU.fbrow + p * K;
+                    T.fb_sums = W2.wt[fb_task[p]].sums;
+                }
+            } else {
+                T.skip = 1;  // outputs: c = NaN, b = 0, count = 0
+            }
+            hU.nt[p] = T;
+        }
+    }
+    NCF_TRY_HIP(hipMemcpyAsync(stg3->d, stg3->h, t3.off, hipMemcpyHostToDevice, J.st));
+    if (ntw2 > 0) {
+        NCF_TRY(launch_window(dU.wt, dU.item0, ntw2, W2.nitems, wflags2, W2.cap, W2.jmax, J.st,
+                              W2.work));
+        NCF_TRY(launch_window_reduce(dU.wt, ntw2, W2.total_rows, dU.wk0, dU.r0, W2.nred1,
+                                     wflags2, J.st));
+    }
+
     // ------------------------------------------------ A8 normalization, outputs
-    NCF_TRY(launch_normalize(dT.nt, (int)J.nprob, J.nprob * K, nullptr, J.st));
-    int32_t* h_fstat = hT.status;  // pinned; the upload above has been enqueued before
-    NCF_TRY_HIP(hipMemcpyAsync(h_fstat, dT.status, sizeof(int32_t) * J.nprob,
+    NCF_TRY(launch_normalize(dU.nt, (int)J.nprob, J.nprob * K, nullptr, J.st));
+    int32_t* h_fstat = hU.status;  // pinned; its upload was enqueued before
+    NCF_TRY_HIP(hipMemcpyAsync(h_fstat, dU.status, sizeof(int32_t) * J.nprob,
                                hipMemcpyDeviceToHost, J.st));
     if (!J.dev_ptrs && K > 0) {
         NCF_TRY_HIP(hipMemcpyAsync(J.c, d_c, sizeof(double) * J.nprob * K, hipMemcpyDeviceToHost,
@@ -986,7 +1150,7 @@ void ncf_release_workspace(void) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return;
     (void)hipDeviceSynchronize();
-    for (int w = 0; w < 2; ++w) {
+    for (int w = 0; w < 3; ++w) {
         auto it = g_ws[w].find(dev);
         if (it != g_ws[w].end() && it->second.ptr) {
             (void)hipFree(it->second.ptr);

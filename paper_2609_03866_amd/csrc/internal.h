@@ -196,8 +196,13 @@ struct SpecTask {
     int32_t K_eval;
     int32_t pad;
     double* numer;         // K_eval results N(tau)
-    double* scale_part;    // per-workgroup partial (S_xx, S_yy) pairs, product kernel
+    double* scale_part;    // per-workgroup partial sums of the product kernel (4 per block:
+                           // S_xx, S_yy, and with with_b the lag-0 pair sums B_xx, B_yy)
     int64_t pos0;          // first element offset of this task in the flattened product launch
+    int32_t with_b;        // also carry the unit-weight channel: pair count b(tau) spectrally
+    int32_t pad2;
+    void* gridb;           // CCF with_b: unit-weight grid (series 1 real, series 2 imaginary)
+    double* bspec;         // with_b: K_eval results b(tau)
 };
 
 int launch_tile_ranges(const SpecTask* d_tasks, const int64_t* d_tile0, int ntasks,
@@ -238,6 +243,12 @@ struct NormTask {
     const int32_t* perm;  // requested lag k -> row of the window sums
     int32_t row0;         // ACF: row of lag 0 in the window sums
     int32_t spectral;     // numerator from the spectral route
+    int32_t spec_b;       // pair counts from the spectral route too (else window sums)
+    int32_t pad3;
+    const double* bspec;  // spectral b per requested lag (+ lag 0 last for ACF)
+    const int32_t* fb_row;  // requested lag -> row of the direct fallback sums, -1 if none
+    const double* fb_sums;  // direct window sums [rows][4] of the fallback lags
+    double beta;          // fallback threshold (window-b path): b < beta * b_ref
     const double* wsums;  // window sums [K_rows][4]
     const double* numer;  // spectral numerator per requested lag (+ lag 0 last for ACF)
     const double* self_x; // CCF: window sums of series 1 on itself at lag 0 ([4])

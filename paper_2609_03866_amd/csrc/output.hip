@@ -16,10 +16,17 @@ constexpr int kThreads = 256;
 
 __device__ __forceinline__ double fl(double v) { return v > kFloor ? v : kFloor; }
 
+// Per requested lag the numerator C and pair sum B come from one of:
+//  * the direct fallback sums (lags whose spectral b was small),
+//  * the spectral route (N, and b when the unit-weight channel ran),
+//  * the window sums (rectangle, direct method; and with the spectral
+//    numerator but window b, the window's direct numerator at lags whose
+//    b < beta * b_ref).
 __global__ void __launch_bounds__(kThreads)
 k_normalize(const NormTask* __restrict__ tasks) {
-    __shared__ double red[2][kThreads];
-    __shared__ double sh_scale;
+    __shared__ double red[4][kThreads];
+    __shared__ double redm[kThreads];
+    __shared__ double sh_scale, sh_bref;
     const NormTask& T = tasks[blockIdx.x];
     const int tid = threadIdx.x;
     if (T.skip) {  // the problem failed validation
@@ -31,42 +38,67 @@ k_normalize(const NormTask* __restrict__ tasks) {
         return;
     }
     const int bq = T.weighted ? 1 : 2;  // which window sum is the denominator B
-    // lag-0 scale
+    // spectral lag-0 sums (CCF): S_xx, S_yy and, with spectral b, B_xx, B_yy
     if (T.ccf && T.spectral) {
-        double sx = 0.0, sy = 0.0;
-        for (int64_t i = tid; i < T.nscale_part; i += kThreads) {
-            sx += T.scale_part[2 * i];
-            sy += T.scale_part[2 * i + 1];
-        }
-        red[0][tid] = sx;
-        red[1][tid] = sy;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int64_t i = tid; i < T.nscale_part; i += kThreads)
+            for (int q = 0; q < 4; ++q) acc[q] += T.scale_part[4 * i + q];
+        for (int q = 0; q < 4; ++q) red[q][tid] = acc[q];
         __syncthreads();
         for (int off = kThreads / 2; off > 0; off >>= 1) {
-            if (tid < off) {
-                red[0][tid] += red[0][tid + off];
-                red[1][tid] += red[1][tid + off];
-            }
+            if (tid < off)
+                for (int q = 0; q < 4; ++q) red[q][tid] += red[q][tid + off];
             __syncthreads();
         }
+    }
+    // reference pair count of the window-b spectral path (ACF: lag 0, CCF:
+    // the largest requested lag)
+    const bool sel_window = T.spectral && !T.spec_b;
+    if (sel_window) {
+        double m = 0.0;
+        if (T.ccf)
+            for (int k = tid; k < T.K; k += kThreads) m = fmax(m, T.wsums[4 * T.perm[k] + bq]);
+        redm[tid] = m;
+        __syncthreads();
+        for (int off = kThreads / 2; off > 0; off >>= 1) {
+            if (tid < off) redm[tid] = fmax(redm[tid], redm[tid + off]);
+            __syncthreads();
+        }
+        if (tid == 0) sh_bref = T.ccf ? redm[0] : T.wsums[4 * T.row0 + bq];
+        __syncthreads();
     }
     if (tid == 0) {
         double scale;
         if (T.ccf) {
-            double cx, cy;
-            if (T.spectral) {
+            double cx, cy, bx, by;
+            if (T.spectral && T.spec_b) {
                 cx = red[0][0];
                 cy = red[1][0];
+                bx = red[2][0];
+                by = red[3][0];
+            } else if (T.spectral) {
+                cx = red[0][0];
+                cy = red[1][0];
+                bx = T.self_x[bq];
+                by = T.self_y[bq];
             } else {
                 cx = T.self_x[0];
                 cy = T.self_y[0];
+                bx = T.self_x[bq];
+                by = T.self_y[bq];
             }
-            const double sxv = cx / fl(T.self_x[bq]);
-            const double syv = cy / fl(T.self_y[bq]);
-            const double prod = sxv * syv;
+            const double prod = (cx / fl(bx)) * (cy / fl(by));
             scale = (prod > 0.0 && isfinite(prod)) ? sqrt(prod) : NAN;
         } else {
-            const double c0 = T.spectral ? T.numer[T.K] : T.wsums[4 * T.row0 + 0];
-            const double r0 = c0 / fl(T.wsums[4 * T.row0 + bq]);
+            double c0, b0;
+            if (T.spectral && T.spec_b) {
+                c0 = T.numer[T.K];
+                b0 = T.bspec[T.K];
+            } else {
+                c0 = T.spectral ? T.numer[T.K] : T.wsums[4 * T.row0 + 0];
+                b0 = T.wsums[4 * T.row0 + bq];
+            }
+            const double r0 = c0 / fl(b0);
             scale = (r0 > 0.0 && isfinite(r0)) ? r0 : NAN;
         }
         sh_scale = scale;
@@ -75,16 +107,34 @@ k_normalize(const NormTask* __restrict__ tasks) {
     __syncthreads();
     const double scale = sh_scale;
     for (int k = tid; k < T.K; k += kThreads) {
-        const int row = T.perm[k];
-        const double* w = T.wsums + 4 * (int64_t)row;
-        // an empty window has numerator exactly 0 (the spectral value there is
-        // rounding noise that the 1e-16 floor would amplify)
-        const bool empty = __double_as_longlong(w[3]) == 0;
-        const double num = empty ? 0.0 : (T.spectral ? T.numer[k] : w[0]);
-        const double r = num / fl(w[bq]);
-        T.c[k] = r / scale;
-        T.b[k] = fl(w[2]);
-        if (T.count) T.count[k] = T.is_rect ? (int64_t)__double_as_longlong(w[3]) : 0;
+        const int fb = T.fb_row ? T.fb_row[k] : -1;
+        double num, den, bout;
+        int64_t cnt = 0;
+        if (fb >= 0) {
+            const double* w = T.fb_sums + 4 * (int64_t)fb;
+            const bool empty = __double_as_longlong(w[3]) == 0;
+            num = empty ? 0.0 : w[0];
+            den = w[bq];
+            bout = w[2];
+        } else if (T.spectral && T.spec_b) {
+            num = T.numer[k];
+            den = T.bspec[k];
+            bout = T.bspec[k];
+        } else {
+            const double* w = T.wsums + 4 * (int64_t)T.perm[k];
+            // an empty window has numerator exactly 0; a window with few
+            // pairs takes the direct numerator (the spectral value there is
+            // rounding noise that a small denominator would amplify)
+            const bool empty = __double_as_longlong(w[3]) == 0;
+            const bool direct = !T.spectral || (w[bq] < T.beta * sh_bref);
+            num = empty ? 0.0 : (direct ? w[0] : T.numer[k]);
+            den = w[bq];
+            bout = w[2];
+            cnt = __double_as_longlong(w[3]);
+        }
+        T.c[k] = (num / fl(den)) / scale;
+        T.b[k] = fl(bout);
+        if (T.count) T.count[k] = T.is_rect ? cnt : 0;
     }
 }
 

@@ -101,10 +101,10 @@ struct PtsLds {
 };
 
 // Accumulate one point set into the thread's 16 cells.
-template <typename R>
-__device__ void gather_set(R (&acc)[kCellsPerThread], PtsLds<R>& P, const double* t, const float* vf,
-                           const double* vd, int64_t p0, int64_t p1, int64_t c0, double t_ref,
-                           double scale, R W, R k2) {
+template <typename R, bool UNIT>
+__device__ void gather_set(R (&acc)[kCellsPerThread], R (&accu)[kCellsPerThread], PtsLds<R>& P,
+                           const double* t, const float* vf, const double* vd, int64_t p0,
+                           int64_t p1, int64_t c0, double t_ref, double scale, R W, R k2) {
     const int tid = threadIdx.x;
     const int cb = tid * kCellsPerThread;  // first own cell, relative to tile
     for (int64_t base = p0; base < p1; base += kPtsChunk) {
@@ -144,6 +144,7 @@ __device__ void gather_set(R (&acc)[kCellsPerThread], PtsLds<R>& P, const double
                     else
                         e = exp(d * d * k2);
                     acc[q] += e * vv;
+                    if (UNIT) accu[q] += e;  // unit weights: pair-count channel
                 }
             }
         }
@@ -159,7 +160,7 @@ k_spread(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ tile0, 
     const int64_t g = blockIdx.x;
     (void)nblocks;
     if (g >= ntiles) return;
-    const int ti = (int)find_task(tile0, ntasks, g);
+    const int ti = ntasks == 1 ? 0 : (int)wave_search<int64_t>(tile0, ntasks, g, true) - 1;
     const SpecTask& T = tasks[ti];
     const int64_t tile = g - T.tile0;
     const int64_t c0 = tile * kTile;
@@ -183,32 +184,52 @@ k_spread(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ tile0, 
     // exp(-d^2 / 2 s^2): FP32 uses exp2 with log2(e) folded in
     const R k2 = sizeof(R) == 4 ? (R)(-0.72134752044448170 / (T.s * T.s))
                                 : (R)(-0.5 / (T.s * T.s));
-    R re[kCellsPerThread], im[kCellsPerThread];
+    R re[kCellsPerThread], im[kCellsPerThread], u0[kCellsPerThread], u1[kCellsPerThread];
 #pragma unroll
-    for (int q = 0; q < kCellsPerThread; ++q) re[q] = im[q] = (R)0;
-    gather_set<R>(re, P, T.t0, T.v0f, T.v0d, rng[0], rng[1], c0, T.t_ref, scale, W, k2);
-    if (T.ccf) gather_set<R>(im, P, T.t1, T.v1f, T.v1d, rng[2], rng[3], c0, T.t_ref, scale, W, k2);
-    // stage the tile through LDS for a coalesced write
-    __syncthreads();
-    C2* out = reinterpret_cast<C2*>(&P);
+    for (int q = 0; q < kCellsPerThread; ++q) re[q] = im[q] = u0[q] = u1[q] = (R)0;
+    if (!T.ccf) {
+        // ACF: values in the real channel, unit weights (with_b) in the imaginary one
+        if (T.with_b)
+            gather_set<R, true>(re, im, P, T.t0, T.v0f, T.v0d, rng[0], rng[1], c0, T.t_ref, scale,
+                                W, k2);
+        else
+            gather_set<R, false>(re, im, P, T.t0, T.v0f, T.v0d, rng[0], rng[1], c0, T.t_ref,
+                                 scale, W, k2);
+    } else if (T.with_b) {
+        // CCF: grid = series 1 values + i series 2 values; gridb = the same with unit weights
+        gather_set<R, true>(re, u0, P, T.t0, T.v0f, T.v0d, rng[0], rng[1], c0, T.t_ref, scale, W,
+                            k2);
+        gather_set<R, true>(im, u1, P, T.t1, T.v1f, T.v1d, rng[2], rng[3], c0, T.t_ref, scale, W,
+                            k2);
+    } else {
+        gather_set<R, false>(re, u0, P, T.t0, T.v0f, T.v0d, rng[0], rng[1], c0, T.t_ref, scale, W,
+                             k2);
+        gather_set<R, false>(im, u1, P, T.t1, T.v1f, T.v1d, rng[2], rng[3], c0, T.t_ref, scale, W,
+                             k2);
+    }
+    // stage the tile through LDS for a coalesced write (two halves, so the
+    // staging fits the point buffer)
     static_assert(sizeof(PtsLds<R>) >= sizeof(C2) * kTile / 2, "LDS staging too small");
-    C2* grid = reinterpret_cast<C2*>(T.grid) + c0;
-    // two halves so the staging fits the point buffer
-    for (int half = 0; half < 2; ++half) {
-        const int hbase = half * (kTile / 2);
-        const int tb = threadIdx.x * kCellsPerThread - hbase;
-        if (tb >= 0 && tb < kTile / 2) {
+    C2* out = reinterpret_cast<C2*>(&P);
+    const int ngrids = (T.ccf && T.with_b) ? 2 : 1;
+    for (int gsel = 0; gsel < ngrids; ++gsel) {
+        C2* grid = reinterpret_cast<C2*>(gsel == 0 ? T.grid : T.gridb) + c0;
+        for (int half = 0; half < 2; ++half) {
+            __syncthreads();
+            const int hbase = half * (kTile / 2);
+            const int tb = threadIdx.x * kCellsPerThread - hbase;
+            if (tb >= 0 && tb < kTile / 2) {
 #pragma unroll
-            for (int q = 0; q < kCellsPerThread; ++q) {
-                C2 v;
-                v.x = re[q];
-                v.y = im[q];
-                out[tb + q] = v;
+                for (int q = 0; q < kCellsPerThread; ++q) {
+                    C2 v;
+                    v.x = gsel == 0 ? re[q] : u0[q];
+                    v.y = gsel == 0 ? im[q] : u1[q];
+                    out[tb + q] = v;
+                }
             }
+            __syncthreads();
+            for (int i = threadIdx.x; i < kTile / 2; i += kThreads) grid[hbase + i] = out[i];
         }
-        __syncthreads();
-        for (int i = threadIdx.x; i < kTile / 2; i += kThreads) grid[hbase + i] = out[i];
-        __syncthreads();
     }
 }
 
@@ -253,24 +274,33 @@ __device__ __forceinline__ double lag_kernel_ft(int kern, double f, double h) {
     return sin(2.0 * M_PI * h * f) / (M_PI * f);
 }
 
+// In-place product on the digit-reversed spectrum. Without the unit-weight
+// channel: ACF -> phihat |X|^2 / (L Psi^3); CCF -> phihat conj(X) Y / (L Psi^3)
+// after unpacking X, Y from the packed grid. With it (with_b) the same
+// factor multiplies the numerator spectrum G_N and the pair-count spectrum
+// G_B (from the unit weights), and the grid receives G_N + i G_B: both are
+// Hermitian, so the inverse transform returns N(tau) in the real part and
+// b(tau) in the imaginary part. CCF blocks also reduce the lag-0 sums
+// S_xx, S_yy (and B_xx, B_yy) = sum_m phihat |.|^2 / (L Psi^2).
 template <typename R>
 __global__ void __launch_bounds__(kThreads)
 k_product(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pos0, int ntasks,
           int64_t total, const RadixInfo* __restrict__ rinfo) {
     using C2 = typename Cplx<R>::T;
-    __shared__ double red[2][kThreads];
-    const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    const int64_t gb = (int64_t)blockIdx.x * kThreads;  // whole block in one task
-    const int ti = (int)find_task(pos0, ntasks, gb);
+    __shared__ double red[4][kThreads];
+    // a block owns kTile consecutive positions of one grid (N >= kTile)
+    const int64_t gb = (int64_t)blockIdx.x * kTile;
+    const int ti = ntasks == 1 ? 0 : (int)wave_search<int64_t>(pos0, ntasks, gb, true) - 1;
     const SpecTask& T = tasks[ti];
     const RadixInfo ri = rinfo[ti];
-    const int64_t p = g - T.pos0;
     const int64_t N = T.N;
     C2* Z = reinterpret_cast<C2*>(T.grid);
+    C2* U = reinterpret_cast<C2*>(T.gridb);
     const double L = T.L, h = T.h, s = T.s;
     const double Nd = (double)N;
-    double sxx = 0.0, syy = 0.0;
-    if (p < N) {
+    double sacc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int it = 0; it < kTile / kThreads; ++it) {
+        const int64_t p = gb - T.pos0 + it * kThreads + threadIdx.x;
         const int64_t k = freq_of_pos(p, ri);
         const int64_t m = k <= N / 2 ? k : k - N;
         const double md = (double)m;
@@ -297,7 +327,7 @@ k_product(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pos0, 
                 f2 = c2 * ker * exp(2.0 * a_psi);
             }
         }
-        if (!T.ccf) {
+        if (!T.ccf && !T.with_b) {
             const C2 z = Z[p];
             const double pw = (double)z.x * z.x + (double)z.y * z.y;
             C2 o;
@@ -305,47 +335,75 @@ k_product(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pos0, 
             o.y = (R)0;
             Z[p] = o;
         } else if (k <= N - k || k == 0) {
-            // pair (m, -m): unpack the packed x (real) / y (imaginary) spectra
+            // pair (m, -m); partner position of frequency -m
             const int64_t kp = (N - k) & (N - 1);
             const int64_t pp = pos_of_freq(kp, ri);
             const C2 za = Z[p];
             const C2 zb = Z[pp];
-            // Fx = (Z_m + conj Z_-m)/2, Fy = (Z_m - conj Z_-m)/(2i)
-            const double fxr = 0.5 * ((double)za.x + zb.x), fxi = 0.5 * ((double)za.y - zb.y);
-            const double fyr = 0.5 * ((double)za.y + zb.y), fyi = -0.5 * ((double)za.x - zb.x);
-            // conj(Fx) * Fy
-            const double gr = fxr * fyr + fxi * fyi;
-            const double gi = fxr * fyi - fxi * fyr;
-            C2 o;
-            o.x = (R)(f3 * gr);
-            o.y = (R)(f3 * gi);
-            Z[p] = o;
-            if (pp != p) {
-                C2 oc;
-                oc.x = o.x;
-                oc.y = -o.y;
-                Z[pp] = oc;
-            }
+            // the two real sequences packed in Z: A = (Z_m + conj Z_-m)/2,
+            // B = (Z_m - conj Z_-m)/(2i)
+            const double ar = 0.5 * ((double)za.x + zb.x), ai = 0.5 * ((double)za.y - zb.y);
+            const double br = 0.5 * ((double)za.y + zb.y), bi = -0.5 * ((double)za.x - zb.x);
             const double mult = (pp != p) ? 2.0 : 1.0;
-            sxx = mult * f2 * (fxr * fxr + fxi * fxi);
-            syy = mult * f2 * (fyr * fyr + fyi * fyi);
+            C2 o, oc;
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            if (!T.ccf) {
+                // ACF with b: A = X (values), B = W (unit weights); G_N = |X|^2, G_B = |W|^2
+                const double gn = ar * ar + ai * ai, gbb = br * br + bi * bi;
+                o.x = (R)(f3 * gn);
+                o.y = (R)(f3 * gbb);
+                oc = o;
+            } else {
+                // CCF: G_N = conj(X) Y
+                const double gr = ar * br + ai * bi;
+                const double gi = ar * bi - ai * br;
+                s0 = mult * f2 * (ar * ar + ai * ai);
+                s1 = mult * f2 * (br * br + bi * bi);
+                if (!T.with_b) {
+                    o.x = (R)(f3 * gr);
+                    o.y = (R)(f3 * gi);
+                    oc.x = o.x;
+                    oc.y = -o.y;
+                } else {
+                    // unit-weight grid: G_B = conj(U_x) U_y
+                    const C2 ua = U[p];
+                    const C2 ub = U[pp];
+                    const double xr = 0.5 * ((double)ua.x + ub.x), xi = 0.5 * ((double)ua.y - ub.y);
+                    const double yr = 0.5 * ((double)ua.y + ub.y), yi = -0.5 * ((double)ua.x - ub.x);
+                    const double hr = xr * yr + xi * yi;
+                    const double hi = xr * yi - xi * yr;
+                    s2 = mult * f2 * (xr * xr + xi * xi);
+                    s3 = mult * f2 * (yr * yr + yi * yi);
+                    // G_N + i G_B at m, conj(G_N) + i conj(G_B) at -m
+                    o.x = (R)(f3 * (gr - hi));
+                    o.y = (R)(f3 * (gi + hr));
+                    oc.x = (R)(f3 * (gr + hi));
+                    oc.y = (R)(f3 * (hr - gi));
+                }
+            }
+            Z[p] = o;
+            if (pp != p) Z[pp] = oc;
+            sacc[0] += s0;
+            sacc[1] += s1;
+            sacc[2] += s2;
+            sacc[3] += s3;
         }
     }
     if (T.ccf) {
-        red[0][threadIdx.x] = sxx;
-        red[1][threadIdx.x] = syy;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) red[q][threadIdx.x] = sacc[q];
         __syncthreads();
         for (int off = kThreads / 2; off > 0; off >>= 1) {
             if (threadIdx.x < off) {
-                red[0][threadIdx.x] += red[0][threadIdx.x + off];
-                red[1][threadIdx.x] += red[1][threadIdx.x + off];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + off];
             }
             __syncthreads();
         }
         if (threadIdx.x == 0) {
-            const int64_t wg = (gb - T.pos0) / kThreads;
-            T.scale_part[2 * wg] = red[0][0];
-            T.scale_part[2 * wg + 1] = red[1][0];
+            const int64_t wg = (gb - T.pos0) / kTile;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) T.scale_part[4 * wg + q] = red[q][0];
         }
     }
 }
@@ -371,14 +429,18 @@ __global__ void k_interp(const SpecTask* __restrict__ tasks, int ntasks, const i
     const C2* G = reinterpret_cast<const C2*>(T.grid);
     const int wi = (int)ceil(T.W);
     const double kk = -0.5 / (T.s * T.s);
-    double acc = 0.0;
+    double acc = 0.0, accb = 0.0;
     for (int q = -wi - 1; q <= wi + 1; ++q) {
         const double d = fr - (double)q;  // u - (cell + q)
         if (d > T.W || d < -T.W) continue;
         const int64_t c = (cell + q) & (T.N - 1);
-        acc += (double)G[c].x * exp(d * d * kk);
+        const double wgt = exp(d * d * kk);
+        const C2 gv = G[c];
+        acc += (double)gv.x * wgt;
+        accb += (double)gv.y * wgt;
     }
     T.numer[k] = acc;
+    if (T.with_b) T.bspec[k] = accb;
 }
 
 }  // namespace
@@ -432,10 +494,10 @@ int launch_product(const SpecTask* d_tasks, const int64_t* d_pos0, int ntasks, i
     const RadixInfo* ri = reinterpret_cast<const RadixInfo*>(d_radix_info);
     ProfScope p(st, fp64 ? "product_f64" : "product_f32", bytes, "bytes");
     if (fp64)
-        hipLaunchKernelGGL(k_product<double>, dim3((unsigned)ceil_div(total, kThreads)),
+        hipLaunchKernelGGL(k_product<double>, dim3((unsigned)ceil_div(total, kTile)),
                            dim3(kThreads), 0, st, d_tasks, d_pos0, ntasks, total, ri);
     else
-        hipLaunchKernelGGL(k_product<float>, dim3((unsigned)ceil_div(total, kThreads)),
+        hipLaunchKernelGGL(k_product<float>, dim3((unsigned)ceil_div(total, kTile)),
                            dim3(kThreads), 0, st, d_tasks, d_pos0, ntasks, total, ri);
     NCF_CHECK_LAUNCH();
     return NCF_OK;

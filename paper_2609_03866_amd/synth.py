@@ -197,6 +197,29 @@ def c3(seed=3, n=10_000_000, K=4096):
                 kernel="gaussian", h=0.25 * mean_gap)
 
 
+def _ou_batch(rng, t, offs, taus, sds):
+    """Independent stationary OU processes for every series of a CSR batch and
+    every (tau, sd) column: exact transitions, advanced one sample index at a
+    time across all series (all columns at once)."""
+    ns = np.diff(offs)
+    order = np.argsort(-ns, kind="stable")  # longest first: active set is a prefix
+    ns_sorted = ns[order]
+    starts = offs[:-1][order]
+    taus = np.asarray(taus, dtype=np.float64)
+    sds = np.asarray(sds, dtype=np.float64)
+    ncol = taus.shape[-1]
+    out = np.empty((t.size, ncol))
+    first = starts
+    out[first] = sds[order] * rng.standard_normal((first.size, ncol))
+    for i in range(1, int(ns_sorted[0])):
+        m = int(np.searchsorted(-ns_sorted, -i, side="left"))  # series with n > i
+        idx = starts[:m] + i
+        a = np.exp(-(t[idx] - t[idx - 1])[:, None] / taus[order[:m]])
+        z = rng.standard_normal((m, ncol))
+        out[idx] = a * out[idx - 1] + sds[order[:m]] * np.sqrt(1.0 - a * a) * z
+    return out
+
+
 def c4(seed=4, n_series=10_000, nmin=100, nmax=50_000, K=256, with_err=False):
     rng = rng_for(seed)
     ns = np.round(np.exp(rng.uniform(math.log(nmin), math.log(nmax), size=n_series))).astype(
@@ -204,23 +227,22 @@ def c4(seed=4, n_series=10_000, nmin=100, nmax=50_000, K=256, with_err=False):
     offs = np.concatenate([[0], np.cumsum(ns)])
     tot = int(offs[-1])
     t = np.empty(tot)
-    x = np.empty(tot)
-    err = np.empty(tot)
+    for c in range(n_series):
+        t[offs[c]:offs[c + 1]] = seasonal_epochs(rng, int(ns[c]), phase=rng.uniform(0.0, YEAR))
+    P = rng.uniform(5.0, 50.0, size=n_series)
+    tauA = rng.uniform(2.0, 5.0, size=n_series) * P
+    phase = rng.uniform(0.0, 2.0 * np.pi, size=n_series)
     flick_tau = np.exp(np.linspace(math.log(0.5), math.log(50.0), 5))
     flick_sd = math.sqrt(0.55 ** 2 / 5.0)
-    for c in range(n_series):
-        n = int(ns[c])
-        tc = seasonal_epochs(rng, n, phase=rng.uniform(0.0, YEAR))
-        P = rng.uniform(5.0, 50.0)
-        tauA = rng.uniform(2.0, 5.0) * P
-        A = 1.0 + ou_at_times(rng, tc, tauA, 0.35)
-        sig = A * np.cos(2.0 * np.pi * tc / P + rng.uniform(0.0, 2.0 * np.pi))
-        for tf in flick_tau:
-            sig += ou_at_times(rng, tc, tf, flick_sd)
-        e = 0.01 * 10.0 ** (0.5 * rng.standard_normal(n))
-        sig += rng.standard_normal(n) * e
-        sl = slice(offs[c], offs[c + 1])
-        t[sl], x[sl], err[sl] = tc, sig, e
+    # columns: amplitude OU (tau_A, 0.35) and 5 flicker components
+    taus = np.column_stack([tauA] + [np.full(n_series, tf) for tf in flick_tau])
+    sds = np.column_stack([np.full(n_series, 0.35)] + [np.full(n_series, flick_sd)] * 5)
+    ou = _ou_batch(rng, t, offs, taus, sds)
+    sid = np.repeat(np.arange(n_series), ns)
+    A = 1.0 + ou[:, 0]
+    x = A * np.cos(2.0 * np.pi * t / P[sid] + phase[sid]) + ou[:, 1:].sum(axis=1)
+    err = 0.01 * 10.0 ** (0.5 * rng.standard_normal(tot))
+    x += rng.standard_normal(tot) * err
     return dict(kind="acf_batch", name="c4", offs=offs, t=t, x=x,
                 err=err if with_err else None, err_values=err, lags=np.arange(float(K)),
                 kernel="gaussian", h=np.full(n_series, 0.5))
