@@ -467,7 +467,11 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     // (unit-weight channel); lags whose spectral b is small against the
     // reference are re-evaluated by the direct window scan.
     const bool spec_b = spectral && !rect && J.opt.method == NCF_AUTO && !weighted;
-    const double beta = fp64 ? 1e-6 : 1e-2;
+    // Mixed: the FP32 transforms leave |dN|, |db| ~ 7e-7 b_ref on every lag, so
+    // |dc| ~ 2 * 7e-7 b_ref / b stays below 1e-5 for b >= 0.1 b_ref. FP64: the
+    // limit is the 6h truncation of the window scan, whose effect is
+    // relatively large where a lag has few pairs.
+    const double beta = fp64 ? 1e-2 : 0.1;
     // window lag rows: sorted offsets delta = eps * tau (ACF: plus lag 0)
     const double epsv = J.ccf ? -1.0 : 1.0;
     std::vector<std::pair<double, int>> rows;

@@ -266,6 +266,15 @@ __device__ __forceinline__ int64_t pos_of_freq(int64_t k, const RadixInfo& ri) {
     return p;
 }
 
+// exp(x) to ~1 FP32 ulp for any x in range: x log2(e) is split in FP64 into
+// an integer part (applied exactly) and a fraction in [0, 1) for exp2.
+__device__ __forceinline__ double exp_split(double x) {
+    const double y = x * 1.4426950408889634;
+    const double n = floor(y);
+    const float f = (float)(y - n);
+    return ldexp((double)__builtin_amdgcn_exp2f(f), (int)n);
+}
+
 template <typename R>
 __device__ __forceinline__ double lag_kernel_ft(int kern, double f, double h) {
     if (kern == NCF_GAUSSIAN) return exp(-2.0 * M_PI * M_PI * h * h * f * f);
@@ -315,8 +324,8 @@ k_product(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pos0, 
             if (T.kern == NCF_GAUSSIAN) {
                 const double a_h = 2.0 * M_PI * M_PI * h * h * (md / L) * (md / L);
                 if (sizeof(R) == 4) {
-                    f3 = c3 * (double)__expf((float)(3.0 * a_psi - a_h));
-                    f2 = c2 * (double)__expf((float)(2.0 * a_psi - a_h));
+                    f3 = c3 * exp_split(3.0 * a_psi - a_h);
+                    f2 = c2 * exp_split(2.0 * a_psi - a_h);
                 } else {
                     f3 = c3 * exp(3.0 * a_psi - a_h);
                     f2 = c2 * exp(2.0 * a_psi - a_h);

@@ -143,8 +143,11 @@ __device__ __forceinline__ void scan_lane(Acc& acc, const V& v, int ja, int jb, 
     double c = v.S(ja) + delta;
     int lo = lower_idx(v, 0, len, c - W);
     int hi = RECT ? upper_idx(v, lo, len, c + W) : lower_idx(v, lo, len, c + W);
-    // exp(-d^2/2h^2) = exp2(d^2 * k2), k2 = -log2(e) / (2 h^2)
-    const float k2 = (float)(-0.72134752044448170 * inv_h * inv_h);
+    // exp(-d^2/2h^2) = exp2(d^2 * k2), k2 = -log2(e) / (2 h^2); the argument
+    // is formed in FP64 and its integer part applied exactly, so the FP32
+    // exp2 only sees the fraction (weights keep FP32 relative accuracy even
+    // at the window edge)
+    const double k2 = -0.72134752044448170 * inv_h * inv_h;
     double s_next = v.S(ja);
     for (int j = ja; j < jb; ++j) {
         c = s_next + delta;
@@ -175,8 +178,11 @@ __device__ __forceinline__ void scan_lane(Acc& acc, const V& v, int ja, int jb, 
                             if (NUMER) Cj += e * v.A1(i + m);
                             if (WTD) Bj += e * v.A2(i + m);
                         } else {
-                            const float df = (float)dd[m];
-                            const float e = __builtin_amdgcn_exp2f(df * df * k2);
+                            const double a = dd[m] * dd[m] * k2;
+                            const double n = floor(a);
+                            const float e =
+                                __builtin_amdgcn_ldexpf(__builtin_amdgcn_exp2f((float)(a - n)),
+                                                        (int)n);
                             bf += e;
                             if (NUMER) Cj += (double)e * v.A1(i + m);
                             if (WTD) Bj += (double)e * v.A2(i + m);
