@@ -167,6 +167,29 @@ def counts_equal(gpu_n, orc_ns, pick=None):
     return bool(all(np.array_equal(g[i], orc_ns[i]) for i in range(len(orc_ns))))
 
 
+def measured_traffic(workload, kernel):
+    """HBM bytes per dispatch of `kernel` from the committed rocprofv3 counter
+    summary (calibrated FETCH_SIZE + WRITE_SIZE), or None when no summary
+    exists for this workload or the kernel's source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        tab = json.load(open(path))["workloads"][workload]
+    except (OSError, KeyError, ValueError):
+        return None
+    hits = [v for k, v in tab.items() if k == kernel or k.startswith(kernel + "_r")]
+    if not hits:
+        return None
+    for v in hits:
+        src = v.get("source")
+        if not src:
+            return None
+        cur = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()[:16]
+        if cur != v.get("source_sha"):
+            return None
+    return sum(v["bytes_per_dispatch"] for v in hits) / len(hits)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -176,6 +199,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU path")
     ap.add_argument("--oracle-series", type=int, default=64)
+    ap.add_argument("--calibrate", action="store_true",
+                    help="first run a 256 MiB device fill and three 256 MiB device copies "
+                         "(known byte counts for HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -188,6 +214,13 @@ def main():
     torch.cuda.set_device(0)
     ncf.lib()
 
+    if args.calibrate:
+        cal_src = torch.ones(64 * 1024 * 1024, device="cuda:0")
+        cal_dst = torch.empty_like(cal_src)
+        for _ in range(3):
+            cal_dst.copy_(cal_src)
+        torch.cuda.synchronize()
+        del cal_src, cal_dst
     log(f"[bench] generating workload {args.workload}")
     host = make_workload(args.workload)
     devs = [to_dev(d) for d in host]
@@ -242,7 +275,7 @@ def main():
         roof = {"bound": "alu", "achieved": work_per_launch / avg_s / 1e12,
                 "peak": VALU_PEAK / 1e12, "unit": "Tlane-op/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(args.workload, name)
     roof["kernel"] = name
     roof["avg_launch_ms"] = avg_s * 1e3
     kernels = {k: {"avg_ms": v["total_ms"] / v["launches"], "launches_per_step":
