@@ -4,7 +4,8 @@ Tolerances (|delta c| absolute per lag, b relative):
   * mixed precision, Gaussian, spectral numerator and pair count: c 1e-5,
     |delta b| <= 1e-5 b_ref (b_ref = the largest pair count of the call):
     the FP32 transforms leave an absolute error of about log2(N) eps32 b_ref
-    on every lag, and lags with b < 1e-2 b_ref are summed directly;
+    on every lag, and lags with b < 0.1 b_ref are summed directly (FP64:
+    b < 1e-2 b_ref);
   * mixed precision with the window-scan pair count: c 1e-5, b 1e-6;
   * FP64 spectral numerator and pair count: c 5e-8, b 2e-8 -- the spectral
     sums have no 6h window truncation, the oracle's do; the Gaussian mass
