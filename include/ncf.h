@@ -79,16 +79,25 @@ typedef enum { NCF_GAUSSIAN = 0, NCF_RECTANGLE = 1 } ncf_kernel_t;
 typedef enum { NCF_MIXED = 0, NCF_FP64 = 1 } ncf_precision_t;
 
 /* NCF_AUTO: Gaussian numerator by the spectral (Wiener-Khinchin + NUFFT)
- *   route (Sec. 2.6), rectangle numerator by prefix sums over the window
- *   (Algorithm "CorrSum, rectangle"); pair counts always by the window scan.
- * NCF_SPECTRAL: as AUTO for the Gaussian; for the rectangle kernel the
- *   spectral route with the box kernel's Fourier transform (diagnostic: its
- *   truncation error decays only as 1/f).
+ *   route (Sec. 2.6). Without errors the Gaussian pair count b takes the
+ *   same route with unit values, and lags whose spectral b falls below a
+ *   fraction beta of the reference (b(0) for the ACF, the largest requested
+ *   lag's b for the CCF; beta = 0.1 mixed, 0.01 FP64) are summed directly by
+ *   the window scan. With errors, b comes from the window scan. Rectangle:
+ *   numerator by prefix sums over the window (Algorithm "CorrSum,
+ *   rectangle") and exact pair counts from the window scan.
+ * NCF_SPECTRAL: Gaussian numerator by the spectral route, pair counts by the
+ *   window scan; for the rectangle kernel the spectral route with the box
+ *   kernel's Fourier transform (diagnostic: its truncation error decays only
+ *   as 1/f).
  * NCF_DIRECT: numerator and pair counts by the window scan (real-space
  *   estimator, Appendix B); with NCF_FP64 this is the plain FP64 GPU path. */
 typedef enum { NCF_AUTO = 0, NCF_SPECTRAL = 1, NCF_DIRECT = 2 } ncf_method_t;
 
 #define NCF_DEVICE_POINTERS 0x1u
+/* Plans only: replay the recorded launches one by one instead of as one
+ * captured HIP graph. */
+#define NCF_PLAN_NO_GRAPH 0x2u
 
 typedef struct {
     uint32_t struct_size; /* sizeof(ncf_options_t) */
@@ -140,6 +149,58 @@ int ncf_ccf_batch(int64_t npair, const int64_t* offx, const double* tx, const do
                   const double* ex, const int64_t* offy, const double* ty, const double* y,
                   const double* ey, int64_t K, const double* lags, int kern, const double* h,
                   double* c, double* b, int64_t* count, int* status, const ncf_options_t* opt);
+
+/* ----------------------------------------------------------------- plans
+ * A plan fixes everything of a batch call except the values: times, errors,
+ * lags, kernel, bandwidths and options. Building it runs the whole path once
+ * on placeholder values, which fixes the grids, the window tiles and the
+ * lags that the direct fallback sums (those depend on the times only), and
+ * records every kernel launch; unless NCF_PLAN_NO_GRAPH is set the launches
+ * are then captured into one HIP graph. Each execution takes new values
+ * (series 1 and, for a CCF, series 2, laid out as at build time), writes
+ * the same outputs as the batch call and needs no host-side planning. Use:
+ * Monte-Carlo or bootstrap over values at fixed sampling, repeated
+ * estimates in a serving loop (the batch scheduler of the paper's "batch
+ * processing of large numbers of light curves" use, Sec. 1).
+ *
+ *  - Arrays given to ncf_plan_acf / ncf_plan_ccf follow the batch calls
+ *    (host pointers, or device pointers with NCF_DEVICE_POINTERS; offsets
+ *    and bandwidths on the host). The plan copies times and errors into its
+ *    own device memory; the caller may free them after the call.
+ *  - The plan owns all its device memory (released by ncf_plan_destroy).
+ *    Series that fail the time checks (unsorted or non-finite times, bad h)
+ *    do not fail the build: every execution reports them in `status`.
+ *  - Executions run on options->stream of the build. Host-pointer plans
+ *    return when the outputs are written, with the first failing per-series
+ *    status. Device-pointer plans only enqueue: x, y, c, b, count and status
+ *    are device arrays, status (nullable, int32 per series) is written on the
+ *    stream, and the return value reports launch errors only.
+ *  - Executions of one plan are ordered on its stream; a plan must not be
+ *    executed from two threads at once. Pair counts and fallback lags are
+ *    those of the build, so results can differ from a batch call on the
+ *    same inputs at the rounding level of the spectral pair count. */
+typedef struct ncf_plan_s ncf_plan_t;
+
+/* Build an ACF plan for nser series (arguments as in ncf_acf_batch, without
+ * values and outputs). *out receives the plan, NULL on failure. */
+int ncf_plan_acf(int64_t nser, const int64_t* offs, const double* t, const double* err,
+                 int64_t K, const double* lags, int kern, const double* h,
+                 const ncf_options_t* opt, ncf_plan_t** out);
+
+/* Build a CCF plan for npair series pairs (arguments as in ncf_ccf_batch,
+ * without values and outputs). */
+int ncf_plan_ccf(int64_t npair, const int64_t* offx, const double* tx, const double* ex,
+                 const int64_t* offy, const double* ty, const double* ey, int64_t K,
+                 const double* lags, int kern, const double* h, const ncf_options_t* opt,
+                 ncf_plan_t** out);
+
+/* Run a plan on values x (series 1, CSR as at build) and y (series 2 of a
+ * CCF plan, NULL for an ACF plan); outputs as in the batch calls. */
+int ncf_plan_execute(ncf_plan_t* plan, const double* x, const double* y, double* c, double* b,
+                     int64_t* count, int* status);
+
+/* Release a plan (NULL is ignored). Waits for the device to finish. */
+void ncf_plan_destroy(ncf_plan_t* plan);
 
 /* Message describing the last failure on the calling thread ("" if none). */
 const char* ncf_last_error(void);

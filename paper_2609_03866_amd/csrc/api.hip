@@ -17,6 +17,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -83,9 +84,13 @@ void prof_flush_locked() {
 
 }  // namespace
 
+namespace {
+thread_local bool g_capturing = false;  // a plan's launches are being captured
+}
+
 ProfScope::ProfScope(hipStream_t s, const char* n, double w, const char* u)
     : stream(s), name(n), work(w), unit(u), ev0(nullptr) {
-    if (!g_prof_on) return;
+    if (!g_prof_on || g_capturing) return;
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return;
     (void)hipEventRecord(e, stream);
@@ -109,13 +114,30 @@ struct DevBuf {
     void* ptr = nullptr;
     size_t cap = 0;
 };
-std::mutex g_ws_mu;
-std::map<int, DevBuf> g_ws[3];  // [arena][device]
 
-int ensure_ws(int which, size_t bytes, void** out) {
-    int dev = 0;
-    NCF_TRY_HIP(hipGetDevice(&dev));
-    DevBuf& b = g_ws[which][dev];
+// Small tables (descriptors, offsets, lag lists) of one phase are laid out
+// in a pinned host buffer mirrored by a device buffer and uploaded with a
+// single copy.
+struct Staging {
+    char* h = nullptr;
+    char* d = nullptr;
+    size_t cap = 0;
+};
+
+// Device memory of a call: three workspace arenas (moments, main phase,
+// fallback) and three table stagings. One-shot calls share one set per
+// device (grown on demand, kept until ncf_release_workspace); a plan owns
+// its own set for its lifetime.
+struct Resources {
+    DevBuf ws[3];
+    Staging stage[3];
+    bool exact = false;  // plan: allocate what is asked, no growth slack
+};
+std::mutex g_ws_mu;
+std::map<int, Resources> g_res;  // one-shot calls, per device
+
+int ensure_ws(Resources& R, int which, size_t bytes, void** out) {
+    DevBuf& b = R.ws[which];
     if (b.cap < bytes) {
         if (b.ptr) {
             NCF_TRY_HIP(hipDeviceSynchronize());
@@ -123,7 +145,7 @@ int ensure_ws(int which, size_t bytes, void** out) {
             b.ptr = nullptr;
             b.cap = 0;
         }
-        size_t want = bytes + bytes / 8 + (1 << 20);
+        size_t want = R.exact ? bytes : bytes + bytes / 8 + (1 << 20);
         hipError_t e = hipMalloc(&b.ptr, want);
         if (e != hipSuccess) {
             (void)hipGetLastError();
@@ -135,6 +157,40 @@ int ensure_ws(int which, size_t bytes, void** out) {
     }
     *out = b.ptr;
     return NCF_OK;
+}
+
+int ensure_stage(Resources& R, int phase, size_t bytes, Staging** out) {
+    Staging& S = R.stage[phase];
+    if (S.cap < bytes) {
+        if (S.h) {
+            NCF_TRY_HIP(hipDeviceSynchronize());
+            NCF_TRY_HIP(hipHostFree(S.h));
+            NCF_TRY_HIP(hipFree(S.d));
+            S = Staging{};
+        }
+        const size_t want = R.exact ? bytes + 256 : 2 * bytes + 65536;
+        if (hipHostMalloc((void**)&S.h, want) != hipSuccess ||
+            hipMalloc((void**)&S.d, want) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("staging allocation of %zu bytes failed", want);
+            return NCF_E_NOMEM;
+        }
+        S.cap = want;
+    }
+    *out = &S;
+    return NCF_OK;
+}
+
+void free_resources(Resources& R) {
+    for (auto& b : R.ws) {
+        if (b.ptr) (void)hipFree(b.ptr);
+        b = DevBuf{};
+    }
+    for (auto& S : R.stage) {
+        if (S.h) (void)hipHostFree(S.h);
+        if (S.d) (void)hipFree(S.d);
+        S = Staging{};
+    }
 }
 
 // Bump allocator over a workspace: first a sizing pass (base == nullptr),
@@ -153,40 +209,6 @@ struct Arena {
 // -------------------------------------------------------------- the job
 
 constexpr int64_t kChunk = 2048;  // samples per moments chunk
-
-// Small tables (descriptors, offsets, lag lists) of one phase are laid out
-// in a pinned host buffer mirrored by a device buffer and uploaded with a
-// single copy. Cached per device and phase, grown on demand.
-struct Staging {
-    char* h = nullptr;
-    char* d = nullptr;
-    size_t cap = 0;
-};
-std::map<int, Staging> g_stage[3];
-
-int ensure_stage(int phase, size_t bytes, Staging** out) {
-    int dev = 0;
-    NCF_TRY_HIP(hipGetDevice(&dev));
-    Staging& S = g_stage[phase][dev];
-    if (S.cap < bytes) {
-        if (S.h) {
-            NCF_TRY_HIP(hipDeviceSynchronize());
-            NCF_TRY_HIP(hipHostFree(S.h));
-            NCF_TRY_HIP(hipFree(S.d));
-            S = Staging{};
-        }
-        const size_t want = 2 * bytes + 65536;
-        if (hipHostMalloc((void**)&S.h, want) != hipSuccess ||
-            hipMalloc((void**)&S.d, want) != hipSuccess) {
-            (void)hipGetLastError();
-            set_error("staging allocation of %zu bytes failed", want);
-            return NCF_E_NOMEM;
-        }
-        S.cap = want;
-    }
-    *out = &S;
-    return NCF_OK;
-}
 
 // Reserve table slots: device address for kernels, host address for filling.
 struct Tables {
@@ -233,7 +255,23 @@ struct Job {
     bool dev_ptrs = false;
     hipStream_t st = nullptr;
     SeriesSet set[2];          // ACF: set[0]; CCF: set[0] = series 1, set[1] = series 2
+    Resources* res = nullptr;  // device memory of this call
+    // plan construction: every launch reads and writes the caller arrays
+    // through this device block (else through blocks in the call's tables),
+    // and is appended to `rec` for replay
+    IoBlock* io_fixed = nullptr;
+    int32_t* io_status = nullptr;  // device status array the block points at
+    std::vector<std::function<int(hipStream_t)>>* rec = nullptr;
+    bool plan_build = false;   // statuses are those of the host checks only
 };
+
+// Enqueue a launch now and, when a plan is being built, keep it for replay.
+template <class F>
+int emit(Job& J, F f) {
+    NCF_TRY(f(J.st));
+    if (J.rec) J.rec->emplace_back(std::move(f));
+    return NCF_OK;
+}
 
 bool use_spectral(const Job& J) {
     if (J.opt.method == NCF_DIRECT) return false;
@@ -335,6 +373,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         for (int s = 0; s < S.nser; ++s) {
             SeriesDesc d{};
             d.n = S.offs[s + 1] - S.offs[s];
+            d.set = si;
             d.chunk0 = (int32_t)chunks.size();
             int32_t nc = 0;
             for (int64_t b = 0; b < d.n; b += kChunk) {
@@ -375,8 +414,9 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     SeriesStat* d_stats;
     Arena a1;
     layout1(a1, &d_cpart, &d_ctot, &d_stats);
+    Resources& R = *J.res;
     void* ws1 = nullptr;
-    NCF_TRY(ensure_ws(0, a1.off + 256, &ws1));
+    NCF_TRY(ensure_ws(R, 0, a1.off + 256, &ws1));
     a1 = Arena{(char*)ws1, 0};
     layout1(a1, &d_cpart, &d_ctot, &d_stats);
     if (!J.dev_ptrs) {
@@ -396,7 +436,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             SeriesDesc& d = sdesc[S.sd0 + s];
             const int64_t o = S.offs[s];
             d.t = S.t + o;
-            d.x = S.x + o;
+            d.xoff = o;
             d.err = S.err ? S.err + o : nullptr;
             d.v32 = S.v32 ? S.v32 + o : nullptr;
             d.v64 = S.v64 ? S.v64 + o : nullptr;
@@ -410,21 +450,27 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     {
         SeriesDesc* hs;
         Chunk* hc;
+        IoBlock* hio;
         SeriesStat* hst;
         t1.take<SeriesDesc>(nsd, &hs);
         t1.take<Chunk>(nch, &hc);
+        t1.take<IoBlock>(1, &hio);
         t1.take<SeriesStat>(nsd, &hst);
     }
-    NCF_TRY(ensure_stage(0, t1.off, &stg1));
+    NCF_TRY(ensure_stage(R, 0, t1.off, &stg1));
     t1 = Tables{stg1->h, stg1->d, 0};
     SeriesDesc* h_sd;
     Chunk* h_ch;
+    IoBlock* h_io1;
     SeriesStat* h_stats;
     SeriesDesc* d_sd = t1.take<SeriesDesc>(nsd, &h_sd);
     Chunk* d_ch = t1.take<Chunk>(nch, &h_ch);
+    IoBlock* d_io1 = t1.take<IoBlock>(1, &h_io1);
     t1.take<SeriesStat>(nsd, &h_stats);  // host landing area of the statistics
     std::memcpy(h_sd, sdesc.data(), sizeof(SeriesDesc) * nsd);
     std::memcpy(h_ch, chunks.data(), sizeof(Chunk) * nch);
+    *h_io1 = IoBlock{};
+    for (int si = 0; si < nsets; ++si) h_io1->x[si] = J.set[si].x;
     const size_t up1 = (size_t)((char*)h_stats - stg1->h);
     NCF_TRY_HIP(hipMemcpyAsync(stg1->d, stg1->h, up1, hipMemcpyHostToDevice, J.st));
     MomentsArgs ma{};
@@ -435,8 +481,9 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     ma.chunk_part = d_cpart;
     ma.chunk_tot = d_ctot;
     ma.stats = d_stats;
+    ma.io = J.io_fixed ? J.io_fixed : d_io1;
     ma.prefix = need_prefix ? 1 : 0;
-    NCF_TRY(launch_moments(ma, J.st));
+    NCF_TRY(emit(J, [ma](hipStream_t s) { return launch_moments(ma, s); }));
     NCF_TRY_HIP(hipMemcpyAsync(h_stats, d_stats, sizeof(SeriesStat) * nsd, hipMemcpyDeviceToHost,
                                J.st));
     NCF_TRY_HIP(hipStreamSynchronize(J.st));
@@ -457,7 +504,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     }
 
     // standardization (+ prefix sums), all series in one launch
-    NCF_TRY(launch_standardize(ma, J.st));
+    NCF_TRY(emit(J, [ma](hipStream_t s) { return launch_standardize(ma, s); }));
 
     // ------------------------------------------------ phase 2 planning (host)
     const int64_t K = J.K;
@@ -692,7 +739,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     Arena a2;
     layout2(a2);
     void* ws2 = nullptr;
-    NCF_TRY(ensure_ws(1, a2.off + 256, &ws2));
+    NCF_TRY(ensure_ws(R, 1, a2.off + 256, &ws2));
     a2 = Arena{(char*)ws2, 0};
     layout2(a2);
 
@@ -728,7 +775,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     Tables t2;
     take2(t2);
     Staging* stg2 = nullptr;
-    NCF_TRY(ensure_stage(1, t2.off, &stg2));
+    NCF_TRY(ensure_stage(R, 1, t2.off, &stg2));
     t2 = Tables{stg2->h, stg2->d, 0};
     take2(t2);
 
@@ -839,23 +886,48 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     NCF_TRY_HIP(hipMemcpyAsync(stg2->d, stg2->h, t2.off, hipMemcpyHostToDevice, J.st));
 
     // ------------------------------------------------ A7 window scan
-    NCF_TRY(launch_window(dT.wt, dT.item0, ntw, W1.nitems, wflags, W1.cap, W1.jmax, J.st,
-                          W1.work));
-    NCF_TRY(launch_window_reduce(dT.wt, ntw, W1.total_rows, dT.wk0, dT.r0, W1.nred1, wflags,
-                                 J.st));
+    {
+        const WinTask* wt = dT.wt;
+        const int64_t *it0 = dT.item0, *wk0 = dT.wk0, *r0 = dT.r0;
+        const int64_t nitems = W1.nitems, rows = W1.total_rows, nred1 = W1.nred1;
+        const int cap = W1.cap, jmax = W1.jmax;
+        const double work = W1.work;
+        if (ntw > 0) {
+            NCF_TRY(emit(J, [=](hipStream_t s) {
+                return launch_window(wt, it0, ntw, nitems, wflags, cap, jmax, s, work);
+            }));
+            NCF_TRY(emit(J, [=](hipStream_t s) {
+                return launch_window_reduce(wt, ntw, rows, wk0, r0, nred1, wflags, s);
+            }));
+        }
+    }
 
     // ------------------------------------------------ A2-A6 spectral route
     if (nts > 0) {
-        NCF_TRY(launch_spread(dT.st, dT.tile0, nts, ntiles, 4096, fp64, J.st, spread_bytes));
-        for (size_t q = 0; q < groups.size(); ++q)
-            NCF_TRY(fft_exec(plans[splans[groups[q].first].g.N], dT.gfwd + fwd_groups[q].first,
-                             fwd_groups[q].second, +1, fp64, J.st));
-        NCF_TRY(launch_product(dT.st, dT.pos0, nts, total_pos, (const int64_t*)dT.rinfo, fp64,
-                               J.st, (two_grids ? 3.0 : 2.0) * total_pos * csz));
-        for (auto& gq : groups)
-            NCF_TRY(fft_exec(plans[splans[gq.first].g.N], dT.ginv + gq.first, gq.second, -1,
-                             fp64, J.st));
-        NCF_TRY(launch_interp(dT.st, nts, dT.sk0, (int64_t)nts * Keval, fp64, J.st));
+        const SpecTask* stk = dT.st;
+        const int64_t *tile0 = dT.tile0, *pos0 = dT.pos0, *sk0 = dT.sk0;
+        const int64_t* rinfo = (const int64_t*)dT.rinfo;
+        const double pbytes = (two_grids ? 3.0 : 2.0) * total_pos * csz;
+        const int64_t nkeval = (int64_t)nts * Keval;
+        NCF_TRY(emit(J, [=](hipStream_t s) {
+            return launch_spread(stk, tile0, nts, ntiles, 4096, fp64, s, spread_bytes);
+        }));
+        for (size_t q = 0; q < groups.size(); ++q) {
+            const FftPlan fp = plans[splans[groups[q].first].g.N];
+            void* const* gp = dT.gfwd + fwd_groups[q].first;
+            const int cnt = fwd_groups[q].second;
+            NCF_TRY(emit(J, [=](hipStream_t s) { return fft_exec(fp, gp, cnt, +1, fp64, s); }));
+        }
+        NCF_TRY(emit(J, [=](hipStream_t s) {
+            return launch_product(stk, pos0, nts, total_pos, rinfo, fp64, s, pbytes);
+        }));
+        for (auto& gq : groups) {
+            const FftPlan fp = plans[splans[gq.first].g.N];
+            void* const* gp = dT.ginv + gq.first;
+            const int cnt = gq.second;
+            NCF_TRY(emit(J, [=](hipStream_t s) { return fft_exec(fp, gp, cnt, -1, fp64, s); }));
+        }
+        NCF_TRY(emit(J, [=](hipStream_t s) { return launch_interp(stk, nts, sk0, nkeval, fp64, s); }));
     }
 
     // ------------------------------------------------ direct fallback (spectral b)
@@ -910,7 +982,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     layout3(a3);
     if (ntw2 > 0) {
         void* ws3 = nullptr;
-        NCF_TRY(ensure_ws(2, a3.off + 256, &ws3));
+        NCF_TRY(ensure_ws(R, 2, a3.off + 256, &ws3));
         a3 = Arena{(char*)ws3, 0};
         layout3(a3);
     }
@@ -922,6 +994,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         int32_t* perm;
         NormTask* nt;
         int32_t* status;
+        IoBlock* io;
     } dU{}, hU{};
     size_t ndl2 = 0;
     for (auto& P : W2.plans) ndl2 += P.dl.size();
@@ -936,11 +1009,12 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         dU.perm = tb.take<int32_t>(K, &hU.perm);
         dU.nt = tb.take<NormTask>(J.nprob, &hU.nt);
         dU.status = tb.take<int32_t>(J.nprob, &hU.status);
+        dU.io = tb.take<IoBlock>(1, &hU.io);
     };
     Tables t3;
     take3(t3);
     Staging* stg3 = nullptr;
-    NCF_TRY(ensure_stage(2, t3.off, &stg3));
+    NCF_TRY(ensure_stage(R, 2, t3.off, &stg3));
     t3 = Tables{stg3->h, stg3->d, 0};
     take3(t3);
     std::vector<int> fb_task(J.nprob, -1);
@@ -985,10 +1059,10 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             T.weighted = weighted ? 1 : 0;
             T.is_rect = rect ? 1 : 0;
             T.beta = beta;
-            T.status = dU.status + p;
-            T.c = d_c + p * K;
-            T.b = d_b + p * K;
-            T.count = d_cnt ? d_cnt + p * K : nullptr;
+            T.out_off = p * K;
+            T.index = p;
+            T.st0 = d_stats + J.set[0].sd0 + p;
+            T.st1 = J.ccf ? d_stats + J.set[1].sd0 + p : nullptr;
             hU.status[p] = pstat[p];
             if (pstat[p] == NCF_OK) {
                 if (main_t[p] >= 0) T.wsums = W1.wt[main_t[p]].sums;
@@ -1009,23 +1083,43 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
                 }
             } else {
                 T.skip = 1;  // outputs: c = NaN, b = 0, count = 0
+                T.skip_status = pstat[p];
             }
             hU.nt[p] = T;
         }
     }
+    // caller arrays of the normalization (one-shot calls)
+    hU.io->x[0] = J.set[0].x;
+    hU.io->x[1] = J.ccf ? J.set[1].x : nullptr;
+    hU.io->c = d_c;
+    hU.io->b = d_b;
+    hU.io->count = d_cnt;
+    hU.io->status = dU.status;
     NCF_TRY_HIP(hipMemcpyAsync(stg3->d, stg3->h, t3.off, hipMemcpyHostToDevice, J.st));
     if (ntw2 > 0) {
-        NCF_TRY(launch_window(dU.wt, dU.item0, ntw2, W2.nitems, wflags2, W2.cap, W2.jmax, J.st,
-                              W2.work));
-        NCF_TRY(launch_window_reduce(dU.wt, ntw2, W2.total_rows, dU.wk0, dU.r0, W2.nred1,
-                                     wflags2, J.st));
+        const WinTask* wt = dU.wt;
+        const int64_t *it0 = dU.item0, *wk0 = dU.wk0, *r0 = dU.r0;
+        const int64_t nitems = W2.nitems, rows = W2.total_rows, nred1 = W2.nred1;
+        const int cap = W2.cap, jmax = W2.jmax;
+        const double work = W2.work;
+        NCF_TRY(emit(J, [=](hipStream_t s) {
+            return launch_window(wt, it0, ntw2, nitems, wflags2, cap, jmax, s, work);
+        }));
+        NCF_TRY(emit(J, [=](hipStream_t s) {
+            return launch_window_reduce(wt, ntw2, rows, wk0, r0, nred1, wflags2, s);
+        }));
     }
 
     // ------------------------------------------------ A8 normalization, outputs
-    NCF_TRY(launch_normalize(dU.nt, (int)J.nprob, J.nprob * K, nullptr, J.st));
+    {
+        const NormTask* nt = dU.nt;
+        const int np = (int)J.nprob;
+        const IoBlock* io = J.io_fixed ? J.io_fixed : dU.io;
+        NCF_TRY(emit(J, [=](hipStream_t s) { return launch_normalize(nt, np, io, s); }));
+    }
     int32_t* h_fstat = hU.status;  // pinned; its upload was enqueued before
-    NCF_TRY_HIP(hipMemcpyAsync(h_fstat, dU.status, sizeof(int32_t) * J.nprob,
-                               hipMemcpyDeviceToHost, J.st));
+    NCF_TRY_HIP(hipMemcpyAsync(h_fstat, J.io_fixed ? J.io_status : dU.status,
+                               sizeof(int32_t) * J.nprob, hipMemcpyDeviceToHost, J.st));
     if (!J.dev_ptrs && K > 0) {
         NCF_TRY_HIP(hipMemcpyAsync(J.c, d_c, sizeof(double) * J.nprob * K, hipMemcpyDeviceToHost,
                                    J.st));
@@ -1039,6 +1133,11 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     if (g_prof_on) {
         std::lock_guard<std::mutex> lock(g_prof_mu);
         prof_flush_locked();
+    }
+    if (J.plan_build) {  // placeholder values: only the host checks count
+        if (J.status)
+            for (int64_t p = 0; p < J.nprob; ++p) J.status[p] = pstat[p];
+        return NCF_OK;
     }
     int first = NCF_OK;
     for (int64_t p = 0; p < J.nprob; ++p) {
@@ -1154,14 +1253,50 @@ void ncf_release_workspace(void) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return;
     (void)hipDeviceSynchronize();
-    for (int w = 0; w < 3; ++w) {
-        auto it = g_ws[w].find(dev);
-        if (it != g_ws[w].end() && it->second.ptr) {
-            (void)hipFree(it->second.ptr);
-            it->second = DevBuf{};
-        }
-    }
+    auto it = g_res.find(dev);
+    if (it != g_res.end()) free_resources(it->second);
 }
+
+}  // extern "C"
+
+namespace ncf {
+namespace {
+
+// Common set-up of an ACF or CCF job (arguments already checked).
+int setup_job(Job& J, bool ccf, int64_t nprob, const int64_t* off0, const int64_t* off1,
+              int64_t tot0, int64_t tot1, int kern, const double* h, int64_t K,
+              const double* lags) {
+    J.ccf = ccf;
+    J.nprob = nprob;
+    J.kern = kern;
+    J.h.assign(h, h + nprob);
+    J.dev_ptrs = (J.opt.flags & NCF_DEVICE_POINTERS) != 0;
+    J.st = (hipStream_t)J.opt.stream;
+    NCF_TRY(load_lags(J, K, lags));
+    J.set[0].ntot = tot0;
+    J.set[0].nser = (int)nprob;
+    J.set[0].offs.assign(off0, off0 + nprob + 1);
+    if (ccf) {
+        J.set[1].ntot = tot1;
+        J.set[1].nser = (int)nprob;
+        J.set[1].offs.assign(off1, off1 + nprob + 1);
+    }
+    return NCF_OK;
+}
+
+Resources* device_resources() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return &g_res[dev];
+}
+
+}  // namespace
+}  // namespace ncf
+
+extern "C" {
 
 int ncf_acf_batch(int64_t nser, const int64_t* offs, const double* t, const double* x,
                   const double* err, int64_t K, const double* lags, int kern, const double* h,
@@ -1176,20 +1311,16 @@ int ncf_acf_batch(int64_t nser, const int64_t* offs, const double* t, const doub
     int64_t total = 0;
     NCF_TRY(check_offs(offs, nser, &total));
     std::lock_guard<std::mutex> lock(g_ws_mu);
-    J.ccf = false;
-    J.nprob = nser;
-    J.kern = kern;
-    J.h.assign(h, h + nser);
     J.c = c;
     J.b = b;
     J.count = count;
     J.status = status;
-    J.dev_ptrs = (J.opt.flags & NCF_DEVICE_POINTERS) != 0;
-    J.st = (hipStream_t)J.opt.stream;
-    NCF_TRY(load_lags(J, K, lags));
-    J.set[0].ntot = total;
-    J.set[0].nser = (int)nser;
-    J.set[0].offs.assign(offs, offs + nser + 1);
+    NCF_TRY(setup_job(J, false, nser, offs, nullptr, total, 0, kern, h, K, lags));
+    J.res = device_resources();
+    if (!J.res) {
+        set_error("no current HIP device");
+        return NCF_E_DEVICE;
+    }
     const double* tin[2] = {t, nullptr};
     const double* xin[2] = {x, nullptr};
     const double* ein[2] = {err, nullptr};
@@ -1211,23 +1342,16 @@ int ncf_ccf_batch(int64_t npair, const int64_t* offx, const double* tx, const do
     NCF_TRY(check_offs(offx, npair, &totx));
     NCF_TRY(check_offs(offy, npair, &toty));
     std::lock_guard<std::mutex> lock(g_ws_mu);
-    J.ccf = true;
-    J.nprob = npair;
-    J.kern = kern;
-    J.h.assign(h, h + npair);
     J.c = c;
     J.b = b;
     J.count = count;
     J.status = status;
-    J.dev_ptrs = (J.opt.flags & NCF_DEVICE_POINTERS) != 0;
-    J.st = (hipStream_t)J.opt.stream;
-    NCF_TRY(load_lags(J, K, lags));
-    J.set[0].ntot = totx;
-    J.set[0].nser = (int)npair;
-    J.set[0].offs.assign(offx, offx + npair + 1);
-    J.set[1].ntot = toty;
-    J.set[1].nser = (int)npair;
-    J.set[1].offs.assign(offy, offy + npair + 1);
+    NCF_TRY(setup_job(J, true, npair, offx, offy, totx, toty, kern, h, K, lags));
+    J.res = device_resources();
+    if (!J.res) {
+        set_error("no current HIP device");
+        return NCF_E_DEVICE;
+    }
     const double* tin[2] = {tx, ty};
     const double* xin[2] = {x, y};
     const double* ein[2] = {ex, ey};
@@ -1256,6 +1380,305 @@ int ncf_ccf(int64_t nx, const double* tx, const double* x, const double* ex, int
     return ncf_ccf_batch(1, ox, tx, x, ex, oy, ty, y, ey, K, lags, kern, &h, c, b, count,
                          nullptr, opt);
 }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ plans
+
+struct ncf_plan_s {
+    int device = 0;
+    bool ccf = false, dev_ptrs = false, use_graph = true;
+    int64_t nprob = 0, K = 0;
+    int64_t ntot[2] = {0, 0};
+    hipStream_t st = nullptr;
+    ncf::Resources res;
+    std::vector<std::function<int(hipStream_t)>> rec;  // the recorded launches
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    // plan-owned device memory
+    ncf::IoBlock* io = nullptr;
+    int32_t* status = nullptr;           // [nprob]
+    double* tcopy[2] = {nullptr, nullptr};
+    double* ecopy[2] = {nullptr, nullptr};
+    double* xbuf[2] = {nullptr, nullptr};  // values (host-pointer plans)
+    double* cbuf = nullptr;               // outputs (host-pointer plans, and the build)
+    double* bbuf = nullptr;
+    int64_t* nbuf = nullptr;
+    std::vector<int32_t> hstatus;          // host statuses (host-pointer plans)
+};
+
+namespace ncf {
+namespace {
+
+void plan_free(ncf_plan_s* P) {
+    if (!P) return;
+    (void)hipDeviceSynchronize();
+    if (P->exec) (void)hipGraphExecDestroy(P->exec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    free_resources(P->res);
+    void* bufs[] = {P->io,       P->status,   P->tcopy[0], P->tcopy[1], P->ecopy[0],
+                    P->ecopy[1], P->xbuf[0], P->xbuf[1], P->cbuf,     P->bbuf,
+                    P->nbuf};
+    for (void* q : bufs)
+        if (q) (void)hipFree(q);
+    delete P;
+}
+
+template <typename T>
+int dev_alloc(T** p, size_t n) {
+    if (hipMalloc((void**)p, sizeof(T) * std::max<size_t>(n, 1)) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        set_error("plan allocation of %zu bytes failed", sizeof(T) * n);
+        return NCF_E_NOMEM;
+    }
+    return NCF_OK;
+}
+
+// Build a plan: copy times and errors, run the whole path once on
+// placeholder values (recording every launch), then capture the launches
+// into a graph.
+int plan_build(ncf_plan_s* P, Job& J, const double* const* tin, const double* const* ein) {
+    const int nsets = J.ccf ? 2 : 1;
+    NCF_TRY_HIP(hipGetDevice(&P->device));
+    P->ccf = J.ccf;
+    P->dev_ptrs = J.dev_ptrs;
+    P->use_graph = (J.opt.flags & NCF_PLAN_NO_GRAPH) == 0;
+    P->nprob = J.nprob;
+    P->K = J.K;
+    P->st = J.st;
+    P->res.exact = true;
+    const hipMemcpyKind kind = J.dev_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    int64_t nmax = 0;
+    for (int si = 0; si < nsets; ++si) {
+        const int64_t n = J.set[si].ntot;
+        P->ntot[si] = n;
+        nmax = std::max(nmax, n);
+        NCF_TRY(dev_alloc(&P->tcopy[si], n));
+        NCF_TRY_HIP(hipMemcpyAsync(P->tcopy[si], tin[si], sizeof(double) * n, kind, J.st));
+        if (ein[si]) {
+            NCF_TRY(dev_alloc(&P->ecopy[si], n));
+            NCF_TRY_HIP(hipMemcpyAsync(P->ecopy[si], ein[si], sizeof(double) * n, kind, J.st));
+        }
+        if (!J.dev_ptrs) NCF_TRY(dev_alloc(&P->xbuf[si], n));
+    }
+    const int64_t nout = std::max<int64_t>(J.nprob * J.K, 1);
+    NCF_TRY(dev_alloc(&P->io, 1));
+    NCF_TRY(dev_alloc(&P->status, J.nprob));
+    NCF_TRY(dev_alloc(&P->cbuf, nout));
+    NCF_TRY(dev_alloc(&P->bbuf, nout));
+    NCF_TRY(dev_alloc(&P->nbuf, nout));
+    P->hstatus.assign(J.nprob, NCF_OK);
+
+    // placeholder values: finite, unit variance (the plan's pair counts and
+    // fallback lags depend on the times only)
+    double* dummy = nullptr;
+    NCF_TRY(dev_alloc(&dummy, nmax));
+    struct Guard {
+        double* p;
+        ~Guard() {
+            if (p) {
+                (void)hipDeviceSynchronize();
+                (void)hipFree(p);
+            }
+        }
+    } guard{dummy};
+    NCF_TRY(launch_fill_alternating(dummy, nmax, J.st));
+    IoBlock io{};
+    io.x[0] = dummy;
+    io.x[1] = J.ccf ? dummy : nullptr;
+    io.c = P->cbuf;
+    io.b = P->bbuf;
+    io.count = P->nbuf;
+    io.status = P->status;
+    NCF_TRY(launch_set_io(P->io, io, J.st));
+
+    Job B = J;  // the build run: device pointers throughout
+    B.dev_ptrs = true;
+    B.c = P->cbuf;
+    B.b = P->bbuf;
+    B.count = P->nbuf;
+    B.status = nullptr;
+    B.res = &P->res;
+    B.io_fixed = P->io;
+    B.io_status = P->status;
+    B.rec = &P->rec;
+    B.plan_build = true;
+    const double* tdev[2] = {P->tcopy[0], P->tcopy[1]};
+    const double* xdev[2] = {dummy, J.ccf ? dummy : nullptr};
+    const double* edev[2] = {P->ecopy[0], P->ecopy[1]};
+    NCF_TRY(run_job(B, tdev, xdev, edev));
+
+    if (P->use_graph) {
+        hipStream_t cs = nullptr;
+        NCF_TRY_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        int rc = NCF_OK;
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            g_capturing = true;
+            for (auto& f : P->rec) {
+                rc = f(cs);
+                if (rc != NCF_OK) break;
+            }
+            g_capturing = false;
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(cs, &g);
+            if (e == hipSuccess && rc == NCF_OK) {
+                P->graph = g;
+                e = hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0);
+            } else if (g) {
+                (void)hipGraphDestroy(g);
+            }
+        }
+        (void)hipStreamDestroy(cs);
+        if (rc != NCF_OK) return rc;
+        if (e != hipSuccess) {
+            set_error("graph capture of the plan failed: %s", hipGetErrorString(e));
+            (void)hipGetLastError();
+            return NCF_E_DEVICE;
+        }
+    }
+    return NCF_OK;
+}
+
+int plan_status_error(const int32_t* st, int64_t n) {
+    for (int64_t p = 0; p < n; ++p)
+        if (st[p] != NCF_OK) {
+            set_error("series %lld failed with status %d", (long long)p, st[p]);
+            return st[p];
+        }
+    return NCF_OK;
+}
+
+}  // namespace
+}  // namespace ncf
+
+extern "C" {
+
+int ncf_plan_acf(int64_t nser, const int64_t* offs, const double* t, const double* err,
+                 int64_t K, const double* lags, int kern, const double* h,
+                 const ncf_options_t* opt, ncf_plan_t** out) {
+    clear_error();
+    if (!out) {
+        set_error("null plan pointer");
+        return NCF_E_INVALID_ARG;
+    }
+    *out = nullptr;
+    Job J;
+    NCF_TRY(common_checks(opt, &J.opt, kern));
+    if (nser <= 0 || !t || !h) {
+        set_error("null argument or nser <= 0");
+        return NCF_E_INVALID_ARG;
+    }
+    int64_t total = 0;
+    NCF_TRY(check_offs(offs, nser, &total));
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    NCF_TRY(setup_job(J, false, nser, offs, nullptr, total, 0, kern, h, K, lags));
+    ncf_plan_s* P = new ncf_plan_s;
+    const double* tin[2] = {t, nullptr};
+    const double* ein[2] = {err, nullptr};
+    const int rc = plan_build(P, J, tin, ein);
+    if (rc != NCF_OK) {
+        plan_free(P);
+        return rc;
+    }
+    *out = P;
+    return NCF_OK;
+}
+
+int ncf_plan_ccf(int64_t npair, const int64_t* offx, const double* tx, const double* ex,
+                 const int64_t* offy, const double* ty, const double* ey, int64_t K,
+                 const double* lags, int kern, const double* h, const ncf_options_t* opt,
+                 ncf_plan_t** out) {
+    clear_error();
+    if (!out) {
+        set_error("null plan pointer");
+        return NCF_E_INVALID_ARG;
+    }
+    *out = nullptr;
+    Job J;
+    NCF_TRY(common_checks(opt, &J.opt, kern));
+    if (npair <= 0 || !tx || !ty || !h) {
+        set_error("null argument or npair <= 0");
+        return NCF_E_INVALID_ARG;
+    }
+    int64_t totx = 0, toty = 0;
+    NCF_TRY(check_offs(offx, npair, &totx));
+    NCF_TRY(check_offs(offy, npair, &toty));
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    NCF_TRY(setup_job(J, true, npair, offx, offy, totx, toty, kern, h, K, lags));
+    ncf_plan_s* P = new ncf_plan_s;
+    const double* tin[2] = {tx, ty};
+    const double* ein[2] = {ex, ey};
+    const int rc = plan_build(P, J, tin, ein);
+    if (rc != NCF_OK) {
+        plan_free(P);
+        return rc;
+    }
+    *out = P;
+    return NCF_OK;
+}
+
+int ncf_plan_execute(ncf_plan_t* P, const double* x, const double* y, double* c, double* b,
+                     int64_t* count, int* status) {
+    clear_error();
+    if (!P || !x || (P->ccf && !y) || (P->K > 0 && (!c || !b))) {
+        set_error("null argument");
+        return NCF_E_INVALID_ARG;
+    }
+    int dev = 0;
+    NCF_TRY_HIP(hipGetDevice(&dev));
+    if (dev != P->device) {
+        set_error("plan belongs to device %d, current device is %d", P->device, dev);
+        return NCF_E_INVALID_ARG;
+    }
+    const hipStream_t st = P->st;
+    IoBlock io{};
+    if (P->dev_ptrs) {
+        io.x[0] = x;
+        io.x[1] = P->ccf ? y : nullptr;
+        io.c = c;
+        io.b = b;
+        io.count = count;
+        io.status = status ? (int32_t*)status : P->status;
+    } else {
+        NCF_TRY_HIP(hipMemcpyAsync(P->xbuf[0], x, sizeof(double) * P->ntot[0],
+                                   hipMemcpyHostToDevice, st));
+        if (P->ccf)
+            NCF_TRY_HIP(hipMemcpyAsync(P->xbuf[1], y, sizeof(double) * P->ntot[1],
+                                       hipMemcpyHostToDevice, st));
+        io.x[0] = P->xbuf[0];
+        io.x[1] = P->xbuf[1];
+        io.c = P->cbuf;
+        io.b = P->bbuf;
+        io.count = count ? P->nbuf : nullptr;
+        io.status = P->status;
+    }
+    NCF_TRY(launch_set_io(P->io, io, st));
+    if (P->exec) {
+        ProfScope ps(st, "plan_graph", 0.0, "launches");
+        NCF_TRY_HIP(hipGraphLaunch(P->exec, st));
+    } else {
+        for (auto& f : P->rec) NCF_TRY(f(st));
+    }
+    if (P->dev_ptrs) return NCF_OK;
+    const int64_t nout = P->nprob * P->K;
+    if (nout > 0) {
+        NCF_TRY_HIP(hipMemcpyAsync(c, P->cbuf, sizeof(double) * nout, hipMemcpyDeviceToHost, st));
+        NCF_TRY_HIP(hipMemcpyAsync(b, P->bbuf, sizeof(double) * nout, hipMemcpyDeviceToHost, st));
+        if (count)
+            NCF_TRY_HIP(
+                hipMemcpyAsync(count, P->nbuf, sizeof(int64_t) * nout, hipMemcpyDeviceToHost, st));
+    }
+    NCF_TRY_HIP(hipMemcpyAsync(P->hstatus.data(), P->status, sizeof(int32_t) * P->nprob,
+                               hipMemcpyDeviceToHost, st));
+    NCF_TRY_HIP(hipStreamSynchronize(st));
+    if (status)
+        for (int64_t p = 0; p < P->nprob; ++p) status[p] = P->hstatus[p];
+    return plan_status_error(P->hstatus.data(), P->nprob);
+}
+
+void ncf_plan_destroy(ncf_plan_t* P) { plan_free(P); }
 
 // ------------------------------------------------------------- diagnostics
 

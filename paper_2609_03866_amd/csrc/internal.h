@@ -87,10 +87,25 @@ __device__ __forceinline__ int64_t wave_search(const T* a, int64_t n, T key, boo
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// ------------------------------------------------------------- call I/O
+// The caller's value arrays and output arrays of one call. Kernels reach
+// them through this device block, so a recorded launch sequence (a plan) can
+// run again on other buffers once the block is rewritten.
+struct IoBlock {
+    const double* x[2];  // values of set 0 and set 1, concatenated over series
+    double* c;           // [problems][K]
+    double* b;           // [problems][K]
+    int64_t* count;      // [problems][K] or null
+    int32_t* status;     // [problems]
+};
+// Write `v` into the device block `dst` on `st` (a one-thread kernel, so the
+// values are taken at enqueue time).
+int launch_set_io(IoBlock* dst, const IoBlock& v, hipStream_t st);
+
 // ----------------------------------------------------------- A1 moments
 struct SeriesDesc {
-    const double* t;  // times, values, optional errors of this series
-    const double* x;
+    const double* t;  // times and optional errors of this series
+    int64_t xoff;     // first value of this series in IoBlock::x[set]
     const double* err;
     float* v32;       // outputs, each may be null: w (x - mean)/sd in FP32 / FP64,
     double* v64;      // weights, and FP64 prefix sums of v and w (n + 1 entries)
@@ -100,6 +115,8 @@ struct SeriesDesc {
     int64_t n;        // samples
     int32_t chunk0;   // first chunk of the series
     int32_t nchunk;   // chunks of the series
+    int32_t set;      // value array of the series (IoBlock::x index)
+    int32_t pad;
 };
 
 struct Chunk {
@@ -122,12 +139,15 @@ struct MomentsArgs {
     double* chunk_part;      // 4 doubles per chunk: sw, mean, M2, flags
     double* chunk_tot;       // 2 doubles per chunk (v, w) totals for the prefix pass
     SeriesStat* stats;       // nseries
+    const IoBlock* io;       // value arrays
     int32_t prefix;          // any series has prefix outputs
     int32_t pad;
 };
 
 int launch_moments(const MomentsArgs& a, hipStream_t st);
 int launch_standardize(const MomentsArgs& a, hipStream_t st);
+// Fill p[0..n) with alternating +1, -1 (finite values of unit variance).
+int launch_fill_alternating(double* p, int64_t n, hipStream_t st);
 
 // ------------------------------------------------------- A7 window scan
 enum WinFlags : uint32_t {
@@ -257,14 +277,14 @@ struct NormTask {
     int64_t nscale_part;
     int32_t weighted;
     int32_t is_rect;
-    int32_t skip;         // problem failed validation: write nothing
-    int32_t pad;
-    int32_t* status;      // per-task status (device)
-    double* c;            // K outputs
-    double* b;
-    int64_t* count;       // may be null
+    int32_t skip;         // problem failed the host checks: outputs NaN / 0 / 0
+    int32_t skip_status;  // its status
+    const SeriesStat* st0;  // device statistics of the problem's series (a failed
+    const SeriesStat* st1;  // value check there also gives NaN / 0 / 0); st1 CCF only
+    int64_t out_off;      // first output of this problem in IoBlock::c, b, count
+    int64_t index;        // problem index (IoBlock::status)
 };
-int launch_normalize(const NormTask* d_tasks, int ntasks, int64_t total_k, const int64_t* d_k0,
-                     hipStream_t st);
+// Every task writes its outputs and its status through `io`.
+int launch_normalize(const NormTask* d_tasks, int ntasks, const IoBlock* io, hipStream_t st);
 
 }  // namespace ncf

@@ -38,11 +38,12 @@ k_chunk_moments(MomentsArgs a) {
     __shared__ double sh[kThreads];
     const Chunk ch = a.chunks[blockIdx.x];
     const SeriesDesc sd = a.series[ch.series];
+    const double* X = a.io->x[sd.set] + sd.xoff;
     const int tid = threadIdx.x;
     double sw = 0.0, swx = 0.0;
     int bad = 0, unsorted = 0;
     for (int64_t i = ch.begin + tid; i < ch.end; i += kThreads) {
-        double ti = sd.t[i], xi = sd.x[i];
+        double ti = sd.t[i], xi = X[i];
         double wi = 1.0;
         if (sd.err) {
             double e = sd.err[i];
@@ -64,7 +65,7 @@ k_chunk_moments(MomentsArgs a) {
             double e = sd.err[i];
             wi = 1.0 / (e * e);
         }
-        double d = sd.x[i] - mean;
+        double d = X[i] - mean;
         m2 += wi * d * d;
     }
     double M2 = block_sum(m2, sh);
@@ -159,6 +160,7 @@ k_standardize(MomentsArgs a) {
     const Chunk ch = a.chunks[blockIdx.x];
     const SeriesDesc sd = a.series[ch.series];
     const SeriesStat st = a.stats[ch.series];
+    const double* X = a.io->x[sd.set] + sd.xoff;
     const int tid = threadIdx.x;
     const bool ok = st.status == NCF_OK;
     const double mean = st.mean;
@@ -175,7 +177,7 @@ k_standardize(MomentsArgs a) {
                 double e = sd.err[i];
                 w = 1.0 / (e * e);
             }
-            v = ok ? w * ((sd.x[i] - mean) * inv_sd) : 0.0;
+            v = ok ? w * ((X[i] - mean) * inv_sd) : 0.0;
             if (sd.v32) sd.v32[i] = (float)v;
             if (sd.v64) sd.v64[i] = v;
             if (sd.w64) sd.w64[i] = w;
@@ -270,7 +272,21 @@ k_prefix_add(MomentsArgs a) {
     }
 }
 
+__global__ void __launch_bounds__(kThreads)
+k_fill_alternating(double* __restrict__ p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) p[i] = (i & 1) ? -1.0 : 1.0;
+}
+
 }  // namespace
+
+int launch_fill_alternating(double* p, int64_t n, hipStream_t st) {
+    if (n <= 0) return NCF_OK;
+    hipLaunchKernelGGL(k_fill_alternating, dim3((unsigned)ceil_div(n, kThreads)), dim3(kThreads),
+                       0, st, p, n);
+    NCF_CHECK_LAUNCH();
+    return NCF_OK;
+}
 
 int launch_moments(const MomentsArgs& a, hipStream_t st) {
     if (a.nchunks > 0) {

@@ -23,18 +23,27 @@ __device__ __forceinline__ double fl(double v) { return v > kFloor ? v : kFloor;
 //    numerator but window b, the window's direct numerator at lags whose
 //    b < beta * b_ref).
 __global__ void __launch_bounds__(kThreads)
-k_normalize(const NormTask* __restrict__ tasks) {
+k_normalize(const NormTask* __restrict__ tasks, const IoBlock* __restrict__ io) {
     __shared__ double red[4][kThreads];
     __shared__ double redm[kThreads];
     __shared__ double sh_scale, sh_bref;
     const NormTask& T = tasks[blockIdx.x];
     const int tid = threadIdx.x;
-    if (T.skip) {  // the problem failed validation
+    double* const out_c = io->c + T.out_off;
+    double* const out_b = io->b + T.out_off;
+    int64_t* const out_n = io->count ? io->count + T.out_off : nullptr;
+    int32_t* const out_st = io->status + T.index;
+    // failed host checks, or failed value checks of this call's moments
+    int32_t fail = T.skip ? T.skip_status : NCF_OK;
+    if (fail == NCF_OK && T.st0 && T.st0->status != NCF_OK) fail = T.st0->status;
+    if (fail == NCF_OK && T.st1 && T.st1->status != NCF_OK) fail = T.st1->status;
+    if (fail != NCF_OK) {
         for (int k = tid; k < T.K; k += kThreads) {
-            T.c[k] = NAN;
-            T.b[k] = 0.0;
-            if (T.count) T.count[k] = 0;
+            out_c[k] = NAN;
+            out_b[k] = 0.0;
+            if (out_n) out_n[k] = 0;
         }
+        if (tid == 0) *out_st = fail;
         return;
     }
     const int bq = T.weighted ? 1 : 2;  // which window sum is the denominator B
@@ -102,7 +111,7 @@ k_normalize(const NormTask* __restrict__ tasks) {
             scale = (r0 > 0.0 && isfinite(r0)) ? r0 : NAN;
         }
         sh_scale = scale;
-        if (!(scale == scale)) *T.status = NCF_E_DEGENERATE;
+        *out_st = (scale == scale) ? NCF_OK : NCF_E_DEGENERATE;
     }
     __syncthreads();
     const double scale = sh_scale;
@@ -132,21 +141,28 @@ k_normalize(const NormTask* __restrict__ tasks) {
             bout = w[2];
             cnt = __double_as_longlong(w[3]);
         }
-        T.c[k] = (num / fl(den)) / scale;
-        T.b[k] = fl(bout);
-        if (T.count) T.count[k] = T.is_rect ? cnt : 0;
+        out_c[k] = (num / fl(den)) / scale;
+        out_b[k] = fl(bout);
+        if (out_n) out_n[k] = T.is_rect ? cnt : 0;
     }
+}
+
+__global__ void k_set_io(IoBlock* __restrict__ dst, IoBlock v) {
+    if (threadIdx.x == 0) *dst = v;
 }
 
 }  // namespace
 
-int launch_normalize(const NormTask* d_tasks, int ntasks, int64_t total_k, const int64_t* d_k0,
-                     hipStream_t st) {
-    (void)total_k;
-    (void)d_k0;
+int launch_normalize(const NormTask* d_tasks, int ntasks, const IoBlock* io, hipStream_t st) {
     if (ntasks <= 0) return NCF_OK;
     ProfScope p(st, "normalize", 0.0, "bytes");
-    hipLaunchKernelGGL(k_normalize, dim3(ntasks), dim3(kThreads), 0, st, d_tasks);
+    hipLaunchKernelGGL(k_normalize, dim3(ntasks), dim3(kThreads), 0, st, d_tasks, io);
+    NCF_CHECK_LAUNCH();
+    return NCF_OK;
+}
+
+int launch_set_io(IoBlock* dst, const IoBlock& v, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_io, dim3(1), dim3(64), 0, st, dst, v);
     NCF_CHECK_LAUNCH();
     return NCF_OK;
 }

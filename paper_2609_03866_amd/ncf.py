@@ -19,6 +19,7 @@ GAUSSIAN, RECTANGLE = 0, 1
 MIXED, FP64 = 0, 1
 AUTO, SPECTRAL, DIRECT = 0, 1, 2
 DEVICE_POINTERS = 0x1
+PLAN_NO_GRAPH = 0x2
 
 OK = 0
 E_INVALID_ARG = -1
@@ -77,6 +78,11 @@ def lib():
         L.ncf_diag_type1.argtypes = [_I64, _P, _P, ctypes.c_double, ctypes.c_double, _I64, _I64,
                                      ctypes.c_int, _P]
         L.ncf_diag_spread_params.argtypes = [ctypes.c_double, ctypes.c_double, _P]
+        L.ncf_plan_acf.argtypes = [_I64, _P, _P, _P, _I64, _P, ctypes.c_int, _P, _P, _P]
+        L.ncf_plan_ccf.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _I64, _P, ctypes.c_int, _P, _P,
+                                   _P]
+        L.ncf_plan_execute.argtypes = [_P, _P, _P, _P, _P, _P, _P]
+        L.ncf_plan_destroy.argtypes = [_P]
         L.ncf_profile_enable.argtypes = [ctypes.c_int]
         L.ncf_profile_read.argtypes = [_P, ctypes.c_int]
         _lib = L
@@ -235,6 +241,97 @@ def ccf_batch(offx, t, x, offy, s, y, lags, kernel="gaussian", h=1.0, ex=None, e
         _check(rc)
     rs = (lambda a: a.reshape(npair, K) if a is not None else None)
     return rs(c), rs(b), rs(cnt), st, rc
+
+
+# ------------------------------------------------------------------ plans
+
+class Plan:
+    """A built plan (ncf_plan_acf / ncf_plan_ccf): run it on new values with
+    execute(); release it with close() (also on garbage collection)."""
+
+    def __init__(self, handle, ccf, nprob, K, device):
+        self._h = handle
+        self.ccf = ccf
+        self.nprob = nprob
+        self.K = K
+        self.device = device
+
+    def execute(self, x, y=None, with_count=True, raise_on_error=True):
+        """ncf_plan_execute. Returns (c[nprob, K], b, count, status[nprob], rc).
+        Device plans take torch CUDA tensors and return torch tensors (status
+        included), enqueued on the plan's stream."""
+        if self._h is None:
+            raise ValueError("plan is closed")
+        m = _Marshal(self.device)
+        n = self.nprob * self.K
+        c, pc = m.out(n, np.float64)
+        b, pb = m.out(n, np.float64)
+        cnt, pn = m.out(n, np.int64) if with_count else (None, None)
+        if self.device:
+            import torch
+            st = torch.zeros(self.nprob, dtype=torch.int32, device=self.device)
+            pst = st.data_ptr()
+        else:
+            st = np.zeros(self.nprob, dtype=np.int32)
+            pst = st.ctypes.data
+        rc = lib().ncf_plan_execute(self._h, m.inp(x), m.inp(y), pc, pb, pn, pst)
+        if raise_on_error:
+            _check(rc)
+        rs = (lambda a: a.reshape(self.nprob, self.K) if a is not None else None)
+        return rs(c), rs(b), rs(cnt), st, rc
+
+    def close(self):
+        if self._h is not None:
+            lib().ncf_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _plan_options(precision, method, tol, sigma, grid_size, dev, stream, graph):
+    o = _options(precision, method, tol, sigma, grid_size, dev, stream)
+    if not graph:
+        o.flags |= PLAN_NO_GRAPH
+    return o
+
+
+def plan_acf(offs, t, lags, kernel="gaussian", h=1.0, err=None, precision="mixed",
+             method="auto", tol=0.0, sigma=0.0, grid_size=0, graph=True, stream=None):
+    """ncf_plan_acf over CSR series (times fixed, values given per execute)."""
+    offs = np.ascontiguousarray(offs, dtype=np.int64)
+    nser = offs.size - 1
+    hs = np.ascontiguousarray(np.broadcast_to(np.asarray(h, dtype=np.float64), (nser,)))
+    dev = t.device if _is_torch(t) else None
+    m = _Marshal(dev)
+    K = int(lags.numel() if _is_torch(lags) else np.asarray(lags).size)
+    o = _plan_options(precision, method, tol, sigma, grid_size, dev, stream, graph)
+    hp = ctypes.c_void_p()
+    _check(lib().ncf_plan_acf(nser, offs.ctypes.data, m.inp(t), m.inp(err), K, m.inp(lags),
+                              _kern(kernel), hs.ctypes.data, ctypes.byref(o), ctypes.byref(hp)))
+    return Plan(hp.value, False, nser, K, dev)
+
+
+def plan_ccf(offx, t, offy, s, lags, kernel="gaussian", h=1.0, ex=None, ey=None,
+             precision="mixed", method="auto", tol=0.0, sigma=0.0, grid_size=0, graph=True,
+             stream=None):
+    """ncf_plan_ccf over CSR series pairs."""
+    offx = np.ascontiguousarray(offx, dtype=np.int64)
+    offy = np.ascontiguousarray(offy, dtype=np.int64)
+    npair = offx.size - 1
+    hs = np.ascontiguousarray(np.broadcast_to(np.asarray(h, dtype=np.float64), (npair,)))
+    dev = t.device if _is_torch(t) else None
+    m = _Marshal(dev)
+    K = int(lags.numel() if _is_torch(lags) else np.asarray(lags).size)
+    o = _plan_options(precision, method, tol, sigma, grid_size, dev, stream, graph)
+    hp = ctypes.c_void_p()
+    _check(lib().ncf_plan_ccf(npair, offx.ctypes.data, m.inp(t), m.inp(ex), offy.ctypes.data,
+                              m.inp(s), m.inp(ey), K, m.inp(lags), _kern(kernel),
+                              hs.ctypes.data, ctypes.byref(o), ctypes.byref(hp)))
+    return Plan(hp.value, True, npair, K, dev)
 
 
 # ------------------------------------------------------------- diagnostics

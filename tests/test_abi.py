@@ -74,3 +74,21 @@ def test_no_device_is_reported_not_crashed():
                             raise_on_error=False)
     assert rc == ncf.E_DEVICE
     assert b"no HIP device" in ncf.lib().ncf_last_error()
+
+
+def test_plan_entry_points_declared_and_report_no_device():
+    names = _declared()
+    for required in ("ncf_plan_acf", "ncf_plan_ccf", "ncf_plan_execute", "ncf_plan_destroy"):
+        assert required in names
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("GPU present")
+    except Exception:
+        pass
+    with pytest.raises(ncf.NcfError) as ei:
+        ncf.plan_acf(np.array([0, 10]), np.arange(10.0), np.arange(3.0), "g", 0.5)
+    assert ei.value.code == ncf.E_DEVICE
+    lib = ncf.lib()
+    lib.ncf_plan_destroy(None)  # NULL is ignored
+    assert lib.ncf_plan_execute(None, None, None, None, None, None, None) == ncf.E_INVALID_ARG

@@ -1,0 +1,188 @@
+"""GPU tests of plans (ncf_plan_acf / ncf_plan_ccf / ncf_plan_execute).
+
+A plan is built once from the times and replayed on new values, as one
+captured HIP graph or as a replay of the recorded launches. Every replay is
+checked against the one-shot batch call on the same values (run eagerly in
+between, with host synchronizations) and against the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2609_03866_amd import ncf, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _values_acf(d, seed):
+    """New values at the plan's times: an OU series per curve plus noise."""
+    rng = synth.rng_for(1000 + seed)
+    offs = d["offs"]
+    out = np.empty_like(d["x"])
+    for i in range(len(offs) - 1):
+        sl = slice(offs[i], offs[i + 1])
+        out[sl] = synth.ou_at_times(rng, d["t"][sl], 10.0) + 0.2 * rng.standard_normal(
+            offs[i + 1] - offs[i])
+    return out
+
+
+def _values_ccf(d, seed):
+    rng = synth.rng_for(2000 + seed)
+    x = np.empty_like(d["x"])
+    y = np.empty_like(d["y"])
+    for p in range(len(d["offx"]) - 1):
+        sx = slice(d["offx"][p], d["offx"][p + 1])
+        sy = slice(d["offy"][p], d["offy"][p + 1])
+        x[sx] = synth.ou_at_times(rng, d["t"][sx], 30.0)
+        y[sy] = synth.ou_at_times(rng, d["s"][sy], 30.0) + 0.1 * rng.standard_normal(
+            d["offy"][p + 1] - d["offy"][p])
+    return x, y
+
+
+def _close_b(b, ob, rel_ref):
+    np.testing.assert_allclose(b, ob, rtol=0, atol=rel_ref * np.max(ob))
+
+
+@pytest.mark.parametrize("graph", [True, False])
+@pytest.mark.parametrize("prec,method,ctol,bref", [
+    ("mixed", "auto", 1e-5, 1e-5),
+    ("fp64", "auto", 5e-8, 2e-8),
+    ("mixed", "direct", 1e-5, 1e-6),
+])
+def test_acf_plan_replays_match_batch_and_oracle(graph, prec, method, ctol, bref):
+    d = synth.small("c4", seed=21)
+    offs = d["offs"]
+    plan = ncf.plan_acf(offs, d["t"], d["lags"], "gaussian", d["h"], precision=prec,
+                        method=method, graph=graph)
+    try:
+        for r in range(4):
+            x = _values_acf(d, r)
+            c, b, n, st, rc = plan.execute(x)
+            assert rc == 0 and np.all(st == 0)
+            # eager one-shot call on the same values between replays
+            c1, b1, n1, st1, rc1 = ncf.acf_batch(offs, d["t"], x, d["lags"], "gaussian",
+                                                 d["h"], precision=prec, method=method)
+            assert rc1 == 0
+            assert np.max(np.abs(c - c1)) <= ctol
+            _close_b(b, b1, bref)
+            for i in (0, r + 3, len(offs) - 2):
+                sl = slice(offs[i], offs[i + 1])
+                s2, oc, ob, on = O.acf(d["t"][sl], x[sl], d["lags"], "gaussian", d["h"][i])
+                assert s2 == 0
+                assert np.max(np.abs(c[i] - oc)) <= ctol
+                _close_b(b[i], ob, bref)
+    finally:
+        plan.close()
+
+
+def test_graph_and_launch_replay_are_identical():
+    d = synth.small("c4", seed=22)
+    pg = ncf.plan_acf(d["offs"], d["t"], d["lags"], "gaussian", d["h"], graph=True)
+    pe = ncf.plan_acf(d["offs"], d["t"], d["lags"], "gaussian", d["h"], graph=False)
+    try:
+        for r in range(3):
+            x = _values_acf(d, 10 + r)
+            cg, bg = pg.execute(x)[:2]
+            ce, be = pe.execute(x)[:2]
+            np.testing.assert_array_equal(cg, ce)
+            np.testing.assert_array_equal(bg, be)
+    finally:
+        pg.close()
+        pe.close()
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_ccf_rectangle_plan_exact_counts(graph):
+    d = synth.small("c5", seed=23)
+    plan = ncf.plan_ccf(d["offx"], d["t"], d["offy"], d["s"], d["lags"], "rectangle", d["h"],
+                        graph=graph)
+    try:
+        for r in range(3):
+            x, y = _values_ccf(d, r)
+            c, b, n, st, rc = plan.execute(x, y)
+            assert rc == 0 and np.all(st == 0)
+            c1, b1, n1, st1, rc1 = ncf.ccf_batch(d["offx"], d["t"], x, d["offy"], d["s"], y,
+                                                 d["lags"], "rectangle", d["h"])
+            np.testing.assert_array_equal(n, n1)
+            np.testing.assert_array_equal(c, c1)
+            for p in (0, len(d["offx"]) - 2):
+                sx = slice(d["offx"][p], d["offx"][p + 1])
+                sy = slice(d["offy"][p], d["offy"][p + 1])
+                s2, oc, ob, on = O.ccf(d["t"][sx], x[sx], d["s"][sy], y[sy], d["lags"],
+                                       "rectangle", d["h"][p])
+                np.testing.assert_array_equal(n[p], on)
+                assert np.max(np.abs(c[p] - oc)) <= 1e-9
+    finally:
+        plan.close()
+
+
+def test_ccf_gaussian_plan_matches_oracle():
+    d = synth.small("c2", seed=24)
+    offx = np.array([0, d["t"].size])
+    offy = np.array([0, d["s"].size])
+    plan = ncf.plan_ccf(offx, d["t"], offy, d["s"], d["lags"], "gaussian", d["h"])
+    try:
+        for r in range(3):
+            rng = synth.rng_for(3000 + r)
+            x = d["x"] + 0.3 * rng.standard_normal(d["x"].size)
+            y = d["y"] + 0.3 * rng.standard_normal(d["y"].size)
+            c, b, n, st, rc = plan.execute(x, y)
+            st2, oc, ob, on = O.ccf(d["t"], x, d["s"], y, d["lags"], "gaussian", d["h"])
+            assert rc == 0 and st2 == 0
+            assert np.max(np.abs(c[0] - oc)) <= 1e-5
+            _close_b(b[0], ob, 1e-5)
+    finally:
+        plan.close()
+
+
+def test_plan_reports_value_and_time_failures_per_series():
+    d = synth.small("c4", seed=25)
+    offs = d["offs"]
+    t = d["t"].copy()
+    t[offs[4]:offs[5]] = t[offs[4]:offs[5]][::-1].copy()  # unsorted times: series 4
+    plan = ncf.plan_acf(offs, t, d["lags"], "gaussian", d["h"])
+    try:
+        for r in range(2):
+            x = _values_acf(d, 20 + r)
+            x[offs[1] + 3] = np.nan          # series 1: non-finite value
+            x[offs[2]:offs[3]] = 2.5         # series 2: constant
+            c, b, n, st, rc = plan.execute(x, raise_on_error=False)
+            assert rc == ncf.E_INVALID_ARG
+            assert st[1] == ncf.E_INVALID_ARG and st[2] == ncf.E_DEGENERATE
+            assert st[4] == ncf.E_UNSORTED
+            assert np.sum(st != 0) == 3
+            for i in (1, 2, 4):
+                assert np.all(np.isnan(c[i])) and np.all(b[i] == 0)
+            sl = slice(offs[0], offs[1])
+            s2, oc, ob, on = O.acf(t[sl], x[sl], d["lags"], "gaussian", d["h"][0])
+            assert np.max(np.abs(c[0] - oc)) <= 1e-5
+        # a clean execution afterwards reports only the time failure
+        x = _values_acf(d, 30)
+        st = plan.execute(x, raise_on_error=False)[3]
+        assert st[4] == ncf.E_UNSORTED and np.sum(st != 0) == 1
+    finally:
+        plan.close()
+
+
+def test_device_pointer_plan_with_torch_tensors():
+    import torch
+    d = synth.small("c4", seed=26)
+    dev = torch.device("cuda:0")
+    offs = d["offs"]
+    tt = torch.as_tensor(d["t"], device=dev)
+    lg = torch.as_tensor(d["lags"], device=dev)
+    plan = ncf.plan_acf(offs, tt, lg, "gaussian", d["h"])
+    try:
+        del tt  # the plan keeps its own copy of the times
+        torch.cuda.synchronize()
+        outs = []
+        xs = [_values_acf(d, 40 + r) for r in range(3)]
+        for x in xs:  # enqueue three executions back to back
+            outs.append(plan.execute(torch.as_tensor(x, device=dev)))
+        torch.cuda.synchronize()
+        for x, (c, b, n, st, rc) in zip(xs, outs):
+            assert rc == 0 and int(st.abs().sum()) == 0
+            c1, b1 = ncf.acf_batch(offs, d["t"], x, d["lags"], "gaussian", d["h"])[:2]
+            assert np.max(np.abs(c.cpu().numpy() - c1)) <= 1e-5
+    finally:
+        plan.close()
