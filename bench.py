@@ -96,6 +96,29 @@ def run_one(d, precision="mixed", method="auto"):
                          d["kernel"], d["h"], **kw)
 
 
+def make_plan(d, precision="mixed", method="auto"):
+    """A plan over the workload's times (device tensors), replayed as a graph."""
+    from paper_2609_03866_amd import ncf
+    kw = dict(precision=precision, method=method)
+    if d["kind"] == "acf":
+        return ncf.plan_acf(np.array([0, d["t"].numel()]), d["t"], d["lags"], d["kernel"],
+                            d["h"], err=d.get("err"), **kw)
+    if d["kind"] == "ccf":
+        return ncf.plan_ccf(np.array([0, d["t"].numel()]), d["t"], np.array([0, d["s"].numel()]),
+                            d["s"], d["lags"], d["kernel"], d["h"], **kw)
+    if d["kind"] == "acf_batch":
+        return ncf.plan_acf(d["offs"], d["t"], d["lags"], d["kernel"], d["h"], err=d.get("err"),
+                            **kw)
+    return ncf.plan_ccf(d["offx"], d["t"], d["offy"], d["s"], d["lags"], d["kernel"], d["h"],
+                        **kw)
+
+
+def run_plan(plan, d):
+    if d["kind"] in ("acf", "acf_batch"):
+        return plan.execute(d["x"])
+    return plan.execute(d["x"], d["y"])
+
+
 def lag_subset(d, max_windows=2.5e9):
     """Indices of an evenly spaced subset of the lags that bounds the oracle's
     work on a single large problem to about ``max_windows`` (j, k) windows."""
@@ -198,7 +221,10 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU path")
+    ap.add_argument("--no-plan", action="store_true", help="skip the plan replay timing")
     ap.add_argument("--oracle-series", type=int, default=64)
+    ap.add_argument("--oracle-seconds", type=float, default=10.0,
+                    help="repeat the oracle sample until it has run this long (>= 3 runs)")
     ap.add_argument("--calibrate", action="store_true",
                     help="first run a 256 MiB device fill and three 256 MiB device copies "
                          "(known byte counts for HBM counter calibration)")
@@ -257,6 +283,27 @@ def main():
         fp64 = {"value": work / dt64, "ms_per_step": dt64 * 1e3, "path": "fp64 direct window sums"}
         log(f"[bench] fp64 direct: {dt64 * 1e3:.3f} ms/step")
 
+    # the same step through plans built beforehand (graph replay on the values)
+    plan_rep = None
+    if not args.no_plan:
+        plans = [make_plan(d) for d in devs]
+        for pl, d in zip(plans, devs):
+            run_plan(pl, d)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(args.steps):
+            pres = [run_plan(pl, d) for pl, d in zip(plans, devs)]
+        torch.cuda.synchronize()
+        dtp = (time.perf_counter() - t2) / args.steps
+        dcp = max(float((pr[0].reshape(-1) - r[0].reshape(-1)).abs().max().item())
+                  for pr, r in zip(pres, res))
+        plan_rep = {"value": work / dtp, "ms_per_step": dtp * 1e3,
+                    "max_abs_dc_vs_call": dcp,
+                    "path": "ncf_plan_execute, captured HIP graph, plans built before timing"}
+        for pl in plans:
+            pl.close()
+        log(f"[bench] plan replay: {dtp * 1e3:.3f} ms/step")
+
     # roofline of the dominant kernel, HIP events on the library's stream
     ncf.profile_enable(True)
     nprof = max(2, min(5, args.steps))
@@ -290,11 +337,20 @@ def main():
         log(f"[bench] oracle on {cores} threads")
         orc_work, orc_time = 0, 0.0
         picks = []
+        rates = []
         for i, (d, r) in enumerate(zip(host, res)):
             cs, ns, w, sec, pick = oracle_subset(d, args.oracle_series)
+            # repeat the same sample (>= 3 runs, about --oracle-seconds in
+            # total); the median run gives the rate
+            secs = [sec]
+            while len(secs) < 3 or sum(secs) < args.oracle_seconds / len(host):
+                secs.append(oracle_subset(d, args.oracle_series)[3])
+                if len(secs) >= 200:
+                    break
             picks.append(pick)
             orc_work += w
-            orc_time += sec
+            orc_time += float(np.median(secs))
+            rates.append(len(secs))
             key = f"{d['name']}_{d['kernel']}"
             acc[key] = {"max_abs_dc_mixed": max_dc(r[0], cs, pick)}
             if d["kernel"] == "rectangle":
@@ -309,7 +365,8 @@ def main():
         else:
             sample = f"first {args.oracle_series} series of the batch"
         cpu = {"value": orc_work / orc_time, "unit": "lag-pairs/s", "cores": cores,
-               "kind": "oracle", "sample": sample, "seconds": orc_time}
+               "kind": "oracle", "sample": sample, "seconds": orc_time,
+               "runs": min(rates), "statistic": "median run"}
 
     d0 = host[0]
     cfg = {"workload": {"c1": "acf_n2000_K101_gauss_fp64plain_vs_mixed",
@@ -334,6 +391,7 @@ def main():
         "config": cfg,
         "series_per_s": nser / dt,
         "fp64_gpu_path": fp64,
+        "plan_replay": plan_rep,
         "accuracy_vs_oracle": acc,
         "roofline": roof,
         "kernels": kernels,

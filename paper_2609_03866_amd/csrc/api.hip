@@ -13,6 +13,7 @@
 // Work items of a batch are flattened across series so that a single
 // launch covers thousands of uneven series.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -580,8 +581,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         W.item0.assign(ntw + 1, 0);
         W.wk0.assign(ntw + 1, 0);
         W.r0.assign(ntw + 1, 0);
-        double need = 0.0;
-        int jneed = 16;
+        std::vector<std::array<double, 3>> dens(ntw);  // window / outer density, extent
         for (int i = 0; i < ntw; ++i) {
             const WinPlan& P = W.plans[i];
             const SeriesSet& SW = J.set[P.wi_set];
@@ -623,9 +623,8 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             const double dens_w = (double)(dw.n - 1) / span_w;
             const double dens_o = (double)(dO.n - 1) / span_o;
             const int n_kt = (int)ceil_div(T.K, 64);
-            auto est = [&](int64_t j) {
-                return dens_w * ((double)j / dens_o + lext + 2.0 * T.W) + 2.0;
-            };
+            const double ext = lext + 2.0 * T.W;
+            auto est = [&](int64_t j) { return dens_w * ((double)j / dens_o + ext) + 2.0; };
             // outer samples per workgroup: as many as keep the window range in
             // LDS (half the capacity, for clustering) while leaving at least
             // 2048 work items (eight per CU) when the problem is big enough
@@ -635,10 +634,41 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
                 Jt *= 2;
             while (Jt > 16 && est(Jt) > 0.5 * cap) Jt /= 2;
             T.J = (int32_t)Jt;
-            need = std::max(need, est(Jt));
-            jneed = std::max(jneed, (int)Jt);
-            T.n_jt = (int32_t)ceil_div(dO.n, Jt);
             T.n_kt = n_kt;
+            dens[i] = {dens_w, dens_o, ext};
+            // algorithmic work: per (j, k) window, searches + per-point weight ops
+            const double pts = rect ? 0.0 : dens_w * 2.0 * T.W;
+            W.work += (double)dO.n * T.K * (8.0 + (rect ? 4.0 : 8.0 * pts));
+            W.wt[i] = T;
+        }
+        // the launch has one LDS size, set by the largest footprint
+        double need = 0.0;
+        int jneed = 16;
+        auto est_of = [&](int i, int64_t j) {
+            return dens[i][0] * ((double)j / dens[i][1] + dens[i][2]) + 2.0;
+        };
+        for (int i = 0; i < ntw; ++i) {
+            need = std::max(need, est_of(i, W.wt[i].J));
+            jneed = std::max(jneed, (int)W.wt[i].J);
+        }
+        // LDS: twice the estimated window range (clustering margin), rounded up
+        const int want = (int)std::min<double>(cap, round_up((int64_t)(2.0 * need) + 64, 256));
+        W.cap = std::max(256, want);
+        W.jmax = (int)round_up(jneed, 64);
+        // items of few lags (e.g. the lag-0 scale tasks) grow within that
+        // footprint until they hold ~8192 windows: a workgroup's searches and
+        // staging cost the same for any size
+        for (int i = 0; i < ntw; ++i) {
+            WinTask& T = W.wt[i];
+            const int64_t kin = std::min<int64_t>(T.K, 64);
+            int64_t Jt = T.J;
+            while (Jt * 2 <= W.jmax && est_of(i, Jt * 2) <= 0.5 * W.cap && Jt * 2 * kin <= 8192)
+                Jt *= 2;
+            T.J = (int32_t)Jt;
+        }
+        for (int i = 0; i < ntw; ++i) {
+            WinTask& T = W.wt[i];
+            T.n_jt = (int32_t)ceil_div(T.n_out, T.J);
             T.item0 = W.nitems;
             W.item0[i] = W.nitems;
             W.wk0[i] = W.total_rows;
@@ -646,18 +676,10 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             W.nitems += (int64_t)T.n_jt * T.n_kt;
             W.nred1 += (int64_t)T.n_kt * ceil_div(T.n_jt, kWinJc);
             W.total_rows += T.K;
-            // algorithmic work: per (j, k) window, searches + per-point weight ops
-            const double pts = rect ? 0.0 : dens_w * 2.0 * T.W;
-            W.work += (double)dO.n * T.K * (8.0 + (rect ? 4.0 : 8.0 * pts));
-            W.wt[i] = T;
         }
         W.item0[ntw] = W.nitems;
         W.wk0[ntw] = W.total_rows;
         W.r0[ntw] = W.nred1;
-        // LDS: twice the estimated window range (clustering margin), rounded up
-        const int want = (int)std::min<double>(cap, round_up((int64_t)(2.0 * need) + 64, 256));
-        W.cap = std::max(256, want);
-        W.jmax = (int)round_up(jneed, 64);
     };
 
     WinLaunch W1;

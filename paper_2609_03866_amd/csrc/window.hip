@@ -198,6 +198,89 @@ __device__ __forceinline__ void scan_lane(Acc& acc, const V& v, int ja, int jb, 
     }
 }
 
+// Rectangle scan over LDS: window times contiguous (t_i, +inf sentinels),
+// their prefix sums P (and PW) in parallel arrays `dp` doubles further on,
+// outer samples as records (s_j[, vo_j][, wo_j]) of QO doubles. The bounds
+// are LDS addresses into the time array, so a prefix value is read at a
+// fixed distance from the time that its bound stopped at, and counts
+// accumulate as address differences. Same predicates and the same order of
+// the numerator sums as scan_lane.
+struct AccR {
+    double C, B;
+    int bytes;  // sum over j of (hi - lo) * 8
+};
+
+template <bool NUMER, bool WTD>
+__device__ __forceinline__ void scan_rect(AccR& acc, int o_t, int dp, int o_o, int len, int ja,
+                                          int jb, double delta, double W) {
+    constexpr int QO = 1 + (NUMER ? 1 : 0) + (WTD ? 1 : 0);
+    constexpr int QW = NUMER ? 2 : 1;  // PW array follows P when both exist
+    if (ja >= jb) return;
+    const double* win = g_win_lds + o_t;
+    const double* po = g_win_lds + o_o + QO * ja;
+    const double* const pend = g_win_lds + o_o + QO * jb;
+    double s = po[0];
+    double vo = NUMER ? po[1] : 0.0;
+    double wo = WTD ? po[QO - 1] : 0.0;
+    // initial bounds of the first outer sample by binary search
+    const double c0 = s + delta;
+    int lo, hi;
+    {
+        const double key = c0 - W;
+        int a = 0, b = len;
+        while (a < b) {
+            const int m = (a + b) >> 1;
+            if (win[m] < key)
+                a = m + 1;
+            else
+                b = m;
+        }
+        lo = a;
+        const double keyh = c0 + W;
+        b = len;
+        while (a < b) {
+            const int m = (a + b) >> 1;
+            if (win[m] <= keyh)
+                a = m + 1;
+            else
+                b = m;
+        }
+        hi = a;
+    }
+    const double* plo = win + lo;
+    const double* phi = win + hi;
+    for (;;) {
+        // next outer record (the staged array has one padding record)
+        const double* pn = po + QO;
+        const double s_n = pn[0];
+        const double vo_n = NUMER ? pn[1] : 0.0;
+        const double wo_n = WTD ? pn[QO - 1] : 0.0;
+        const double c = s + delta;
+        const double lk = c - W;
+        const double hk = c + W;
+        for (;;) {
+            const double x0 = plo[0], x1 = plo[1], x2 = plo[2], x3 = plo[3];
+            const int a = (x0 < lk) + (x1 < lk) + (x2 < lk) + (x3 < lk);
+            plo += a;
+            if (a < 4) break;
+        }
+        for (;;) {
+            const double x0 = phi[0], x1 = phi[1], x2 = phi[2], x3 = phi[3];
+            const int a = (x0 <= hk) + (x1 <= hk) + (x2 <= hk) + (x3 <= hk);
+            phi += a;
+            if (a < 4) break;
+        }
+        acc.bytes += (int)((const char*)phi - (const char*)plo);
+        if (NUMER) acc.C += vo * (phi[dp] - plo[dp]);
+        if (WTD) acc.B += wo * (phi[QW * dp] - plo[QW * dp]);
+        po = pn;
+        if (po == pend) break;
+        s = s_n;
+        vo = vo_n;
+        wo = wo_n;
+    }
+}
+
 template <uint32_t F>
 __global__ void __launch_bounds__(kThreads)
 k_window(const WinTask* __restrict__ tasks, const int64_t* __restrict__ item0, int ntasks,
@@ -262,7 +345,26 @@ k_window(const WinTask* __restrict__ tasks, const int64_t* __restrict__ item0, i
     const double* A1g = RECT ? T.pv : T.v;
     const double* A2g = RECT ? T.pw : T.w;
     const int a_len = RECT ? len + 1 : len;  // prefix arrays need the entry at hi
-    if (fits) {
+    // rectangle: times, prefix arrays (each cap + 8 long), then outer
+    // records (s[, vo][, wo])
+    constexpr int QR = 1 + (NUMER ? 1 : 0) + (WTD ? 1 : 0);
+    const int o_rw = 0;
+    const int dp = cap + 8;
+    const int o_ro = QR * (cap + 8);
+    if (RECT && fits) {
+        for (int i = tid; i < len + 8; i += kThreads) {
+            double* r = g_win_lds + o_rw + i;
+            r[0] = i < len ? T.t[tlo + i] : kInf;
+            if (NUMER) r[dp] = i <= len ? T.pv[tlo + i] : 0.0;
+            if (WTD) r[(QR - 1) * dp] = i <= len ? T.pw[tlo + i] : 0.0;
+        }
+        for (int i = tid; i <= nj; i += kThreads) {
+            double* r = g_win_lds + o_ro + QR * i;
+            r[0] = i < nj ? T.s[j0 + i] : 0.0;
+            if (NUMER) r[1] = i < nj ? T.vo[j0 + i] : 0.0;
+            if (WTD) r[QR - 1] = i < nj ? T.wo[j0 + i] : 0.0;
+        }
+    } else if (fits) {
         for (int i = tid; i < len + 8; i += kThreads)
             g_win_lds[o_t + i] = i < len ? T.t[tlo + i] : kInf;
         if (HAS_A1)
@@ -292,7 +394,13 @@ k_window(const WinTask* __restrict__ tasks, const int64_t* __restrict__ item0, i
     const double inv_h = 1.0 / T.h;
 
     Acc acc = {0.0, 0.0, 0.0, 0};
-    if (active) {
+    if (RECT && fits) {
+        AccR ar = {0.0, 0.0, 0};
+        if (active) scan_rect<NUMER, WTD>(ar, o_rw, dp, o_ro, len, ja, jb, delta, W);
+        acc.C = ar.C;
+        acc.B = ar.B;
+        acc.n = ar.bytes / (int)sizeof(double);
+    } else if (active) {
         if (fits) {
             LdsView v{o_t, o_a1, o_a2, o_s, o_vo, o_wo, len};
             scan_lane<F>(acc, v, ja, jb, delta, W, inv_h);
@@ -434,7 +542,7 @@ int launch_window_t(const WinTask* d_tasks, const int64_t* d_item0, int ntasks, 
     constexpr bool NUMER = (F & WIN_NUMER) != 0;
     constexpr bool WTD = (F & WIN_WEIGHTED) != 0;
     size_t stage = (size_t)(cap + 8) * (1 + (NUMER ? 1 : 0) + (WTD ? 1 : 0)) +
-                   (size_t)jmax * (1 + (NUMER ? 1 : 0) + (WTD ? 1 : 0));
+                   (size_t)(jmax + 2) * (1 + (NUMER ? 1 : 0) + (WTD ? 1 : 0));
     size_t red = 4 * kThreads;
     size_t bytes = (stage > red ? stage : red) * sizeof(double);
     (void)RECT;
