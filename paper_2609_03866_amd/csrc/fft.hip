@@ -10,14 +10,18 @@
 // order and producing natural order. The spectral product works in the
 // digit-reversed order directly, so no transpose pass is ever made.
 //
-// A workgroup transforms one tile of 4096 elements: R_i rows by
-// C_i = 4096 / R_i adjacent columns (C_i * element size contiguous bytes per
-// row in HBM). Each column's DFT is a Stockham autosort sequence of radix-16
+// A workgroup transforms one tile of T = 4096 or 8192 elements: R_i rows by
+// C_i = T / R_i adjacent columns (C_i * element size contiguous bytes per
+// row in HBM; the strided passes use the larger tile for longer runs). Each column's DFT is a Stockham autosort sequence of radix-16
 // stages (and one radix-8/4/2 stage for the remainder) with 16 elements per
 // thread in registers: the first stage reads HBM directly, the last writes
 // HBM directly, and the stages in between exchange through padded LDS.
-// Twiddles come from tables computed in FP64 on the host and rounded once to
-// the working precision.
+// Twiddles: the factors a thread applies to its 16 elements form geometric
+// progressions (w^(e0 + i d), i = 0, 1, ...). The thread looks up the start and
+// the ratio in FP64 tables (computed on the host with exact integer range
+// reduction), forms the powers by FP64 recurrence (relative error ~i 2^-53)
+// and rounds each once to the working precision: two table lookups per
+// progression instead of one per element.
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -29,8 +33,7 @@ namespace ncf {
 
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kTileElems = 4096;
+constexpr int kTileElems = 4096;  // last pass (radix 4096) and the w_4096 table
 
 template <typename R>
 struct C2T;
@@ -93,15 +96,16 @@ struct PassArgs {
     int lgR;             // log2 radix of this pass
     int64_t S;           // column stride (elements)
     int64_t B;           // block size R * S
-    int lgC;             // log2 columns per tile (4096 / R)
-    int64_t tiles_per_grid;  // N / 4096
+    int lgC;             // log2 columns per tile (T / R)
+    int lgT;             // log2 tile elements (12 or 13)
+    int64_t tiles_per_grid;  // N / T
     int64_t ntiles;          // tiles over all grids
     int64_t nblocks;         // launched workgroups (multiple of 8)
     int sign;            // +1 forward (DIF, twiddle after), -1 inverse (DIT, twiddle before)
     int lobits;
-    const void* wlo;     // w_N^e, e < 2^lobits     (sign +1)
-    const void* whi;     // w_N^(e << lobits)
-    const void* wsmall;  // w_4096^e
+    const void* wlo;     // FP64 w_N^e, e < 2^lobits     (sign +1)
+    const void* whi;     // FP64 w_N^(e << lobits)
+    const void* wsmall;  // FP64 w_4096^e
 };
 
 // Global-memory element access through address-space-1 scalar pointers
@@ -126,17 +130,27 @@ __device__ __forceinline__ void gst(void* base, int64_t idx, C2 v) {
     p[2 * idx + 1] = v.y;
 }
 
-template <typename C2>
-__device__ __forceinline__ C2 tw_big(const PassArgs& a, int64_t e) {
-    // w_N^e for 0 <= e < N, with the sign of the pass
-    C2 w = cmul(gld<C2>(a.whi, e >> a.lobits), gld<C2>(a.wlo, e & ((1LL << a.lobits) - 1)));
+// w_N^e (any e >= 0, reduced mod N), FP64, with the sign of the pass
+__device__ __forceinline__ double2 tw_big(const PassArgs& a, int64_t e) {
+    e &= a.N - 1;
+    double2 w = cmul(gld<double2>(a.whi, e >> a.lobits),
+                     gld<double2>(a.wlo, e & ((1LL << a.lobits) - 1)));
+    return a.sign > 0 ? w : cconj(w);
+}
+
+// w_4096^e, FP64, with the sign of the pass
+__device__ __forceinline__ double2 tw_small(const PassArgs& a, int e) {
+    double2 w = gld<double2>(a.wsmall, e & (kTileElems - 1));
     return a.sign > 0 ? w : cconj(w);
 }
 
 template <typename C2>
-__device__ __forceinline__ C2 tw_small(const PassArgs& a, int e) {
-    C2 w = gld<C2>(a.wsmall, e & (kTileElems - 1));
-    return a.sign > 0 ? w : cconj(w);
+__device__ __forceinline__ C2 round_tw(double2 w) {
+    typedef decltype(C2{}.x) R;
+    C2 r;
+    r.x = (R)w.x;
+    r.y = (R)w.y;
+    return r;
 }
 
 // ------------------------------------------------ small DFTs in registers
@@ -250,11 +264,12 @@ __device__ __forceinline__ int lds_pad(int e) { return e + (e >> 4); }
 // One Stockham stage of radix RADIX over the tile's C columns of length R.
 // Each thread owns 16 / RADIX butterflies (16 elements). Inputs come from
 // `src` (global or LDS view), outputs go to `dst`.
-template <int RADIX, bool FROM_GLOBAL, bool TO_GLOBAL, int LGR, int NS, typename C2>
+template <int RADIX, bool FROM_GLOBAL, bool TO_GLOBAL, int LGR, int NS, int LGT, typename C2>
 __device__ __forceinline__ void stockham_stage(const PassArgs& a, C2* lds, C2* gbase,
                                                int64_t s0) {
+    constexpr int kThreads = 1 << (LGT - 4);  // 16 elements per thread
     constexpr int NB = 16 / RADIX;  // butterflies per thread
-    constexpr int lgC = 12 - LGR;
+    constexpr int lgC = LGT - LGR;
     constexpr int R = 1 << LGR;
     constexpr int C = 1 << lgC;
     constexpr int Rr = R / RADIX;
@@ -272,26 +287,32 @@ __device__ __forceinline__ void stockham_stage(const PassArgs& a, C2* lds, C2* g
 #pragma unroll
         for (int i = 0; i < RADIX; ++i) {
             const int row = j + i * Rr;
-            C2 x;
-            if (FROM_GLOBAL) {
-                x = gld<C2>(gbase, (int64_t)row * a.S + c);
-                if (a.sign < 0) {
-                    // adjoint of the forward pass twiddle, applied before the DFT
-                    const int64_t ex = (s0 + c) * (int64_t)row * (a.N / a.B);
-                    if (ex) x = cmul(x, tw_big<C2>(a, ex));
-                }
-            } else {
-                x = lds[lds_pad(row * C + c)];
-            }
-            v[u * RADIX + i] = x;
+            v[u * RADIX + i] = FROM_GLOBAL ? gld<C2>(gbase, (int64_t)row * a.S + c)
+                                           : lds[lds_pad(row * C + c)];
         }
-        // stage twiddles w_{Ns r}^(i k), k = j mod Ns, from the w_4096 table
+        if (FROM_GLOBAL && a.sign < 0) {
+            // adjoint of the forward pass twiddle, applied before the DFT:
+            // w^(E row), rows j + i Rr, E = (s0 + c) N / B
+            const int64_t E = (s0 + c) * (a.N / a.B);
+            double2 t = tw_big(a, E * j);
+            const double2 d = tw_big(a, E * Rr);
+#pragma unroll
+            for (int i = 0; i < RADIX; ++i) {
+                if (i) t = cmul(t, d);
+                v[u * RADIX + i] = cmul(v[u * RADIX + i], round_tw<C2>(t));
+            }
+        }
+        // stage twiddles w_{Ns r}^(i k), k = j mod Ns: powers of w_4096^(k step)
         const int k = j & (Ns - 1);
         if (Ns > 1 && k) {
             const int step = kTileElems / (Ns * RADIX);
+            const double2 d = tw_small(a, k * step);
+            double2 t = d;
 #pragma unroll
-            for (int i = 1; i < RADIX; ++i)
-                v[u * RADIX + i] = cmul(v[u * RADIX + i], tw_small<C2>(a, i * k * step));
+            for (int i = 1; i < RADIX; ++i) {
+                if (i > 1) t = cmul(t, d);
+                v[u * RADIX + i] = cmul(v[u * RADIX + i], round_tw<C2>(t));
+            }
         }
         dft_r<RADIX>(v + u * RADIX, a.sign);
     }
@@ -303,19 +324,24 @@ __device__ __forceinline__ void stockham_stage(const PassArgs& a, C2* lds, C2* g
         const int j = jj[u], c = cc[u];
         const int k = j & (Ns - 1);
         const int obase = (j / Ns) * Ns * RADIX + k;
+        if (TO_GLOBAL && a.sign > 0) {
+            // pass twiddle w^(E row), rows obase + i Ns, E = (s0 + c) N / B
+            const int64_t E = (s0 + c) * (a.N / a.B);
+            double2 t = tw_big(a, E * obase);
+            const double2 d = tw_big(a, E * Ns);
+#pragma unroll
+            for (int i = 0; i < RADIX; ++i) {
+                if (i) t = cmul(t, d);
+                v[u * RADIX + i] = cmul(v[u * RADIX + i], round_tw<C2>(t));
+            }
+        }
 #pragma unroll
         for (int i = 0; i < RADIX; ++i) {
             const int row = obase + i * Ns;
-            C2 x = v[u * RADIX + i];
-            if (TO_GLOBAL) {
-                if (a.sign > 0) {
-                    const int64_t ex = (s0 + c) * (int64_t)row * (a.N / a.B);
-                    if (ex) x = cmul(x, tw_big<C2>(a, ex));
-                }
-                gst<C2>(gbase, (int64_t)row * a.S + c, x);
-            } else {
-                lds[lds_pad(row * C + c)] = x;
-            }
+            if (TO_GLOBAL)
+                gst<C2>(gbase, (int64_t)row * a.S + c, v[u * RADIX + i]);
+            else
+                lds[lds_pad(row * C + c)] = v[u * RADIX + i];
         }
     }
     if (!TO_GLOBAL) __syncthreads();  // outputs visible to the next stage
@@ -323,7 +349,7 @@ __device__ __forceinline__ void stockham_stage(const PassArgs& a, C2* lds, C2* g
 
 // Radix schedule of a column of length R = 2^LGR: radix-16 stages first, then
 // one stage of 8, 4 or 2 for the remainder; fixed at compile time.
-template <int LGR, int ST, int NS, typename C2>
+template <int LGR, int ST, int NS, int LGT, typename C2>
 __device__ __forceinline__ void run_stages(const PassArgs& a, C2* lds, C2* gbase,
                                            int64_t s0) {
     constexpr int n16 = LGR / 4;
@@ -331,17 +357,18 @@ __device__ __forceinline__ void run_stages(const PassArgs& a, C2* lds, C2* gbase
     constexpr int nst = n16 + (rem ? 1 : 0);
     if constexpr (ST < nst) {
         constexpr int RX = ST < n16 ? 16 : (1 << rem);
-        stockham_stage<RX, ST == 0, ST == nst - 1, LGR, NS>(a, lds, gbase, s0);
-        run_stages<LGR, ST + 1, NS * RX>(a, lds, gbase, s0);
+        stockham_stage<RX, ST == 0, ST == nst - 1, LGR, NS, LGT>(a, lds, gbase, s0);
+        run_stages<LGR, ST + 1, NS * RX, LGT>(a, lds, gbase, s0);
     }
 }
 
-template <typename Real, int LGR>
-__global__ void __launch_bounds__(kThreads)
+template <typename Real, int LGR, int LGT>
+__global__ void __launch_bounds__(1 << (LGT - 4))
 k_fft_pass(PassArgs a) {
     using C2 = typename C2T<Real>::T;
-    constexpr int lgC = 12 - LGR;
-    __shared__ C2 buf[kTileElems + kTileElems / 16];
+    constexpr int lgC = LGT - LGR;
+    constexpr int kElems = 1 << LGT;
+    __shared__ C2 buf[kElems + kElems / 16];
     const int64_t wg = blockIdx.x;
     if (wg >= a.ntiles) return;
     const int64_t gidx = wg / a.tiles_per_grid;
@@ -353,28 +380,37 @@ k_fft_pass(PassArgs a) {
     const int64_t blk = tile / chunks_per_block;
     const int64_t s0 = (tile % chunks_per_block) << lgC;
     C2* base = data + blk * a.B + s0;
-    run_stages<LGR, 0, 1>(a, buf, base, s0);
+    run_stages<LGR, 0, 1, LGT>(a, buf, base, s0);
 }
 
 template <typename Real>
 using PassKernel = void (*)(PassArgs);
 
-template <typename Real>
-PassKernel<Real> pass_kernel(int lgR) {
+template <typename Real, int LGT>
+PassKernel<Real> pass_kernel_t(int lgR) {
     switch (lgR) {
-        case 1: return k_fft_pass<Real, 1>;
-        case 2: return k_fft_pass<Real, 2>;
-        case 3: return k_fft_pass<Real, 3>;
-        case 4: return k_fft_pass<Real, 4>;
-        case 5: return k_fft_pass<Real, 5>;
-        case 6: return k_fft_pass<Real, 6>;
-        case 7: return k_fft_pass<Real, 7>;
-        case 8: return k_fft_pass<Real, 8>;
-        case 9: return k_fft_pass<Real, 9>;
-        case 10: return k_fft_pass<Real, 10>;
-        case 11: return k_fft_pass<Real, 11>;
-        default: return k_fft_pass<Real, 12>;
+        case 1: return k_fft_pass<Real, 1, LGT>;
+        case 2: return k_fft_pass<Real, 2, LGT>;
+        case 3: return k_fft_pass<Real, 3, LGT>;
+        case 4: return k_fft_pass<Real, 4, LGT>;
+        case 5: return k_fft_pass<Real, 5, LGT>;
+        case 6: return k_fft_pass<Real, 6, LGT>;
+        case 7: return k_fft_pass<Real, 7, LGT>;
+        case 8: return k_fft_pass<Real, 8, LGT>;
+        case 9: return k_fft_pass<Real, 9, LGT>;
+        case 10: return k_fft_pass<Real, 10, LGT>;
+        case 11: return k_fft_pass<Real, 11, LGT>;
+        default: return k_fft_pass<Real, 12, LGT>;
     }
+}
+
+// radix 2^lgR on tiles of 2^lgT elements (lgT = 13 only for strided passes)
+template <typename Real>
+PassKernel<Real> pass_kernel(int lgR, int lgT) {
+    if constexpr (sizeof(Real) == 4) {
+        if (lgT == 13 && lgR <= 11) return pass_kernel_t<Real, 13>(lgR);
+    }
+    return pass_kernel_t<Real, 12>(lgR);
 }
 
 struct TwKey {
@@ -455,6 +491,8 @@ int fft_plan(int64_t N, bool fp64, FftPlan* plan, hipStream_t st) {
     for (int i = 0; i < plan->npass; ++i) {
         plan->stride[i] = B / plan->radix[i];
         B = plan->stride[i];
+        // strided passes of the FP32 transform move 8192-element tiles
+        plan->lgt[i] = (i < plan->npass - 1 && !fp64) ? 13 : 12;
     }
     int dev = 0;
     NCF_TRY_HIP(hipGetDevice(&dev));
@@ -469,15 +507,9 @@ int fft_plan(int64_t N, bool fp64, FftPlan* plan, hipStream_t st) {
         auto lo = twiddles(N, nlo, 1);
         auto hi = twiddles(N, nhi, nlo);
         auto sm = twiddles(kTileElems, kTileElems, 1);
-        if (fp64) {
-            NCF_TRY(upload_table<double>(lo, &v.lo, st));
-            NCF_TRY(upload_table<double>(hi, &v.hi, st));
-            NCF_TRY(upload_table<double>(sm, &v.small, st));
-        } else {
-            NCF_TRY(upload_table<float>(lo, &v.lo, st));
-            NCF_TRY(upload_table<float>(hi, &v.hi, st));
-            NCF_TRY(upload_table<float>(sm, &v.small, st));
-        }
+        NCF_TRY(upload_table<double>(lo, &v.lo, st));
+        NCF_TRY(upload_table<double>(hi, &v.hi, st));
+        NCF_TRY(upload_table<double>(sm, &v.small, st));
         it = g_tw.emplace(key, v).first;
     }
     plan->lobits = it->second.lobits;
@@ -507,9 +539,6 @@ int fft_exec(const FftPlan& plan, void* const* d_grids, int count, int sign, boo
     a.grid_stride = 0;
     a.grids = reinterpret_cast<const void* const*>(d_grids);
     a.N = plan.N;
-    a.tiles_per_grid = plan.N / kTileElems;
-    a.ntiles = a.tiles_per_grid * count;
-    a.nblocks = round_up(a.ntiles, kXcds);
     a.sign = sign;
     a.lobits = plan.lobits;
     a.wlo = plan.wlo;
@@ -519,16 +548,21 @@ int fft_exec(const FftPlan& plan, void* const* d_grids, int count, int sign, boo
     for (int q = 0; q < plan.npass; ++q) {
         const int i = sign > 0 ? q : plan.npass - 1 - q;
         a.lgR = ilog2(plan.radix[i]);
-        a.lgC = 12 - a.lgR;
+        a.lgT = plan.lgt[i];
+        a.lgC = a.lgT - a.lgR;
         a.S = plan.stride[i];
         a.B = a.S * plan.radix[i];
+        a.tiles_per_grid = plan.N >> a.lgT;
+        a.ntiles = a.tiles_per_grid * count;
+        a.nblocks = round_up(a.ntiles, kXcds);
+        const unsigned threads = 1u << (a.lgT - 4);
         ProfScope p(st, fp64 ? "fft_pass_f64" : "fft_pass_f32", bytes, "bytes");
         if (fp64)
-            hipLaunchKernelGGL(pass_kernel<double>(a.lgR), dim3((unsigned)a.nblocks),
-                               dim3(kThreads), 0, st, a);
+            hipLaunchKernelGGL(pass_kernel<double>(a.lgR, a.lgT), dim3((unsigned)a.nblocks),
+                               dim3(threads), 0, st, a);
         else
-            hipLaunchKernelGGL(pass_kernel<float>(a.lgR), dim3((unsigned)a.nblocks),
-                               dim3(kThreads), 0, st, a);
+            hipLaunchKernelGGL(pass_kernel<float>(a.lgR, a.lgT), dim3((unsigned)a.nblocks),
+                               dim3(threads), 0, st, a);
         NCF_CHECK_LAUNCH();
     }
     return NCF_OK;

@@ -238,6 +238,7 @@ struct FftPlan {
     int npass;
     int radix[4];       // first pass first
     int64_t stride[4];  // S of each pass
+    int lgt[4];         // log2 tile elements of each pass (12 or 13)
     // twiddles: wlo[e] = w_N^e (e < 2^b), whi[e] = w_N^(e << b); small[e] = w_4096^e
     int lobits;
     void* wlo;  // float2 or double2
