@@ -931,6 +931,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         const int64_t* rinfo = (const int64_t*)dT.rinfo;
         const double pbytes = (two_grids ? 3.0 : 2.0) * total_pos * csz;
         const int64_t nkeval = (int64_t)nts * Keval;
+        const bool ccf = J.ccf;
         NCF_TRY(emit(J, [=](hipStream_t s) {
             return launch_spread(stk, tile0, nts, ntiles, 4096, fp64, s, spread_bytes);
         }));
@@ -941,7 +942,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             NCF_TRY(emit(J, [=](hipStream_t s) { return fft_exec(fp, gp, cnt, +1, fp64, s); }));
         }
         NCF_TRY(emit(J, [=](hipStream_t s) {
-            return launch_product(stk, pos0, nts, total_pos, rinfo, fp64, s, pbytes);
+            return launch_product(stk, pos0, nts, total_pos, rinfo, ccf, spec_b, fp64, s, pbytes);
         }));
         for (auto& gq : groups) {
             const FftPlan fp = plans[splans[gq.first].g.N];

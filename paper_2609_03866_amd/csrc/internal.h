@@ -58,10 +58,20 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nblocks) {
     return (b % kXcds) * per + b / kXcds;
 }
 
-// First index i in [0, n) with (upper ? a[i] > key : a[i] >= key), else n.
-// Called by a whole wavefront: 64 probes per round.
+// Global-memory views of device pointers: accesses through them compile to
+// global (not flat) memory instructions, which do not wait on LDS traffic.
 template <typename T>
-__device__ __forceinline__ int64_t wave_search(const T* a, int64_t n, T key, bool upper) {
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> gbl(T* p) {
+    return (gptr<T>)p;
+}
+
+// First index i in [0, n) with (upper ? a[i] > key : a[i] >= key), else n.
+// Called by a whole wavefront: 64 probes per round. `a` is in global memory.
+template <typename T>
+__device__ __forceinline__ int64_t wave_search(const T* a_, int64_t n, T key, bool upper) {
+    const gptr<const T> a = gbl(a_);
     const int lane = threadIdx.x & 63;
     int64_t lo = 0, hi = n;
     while (hi > lo) {
@@ -254,8 +264,11 @@ int fft_exec(const FftPlan& plan, void* const* d_grids, int count, int sign, boo
 int64_t fft_position(const FftPlan& plan, int64_t k);
 
 // A5 spectral product (in place, digit-reversed order)
+// All tasks of one launch share the mode: ACF or CCF, with or without the
+// unit-weight (pair-count) channel.
 int launch_product(const SpecTask* d_tasks, const int64_t* d_pos0, int ntasks, int64_t total,
-                   const int64_t* d_radix_info, bool fp64, hipStream_t st, double bytes);
+                   const int64_t* d_radix_info, bool ccf, bool with_b, bool fp64, hipStream_t st,
+                   double bytes);
 
 // ------------------------------------------------------------ A8 output
 struct NormTask {

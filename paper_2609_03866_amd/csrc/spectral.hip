@@ -110,12 +110,13 @@ __device__ void gather_set(R (&acc)[kCellsPerThread], R (&accu)[kCellsPerThread]
     for (int64_t base = p0; base < p1; base += kPtsChunk) {
         const int np = (int)min((int64_t)kPtsChunk, p1 - base);
         __syncthreads();
+        const gptr<const double> tg = gbl(t);
         for (int i = tid; i < np; i += kThreads) {
-            const double u = (t[base + i] - t_ref) * scale;  // FP64 grid coordinate
+            const double u = (tg[base + i] - t_ref) * scale;  // FP64 grid coordinate
             const double cf = floor(u);
             P.cell[i] = (int)((int64_t)cf - c0);
             P.frac[i] = (R)(u - cf);
-            P.val[i] = vd ? (R)vd[base + i] : (R)vf[base + i];
+            P.val[i] = vd ? (R)gbl(vd)[base + i] : (R)gbl(vf)[base + i];
         }
         __syncthreads();
         // first staged point whose cell can reach cell cb: cell >= cb - W - 1
@@ -208,12 +209,14 @@ k_spread(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ tile0, 
                              k2);
     }
     // stage the tile through LDS for a coalesced write (two halves, so the
-    // staging fits the point buffer)
-    static_assert(sizeof(PtsLds<R>) >= sizeof(C2) * kTile / 2, "LDS staging too small");
+    // staging fits the point buffer); one pad slot per 16 cells keeps the
+    // threads' 16-cell runs on different banks
+    static_assert(sizeof(PtsLds<R>) >= sizeof(C2) * (kTile / 2 + kTile / 32),
+                  "LDS staging too small");
     C2* out = reinterpret_cast<C2*>(&P);
     const int ngrids = (T.ccf && T.with_b) ? 2 : 1;
     for (int gsel = 0; gsel < ngrids; ++gsel) {
-        C2* grid = reinterpret_cast<C2*>(gsel == 0 ? T.grid : T.gridb) + c0;
+        const gptr<R> grid = gbl(reinterpret_cast<R*>(gsel == 0 ? T.grid : T.gridb) + 2 * c0);
         for (int half = 0; half < 2; ++half) {
             __syncthreads();
             const int hbase = half * (kTile / 2);
@@ -224,11 +227,15 @@ k_spread(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ tile0, 
                     C2 v;
                     v.x = gsel == 0 ? re[q] : u0[q];
                     v.y = gsel == 0 ? im[q] : u1[q];
-                    out[tb + q] = v;
+                    out[tb + q + (tb >> 4)] = v;
                 }
             }
             __syncthreads();
-            for (int i = threadIdx.x; i < kTile / 2; i += kThreads) grid[hbase + i] = out[i];
+            for (int i = threadIdx.x; i < kTile / 2; i += kThreads) {
+                const C2 v = out[i + (i >> 4)];
+                grid[2 * (hbase + i)] = v.x;
+                grid[2 * (hbase + i) + 1] = v.y;
+            }
         }
     }
 }
@@ -283,6 +290,117 @@ __device__ __forceinline__ double lag_kernel_ft(int kern, double f, double h) {
     return sin(2.0 * M_PI * h * f) / (M_PI * f);
 }
 
+// complex element i of a global-memory grid of R pairs
+template <typename C2, typename R>
+__device__ __forceinline__ C2 cld(gptr<R> g, int64_t i) {
+    C2 v;
+    v.x = g[2 * i];
+    v.y = g[2 * i + 1];
+    return v;
+}
+template <typename C2, typename R>
+__device__ __forceinline__ void cst(gptr<R> g, int64_t i, C2 v) {
+    g[2 * i] = v.x;
+    g[2 * i + 1] = v.y;
+}
+
+template <typename R>
+struct ProductCtx {
+    gptr<R> Z;
+    gptr<R> U;
+    int64_t N, M;
+    double L, h, s;
+    int32_t kern;
+};
+
+// Product at one owned position p (partner pp = position of -k); z*/u* are
+// the values loaded at p and pp. Writes Z[p] (and Z[pp]) and adds the lag-0
+// partial sums.
+template <typename R, bool CCF, bool WB>
+__device__ __forceinline__ void product_item(const ProductCtx<R>& X, const RadixInfo& ri,
+                                             int64_t p, int64_t pp, typename Cplx<R>::T a,
+                                             typename Cplx<R>::T b, typename Cplx<R>::T va,
+                                             typename Cplx<R>::T vb, double (&sacc)[4]) {
+    using C2 = typename Cplx<R>::T;
+    const int64_t N = X.N;
+    const int64_t k = freq_of_pos(p, ri);
+    const int64_t m = k <= N / 2 ? k : k - N;
+    const double md = (double)m;
+    const double Nd = (double)N;
+    const double L = X.L, h = X.h, s = X.s;
+    const bool keep = (m <= X.M && m >= -X.M);
+    // phihat(m/L) / (L Psi^3) and phihat(m/L) / (L Psi^2) with
+    // Psi(m/N) = sqrt(2 pi) s exp(-2 pi^2 s^2 m^2 / N^2)
+    const double a_psi = 2.0 * M_PI * M_PI * s * s * md * md / (Nd * Nd);
+    double f3 = 0.0, f2 = 0.0;
+    if (keep) {
+        const double c3 = 1.0 / (L * 15.749609945722419 * s * s * s);
+        const double c2 = 1.0 / (L * 6.283185307179586 * s * s);
+        if (X.kern == NCF_GAUSSIAN) {
+            const double a_h = 2.0 * M_PI * M_PI * h * h * (md / L) * (md / L);
+            if (sizeof(R) == 4) {
+                f3 = c3 * exp_split(3.0 * a_psi - a_h);
+                if (CCF) f2 = c2 * exp_split(2.0 * a_psi - a_h);
+            } else {
+                f3 = c3 * exp(3.0 * a_psi - a_h);
+                if (CCF) f2 = c2 * exp(2.0 * a_psi - a_h);
+            }
+        } else {
+            const double ker = lag_kernel_ft<R>(X.kern, md / L, h);
+            f3 = c3 * ker * exp(3.0 * a_psi);
+            f2 = c2 * ker * exp(2.0 * a_psi);
+        }
+    }
+    if (!CCF && !WB) {
+        const double pw = (double)a.x * a.x + (double)a.y * a.y;
+        C2 o;
+        o.x = (R)(f3 * pw);
+        o.y = (R)0;
+        cst(X.Z, p, o);
+        return;
+    }
+    // the two real sequences packed in Z: A = (Z_m + conj Z_-m)/2,
+    // B = (Z_m - conj Z_-m)/(2i)
+    const double ar = 0.5 * ((double)a.x + b.x), ai = 0.5 * ((double)a.y - b.y);
+    const double br = 0.5 * ((double)a.y + b.y), bi = -0.5 * ((double)a.x - b.x);
+    const double mult = (pp != p) ? 2.0 : 1.0;
+    C2 o, oc;
+    if (!CCF) {
+        // ACF with b: A = X (values), B = W (unit weights); G_N = |X|^2, G_B = |W|^2
+        const double gn = ar * ar + ai * ai, gbb = br * br + bi * bi;
+        o.x = (R)(f3 * gn);
+        o.y = (R)(f3 * gbb);
+        oc = o;
+    } else {
+        // CCF: G_N = conj(X) Y
+        const double gr = ar * br + ai * bi;
+        const double gi = ar * bi - ai * br;
+        sacc[0] += mult * f2 * (ar * ar + ai * ai);
+        sacc[1] += mult * f2 * (br * br + bi * bi);
+        if (!WB) {
+            o.x = (R)(f3 * gr);
+            o.y = (R)(f3 * gi);
+            oc.x = o.x;
+            oc.y = -o.y;
+        } else {
+            // unit-weight grid: G_B = conj(U_x) U_y
+            const double xr = 0.5 * ((double)va.x + vb.x), xi = 0.5 * ((double)va.y - vb.y);
+            const double yr = 0.5 * ((double)va.y + vb.y), yi = -0.5 * ((double)va.x - vb.x);
+            const double hr = xr * yr + xi * yi;
+            const double hi = xr * yi - xi * yr;
+            sacc[2] += mult * f2 * (xr * xr + xi * xi);
+            sacc[3] += mult * f2 * (yr * yr + yi * yi);
+            // G_N + i G_B at m, conj(G_N) + i conj(G_B) at -m
+            o.x = (R)(f3 * (gr - hi));
+            o.y = (R)(f3 * (gi + hr));
+            oc.x = (R)(f3 * (gr + hi));
+            oc.y = (R)(f3 * (hr - gi));
+        }
+    }
+    cst(X.Z, p, o);
+    if (pp != p) cst(X.Z, pp, oc);
+}
+
 // In-place product on the digit-reversed spectrum. Without the unit-weight
 // channel: ACF -> phihat |X|^2 / (L Psi^3); CCF -> phihat conj(X) Y / (L Psi^3)
 // after unpacking X, Y from the packed grid. With it (with_b) the same
@@ -291,7 +409,7 @@ __device__ __forceinline__ double lag_kernel_ft(int kern, double f, double h) {
 // Hermitian, so the inverse transform returns N(tau) in the real part and
 // b(tau) in the imaginary part. CCF blocks also reduce the lag-0 sums
 // S_xx, S_yy (and B_xx, B_yy) = sum_m phihat |.|^2 / (L Psi^2).
-template <typename R>
+template <typename R, int MODE>
 __global__ void __launch_bounds__(kThreads)
 k_product(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pos0, int ntasks,
           int64_t total, const RadixInfo* __restrict__ rinfo) {
@@ -303,102 +421,54 @@ k_product(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pos0, 
     const SpecTask& T = tasks[ti];
     const RadixInfo ri = rinfo[ti];
     const int64_t N = T.N;
-    C2* Z = reinterpret_cast<C2*>(T.grid);
-    C2* U = reinterpret_cast<C2*>(T.gridb);
-    const double L = T.L, h = T.h, s = T.s;
-    const double Nd = (double)N;
+    const gptr<R> Z = gbl(reinterpret_cast<R*>(T.grid));
+    const gptr<R> U = gbl(reinterpret_cast<R*>(T.gridb));
     double sacc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int it = 0; it < kTile / kThreads; ++it) {
-        const int64_t p = gb - T.pos0 + it * kThreads + threadIdx.x;
-        const int64_t k = freq_of_pos(p, ri);
-        const int64_t m = k <= N / 2 ? k : k - N;
-        const double md = (double)m;
-        const bool keep = (m <= T.M && m >= -T.M);
-        // phihat(m/L) / (L Psi^3) and phihat(m/L) / (L Psi^2) with
-        // Psi(m/N) = sqrt(2 pi) s exp(-2 pi^2 s^2 m^2 / N^2)
-        const double a_psi = 2.0 * M_PI * M_PI * s * s * md * md / (Nd * Nd);
-        double f3 = 0.0, f2 = 0.0;
-        if (keep) {
-            const double c3 = 1.0 / (L * 15.749609945722419 * s * s * s);
-            const double c2 = 1.0 / (L * 6.283185307179586 * s * s);
-            if (T.kern == NCF_GAUSSIAN) {
-                const double a_h = 2.0 * M_PI * M_PI * h * h * (md / L) * (md / L);
-                if (sizeof(R) == 4) {
-                    f3 = c3 * exp_split(3.0 * a_psi - a_h);
-                    f2 = c2 * exp_split(2.0 * a_psi - a_h);
-                } else {
-                    f3 = c3 * exp(3.0 * a_psi - a_h);
-                    f2 = c2 * exp(2.0 * a_psi - a_h);
-                }
-            } else {
-                const double ker = lag_kernel_ft<R>(T.kern, md / L, h);
-                f3 = c3 * ker * exp(3.0 * a_psi);
-                f2 = c2 * ker * exp(2.0 * a_psi);
+    // Each (m, -m) pair is handled by the thread that owns the position of
+    // its frequency k in [0, N/2]. The top bit of k is bit 11 of the position
+    // (the last pass has radix 4096), so the owned positions are the first
+    // half of every 4096-position tile, plus k = N/2 at position 2048 of
+    // tile 0. A thread issues the loads of its positions before any store:
+    // pairs are disjoint, so nothing is read after being written.
+    constexpr bool CCF = (MODE & 2) != 0;
+    constexpr bool WB = (MODE & 1) != 0;
+    constexpr bool two = CCF || WB;    // pairs (m, -m) needed
+    constexpr bool unit = CCF && WB;   // second (unit-weight) grid
+    const int64_t tb = gb - T.pos0;    // first position of the tile in its grid
+    constexpr int kIt = kTile / 2 / kThreads;
+    const ProductCtx<R> X{Z, U, N, T.M, T.L, T.h, T.s, T.kern};
+    for (int half = 0; half < (two ? 1 : 2); ++half) {
+        int64_t pb[kIt];
+        C2 za[kIt], zb[kIt], ua[kIt], ub[kIt];
+        const int64_t p0 = tb + half * (kTile / 2) + threadIdx.x;
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const int64_t p = p0 + it * kThreads;
+            za[it] = cld<C2>(Z, p);
+            if constexpr (two) {
+                pb[it] = pos_of_freq((N - freq_of_pos(p, ri)) & (N - 1), ri);
+                zb[it] = cld<C2>(Z, pb[it]);
+            }
+            if constexpr (unit) {
+                ua[it] = cld<C2>(U, p);
+                ub[it] = cld<C2>(U, pb[it]);
             }
         }
-        if (!T.ccf && !T.with_b) {
-            const C2 z = Z[p];
-            const double pw = (double)z.x * z.x + (double)z.y * z.y;
-            C2 o;
-            o.x = (R)(f3 * pw);
-            o.y = (R)0;
-            Z[p] = o;
-        } else if (k <= N - k || k == 0) {
-            // pair (m, -m); partner position of frequency -m
-            const int64_t kp = (N - k) & (N - 1);
-            const int64_t pp = pos_of_freq(kp, ri);
-            const C2 za = Z[p];
-            const C2 zb = Z[pp];
-            // the two real sequences packed in Z: A = (Z_m + conj Z_-m)/2,
-            // B = (Z_m - conj Z_-m)/(2i)
-            const double ar = 0.5 * ((double)za.x + zb.x), ai = 0.5 * ((double)za.y - zb.y);
-            const double br = 0.5 * ((double)za.y + zb.y), bi = -0.5 * ((double)za.x - zb.x);
-            const double mult = (pp != p) ? 2.0 : 1.0;
-            C2 o, oc;
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-            if (!T.ccf) {
-                // ACF with b: A = X (values), B = W (unit weights); G_N = |X|^2, G_B = |W|^2
-                const double gn = ar * ar + ai * ai, gbb = br * br + bi * bi;
-                o.x = (R)(f3 * gn);
-                o.y = (R)(f3 * gbb);
-                oc = o;
-            } else {
-                // CCF: G_N = conj(X) Y
-                const double gr = ar * br + ai * bi;
-                const double gi = ar * bi - ai * br;
-                s0 = mult * f2 * (ar * ar + ai * ai);
-                s1 = mult * f2 * (br * br + bi * bi);
-                if (!T.with_b) {
-                    o.x = (R)(f3 * gr);
-                    o.y = (R)(f3 * gi);
-                    oc.x = o.x;
-                    oc.y = -o.y;
-                } else {
-                    // unit-weight grid: G_B = conj(U_x) U_y
-                    const C2 ua = U[p];
-                    const C2 ub = U[pp];
-                    const double xr = 0.5 * ((double)ua.x + ub.x), xi = 0.5 * ((double)ua.y - ub.y);
-                    const double yr = 0.5 * ((double)ua.y + ub.y), yi = -0.5 * ((double)ua.x - ub.x);
-                    const double hr = xr * yr + xi * yi;
-                    const double hi = xr * yi - xi * yr;
-                    s2 = mult * f2 * (xr * xr + xi * xi);
-                    s3 = mult * f2 * (yr * yr + yi * yi);
-                    // G_N + i G_B at m, conj(G_N) + i conj(G_B) at -m
-                    o.x = (R)(f3 * (gr - hi));
-                    o.y = (R)(f3 * (gi + hr));
-                    oc.x = (R)(f3 * (gr + hi));
-                    oc.y = (R)(f3 * (hr - gi));
-                }
-            }
-            Z[p] = o;
-            if (pp != p) Z[pp] = oc;
-            sacc[0] += s0;
-            sacc[1] += s1;
-            sacc[2] += s2;
-            sacc[3] += s3;
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const int64_t p = p0 + it * kThreads;
+            product_item<R, CCF, WB>(X, ri, p, two ? pb[it] : p, za[it], two ? zb[it] : za[it],
+                                     unit ? ua[it] : za[it], unit ? ub[it] : za[it], sacc);
         }
     }
-    if (T.ccf) {
+    if (two && tb == 0 && threadIdx.x == 0) {  // k = N/2, its own partner
+        const int64_t p = kTile / 2;
+        const int64_t pp = pos_of_freq((N - freq_of_pos(p, ri)) & (N - 1), ri);
+        const C2 a = cld<C2>(Z, p), b = cld<C2>(Z, pp);
+        const C2 c = unit ? cld<C2>(U, p) : a, d = unit ? cld<C2>(U, pp) : a;
+        product_item<R, CCF, WB>(X, ri, p, pp, a, b, c, d, sacc);
+    }
+    if (CCF) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) red[q][threadIdx.x] = sacc[q];
         __syncthreads();
@@ -497,16 +567,29 @@ int launch_spread(const SpecTask* d_tasks, const int64_t* d_tile0, int ntasks, i
     return NCF_OK;
 }
 
+template <typename R>
+void (*product_kernel(int mode))(const SpecTask*, const int64_t*, int, int64_t,
+                                  const RadixInfo*) {
+    switch (mode & 3) {
+        case 0: return k_product<R, 0>;
+        case 1: return k_product<R, 1>;
+        case 2: return k_product<R, 2>;
+        default: return k_product<R, 3>;
+    }
+}
+
 int launch_product(const SpecTask* d_tasks, const int64_t* d_pos0, int ntasks, int64_t total,
-                   const int64_t* d_radix_info, bool fp64, hipStream_t st, double bytes) {
+                   const int64_t* d_radix_info, bool ccf, bool with_b, bool fp64, hipStream_t st,
+                   double bytes) {
     if (total <= 0) return NCF_OK;
     const RadixInfo* ri = reinterpret_cast<const RadixInfo*>(d_radix_info);
+    const int mode = (ccf ? 2 : 0) | (with_b ? 1 : 0);
     ProfScope p(st, fp64 ? "product_f64" : "product_f32", bytes, "bytes");
     if (fp64)
-        hipLaunchKernelGGL(k_product<double>, dim3((unsigned)ceil_div(total, kTile)),
+        hipLaunchKernelGGL(product_kernel<double>(mode), dim3((unsigned)ceil_div(total, kTile)),
                            dim3(kThreads), 0, st, d_tasks, d_pos0, ntasks, total, ri);
     else
-        hipLaunchKernelGGL(k_product<float>, dim3((unsigned)ceil_div(total, kTile)),
+        hipLaunchKernelGGL(product_kernel<float>(mode), dim3((unsigned)ceil_div(total, kTile)),
                            dim3(kThreads), 0, st, d_tasks, d_pos0, ntasks, total, ri);
     NCF_CHECK_LAUNCH();
     return NCF_OK;

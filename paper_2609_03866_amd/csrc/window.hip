@@ -351,30 +351,32 @@ k_window(const WinTask* __restrict__ tasks, const int64_t* __restrict__ item0, i
     const int o_rw = 0;
     const int dp = cap + 8;
     const int o_ro = QR * (cap + 8);
+    const gdp gt = (gdp)T.t, gs = (gdp)T.s, gvo = (gdp)T.vo, gwo = (gdp)T.wo;
+    const gdp ga1 = (gdp)A1g, ga2 = (gdp)A2g;
     if (RECT && fits) {
         for (int i = tid; i < len + 8; i += kThreads) {
             double* r = g_win_lds + o_rw + i;
-            r[0] = i < len ? T.t[tlo + i] : kInf;
-            if (NUMER) r[dp] = i <= len ? T.pv[tlo + i] : 0.0;
-            if (WTD) r[(QR - 1) * dp] = i <= len ? T.pw[tlo + i] : 0.0;
+            r[0] = i < len ? gt[tlo + i] : kInf;
+            if (NUMER) r[dp] = i <= len ? ga1[tlo + i] : 0.0;
+            if (WTD) r[(QR - 1) * dp] = i <= len ? ga2[tlo + i] : 0.0;
         }
         for (int i = tid; i <= nj; i += kThreads) {
             double* r = g_win_lds + o_ro + QR * i;
-            r[0] = i < nj ? T.s[j0 + i] : 0.0;
-            if (NUMER) r[1] = i < nj ? T.vo[j0 + i] : 0.0;
-            if (WTD) r[QR - 1] = i < nj ? T.wo[j0 + i] : 0.0;
+            r[0] = i < nj ? gs[j0 + i] : 0.0;
+            if (NUMER) r[1] = i < nj ? gvo[j0 + i] : 0.0;
+            if (WTD) r[QR - 1] = i < nj ? gwo[j0 + i] : 0.0;
         }
     } else if (fits) {
         for (int i = tid; i < len + 8; i += kThreads)
-            g_win_lds[o_t + i] = i < len ? T.t[tlo + i] : kInf;
+            g_win_lds[o_t + i] = i < len ? gt[tlo + i] : kInf;
         if (HAS_A1)
-            for (int i = tid; i < a_len; i += kThreads) g_win_lds[o_a1 + i] = A1g[tlo + i];
+            for (int i = tid; i < a_len; i += kThreads) g_win_lds[o_a1 + i] = ga1[tlo + i];
         if (HAS_A2)
-            for (int i = tid; i < a_len; i += kThreads) g_win_lds[o_a2 + i] = A2g[tlo + i];
+            for (int i = tid; i < a_len; i += kThreads) g_win_lds[o_a2 + i] = ga2[tlo + i];
         for (int i = tid; i < nj; i += kThreads) {
-            g_win_lds[o_s + i] = T.s[j0 + i];
-            if (NUMER) g_win_lds[o_vo + i] = T.vo[j0 + i];
-            if (WTD) g_win_lds[o_wo + i] = T.wo[j0 + i];
+            g_win_lds[o_s + i] = gs[j0 + i];
+            if (NUMER) g_win_lds[o_vo + i] = gvo[j0 + i];
+            if (WTD) g_win_lds[o_wo + i] = gwo[j0 + i];
         }
     }
     __syncthreads();
