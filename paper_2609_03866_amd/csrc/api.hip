@@ -728,6 +728,12 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     // ------------------------------------------------ phase 2 device workspace
     std::vector<void*> grids(nts), gridbs(nts, nullptr);
     std::vector<double*> numer(nts), bspec(nts, nullptr), spart(nts, nullptr);
+    int64_t ntiles_all = 0;
+    for (int i = 0; i < nts; ++i) ntiles_all += splans[i].g.N / 4096;
+    // sample ranges of the spreading tiles: one pass over the samples when
+    // there are many tiles; with a few, each spreading workgroup searches
+    const bool bounds_pass = ntiles_all > 4096;
+    int64_t* d_rng = nullptr;  // [tiles][4] sample ranges of every spreading tile
     double *d_c = nullptr, *d_b = nullptr;
     int64_t* d_cnt = nullptr;
     auto layout2 = [&](Arena& ar) {
@@ -741,6 +747,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         double* numer_all = ar.take<double>((size_t)std::max(nts, 1) * std::max(Keval, 1));
         double* bspec_all =
             spec_b ? ar.take<double>((size_t)std::max(nts, 1) * std::max(Keval, 1)) : nullptr;
+        d_rng = (nts > 0 && bounds_pass) ? ar.take<int64_t>(4 * (size_t)ntiles_all) : nullptr;
         for (int i = 0; i < nts; ++i) {
             grids[i] = ar.take<char>((size_t)splans[i].g.N * csz);
             if (two_grids) gridbs[i] = ar.take<char>((size_t)splans[i].g.N * csz);
@@ -772,6 +779,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         double* dl;
         SpecTask* st;
         int64_t *tile0, *pos0, *sk0;
+        int32_t* smap;
         int32_t* rinfo;
         double* ev;
         void** gfwd;
@@ -789,6 +797,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         dT.tile0 = tb.take<int64_t>(nts + 1, &hT.tile0);
         dT.pos0 = tb.take<int64_t>(nts + 1, &hT.pos0);
         dT.sk0 = tb.take<int64_t>(nts + 1, &hT.sk0);
+        dT.smap = tb.take<int32_t>(nsd, &hT.smap);
         dT.rinfo = tb.take<int32_t>(6 * (size_t)nts, &hT.rinfo);
         dT.ev = tb.take<double>(Keval, &hT.ev);
         dT.gfwd = tb.take<void*>(2 * (size_t)nts, &hT.gfwd);
@@ -819,7 +828,8 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
 
     // spectral tables
     std::map<int64_t, FftPlan> plans;
-    int64_t total_pos = 0, ntiles = 0;
+    int64_t total_pos = 0, ntiles = 0, total_samp = 0;
+    for (int q = 0; q < nsd; ++q) hT.smap[q] = -1;
     double spread_bytes = 0.0;
     std::vector<std::pair<int, int>> groups;  // (first task, count) per grid size
     for (int i = 0; i < nts; ++i) {
@@ -852,8 +862,11 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         T.bspec = bspec[i];
         T.tile0 = ntiles;
         T.ntiles = P.g.N / 4096;
+        T.tile_rng = d_rng ? d_rng + 4 * ntiles : nullptr;
         ntiles += T.ntiles;
-        T.tile_rng = nullptr;
+        total_samp += T.n0 + T.n1;
+        hT.smap[J.set[0].sd0 + P.prob] = 2 * i;
+        if (J.ccf) hT.smap[J.set[1].sd0 + P.prob] = 2 * i + 1;
         T.lags = dT.ev;
         T.K_eval = Keval;
         T.numer = numer[i];
@@ -932,6 +945,13 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         const double pbytes = (two_grids ? 3.0 : 2.0) * total_pos * csz;
         const int64_t nkeval = (int64_t)nts * Keval;
         const bool ccf = J.ccf;
+        const int32_t* smap = dT.smap;
+        const Chunk* dch = d_ch;
+        const double tb_bytes = 8.0 * (double)total_samp;
+        if (bounds_pass)
+            NCF_TRY(emit(J, [=](hipStream_t s) {
+                return launch_tile_bounds(stk, dch, nch, smap, s, tb_bytes);
+            }));
         NCF_TRY(emit(J, [=](hipStream_t s) {
             return launch_spread(stk, tile0, nts, ntiles, 4096, fp64, s, spread_bytes);
         }));
@@ -1812,6 +1832,8 @@ int ncf_diag_type1(int64_t n, const double* t, const double* v, double t_ref, do
     int64_t* rng;
     SpecTask* dtask;
     int64_t* dtile0;
+    Chunk* dch;
+    int32_t* dmap;
     void** dg;
     NCF_TRY_HIP(hipMalloc((void**)&dt, sizeof(double) * n));
     NCF_TRY_HIP(hipMalloc(&dv, (fp64 ? 8 : 4) * n));
@@ -1819,6 +1841,11 @@ int ncf_diag_type1(int64_t n, const double* t, const double* v, double t_ref, do
     NCF_TRY_HIP(hipMalloc((void**)&rng, sizeof(int64_t) * 4 * (N / 4096)));
     NCF_TRY_HIP(hipMalloc((void**)&dtask, sizeof(SpecTask)));
     NCF_TRY_HIP(hipMalloc((void**)&dtile0, sizeof(int64_t) * 2));
+    std::vector<Chunk> hch;
+    for (int64_t b = 0; b < n; b += kChunk) hch.push_back(Chunk{b, std::min(b + kChunk, n), 0, 0});
+    const int32_t hmap = 0;  // series 0 -> task 0, set 0
+    NCF_TRY_HIP(hipMalloc((void**)&dch, sizeof(Chunk) * hch.size()));
+    NCF_TRY_HIP(hipMalloc((void**)&dmap, sizeof(int32_t)));
     NCF_TRY_HIP(hipMalloc((void**)&dg, sizeof(void*)));
     NCF_TRY_HIP(hipMemcpy(dt, t, sizeof(double) * n, hipMemcpyHostToDevice));
     if (fp64) {
@@ -1845,8 +1872,10 @@ int ncf_diag_type1(int64_t n, const double* t, const double* v, double t_ref, do
     int64_t t0h[2] = {0, T.ntiles};
     NCF_TRY_HIP(hipMemcpy(dtask, &T, sizeof T, hipMemcpyHostToDevice));
     NCF_TRY_HIP(hipMemcpy(dtile0, t0h, sizeof t0h, hipMemcpyHostToDevice));
+    NCF_TRY_HIP(hipMemcpy(dch, hch.data(), sizeof(Chunk) * hch.size(), hipMemcpyHostToDevice));
+    NCF_TRY_HIP(hipMemcpy(dmap, &hmap, sizeof hmap, hipMemcpyHostToDevice));
     NCF_TRY_HIP(hipMemcpy(dg, &grid, sizeof(void*), hipMemcpyHostToDevice));
-    int rc = launch_tile_ranges(dtask, dtile0, 1, T.ntiles, 4096, st);
+    int rc = launch_tile_bounds(dtask, dch, (int)hch.size(), dmap, st, 8.0 * n);
     if (rc == NCF_OK) rc = launch_spread(dtask, dtile0, 1, T.ntiles, 4096, fp64, st, 0.0);
     FftPlan plan;
     if (rc == NCF_OK) rc = fft_plan(N, fp64, &plan, st);
@@ -1879,6 +1908,8 @@ int ncf_diag_type1(int64_t n, const double* t, const double* v, double t_ref, do
     (void)hipFree(rng);
     (void)hipFree(dtask);
     (void)hipFree(dtile0);
+    (void)hipFree(dch);
+    (void)hipFree(dmap);
     (void)hipFree(dg);
     return rc;
 }

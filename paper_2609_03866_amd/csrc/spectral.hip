@@ -24,6 +24,8 @@
 // samples that can reach it (sorted times -> contiguous index range) in LDS,
 // and every thread sums the samples near its own cells. No atomics; one
 // coalesced write per cell; deterministic.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace ncf {
@@ -70,26 +72,60 @@ __device__ __forceinline__ int64_t lower_bound_d(const double* a, int64_t n, dou
     return lo;
 }
 
-// Sample index ranges that can reach each tile: [p0, p1) per point set.
-__global__ void k_tile_ranges(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ tile0,
-                              int ntasks, int64_t ntiles) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ntiles) return;
-    const int ti = (int)find_task(tile0, ntasks, g);
-    const SpecTask& T = tasks[ti];
-    const int64_t tile = g - T.tile0;
-    const double c0 = (double)(tile * kTile);
-    const double inv_scale = T.L / (double)T.N;  // time per cell
-    const double lo_t = T.t_ref + (c0 - T.W - 2.0) * inv_scale;
-    const double hi_t = T.t_ref + (c0 + kTile + T.W + 2.0) * inv_scale;
-    int64_t* r = T.tile_rng + 4 * tile;
-    r[0] = lower_bound_d(T.t0, T.n0, lo_t);
-    r[1] = lower_bound_d(T.t0, T.n0, hi_t);
-    if (T.ccf) {
-        r[2] = lower_bound_d(T.t1, T.n1, lo_t);
-        r[3] = lower_bound_d(T.t1, T.n1, hi_t);
-    } else {
-        r[2] = r[3] = 0;
+// Sample index ranges [p0, p1) that reach each spreading tile, from one
+// coalesced pass over the sorted samples instead of a search per tile. With
+// u_i the FP64 grid coordinate of sample i, tile g (cells [gT, gT + T)) needs
+// the samples with u in [gT - W - 2, gT + T + W + 2) (one cell of slack past
+// the truncation radius). A(i) = floor((u_i + W + 2) / T) and
+// B(i) = floor((u_i - W - 2) / T) are non-decreasing in i, so
+// p0(g) = first i with A(i) >= g and p1(g) = first i with B(i) >= g + 1;
+// sample i writes p0 of the tiles g in (A(i-1), A(i)] and p1 of those with
+// g + 1 in (B(i-1), B(i)]. Every bound is written exactly once.
+// Tiles reached by a sample at grid coordinate u: A = floor((u + W + 2) / T)
+// is the last tile whose range starts at or before it, B = floor((u - W - 2)
+// / T) the last tile + 1 it closes. One expression for both kernels below.
+__device__ __forceinline__ void tile_reach(double u, double reach, int64_t& A, int64_t& B) {
+    constexpr double inv_tile = 1.0 / kTile;  // exact: a power of two
+    A = (int64_t)floor((u + reach) * inv_tile);
+    B = (int64_t)floor((u - reach) * inv_tile);
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_tile_bounds(const SpecTask* __restrict__ tasks, const Chunk* __restrict__ chunks,
+              const int32_t* __restrict__ series_map) {
+    // one workgroup per chunk of one series; lanes take consecutive samples
+    const Chunk ch = chunks[blockIdx.x];
+    const int32_t code = series_map[ch.series];  // 2 * task + set, or -1
+    if (code < 0) return;
+    const SpecTask& T = tasks[code >> 1];
+    const int set = code & 1;
+    const gptr<const double> t = gbl(set ? T.t1 : T.t0);
+    const double sc = (double)T.N / T.L;
+    const double reach = T.W + 2.0;
+    const int64_t nt = T.ntiles;
+    const gptr<int64_t> rng = gbl(T.tile_rng);
+    const int lane = threadIdx.x & 63;
+    for (int64_t b = ch.begin; b < ch.end; b += kThreads) {
+        const int64_t i = b + threadIdx.x;
+        const bool live = i < ch.end;
+        int64_t a1 = 0, b1 = 0;
+        if (live) tile_reach((t[i] - T.t_ref) * sc, reach, a1, b1);
+        // the previous sample's A, B from the neighbouring lane (same chunk,
+        // consecutive samples), recomputed by the first lane of each wave
+        int64_t a0 = __shfl_up(a1, 1), b0 = __shfl_up(b1, 1);
+        if (!live) continue;
+        if (i == 0) {
+            a0 = -1;
+            b0 = -1;
+        } else if (lane == 0) {
+            tile_reach((t[i - 1] - T.t_ref) * sc, reach, a0, b0);
+        }
+        // tiles past the last sample's reach are not written here: the
+        // spread derives their bounds (n) from the last sample itself
+        for (int64_t q = max(a0 + 1, (int64_t)0); q <= min(a1, nt - 1); ++q)
+            rng[4 * q + 2 * set] = i;
+        for (int64_t q = max(b0, (int64_t)0); q <= min(b1 - 1, nt - 1); ++q)
+            rng[4 * q + 2 * set + 1] = i;
     }
 }
 
@@ -165,9 +201,12 @@ k_spread(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ tile0, 
     const SpecTask& T = tasks[ti];
     const int64_t tile = g - T.tile0;
     const int64_t c0 = tile * kTile;
-    // sample index ranges that can reach this tile (sorted times)
-    __shared__ int64_t rng[4];
-    {
+    // sample index ranges that reach this tile: from k_tile_bounds (a tile
+    // past the last sample's reach has bound n, found from that sample), or
+    // for calls with few tiles by wave searches in this workgroup
+    __shared__ int64_t srng[4];
+    int64_t rng[4];
+    if (!T.tile_rng) {
         const int wave = threadIdx.x >> 6;
         const double inv_scale = T.L / (double)T.N;  // time per cell
         const double lo_t = T.t_ref + ((double)c0 - T.W - 2.0) * inv_scale;
@@ -177,8 +216,22 @@ k_spread(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ tile0, 
         if (wave == 1) r = wave_search<double>(T.t0, T.n0, hi_t, false);
         if (wave == 2) r = T.ccf ? wave_search<double>(T.t1, T.n1, lo_t, false) : 0;
         if (wave == 3) r = T.ccf ? wave_search<double>(T.t1, T.n1, hi_t, false) : 0;
-        if ((threadIdx.x & 63) == 0) rng[wave] = r;
+        if ((threadIdx.x & 63) == 0) srng[wave] = r;
         __syncthreads();
+        for (int q = 0; q < 4; ++q) rng[q] = srng[q];
+    } else {
+        const gptr<const int64_t> r = gbl((const int64_t*)T.tile_rng) + 4 * tile;
+        const double sc = (double)T.N / T.L;
+        const double reach = T.W + 2.0;
+        for (int set = 0; set < (T.ccf ? 2 : 1); ++set) {
+            const double* tp = set ? T.t1 : T.t0;
+            const int64_t n = set ? T.n1 : T.n0;
+            int64_t A, B;
+            tile_reach((gbl(tp)[n - 1] - T.t_ref) * sc, reach, A, B);
+            rng[2 * set] = tile > A ? n : r[2 * set];
+            rng[2 * set + 1] = tile + 1 > B ? n : r[2 * set + 1];
+        }
+        if (!T.ccf) rng[2] = rng[3] = 0;
     }
     const double scale = (double)T.N / T.L;
     const R W = (R)T.W;
@@ -534,16 +587,12 @@ SpreadParams spread_params(double sigma, double eps) {
     return p;
 }
 
-int launch_tile_ranges(const SpecTask* d_tasks, const int64_t* d_tile0, int ntasks,
-                       int64_t ntiles, int tile, hipStream_t st) {
-    if (tile != kTile) {
-        set_error("spread tile mismatch");
-        return NCF_E_UNSUPPORTED;
-    }
-    if (ntiles <= 0) return NCF_OK;
-    ProfScope p(st, "tile_ranges", 0.0, "bytes");
-    hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)ceil_div(ntiles, 128)), dim3(128), 0, st,
-                       d_tasks, d_tile0, ntasks, ntiles);
+int launch_tile_bounds(const SpecTask* d_tasks, const Chunk* d_chunks, int nchunks,
+                       const int32_t* d_series_map, hipStream_t st, double bytes) {
+    if (nchunks <= 0) return NCF_OK;
+    ProfScope p(st, "tile_bounds", bytes, "bytes");
+    hipLaunchKernelGGL(k_tile_bounds, dim3((unsigned)nchunks), dim3(kThreads), 0, st, d_tasks,
+                       d_chunks, d_series_map);
     NCF_CHECK_LAUNCH();
     return NCF_OK;
 }
