@@ -82,9 +82,12 @@ def to_dev(d):
     return out
 
 
+WINDOW_QUEUE = False  # --window-queue: queue dispatch of the window scans
+
+
 def run_one(d, precision="mixed", method="auto"):
     from paper_2609_03866_amd import ncf
-    kw = dict(precision=precision, method=method, with_count=True)
+    kw = dict(precision=precision, method=method, with_count=True, window_queue=WINDOW_QUEUE)
     if d["kind"] == "acf":
         return ncf.acf(d["t"], d["x"], d["lags"], d["kernel"], d["h"], err=d.get("err"), **kw)
     if d["kind"] == "ccf":
@@ -99,7 +102,7 @@ def run_one(d, precision="mixed", method="auto"):
 def make_plan(d, precision="mixed", method="auto"):
     """A plan over the workload's times (device tensors), replayed as a graph."""
     from paper_2609_03866_amd import ncf
-    kw = dict(precision=precision, method=method)
+    kw = dict(precision=precision, method=method, window_queue=WINDOW_QUEUE)
     if d["kind"] == "acf":
         return ncf.plan_acf(np.array([0, d["t"].numel()]), d["t"], d["lags"], d["kernel"],
                             d["h"], err=d.get("err"), **kw)
@@ -222,6 +225,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU path")
     ap.add_argument("--no-plan", action="store_true", help="skip the plan replay timing")
+    ap.add_argument("--window-queue", action="store_true",
+                    help="window scans as persistent workgroups on a device work queue")
     ap.add_argument("--oracle-series", type=int, default=64)
     ap.add_argument("--oracle-seconds", type=float, default=10.0,
                     help="repeat the oracle sample until it has run this long (>= 3 runs)")
@@ -229,6 +234,8 @@ def main():
                     help="first run a 256 MiB device fill and three 256 MiB device copies "
                          "(known byte counts for HBM counter calibration)")
     args = ap.parse_args()
+    global WINDOW_QUEUE
+    WINDOW_QUEUE = args.window_queue
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                           "(multi-GPU sharding is described in DESIGN.md, not built)"}))

@@ -98,6 +98,10 @@ typedef enum { NCF_AUTO = 0, NCF_SPECTRAL = 1, NCF_DIRECT = 2 } ncf_method_t;
 /* Plans only: replay the recorded launches one by one instead of as one
  * captured HIP graph. */
 #define NCF_PLAN_NO_GRAPH 0x2u
+/* Scheduling: run the window scans as persistent workgroups that pull
+ * (series, outer-sample tile, lag tile) work items from a device queue,
+ * instead of one workgroup per item. Results are identical. */
+#define NCF_WINDOW_QUEUE 0x4u
 
 typedef struct {
     uint32_t struct_size; /* sizeof(ncf_options_t) */

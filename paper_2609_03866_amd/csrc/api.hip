@@ -132,8 +132,28 @@ struct Staging {
 struct Resources {
     DevBuf ws[3];
     Staging stage[3];
+    unsigned long long* queue = nullptr;  // work-queue counter pairs, zeroed once
     bool exact = false;  // plan: allocate what is asked, no growth slack
 };
+
+constexpr int kQueuePairs = 4;
+
+// Counter pairs of the queue-dispatched launches (zeroed once at allocation;
+// each launch leaves its pair zeroed).
+int ensure_queue(Resources& R, unsigned long long** out) {
+    if (!R.queue) {
+        if (hipMalloc((void**)&R.queue, sizeof(unsigned long long) * 2 * kQueuePairs) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            R.queue = nullptr;
+            set_error("work-queue counter allocation failed");
+            return NCF_E_NOMEM;
+        }
+        NCF_TRY_HIP(hipMemset(R.queue, 0, sizeof(unsigned long long) * 2 * kQueuePairs));
+    }
+    *out = R.queue;
+    return NCF_OK;
+}
 std::mutex g_ws_mu;
 std::map<int, Resources> g_res;  // one-shot calls, per device
 
@@ -183,6 +203,8 @@ int ensure_stage(Resources& R, int phase, size_t bytes, Staging** out) {
 }
 
 void free_resources(Resources& R) {
+    if (R.queue) (void)hipFree(R.queue);
+    R.queue = nullptr;
     for (auto& b : R.ws) {
         if (b.ptr) (void)hipFree(b.ptr);
         b = DevBuf{};
@@ -209,7 +231,7 @@ struct Arena {
 
 // -------------------------------------------------------------- the job
 
-constexpr int64_t kChunk = 2048;  // samples per moments chunk
+constexpr int64_t kChunk = kMomentChunk;  // samples per moments chunk
 
 // Reserve table slots: device address for kernels, host address for filling.
 struct Tables {
@@ -247,6 +269,7 @@ struct Job {
     int kern = NCF_GAUSSIAN;
     std::vector<double> h;     // per problem
     std::vector<double> lags;  // host copy, K
+    const double* lags_dev = nullptr;  // device lags still to be copied (phase 1)
     int64_t K = 0;
     double* c = nullptr;       // user outputs
     double* b = nullptr;
@@ -265,6 +288,15 @@ struct Job {
     std::vector<std::function<int(hipStream_t)>>* rec = nullptr;
     bool plan_build = false;   // statuses are those of the host checks only
 };
+
+int check_lags(const Job& J) {
+    for (double v : J.lags)
+        if (!std::isfinite(v)) {
+            set_error("non-finite lag");
+            return NCF_E_INVALID_ARG;
+        }
+    return NCF_OK;
+}
 
 // Enqueue a launch now and, when a plan is being built, keep it for replay.
 template <class F>
@@ -457,6 +489,8 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         t1.take<Chunk>(nch, &hc);
         t1.take<IoBlock>(1, &hio);
         t1.take<SeriesStat>(nsd, &hst);
+        double* hl;
+        t1.take<double>(J.lags_dev ? J.K : 0, &hl);
     }
     NCF_TRY(ensure_stage(R, 0, t1.off, &stg1));
     t1 = Tables{stg1->h, stg1->d, 0};
@@ -468,6 +502,8 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     Chunk* d_ch = t1.take<Chunk>(nch, &h_ch);
     IoBlock* d_io1 = t1.take<IoBlock>(1, &h_io1);
     t1.take<SeriesStat>(nsd, &h_stats);  // host landing area of the statistics
+    double* h_lags;
+    t1.take<double>(J.lags_dev ? J.K : 0, &h_lags);  // and of device lags
     std::memcpy(h_sd, sdesc.data(), sizeof(SeriesDesc) * nsd);
     std::memcpy(h_ch, chunks.data(), sizeof(Chunk) * nch);
     *h_io1 = IoBlock{};
@@ -487,7 +523,15 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     NCF_TRY(emit(J, [ma](hipStream_t s) { return launch_moments(ma, s); }));
     NCF_TRY_HIP(hipMemcpyAsync(h_stats, d_stats, sizeof(SeriesStat) * nsd, hipMemcpyDeviceToHost,
                                J.st));
+    if (J.lags_dev)
+        NCF_TRY_HIP(hipMemcpyAsync(h_lags, J.lags_dev, sizeof(double) * J.K,
+                                   hipMemcpyDeviceToHost, J.st));
     NCF_TRY_HIP(hipStreamSynchronize(J.st));
+    if (J.lags_dev) {
+        std::memcpy(J.lags.data(), h_lags, sizeof(double) * J.K);
+        J.lags_dev = nullptr;
+        NCF_TRY(check_lags(J));
+    }
     std::vector<SeriesStat> stats(h_stats, h_stats + nsd);
     auto stat_of = [&](int si, int64_t s) -> const SeriesStat& {
         return stats[J.set[si].sd0 + s];
@@ -921,15 +965,19 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     NCF_TRY_HIP(hipMemcpyAsync(stg2->d, stg2->h, t2.off, hipMemcpyHostToDevice, J.st));
 
     // ------------------------------------------------ A7 window scan
+    // work-queue dispatch of the window scans (scheduling option)
+    unsigned long long* qbase = nullptr;
+    if (J.opt.flags & NCF_WINDOW_QUEUE) NCF_TRY(ensure_queue(R, &qbase));
     {
         const WinTask* wt = dT.wt;
         const int64_t *it0 = dT.item0, *wk0 = dT.wk0, *r0 = dT.r0;
         const int64_t nitems = W1.nitems, rows = W1.total_rows, nred1 = W1.nred1;
         const int cap = W1.cap, jmax = W1.jmax;
         const double work = W1.work;
+        unsigned long long* q = qbase;
         if (ntw > 0) {
             NCF_TRY(emit(J, [=](hipStream_t s) {
-                return launch_window(wt, it0, ntw, nitems, wflags, cap, jmax, s, work);
+                return launch_window(wt, it0, ntw, nitems, wflags, cap, jmax, q, s, work);
             }));
             NCF_TRY(emit(J, [=](hipStream_t s) {
                 return launch_window_reduce(wt, ntw, rows, wk0, r0, nred1, wflags, s);
@@ -1145,8 +1193,9 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         const int64_t nitems = W2.nitems, rows = W2.total_rows, nred1 = W2.nred1;
         const int cap = W2.cap, jmax = W2.jmax;
         const double work = W2.work;
+        unsigned long long* q = qbase ? qbase + 2 : nullptr;
         NCF_TRY(emit(J, [=](hipStream_t s) {
-            return launch_window(wt, it0, ntw2, nitems, wflags2, cap, jmax, s, work);
+            return launch_window(wt, it0, ntw2, nitems, wflags2, cap, jmax, q, s, work);
         }));
         NCF_TRY(emit(J, [=](hipStream_t s) {
             return launch_window_reduce(wt, ntw2, rows, wk0, r0, nred1, wflags2, s);
@@ -1242,19 +1291,13 @@ int load_lags(Job& J, int64_t K, const double* lags) {
     J.lags.resize(K);
     if (K > 0) {
         if (J.dev_ptrs) {
-            NCF_TRY_HIP(hipMemcpyAsync(J.lags.data(), lags, sizeof(double) * K,
-                                       hipMemcpyDeviceToHost, J.st));
-            NCF_TRY_HIP(hipStreamSynchronize(J.st));
-        } else {
-            std::memcpy(J.lags.data(), lags, sizeof(double) * K);
+            // copied with the phase-1 statistics (one synchronization)
+            J.lags_dev = lags;
+            return NCF_OK;
         }
+        std::memcpy(J.lags.data(), lags, sizeof(double) * K);
     }
-    for (double v : J.lags)
-        if (!std::isfinite(v)) {
-            set_error("non-finite lag");
-            return NCF_E_INVALID_ARG;
-        }
-    return NCF_OK;
+    return check_lags(J);
 }
 
 int check_offs(const int64_t* offs, int64_t n, int64_t* total) {

@@ -129,6 +129,8 @@ struct SeriesDesc {
     int32_t pad;
 };
 
+constexpr int64_t kMomentChunk = 2048;  // samples per moments chunk (8 per thread)
+
 struct Chunk {
     int64_t begin, end;  // sample range [begin, end) within the series
     int32_t series;
@@ -192,8 +194,11 @@ struct WinTask {
     int64_t item0;       // first work item of this task
 };
 
+// queue: null for flat dispatch, else a zeroed device counter pair (reset by
+// the launch itself when it ends) for queue dispatch over resident workgroups.
 int launch_window(const WinTask* d_tasks, const int64_t* d_item0, int ntasks, int64_t nitems,
-                  uint32_t flags, int cap, int jmax, hipStream_t st, double work_units);
+                  uint32_t flags, int cap, int jmax, unsigned long long* queue, hipStream_t st,
+                  double work_units);
 int launch_window_reduce(const WinTask* d_tasks, int ntasks, int64_t total_k, const int64_t* d_k0,
                          const int64_t* d_r0, int64_t nred1, uint32_t flags, hipStream_t st);
 constexpr int kWinJc = 64;  // j-tiles per first-level reduction block

@@ -17,66 +17,94 @@ namespace ncf {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr int kPer = (int)(kMomentChunk / kThreads);  // samples per thread in a chunk
+static_assert(kPer * kThreads == kMomentChunk, "chunk must be a multiple of the block");
 
-// Fixed-order block reduction of one double per thread.
-__device__ double block_sum(double v, double* sh) {
-    // wave-level tree via LDS (fixed order, independent of timing)
-    const int tid = threadIdx.x;
-    sh[tid] = v;
+// Sum over a wave by a fixed butterfly (every lane ends with the same total:
+// each step adds the same two values on both partners), then over the
+// block's waves in index order: deterministic, one barrier.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+template <int Q>
+__device__ __forceinline__ void block_sum(double (&v)[Q], double (*sh)[kWaves]) {
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) v[q] = wave_sum(v[q]);
+    __syncthreads();  // the exchange area may still be read by a previous call
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) sh[q][wave] = v[q];
     __syncthreads();
-    for (int off = kThreads / 2; off > 0; off >>= 1) {
-        if (tid < off) sh[tid] += sh[tid + off];
-        __syncthreads();
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        double t = sh[q][0];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) t += sh[q][w];
+        v[q] = t;
     }
-    double r = sh[0];
-    __syncthreads();
-    return r;
 }
 
 __global__ void __launch_bounds__(kThreads)
 k_chunk_moments(MomentsArgs a) {
-    __shared__ double sh[kThreads];
+    __shared__ double sh[3][kWaves];
+    __shared__ int shf[kWaves];
     const Chunk ch = a.chunks[blockIdx.x];
     const SeriesDesc sd = a.series[ch.series];
-    const double* X = a.io->x[sd.set] + sd.xoff;
+    const gptr<const double> X = gbl(a.io->x[sd.set] + sd.xoff);
+    const gptr<const double> t = gbl(sd.t);
+    const gptr<const double> er = gbl(sd.err);
     const int tid = threadIdx.x;
-    double sw = 0.0, swx = 0.0;
+    // the thread's samples stay in registers for the second pass
+    double xs[kPer], ws[kPer];
     int bad = 0, unsorted = 0;
-    for (int64_t i = ch.begin + tid; i < ch.end; i += kThreads) {
-        double ti = sd.t[i], xi = X[i];
-        double wi = 1.0;
-        if (sd.err) {
-            double e = sd.err[i];
-            if (!(e > 0.0) || !isfinite(e)) bad = 1;
-            wi = 1.0 / (e * e);
+    double acc[2] = {0.0, 0.0};  // sum w, sum w x
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int64_t i = ch.begin + tid + (int64_t)k * kThreads;
+        xs[k] = 0.0;
+        ws[k] = 0.0;
+        if (i < ch.end) {
+            const double ti = t[i], xi = X[i];
+            double wi = 1.0;
+            if (sd.err) {
+                const double e = er[i];
+                if (!(e > 0.0) || !isfinite(e)) bad = 1;
+                wi = 1.0 / (e * e);
+            }
+            if (!isfinite(ti) || !isfinite(xi)) bad = 1;
+            if (i > 0 && !(ti >= t[i - 1])) unsorted = 1;
+            xs[k] = xi;
+            ws[k] = wi;
+            acc[0] += wi;
+            acc[1] += wi * xi;
         }
-        if (!isfinite(ti) || !isfinite(xi)) bad = 1;
-        if (i > 0 && !(ti >= sd.t[i - 1])) unsorted = 1;
-        sw += wi;
-        swx += wi * xi;
     }
-    double Sw = block_sum(sw, sh);
-    double Swx = block_sum(swx, sh);
-    double mean = Swx / Sw;
-    double m2 = 0.0;
-    for (int64_t i = ch.begin + tid; i < ch.end; i += kThreads) {
-        double wi = 1.0;
-        if (sd.err) {
-            double e = sd.err[i];
-            wi = 1.0 / (e * e);
-        }
-        double d = X[i] - mean;
-        m2 += wi * d * d;
+    int fl = bad | (unsorted << 1);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) fl |= __shfl_xor(fl, off);
+    if ((tid & 63) == 0) shf[tid >> 6] = fl;
+    block_sum<2>(acc, sh);
+    const double mean = acc[1] / acc[0];
+    double m2[1] = {0.0};
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const double d = xs[k] - mean;
+        m2[0] += ws[k] * d * d;  // zero weight outside the chunk
     }
-    double M2 = block_sum(m2, sh);
-    double nbad = block_sum((double)bad, sh);
-    double nuns = block_sum((double)unsorted, sh);
+    block_sum<1>(m2, sh);
     if (tid == 0) {
+        int f = 0;
+        for (int w = 0; w < kWaves; ++w) f |= shf[w];
         double* p = a.chunk_part + 4 * (int64_t)blockIdx.x;
-        p[0] = Sw;
+        p[0] = acc[0];
         p[1] = mean;
-        p[2] = M2;
-        p[3] = (nbad > 0.0 ? 1.0 : 0.0) + (nuns > 0.0 ? 2.0 : 0.0);
+        p[2] = m2[0];
+        p[3] = (double)f;
     }
 }
 
@@ -98,13 +126,15 @@ __device__ __forceinline__ void merge_moments(double& sw, double& mean, double& 
 }
 
 // One workgroup per series: each thread merges a contiguous run of chunks in
-// order, then the threads' results are merged pairwise in a fixed tree.
+// order; then a fixed left-to-right pairwise tree over the lanes of each
+// wave (shuffles) and over the waves in order.
 __global__ void __launch_bounds__(kThreads)
 k_series_finalize(MomentsArgs a) {
-    __shared__ double sh[3][kThreads];
-    __shared__ int shf[kThreads];
+    __shared__ double sh[3][kWaves];
+    __shared__ int shf[kWaves];
     const int s = blockIdx.x;
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
     const SeriesDesc sd = a.series[s];
     double sw = 0.0, mean = 0.0, m2 = 0.0;
     int fl = 0;
@@ -115,53 +145,72 @@ k_series_finalize(MomentsArgs a) {
         merge_moments(sw, mean, m2, p[0], p[1], p[2]);
         fl |= (int)p[3];
     }
-    sh[0][tid] = sw;
-    sh[1][tid] = mean;
-    sh[2][tid] = m2;
-    shf[tid] = fl;
-    __syncthreads();
-    for (int off = 1; off < kThreads; off <<= 1) {
-        if ((tid & (2 * off - 1)) == 0 && tid + off < kThreads) {
-            double w0 = sh[0][tid], m0 = sh[1][tid], q0 = sh[2][tid];
-            merge_moments(w0, m0, q0, sh[0][tid + off], sh[1][tid + off], sh[2][tid + off]);
-            sh[0][tid] = w0;
-            sh[1][tid] = m0;
-            sh[2][tid] = q0;
-            shf[tid] |= shf[tid + off];
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double w1 = __shfl_down(sw, off), m1 = __shfl_down(mean, off),
+                     q1 = __shfl_down(m2, off);
+        const int f1 = __shfl_down(fl, off);
+        if ((lane & (2 * off - 1)) == 0) {  // left operand of this level
+            merge_moments(sw, mean, m2, w1, m1, q1);
+            fl |= f1;
         }
-        __syncthreads();
     }
+    if (lane == 0) {
+        sh[0][wave] = sw;
+        sh[1][wave] = mean;
+        sh[2][wave] = m2;
+        shf[wave] = fl;
+    }
+    __syncthreads();
     if (tid != 0) return;
+    sw = sh[0][0];
+    mean = sh[1][0];
+    m2 = sh[2][0];
+    fl = shf[0];
+    for (int w = 1; w < kWaves; ++w) {
+        merge_moments(sw, mean, m2, sh[0][w], sh[1][w], sh[2][w]);
+        fl |= shf[w];
+    }
     SeriesStat st;
     st.status = NCF_OK;
     st.pad = 0;
-    const int flags = shf[0];
-    const double swt = sh[0][0];
-    const double sdv = sqrt(sh[2][0] / swt);
-    st.mean = sh[1][0];
+    const double sdv = sqrt(m2 / sw);
+    st.mean = mean;
     st.sd = sdv;
-    st.sw = swt;
+    st.sw = sw;
     st.tmin = sd.t[0];
     st.tmax = sd.t[sd.n - 1];
-    if (sd.n < 2 || (flags & 1))
+    if (sd.n < 2 || (fl & 1))
         st.status = NCF_E_INVALID_ARG;
-    else if (flags & 2)
+    else if (fl & 2)
         st.status = NCF_E_UNSORTED;
     else if (!(sdv > 0.0) || !isfinite(sdv))
         st.status = NCF_E_DEGENERATE;
     a.stats[s] = st;
 }
 
+// Inclusive sum over a wave by shuffles (fixed order per lane).
+__device__ __forceinline__ double wave_scan(double v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double t = __shfl_up(v, off);
+        if (lane >= off) v += t;
+    }
+    return v;
+}
+
 // Standardize one chunk and write the chunk-local inclusive prefix sums.
 __global__ void __launch_bounds__(kThreads)
 k_standardize(MomentsArgs a) {
-    __shared__ double shv[kThreads];
-    __shared__ double shw[kThreads];
+    __shared__ double shv[2][kWaves];
     const Chunk ch = a.chunks[blockIdx.x];
     const SeriesDesc sd = a.series[ch.series];
     const SeriesStat st = a.stats[ch.series];
-    const double* X = a.io->x[sd.set] + sd.xoff;
+    const gptr<const double> X = gbl(a.io->x[sd.set] + sd.xoff);
+    const gptr<const double> er = gbl(sd.err);
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
     const bool ok = st.status == NCF_OK;
     const double mean = st.mean;
     const double inv_sd = ok ? 1.0 / st.sd : 0.0;
@@ -174,33 +223,36 @@ k_standardize(MomentsArgs a) {
         if (i < ch.end) {
             w = 1.0;
             if (sd.err) {
-                double e = sd.err[i];
+                double e = er[i];
                 w = 1.0 / (e * e);
             }
             v = ok ? w * ((X[i] - mean) * inv_sd) : 0.0;
-            if (sd.v32) sd.v32[i] = (float)v;
-            if (sd.v64) sd.v64[i] = v;
-            if (sd.w64) sd.w64[i] = w;
+            if (sd.v32) gbl(sd.v32)[i] = (float)v;
+            if (sd.v64) gbl(sd.v64)[i] = v;
+            if (sd.w64) gbl(sd.w64)[i] = w;
         }
         if (do_prefix) {
-            // inclusive Hillis-Steele scan over the block (fixed order)
-            shv[tid] = v;
-            shw[tid] = w;
+            // inclusive scan: within each wave by shuffles, then the totals
+            // of the preceding waves in index order
+            const double sv = wave_scan(v), swt = wave_scan(w);
+            if (lane == 63) {
+                shv[0][wave] = sv;
+                shv[1][wave] = swt;
+            }
             __syncthreads();
-            for (int off = 1; off < kThreads; off <<= 1) {
-                double av = tid >= off ? shv[tid - off] : 0.0;
-                double aw = tid >= off ? shw[tid - off] : 0.0;
-                __syncthreads();
-                shv[tid] += av;
-                shw[tid] += aw;
-                __syncthreads();
+            double ov = carry_v, ow = carry_w;
+            for (int q = 0; q < wave; ++q) {
+                ov += shv[0][q];
+                ow += shv[1][q];
             }
             if (i < ch.end) {
-                sd.pv[i + 1] = carry_v + shv[tid];
-                if (sd.pw) sd.pw[i + 1] = carry_w + shw[tid];
+                gbl(sd.pv)[i + 1] = ov + sv;
+                if (sd.pw) gbl(sd.pw)[i + 1] = ow + swt;
             }
-            carry_v += shv[kThreads - 1];
-            carry_w += shw[kThreads - 1];
+            for (int q = 0; q < kWaves; ++q) {
+                carry_v += shv[0][q];
+                carry_w += shv[1][q];
+            }
             __syncthreads();
         }
     }

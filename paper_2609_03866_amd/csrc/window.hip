@@ -22,6 +22,11 @@
 // Window predicates are evaluated exactly as (s_j + delta_k) - W and
 // (s_j + delta_k) + W in FP64 with W = 6h or h, so rectangle counts are
 // bit-identical to a sequential scan.
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "internal.h"
 
 namespace ncf {
@@ -281,10 +286,11 @@ __device__ __forceinline__ void scan_rect(AccR& acc, int o_t, int dp, int o_o, i
     }
 }
 
+// One work item: (task, j-tile, lag-tile) -> partial sums of the tile.
 template <uint32_t F>
-__global__ void __launch_bounds__(kThreads)
-k_window(const WinTask* __restrict__ tasks, const int64_t* __restrict__ item0, int ntasks,
-         int64_t nitems, int64_t nblocks, int cap, int jmax) {
+__device__ __forceinline__ void window_item(const WinTask* __restrict__ tasks,
+                                            const int64_t* __restrict__ item0, int ntasks,
+                                            int64_t item, int cap, int jmax) {
     constexpr bool RECT = (F & WIN_RECT) != 0;
     constexpr bool NUMER = (F & WIN_NUMER) != 0;
     constexpr bool WTD = (F & WIN_WEIGHTED) != 0;
@@ -293,12 +299,6 @@ k_window(const WinTask* __restrict__ tasks, const int64_t* __restrict__ item0, i
     constexpr bool HAS_A1 = NUMER;
     constexpr bool HAS_A2 = WTD;
     __shared__ int64_t sh_rng[4];
-
-    // work items are dispatched in order: the hardware spreads consecutive
-    // workgroups over the XCDs, which balances tiles of uneven cost
-    const int64_t item = blockIdx.x;
-    (void)nblocks;
-    if (item >= nitems) return;
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int lane = tid & 63;
@@ -443,6 +443,40 @@ k_window(const WinTask* __restrict__ tasks, const int64_t* __restrict__ item0, i
     }
 }
 
+// Work items (series x j-tile x lag-tile) of a whole batch in one launch.
+// Flat dispatch: workgroup b runs item b (the hardware hands workgroups out
+// in order). Queue dispatch: a grid of resident workgroups pulls items from
+// a device counter until the items run out; the last workgroup to leave
+// resets the counter pair for the next launch (no memset, so a captured
+// graph can replay it). Every item writes its own partial sums, so results
+// do not depend on which workgroup ran it.
+template <uint32_t F>
+__global__ void __launch_bounds__(kThreads)
+k_window(const WinTask* __restrict__ tasks, const int64_t* __restrict__ item0, int ntasks,
+         int64_t nitems, int cap, int jmax, unsigned long long* __restrict__ queue) {
+    if (!queue) {
+        if ((int64_t)blockIdx.x < nitems)
+            window_item<F>(tasks, item0, ntasks, (int64_t)blockIdx.x, cap, jmax);
+        return;
+    }
+    __shared__ int64_t sh_item;
+    for (;;) {
+        if (threadIdx.x == 0) sh_item = (int64_t)atomicAdd(queue, 1ull);
+        __syncthreads();
+        const int64_t item = sh_item;
+        __syncthreads();  // every thread has the item before the next pull
+        if (item >= nitems) break;
+        window_item<F>(tasks, item0, ntasks, item, cap, jmax);
+    }
+    if (threadIdx.x == 0) {
+        const unsigned long long done = atomicAdd(queue + 1, 1ull);
+        if (done == (unsigned long long)gridDim.x - 1) {  // all workgroups have left
+            atomicExch(queue, 0ull);
+            atomicExch(queue + 1, 0ull);
+        }
+    }
+}
+
 // Level 1: sum the partials of up to kJc consecutive j-tiles for 64 lags
 // (one lane per lag, four waves over interleaved j-tiles, combined in a fixed
 // order) into part2[chunk][k].
@@ -537,9 +571,32 @@ __global__ void k_window_reduce(const WinTask* __restrict__ tasks, int ntasks,
     out[3] = __longlong_as_double(n);
 }
 
+// Resident workgroups of a window kernel instance with `bytes` of LDS on the
+// current device (cached: the first eager launch fills it, later launches,
+// also under graph capture, only read it).
+template <uint32_t F>
+int resident_blocks(size_t bytes, int64_t* out) {
+    static std::mutex mu;
+    static std::map<std::pair<int, size_t>, int64_t> cache;
+    int dev = 0;
+    NCF_TRY_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    auto key = std::make_pair(dev, bytes);
+    auto it = cache.find(key);
+    if (it == cache.end()) {
+        int per_cu = 0, cus = 0;
+        NCF_TRY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_window<F>, kThreads,
+                                                                 bytes));
+        NCF_TRY_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        it = cache.emplace(key, (int64_t)std::max(per_cu, 1) * std::max(cus, 1)).first;
+    }
+    *out = it->second;
+    return NCF_OK;
+}
+
 template <uint32_t F>
 int launch_window_t(const WinTask* d_tasks, const int64_t* d_item0, int ntasks, int64_t nitems,
-                    int cap, int jmax, hipStream_t st, double work) {
+                    int cap, int jmax, unsigned long long* queue, hipStream_t st, double work) {
     constexpr bool RECT = (F & WIN_RECT) != 0;
     constexpr bool NUMER = (F & WIN_NUMER) != 0;
     constexpr bool WTD = (F & WIN_WEIGHTED) != 0;
@@ -549,9 +606,14 @@ int launch_window_t(const WinTask* d_tasks, const int64_t* d_item0, int ntasks, 
     size_t bytes = (stage > red ? stage : red) * sizeof(double);
     (void)RECT;
     int64_t nblocks = round_up(nitems, kXcds);
+    if (queue) {
+        int64_t res = 0;
+        NCF_TRY(resident_blocks<F>(bytes, &res));
+        nblocks = std::min(nitems, res);
+    }
     ProfScope p(st, RECT ? "window_rect" : "window_gauss", work, "valu_ops");
     hipLaunchKernelGGL(k_window<F>, dim3((unsigned)nblocks), dim3(kThreads), bytes, st, d_tasks,
-                       d_item0, ntasks, nitems, nblocks, cap, jmax);
+                       d_item0, ntasks, nitems, cap, jmax, queue);
     NCF_CHECK_LAUNCH();
     return NCF_OK;
 }
@@ -559,12 +621,13 @@ int launch_window_t(const WinTask* d_tasks, const int64_t* d_item0, int ntasks, 
 }  // namespace
 
 int launch_window(const WinTask* d_tasks, const int64_t* d_item0, int ntasks, int64_t nitems,
-                  uint32_t flags, int cap, int jmax, hipStream_t st, double work) {
+                  uint32_t flags, int cap, int jmax, unsigned long long* queue, hipStream_t st,
+                  double work) {
     if (nitems <= 0) return NCF_OK;
     switch (flags) {
 #define NCF_WIN_CASE(f) \
     case (f):           \
-        return launch_window_t<(f)>(d_tasks, d_item0, ntasks, nitems, cap, jmax, st, work);
+        return launch_window_t<(f)>(d_tasks, d_item0, ntasks, nitems, cap, jmax, queue, st, work);
         NCF_WIN_CASE(0)
         NCF_WIN_CASE(WIN_NUMER)
         NCF_WIN_CASE(WIN_WEIGHTED)

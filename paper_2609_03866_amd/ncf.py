@@ -20,6 +20,7 @@ MIXED, FP64 = 0, 1
 AUTO, SPECTRAL, DIRECT = 0, 1, 2
 DEVICE_POINTERS = 0x1
 PLAN_NO_GRAPH = 0x2
+WINDOW_QUEUE = 0x4
 
 OK = 0
 E_INVALID_ARG = -1
@@ -131,7 +132,7 @@ class _Marshal:
         return a, a.ctypes.data
 
 
-def _options(precision, method, tol, sigma, grid_size, device, stream):
+def _options(precision, method, tol, sigma, grid_size, device, stream, window_queue=False):
     o = Options()
     lib().ncf_options_init(ctypes.byref(o))
     o.precision = {"mixed": MIXED, "fp64": FP64}.get(precision, precision) \
@@ -145,6 +146,8 @@ def _options(precision, method, tol, sigma, grid_size, device, stream):
         import torch
         o.flags = DEVICE_POINTERS
         o.stream = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    if window_queue:
+        o.flags |= WINDOW_QUEUE
     return o
 
 
@@ -155,7 +158,8 @@ def _check(rc, allow=()):
 
 
 def acf(t, x, lags, kernel="gaussian", h=1.0, err=None, precision="mixed", method="auto",
-        tol=0.0, sigma=0.0, grid_size=0, with_count=True, raise_on_error=True, stream=None):
+        tol=0.0, sigma=0.0, grid_size=0, with_count=True, raise_on_error=True, stream=None,
+        window_queue=False):
     """ncf_acf. Returns (c, b, count, status). numpy in -> numpy out; torch CUDA
     tensors in -> torch CUDA tensors out (stream-ordered on `stream`)."""
     dev = t.device if _is_torch(t) else None
@@ -165,7 +169,7 @@ def acf(t, x, lags, kernel="gaussian", h=1.0, err=None, precision="mixed", metho
     b, pb = m.out(K, np.float64)
     cnt, pn = m.out(K, np.int64) if with_count else (None, None)
     n = int(t.numel() if _is_torch(t) else np.asarray(t).size)
-    o = _options(precision, method, tol, sigma, grid_size, dev, stream)
+    o = _options(precision, method, tol, sigma, grid_size, dev, stream, window_queue)
     rc = lib().ncf_acf(n, m.inp(t), m.inp(x), m.inp(err), K, m.inp(lags), _kern(kernel),
                        float(h), pc, pb, pn, ctypes.byref(o))
     if raise_on_error:
@@ -175,7 +179,7 @@ def acf(t, x, lags, kernel="gaussian", h=1.0, err=None, precision="mixed", metho
 
 def ccf(t, x, s, y, lags, kernel="gaussian", h=1.0, ex=None, ey=None, precision="mixed",
         method="auto", tol=0.0, sigma=0.0, grid_size=0, with_count=True, raise_on_error=True,
-        stream=None):
+        stream=None, window_queue=False):
     """ncf_ccf (lag +tau: series 2 (s, y) lags series 1 (t, x) by tau)."""
     dev = t.device if _is_torch(t) else None
     m = _Marshal(dev)
@@ -185,7 +189,7 @@ def ccf(t, x, s, y, lags, kernel="gaussian", h=1.0, ex=None, ey=None, precision=
     cnt, pn = m.out(K, np.int64) if with_count else (None, None)
     nx = int(t.numel() if _is_torch(t) else np.asarray(t).size)
     ny = int(s.numel() if _is_torch(s) else np.asarray(s).size)
-    o = _options(precision, method, tol, sigma, grid_size, dev, stream)
+    o = _options(precision, method, tol, sigma, grid_size, dev, stream, window_queue)
     rc = lib().ncf_ccf(nx, m.inp(t), m.inp(x), m.inp(ex), ny, m.inp(s), m.inp(y), m.inp(ey), K,
                        m.inp(lags), _kern(kernel), float(h), pc, pb, pn, ctypes.byref(o))
     if raise_on_error:
@@ -195,7 +199,7 @@ def ccf(t, x, s, y, lags, kernel="gaussian", h=1.0, ex=None, ey=None, precision=
 
 def acf_batch(offs, t, x, lags, kernel="gaussian", h=1.0, err=None, precision="mixed",
               method="auto", tol=0.0, sigma=0.0, grid_size=0, with_count=True,
-              raise_on_error=True, stream=None):
+              raise_on_error=True, stream=None, window_queue=False):
     """ncf_acf_batch over CSR series. Returns (c[nser, K], b, count, status[nser], rc)."""
     offs = np.ascontiguousarray(offs, dtype=np.int64)
     nser = offs.size - 1
@@ -207,7 +211,7 @@ def acf_batch(offs, t, x, lags, kernel="gaussian", h=1.0, err=None, precision="m
     b, pb = m.out(nser * K, np.float64)
     cnt, pn = m.out(nser * K, np.int64) if with_count else (None, None)
     st = np.zeros(nser, dtype=np.int32)
-    o = _options(precision, method, tol, sigma, grid_size, dev, stream)
+    o = _options(precision, method, tol, sigma, grid_size, dev, stream, window_queue)
     rc = lib().ncf_acf_batch(nser, offs.ctypes.data, m.inp(t), m.inp(x), m.inp(err), K,
                              m.inp(lags), _kern(kernel), hs.ctypes.data, pc, pb, pn,
                              st.ctypes.data, ctypes.byref(o))
@@ -219,7 +223,7 @@ def acf_batch(offs, t, x, lags, kernel="gaussian", h=1.0, err=None, precision="m
 
 def ccf_batch(offx, t, x, offy, s, y, lags, kernel="gaussian", h=1.0, ex=None, ey=None,
               precision="mixed", method="auto", tol=0.0, sigma=0.0, grid_size=0,
-              with_count=True, raise_on_error=True, stream=None):
+              with_count=True, raise_on_error=True, stream=None, window_queue=False):
     """ncf_ccf_batch over CSR series pairs."""
     offx = np.ascontiguousarray(offx, dtype=np.int64)
     offy = np.ascontiguousarray(offy, dtype=np.int64)
@@ -232,7 +236,7 @@ def ccf_batch(offx, t, x, offy, s, y, lags, kernel="gaussian", h=1.0, ex=None, e
     b, pb = m.out(npair * K, np.float64)
     cnt, pn = m.out(npair * K, np.int64) if with_count else (None, None)
     st = np.zeros(npair, dtype=np.int32)
-    o = _options(precision, method, tol, sigma, grid_size, dev, stream)
+    o = _options(precision, method, tol, sigma, grid_size, dev, stream, window_queue)
     rc = lib().ncf_ccf_batch(npair, offx.ctypes.data, m.inp(t), m.inp(x), m.inp(ex),
                              offy.ctypes.data, m.inp(s), m.inp(y), m.inp(ey), K, m.inp(lags),
                              _kern(kernel), hs.ctypes.data, pc, pb, pn, st.ctypes.data,
@@ -292,15 +296,17 @@ class Plan:
             pass
 
 
-def _plan_options(precision, method, tol, sigma, grid_size, dev, stream, graph):
-    o = _options(precision, method, tol, sigma, grid_size, dev, stream)
+def _plan_options(precision, method, tol, sigma, grid_size, dev, stream, graph,
+                  window_queue=False):
+    o = _options(precision, method, tol, sigma, grid_size, dev, stream, window_queue)
     if not graph:
         o.flags |= PLAN_NO_GRAPH
     return o
 
 
 def plan_acf(offs, t, lags, kernel="gaussian", h=1.0, err=None, precision="mixed",
-             method="auto", tol=0.0, sigma=0.0, grid_size=0, graph=True, stream=None):
+             method="auto", tol=0.0, sigma=0.0, grid_size=0, graph=True, stream=None,
+             window_queue=False):
     """ncf_plan_acf over CSR series (times fixed, values given per execute)."""
     offs = np.ascontiguousarray(offs, dtype=np.int64)
     nser = offs.size - 1
@@ -308,7 +314,8 @@ def plan_acf(offs, t, lags, kernel="gaussian", h=1.0, err=None, precision="mixed
     dev = t.device if _is_torch(t) else None
     m = _Marshal(dev)
     K = int(lags.numel() if _is_torch(lags) else np.asarray(lags).size)
-    o = _plan_options(precision, method, tol, sigma, grid_size, dev, stream, graph)
+    o = _plan_options(precision, method, tol, sigma, grid_size, dev, stream, graph,
+                      window_queue)
     hp = ctypes.c_void_p()
     _check(lib().ncf_plan_acf(nser, offs.ctypes.data, m.inp(t), m.inp(err), K, m.inp(lags),
                               _kern(kernel), hs.ctypes.data, ctypes.byref(o), ctypes.byref(hp)))
@@ -317,7 +324,7 @@ def plan_acf(offs, t, lags, kernel="gaussian", h=1.0, err=None, precision="mixed
 
 def plan_ccf(offx, t, offy, s, lags, kernel="gaussian", h=1.0, ex=None, ey=None,
              precision="mixed", method="auto", tol=0.0, sigma=0.0, grid_size=0, graph=True,
-             stream=None):
+             stream=None, window_queue=False):
     """ncf_plan_ccf over CSR series pairs."""
     offx = np.ascontiguousarray(offx, dtype=np.int64)
     offy = np.ascontiguousarray(offy, dtype=np.int64)
@@ -326,7 +333,8 @@ def plan_ccf(offx, t, offy, s, lags, kernel="gaussian", h=1.0, ex=None, ey=None,
     dev = t.device if _is_torch(t) else None
     m = _Marshal(dev)
     K = int(lags.numel() if _is_torch(lags) else np.asarray(lags).size)
-    o = _plan_options(precision, method, tol, sigma, grid_size, dev, stream, graph)
+    o = _plan_options(precision, method, tol, sigma, grid_size, dev, stream, graph,
+                      window_queue)
     hp = ctypes.c_void_p()
     _check(lib().ncf_plan_ccf(npair, offx.ctypes.data, m.inp(t), m.inp(ex), offy.ctypes.data,
                               m.inp(s), m.inp(ey), K, m.inp(lags), _kern(kernel),
