@@ -99,10 +99,10 @@ def run_one(d, precision="mixed", method="auto"):
                          d["kernel"], d["h"], **kw)
 
 
-def make_plan(d, precision="mixed", method="auto"):
+def make_plan(d, precision="mixed", method="auto", autotune=False):
     """A plan over the workload's times (device tensors), replayed as a graph."""
     from paper_2609_03866_amd import ncf
-    kw = dict(precision=precision, method=method, window_queue=WINDOW_QUEUE)
+    kw = dict(precision=precision, method=method, window_queue=WINDOW_QUEUE, autotune=autotune)
     if d["kind"] == "acf":
         return ncf.plan_acf(np.array([0, d["t"].numel()]), d["t"], d["lags"], d["kernel"],
                             d["h"], err=d.get("err"), **kw)
@@ -310,6 +310,29 @@ def main():
         for pl in plans:
             pl.close()
         log(f"[bench] plan replay: {dtp * 1e3:.3f} ms/step")
+        # the same with autotuned plans (settings chosen by timing candidates)
+        t3 = time.perf_counter()
+        plans = [make_plan(d, autotune=True) for d in devs]
+        torch.cuda.synchronize()
+        tune_s = time.perf_counter() - t3
+        for pl, d in zip(plans, devs):
+            run_plan(pl, d)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        for _ in range(args.steps):
+            pres = [run_plan(pl, d) for pl, d in zip(plans, devs)]
+        torch.cuda.synchronize()
+        dta = (time.perf_counter() - t4) / args.steps
+        dca = max(float((pr[0].reshape(-1) - r[0].reshape(-1)).abs().max().item())
+                  for pr, r in zip(pres, res))
+        keys = ("candidates", "sigma", "fft_split", "fft_tile_log2", "window_tile_scale",
+                "window_queue", "grid_cells", "window_items")
+        plan_rep["autotuned"] = {"value": work / dta, "ms_per_step": dta * 1e3,
+                                 "max_abs_dc_vs_call": dca, "tuning_seconds": tune_s,
+                                 "settings": [{k: pl.info()[k] for k in keys} for pl in plans]}
+        for pl in plans:
+            pl.close()
+        log(f"[bench] autotuned plan replay: {dta * 1e3:.3f} ms/step (tuning {tune_s:.2f} s)")
 
     # roofline of the dominant kernel, HIP events on the library's stream
     ncf.profile_enable(True)

@@ -102,6 +102,12 @@ typedef enum { NCF_AUTO = 0, NCF_SPECTRAL = 1, NCF_DIRECT = 2 } ncf_method_t;
  * (series, outer-sample tile, lag tile) work items from a device queue,
  * instead of one workgroup per item. Results are identical. */
 #define NCF_WINDOW_QUEUE 0x4u
+/* Plans only: build and time candidate scheduling settings (minimum grid
+ * oversampling, FFT radix split and strided-pass tile, window tile scale,
+ * window dispatch) by coordinate descent from the defaults, and keep the
+ * fastest. Results may differ from an untuned plan at the rounding level
+ * (another grid size or FFT order); building takes several plan builds. */
+#define NCF_PLAN_AUTOTUNE 0x8u
 
 typedef struct {
     uint32_t struct_size; /* sizeof(ncf_options_t) */
@@ -205,6 +211,26 @@ int ncf_plan_execute(ncf_plan_t* plan, const double* x, const double* y, double*
 
 /* Release a plan (NULL is ignored). Waits for the device to finish. */
 void ncf_plan_destroy(ncf_plan_t* plan);
+
+/* What a plan holds and how it was scheduled. Set struct_size first. */
+typedef struct {
+    uint32_t struct_size;      /* sizeof(ncf_plan_info_t) */
+    int32_t autotuned;         /* 1 if built with NCF_PLAN_AUTOTUNE */
+    int32_t candidates;        /* settings timed by the autotuner */
+    int32_t spectral_grids;    /* spreading grids (spectral problems) */
+    int32_t window_launches;   /* window-scan launches per execution */
+    int32_t graph;             /* 1 if executions replay a captured graph */
+    int64_t grid_cells;        /* cells over all grids */
+    int64_t window_items;      /* window work items per execution */
+    double sigma;              /* minimum grid oversampling chosen, 0 = default */
+    int32_t fft_split;         /* 0 default radices, 1 swapped order, 2 three passes */
+    int32_t fft_tile_log2;     /* strided-pass tile, 0 = default */
+    int32_t window_tile_scale; /* log2 factor on the outer samples per workgroup */
+    int32_t window_queue;      /* 1: work-queue dispatch of the window scans */
+    double replay_ms;          /* autotuned: measured time of one execution */
+} ncf_plan_info_t;
+
+int ncf_plan_info(const ncf_plan_t* plan, ncf_plan_info_t* info);
 
 /* Message describing the last failure on the calling thread ("" if none). */
 const char* ncf_last_error(void);

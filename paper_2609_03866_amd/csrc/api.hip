@@ -263,6 +263,15 @@ struct SeriesSet {
     int sd0 = 0;           // first descriptor of this set in the moments table
 };
 
+// Scheduling settings that change speed, not the estimator (results differ
+// at most at the rounding level): chosen by the plan autotuner.
+struct Tune {
+    double sigma = 0.0;  // minimum grid oversampling (0: options or 1.5)
+    FftVariant fft;      // radix split and strided-pass tile of the FFTs
+    int jscale = 0;      // window tiles (outer samples per workgroup) times 2^jscale
+    bool queue = false;  // window scans by work-queue dispatch
+};
+
 struct Job {
     bool ccf = false;
     int64_t nprob = 0;
@@ -287,6 +296,10 @@ struct Job {
     int32_t* io_status = nullptr;  // device status array the block points at
     std::vector<std::function<int(hipStream_t)>>* rec = nullptr;
     bool plan_build = false;   // statuses are those of the host checks only
+    Tune tune;
+    // filled by run_job: what the call planned
+    int64_t info_grid_cells = 0, info_window_items = 0;
+    int info_grids = 0, info_window_launches = 0;
 };
 
 int check_lags(const Job& J) {
@@ -328,7 +341,7 @@ int plan_grid(const Job& J, double tmin, double tmax, double maxlag, double h, S
     const bool fp64 = J.opt.precision == NCF_FP64;
     const double tol = J.opt.tol > 0 ? J.opt.tol : (fp64 ? 1e-13 : 1e-9);
     const double eps_s = fp64 ? 1e-13 : 1e-7;  // spreading accuracy
-    const double sig_min = J.opt.sigma > 1.0 ? J.opt.sigma : 1.5;
+    const double sig_min = J.tune.sigma > 1.0 ? J.tune.sigma : J.opt.sigma > 1.0 ? J.opt.sigma : 1.5;
     const double span = tmax - tmin;
     double Wh, fcut;
     if (J.kern == NCF_GAUSSIAN) {
@@ -677,6 +690,8 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
                    (double)dO.n * n_kt / (double)(Jt * 2) >= 2048.0)
                 Jt *= 2;
             while (Jt > 16 && est(Jt) > 0.5 * cap) Jt /= 2;
+            if (J.tune.jscale > 0) Jt = std::min<int64_t>(Jt << J.tune.jscale, jmax);
+            if (J.tune.jscale < 0) Jt = std::max<int64_t>(Jt >> -J.tune.jscale, 16);
             T.J = (int32_t)Jt;
             T.n_kt = n_kt;
             dens[i] = {dens_w, dens_o, ext};
@@ -766,6 +781,11 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     }
     const int nts = (int)splans.size();
     const int Keval = (int)(J.ccf ? K : K + 1);
+    J.info_grids = nts;
+    J.info_grid_cells = 0;
+    for (auto& sp : splans) J.info_grid_cells += sp.g.N;
+    J.info_window_items = W1.nitems;
+    J.info_window_launches = ntw > 0 ? 1 : 0;
     const size_t csz = fp64 ? 16 : 8;
     const bool two_grids = spec_b && J.ccf;
 
@@ -927,7 +947,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             groups.back().second++;
         if (!plans.count(T.N)) {
             FftPlan fp;
-            NCF_TRY(fft_plan(T.N, fp64, &fp, J.st));
+            NCF_TRY(fft_plan(T.N, fp64, &fp, J.st, J.tune.fft));
             plans[T.N] = fp;
         }
         const FftPlan& fp = plans[T.N];
@@ -967,7 +987,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     // ------------------------------------------------ A7 window scan
     // work-queue dispatch of the window scans (scheduling option)
     unsigned long long* qbase = nullptr;
-    if (J.opt.flags & NCF_WINDOW_QUEUE) NCF_TRY(ensure_queue(R, &qbase));
+    if ((J.opt.flags & NCF_WINDOW_QUEUE) || J.tune.queue) NCF_TRY(ensure_queue(R, &qbase));
     {
         const WinTask* wt = dT.wt;
         const int64_t *it0 = dT.item0, *wk0 = dT.wk0, *r0 = dT.r0;
@@ -1058,6 +1078,8 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         plan_window(W2);
     }
     const int ntw2 = (int)W2.plans.size();
+    J.info_window_items += W2.nitems;
+    J.info_window_launches += ntw2 > 0 ? 1 : 0;
     const uint32_t wflags2 = (fp64 ? (uint32_t)WIN_EXP64 : 0u) | (uint32_t)WIN_NUMER;
 
     // fallback workspace and the output tables
@@ -1491,6 +1513,12 @@ struct ncf_plan_s {
     double* bbuf = nullptr;
     int64_t* nbuf = nullptr;
     std::vector<int32_t> hstatus;          // host statuses (host-pointer plans)
+    // what was planned, and how (ncf_plan_info)
+    ncf::Tune tune;
+    int grids = 0, window_launches = 0;
+    int64_t grid_cells = 0, window_items = 0;
+    int autotuned = 0, candidates = 0;
+    double replay_ms = 0.0;
 };
 
 namespace ncf {
@@ -1524,7 +1552,8 @@ int dev_alloc(T** p, size_t n) {
 // Build a plan: copy times and errors, run the whole path once on
 // placeholder values (recording every launch), then capture the launches
 // into a graph.
-int plan_build(ncf_plan_s* P, Job& J, const double* const* tin, const double* const* ein) {
+int plan_build(ncf_plan_s* P, Job& J, const double* const* tin, const double* const* ein,
+               const Tune& tune, double* dummy) {
     const int nsets = J.ccf ? 2 : 1;
     NCF_TRY_HIP(hipGetDevice(&P->device));
     P->ccf = J.ccf;
@@ -1556,20 +1585,7 @@ int plan_build(ncf_plan_s* P, Job& J, const double* const* tin, const double* co
     NCF_TRY(dev_alloc(&P->nbuf, nout));
     P->hstatus.assign(J.nprob, NCF_OK);
 
-    // placeholder values: finite, unit variance (the plan's pair counts and
-    // fallback lags depend on the times only)
-    double* dummy = nullptr;
-    NCF_TRY(dev_alloc(&dummy, nmax));
-    struct Guard {
-        double* p;
-        ~Guard() {
-            if (p) {
-                (void)hipDeviceSynchronize();
-                (void)hipFree(p);
-            }
-        }
-    } guard{dummy};
-    NCF_TRY(launch_fill_alternating(dummy, nmax, J.st));
+    (void)nmax;
     IoBlock io{};
     io.x[0] = dummy;
     io.x[1] = J.ccf ? dummy : nullptr;
@@ -1590,10 +1606,16 @@ int plan_build(ncf_plan_s* P, Job& J, const double* const* tin, const double* co
     B.io_status = P->status;
     B.rec = &P->rec;
     B.plan_build = true;
+    B.tune = tune;
     const double* tdev[2] = {P->tcopy[0], P->tcopy[1]};
     const double* xdev[2] = {dummy, J.ccf ? dummy : nullptr};
     const double* edev[2] = {P->ecopy[0], P->ecopy[1]};
     NCF_TRY(run_job(B, tdev, xdev, edev));
+    P->tune = tune;
+    P->grids = B.info_grids;
+    P->grid_cells = B.info_grid_cells;
+    P->window_items = B.info_window_items;
+    P->window_launches = B.info_window_launches;
 
     if (P->use_graph) {
         hipStream_t cs = nullptr;
@@ -1624,6 +1646,142 @@ int plan_build(ncf_plan_s* P, Job& J, const double* const* tin, const double* co
             return NCF_E_DEVICE;
         }
     }
+    return NCF_OK;
+}
+
+// Mean time of one execution of a built plan on the placeholder values
+// (one warm-up execution, then `reps` timed with events on the plan stream).
+int plan_time(ncf_plan_s* P, double* dummy, int reps, double* ms) {
+    IoBlock io{};
+    io.x[0] = dummy;
+    io.x[1] = P->ccf ? dummy : nullptr;
+    io.c = P->cbuf;
+    io.b = P->bbuf;
+    io.count = P->nbuf;
+    io.status = P->status;
+    NCF_TRY(launch_set_io(P->io, io, P->st));
+    auto run = [&]() -> int {
+        if (P->exec) {
+            NCF_TRY_HIP(hipGraphLaunch(P->exec, P->st));
+        } else {
+            for (auto& f : P->rec) NCF_TRY(f(P->st));
+        }
+        return NCF_OK;
+    };
+    NCF_TRY(run());
+    hipEvent_t e0, e1;
+    NCF_TRY_HIP(hipEventCreate(&e0));
+    NCF_TRY_HIP(hipEventCreate(&e1));
+    int rc = NCF_OK;
+    if (hipEventRecord(e0, P->st) != hipSuccess) rc = NCF_E_DEVICE;
+    for (int r = 0; r < reps && rc == NCF_OK; ++r) rc = run();
+    float el = 0.f;
+    if (rc == NCF_OK && (hipEventRecord(e1, P->st) != hipSuccess ||
+                         hipEventSynchronize(e1) != hipSuccess ||
+                         hipEventElapsedTime(&el, e0, e1) != hipSuccess))
+        rc = NCF_E_DEVICE;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = el / std::max(reps, 1);
+    return rc;
+}
+
+// Build a plan; with NCF_PLAN_AUTOTUNE, build and time candidate settings by
+// coordinate descent from the defaults (minimum oversampling, FFT radix split
+// and strided tile, window tile scale, window dispatch) and keep the fastest.
+int plan_create(Job& J, const double* const* tin, const double* const* ein, ncf_plan_t** out) {
+    int64_t nmax = J.set[0].ntot;
+    if (J.ccf) nmax = std::max(nmax, J.set[1].ntot);
+    // placeholder values: finite, unit variance (the plan's pair counts and
+    // fallback lags depend on the times only)
+    double* dummy = nullptr;
+    NCF_TRY(dev_alloc(&dummy, nmax));
+    struct Guard {
+        double* p;
+        ~Guard() {
+            (void)hipDeviceSynchronize();
+            (void)hipFree(p);
+        }
+    } guard{dummy};
+    NCF_TRY(launch_fill_alternating(dummy, nmax, J.st));
+
+    ncf_plan_s* best = new ncf_plan_s;
+    int rc = plan_build(best, J, tin, ein, Tune{}, dummy);
+    if (rc != NCF_OK) {
+        plan_free(best);
+        return rc;
+    }
+    if (J.opt.flags & NCF_PLAN_AUTOTUNE) {
+        constexpr int kReps = 3;
+        double tb = 0.0;
+        rc = plan_time(best, dummy, kReps, &tb);
+        if (rc != NCF_OK) {
+            plan_free(best);
+            return rc;
+        }
+        int ncand = 1;
+        auto attempt = [&](const Tune& t) -> int {
+            ncf_plan_s* P = new ncf_plan_s;
+            double tp = 0.0;
+            int r = plan_build(P, J, tin, ein, t, dummy);
+            if (r == NCF_OK) r = plan_time(P, dummy, kReps, &tp);
+            if (r != NCF_OK) {  // e.g. a larger grid that does not fit: skip it
+                plan_free(P);
+                clear_error();
+                return r == NCF_E_DEVICE ? r : NCF_OK;
+            }
+            ++ncand;
+            if (tp < 0.97 * tb) {
+                plan_free(best);
+                best = P;
+                tb = tp;
+            } else {
+                plan_free(P);
+            }
+            return NCF_OK;
+        };
+        const bool fp64 = J.opt.precision == NCF_FP64;
+        if (best->grids > 0) {
+            for (double sg : {1.25, 2.0}) {
+                Tune t = best->tune;
+                t.sigma = sg;
+                rc = attempt(t);
+                if (rc != NCF_OK) break;
+            }
+            for (int sp : {1, 2}) {
+                if (rc != NCF_OK) break;
+                Tune t = best->tune;
+                t.fft.split = sp;
+                rc = attempt(t);
+            }
+            if (rc == NCF_OK && !fp64) {
+                Tune t = best->tune;
+                t.fft.lgt_strided = 12;
+                rc = attempt(t);
+            }
+        }
+        if (rc == NCF_OK && best->window_items > 0) {
+            for (int js : {-1, 1}) {
+                Tune t = best->tune;
+                t.jscale = js;
+                rc = attempt(t);
+                if (rc != NCF_OK) break;
+            }
+            if (rc == NCF_OK) {
+                Tune t = best->tune;
+                t.queue = true;
+                rc = attempt(t);
+            }
+        }
+        if (rc != NCF_OK) {
+            plan_free(best);
+            return rc;
+        }
+        best->autotuned = 1;
+        best->candidates = ncand;
+        best->replay_ms = tb;
+    }
+    *out = best;
     return NCF_OK;
 }
 
@@ -1660,16 +1818,9 @@ int ncf_plan_acf(int64_t nser, const int64_t* offs, const double* t, const doubl
     NCF_TRY(check_offs(offs, nser, &total));
     std::lock_guard<std::mutex> lock(g_ws_mu);
     NCF_TRY(setup_job(J, false, nser, offs, nullptr, total, 0, kern, h, K, lags));
-    ncf_plan_s* P = new ncf_plan_s;
     const double* tin[2] = {t, nullptr};
     const double* ein[2] = {err, nullptr};
-    const int rc = plan_build(P, J, tin, ein);
-    if (rc != NCF_OK) {
-        plan_free(P);
-        return rc;
-    }
-    *out = P;
-    return NCF_OK;
+    return plan_create(J, tin, ein, out);
 }
 
 int ncf_plan_ccf(int64_t npair, const int64_t* offx, const double* tx, const double* ex,
@@ -1693,16 +1844,9 @@ int ncf_plan_ccf(int64_t npair, const int64_t* offx, const double* tx, const dou
     NCF_TRY(check_offs(offy, npair, &toty));
     std::lock_guard<std::mutex> lock(g_ws_mu);
     NCF_TRY(setup_job(J, true, npair, offx, offy, totx, toty, kern, h, K, lags));
-    ncf_plan_s* P = new ncf_plan_s;
     const double* tin[2] = {tx, ty};
     const double* ein[2] = {ex, ey};
-    const int rc = plan_build(P, J, tin, ein);
-    if (rc != NCF_OK) {
-        plan_free(P);
-        return rc;
-    }
-    *out = P;
-    return NCF_OK;
+    return plan_create(J, tin, ein, out);
 }
 
 int ncf_plan_execute(ncf_plan_t* P, const double* x, const double* y, double* c, double* b,
@@ -1765,6 +1909,28 @@ int ncf_plan_execute(ncf_plan_t* P, const double* x, const double* y, double* c,
 }
 
 void ncf_plan_destroy(ncf_plan_t* P) { plan_free(P); }
+
+int ncf_plan_info(const ncf_plan_t* P, ncf_plan_info_t* info) {
+    clear_error();
+    if (!P || !info || info->struct_size != sizeof(ncf_plan_info_t)) {
+        set_error("null plan or info, or info.struct_size mismatch");
+        return NCF_E_INVALID_ARG;
+    }
+    info->autotuned = P->autotuned;
+    info->candidates = P->candidates;
+    info->spectral_grids = P->grids;
+    info->window_launches = P->window_launches;
+    info->grid_cells = P->grid_cells;
+    info->window_items = P->window_items;
+    info->sigma = P->tune.sigma > 1.0 ? P->tune.sigma : 0.0;
+    info->fft_split = P->tune.fft.split;
+    info->fft_tile_log2 = P->tune.fft.lgt_strided;
+    info->window_tile_scale = P->tune.jscale;
+    info->window_queue = P->tune.queue ? 1 : 0;
+    info->graph = P->exec ? 1 : 0;
+    info->replay_ms = P->replay_ms;
+    return NCF_OK;
+}
 
 // ------------------------------------------------------------- diagnostics
 

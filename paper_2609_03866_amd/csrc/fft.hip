@@ -25,6 +25,7 @@
 #include <cmath>
 #include <map>
 #include <mutex>
+#include <utility>
 #include <vector>
 
 #include "internal.h"
@@ -466,25 +467,27 @@ std::vector<double> twiddles(int64_t M, int64_t count, int64_t mult) {
 
 }  // namespace
 
-int fft_plan(int64_t N, bool fp64, FftPlan* plan, hipStream_t st) {
+int fft_plan(int64_t N, bool fp64, FftPlan* plan, hipStream_t st, const FftVariant& var) {
     if (N < kTileElems || (N & (N - 1)) || N > (1LL << 31)) {
         set_error("fft: N = %lld must be a power of two in [4096, 2^31]", (long long)N);
         return NCF_E_INVALID_ARG;
     }
     const int p = ilog2(N);
+    const int r = p - 12;  // log2 of the strided part
     plan->N = N;
     if (p == 12) {
         plan->npass = 1;
         plan->radix[0] = 4096;
-    } else if (p <= 22) {
+    } else if (p <= 22 && !(var.split == 2 && r >= 2)) {
         plan->npass = 2;
-        plan->radix[0] = 1 << (p - 12);
+        plan->radix[0] = 1 << r;
         plan->radix[1] = 4096;
     } else {
         plan->npass = 3;
-        const int r = p - 12;
-        plan->radix[0] = 1 << ((r + 1) / 2);
-        plan->radix[1] = 1 << (r / 2);
+        int a = (r + 1) / 2, b = r / 2;  // larger strided radix first
+        if (var.split == 1) std::swap(a, b);
+        plan->radix[0] = 1 << a;
+        plan->radix[1] = 1 << b;
         plan->radix[2] = 4096;
     }
     int64_t B = N;
@@ -492,7 +495,10 @@ int fft_plan(int64_t N, bool fp64, FftPlan* plan, hipStream_t st) {
         plan->stride[i] = B / plan->radix[i];
         B = plan->stride[i];
         // strided passes of the FP32 transform move 8192-element tiles
-        plan->lgt[i] = (i < plan->npass - 1 && !fp64) ? 13 : 12;
+        int lgt = (i < plan->npass - 1 && !fp64) ? 13 : 12;
+        if (i < plan->npass - 1 && var.lgt_strided == 12) lgt = 12;
+        if (i < plan->npass - 1 && var.lgt_strided == 13 && !fp64) lgt = 13;
+        plan->lgt[i] = lgt;
     }
     int dev = 0;
     NCF_TRY_HIP(hipGetDevice(&dev));

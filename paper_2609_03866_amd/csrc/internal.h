@@ -264,7 +264,17 @@ struct FftPlan {
     void* whi;
     void* small;
 };
-int fft_plan(int64_t N, bool fp64, FftPlan* plan, hipStream_t st);  // tables cached per (N, fp64)
+// Plan variants (chosen by the autotuner): split 0 = default radices (larger
+// strided radix first), 1 = strided radices in the other order, 2 = three
+// passes where the default has two; lgt_strided 0 = default tile of the
+// strided passes (8192 elements in FP32, 4096 in FP64), else 12 or 13.
+struct FftVariant {
+    int split = 0;
+    int lgt_strided = 0;
+};
+// Twiddle tables are cached per (N, fp64, device).
+int fft_plan(int64_t N, bool fp64, FftPlan* plan, hipStream_t st,
+             const FftVariant& v = FftVariant{});
 // Batched transform of `count` grids of the same N laid out at `grids[i]`.
 // sign +1: natural -> digit-reversed; sign -1: digit-reversed -> natural.
 int fft_exec(const FftPlan& plan, void* const* d_grids, int count, int sign, bool fp64,

@@ -21,6 +21,7 @@ AUTO, SPECTRAL, DIRECT = 0, 1, 2
 DEVICE_POINTERS = 0x1
 PLAN_NO_GRAPH = 0x2
 WINDOW_QUEUE = 0x4
+PLAN_AUTOTUNE = 0x8
 
 OK = 0
 E_INVALID_ARG = -1
@@ -43,6 +44,16 @@ class Options(ctypes.Structure):
                 ("sigma", ctypes.c_double), ("grid_size", ctypes.c_int64),
                 ("stream", ctypes.c_void_p), ("flags", ctypes.c_uint32),
                 ("reserved", ctypes.c_uint32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("autotuned", ctypes.c_int32),
+                ("candidates", ctypes.c_int32), ("spectral_grids", ctypes.c_int32),
+                ("window_launches", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("grid_cells", ctypes.c_int64), ("window_items", ctypes.c_int64),
+                ("sigma", ctypes.c_double), ("fft_split", ctypes.c_int32),
+                ("fft_tile_log2", ctypes.c_int32), ("window_tile_scale", ctypes.c_int32),
+                ("window_queue", ctypes.c_int32), ("replay_ms", ctypes.c_double)]
 
 
 class ProfileRecord(ctypes.Structure):
@@ -84,6 +95,7 @@ def lib():
                                    _P]
         L.ncf_plan_execute.argtypes = [_P, _P, _P, _P, _P, _P, _P]
         L.ncf_plan_destroy.argtypes = [_P]
+        L.ncf_plan_info.argtypes = [_P, _P]
         L.ncf_profile_enable.argtypes = [ctypes.c_int]
         L.ncf_profile_read.argtypes = [_P, ctypes.c_int]
         _lib = L
@@ -284,6 +296,15 @@ class Plan:
         rs = (lambda a: a.reshape(self.nprob, self.K) if a is not None else None)
         return rs(c), rs(b), rs(cnt), st, rc
 
+    def info(self):
+        """ncf_plan_info as a dict."""
+        if self._h is None:
+            raise ValueError("plan is closed")
+        i = PlanInfo()
+        i.struct_size = ctypes.sizeof(PlanInfo)
+        _check(lib().ncf_plan_info(self._h, ctypes.byref(i)))
+        return {name: getattr(i, name) for name, _ in PlanInfo._fields_ if name != "struct_size"}
+
     def close(self):
         if self._h is not None:
             lib().ncf_plan_destroy(self._h)
@@ -297,16 +318,18 @@ class Plan:
 
 
 def _plan_options(precision, method, tol, sigma, grid_size, dev, stream, graph,
-                  window_queue=False):
+                  window_queue=False, autotune=False):
     o = _options(precision, method, tol, sigma, grid_size, dev, stream, window_queue)
     if not graph:
         o.flags |= PLAN_NO_GRAPH
+    if autotune:
+        o.flags |= PLAN_AUTOTUNE
     return o
 
 
 def plan_acf(offs, t, lags, kernel="gaussian", h=1.0, err=None, precision="mixed",
              method="auto", tol=0.0, sigma=0.0, grid_size=0, graph=True, stream=None,
-             window_queue=False):
+             window_queue=False, autotune=False):
     """ncf_plan_acf over CSR series (times fixed, values given per execute)."""
     offs = np.ascontiguousarray(offs, dtype=np.int64)
     nser = offs.size - 1
@@ -315,7 +338,7 @@ def plan_acf(offs, t, lags, kernel="gaussian", h=1.0, err=None, precision="mixed
     m = _Marshal(dev)
     K = int(lags.numel() if _is_torch(lags) else np.asarray(lags).size)
     o = _plan_options(precision, method, tol, sigma, grid_size, dev, stream, graph,
-                      window_queue)
+                      window_queue, autotune)
     hp = ctypes.c_void_p()
     _check(lib().ncf_plan_acf(nser, offs.ctypes.data, m.inp(t), m.inp(err), K, m.inp(lags),
                               _kern(kernel), hs.ctypes.data, ctypes.byref(o), ctypes.byref(hp)))
@@ -324,7 +347,7 @@ def plan_acf(offs, t, lags, kernel="gaussian", h=1.0, err=None, precision="mixed
 
 def plan_ccf(offx, t, offy, s, lags, kernel="gaussian", h=1.0, ex=None, ey=None,
              precision="mixed", method="auto", tol=0.0, sigma=0.0, grid_size=0, graph=True,
-             stream=None, window_queue=False):
+             stream=None, window_queue=False, autotune=False):
     """ncf_plan_ccf over CSR series pairs."""
     offx = np.ascontiguousarray(offx, dtype=np.int64)
     offy = np.ascontiguousarray(offy, dtype=np.int64)
@@ -334,7 +357,7 @@ def plan_ccf(offx, t, offy, s, lags, kernel="gaussian", h=1.0, ex=None, ey=None,
     m = _Marshal(dev)
     K = int(lags.numel() if _is_torch(lags) else np.asarray(lags).size)
     o = _plan_options(precision, method, tol, sigma, grid_size, dev, stream, graph,
-                      window_queue)
+                      window_queue, autotune)
     hp = ctypes.c_void_p()
     _check(lib().ncf_plan_ccf(npair, offx.ctypes.data, m.inp(t), m.inp(ex), offy.ctypes.data,
                               m.inp(s), m.inp(ey), K, m.inp(lags), _kern(kernel),

@@ -225,3 +225,53 @@ def test_queue_dispatch_in_graph_replays():
             np.testing.assert_array_equal(c, c1)
     finally:
         pq.close()
+
+
+@pytest.mark.parametrize("kind", ["acf_gauss", "ccf_rect", "ccf_gauss"])
+def test_autotuned_plans_match_oracle_and_default_plan(kind):
+    # the autotuner may pick another grid oversampling, FFT radix split or
+    # tile, window tiling and dispatch: results stay within the parity
+    # tolerances (rectangle counts exact)
+    if kind == "acf_gauss":
+        d = synth.small("c4", seed=41)
+        pa = ncf.plan_acf(d["offs"], d["t"], d["lags"], "gaussian", d["h"], autotune=True)
+        pd = ncf.plan_acf(d["offs"], d["t"], d["lags"], "gaussian", d["h"])
+        vals = (_values_acf(d, 60),)
+    else:
+        d = synth.small("c5" if kind == "ccf_rect" else "c2", seed=42)
+        if kind == "ccf_gauss":
+            d = dict(d, offx=np.array([0, d["t"].size]), offy=np.array([0, d["s"].size]),
+                     h=np.array([d["h"]]))
+        kern = "rectangle" if kind == "ccf_rect" else "gaussian"
+        pa = ncf.plan_ccf(d["offx"], d["t"], d["offy"], d["s"], d["lags"], kern, d["h"],
+                          autotune=True)
+        pd = ncf.plan_ccf(d["offx"], d["t"], d["offy"], d["s"], d["lags"], kern, d["h"])
+        vals = (d["x"], d["y"])
+    try:
+        info = pa.info()
+        assert info["autotuned"] == 1 and info["candidates"] >= 2 and info["replay_ms"] > 0
+        assert pd.info()["autotuned"] == 0
+        ca, ba, na = pa.execute(*vals)[:3]
+        cd, bd, nd = pd.execute(*vals)[:3]
+        if kind == "ccf_rect":
+            np.testing.assert_array_equal(na, nd)
+            assert np.max(np.abs(ca - cd)) <= 1e-9
+            sx = slice(d["offx"][0], d["offx"][1])
+            sy = slice(d["offy"][0], d["offy"][1])
+            st, oc, ob, on = O.ccf(d["t"][sx], vals[0][sx], d["s"][sy], vals[1][sy], d["lags"],
+                                   "rectangle", d["h"][0])
+            np.testing.assert_array_equal(na[0], on)
+        else:
+            assert np.max(np.abs(ca - cd)) <= 1e-5
+            if kind == "acf_gauss":
+                sl = slice(d["offs"][0], d["offs"][1])
+                st, oc, ob, on = O.acf(d["t"][sl], vals[0][sl], d["lags"], "gaussian",
+                                       d["h"][0])
+            else:
+                st, oc, ob, on = O.ccf(d["t"], vals[0], d["s"], vals[1], d["lags"], "gaussian",
+                                       d["h"][0])
+            assert np.max(np.abs(ca[0] - oc)) <= 1e-5
+            _close_b(ba[0], ob, 1e-5)
+    finally:
+        pa.close()
+        pd.close()
