@@ -811,7 +811,8 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         double* numer_all = ar.take<double>((size_t)std::max(nts, 1) * std::max(Keval, 1));
         double* bspec_all =
             spec_b ? ar.take<double>((size_t)std::max(nts, 1) * std::max(Keval, 1)) : nullptr;
-        d_rng = (nts > 0 && bounds_pass) ? ar.take<int64_t>(4 * (size_t)ntiles_all) : nullptr;
+        d_rng = (nts > 0 && bounds_pass) ? ar.take<int64_t>(kTileRec * (size_t)ntiles_all)
+                                         : nullptr;
         for (int i = 0; i < nts; ++i) {
             grids[i] = ar.take<char>((size_t)splans[i].g.N * csz);
             if (two_grids) gridbs[i] = ar.take<char>((size_t)splans[i].g.N * csz);
@@ -926,7 +927,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         T.bspec = bspec[i];
         T.tile0 = ntiles;
         T.ntiles = P.g.N / 4096;
-        T.tile_rng = d_rng ? d_rng + 4 * ntiles : nullptr;
+        T.tile_rng = d_rng ? d_rng + kTileRec * ntiles : nullptr;
         ntiles += T.ntiles;
         total_samp += T.n0 + T.n1;
         hT.smap[J.set[0].sd0 + P.prob] = 2 * i;
@@ -1014,6 +1015,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         const int64_t nkeval = (int64_t)nts * Keval;
         const bool ccf = J.ccf;
         const int32_t* smap = dT.smap;
+        const int64_t* rec_all = d_rng;
         const Chunk* dch = d_ch;
         const double tb_bytes = 8.0 * (double)total_samp;
         if (bounds_pass)
@@ -1021,7 +1023,8 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
                 return launch_tile_bounds(stk, dch, nch, smap, s, tb_bytes);
             }));
         NCF_TRY(emit(J, [=](hipStream_t s) {
-            return launch_spread(stk, tile0, nts, ntiles, 4096, fp64, s, spread_bytes);
+            return launch_spread(stk, tile0, nts, ntiles, rec_all, 4096, ccf, spec_b, fp64, s,
+                                 spread_bytes);
         }));
         for (size_t q = 0; q < groups.size(); ++q) {
             const FftPlan fp = plans[splans[groups[q].first].g.N];
@@ -2047,7 +2050,7 @@ int ncf_diag_type1(int64_t n, const double* t, const double* v, double t_ref, do
     NCF_TRY_HIP(hipMalloc((void**)&dt, sizeof(double) * n));
     NCF_TRY_HIP(hipMalloc(&dv, (fp64 ? 8 : 4) * n));
     NCF_TRY_HIP(hipMalloc(&grid, esz * N));
-    NCF_TRY_HIP(hipMalloc((void**)&rng, sizeof(int64_t) * 4 * (N / 4096)));
+    NCF_TRY_HIP(hipMalloc((void**)&rng, sizeof(int64_t) * kTileRec * (N / 4096)));
     NCF_TRY_HIP(hipMalloc((void**)&dtask, sizeof(SpecTask)));
     NCF_TRY_HIP(hipMalloc((void**)&dtile0, sizeof(int64_t) * 2));
     std::vector<Chunk> hch;
@@ -2085,7 +2088,8 @@ int ncf_diag_type1(int64_t n, const double* t, const double* v, double t_ref, do
     NCF_TRY_HIP(hipMemcpy(dmap, &hmap, sizeof hmap, hipMemcpyHostToDevice));
     NCF_TRY_HIP(hipMemcpy(dg, &grid, sizeof(void*), hipMemcpyHostToDevice));
     int rc = launch_tile_bounds(dtask, dch, (int)hch.size(), dmap, st, 8.0 * n);
-    if (rc == NCF_OK) rc = launch_spread(dtask, dtile0, 1, T.ntiles, 4096, fp64, st, 0.0);
+    if (rc == NCF_OK)
+        rc = launch_spread(dtask, dtile0, 1, T.ntiles, rng, 4096, false, false, fp64, st, 0.0);
     FftPlan plan;
     if (rc == NCF_OK) rc = fft_plan(N, fp64, &plan, st);
     if (rc == NCF_OK) rc = fft_exec(plan, dg, 1, +1, fp64, st);

@@ -226,7 +226,7 @@ struct SpecTask {
     void* grid;            // N complex (float2 or double2)
     int64_t tile0;         // first spreading tile of this task
     int64_t ntiles;
-    int64_t* tile_rng;     // [ntiles][4]: sample ranges p0, p1 of set 0 and of set 1
+    int64_t* tile_rng;     // [ntiles][kTileRec] bounds records of this task's tiles
     double* lags;          // K_eval lags to evaluate (device)
     int32_t K_eval;
     int32_t pad;
@@ -240,14 +240,22 @@ struct SpecTask {
     double* bspec;         // with_b: K_eval results b(tau)
 };
 
-// Fill every task's tile_rng ([ntiles][4]: p0, p1 of set 0, p0, p1 of set 1)
-// for the spread, one workgroup per chunk of samples (the moments chunks);
+// Spreading tile records: p0, p1 of set 0, p0, p1 of set 1, task index,
+// padding (kTileRec int64 per tile, one cache line).
+constexpr int kTileRec = 8;
+
+// Fill every task's tile records (tile_rng) for the spread, one workgroup
+// per chunk of samples (the moments chunks);
 // d_series_map[chunk.series] = 2 * task + set, or -1 for a series without a
 // spectral task.
 int launch_tile_bounds(const SpecTask* d_tasks, const Chunk* d_chunks, int nchunks,
                        const int32_t* d_series_map, hipStream_t st, double bytes);
+// All tasks of one launch share the mode (ACF/CCF, unit-weight channel).
+// d_tile_rec: the tile records of all tasks (contiguous, in tile order) from
+// launch_tile_bounds, or null to search the ranges in each workgroup.
 int launch_spread(const SpecTask* d_tasks, const int64_t* d_tile0, int ntasks, int64_t ntiles,
-                  int tile, bool fp64, hipStream_t st, double bytes);
+                  const int64_t* d_tile_rec, int tile, bool ccf, bool with_b, bool fp64,
+                  hipStream_t st, double bytes);
 int launch_interp(const SpecTask* d_tasks, int ntasks, const int64_t* d_k0, int64_t total_k,
                   bool fp64, hipStream_t st);
 

@@ -97,13 +97,15 @@ k_tile_bounds(const SpecTask* __restrict__ tasks, const Chunk* __restrict__ chun
     const Chunk ch = chunks[blockIdx.x];
     const int32_t code = series_map[ch.series];  // 2 * task + set, or -1
     if (code < 0) return;
-    const SpecTask& T = tasks[code >> 1];
+    const int task = code >> 1;
+    const SpecTask& T = tasks[task];
     const int set = code & 1;
     const gptr<const double> t = gbl(set ? T.t1 : T.t0);
+    const int64_t n = set ? T.n1 : T.n0;
     const double sc = (double)T.N / T.L;
     const double reach = T.W + 2.0;
     const int64_t nt = T.ntiles;
-    const gptr<int64_t> rng = gbl(T.tile_rng);
+    const gptr<int64_t> rec = gbl(T.tile_rng);  // [tile][kTileRec]
     const int lane = threadIdx.x & 63;
     for (int64_t b = ch.begin; b < ch.end; b += kThreads) {
         const int64_t i = b + threadIdx.x;
@@ -120,12 +122,24 @@ k_tile_bounds(const SpecTask* __restrict__ tasks, const Chunk* __restrict__ chun
         } else if (lane == 0) {
             tile_reach((t[i - 1] - T.t_ref) * sc, reach, a0, b0);
         }
-        // tiles past the last sample's reach are not written here: the
-        // spread derives their bounds (n) from the last sample itself
-        for (int64_t q = max(a0 + 1, (int64_t)0); q <= min(a1, nt - 1); ++q)
-            rng[4 * q + 2 * set] = i;
+        for (int64_t q = max(a0 + 1, (int64_t)0); q <= min(a1, nt - 1); ++q) {
+            rec[kTileRec * q + 2 * set] = i;
+            if (set == 0) rec[kTileRec * q + 4] = task;
+        }
         for (int64_t q = max(b0, (int64_t)0); q <= min(b1 - 1, nt - 1); ++q)
-            rng[4 * q + 2 * set + 1] = i;
+            rec[kTileRec * q + 2 * set + 1] = i;
+    }
+    // tiles past the last sample's reach: bound n, filled by the workgroup
+    // that holds the last sample, all threads together
+    if (ch.end == n) {
+        int64_t A, B;
+        tile_reach((t[n - 1] - T.t_ref) * sc, reach, A, B);
+        for (int64_t q = max(A + 1, (int64_t)0) + threadIdx.x; q < nt; q += kThreads) {
+            rec[kTileRec * q + 2 * set] = n;
+            if (set == 0) rec[kTileRec * q + 4] = task;
+        }
+        for (int64_t q = max(B, (int64_t)0) + threadIdx.x; q < nt; q += kThreads)
+            rec[kTileRec * q + 2 * set + 1] = n;
     }
 }
 
@@ -188,25 +202,39 @@ __device__ void gather_set(R (&acc)[kCellsPerThread], R (&accu)[kCellsPerThread]
     }
 }
 
-template <typename R>
+// MODE: bit 1 CCF (two point sets), bit 0 unit-weight channel; fixed per
+// launch, so accumulators that a mode does not use cost no registers.
+template <typename R, int MODE>
 __global__ void __launch_bounds__(kThreads)
 k_spread(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ tile0, int ntasks,
-         int64_t ntiles, int64_t nblocks) {
+         int64_t ntiles, int64_t nblocks, const int64_t* __restrict__ tile_rec) {
     using C2 = typename Cplx<R>::T;
+    constexpr bool CCF = (MODE & 2) != 0;
+    constexpr bool WB = (MODE & 1) != 0;
     __shared__ PtsLds<R> P;
     const int64_t g = blockIdx.x;
     (void)nblocks;
     if (g >= ntiles) return;
-    const int ti = ntasks == 1 ? 0 : (int)wave_search<int64_t>(tile0, ntasks, g, true) - 1;
+    // task of this tile: from its bounds record (bounds pass), else by search
+    int ti;
+    int64_t rec[kTileRec];
+    const bool have_rec = tile_rec != nullptr;
+    if (have_rec) {
+        const gptr<const int64_t> r = gbl(tile_rec) + kTileRec * g;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) rec[q] = r[q];
+        ti = (int)rec[4];
+    } else {
+        ti = ntasks == 1 ? 0 : (int)wave_search<int64_t>(tile0, ntasks, g, true) - 1;
+    }
     const SpecTask& T = tasks[ti];
     const int64_t tile = g - T.tile0;
     const int64_t c0 = tile * kTile;
-    // sample index ranges that reach this tile: from k_tile_bounds (a tile
-    // past the last sample's reach has bound n, found from that sample), or
+    // sample index ranges that reach this tile: from the bounds record, or
     // for calls with few tiles by wave searches in this workgroup
     __shared__ int64_t srng[4];
     int64_t rng[4];
-    if (!T.tile_rng) {
+    if (!have_rec) {
         const int wave = threadIdx.x >> 6;
         const double inv_scale = T.L / (double)T.N;  // time per cell
         const double lo_t = T.t_ref + ((double)c0 - T.W - 2.0) * inv_scale;
@@ -220,18 +248,20 @@ k_spread(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ tile0, 
         __syncthreads();
         for (int q = 0; q < 4; ++q) rng[q] = srng[q];
     } else {
-        const gptr<const int64_t> r = gbl((const int64_t*)T.tile_rng) + 4 * tile;
-        const double sc = (double)T.N / T.L;
-        const double reach = T.W + 2.0;
-        for (int set = 0; set < (T.ccf ? 2 : 1); ++set) {
-            const double* tp = set ? T.t1 : T.t0;
-            const int64_t n = set ? T.n1 : T.n0;
-            int64_t A, B;
-            tile_reach((gbl(tp)[n - 1] - T.t_ref) * sc, reach, A, B);
-            rng[2 * set] = tile > A ? n : r[2 * set];
-            rng[2 * set + 1] = tile + 1 > B ? n : r[2 * set + 1];
+        rng[0] = rec[0];
+        rng[1] = rec[1];
+        rng[2] = CCF ? rec[2] : 0;
+        rng[3] = CCF ? rec[3] : 0;
+    }
+    // a tile no sample reaches (lag padding, seasonal gaps): coalesced zeros,
+    // no staging
+    if (rng[0] >= rng[1] && rng[2] >= rng[3]) {
+        constexpr int ngz = (CCF && WB) ? 2 : 1;
+        for (int gsel = 0; gsel < ngz; ++gsel) {
+            const gptr<R> grid = gbl(reinterpret_cast<R*>(gsel == 0 ? T.grid : T.gridb) + 2 * c0);
+            for (int i = threadIdx.x; i < 2 * kTile; i += kThreads) grid[i] = (R)0;
         }
-        if (!T.ccf) rng[2] = rng[3] = 0;
+        return;
     }
     const double scale = (double)T.N / T.L;
     const R W = (R)T.W;
@@ -241,15 +271,11 @@ k_spread(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ tile0, 
     R re[kCellsPerThread], im[kCellsPerThread], u0[kCellsPerThread], u1[kCellsPerThread];
 #pragma unroll
     for (int q = 0; q < kCellsPerThread; ++q) re[q] = im[q] = u0[q] = u1[q] = (R)0;
-    if (!T.ccf) {
+    if constexpr (!CCF) {
         // ACF: values in the real channel, unit weights (with_b) in the imaginary one
-        if (T.with_b)
-            gather_set<R, true>(re, im, P, T.t0, T.v0f, T.v0d, rng[0], rng[1], c0, T.t_ref, scale,
-                                W, k2);
-        else
-            gather_set<R, false>(re, im, P, T.t0, T.v0f, T.v0d, rng[0], rng[1], c0, T.t_ref,
-                                 scale, W, k2);
-    } else if (T.with_b) {
+        gather_set<R, WB>(re, im, P, T.t0, T.v0f, T.v0d, rng[0], rng[1], c0, T.t_ref, scale, W,
+                          k2);
+    } else if constexpr (WB) {
         // CCF: grid = series 1 values + i series 2 values; gridb = the same with unit weights
         gather_set<R, true>(re, u0, P, T.t0, T.v0f, T.v0d, rng[0], rng[1], c0, T.t_ref, scale, W,
                             k2);
@@ -267,7 +293,7 @@ k_spread(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ tile0, 
     static_assert(sizeof(PtsLds<R>) >= sizeof(C2) * (kTile / 2 + kTile / 32),
                   "LDS staging too small");
     C2* out = reinterpret_cast<C2*>(&P);
-    const int ngrids = (T.ccf && T.with_b) ? 2 : 1;
+    constexpr int ngrids = (CCF && WB) ? 2 : 1;
     for (int gsel = 0; gsel < ngrids; ++gsel) {
         const gptr<R> grid = gbl(reinterpret_cast<R*>(gsel == 0 ? T.grid : T.gridb) + 2 * c0);
         for (int half = 0; half < 2; ++half) {
@@ -597,21 +623,34 @@ int launch_tile_bounds(const SpecTask* d_tasks, const Chunk* d_chunks, int nchun
     return NCF_OK;
 }
 
+template <typename R>
+void (*spread_kernel(int mode))(const SpecTask*, const int64_t*, int, int64_t, int64_t,
+                                const int64_t*) {
+    switch (mode & 3) {
+        case 0: return k_spread<R, 0>;
+        case 1: return k_spread<R, 1>;
+        case 2: return k_spread<R, 2>;
+        default: return k_spread<R, 3>;
+    }
+}
+
 int launch_spread(const SpecTask* d_tasks, const int64_t* d_tile0, int ntasks, int64_t ntiles,
-                  int tile, bool fp64, hipStream_t st, double bytes) {
+                  const int64_t* d_tile_rec, int tile, bool ccf, bool with_b, bool fp64,
+                  hipStream_t st, double bytes) {
     if (tile != kTile) {
         set_error("spread tile mismatch");
         return NCF_E_UNSUPPORTED;
     }
     if (ntiles <= 0) return NCF_OK;
     const int64_t nblocks = round_up(ntiles, kXcds);
+    const int mode = (ccf ? 2 : 0) | (with_b ? 1 : 0);
     ProfScope p(st, fp64 ? "spread_f64" : "spread_f32", bytes, "bytes");
     if (fp64)
-        hipLaunchKernelGGL(k_spread<double>, dim3((unsigned)nblocks), dim3(kThreads), 0, st,
-                           d_tasks, d_tile0, ntasks, ntiles, nblocks);
+        hipLaunchKernelGGL(spread_kernel<double>(mode), dim3((unsigned)nblocks), dim3(kThreads),
+                           0, st, d_tasks, d_tile0, ntasks, ntiles, nblocks, d_tile_rec);
     else
-        hipLaunchKernelGGL(k_spread<float>, dim3((unsigned)nblocks), dim3(kThreads), 0, st,
-                           d_tasks, d_tile0, ntasks, ntiles, nblocks);
+        hipLaunchKernelGGL(spread_kernel<float>(mode), dim3((unsigned)nblocks), dim3(kThreads),
+                           0, st, d_tasks, d_tile0, ntasks, ntiles, nblocks, d_tile_rec);
     NCF_CHECK_LAUNCH();
     return NCF_OK;
 }
