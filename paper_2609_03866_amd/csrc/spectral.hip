@@ -35,7 +35,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kCellsPerThread = 16;
 constexpr int kTile = kThreads * kCellsPerThread;  // 4096 cells per workgroup
-constexpr int kPtsChunk = 2048;
+constexpr int kPtsChunk = 1024;  // staged samples per round (a tile holds a few hundred)
 
 template <typename R>
 struct Cplx;
@@ -143,11 +143,18 @@ k_tile_bounds(const SpecTask* __restrict__ tasks, const Chunk* __restrict__ chun
     }
 }
 
+// LDS of a spreading workgroup: the staged samples, later reused to stage
+// half of the tile's cells for the coalesced write (one pad slot per 16).
 template <typename R>
 struct PtsLds {
-    int cell[kPtsChunk];  // cell index relative to the tile start
-    R frac[kPtsChunk];    // fraction in [0, 1)
-    R val[kPtsChunk];
+    union {
+        struct {
+            int cell[kPtsChunk];  // cell index relative to the tile start
+            R frac[kPtsChunk];    // fraction in [0, 1)
+            R val[kPtsChunk];
+        };
+        typename Cplx<R>::T out[kTile / 2 + kTile / 32];
+    };
 };
 
 // Accumulate one point set into the thread's 16 cells.
@@ -223,7 +230,8 @@ k_spread(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ tile0, 
         const gptr<const int64_t> r = gbl(tile_rec) + kTileRec * g;
 #pragma unroll
         for (int q = 0; q < 5; ++q) rec[q] = r[q];
-        ti = (int)rec[4];
+        // one task: its descriptor loads need not wait for the record
+        ti = ntasks == 1 ? 0 : (int)rec[4];
     } else {
         ti = ntasks == 1 ? 0 : (int)wave_search<int64_t>(tile0, ntasks, g, true) - 1;
     }
@@ -292,7 +300,7 @@ k_spread(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ tile0, 
     // threads' 16-cell runs on different banks
     static_assert(sizeof(PtsLds<R>) >= sizeof(C2) * (kTile / 2 + kTile / 32),
                   "LDS staging too small");
-    C2* out = reinterpret_cast<C2*>(&P);
+    C2* out = P.out;
     constexpr int ngrids = (CCF && WB) ? 2 : 1;
     for (int gsel = 0; gsel < ngrids; ++gsel) {
         const gptr<R> grid = gbl(reinterpret_cast<R*>(gsel == 0 ? T.grid : T.gridb) + 2 * c0);
