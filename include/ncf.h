@@ -160,6 +160,63 @@ int ncf_ccf_batch(int64_t npair, const int64_t* offx, const double* tx, const do
                   const double* ey, int64_t K, const double* lags, int kern, const double* h,
                   double* c, double* b, int64_t* count, int* status, const ncf_options_t* opt);
 
+/* ------------------------------------------------ regular-lattice family
+ * Classic-FFT estimators for series sampled on a regular time lattice
+ * (Sec. "Regularly-sampled data"; eq. wienerkhinchin of Sec. "Correlation
+ * estimation on a regular grid"). They compute the same Gaussian/rectangle
+ * kernel estimator (eq. kernel_estimator) as ncf_acf / ncf_ccf, at a cost
+ * of O(N log N) with N ~ 2 x the lattice length, independent of K: one FP64
+ * FFT correlation gives the raw lag correlations R(q) of the lattice grids
+ * and the raw pair counts N(q) of the sample-count grids (the ramp n - |q|
+ * without gaps), and every requested lag filters them with the kernel
+ * weights (the pair count is the filtered N, as Sec. "Effective pair count"
+ * describes for this family).
+ *
+ *  - Lattice: t_i = t_ref + m_i dt with integer m_i, where t_ref is the
+ *    first time of the series (CCF: of either series, so both series must
+ *    share one lattice). Gaps (missing m) and repeated times are allowed;
+ *    times must be non-decreasing. A time farther than 1e-6 dt from its
+ *    lattice point gives NCF_E_INVALID_ARG for its series (pair). dt > 0 is
+ *    given by the caller (one per problem in the batch calls).
+ *  - Reading of the estimator on the lattice: each sample sits exactly at
+ *    its lattice point, so a pair's lag is q dt. Lattice lag q is in the
+ *    window of lag tau when q lies between (tau - W)/dt and (tau + W)/dt
+ *    (W = 6h Gaussian, h rectangle), each bound first rounded to the
+ *    nearest integer when within 1e-9 (relative) of it, with the open and
+ *    closed ends of the irregular estimator: Gaussian ACF [lo, hi), Gaussian
+ *    CCF (lo, hi] (lag q = m_y - m_x), rectangle [lo, hi]. The weight is
+ *    the kernel at q dt - tau. Where the times, lags, dt and h are exact
+ *    binary fractions this is exactly the estimator of ncf_acf / ncf_ccf.
+ *  - Always computed in FP64 (options->precision and ->method are
+ *    ignored): the pair counts come out exact (count) and c agrees with the
+ *    direct FP64 sums to ~1e-12.
+ *  - Outputs, statuses, host/device pointers and streams as in the batch
+ *    calls; lags may be any finite values (not only multiples of dt).
+ *  - The lattice length (last time - t_ref)/dt + 1 plus the largest lag
+ *    reach (max|tau| + W)/dt must stay below 2^31 (else NCF_E_UNSUPPORTED).
+ */
+int ncf_acf_regular(int64_t n, const double* t, const double* x, const double* err, double dt,
+                    int64_t K, const double* lags, int kern, double h, double* c, double* b,
+                    int64_t* count, const ncf_options_t* opt);
+
+int ncf_ccf_regular(int64_t nx, const double* tx, const double* x, const double* ex, int64_t ny,
+                    const double* ty, const double* y, const double* ey, double dt, int64_t K,
+                    const double* lags, int kern, double h, double* c, double* b,
+                    int64_t* count, const ncf_options_t* opt);
+
+/* Batched forms (layout as in ncf_acf_batch / ncf_ccf_batch); dt is a HOST
+ * array of one lattice step per series (pair). */
+int ncf_acf_regular_batch(int64_t nser, const int64_t* offs, const double* t, const double* x,
+                          const double* err, const double* dt, int64_t K, const double* lags,
+                          int kern, const double* h, double* c, double* b, int64_t* count,
+                          int* status, const ncf_options_t* opt);
+
+int ncf_ccf_regular_batch(int64_t npair, const int64_t* offx, const double* tx, const double* x,
+                          const double* ex, const int64_t* offy, const double* ty,
+                          const double* y, const double* ey, const double* dt, int64_t K,
+                          const double* lags, int kern, const double* h, double* c, double* b,
+                          int64_t* count, int* status, const ncf_options_t* opt);
+
 /* ----------------------------------------------------------------- plans
  * A plan fixes everything of a batch call except the values: times, errors,
  * lags, kernel, bandwidths and options. Building it runs the whole path once

@@ -121,6 +121,10 @@ typedef struct {
     int64_t n_win;
     const double *t, *v_win, *w_win;
     double h;
+    /* lattice reading (regular-lattice estimators): lattice indices of the
+     * outer and window samples and the step; m_out == NULL for real times */
+    const int64_t *m_out, *m_win;
+    double dt;
 } scan_args;
 
 /* Two-pointer window scan for one lag (PairCount / CorrSum loop body). */
@@ -165,6 +169,53 @@ static void scan_one_lag(const scan_args* a, double tau, double* C, double* B, d
     *count = n_acc;
 }
 
+/* ------------------------------------------- lattice reading of the scan */
+
+/* Regular-lattice estimators (Sec. "Regularly-sampled data"): every sample
+ * sits at its lattice point t_ref + m dt, so the pair (i, j) has lag
+ * (m_i - m_j) dt and d = (m_i - m_j) dt - eps*tau. The window is decided in
+ * lattice units: with lo = (eps*tau - W)/dt and hi = (eps*tau + W)/dt, each
+ * rounded to the nearest integer when within 1e-9 (relative) of it, the pair
+ * is in the window when lo <= m_i - m_j < hi (Gaussian, W = 6h) or
+ * lo <= m_i - m_j <= hi (rectangle, W = h): the predicates above with the
+ * times replaced by their lattice points. */
+static double snap_edge(double e) {
+    double r = nearbyint(e);
+    return fabs(e - r) <= 1e-9 * fmax(1.0, fabs(e)) ? r : e;
+}
+
+static void lattice_one_lag(const scan_args* a, double tau, double* C, double* B, double* b,
+                            int64_t* count) {
+    double c_acc = 0.0, B_acc = 0.0, b_acc = 0.0;
+    int64_t n_acc = 0;
+    const double e = (double)a->eps;
+    const int gauss = a->kernel == ORC_GAUSSIAN;
+    const double W = gauss ? 6.0 * a->h : a->h;
+    const double lo = snap_edge((e * tau - W) / a->dt);
+    const double hi = snap_edge((e * tau + W) / a->dt);
+    int64_t i_lo = 0, i_hi = 0;
+    for (int64_t j = 0; j < a->n_out; ++j) {
+        const int64_t mj = a->m_out[j];
+        while (i_lo < a->n_win && (double)(a->m_win[i_lo] - mj) < lo) i_lo++;
+        if (i_hi < i_lo) i_hi = i_lo;
+        while (i_hi < a->n_win &&
+               (gauss ? (double)(a->m_win[i_hi] - mj) < hi : (double)(a->m_win[i_hi] - mj) <= hi))
+            i_hi++;
+        for (int64_t i = i_lo; i < i_hi; ++i) {
+            const double q = (double)(a->m_win[i] - mj);
+            const double wt = gauss ? gauss_weight(q * a->dt - e * tau, a->h) : 1.0;
+            c_acc += wt * a->v_win[i] * a->v_out[j];
+            B_acc += wt * a->w_win[i] * a->w_out[j];
+            b_acc += wt;
+            n_acc += 1;
+        }
+    }
+    *C = c_acc;
+    *B = B_acc;
+    *b = b_acc;
+    *count = n_acc;
+}
+
 /* All-pairs evaluation of the same window predicates (no scan). */
 static void brute_one_lag(const scan_args* a, double tau, double* C, double* B, double* b,
                           int64_t* count) {
@@ -197,20 +248,25 @@ static void brute_one_lag(const scan_args* a, double tau, double* C, double* B, 
 }
 
 /* Window sums for every lag; lags distributed over threads as the paper's
- * parallel-for over k. Outputs are raw (not floored). */
-int oracle_window_sums(int kernel, int eps, int64_t n_out, const double* s, const double* v_out,
+ * parallel-for over k. Outputs are raw (not floored). m_out/m_win: lattice
+ * indices for the lattice reading, or NULL. */
+static int window_sums(int kernel, int eps, int64_t n_out, const double* s, const double* v_out,
                        const double* w_out, int64_t n_win, const double* t, const double* v_win,
-                       const double* w_win, int64_t K, const double* lags, double h, double* C,
-                       double* B, double* b, int64_t* count, int nthreads, int brute) {
+                       const double* w_win, const int64_t* m_out, const int64_t* m_win,
+                       double dt, int64_t K, const double* lags, double h, double* C, double* B,
+                       double* b, int64_t* count, int nthreads, int brute) {
     if (kernel != ORC_GAUSSIAN && kernel != ORC_RECTANGLE) return ORC_E_INVALID_ARG;
     if (eps != 1 && eps != -1) return ORC_E_INVALID_ARG;
-    scan_args a = {kernel, eps, n_out, s, v_out, w_out, n_win, t, v_win, w_win, h};
+    scan_args a = {kernel, eps, n_out, s, v_out, w_out, n_win, t, v_win, w_win, h,
+                   m_out, m_win, dt};
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 1)
 #endif
     for (int64_t k = 0; k < K; ++k) {
-        if (brute)
+        if (m_out)
+            lattice_one_lag(&a, lags[k], &C[k], &B[k], &b[k], &count[k]);
+        else if (brute)
             brute_one_lag(&a, lags[k], &C[k], &B[k], &b[k], &count[k]);
         else
             scan_one_lag(&a, lags[k], &C[k], &B[k], &b[k], &count[k]);
@@ -219,18 +275,39 @@ int oracle_window_sums(int kernel, int eps, int64_t n_out, const double* s, cons
     return ORC_OK;
 }
 
+int oracle_window_sums(int kernel, int eps, int64_t n_out, const double* s, const double* v_out,
+                       const double* w_out, int64_t n_win, const double* t, const double* v_win,
+                       const double* w_win, int64_t K, const double* lags, double h, double* C,
+                       double* B, double* b, int64_t* count, int nthreads, int brute) {
+    return window_sums(kernel, eps, n_out, s, v_out, w_out, n_win, t, v_win, w_win, NULL, NULL,
+                       0.0, K, lags, h, C, B, b, count, nthreads, brute);
+}
+
+/* Lattice indices m_i = round((t_i - t_ref)/dt); a time farther than
+ * 1e-6 dt from its lattice point is rejected. */
+static int lattice_indices(int64_t n, const double* t, double t_ref, double dt, int64_t* m) {
+    for (int64_t i = 0; i < n; ++i) {
+        double u = nearbyint((t[i] - t_ref) / dt);
+        if (!(fabs(t[i] - (t_ref + u * dt)) <= 1e-6 * dt)) return ORC_E_INVALID_ARG;
+        m[i] = (int64_t)u;
+    }
+    return ORC_OK;
+}
+
 /* ------------------------------------------------------------ estimators */
 
 static double floor_b(double v) { return v > ORC_FLOOR ? v : ORC_FLOOR; }
 
-int oracle_acf(int64_t n, const double* t, const double* x, const double* err, int64_t K,
-               const double* lags, int kernel, double h, double* c, double* b_out,
-               int64_t* count_out, int nthreads, int brute) {
+/* dt > 0: lattice reading with t_ref = t[0] (regular-lattice estimators) */
+static int acf_impl(int64_t n, const double* t, const double* x, const double* err, int64_t K,
+                    const double* lags, int kernel, double h, double* c, double* b_out,
+                    int64_t* count_out, int nthreads, int brute, double dt) {
     int st = check_series(n, t, x, err);
     if (st) return st;
     st = check_lags(K, lags, h);
     if (st) return st;
     if (kernel != ORC_GAUSSIAN && kernel != ORC_RECTANGLE) return ORC_E_INVALID_ARG;
+    if (dt != 0.0 && (!(dt > 0.0) || !isfinite(dt))) return ORC_E_INVALID_ARG;
 
     double* v = malloc(sizeof(double) * n);
     double* w = malloc(sizeof(double) * n);
@@ -239,17 +316,22 @@ int oracle_acf(int64_t n, const double* t, const double* x, const double* err, i
     double* B = malloc(sizeof(double) * (K + 1));
     double* bb = malloc(sizeof(double) * (K + 1));
     int64_t* cnt = malloc(sizeof(int64_t) * (K + 1));
-    if (!v || !w || !ev || !C || !B || !bb || !cnt) {
+    int64_t* m = dt > 0.0 ? malloc(sizeof(int64_t) * n) : NULL;
+    if (!v || !w || !ev || !C || !B || !bb || !cnt || (dt > 0.0 && !m)) {
         st = ORC_E_NOMEM;
         goto done;
+    }
+    if (m) {
+        st = lattice_indices(n, t, t[0], dt, m);
+        if (st) goto done;
     }
     st = oracle_standardize(n, x, err, v, w);
     if (st) goto done;
     /* evaluation lags (0, tau_1, ..., tau_K): lag 0 is prepended */
     ev[0] = 0.0;
     for (int64_t k = 0; k < K; ++k) ev[k + 1] = lags[k];
-    oracle_window_sums(kernel, +1, n, t, v, w, n, t, v, w, K + 1, ev, h, C, B, bb, cnt, nthreads,
-                       brute);
+    window_sums(kernel, +1, n, t, v, w, n, t, v, w, m, m, dt, K + 1, ev, h, C, B, bb, cnt,
+                nthreads, brute);
     double r0 = C[0] / floor_b(B[0]);
     if (!(r0 > 0.0) || !isfinite(r0)) {
         for (int64_t k = 0; k < K; ++k) {
@@ -274,13 +356,28 @@ done:
     free(B);
     free(bb);
     free(cnt);
+    free(m);
     return st;
 }
 
-int oracle_ccf(int64_t nx, const double* t, const double* x, const double* ex, int64_t ny,
-               const double* s, const double* y, const double* ey, int64_t K, const double* lags,
-               int kernel, double h, double* c, double* b_out, int64_t* count_out, int nthreads,
-               int brute) {
+int oracle_acf(int64_t n, const double* t, const double* x, const double* err, int64_t K,
+               const double* lags, int kernel, double h, double* c, double* b_out,
+               int64_t* count_out, int nthreads, int brute) {
+    return acf_impl(n, t, x, err, K, lags, kernel, h, c, b_out, count_out, nthreads, brute, 0.0);
+}
+
+int oracle_acf_regular(int64_t n, const double* t, const double* x, const double* err,
+                       double dt, int64_t K, const double* lags, int kernel, double h, double* c,
+                       double* b_out, int64_t* count_out, int nthreads) {
+    if (!(dt > 0.0)) return ORC_E_INVALID_ARG;
+    return acf_impl(n, t, x, err, K, lags, kernel, h, c, b_out, count_out, nthreads, 0, dt);
+}
+
+/* dt > 0: lattice reading with t_ref = min(t[0], s[0]) */
+static int ccf_impl(int64_t nx, const double* t, const double* x, const double* ex, int64_t ny,
+                    const double* s, const double* y, const double* ey, int64_t K,
+                    const double* lags, int kernel, double h, double* c, double* b_out,
+                    int64_t* count_out, int nthreads, int brute, double dt) {
     int st = check_series(nx, t, x, ex);
     if (st) return st;
     st = check_series(ny, s, y, ey);
@@ -288,6 +385,7 @@ int oracle_ccf(int64_t nx, const double* t, const double* x, const double* ex, i
     st = check_lags(K, lags, h);
     if (st) return st;
     if (kernel != ORC_GAUSSIAN && kernel != ORC_RECTANGLE) return ORC_E_INVALID_ARG;
+    if (dt != 0.0 && (!(dt > 0.0) || !isfinite(dt))) return ORC_E_INVALID_ARG;
 
     double *vx = malloc(sizeof(double) * nx), *wx = malloc(sizeof(double) * nx);
     double *vy = malloc(sizeof(double) * ny), *wy = malloc(sizeof(double) * ny);
@@ -295,9 +393,18 @@ int oracle_ccf(int64_t nx, const double* t, const double* x, const double* ex, i
     double* B = malloc(sizeof(double) * (K + 1));
     double* bb = malloc(sizeof(double) * (K + 1));
     int64_t* cnt = malloc(sizeof(int64_t) * (K + 1));
-    if (!vx || !wx || !vy || !wy || !C || !B || !bb || !cnt) {
+    int64_t* mx = dt > 0.0 ? malloc(sizeof(int64_t) * nx) : NULL;
+    int64_t* my = dt > 0.0 ? malloc(sizeof(int64_t) * ny) : NULL;
+    if (!vx || !wx || !vy || !wy || !C || !B || !bb || !cnt || (dt > 0.0 && (!mx || !my))) {
         st = ORC_E_NOMEM;
         goto done;
+    }
+    if (dt > 0.0) {
+        const double t_ref = t[0] < s[0] ? t[0] : s[0];
+        st = lattice_indices(nx, t, t_ref, dt, mx);
+        if (st) goto done;
+        st = lattice_indices(ny, s, t_ref, dt, my);
+        if (st) goto done;
     }
     st = oracle_standardize(nx, x, ex, vx, wx);
     if (st) goto done;
@@ -306,16 +413,16 @@ int oracle_ccf(int64_t nx, const double* t, const double* x, const double* ex, i
 
     /* cross sums: outer array = series 2 (s), window array = series 1 (t), eps = -1 */
     if (K > 0)
-        oracle_window_sums(kernel, -1, ny, s, vy, wy, nx, t, vx, wx, K, lags, h, C, B, bb, cnt,
-                           nthreads, brute);
+        window_sums(kernel, -1, ny, s, vy, wy, nx, t, vx, wx, my, mx, dt, K, lags, h, C, B, bb,
+                    cnt, nthreads, brute);
     /* lag-0 scales of each series on itself, eps = +1 */
     double zero = 0.0, Cs, Bs, bs;
     int64_t ns;
-    oracle_window_sums(kernel, +1, nx, t, vx, wx, nx, t, vx, wx, 1, &zero, h, &Cs, &Bs, &bs, &ns,
-                       nthreads, brute);
+    window_sums(kernel, +1, nx, t, vx, wx, nx, t, vx, wx, mx, mx, dt, 1, &zero, h, &Cs, &Bs, &bs,
+                &ns, nthreads, brute);
     double scale_x = Cs / floor_b(Bs);
-    oracle_window_sums(kernel, +1, ny, s, vy, wy, ny, s, vy, wy, 1, &zero, h, &Cs, &Bs, &bs, &ns,
-                       nthreads, brute);
+    window_sums(kernel, +1, ny, s, vy, wy, ny, s, vy, wy, my, my, dt, 1, &zero, h, &Cs, &Bs, &bs,
+                &ns, nthreads, brute);
     double scale_y = Cs / floor_b(Bs);
     double prod = scale_x * scale_y;
     int degenerate = !(prod > 0.0) || !isfinite(prod);
@@ -336,7 +443,26 @@ done:
     free(B);
     free(bb);
     free(cnt);
+    free(mx);
+    free(my);
     return st;
+}
+
+int oracle_ccf(int64_t nx, const double* t, const double* x, const double* ex, int64_t ny,
+               const double* s, const double* y, const double* ey, int64_t K, const double* lags,
+               int kernel, double h, double* c, double* b_out, int64_t* count_out, int nthreads,
+               int brute) {
+    return ccf_impl(nx, t, x, ex, ny, s, y, ey, K, lags, kernel, h, c, b_out, count_out,
+                    nthreads, brute, 0.0);
+}
+
+int oracle_ccf_regular(int64_t nx, const double* t, const double* x, const double* ex,
+                       int64_t ny, const double* s, const double* y, const double* ey, double dt,
+                       int64_t K, const double* lags, int kernel, double h, double* c,
+                       double* b_out, int64_t* count_out, int nthreads) {
+    if (!(dt > 0.0)) return ORC_E_INVALID_ARG;
+    return ccf_impl(nx, t, x, ex, ny, s, y, ey, K, lags, kernel, h, c, b_out, count_out,
+                    nthreads, 0, dt);
 }
 
 int oracle_max_threads(void) {

@@ -51,6 +51,12 @@ def _load():
         lib.oracle_ccf.argtypes = [ctypes.c_int64, d, d, d, ctypes.c_int64, d, d, d,
                                    ctypes.c_int64, d, ctypes.c_int, ctypes.c_double, d, d, i64p,
                                    ctypes.c_int, ctypes.c_int]
+        lib.oracle_acf_regular.argtypes = [ctypes.c_int64, d, d, d, ctypes.c_double,
+                                           ctypes.c_int64, d, ctypes.c_int, ctypes.c_double, d,
+                                           d, i64p, ctypes.c_int]
+        lib.oracle_ccf_regular.argtypes = [ctypes.c_int64, d, d, d, ctypes.c_int64, d, d, d,
+                                           ctypes.c_double, ctypes.c_int64, d, ctypes.c_int,
+                                           ctypes.c_double, d, d, i64p, ctypes.c_int]
         lib.oracle_window_sums.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, d, d, d,
                                            ctypes.c_int64, d, d, d, ctypes.c_int64, d,
                                            ctypes.c_double, d, d, d, i64p, ctypes.c_int,
@@ -109,6 +115,35 @@ def ccf(t, x, s, y, lags, kernel, h, ex=None, ey=None, threads=0, brute=False):
                         _dp(lags), kernel_id(kernel), float(h), _dp(c), _dp(b),
                         cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), int(threads),
                         int(bool(brute)))
+    return st, c, b, cnt
+
+
+def acf_regular(t, x, lags, dt, kernel, h, err=None, threads=0):
+    """FP64 ACF in the lattice reading (times at t[0] + m dt). Returns (status, c, b, count)."""
+    lib = _load()
+    t, x, err, lags = _f64(t), _f64(x), _f64(err), _f64(lags)
+    K = lags.size
+    c = np.zeros(K)
+    b = np.zeros(K)
+    cnt = np.zeros(K, dtype=np.int64)
+    st = lib.oracle_acf_regular(t.size, _dp(t), _dp(x), _dp(err), float(dt), K, _dp(lags),
+                                kernel_id(kernel), float(h), _dp(c), _dp(b),
+                                cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), int(threads))
+    return st, c, b, cnt
+
+
+def ccf_regular(t, x, s, y, lags, dt, kernel, h, ex=None, ey=None, threads=0):
+    """FP64 CCF in the lattice reading (both series on min(t[0], s[0]) + m dt)."""
+    lib = _load()
+    t, x, s, y, ex, ey, lags = (_f64(a) for a in (t, x, s, y, ex, ey, lags))
+    K = lags.size
+    c = np.zeros(K)
+    b = np.zeros(K)
+    cnt = np.zeros(K, dtype=np.int64)
+    st = lib.oracle_ccf_regular(t.size, _dp(t), _dp(x), _dp(ex), s.size, _dp(s), _dp(y),
+                                _dp(ey), float(dt), K, _dp(lags), kernel_id(kernel), float(h),
+                                _dp(c), _dp(b), cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                int(threads))
     return st, c, b, cnt
 
 

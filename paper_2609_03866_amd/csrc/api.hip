@@ -297,6 +297,9 @@ struct Job {
     std::vector<std::function<int(hipStream_t)>>* rec = nullptr;
     bool plan_build = false;   // statuses are those of the host checks only
     Tune tune;
+    // regular-lattice estimators: lattice step per problem
+    bool regular = false;
+    std::vector<double> dt;
     // filled by run_job: what the call planned
     int64_t info_grid_cells = 0, info_window_items = 0;
     int info_grids = 0, info_window_launches = 0;
@@ -394,6 +397,316 @@ int plan_grid(const Job& J, double tmin, double tmax, double maxlag, double h, S
     return NCF_E_UNSUPPORTED;
 }
 
+// Per-problem statuses of a finished call (h_fstat: device statuses read
+// back); the call returns the first failure.
+int finish_status(Job& J, const std::vector<int>& pstat, const int32_t* h_fstat) {
+    if (J.plan_build) {  // placeholder values: only the host checks count
+        if (J.status)
+            for (int64_t p = 0; p < J.nprob; ++p) J.status[p] = pstat[p];
+        return NCF_OK;
+    }
+    int first = NCF_OK;
+    for (int64_t p = 0; p < J.nprob; ++p) {
+        if (J.status) J.status[p] = h_fstat[p];
+        if (h_fstat[p] != NCF_OK && first == NCF_OK) first = h_fstat[p];
+    }
+    if (first != NCF_OK) {
+        static const char* names[] = {"ok", "invalid argument", "unsorted times",
+                                      "degenerate series", "out of memory", "device error",
+                                      "unsupported"};
+        int idx = -first;
+        set_error("series failed: %s", (idx >= 0 && idx <= 6) ? names[idx] : "error");
+    }
+    return first;
+}
+
+// ------------------------------------------------------------ regular lattice
+
+// The classic-FFT route for series on a common time lattice (after the
+// moments and the standardization of run_job): lattice grids, FP64
+// transforms, correlation products, inverse transforms and the lag filter.
+int run_regular(Job& J, const std::vector<SeriesDesc>& sdesc,
+                const std::vector<SeriesStat>& stats, std::vector<int>& pstat,
+                const SeriesStat* d_stats) {
+    const int64_t K = J.K;
+    const bool rect = J.kern == NCF_RECTANGLE;
+    const int nsets = J.ccf ? 2 : 1;
+    bool weighted = false;
+    for (int si = 0; si < nsets; ++si) weighted |= (J.set[si].err != nullptr);
+    const int mode = (J.ccf ? 2 : 0) + (weighted ? 1 : 0);
+    const int ng = reg_in_grids(mode), no = reg_out_grids(mode), ngr = reg_grids(mode);
+    double maxlag = 0.0;
+    for (double v : J.lags) maxlag = std::max(maxlag, std::fabs(v));
+    auto stat_of = [&](int si, int64_t s) -> const SeriesStat& {
+        return stats[J.set[si].sd0 + s];
+    };
+
+    // lattice geometry of every problem that passed the host checks
+    struct RegPlan {
+        int64_t prob;
+        double t_ref;
+        int64_t G, Q, N;
+    };
+    std::vector<RegPlan> rps;
+    for (int64_t p = 0; p < J.nprob; ++p) {
+        if (pstat[p] != NCF_OK) continue;
+        const double dt = J.dt[p];
+        if (!(dt > 0.0) || !std::isfinite(dt)) {
+            pstat[p] = NCF_E_INVALID_ARG;
+            continue;
+        }
+        double t0 = stat_of(0, p).tmin, t1 = stat_of(0, p).tmax;
+        if (J.ccf) {
+            t0 = std::min(t0, stat_of(1, p).tmin);
+            t1 = std::max(t1, stat_of(1, p).tmax);
+        }
+        const double W = rect ? J.h[p] : 6.0 * J.h[p];
+        const double cells = std::rint((t1 - t0) / dt) + 1.0;
+        const double qreach = std::ceil((maxlag + W) / dt) + 2.0;
+        if (!(cells < 2147483648.0)) {
+            pstat[p] = NCF_E_UNSUPPORTED;  // lattice longer than the largest transform
+            continue;
+        }
+        RegPlan rp;
+        rp.prob = p;
+        rp.t_ref = t0;
+        rp.G = (int64_t)cells;
+        rp.Q = (int64_t)std::min((double)(rp.G - 1), qreach);
+        rp.N = std::max<int64_t>(4096, pow2_at_least((double)(rp.G + rp.Q)));
+        if (rp.N > (1LL << 31)) {
+            pstat[p] = NCF_E_UNSUPPORTED;
+            continue;
+        }
+        rps.push_back(rp);
+    }
+    std::stable_sort(rps.begin(), rps.end(),
+                     [](const RegPlan& a, const RegPlan& b) { return a.N < b.N; });
+    const int nreg = (int)rps.size();
+    J.info_grids = nreg;
+    J.info_grid_cells = 0;
+    for (auto& rp : rps) J.info_grid_cells += rp.N;
+    J.info_window_items = 0;
+    J.info_window_launches = 0;
+
+    // device workspace: grids, lattice flags, outputs (host mode)
+    Resources& R = *J.res;
+    std::vector<double*> grids(nreg);
+    int32_t* d_bad = nullptr;
+    double *d_c = nullptr, *d_b = nullptr;
+    int64_t* d_cnt = nullptr;
+    auto layout = [&](Arena& ar) {
+        for (int i = 0; i < nreg; ++i) grids[i] = ar.take<double>(2 * (size_t)rps[i].N * ngr);
+        d_bad = ar.take<int32_t>(std::max(nreg, 1));
+        if (J.dev_ptrs) {
+            d_c = J.c;
+            d_b = J.b;
+            d_cnt = J.count;
+        } else {
+            d_c = ar.take<double>(std::max<int64_t>(J.nprob * K, 1));
+            d_b = ar.take<double>(std::max<int64_t>(J.nprob * K, 1));
+            d_cnt = J.count ? ar.take<int64_t>(std::max<int64_t>(J.nprob * K, 1)) : nullptr;
+        }
+    };
+    Arena a2;
+    layout(a2);
+    void* ws2 = nullptr;
+    NCF_TRY(ensure_ws(R, 1, a2.off + 256, &ws2));
+    a2 = Arena{(char*)ws2, 0};
+    layout(a2);
+
+    // transform plans and size groups
+    std::map<int64_t, FftPlan> plans;
+    std::vector<std::pair<int, int>> groups;  // first task, tasks
+    for (int i = 0; i < nreg; ++i) {
+        if (!plans.count(rps[i].N)) {
+            FftPlan fp;
+            NCF_TRY(fft_plan(rps[i].N, true, &fp, J.st));
+            plans[rps[i].N] = fp;
+        }
+        if (i == 0 || rps[i].N != rps[i - 1].N)
+            groups.push_back({i, 1});
+        else
+            groups.back().second++;
+    }
+
+    // tables: tasks (lattice problems first, then the failed ones), prefix
+    // arrays, lags, grid pointers, outputs block, statuses
+    const int ntask = (int)J.nprob;
+    struct TT {
+        RegTask* task;
+        int64_t *blk0, *pos0;
+        double* lags;
+        void** gfwd;
+        void** ginv;
+        IoBlock* io;
+        int32_t* status;
+    } dU{}, hU{};
+    auto take = [&](Tables& tb) {
+        dU.task = tb.take<RegTask>(ntask, &hU.task);
+        dU.blk0 = tb.take<int64_t>(nreg + 1, &hU.blk0);
+        dU.pos0 = tb.take<int64_t>(nreg + 1, &hU.pos0);
+        dU.lags = tb.take<double>(std::max<int64_t>(K, 1), &hU.lags);
+        dU.gfwd = tb.take<void*>((size_t)nreg * ng, &hU.gfwd);
+        dU.ginv = tb.take<void*>((size_t)nreg * no, &hU.ginv);
+        dU.io = tb.take<IoBlock>(1, &hU.io);
+        dU.status = tb.take<int32_t>(J.nprob, &hU.status);
+    };
+    Tables tb;
+    take(tb);
+    Staging* stg = nullptr;
+    NCF_TRY(ensure_stage(R, 1, tb.off, &stg));
+    tb = Tables{stg->h, stg->d, 0};
+    take(tb);
+    int64_t nblocks = 0, total_pos = 0, nsamp = 0;
+    double cells_all = 0.0;
+    std::vector<bool> has_task(J.nprob, false);
+    for (int i = 0; i < nreg; ++i) {
+        const RegPlan& rp = rps[i];
+        const int64_t p = rp.prob;
+        has_task[p] = true;
+        RegTask T{};
+        for (int si = 0; si < nsets; ++si) {
+            const SeriesDesc& d = sdesc[J.set[si].sd0 + p];
+            T.t[si] = d.t;
+            T.v[si] = d.v64;
+            T.w[si] = d.w64;
+            T.n[si] = d.n;
+            nsamp += d.n;
+        }
+        T.t_ref = rp.t_ref;
+        T.dt = J.dt[p];
+        T.tol = 1e-6 * J.dt[p];
+        T.h = J.h[p];
+        T.G = rp.G;
+        T.N = rp.N;
+        T.Q = rp.Q;
+        T.grids = grids[i];
+        T.bad = d_bad + i;
+        T.blk0 = nblocks;
+        T.pos0 = total_pos;
+        const FftPlan& fp = plans[rp.N];
+        T.ri.npass = fp.npass;
+        for (int q = 0; q < 4; ++q) {
+            int lg = 0;
+            if (q < fp.npass)
+                while ((1 << lg) < fp.radix[q]) ++lg;
+            T.ri.lg[q] = lg;
+        }
+        int lgN = 0;
+        while ((1LL << lgN) < rp.N) ++lgN;
+        T.ri.lgN = lgN;
+        T.st0 = d_stats + J.set[0].sd0 + p;
+        T.st1 = J.ccf ? d_stats + J.set[1].sd0 + p : nullptr;
+        T.out_off = p * K;
+        T.index = p;
+        hU.task[i] = T;
+        hU.blk0[i] = nblocks;
+        hU.pos0[i] = total_pos;
+        nblocks += rp.N / kRegCells;
+        total_pos += rp.N;
+        cells_all += (double)rp.N;
+    }
+    hU.blk0[nreg] = nblocks;
+    hU.pos0[nreg] = total_pos;
+    {
+        int o = nreg;
+        for (int64_t p = 0; p < J.nprob; ++p) {
+            hU.status[p] = pstat[p];
+            if (has_task[p]) continue;
+            RegTask T{};
+            T.skip = 1;
+            T.skip_status = pstat[p];
+            T.out_off = p * K;
+            T.index = p;
+            hU.task[o++] = T;
+        }
+    }
+    for (int64_t k = 0; k < K; ++k) hU.lags[k] = J.lags[k];
+    {
+        int of = 0, oi = 0;
+        for (auto& gq : groups)
+            for (int i = gq.first; i < gq.first + gq.second; ++i) {
+                for (int g = 0; g < ng; ++g)
+                    hU.gfwd[of + (i - gq.first) + (int64_t)g * gq.second] =
+                        grids[i] + 2 * (size_t)rps[i].N * g;
+                for (int g = 0; g < no; ++g)
+                    hU.ginv[oi + (i - gq.first) + (int64_t)g * gq.second] =
+                        grids[i] + 2 * (size_t)rps[i].N * g;
+                if (i == gq.first + gq.second - 1) {
+                    of += ng * gq.second;
+                    oi += no * gq.second;
+                }
+            }
+    }
+    *hU.io = IoBlock{};
+    hU.io->x[0] = J.set[0].x;
+    hU.io->x[1] = J.ccf ? J.set[1].x : nullptr;
+    hU.io->c = d_c;
+    hU.io->b = d_b;
+    hU.io->count = d_cnt;
+    hU.io->status = dU.status;
+    NCF_TRY_HIP(hipMemcpyAsync(stg->d, stg->h, tb.off, hipMemcpyHostToDevice, J.st));
+
+    // launches
+    const RegTask* tasks = dU.task;
+    const int64_t* blk0 = dU.blk0;
+    const int64_t* pos0 = dU.pos0;
+    const double fill_bytes =
+        (double)nsamp * (weighted ? 24.0 : 16.0) + cells_all * 16.0 * ng;
+    const double prod_bytes = cells_all * 16.0 * (ng + no);
+    if (nreg > 0) {
+        NCF_TRY(emit(J, [=](hipStream_t s) { return launch_reg_clear(tasks, nreg, s); }));
+        NCF_TRY(emit(J, [=](hipStream_t s) {
+            return launch_reg_fill(tasks, blk0, nreg, nblocks, mode, s, fill_bytes);
+        }));
+        int of = 0;
+        for (auto& gq : groups) {
+            const FftPlan fp = plans[rps[gq.first].N];
+            void* const* gp = dU.gfwd + of;
+            const int cnt = ng * gq.second;
+            NCF_TRY(emit(J, [=](hipStream_t s) { return fft_exec(fp, gp, cnt, +1, true, s); }));
+            of += cnt;
+        }
+        NCF_TRY(emit(J, [=](hipStream_t s) {
+            return launch_reg_product(tasks, pos0, nreg, total_pos, mode, s, prod_bytes);
+        }));
+        int oi = 0;
+        for (auto& gq : groups) {
+            const FftPlan fp = plans[rps[gq.first].N];
+            void* const* gp = dU.ginv + oi;
+            const int cnt = no * gq.second;
+            NCF_TRY(emit(J, [=](hipStream_t s) { return fft_exec(fp, gp, cnt, -1, true, s); }));
+            oi += cnt;
+        }
+    }
+    {
+        const double* lg = dU.lags;
+        const IoBlock* io = J.io_fixed ? J.io_fixed : dU.io;
+        const int kern = J.kern;
+        NCF_TRY(emit(J, [=](hipStream_t s) {
+            return launch_reg_finish(tasks, ntask, lg, K, mode, kern, io, s);
+        }));
+    }
+    int32_t* h_fstat = hU.status;
+    NCF_TRY_HIP(hipMemcpyAsync(h_fstat, J.io_fixed ? J.io_status : dU.status,
+                               sizeof(int32_t) * J.nprob, hipMemcpyDeviceToHost, J.st));
+    if (!J.dev_ptrs && K > 0) {
+        NCF_TRY_HIP(hipMemcpyAsync(J.c, d_c, sizeof(double) * J.nprob * K, hipMemcpyDeviceToHost,
+                                   J.st));
+        NCF_TRY_HIP(hipMemcpyAsync(J.b, d_b, sizeof(double) * J.nprob * K, hipMemcpyDeviceToHost,
+                                   J.st));
+        if (J.count)
+            NCF_TRY_HIP(hipMemcpyAsync(J.count, d_cnt, sizeof(int64_t) * J.nprob * K,
+                                       hipMemcpyDeviceToHost, J.st));
+    }
+    NCF_TRY_HIP(hipStreamSynchronize(J.st));
+    if (g_prof_on) {
+        std::lock_guard<std::mutex> lock(g_prof_mu);
+        prof_flush_locked();
+    }
+    return finish_status(J, pstat, h_fstat);
+}
+
 int run_job(Job& J, const double* const* tin, const double* const* xin,
             const double* const* ein) {
     const bool fp64 = J.opt.precision == NCF_FP64;
@@ -407,7 +720,9 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     // FP64 values: FP64 spreading, and every Gaussian window pass (its direct
     // numerator backs up the spectral one at lags with few pairs)
     const bool need_v64 = (spectral && fp64) || numer_in_window || !rect;
-    const bool need_prefix = rect && numer_in_window;
+    const bool need_prefix = rect && numer_in_window && !J.regular;
+    const bool v32_needed = need_v32 && !J.regular;
+    const bool v64_needed = need_v64 || J.regular;
 
     // ------------------------------------------------ phase 1: A1 moments
     // chunks of every series of every set, one launch for all of them
@@ -446,8 +761,8 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
                 S.x = ar.take<double>(S.ntot);
                 S.err = ein[si] ? ar.take<double>(S.ntot) : nullptr;
             }
-            S.v32 = need_v32 ? ar.take<float>(S.ntot) : nullptr;
-            S.v64 = need_v64 ? ar.take<double>(S.ntot) : nullptr;
+            S.v32 = v32_needed ? ar.take<float>(S.ntot) : nullptr;
+            S.v64 = v64_needed ? ar.take<double>(S.ntot) : nullptr;
             S.w64 = ein[si] ? ar.take<double>(S.ntot) : nullptr;
             S.pv = need_prefix ? ar.take<double>(S.ntot + S.nser) : nullptr;
             S.pw = (need_prefix && ein[si]) ? ar.take<double>(S.ntot + S.nser) : nullptr;
@@ -563,6 +878,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
 
     // standardization (+ prefix sums), all series in one launch
     NCF_TRY(emit(J, [ma](hipStream_t s) { return launch_standardize(ma, s); }));
+    if (J.regular) return run_regular(J, sdesc, stats, pstat, d_stats);
 
     // ------------------------------------------------ phase 2 planning (host)
     const int64_t K = J.K;
@@ -1251,24 +1567,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         std::lock_guard<std::mutex> lock(g_prof_mu);
         prof_flush_locked();
     }
-    if (J.plan_build) {  // placeholder values: only the host checks count
-        if (J.status)
-            for (int64_t p = 0; p < J.nprob; ++p) J.status[p] = pstat[p];
-        return NCF_OK;
-    }
-    int first = NCF_OK;
-    for (int64_t p = 0; p < J.nprob; ++p) {
-        if (J.status) J.status[p] = h_fstat[p];
-        if (h_fstat[p] != NCF_OK && first == NCF_OK) first = h_fstat[p];
-    }
-    if (first != NCF_OK) {
-        static const char* names[] = {"ok", "invalid argument", "unsorted times",
-                                      "degenerate series", "out of memory", "device error",
-                                      "unsupported"};
-        int idx = -first;
-        set_error("series failed: %s", (idx >= 0 && idx <= 6) ? names[idx] : "error");
-    }
-    return first;
+    return finish_status(J, pstat, h_fstat);
 }
 
 // ---------------------------------------------------------- entry helpers
@@ -1407,15 +1706,18 @@ Resources* device_resources() {
 }  // namespace
 }  // namespace ncf
 
-extern "C" {
+namespace ncf {
+namespace {
 
-int ncf_acf_batch(int64_t nser, const int64_t* offs, const double* t, const double* x,
-                  const double* err, int64_t K, const double* lags, int kern, const double* h,
-                  double* c, double* b, int64_t* count, int* status, const ncf_options_t* opt) {
+// ACF and CCF batches; dt (per problem) selects the regular-lattice route.
+int acf_batch_impl(int64_t nser, const int64_t* offs, const double* t, const double* x,
+                   const double* err, const double* dt, bool regular, int64_t K,
+                   const double* lags, int kern, const double* h, double* c, double* b,
+                   int64_t* count, int* status, const ncf_options_t* opt) {
     clear_error();
     Job J;
     NCF_TRY(common_checks(opt, &J.opt, kern));
-    if (nser <= 0 || !t || !x || !h || (K > 0 && (!c || !b))) {
+    if (nser <= 0 || !t || !x || !h || (regular && !dt) || (K > 0 && (!c || !b))) {
         set_error("null argument or nser <= 0");
         return NCF_E_INVALID_ARG;
     }
@@ -1426,6 +1728,8 @@ int ncf_acf_batch(int64_t nser, const int64_t* offs, const double* t, const doub
     J.b = b;
     J.count = count;
     J.status = status;
+    J.regular = regular;
+    if (regular) J.dt.assign(dt, dt + nser);
     NCF_TRY(setup_job(J, false, nser, offs, nullptr, total, 0, kern, h, K, lags));
     J.res = device_resources();
     if (!J.res) {
@@ -1438,14 +1742,16 @@ int ncf_acf_batch(int64_t nser, const int64_t* offs, const double* t, const doub
     return run_job(J, tin, xin, ein);
 }
 
-int ncf_ccf_batch(int64_t npair, const int64_t* offx, const double* tx, const double* x,
-                  const double* ex, const int64_t* offy, const double* ty, const double* y,
-                  const double* ey, int64_t K, const double* lags, int kern, const double* h,
-                  double* c, double* b, int64_t* count, int* status, const ncf_options_t* opt) {
+int ccf_batch_impl(int64_t npair, const int64_t* offx, const double* tx, const double* x,
+                   const double* ex, const int64_t* offy, const double* ty, const double* y,
+                   const double* ey, const double* dt, bool regular, int64_t K,
+                   const double* lags, int kern, const double* h, double* c, double* b,
+                   int64_t* count, int* status, const ncf_options_t* opt) {
     clear_error();
     Job J;
     NCF_TRY(common_checks(opt, &J.opt, kern));
-    if (npair <= 0 || !tx || !x || !ty || !y || !h || (K > 0 && (!c || !b))) {
+    if (npair <= 0 || !tx || !x || !ty || !y || !h || (regular && !dt) ||
+        (K > 0 && (!c || !b))) {
         set_error("null argument or npair <= 0");
         return NCF_E_INVALID_ARG;
     }
@@ -1457,6 +1763,8 @@ int ncf_ccf_batch(int64_t npair, const int64_t* offx, const double* tx, const do
     J.b = b;
     J.count = count;
     J.status = status;
+    J.regular = regular;
+    if (regular) J.dt.assign(dt, dt + npair);
     NCF_TRY(setup_job(J, true, npair, offx, offy, totx, toty, kern, h, K, lags));
     J.res = device_resources();
     if (!J.res) {
@@ -1467,6 +1775,68 @@ int ncf_ccf_batch(int64_t npair, const int64_t* offx, const double* tx, const do
     const double* xin[2] = {x, y};
     const double* ein[2] = {ex, ey};
     return run_job(J, tin, xin, ein);
+}
+
+}  // namespace
+}  // namespace ncf
+
+extern "C" {
+
+int ncf_acf_batch(int64_t nser, const int64_t* offs, const double* t, const double* x,
+                  const double* err, int64_t K, const double* lags, int kern, const double* h,
+                  double* c, double* b, int64_t* count, int* status, const ncf_options_t* opt) {
+    return acf_batch_impl(nser, offs, t, x, err, nullptr, false, K, lags, kern, h, c, b, count,
+                          status, opt);
+}
+
+int ncf_ccf_batch(int64_t npair, const int64_t* offx, const double* tx, const double* x,
+                  const double* ex, const int64_t* offy, const double* ty, const double* y,
+                  const double* ey, int64_t K, const double* lags, int kern, const double* h,
+                  double* c, double* b, int64_t* count, int* status, const ncf_options_t* opt) {
+    return ccf_batch_impl(npair, offx, tx, x, ex, offy, ty, y, ey, nullptr, false, K, lags, kern,
+                          h, c, b, count, status, opt);
+}
+
+int ncf_acf_regular_batch(int64_t nser, const int64_t* offs, const double* t, const double* x,
+                          const double* err, const double* dt, int64_t K, const double* lags,
+                          int kern, const double* h, double* c, double* b, int64_t* count,
+                          int* status, const ncf_options_t* opt) {
+    return acf_batch_impl(nser, offs, t, x, err, dt, true, K, lags, kern, h, c, b, count, status,
+                          opt);
+}
+
+int ncf_ccf_regular_batch(int64_t npair, const int64_t* offx, const double* tx, const double* x,
+                          const double* ex, const int64_t* offy, const double* ty,
+                          const double* y, const double* ey, const double* dt, int64_t K,
+                          const double* lags, int kern, const double* h, double* c, double* b,
+                          int64_t* count, int* status, const ncf_options_t* opt) {
+    return ccf_batch_impl(npair, offx, tx, x, ex, offy, ty, y, ey, dt, true, K, lags, kern, h, c,
+                          b, count, status, opt);
+}
+
+int ncf_acf_regular(int64_t n, const double* t, const double* x, const double* err, double dt,
+                    int64_t K, const double* lags, int kern, double h, double* c, double* b,
+                    int64_t* count, const ncf_options_t* opt) {
+    if (n < 2) {
+        set_error("n must be >= 2");
+        return NCF_E_INVALID_ARG;
+    }
+    int64_t offs[2] = {0, n};
+    return ncf_acf_regular_batch(1, offs, t, x, err, &dt, K, lags, kern, &h, c, b, count,
+                                 nullptr, opt);
+}
+
+int ncf_ccf_regular(int64_t nx, const double* tx, const double* x, const double* ex, int64_t ny,
+                    const double* ty, const double* y, const double* ey, double dt, int64_t K,
+                    const double* lags, int kern, double h, double* c, double* b,
+                    int64_t* count, const ncf_options_t* opt) {
+    if (nx < 2 || ny < 2) {
+        set_error("nx and ny must be >= 2");
+        return NCF_E_INVALID_ARG;
+    }
+    int64_t ox[2] = {0, nx}, oy[2] = {0, ny};
+    return ncf_ccf_regular_batch(1, ox, tx, x, ex, oy, ty, y, ey, &dt, K, lags, kern, &h, c, b,
+                                 count, nullptr, opt);
 }
 
 int ncf_acf(int64_t n, const double* t, const double* x, const double* err, int64_t K,

@@ -97,6 +97,41 @@ __device__ __forceinline__ int64_t wave_search(const T* a_, int64_t n, T key, bo
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// ------------------------------------------- digit-reversed positions
+// Radices of a transform plan (first pass first): the forward transform
+// leaves frequency k at position p with p = sum_i d_i 2^(lgN - B_i) where
+// k = sum_i d_i 2^(B_{i-1}) and B_i is the bit count of the first i radices.
+struct RadixInfo {
+    int npass;
+    int lg[4];  // log2 radix of each pass (first pass first)
+    int lgN;
+};
+
+__device__ __forceinline__ int64_t freq_of_pos(int64_t p, const RadixInfo& ri) {
+    // p = sum_i d_i * 2^(lgN - B_i), k = sum_i d_i * 2^(B_{i-1})
+    int64_t k = 0;
+    int B = 0;
+    for (int i = 0; i < ri.npass; ++i) {
+        const int lg = ri.lg[i];
+        const int64_t d = (p >> (ri.lgN - B - lg)) & ((1LL << lg) - 1);
+        k |= d << B;
+        B += lg;
+    }
+    return k;
+}
+
+__device__ __forceinline__ int64_t pos_of_freq(int64_t k, const RadixInfo& ri) {
+    int64_t p = 0;
+    int B = 0;
+    for (int i = 0; i < ri.npass; ++i) {
+        const int lg = ri.lg[i];
+        const int64_t d = (k >> B) & ((1LL << lg) - 1);
+        p |= d << (ri.lgN - B - lg);
+        B += lg;
+    }
+    return p;
+}
+
 // ------------------------------------------------------------- call I/O
 // The caller's value arrays and output arrays of one call. Kernels reach
 // them through this device block, so a recorded launch sequence (a plan) can
@@ -296,6 +331,66 @@ int64_t fft_position(const FftPlan& plan, int64_t k);
 int launch_product(const SpecTask* d_tasks, const int64_t* d_pos0, int ntasks, int64_t total,
                    const int64_t* d_radix_info, bool ccf, bool with_b, bool fp64, hipStream_t st,
                    double bytes);
+
+// ------------------------------------------- regular-lattice estimators
+// Series whose times sit on a common lattice t_ref + m dt: the pair lags are
+// whole multiples of dt, so the raw lag correlations R(q) = sum_c a_c b_(c+q)
+// of the lattice grids (values, weights, sample counts) come from one
+// zero-padded FFT correlation, and every lag tau is a filter over q.
+//
+// Channel modes (all tasks of a launch share one):
+//   0 ACF       grids (v, n)               outputs (R_vv, R_nn)
+//   1 ACF + w   grids (v, w), (n, 0)       outputs (R_vv, R_ww), (R_nn, 0)
+//   2 CCF       grids (vx, vy), (nx, ny)   outputs (R_xy, N_xy), (R_xx, R_yy), (N_xx, N_yy)
+//   3 CCF + w   grids (vx, vy), (wx, wy), (nx, ny)
+//               outputs (R_xy, W_xy), (N_xy, 0), (R_xx, R_yy), (W_xx, W_yy)
+// with v = w (x - mean)/sd, w the sample weights and n the sample counts per
+// lattice cell. Input grids are transformed in place and the products
+// overwrite them (the extra output grids follow the inputs).
+constexpr int kRegCells = 1024;  // lattice cells per fill workgroup
+__host__ __device__ constexpr int reg_in_grids(int mode) { return mode == 3 ? 3 : mode == 0 ? 1 : 2; }
+__host__ __device__ constexpr int reg_out_grids(int mode) { return mode == 0 ? 1 : mode == 1 ? 2 : mode == 2 ? 3 : 4; }
+__host__ __device__ constexpr int reg_grids(int mode) {
+    return reg_in_grids(mode) > reg_out_grids(mode) ? reg_in_grids(mode) : reg_out_grids(mode);
+}
+
+struct RegTask {
+    const double* t[2];   // times of series 1 and (CCF) series 2
+    const double* v[2];   // FP64 standardized weighted values
+    const double* w[2];   // FP64 weights, or null (unit weights)
+    int64_t n[2];
+    double t_ref;         // lattice origin (first time of either series)
+    double dt;            // lattice step
+    double tol;           // accepted distance of a time from its lattice point
+    double h;             // lag-kernel bandwidth
+    int64_t G;            // lattice cells from t_ref to the last time
+    int64_t N;            // transform length (power of two >= G + Q)
+    int64_t Q;            // largest |q| any requested window reaches (<= G - 1)
+    double* grids;        // reg_grids(mode) grids of N complex128 values
+    int32_t* bad;         // set to 1 when a time is off the lattice
+    int64_t blk0;         // first fill workgroup of this task
+    int64_t pos0;         // first position of this task in the product launch
+    RadixInfo ri;         // transform radices (digit-reversed positions)
+    // normalization
+    const SeriesStat* st0;
+    const SeriesStat* st1;
+    int32_t skip;         // failed the host checks: outputs NaN / 0 / 0
+    int32_t skip_status;
+    int64_t out_off;      // first output of this problem in IoBlock::c, b, count
+    int64_t index;        // problem index (IoBlock::status)
+};
+// Zero the lattice flags of `n` tasks.
+int launch_reg_clear(const RegTask* d_tasks, int ntasks, hipStream_t st);
+// Lattice grids of every task (natural order, zero-padded to N cells).
+int launch_reg_fill(const RegTask* d_tasks, const int64_t* d_blk0, int ntasks, int64_t nblocks,
+                    int mode, hipStream_t st, double bytes);
+// Correlation spectra from the forward-transformed grids (digit-reversed
+// order, in place), scaled by 1/N for the inverse transform.
+int launch_reg_product(const RegTask* d_tasks, const int64_t* d_pos0, int ntasks, int64_t total,
+                       int mode, hipStream_t st, double bytes);
+// Lag filter, normalization and outputs (request order) of every task.
+int launch_reg_finish(const RegTask* d_tasks, int ntasks, const double* d_lags, int64_t K,
+                      int mode, int kern, const IoBlock* io, hipStream_t st);
 
 // ------------------------------------------------------------ A8 output
 struct NormTask {

@@ -329,37 +329,6 @@ k_spread(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ tile0, 
 
 // ---------------------------------------------------------------- product
 
-struct RadixInfo {
-    int npass;
-    int lg[4];  // log2 radix of each pass (first pass first)
-    int lgN;
-};
-
-__device__ __forceinline__ int64_t freq_of_pos(int64_t p, const RadixInfo& ri) {
-    // p = sum_i d_i * 2^(lgN - B_i), k = sum_i d_i * 2^(B_{i-1})
-    int64_t k = 0;
-    int B = 0;
-    for (int i = 0; i < ri.npass; ++i) {
-        const int lg = ri.lg[i];
-        const int64_t d = (p >> (ri.lgN - B - lg)) & ((1LL << lg) - 1);
-        k |= d << B;
-        B += lg;
-    }
-    return k;
-}
-
-__device__ __forceinline__ int64_t pos_of_freq(int64_t k, const RadixInfo& ri) {
-    int64_t p = 0;
-    int B = 0;
-    for (int i = 0; i < ri.npass; ++i) {
-        const int lg = ri.lg[i];
-        const int64_t d = (k >> B) & ((1LL << lg) - 1);
-        p |= d << (ri.lgN - B - lg);
-        B += lg;
-    }
-    return p;
-}
-
 // exp(x) to ~1 FP32 ulp for any x in range: x log2(e) is split in FP64 into
 // an integer part (applied exactly) and a fraction in [0, 1) for exp2.
 __device__ __forceinline__ double exp_split(double x) {

@@ -83,6 +83,14 @@ def lib():
                                     _P, _P]
         L.ncf_ccf_batch.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _I64, _P,
                                     ctypes.c_int, _P, _P, _P, _P, _P, _P]
+        L.ncf_acf_regular.argtypes = [_I64, _P, _P, _P, ctypes.c_double, _I64, _P, ctypes.c_int,
+                                      ctypes.c_double, _P, _P, _P, _P]
+        L.ncf_ccf_regular.argtypes = [_I64, _P, _P, _P, _I64, _P, _P, _P, ctypes.c_double, _I64,
+                                      _P, ctypes.c_int, ctypes.c_double, _P, _P, _P, _P]
+        L.ncf_acf_regular_batch.argtypes = [_I64, _P, _P, _P, _P, _P, _I64, _P, ctypes.c_int,
+                                            _P, _P, _P, _P, _P, _P]
+        L.ncf_ccf_regular_batch.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _I64, _P,
+                                            ctypes.c_int, _P, _P, _P, _P, _P, _P]
         L.ncf_last_error.restype = ctypes.c_char_p
         L.ncf_options_init.argtypes = [_P]
         L.ncf_diag_fft.argtypes = [_I64, ctypes.c_int, ctypes.c_int, _P]
@@ -253,6 +261,98 @@ def ccf_batch(offx, t, x, offy, s, y, lags, kernel="gaussian", h=1.0, ex=None, e
                              offy.ctypes.data, m.inp(s), m.inp(y), m.inp(ey), K, m.inp(lags),
                              _kern(kernel), hs.ctypes.data, pc, pb, pn, st.ctypes.data,
                              ctypes.byref(o))
+    if raise_on_error:
+        _check(rc)
+    rs = (lambda a: a.reshape(npair, K) if a is not None else None)
+    return rs(c), rs(b), rs(cnt), st, rc
+
+
+# ------------------------------------------------- regular-lattice family
+
+def acf_regular(t, x, lags, dt, kernel="gaussian", h=1.0, err=None, with_count=True,
+                raise_on_error=True, stream=None):
+    """ncf_acf_regular: times on the lattice t_ref + m dt (classic-FFT route).
+    Returns (c, b, count, status); numpy or torch CUDA as in acf."""
+    dev = t.device if _is_torch(t) else None
+    m = _Marshal(dev)
+    K = int(lags.numel() if _is_torch(lags) else np.asarray(lags).size)
+    c, pc = m.out(K, np.float64)
+    b, pb = m.out(K, np.float64)
+    cnt, pn = m.out(K, np.int64) if with_count else (None, None)
+    n = int(t.numel() if _is_torch(t) else np.asarray(t).size)
+    o = _options("fp64", "auto", 0.0, 0.0, 0, dev, stream)
+    rc = lib().ncf_acf_regular(n, m.inp(t), m.inp(x), m.inp(err), float(dt), K, m.inp(lags),
+                               _kern(kernel), float(h), pc, pb, pn, ctypes.byref(o))
+    if raise_on_error:
+        _check(rc)
+    return c, b, cnt, rc
+
+
+def ccf_regular(t, x, s, y, lags, dt, kernel="gaussian", h=1.0, ex=None, ey=None,
+                with_count=True, raise_on_error=True, stream=None):
+    """ncf_ccf_regular: both series on one lattice (lag +tau: series 2 lags series 1)."""
+    dev = t.device if _is_torch(t) else None
+    m = _Marshal(dev)
+    K = int(lags.numel() if _is_torch(lags) else np.asarray(lags).size)
+    c, pc = m.out(K, np.float64)
+    b, pb = m.out(K, np.float64)
+    cnt, pn = m.out(K, np.int64) if with_count else (None, None)
+    nx = int(t.numel() if _is_torch(t) else np.asarray(t).size)
+    ny = int(s.numel() if _is_torch(s) else np.asarray(s).size)
+    o = _options("fp64", "auto", 0.0, 0.0, 0, dev, stream)
+    rc = lib().ncf_ccf_regular(nx, m.inp(t), m.inp(x), m.inp(ex), ny, m.inp(s), m.inp(y),
+                               m.inp(ey), float(dt), K, m.inp(lags), _kern(kernel), float(h),
+                               pc, pb, pn, ctypes.byref(o))
+    if raise_on_error:
+        _check(rc)
+    return c, b, cnt, rc
+
+
+def acf_regular_batch(offs, t, x, lags, dt, kernel="gaussian", h=1.0, err=None,
+                      with_count=True, raise_on_error=True, stream=None):
+    """ncf_acf_regular_batch over CSR series; dt and h scalars or one per series."""
+    offs = np.ascontiguousarray(offs, dtype=np.int64)
+    nser = offs.size - 1
+    hs = np.ascontiguousarray(np.broadcast_to(np.asarray(h, dtype=np.float64), (nser,)))
+    dts = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, dtype=np.float64), (nser,)))
+    dev = t.device if _is_torch(t) else None
+    m = _Marshal(dev)
+    K = int(lags.numel() if _is_torch(lags) else np.asarray(lags).size)
+    c, pc = m.out(nser * K, np.float64)
+    b, pb = m.out(nser * K, np.float64)
+    cnt, pn = m.out(nser * K, np.int64) if with_count else (None, None)
+    st = np.zeros(nser, dtype=np.int32)
+    o = _options("fp64", "auto", 0.0, 0.0, 0, dev, stream)
+    rc = lib().ncf_acf_regular_batch(nser, offs.ctypes.data, m.inp(t), m.inp(x), m.inp(err),
+                                     dts.ctypes.data, K, m.inp(lags), _kern(kernel),
+                                     hs.ctypes.data, pc, pb, pn, st.ctypes.data, ctypes.byref(o))
+    if raise_on_error:
+        _check(rc)
+    rs = (lambda a: a.reshape(nser, K) if a is not None else None)
+    return rs(c), rs(b), rs(cnt), st, rc
+
+
+def ccf_regular_batch(offx, t, x, offy, s, y, lags, dt, kernel="gaussian", h=1.0, ex=None,
+                      ey=None, with_count=True, raise_on_error=True, stream=None):
+    """ncf_ccf_regular_batch over CSR series pairs."""
+    offx = np.ascontiguousarray(offx, dtype=np.int64)
+    offy = np.ascontiguousarray(offy, dtype=np.int64)
+    npair = offx.size - 1
+    hs = np.ascontiguousarray(np.broadcast_to(np.asarray(h, dtype=np.float64), (npair,)))
+    dts = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, dtype=np.float64), (npair,)))
+    dev = t.device if _is_torch(t) else None
+    m = _Marshal(dev)
+    K = int(lags.numel() if _is_torch(lags) else np.asarray(lags).size)
+    c, pc = m.out(npair * K, np.float64)
+    b, pb = m.out(npair * K, np.float64)
+    cnt, pn = m.out(npair * K, np.int64) if with_count else (None, None)
+    st = np.zeros(npair, dtype=np.int32)
+    o = _options("fp64", "auto", 0.0, 0.0, 0, dev, stream)
+    rc = lib().ncf_ccf_regular_batch(npair, offx.ctypes.data, m.inp(t), m.inp(x), m.inp(ex),
+                                     offy.ctypes.data, m.inp(s), m.inp(y), m.inp(ey),
+                                     dts.ctypes.data, K, m.inp(lags), _kern(kernel),
+                                     hs.ctypes.data, pc, pb, pn, st.ctypes.data,
+                                     ctypes.byref(o))
     if raise_on_error:
         _check(rc)
     rs = (lambda a: a.reshape(npair, K) if a is not None else None)

@@ -31,6 +31,14 @@ Workloads (all seeded with numpy's PCG64):
   U[5, 100] d plus noise sd 0.05; 512 lags over [-300, 300] d, rectangle,
   h = 0.5 d.
 
+* ``r1`` -- regular-lattice ACF (the paper's benchmark on regularly sampled
+  data, Sec. "Regularly-sampled data"): white noise N(0, 1) on t = m dt,
+  dt = 1 d, n = 2.56e5 samples without gaps, integer lags 0..365 d
+  (K = 366), Gaussian and rectangle kernels with h = 0.5 d.
+* ``r2`` -- batched regular-lattice ACF: 4,096 series on 1-d lattices,
+  lengths log-uniform in [1e3, 1e5], 10 % of lattice points dropped, white
+  noise; lags 0..365 d, rectangle, h = 0.5 d.
+
 Scaled-down variants (``scale`` < 1) keep the sampling pattern and signal and
 shrink only the lengths / counts; tests use them at sizes the oracle finishes
 in seconds.
@@ -270,7 +278,45 @@ def c5(seed=5, n_pairs=2048, nmin=1000, nmax=200_000, K=512):
                 lags=lags, kernel="rectangle", h=np.full(n_pairs, 0.5), delays=delays)
 
 
-WORKLOADS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5}
+# --------------------------------------------------------- regular lattice
+
+def lattice_times(rng, n, dt=1.0, keep=1.0, t0=0.0, dup_frac=0.0):
+    """n times on the lattice t0 + m dt (m increasing from 0); each lattice
+    point kept with probability `keep`, and a fraction `dup_frac` of the
+    samples repeated at the previous sample's time."""
+    if keep >= 1.0:
+        m = np.arange(n, dtype=np.int64)
+    else:
+        gaps = rng.geometric(keep, size=n - 1)
+        m = np.concatenate([[0], np.cumsum(gaps)]).astype(np.int64)
+    if dup_frac > 0.0:
+        k = int(dup_frac * n)
+        idx = np.sort(rng.integers(1, n, size=k))
+        m[idx] = m[idx - 1]
+        m = np.sort(m)
+    return t0 + m * dt
+
+
+def r1(seed=11, n=256_000, kernel="gaussian", K=366):
+    rng = rng_for(seed)
+    t = lattice_times(rng, n, dt=1.0)
+    x = rng.normal(size=n)
+    return dict(t=t, x=x, dt=1.0, lags=np.arange(K, dtype=np.float64), kernel=kernel, h=0.5)
+
+
+def r2(seed=12, n_series=4096, nmin=1000, nmax=100_000, K=366, kernel="rectangle"):
+    rng = rng_for(seed)
+    ns = np.round(np.exp(rng.uniform(math.log(nmin), math.log(nmax), n_series))).astype(np.int64)
+    offs = np.concatenate([[0], np.cumsum(ns)])
+    t = np.empty(offs[-1])
+    for i in range(n_series):
+        t[offs[i]:offs[i + 1]] = lattice_times(rng, int(ns[i]), dt=1.0, keep=0.9)
+    x = rng.normal(size=offs[-1])
+    return dict(offs=offs, t=t, x=x, dt=np.ones(n_series), lags=np.arange(K, dtype=np.float64),
+                kernel=kernel, h=np.full(n_series, 0.5))
+
+
+WORKLOADS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5, "r1": r1, "r2": r2}
 
 
 def small(name, seed=0):
@@ -286,4 +332,8 @@ def small(name, seed=0):
         return c4(seed, n_series=24, nmin=100, nmax=3000, K=64)
     if name == "c5":
         return c5(seed, n_pairs=12, nmin=300, nmax=4000, K=96)
+    if name == "r1":
+        return r1(seed, n=20_000, K=366)
+    if name == "r2":
+        return r2(seed, n_series=16, nmin=200, nmax=6000, K=120)
     raise KeyError(name)

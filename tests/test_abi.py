@@ -26,7 +26,8 @@ def _declared():
 def test_headers_declare_entry_points():
     names = _declared()
     for required in ("ncf_acf", "ncf_ccf", "ncf_acf_batch", "ncf_ccf_batch", "ncf_last_error",
-                     "ncf_diag_fft", "ncf_diag_type1", "ncf_profile_read"):
+                     "ncf_diag_fft", "ncf_diag_type1", "ncf_profile_read", "ncf_acf_regular",
+                     "ncf_ccf_regular", "ncf_acf_regular_batch", "ncf_ccf_regular_batch"):
         assert required in names
 
 
@@ -74,6 +75,21 @@ def test_no_device_is_reported_not_crashed():
                             raise_on_error=False)
     assert rc == ncf.E_DEVICE
     assert b"no HIP device" in ncf.lib().ncf_last_error()
+
+
+def test_regular_entry_points_report_no_device():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("GPU present")
+    except Exception:
+        pass
+    t = np.arange(10.0)
+    rc = ncf.acf_regular(t, t % 3, np.arange(3.0), 1.0, "r", 0.5, raise_on_error=False)[3]
+    assert rc == ncf.E_DEVICE
+    rc = ncf.ccf_regular(t, t % 3, t, t % 2, np.arange(3.0), 1.0, "g", 0.5,
+                         raise_on_error=False)[3]
+    assert rc == ncf.E_DEVICE
 
 
 def test_plan_entry_points_declared_and_report_no_device():
