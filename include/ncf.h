@@ -261,6 +261,20 @@ int ncf_plan_ccf(int64_t npair, const int64_t* offx, const double* tx, const dou
                  const double* lags, int kern, const double* h, const ncf_options_t* opt,
                  ncf_plan_t** out);
 
+/* Plans of the regular-lattice estimators (arguments as in
+ * ncf_acf_regular_batch / ncf_ccf_regular_batch, without values and
+ * outputs; dt a HOST array of one lattice step per series or pair). The
+ * lattice check of the times is part of every execution: a series off its
+ * lattice reports NCF_E_INVALID_ARG in `status`. */
+int ncf_plan_acf_regular(int64_t nser, const int64_t* offs, const double* t, const double* err,
+                         const double* dt, int64_t K, const double* lags, int kern,
+                         const double* h, const ncf_options_t* opt, ncf_plan_t** out);
+
+int ncf_plan_ccf_regular(int64_t npair, const int64_t* offx, const double* tx, const double* ex,
+                         const int64_t* offy, const double* ty, const double* ey,
+                         const double* dt, int64_t K, const double* lags, int kern,
+                         const double* h, const ncf_options_t* opt, ncf_plan_t** out);
+
 /* Run a plan on values x (series 1, CSR as at build) and y (series 2 of a
  * CCF plan, NULL for an ACF plan); outputs as in the batch calls. */
 int ncf_plan_execute(ncf_plan_t* plan, const double* x, const double* y, double* c, double* b,
@@ -274,10 +288,10 @@ typedef struct {
     uint32_t struct_size;      /* sizeof(ncf_plan_info_t) */
     int32_t autotuned;         /* 1 if built with NCF_PLAN_AUTOTUNE */
     int32_t candidates;        /* settings timed by the autotuner */
-    int32_t spectral_grids;    /* spreading grids (spectral problems) */
+    int32_t spectral_grids;    /* spreading grids (spectral problems; regular plans: lattice problems) */
     int32_t window_launches;   /* window-scan launches per execution */
     int32_t graph;             /* 1 if executions replay a captured graph */
-    int64_t grid_cells;        /* cells over all grids */
+    int64_t grid_cells;        /* cells over all grids (transform length) */
     int64_t window_items;      /* window work items per execution */
     double sigma;              /* minimum grid oversampling chosen, 0 = default */
     int32_t fft_split;         /* 0 default radices, 1 swapped order, 2 three passes */

@@ -520,7 +520,7 @@ int run_regular(Job& J, const std::vector<SeriesDesc>& sdesc,
     for (int i = 0; i < nreg; ++i) {
         if (!plans.count(rps[i].N)) {
             FftPlan fp;
-            NCF_TRY(fft_plan(rps[i].N, true, &fp, J.st));
+            NCF_TRY(fft_plan(rps[i].N, true, &fp, J.st, J.tune.fft));
             plans[rps[i].N] = fp;
         }
         if (i == 0 || rps[i].N != rps[i - 1].N)
@@ -2114,20 +2114,22 @@ int plan_create(Job& J, const double* const* tin, const double* const* ein, ncf_
             return NCF_OK;
         };
         const bool fp64 = J.opt.precision == NCF_FP64;
-        if (best->grids > 0) {
+        if (best->grids > 0 && !J.regular) {
             for (double sg : {1.25, 2.0}) {
                 Tune t = best->tune;
                 t.sigma = sg;
                 rc = attempt(t);
                 if (rc != NCF_OK) break;
             }
+        }
+        if (best->grids > 0) {
             for (int sp : {1, 2}) {
                 if (rc != NCF_OK) break;
                 Tune t = best->tune;
                 t.fft.split = sp;
                 rc = attempt(t);
             }
-            if (rc == NCF_OK && !fp64) {
+            if (rc == NCF_OK && !fp64 && !J.regular) {
                 Tune t = best->tune;
                 t.fft.lgt_strided = 12;
                 rc = attempt(t);
@@ -2158,6 +2160,60 @@ int plan_create(Job& J, const double* const* tin, const double* const* ein, ncf_
     return NCF_OK;
 }
 
+int plan_acf_impl(int64_t nser, const int64_t* offs, const double* t, const double* err,
+                  const double* dt, bool regular, int64_t K, const double* lags, int kern,
+                  const double* h, const ncf_options_t* opt, ncf_plan_t** out) {
+    clear_error();
+    if (!out) {
+        set_error("null plan pointer");
+        return NCF_E_INVALID_ARG;
+    }
+    *out = nullptr;
+    Job J;
+    NCF_TRY(common_checks(opt, &J.opt, kern));
+    if (nser <= 0 || !t || !h || (regular && !dt)) {
+        set_error("null argument or nser <= 0");
+        return NCF_E_INVALID_ARG;
+    }
+    int64_t total = 0;
+    NCF_TRY(check_offs(offs, nser, &total));
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    J.regular = regular;
+    if (regular) J.dt.assign(dt, dt + nser);
+    NCF_TRY(setup_job(J, false, nser, offs, nullptr, total, 0, kern, h, K, lags));
+    const double* tin[2] = {t, nullptr};
+    const double* ein[2] = {err, nullptr};
+    return plan_create(J, tin, ein, out);
+}
+
+int plan_ccf_impl(int64_t npair, const int64_t* offx, const double* tx, const double* ex,
+                  const int64_t* offy, const double* ty, const double* ey, const double* dt,
+                  bool regular, int64_t K, const double* lags, int kern, const double* h,
+                  const ncf_options_t* opt, ncf_plan_t** out) {
+    clear_error();
+    if (!out) {
+        set_error("null plan pointer");
+        return NCF_E_INVALID_ARG;
+    }
+    *out = nullptr;
+    Job J;
+    NCF_TRY(common_checks(opt, &J.opt, kern));
+    if (npair <= 0 || !tx || !ty || !h || (regular && !dt)) {
+        set_error("null argument or npair <= 0");
+        return NCF_E_INVALID_ARG;
+    }
+    int64_t totx = 0, toty = 0;
+    NCF_TRY(check_offs(offx, npair, &totx));
+    NCF_TRY(check_offs(offy, npair, &toty));
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    J.regular = regular;
+    if (regular) J.dt.assign(dt, dt + npair);
+    NCF_TRY(setup_job(J, true, npair, offx, offy, totx, toty, kern, h, K, lags));
+    const double* tin[2] = {tx, ty};
+    const double* ein[2] = {ex, ey};
+    return plan_create(J, tin, ein, out);
+}
+
 int plan_status_error(const int32_t* st, int64_t n) {
     for (int64_t p = 0; p < n; ++p)
         if (st[p] != NCF_OK) {
@@ -2175,51 +2231,29 @@ extern "C" {
 int ncf_plan_acf(int64_t nser, const int64_t* offs, const double* t, const double* err,
                  int64_t K, const double* lags, int kern, const double* h,
                  const ncf_options_t* opt, ncf_plan_t** out) {
-    clear_error();
-    if (!out) {
-        set_error("null plan pointer");
-        return NCF_E_INVALID_ARG;
-    }
-    *out = nullptr;
-    Job J;
-    NCF_TRY(common_checks(opt, &J.opt, kern));
-    if (nser <= 0 || !t || !h) {
-        set_error("null argument or nser <= 0");
-        return NCF_E_INVALID_ARG;
-    }
-    int64_t total = 0;
-    NCF_TRY(check_offs(offs, nser, &total));
-    std::lock_guard<std::mutex> lock(g_ws_mu);
-    NCF_TRY(setup_job(J, false, nser, offs, nullptr, total, 0, kern, h, K, lags));
-    const double* tin[2] = {t, nullptr};
-    const double* ein[2] = {err, nullptr};
-    return plan_create(J, tin, ein, out);
+    return plan_acf_impl(nser, offs, t, err, nullptr, false, K, lags, kern, h, opt, out);
 }
 
 int ncf_plan_ccf(int64_t npair, const int64_t* offx, const double* tx, const double* ex,
                  const int64_t* offy, const double* ty, const double* ey, int64_t K,
                  const double* lags, int kern, const double* h, const ncf_options_t* opt,
                  ncf_plan_t** out) {
-    clear_error();
-    if (!out) {
-        set_error("null plan pointer");
-        return NCF_E_INVALID_ARG;
-    }
-    *out = nullptr;
-    Job J;
-    NCF_TRY(common_checks(opt, &J.opt, kern));
-    if (npair <= 0 || !tx || !ty || !h) {
-        set_error("null argument or npair <= 0");
-        return NCF_E_INVALID_ARG;
-    }
-    int64_t totx = 0, toty = 0;
-    NCF_TRY(check_offs(offx, npair, &totx));
-    NCF_TRY(check_offs(offy, npair, &toty));
-    std::lock_guard<std::mutex> lock(g_ws_mu);
-    NCF_TRY(setup_job(J, true, npair, offx, offy, totx, toty, kern, h, K, lags));
-    const double* tin[2] = {tx, ty};
-    const double* ein[2] = {ex, ey};
-    return plan_create(J, tin, ein, out);
+    return plan_ccf_impl(npair, offx, tx, ex, offy, ty, ey, nullptr, false, K, lags, kern, h, opt,
+                         out);
+}
+
+int ncf_plan_acf_regular(int64_t nser, const int64_t* offs, const double* t, const double* err,
+                         const double* dt, int64_t K, const double* lags, int kern,
+                         const double* h, const ncf_options_t* opt, ncf_plan_t** out) {
+    return plan_acf_impl(nser, offs, t, err, dt, true, K, lags, kern, h, opt, out);
+}
+
+int ncf_plan_ccf_regular(int64_t npair, const int64_t* offx, const double* tx, const double* ex,
+                         const int64_t* offy, const double* ty, const double* ey,
+                         const double* dt, int64_t K, const double* lags, int kern,
+                         const double* h, const ncf_options_t* opt, ncf_plan_t** out) {
+    return plan_ccf_impl(npair, offx, tx, ex, offy, ty, ey, dt, true, K, lags, kern, h, opt,
+                         out);
 }
 
 int ncf_plan_execute(ncf_plan_t* P, const double* x, const double* y, double* c, double* b,

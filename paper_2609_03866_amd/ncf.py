@@ -101,6 +101,10 @@ def lib():
         L.ncf_plan_acf.argtypes = [_I64, _P, _P, _P, _I64, _P, ctypes.c_int, _P, _P, _P]
         L.ncf_plan_ccf.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _I64, _P, ctypes.c_int, _P, _P,
                                    _P]
+        L.ncf_plan_acf_regular.argtypes = [_I64, _P, _P, _P, _P, _I64, _P, ctypes.c_int, _P, _P,
+                                           _P]
+        L.ncf_plan_ccf_regular.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _I64, _P,
+                                           ctypes.c_int, _P, _P, _P]
         L.ncf_plan_execute.argtypes = [_P, _P, _P, _P, _P, _P, _P]
         L.ncf_plan_destroy.argtypes = [_P]
         L.ncf_plan_info.argtypes = [_P, _P]
@@ -462,6 +466,44 @@ def plan_ccf(offx, t, offy, s, lags, kernel="gaussian", h=1.0, ex=None, ey=None,
     _check(lib().ncf_plan_ccf(npair, offx.ctypes.data, m.inp(t), m.inp(ex), offy.ctypes.data,
                               m.inp(s), m.inp(ey), K, m.inp(lags), _kern(kernel),
                               hs.ctypes.data, ctypes.byref(o), ctypes.byref(hp)))
+    return Plan(hp.value, True, npair, K, dev)
+
+
+def plan_acf_regular(offs, t, lags, dt, kernel="gaussian", h=1.0, err=None, graph=True,
+                     stream=None, autotune=False):
+    """ncf_plan_acf_regular over CSR series on regular lattices."""
+    offs = np.ascontiguousarray(offs, dtype=np.int64)
+    nser = offs.size - 1
+    hs = np.ascontiguousarray(np.broadcast_to(np.asarray(h, dtype=np.float64), (nser,)))
+    dts = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, dtype=np.float64), (nser,)))
+    dev = t.device if _is_torch(t) else None
+    m = _Marshal(dev)
+    K = int(lags.numel() if _is_torch(lags) else np.asarray(lags).size)
+    o = _plan_options("fp64", "auto", 0.0, 0.0, 0, dev, stream, graph, False, autotune)
+    hp = ctypes.c_void_p()
+    _check(lib().ncf_plan_acf_regular(nser, offs.ctypes.data, m.inp(t), m.inp(err),
+                                      dts.ctypes.data, K, m.inp(lags), _kern(kernel),
+                                      hs.ctypes.data, ctypes.byref(o), ctypes.byref(hp)))
+    return Plan(hp.value, False, nser, K, dev)
+
+
+def plan_ccf_regular(offx, t, offy, s, lags, dt, kernel="gaussian", h=1.0, ex=None, ey=None,
+                     graph=True, stream=None, autotune=False):
+    """ncf_plan_ccf_regular over CSR series pairs on common lattices."""
+    offx = np.ascontiguousarray(offx, dtype=np.int64)
+    offy = np.ascontiguousarray(offy, dtype=np.int64)
+    npair = offx.size - 1
+    hs = np.ascontiguousarray(np.broadcast_to(np.asarray(h, dtype=np.float64), (npair,)))
+    dts = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, dtype=np.float64), (npair,)))
+    dev = t.device if _is_torch(t) else None
+    m = _Marshal(dev)
+    K = int(lags.numel() if _is_torch(lags) else np.asarray(lags).size)
+    o = _plan_options("fp64", "auto", 0.0, 0.0, 0, dev, stream, graph, False, autotune)
+    hp = ctypes.c_void_p()
+    _check(lib().ncf_plan_ccf_regular(npair, offx.ctypes.data, m.inp(t), m.inp(ex),
+                                      offy.ctypes.data, m.inp(s), m.inp(ey), dts.ctypes.data, K,
+                                      m.inp(lags), _kern(kernel), hs.ctypes.data,
+                                      ctypes.byref(o), ctypes.byref(hp)))
     return Plan(hp.value, True, npair, K, dev)
 
 

@@ -218,3 +218,63 @@ def test_r1_full_size(kernel):
     c, b, cnt, rc = ncf.acf_regular(d["t"], d["x"], d["lags"], d["dt"], kernel, d["h"])
     assert rc == 0
     _check(c, b, cnt, oc, ob, on, kernel)
+
+
+# ------------------------------------------------------------------ plans
+
+@pytest.mark.parametrize("graph", [True, False])
+@pytest.mark.parametrize("kernel", ["gaussian", "rectangle"])
+def test_regular_plan_replays(kernel, graph):
+    d = synth.small("r2", seed=9)
+    offs, t, lags = d["offs"], d["t"], d["lags"]
+    hs = 0.5 if kernel == "gaussian" else 1.0
+    plan = ncf.plan_acf_regular(offs, t, lags, 1.0, kernel, hs, graph=graph)
+    try:
+        info = plan.info()
+        assert info["graph"] == (1 if graph else 0) and info["spectral_grids"] == offs.size - 1
+        rng = synth.rng_for(1)
+        for rep in range(3):  # new values each execution
+            x = rng.normal(size=t.size)
+            c, b, cnt, st, rc = plan.execute(x)
+            assert rc == 0 and np.all(st == 0)
+            c1, b1, n1, st1, _ = ncf.acf_regular_batch(offs, t, x, lags, 1.0, kernel, hs)
+            np.testing.assert_allclose(c, c1, rtol=0, atol=1e-14)
+            np.testing.assert_array_equal(b, b1)
+            np.testing.assert_array_equal(cnt, n1)
+            if rep == 0:
+                for i in (0, offs.size - 2):
+                    seg = slice(offs[i], offs[i + 1])
+                    _, oc, ob, on = O.acf_regular(t[seg], x[seg], lags, 1.0, kernel, hs)
+                    _check(c[i], b[i], cnt[i], oc, ob, on, kernel)
+    finally:
+        plan.close()
+
+
+def test_regular_ccf_plan_status_and_autotune():
+    rng = synth.rng_for(31)
+    offx, offy, tx, ty = [0], [0], [], []
+    for i in range(3):
+        t = synth.lattice_times(rng, 3000 + 2000 * i, dt=0.5, keep=0.9)
+        s = synth.lattice_times(rng, 4000, dt=0.5, keep=0.9, t0=1.5)
+        if i == 1:
+            s = s + 0.2  # off the common lattice
+        tx.append(t)
+        ty.append(s)
+        offx.append(offx[-1] + t.size)
+        offy.append(offy[-1] + s.size)
+    TX, TY = np.concatenate(tx), np.concatenate(ty)
+    lags = np.arange(-100, 101) * 0.5
+    plan = ncf.plan_ccf_regular(offx, TX, offy, TY, lags, 0.5, "gaussian", 0.3, autotune=True)
+    try:
+        assert plan.info()["autotuned"] == 1
+        x = rng.normal(size=TX.size)
+        y = rng.normal(size=TY.size)
+        c, b, cnt, st, rc = plan.execute(x, y, raise_on_error=False)
+        assert rc == ncf.E_INVALID_ARG and list(st) == [0, ncf.E_INVALID_ARG, 0]
+        for i in (0, 2):
+            xs = x[offx[i]:offx[i + 1]]
+            ys = y[offy[i]:offy[i + 1]]
+            _, oc, ob, on = O.ccf_regular(tx[i], xs, ty[i], ys, lags, 0.5, "gaussian", 0.3)
+            _check(c[i], b[i], cnt[i], oc, ob, on, "gaussian")
+    finally:
+        plan.close()
