@@ -9,7 +9,11 @@ resident in HBM. The metric is n*K lag-pairs per second with n = nx + ny
 per CCF (the paper's O((n1 + n2) K) unit of work).
 
 Other workloads (``--workload c1|c3|c4|c5``) are reported the same way and
-add series/s for the batched ones.
+add series/s for the batched ones. ``r1`` and ``r2`` are regular-lattice
+ACFs (the paper's regular-data benchmark: white noise on a 1-d lattice,
+366 integer lags) through the classic-FFT route in FP64, with the general
+NUFFT route (``nufft_gpu_path``) and the FP64 direct window sums timed on the
+same data.
 
 Prints one JSON line. ``roofline`` describes the kernel with the largest
 share of GPU time, timed with HIP events on the stream the library
@@ -50,6 +54,10 @@ def make_workload(name):
         return [synth.c4()]
     if name == "c5":
         return [synth.c5()]
+    if name == "r1":
+        return [synth.r1(kernel="gaussian"), synth.r1(kernel="rectangle")]
+    if name == "r2":
+        return [synth.r2()]
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -86,7 +94,16 @@ WINDOW_QUEUE = False  # --window-queue: queue dispatch of the window scans
 
 
 def run_one(d, precision="mixed", method="auto"):
+    """One call of the workload. Regular-lattice workloads (with "dt") take the
+    classic-FFT route unless method names another ("spectral", "direct")."""
     from paper_2609_03866_amd import ncf
+    if d.get("dt") is not None and method == "auto":
+        if d["kind"] == "acf":
+            return ncf.acf_regular(d["t"], d["x"], d["lags"], d["dt"], d["kernel"], d["h"])
+        return ncf.acf_regular_batch(d["offs"], d["t"], d["x"], d["lags"], d["dt"], d["kernel"],
+                                     d["h"])
+    if d.get("dt") is not None and method == "nufft":
+        method = "auto"
     kw = dict(precision=precision, method=method, with_count=True, window_queue=WINDOW_QUEUE)
     if d["kind"] == "acf":
         return ncf.acf(d["t"], d["x"], d["lags"], d["kernel"], d["h"], err=d.get("err"), **kw)
@@ -102,6 +119,10 @@ def run_one(d, precision="mixed", method="auto"):
 def make_plan(d, precision="mixed", method="auto", autotune=False):
     """A plan over the workload's times (device tensors), replayed as a graph."""
     from paper_2609_03866_amd import ncf
+    if d.get("dt") is not None:
+        offs = d["offs"] if d["kind"] == "acf_batch" else np.array([0, d["t"].numel()])
+        return ncf.plan_acf_regular(offs, d["t"], d["lags"], d["dt"], d["kernel"], d["h"],
+                                    autotune=autotune)
     kw = dict(precision=precision, method=method, window_queue=WINDOW_QUEUE, autotune=autotune)
     if d["kind"] == "acf":
         return ncf.plan_acf(np.array([0, d["t"].numel()]), d["t"], d["lags"], d["kernel"],
@@ -140,7 +161,12 @@ def oracle_subset(d, max_series):
     t0 = time.perf_counter()
     cs, ns, work = [], [], 0
     pick = None
-    if d["kind"] == "acf":
+    regular = d.get("dt") is not None
+    if d["kind"] == "acf" and regular:
+        pick = np.arange(d["lags"].size)
+        st, c, b, n = O.acf_regular(d["t"], d["x"], d["lags"], d["dt"], d["kernel"], d["h"])
+        cs, ns, work = [c], [n], d["t"].size * pick.size
+    elif d["kind"] == "acf":
         pick = lag_subset(d)
         st, c, b, n = O.acf(d["t"], d["x"], d["lags"][pick], d["kernel"], d["h"],
                             err=d.get("err"))
@@ -154,8 +180,12 @@ def oracle_subset(d, max_series):
         o = d["offs"]
         for i in range(min(max_series, o.size - 1)):
             sl = slice(o[i], o[i + 1])
-            st, c, b, n = O.acf(d["t"][sl], d["x"][sl], d["lags"], d["kernel"], d["h"][i],
-                                err=None if d.get("err") is None else d["err"][sl])
+            if regular:
+                st, c, b, n = O.acf_regular(d["t"][sl], d["x"][sl], d["lags"], d["dt"][i],
+                                            d["kernel"], d["h"][i])
+            else:
+                st, c, b, n = O.acf(d["t"][sl], d["x"][sl], d["lags"], d["kernel"], d["h"][i],
+                                    err=None if d.get("err") is None else d["err"][sl])
             cs.append(c)
             ns.append(n)
             work += (o[i + 1] - o[i]) * d["lags"].size
@@ -290,6 +320,22 @@ def main():
         fp64 = {"value": work / dt64, "ms_per_step": dt64 * 1e3, "path": "fp64 direct window sums"}
         log(f"[bench] fp64 direct: {dt64 * 1e3:.3f} ms/step")
 
+    # regular-lattice workloads: the general (NUFFT, mixed precision) route on
+    # the same data, the comparison of the paper's regular-data benchmark
+    nufft = None
+    regular = host[0].get("dt") is not None
+    if regular:
+        step("mixed", "nufft")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(max(2, args.steps // 4)):
+            resn = step("mixed", "nufft")
+        torch.cuda.synchronize()
+        dtn = (time.perf_counter() - t1) / max(2, args.steps // 4)
+        nufft = {"value": work / dtn, "ms_per_step": dtn * 1e3,
+                 "path": "general route (NUFFT numerator, spectral/window pair counts), mixed"}
+        log(f"[bench] nufft mixed: {dtn * 1e3:.3f} ms/step")
+
     # the same step through plans built beforehand (graph replay on the values)
     plan_rep = None
     if not args.no_plan:
@@ -382,7 +428,8 @@ def main():
             orc_time += float(np.median(secs))
             rates.append(len(secs))
             key = f"{d['name']}_{d['kernel']}"
-            acc[key] = {"max_abs_dc_mixed": max_dc(r[0], cs, pick)}
+            acc[key] = {("max_abs_dc_regular_fp64" if regular else "max_abs_dc_mixed"):
+                        max_dc(r[0], cs, pick)}
             if d["kernel"] == "rectangle":
                 acc[key]["counts_bit_exact"] = counts_equal(r[2], ns, pick)
             if fp64 is not None:
@@ -403,7 +450,9 @@ def main():
                         "c2": "ccf_n1e5x2_K401_gauss+rect_mixed",
                         "c3": "acf_n1e7_K4096_gauss_mixed",
                         "c4": "acf_batch_10000_curves_K256_gauss_mixed",
-                        "c5": "ccf_batch_2048_pairs_K512_rect_mixed"}[args.workload],
+                        "c5": "ccf_batch_2048_pairs_K512_rect_mixed",
+                        "r1": "acf_regular_n256000_K366_gauss+rect_fp64",
+                        "r2": "acf_regular_batch_4096_K366_rect_fp64"}[args.workload],
            "lag_pairs_per_step": int(work), "series_per_step": int(nser)}
     out = {
         "metric": METRIC,
@@ -416,11 +465,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64 (mixed)",
+        "dtype": "f64" if regular else "f32+f64 (mixed)",
         "data": "synthetic",
         "config": cfg,
         "series_per_s": nser / dt,
         "fp64_gpu_path": fp64,
+        "nufft_gpu_path": nufft,
         "plan_replay": plan_rep,
         "accuracy_vs_oracle": acc,
         "roofline": roof,

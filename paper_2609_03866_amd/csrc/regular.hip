@@ -141,32 +141,19 @@ __device__ __forceinline__ Spec cross(const Spec& a, const Spec& b) {
 }
 __device__ __forceinline__ Spec power(const Spec& a) { return Spec{a.r * a.r + a.i * a.i, 0.0}; }
 
-// Each thread owns one position whose frequency k is in [0, N/2] and its
-// partner at -k. The packed grid Z = A + iB of two real channels gives
-// A_k = (Z_k + conj Z_-k)/2 and B_k = (Z_k - conj Z_-k)/(2i). Every output
-// grid receives S1 + i S2 for two Hermitian spectra, so that the inverse
-// transform returns both real lag sequences (real and imaginary parts).
+// Spectra of one (k, -k) pair: unpack the channels of every input grid from
+// the values at p (frequency k) and pp (frequency -k), form the products and
+// store S1 + i S2 of every output grid at p and conj(S1) + i conj(S2) at pp.
+// The packed grid Z = A + iB of two real channels gives
+// A_k = (Z_k + conj Z_-k)/2 and B_k = (Z_k - conj Z_-k)/(2i); the inverse
+// transform of S1 + i S2 returns both real lag sequences (real and imaginary
+// parts).
 template <int MODE>
-__global__ void __launch_bounds__(kThreads)
-k_reg_product(const RegTask* __restrict__ tasks, const int64_t* __restrict__ pos0, int ntasks) {
+__device__ __forceinline__ void reg_pair(gptr<double> Z, int64_t N, int64_t p, int64_t pp,
+                                         const C64 (&za)[reg_in_grids(MODE)],
+                                         const C64 (&zb)[reg_in_grids(MODE)]) {
     constexpr int NG = reg_in_grids(MODE);
     constexpr int NO = reg_out_grids(MODE);
-    const int64_t gb = (int64_t)blockIdx.x * kThreads;
-    const int ti = ntasks == 1 ? 0 : (int)wave_search<int64_t>(pos0, ntasks, gb, true) - 1;
-    const RegTask& T = tasks[ti];
-    const int64_t N = T.N;
-    const int64_t p = gb + threadIdx.x - T.pos0;
-    const RadixInfo ri = T.ri;
-    const int64_t k = freq_of_pos(p, ri);
-    if (k > N / 2) return;
-    const int64_t pp = pos_of_freq((N - k) & (N - 1), ri);
-    const gptr<double> Z = gbl(T.grids);
-    C64 za[NG], zb[NG];
-#pragma unroll
-    for (int g = 0; g < NG; ++g) {
-        za[g] = ld(Z, g * N + p);
-        zb[g] = ld(Z, g * N + pp);
-    }
     Spec ch[2 * NG];
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
@@ -208,6 +195,60 @@ k_reg_product(const RegTask* __restrict__ tasks, const int64_t* __restrict__ pos
         const C64 am{inv * (s1[o].r + s2[o].i), inv * (s2[o].r - s1[o].i)};
         st(Z, o * N + p, at);
         if (pp != p) st(Z, o * N + pp, am);
+    }
+}
+
+// A workgroup owns kProdTile consecutive positions of one task. The last
+// transform pass has radix 4096, so the top bit of the frequency k is bit 11
+// of the position: positions with that bit clear hold k < N/2 and own the
+// pair (k, -k); k = N/2 (position 2048 of the first tile) is its own
+// partner and is handled there. Each thread issues the loads of its
+// positions before any store (pairs are disjoint, so nothing is read after
+// being written).
+constexpr int kProdTile = 4096;
+// pairs per thread (fewer with more input grids, to bound registers) and
+// threads per workgroup
+__host__ __device__ constexpr int prod_it(int mode) { return reg_in_grids(mode) == 1 ? 8 : reg_in_grids(mode) == 2 ? 4 : 2; }
+__host__ __device__ constexpr int prod_threads(int mode) { return kProdTile / 2 / prod_it(mode); }
+
+template <int MODE>
+__global__ void __launch_bounds__(prod_threads(MODE))
+k_reg_product(const RegTask* __restrict__ tasks, const int64_t* __restrict__ pos0, int ntasks) {
+    constexpr int NG = reg_in_grids(MODE);
+    constexpr int kProdIt = prod_it(MODE);
+    constexpr int kTh = prod_threads(MODE);
+    const int64_t gb = (int64_t)blockIdx.x * kProdTile;
+    const int ti = ntasks == 1 ? 0 : (int)wave_search<int64_t>(pos0, ntasks, gb, true) - 1;
+    const RegTask& T = tasks[ti];
+    const int64_t N = T.N;
+    const int64_t tb = gb - T.pos0;  // first position of the tile in its grid
+    const RadixInfo ri = T.ri;
+    const gptr<double> Z = gbl(T.grids);
+    int64_t pb[kProdIt];
+    C64 za[kProdIt][NG], zb[kProdIt][NG];
+#pragma unroll
+    for (int it = 0; it < kProdIt; ++it) {
+        const int64_t p = tb + threadIdx.x + it * kTh;
+        pb[it] = pos_of_freq((N - freq_of_pos(p, ri)) & (N - 1), ri);
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            za[it][g] = ld(Z, g * N + p);
+            zb[it][g] = ld(Z, g * N + pb[it]);
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < kProdIt; ++it)
+        reg_pair<MODE>(Z, N, tb + threadIdx.x + it * kTh, pb[it], za[it], zb[it]);
+    if (tb == 0 && threadIdx.x == 0) {  // k = N/2
+        const int64_t p = kProdTile / 2;
+        const int64_t pp = pos_of_freq((N - freq_of_pos(p, ri)) & (N - 1), ri);
+        C64 a[NG], b[NG];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            a[g] = ld(Z, g * N + p);
+            b[g] = ld(Z, g * N + pp);
+        }
+        reg_pair<MODE>(Z, N, p, pp, a, b);
     }
 }
 
@@ -406,12 +447,12 @@ int launch_reg_product(const RegTask* d_tasks, const int64_t* d_pos0, int ntasks
                        int mode, hipStream_t st, double bytes) {
     if (ntasks <= 0 || total <= 0) return NCF_OK;
     ProfScope p(st, "reg_product", bytes, "bytes");
-    const dim3 grid((unsigned)ceil_div(total, kThreads));
+    const dim3 grid((unsigned)ceil_div(total, kProdTile));
     switch (mode) {
-        case 0: hipLaunchKernelGGL(k_reg_product<0>, grid, dim3(kThreads), 0, st, d_tasks, d_pos0, ntasks); break;
-        case 1: hipLaunchKernelGGL(k_reg_product<1>, grid, dim3(kThreads), 0, st, d_tasks, d_pos0, ntasks); break;
-        case 2: hipLaunchKernelGGL(k_reg_product<2>, grid, dim3(kThreads), 0, st, d_tasks, d_pos0, ntasks); break;
-        default: hipLaunchKernelGGL(k_reg_product<3>, grid, dim3(kThreads), 0, st, d_tasks, d_pos0, ntasks); break;
+        case 0: hipLaunchKernelGGL(k_reg_product<0>, grid, dim3(prod_threads(0)), 0, st, d_tasks, d_pos0, ntasks); break;
+        case 1: hipLaunchKernelGGL(k_reg_product<1>, grid, dim3(prod_threads(1)), 0, st, d_tasks, d_pos0, ntasks); break;
+        case 2: hipLaunchKernelGGL(k_reg_product<2>, grid, dim3(prod_threads(2)), 0, st, d_tasks, d_pos0, ntasks); break;
+        default: hipLaunchKernelGGL(k_reg_product<3>, grid, dim3(prod_threads(3)), 0, st, d_tasks, d_pos0, ntasks); break;
     }
     NCF_CHECK_LAUNCH();
     return NCF_OK;

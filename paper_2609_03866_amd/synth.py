@@ -301,7 +301,8 @@ def r1(seed=11, n=256_000, kernel="gaussian", K=366):
     rng = rng_for(seed)
     t = lattice_times(rng, n, dt=1.0)
     x = rng.normal(size=n)
-    return dict(t=t, x=x, dt=1.0, lags=np.arange(K, dtype=np.float64), kernel=kernel, h=0.5)
+    return dict(kind="acf", name="r1", t=t, x=x, err=None, dt=1.0,
+                lags=np.arange(K, dtype=np.float64), kernel=kernel, h=0.5)
 
 
 def r2(seed=12, n_series=4096, nmin=1000, nmax=100_000, K=366, kernel="rectangle"):
@@ -312,8 +313,8 @@ def r2(seed=12, n_series=4096, nmin=1000, nmax=100_000, K=366, kernel="rectangle
     for i in range(n_series):
         t[offs[i]:offs[i + 1]] = lattice_times(rng, int(ns[i]), dt=1.0, keep=0.9)
     x = rng.normal(size=offs[-1])
-    return dict(offs=offs, t=t, x=x, dt=np.ones(n_series), lags=np.arange(K, dtype=np.float64),
-                kernel=kernel, h=np.full(n_series, 0.5))
+    return dict(kind="acf_batch", name="r2", offs=offs, t=t, x=x, err=None, dt=np.ones(n_series),
+                lags=np.arange(K, dtype=np.float64), kernel=kernel, h=np.full(n_series, 0.5))
 
 
 WORKLOADS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5, "r1": r1, "r2": r2}
