@@ -243,7 +243,10 @@ def measured_traffic(workload, kernel):
         cur = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()[:16]
         if cur != v.get("source_sha"):
             return None
-    return sum(v["bytes_per_dispatch"] for v in hits) / len(hits)
+    # variants of one kernel (FFT passes of several radices): per-dispatch
+    # mean weighted by their dispatch counts
+    n = sum(v.get("dispatches", 1) for v in hits)
+    return sum(v["bytes_per_dispatch"] * v.get("dispatches", 1) for v in hits) / n
 
 
 def main():
@@ -255,6 +258,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU path")
     ap.add_argument("--no-plan", action="store_true", help="skip the plan replay timing")
+    ap.add_argument("--no-nufft", action="store_true",
+                    help="regular-lattice workloads: skip the NUFFT-route comparison")
     ap.add_argument("--window-queue", action="store_true",
                     help="window scans as persistent workgroups on a device work queue")
     ap.add_argument("--oracle-series", type=int, default=64)
@@ -324,7 +329,7 @@ def main():
     # the same data, the comparison of the paper's regular-data benchmark
     nufft = None
     regular = host[0].get("dt") is not None
-    if regular:
+    if regular and not args.no_nufft:
         step("mixed", "nufft")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
