@@ -217,6 +217,56 @@ int ncf_ccf_regular_batch(int64_t npair, const int64_t* offx, const double* tx, 
                           const double* lags, int kern, const double* h, double* c, double* b,
                           int64_t* count, int* status, const ncf_options_t* opt);
 
+/* ------------------------------------------------- replicate error bars
+ * Per-lag uncertainties by Monte-Carlo and bootstrap resampling, which the
+ * paper leaves to the user (Sec. "Discussion": the estimator supplies no
+ * per-lag error bars; they come from bootstrap or Monte-Carlo resampling of
+ * the data, as pyZDCF does internally). R replicates of the series are
+ * estimated as one batch over shared times; the call returns, per lag, the
+ * mean and the sample standard deviation (R - 1 denominator) of c over the
+ * replicates that succeed.
+ *
+ * Replicate r (0 <= r < R) of a series of n samples:
+ *  - values x_i + sigma_i z[r*n + i] (flux randomization) when z is given;
+ *    z holds caller-drawn deviates (normal for the usual scheme), sigma the
+ *    per-sample scale (often the measurement errors). z and sigma go
+ *    together; without them the values are x.
+ *  - sample i counted mult[r*n + i] >= 0 times (bootstrap resampling with
+ *    replacement: the multiplicities of n draws; 0 drops the sample) when
+ *    mult is given. A sample counted k times is exactly the series with that
+ *    sample repeated k times: the estimator runs with sample weights k
+ *    (times 1/err_i^2 when err is given), which give the repeated series'
+ *    mean, sd and pair sums.
+ *  - err (nullable) weights the estimator as in ncf_acf; it is not used to
+ *    perturb the values (pass it as sigma too for that).
+ * The replicates use the precision and method of the options, as ncf_acf
+ * does. Arrays follow NCF_DEVICE_POINTERS (then t, x, err, sigma, z, mult,
+ * lags, c_mean, c_sd and c_rep are device arrays); status is a HOST array.
+ *   c_mean, c_sd  K outputs each (NaN where fewer than 1 / 2 replicates
+ *                 succeed)
+ *   c_rep         optional R*K output: every replicate's c (NaN for a
+ *                 replicate that failed)
+ *   status        optional R per-replicate statuses (a bootstrap draw that
+ *                 leaves a constant series gives NCF_E_DEGENERATE)
+ * Returns NCF_OK when at least one replicate succeeds, else the first
+ * replicate's status; argument errors as in ncf_acf. n x R must stay below
+ * 4e9 (NCF_E_UNSUPPORTED). */
+int ncf_acf_resample(int64_t n, const double* t, const double* x, const double* err,
+                     const double* sigma, int64_t R, const double* z, const int32_t* mult,
+                     int64_t K, const double* lags, int kern, double h, double* c_mean,
+                     double* c_sd, double* c_rep, int* status, const ncf_options_t* opt);
+
+/* Cross-correlation replicates: series 1 (nx samples: tx, x, ex, sx, zx,
+ * multx) and series 2 (ny samples: ty, y, ey, sy, zy, multy), each
+ * resampled with its own deviates and multiplicities (R*nx and R*ny);
+ * other arguments as in ncf_acf_resample. */
+int ncf_ccf_resample(int64_t nx, const double* tx, const double* x, const double* ex,
+                     const double* sx, const double* zx, const int32_t* multx, int64_t ny,
+                     const double* ty, const double* y, const double* ey, const double* sy,
+                     const double* zy, const int32_t* multy, int64_t R, int64_t K,
+                     const double* lags, int kern, double h, double* c_mean, double* c_sd,
+                     double* c_rep, int* status, const ncf_options_t* opt);
+
 /* ----------------------------------------------------------------- plans
  * A plan fixes everything of a batch call except the values: times, errors,
  * lags, kernel, bandwidths and options. Building it runs the whole path once

@@ -172,3 +172,52 @@ def standardize(x, err=None):
     w = np.zeros(x.size)
     st = lib.oracle_standardize(x.size, _dp(x), _dp(err), _dp(v), _dp(w))
     return st, v, w
+
+
+def _replicate(t, x, err, sigma, z, mult, r):
+    """Replicate r by its definition: values perturbed by sigma * z[r], then
+    sample i written out mult[r, i] times (0 drops it)."""
+    xr = np.asarray(x, float) + (np.asarray(sigma, float) * z[r] if z is not None else 0.0)
+    if mult is None:
+        return np.asarray(t, float), xr, err
+    idx = np.repeat(np.arange(len(t)), mult[r])
+    return np.asarray(t, float)[idx], xr[idx], (None if err is None else np.asarray(err)[idx])
+
+
+def _rep_stats(cs):
+    """Per-lag mean and sample sd over the replicates whose estimate is a number."""
+    C = np.array(cs)
+    mean = np.array([np.mean(col[~np.isnan(col)]) if np.any(~np.isnan(col)) else np.nan
+                     for col in C.T])
+    sd = np.array([np.std(col[~np.isnan(col)], ddof=1) if np.sum(~np.isnan(col)) > 1 else np.nan
+                   for col in C.T])
+    return mean, sd
+
+
+def acf_resample(t, x, lags, kernel, h, err=None, sigma=None, z=None, mult=None, threads=0):
+    """Replicate ACFs (flux randomization and/or bootstrap by repetition of
+    samples). Returns (statuses, c_rep[R, K], c_mean, c_sd)."""
+    R = (z if z is not None else mult).shape[0]
+    sts, cs = [], []
+    for r in range(R):
+        tr, xr, er = _replicate(t, x, err, sigma, z, mult, r)
+        st, c, _, _ = acf(tr, xr, lags, kernel, h, err=er, threads=threads)
+        sts.append(st)
+        cs.append(c if st == OK else np.full(len(lags), np.nan))
+    mean, sd = _rep_stats(cs)
+    return np.array(sts), np.array(cs), mean, sd
+
+
+def ccf_resample(t, x, s, y, lags, kernel, h, ex=None, ey=None, sx=None, sy=None, zx=None,
+                 zy=None, multx=None, multy=None, threads=0):
+    """Replicate CCFs, each series resampled with its own draws."""
+    R = next(a.shape[0] for a in (zx, multx, zy, multy) if a is not None)
+    sts, cs = [], []
+    for r in range(R):
+        tr, xr, er = _replicate(t, x, ex, sx, zx, multx, r)
+        sr, yr, fr = _replicate(s, y, ey, sy, zy, multy, r)
+        st, c, _, _ = ccf(tr, xr, sr, yr, lags, kernel, h, ex=er, ey=fr, threads=threads)
+        sts.append(st)
+        cs.append(c if st == OK else np.full(len(lags), np.nan))
+    mean, sd = _rep_stats(cs)
+    return np.array(sts), np.array(cs), mean, sd

@@ -125,12 +125,12 @@ struct Staging {
     size_t cap = 0;
 };
 
-// Device memory of a call: three workspace arenas (moments, main phase,
-// fallback) and three table stagings. One-shot calls share one set per
+// Device memory of a call: workspace arenas (moments, main phase, fallback,
+// and the replicate series of the resampling calls) and three table stagings. One-shot calls share one set per
 // device (grown on demand, kept until ncf_release_workspace); a plan owns
 // its own set for its lifetime.
 struct Resources {
-    DevBuf ws[3];
+    DevBuf ws[4];  // moments, main phase, fallback, replicate inputs
     Staging stage[3];
     unsigned long long* queue = nullptr;  // work-queue counter pairs, zeroed once
     bool exact = false;  // plan: allocate what is asked, no growth slack
@@ -261,6 +261,8 @@ struct SeriesSet {
     double* pv = nullptr;  // ntot + nser entries (n + 1 per series)
     double* pw = nullptr;
     int sd0 = 0;           // first descriptor of this set in the moments table
+    bool shared_t = false; // every series of the set has the same times (t holds one copy)
+    bool wmode = false;    // err holds sample weights (w >= 0) instead of errors
 };
 
 // Scheduling settings that change speed, not the estimator (results differ
@@ -757,7 +759,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
                 S.x = xin[si];
                 S.err = ein[si];
             } else {
-                S.t = ar.take<double>(S.ntot);
+                S.t = ar.take<double>(S.shared_t ? S.offs[1] : S.ntot);
                 S.x = ar.take<double>(S.ntot);
                 S.err = ein[si] ? ar.take<double>(S.ntot) : nullptr;
             }
@@ -784,7 +786,8 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         for (int si = 0; si < nsets; ++si) {
             SeriesSet& S = J.set[si];
             const size_t by = sizeof(double) * S.ntot;
-            NCF_TRY_HIP(hipMemcpyAsync((void*)S.t, tin[si], by, hipMemcpyHostToDevice, J.st));
+            const size_t byt = sizeof(double) * (S.shared_t ? S.offs[1] : S.ntot);
+            NCF_TRY_HIP(hipMemcpyAsync((void*)S.t, tin[si], byt, hipMemcpyHostToDevice, J.st));
             NCF_TRY_HIP(hipMemcpyAsync((void*)S.x, xin[si], by, hipMemcpyHostToDevice, J.st));
             if (ein[si])
                 NCF_TRY_HIP(
@@ -796,7 +799,8 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         for (int s = 0; s < S.nser; ++s) {
             SeriesDesc& d = sdesc[S.sd0 + s];
             const int64_t o = S.offs[s];
-            d.t = S.t + o;
+            d.t = S.shared_t ? S.t : S.t + o;
+            d.wmode = S.wmode ? 1 : 0;
             d.xoff = o;
             d.err = S.err ? S.err + o : nullptr;
             d.v32 = S.v32 ? S.v32 + o : nullptr;
@@ -1860,6 +1864,205 @@ int ncf_ccf(int64_t nx, const double* tx, const double* x, const double* ex, int
     int64_t ox[2] = {0, nx}, oy[2] = {0, ny};
     return ncf_ccf_batch(1, ox, tx, x, ex, oy, ty, y, ey, K, lags, kern, &h, c, b, count,
                          nullptr, opt);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ resampling
+
+namespace ncf {
+namespace {
+
+struct ResampleSet {
+    int64_t n;
+    const double* t;
+    const double* x;
+    const double* err;
+    const double* sigma;
+    const double* z;
+    const int32_t* mult;
+};
+
+// R replicates of an ACF (one set) or CCF (two sets) as one batch over
+// shared times; per-lag mean and standard deviation of c over the
+// replicates that succeed.
+int resample_impl(bool ccf, const ResampleSet* in, int64_t R, int64_t K, const double* lags,
+                  int kern, double h, double* c_mean, double* c_sd, double* c_rep, int* status,
+                  const ncf_options_t* opt) {
+    clear_error();
+    ncf_options_t o;
+    NCF_TRY(common_checks(opt, &o, kern));
+    const int nsets = ccf ? 2 : 1;
+    if (R < 1 || K < 0 || (K > 0 && (!lags || !c_mean || !c_sd))) {
+        set_error("invalid replicate count, lags or outputs");
+        return NCF_E_INVALID_ARG;
+    }
+    for (int si = 0; si < nsets; ++si) {
+        const ResampleSet& S = in[si];
+        if (S.n < 2 || !S.t || !S.x) {
+            set_error("series %d: fewer than 2 samples or null arrays", si + 1);
+            return NCF_E_INVALID_ARG;
+        }
+        if ((S.z == nullptr) != (S.sigma == nullptr)) {
+            set_error("series %d: deviates z and their scale sigma go together", si + 1);
+            return NCF_E_INVALID_ARG;
+        }
+        if ((double)S.n * (double)R > 4.0e9) {
+            set_error("series %d: n x R above 4e9 samples", si + 1);
+            return NCF_E_UNSUPPORTED;
+        }
+    }
+    const bool dev = (o.flags & NCF_DEVICE_POINTERS) != 0;
+    hipStream_t st = (hipStream_t)o.stream;
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    Resources* res = device_resources();
+    if (!res) {
+        set_error("no current HIP device");
+        return NCF_E_DEVICE;
+    }
+
+    // replicate workspace: device copies of host inputs, replicate values
+    // and weights, replicate estimates and (host mode) the statistics
+    struct Dev {
+        const double *t, *x, *err, *sigma, *z;
+        const int32_t* mult;
+        double *xr, *wr;
+    } D[2] = {};
+    double *crep = nullptr, *brep = nullptr, *cm = nullptr, *cs = nullptr;
+    const double* dlags = lags;
+    auto layout = [&](Arena& ar) {
+        for (int si = 0; si < nsets; ++si) {
+            const ResampleSet& S = in[si];
+            Dev& d = D[si];
+            const size_t nr = (size_t)S.n * R;
+            if (dev) {
+                d.t = S.t;
+                d.x = S.x;
+                d.err = S.err;
+                d.sigma = S.sigma;
+                d.z = S.z;
+                d.mult = S.mult;
+            } else {
+                d.t = ar.take<double>(S.n);
+                d.x = ar.take<double>(S.n);
+                d.err = S.err ? ar.take<double>(S.n) : nullptr;
+                d.sigma = S.sigma ? ar.take<double>(S.n) : nullptr;
+                d.z = S.z ? ar.take<double>(nr) : nullptr;
+                d.mult = S.mult ? ar.take<int32_t>(nr) : nullptr;
+            }
+            d.xr = ar.take<double>(nr);
+            d.wr = (S.mult || S.err) ? ar.take<double>(nr) : nullptr;
+        }
+        if (!dev) dlags = ar.take<double>(std::max<int64_t>(K, 1));
+        crep = (dev && c_rep) ? c_rep : ar.take<double>(std::max<int64_t>(R * K, 1));
+        brep = ar.take<double>(std::max<int64_t>(R * K, 1));
+        cm = dev ? c_mean : ar.take<double>(std::max<int64_t>(K, 1));
+        cs = dev ? c_sd : ar.take<double>(std::max<int64_t>(K, 1));
+    };
+    Arena a;
+    layout(a);
+    void* ws = nullptr;
+    NCF_TRY(ensure_ws(*res, 3, a.off + 256, &ws));
+    a = Arena{(char*)ws, 0};
+    layout(a);
+    if (!dev) {
+        auto up = [&](const void* dst, const void* src, size_t by) -> int {
+            if (src && by)
+                NCF_TRY_HIP(hipMemcpyAsync((void*)dst, src, by, hipMemcpyHostToDevice, st));
+            return NCF_OK;
+        };
+        for (int si = 0; si < nsets; ++si) {
+            const ResampleSet& S = in[si];
+            const size_t nr = (size_t)S.n * R;
+            NCF_TRY(up(D[si].t, S.t, sizeof(double) * S.n));
+            NCF_TRY(up(D[si].x, S.x, sizeof(double) * S.n));
+            NCF_TRY(up(D[si].err, S.err, sizeof(double) * S.n));
+            NCF_TRY(up(D[si].sigma, S.sigma, sizeof(double) * S.n));
+            NCF_TRY(up(D[si].z, S.z, sizeof(double) * nr));
+            NCF_TRY(up(D[si].mult, S.mult, sizeof(int32_t) * nr));
+        }
+        NCF_TRY(up(dlags, lags, sizeof(double) * K));
+    }
+    for (int si = 0; si < nsets; ++si)
+        NCF_TRY(launch_resample_prep(in[si].n, R, D[si].x, D[si].sigma, D[si].z, D[si].err,
+                                     D[si].mult, D[si].xr, D[si].wr, st));
+
+    // the replicates as one batch over shared times
+    Job J;
+    J.opt = o;
+    J.opt.flags |= NCF_DEVICE_POINTERS;
+    J.res = res;
+    std::vector<double> hs((size_t)R, h);
+    // statuses are written only when the batch runs to its end; the sentinel
+    // marks a call that failed before (invalid lags, a device error)
+    constexpr int kNotRun = -1000;
+    std::vector<int> rstat((size_t)R, kNotRun);
+    std::vector<int64_t> offs[2];
+    for (int si = 0; si < nsets; ++si) {
+        offs[si].resize((size_t)R + 1);
+        for (int64_t r = 0; r <= R; ++r) offs[si][r] = r * in[si].n;
+    }
+    J.c = crep;
+    J.b = brep;
+    J.count = nullptr;
+    J.status = rstat.data();
+    NCF_TRY(setup_job(J, ccf, R, offs[0].data(), ccf ? offs[1].data() : nullptr, R * in[0].n,
+                      ccf ? R * in[1].n : 0, kern, hs.data(), K, dlags));
+    const double* tin[2] = {D[0].t, ccf ? D[1].t : nullptr};
+    const double* xin[2] = {D[0].xr, ccf ? D[1].xr : nullptr};
+    const double* ein[2] = {D[0].wr, ccf ? D[1].wr : nullptr};
+    for (int si = 0; si < nsets; ++si) {
+        J.set[si].shared_t = true;
+        J.set[si].wmode = D[si].wr != nullptr;
+    }
+    const int rc = run_job(J, tin, xin, ein);
+    if (rstat[0] == kNotRun) return rc != NCF_OK ? rc : NCF_E_DEVICE;
+    clear_error();
+    NCF_TRY(launch_resample_stats(crep, R, K, cm, cs, st));
+    if (!dev && K > 0) {
+        NCF_TRY_HIP(hipMemcpyAsync(c_mean, cm, sizeof(double) * K, hipMemcpyDeviceToHost, st));
+        NCF_TRY_HIP(hipMemcpyAsync(c_sd, cs, sizeof(double) * K, hipMemcpyDeviceToHost, st));
+        if (c_rep)
+            NCF_TRY_HIP(hipMemcpyAsync(c_rep, crep, sizeof(double) * R * K, hipMemcpyDeviceToHost,
+                                       st));
+    }
+    NCF_TRY_HIP(hipStreamSynchronize(st));
+    int first = NCF_OK, ok = 0;
+    for (int64_t r = 0; r < R; ++r) {
+        if (status) status[r] = rstat[r];
+        if (rstat[r] == NCF_OK)
+            ++ok;
+        else if (first == NCF_OK)
+            first = rstat[r];
+    }
+    if (ok == 0) {
+        set_error("no replicate succeeded (first status %d)", first);
+        return first;
+    }
+    return NCF_OK;
+}
+
+}  // namespace
+}  // namespace ncf
+
+extern "C" {
+
+int ncf_acf_resample(int64_t n, const double* t, const double* x, const double* err,
+                     const double* sigma, int64_t R, const double* z, const int32_t* mult,
+                     int64_t K, const double* lags, int kern, double h, double* c_mean,
+                     double* c_sd, double* c_rep, int* status, const ncf_options_t* opt) {
+    ResampleSet S{n, t, x, err, sigma, z, mult};
+    return resample_impl(false, &S, R, K, lags, kern, h, c_mean, c_sd, c_rep, status, opt);
+}
+
+int ncf_ccf_resample(int64_t nx, const double* tx, const double* x, const double* ex,
+                     const double* sx, const double* zx, const int32_t* multx, int64_t ny,
+                     const double* ty, const double* y, const double* ey, const double* sy,
+                     const double* zy, const int32_t* multy, int64_t R, int64_t K,
+                     const double* lags, int kern, double h, double* c_mean, double* c_sd,
+                     double* c_rep, int* status, const ncf_options_t* opt) {
+    ResampleSet S[2] = {{nx, tx, x, ex, sx, zx, multx}, {ny, ty, y, ey, sy, zy, multy}};
+    return resample_impl(true, S, R, K, lags, kern, h, c_mean, c_sd, c_rep, status, opt);
 }
 
 }  // extern "C"

@@ -161,7 +161,7 @@ struct SeriesDesc {
     int32_t chunk0;   // first chunk of the series
     int32_t nchunk;   // chunks of the series
     int32_t set;      // value array of the series (IoBlock::x index)
-    int32_t pad;
+    int32_t wmode;    // 1: err holds sample weights w >= 0 directly (else errors, w = 1/err^2)
 };
 
 constexpr int64_t kMomentChunk = 2048;  // samples per moments chunk (8 per thread)
@@ -195,6 +195,19 @@ int launch_moments(const MomentsArgs& a, hipStream_t st);
 int launch_standardize(const MomentsArgs& a, hipStream_t st);
 // Fill p[0..n) with alternating +1, -1 (finite values of unit variance).
 int launch_fill_alternating(double* p, int64_t n, hipStream_t st);
+
+// --------------------------------------------------- replicate statistics
+// Replicate r of a series of n samples: values x + sigma z_r (z_r: R x n,
+// row-major) and weights mult_r (x 1/err^2 when err is given). Either part
+// may be absent (sigma/z null: the values are copied; mult and err null: no
+// weights are written).
+int launch_resample_prep(int64_t n, int64_t R, const double* x, const double* sigma,
+                         const double* z, const double* err, const int32_t* mult, double* xr,
+                         double* wr, hipStream_t st);
+// Per lag, the mean and sample standard deviation (n - 1) of the replicate
+// estimates c_rep[R][K] over the replicates whose estimate is a number.
+int launch_resample_stats(const double* c_rep, int64_t R, int64_t K, double* c_mean,
+                          double* c_sd, hipStream_t st);
 
 // ------------------------------------------------------- A7 window scan
 enum WinFlags : uint32_t {

@@ -73,8 +73,13 @@ k_chunk_moments(MomentsArgs a) {
             double wi = 1.0;
             if (sd.err) {
                 const double e = er[i];
-                if (!(e > 0.0) || !isfinite(e)) bad = 1;
-                wi = 1.0 / (e * e);
+                if (sd.wmode) {
+                    if (!(e >= 0.0) || !isfinite(e)) bad = 1;
+                    wi = e;
+                } else {
+                    if (!(e > 0.0) || !isfinite(e)) bad = 1;
+                    wi = 1.0 / (e * e);
+                }
             }
             if (!isfinite(ti) || !isfinite(xi)) bad = 1;
             if (i > 0 && !(ti >= t[i - 1])) unsorted = 1;
@@ -224,7 +229,7 @@ k_standardize(MomentsArgs a) {
             w = 1.0;
             if (sd.err) {
                 double e = er[i];
-                w = 1.0 / (e * e);
+                w = sd.wmode ? e : 1.0 / (e * e);
             }
             v = ok ? w * ((X[i] - mean) * inv_sd) : 0.0;
             if (sd.v32) gbl(sd.v32)[i] = (float)v;

@@ -91,6 +91,11 @@ def lib():
                                             _P, _P, _P, _P, _P, _P]
         L.ncf_ccf_regular_batch.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _I64, _P,
                                             ctypes.c_int, _P, _P, _P, _P, _P, _P]
+        L.ncf_acf_resample.argtypes = [_I64, _P, _P, _P, _P, _I64, _P, _P, _I64, _P, ctypes.c_int,
+                                       ctypes.c_double, _P, _P, _P, _P, _P]
+        L.ncf_ccf_resample.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _I64, _P, _P, _P, _P, _P, _P,
+                                       _I64, _I64, _P, ctypes.c_int, ctypes.c_double, _P, _P, _P,
+                                       _P, _P]
         L.ncf_last_error.restype = ctypes.c_char_p
         L.ncf_options_init.argtypes = [_P]
         L.ncf_diag_fft.argtypes = [_I64, ctypes.c_int, ctypes.c_int, _P]
@@ -137,8 +142,9 @@ class _Marshal:
             return None
         if self.device:
             import torch
-            assert a.is_cuda and a.dtype == torch.float64 and a.is_contiguous(), \
-                "device arrays must be contiguous float64 CUDA tensors"
+            tdt = {np.float64: torch.float64, np.int32: torch.int32}[dtype]
+            assert a.is_cuda and a.dtype == tdt and a.is_contiguous(), \
+                f"device arrays must be contiguous {tdt} CUDA tensors"
             return a.data_ptr()
         a = np.ascontiguousarray(a, dtype=dtype)
         self.keep.append(a)
@@ -361,6 +367,66 @@ def ccf_regular_batch(offx, t, x, offy, s, y, lags, dt, kernel="gaussian", h=1.0
         _check(rc)
     rs = (lambda a: a.reshape(npair, K) if a is not None else None)
     return rs(c), rs(b), rs(cnt), st, rc
+
+
+# ------------------------------------------------ replicate error bars
+
+def _numel(a):
+    return int(a.numel() if _is_torch(a) else np.asarray(a).size)
+
+
+def acf_resample(t, x, lags, kernel="gaussian", h=1.0, err=None, sigma=None, z=None, mult=None,
+                 R=None, with_reps=False, precision="mixed", method="auto", raise_on_error=True,
+                 stream=None):
+    """ncf_acf_resample: R replicates (flux randomization x + sigma z[r],
+    bootstrap multiplicities mult[r]); z and mult are (R, n) arrays drawn by
+    the caller. Returns (c_mean, c_sd, c_rep or None, status[R], rc)."""
+    n = _numel(t)
+    if R is None:
+        R = (_numel(z) if z is not None else _numel(mult)) // n
+    dev = t.device if _is_torch(t) else None
+    m = _Marshal(dev)
+    K = _numel(lags)
+    cm, pm = m.out(K, np.float64)
+    cs, ps = m.out(K, np.float64)
+    cr, pr = m.out(R * K, np.float64) if with_reps else (None, None)
+    st = np.zeros(R, dtype=np.int32)
+    o = _options(precision, method, 0.0, 0.0, 0, dev, stream)
+    rc = lib().ncf_acf_resample(n, m.inp(t), m.inp(x), m.inp(err), m.inp(sigma), int(R),
+                                m.inp(z), m.inp(mult, np.int32), K, m.inp(lags), _kern(kernel),
+                                float(h), pm, ps, pr, st.ctypes.data, ctypes.byref(o))
+    if raise_on_error:
+        _check(rc)
+    return cm, cs, (cr.reshape(R, K) if cr is not None else None), st, rc
+
+
+def ccf_resample(t, x, s, y, lags, kernel="gaussian", h=1.0, ex=None, ey=None, sx=None,
+                 sy=None, zx=None, zy=None, multx=None, multy=None, R=None, with_reps=False,
+                 precision="mixed", method="auto", raise_on_error=True, stream=None):
+    """ncf_ccf_resample (series 1 = (t, x), series 2 = (s, y), each with its own
+    deviates and multiplicities, (R, nx) and (R, ny))."""
+    nx, ny = _numel(t), _numel(s)
+    if R is None:
+        for a, nn in ((zx, nx), (multx, nx), (zy, ny), (multy, ny)):
+            if a is not None:
+                R = _numel(a) // nn
+                break
+    dev = t.device if _is_torch(t) else None
+    m = _Marshal(dev)
+    K = _numel(lags)
+    cm, pm = m.out(K, np.float64)
+    cs, ps = m.out(K, np.float64)
+    cr, pr = m.out(R * K, np.float64) if with_reps else (None, None)
+    st = np.zeros(R, dtype=np.int32)
+    o = _options(precision, method, 0.0, 0.0, 0, dev, stream)
+    rc = lib().ncf_ccf_resample(nx, m.inp(t), m.inp(x), m.inp(ex), m.inp(sx), m.inp(zx),
+                                m.inp(multx, np.int32), ny, m.inp(s), m.inp(y), m.inp(ey),
+                                m.inp(sy), m.inp(zy), m.inp(multy, np.int32), int(R), K,
+                                m.inp(lags), _kern(kernel), float(h), pm, ps, pr,
+                                st.ctypes.data, ctypes.byref(o))
+    if raise_on_error:
+        _check(rc)
+    return cm, cs, (cr.reshape(R, K) if cr is not None else None), st, rc
 
 
 # ------------------------------------------------------------------ plans

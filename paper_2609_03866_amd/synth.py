@@ -35,6 +35,10 @@ Workloads (all seeded with numpy's PCG64):
   data, Sec. "Regularly-sampled data"): white noise N(0, 1) on t = m dt,
   dt = 1 d, n = 2.56e5 samples without gaps, integer lags 0..365 d
   (K = 366), Gaussian and rectangle kernels with h = 0.5 d.
+* ``m1`` -- Monte-Carlo error bars of a c2-shaped CCF: n = 2e4 samples per
+  series, errors sd 0.05, R = 100 replicates, each with flux randomization
+  (standard normal deviates) and a bootstrap resampling (multiplicities of
+  n draws with replacement); lags -200..200 d, Gaussian, h = 0.5 d.
 * ``r2`` -- batched regular-lattice ACF: 4,096 series on 1-d lattices,
   lengths log-uniform in [1e3, 1e5], 10 % of lattice points dropped, white
   noise; lags 0..365 d, rectangle, h = 0.5 d.
@@ -317,7 +321,38 @@ def r2(seed=12, n_series=4096, nmin=1000, nmax=100_000, K=366, kernel="rectangle
                 lags=np.arange(K, dtype=np.float64), kernel=kernel, h=np.full(n_series, 0.5))
 
 
-WORKLOADS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5, "r1": r1, "r2": r2}
+# ------------------------------------------------------- replicate draws
+
+def resample_draws(rng, n, R, flux=True, bootstrap=True):
+    """Random inputs of R replicates of an n-sample series: z (R, n) standard
+    normal deviates for flux randomization, and mult (R, n) int32 bootstrap
+    multiplicities (the counts of n draws with replacement). Either may be
+    None."""
+    z = rng.normal(size=(R, n)) if flux else None
+    mult = None
+    if bootstrap:
+        mult = np.stack([np.bincount(rng.integers(0, n, size=n), minlength=n)
+                         for _ in range(R)]).astype(np.int32)
+    return z, mult
+
+
+def m1(seed=13, n=20_000, R=100, K=401):
+    """Monte-Carlo error bars of a c2-shaped CCF: two seasonal series of n
+    samples (DRW driver, delayed top-hat response), measurement errors sd
+    0.05 on both; R replicates with flux randomization and bootstrap
+    resampling; lags -200..200 d, Gaussian, h = 0.5 d."""
+    d = c2(seed, n=n, kernel="gaussian")
+    rng = rng_for(seed + 1000)
+    nx, ny = d["t"].size, d["s"].size
+    d["ex"] = np.full(nx, 0.05)
+    d["ey"] = np.full(ny, 0.05)
+    d["zx"], d["multx"] = resample_draws(rng, nx, R)
+    d["zy"], d["multy"] = resample_draws(rng, ny, R)
+    d.update(kind="ccf_resample", name="m1", R=R)
+    return d
+
+
+WORKLOADS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5, "r1": r1, "r2": r2, "m1": m1}
 
 
 def small(name, seed=0):
@@ -337,4 +372,6 @@ def small(name, seed=0):
         return r1(seed, n=20_000, K=366)
     if name == "r2":
         return r2(seed, n_series=16, nmin=200, nmax=6000, K=120)
+    if name == "m1":
+        return m1(seed, n=1500, R=12, K=101)
     raise KeyError(name)

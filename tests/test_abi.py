@@ -27,7 +27,8 @@ def test_headers_declare_entry_points():
     names = _declared()
     for required in ("ncf_acf", "ncf_ccf", "ncf_acf_batch", "ncf_ccf_batch", "ncf_last_error",
                      "ncf_diag_fft", "ncf_diag_type1", "ncf_profile_read", "ncf_acf_regular",
-                     "ncf_ccf_regular", "ncf_acf_regular_batch", "ncf_ccf_regular_batch"):
+                     "ncf_ccf_regular", "ncf_acf_regular_batch", "ncf_ccf_regular_batch",
+                     "ncf_acf_resample", "ncf_ccf_resample"):
         assert required in names
 
 
@@ -89,6 +90,23 @@ def test_regular_entry_points_report_no_device():
     assert rc == ncf.E_DEVICE
     rc = ncf.ccf_regular(t, t % 3, t, t % 2, np.arange(3.0), 1.0, "g", 0.5,
                          raise_on_error=False)[3]
+    assert rc == ncf.E_DEVICE
+
+
+def test_resample_entry_points_report_no_device():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("GPU present")
+    except Exception:
+        pass
+    t = np.arange(10.0)
+    mult = np.ones((3, 10), dtype=np.int32)
+    rc = ncf.acf_resample(t, t % 3, np.arange(3.0), "g", 0.5, mult=mult,
+                          raise_on_error=False)[4]
+    assert rc == ncf.E_DEVICE
+    rc = ncf.ccf_resample(t, t % 3, t, t % 2, np.arange(3.0), "r", 0.5, multx=mult,
+                          raise_on_error=False)[4]
     assert rc == ncf.E_DEVICE
 
 
