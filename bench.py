@@ -15,6 +15,10 @@ ACFs (the paper's regular-data benchmark: white noise on a 1-d lattice,
 NUFFT route (``nufft_gpu_path``) and the FP64 direct window sums timed on the
 same data.
 
+``m1`` times Monte-Carlo error bars: 100 flux-randomized and bootstrap-
+resampled replicates of a c2-shaped CCF (2e4 samples per series) in one
+call; lag-pairs count every replicate.
+
 Prints one JSON line. ``roofline`` describes the kernel with the largest
 share of GPU time, timed with HIP events on the stream the library
 launches on; ``cpu_baseline`` times the FP64 CPU oracle on the host.
@@ -58,11 +62,15 @@ def make_workload(name):
         return [synth.r1(kernel="gaussian"), synth.r1(kernel="rectangle")]
     if name == "r2":
         return [synth.r2()]
+    if name == "m1":
+        return [synth.m1()]
     raise SystemExit(f"unknown workload {name}")
 
 
 def lag_pairs(d):
     K = d["lags"].size
+    if d["kind"] == "ccf_resample":
+        return d["R"] * (d["t"].size + d["s"].size) * K
     if d["kind"] == "acf":
         return d["t"].size * K
     if d["kind"] == "ccf":
@@ -73,6 +81,8 @@ def lag_pairs(d):
 
 
 def n_series(d):
+    if d["kind"] == "ccf_resample":
+        return d["R"]
     if d["kind"] == "acf_batch":
         return d["offs"].size - 1
     if d["kind"] == "ccf_batch":
@@ -84,9 +94,12 @@ def to_dev(d):
     import torch
     dev = torch.device("cuda:0")
     out = dict(d)
-    for k in ("t", "x", "s", "y", "lags", "err"):
+    for k in ("t", "x", "s", "y", "lags", "err", "ex", "ey", "zx", "zy"):
         if d.get(k) is not None:
             out[k] = torch.as_tensor(np.ascontiguousarray(d[k], dtype=np.float64), device=dev)
+    for k in ("multx", "multy"):
+        if d.get(k) is not None:
+            out[k] = torch.as_tensor(np.ascontiguousarray(d[k], dtype=np.int32), device=dev)
     return out
 
 
@@ -97,6 +110,11 @@ def run_one(d, precision="mixed", method="auto"):
     """One call of the workload. Regular-lattice workloads (with "dt") take the
     classic-FFT route unless method names another ("spectral", "direct")."""
     from paper_2609_03866_amd import ncf
+    if d["kind"] == "ccf_resample":
+        return ncf.ccf_resample(d["t"], d["x"], d["s"], d["y"], d["lags"], d["kernel"], d["h"],
+                                sx=d["ex"], sy=d["ey"], zx=d["zx"],
+                                zy=d["zy"], multx=d["multx"], multy=d["multy"], with_reps=True,
+                                precision=precision, method=method)
     if d.get("dt") is not None and method == "auto":
         if d["kind"] == "acf":
             return ncf.acf_regular(d["t"], d["x"], d["lags"], d["dt"], d["kernel"], d["h"])
@@ -162,7 +180,15 @@ def oracle_subset(d, max_series):
     cs, ns, work = [], [], 0
     pick = None
     regular = d.get("dt") is not None
-    if d["kind"] == "acf" and regular:
+    if d["kind"] == "ccf_resample":
+        m = min(max_series, d["R"])
+        st, crep, _, _ = O.ccf_resample(d["t"], d["x"], d["s"], d["y"], d["lags"], d["kernel"],
+                                        d["h"], sx=d["ex"], sy=d["ey"],
+                                        zx=d["zx"][:m], zy=d["zy"][:m], multx=d["multx"][:m],
+                                        multy=d["multy"][:m])
+        cs, ns = list(crep), [None] * m
+        work = m * (d["t"].size + d["s"].size) * d["lags"].size
+    elif d["kind"] == "acf" and regular:
         pick = np.arange(d["lags"].size)
         st, c, b, n = O.acf_regular(d["t"], d["x"], d["lags"], d["dt"], d["kernel"], d["h"])
         cs, ns, work = [c], [n], d["t"].size * pick.size
@@ -343,7 +369,7 @@ def main():
 
     # the same step through plans built beforehand (graph replay on the values)
     plan_rep = None
-    if not args.no_plan:
+    if not args.no_plan and host[0]["kind"] != "ccf_resample":
         plans = [make_plan(d) for d in devs]
         for pl, d in zip(plans, devs):
             run_plan(pl, d)
@@ -433,17 +459,21 @@ def main():
             orc_time += float(np.median(secs))
             rates.append(len(secs))
             key = f"{d['name']}_{d['kernel']}"
+            rc_ = r[2] if d["kind"] == "ccf_resample" else r[0]
             acc[key] = {("max_abs_dc_regular_fp64" if regular else "max_abs_dc_mixed"):
-                        max_dc(r[0], cs, pick)}
+                        max_dc(rc_, cs, pick)}
             if d["kernel"] == "rectangle":
                 acc[key]["counts_bit_exact"] = counts_equal(r[2], ns, pick)
             if fp64 is not None:
-                acc[key]["max_abs_dc_fp64_direct"] = max_dc(res64[i][0], cs, pick)
+                r64 = res64[i][2] if d["kind"] == "ccf_resample" else res64[i][0]
+                acc[key]["max_abs_dc_fp64_direct"] = max_dc(r64, cs, pick)
         d0 = host[0]
         if d0["kind"] in ("acf", "ccf"):
             npick = picks[0].size
             sample = ("whole workload" if npick == d0["lags"].size else
                       f"all samples, {npick} of {d0['lags'].size} lags (evenly spaced)")
+        elif d0["kind"] == "ccf_resample":
+            sample = f"first {min(args.oracle_series, d0['R'])} replicates"
         else:
             sample = f"first {args.oracle_series} series of the batch"
         cpu = {"value": orc_work / orc_time, "unit": "lag-pairs/s", "cores": cores,
@@ -457,7 +487,8 @@ def main():
                         "c4": "acf_batch_10000_curves_K256_gauss_mixed",
                         "c5": "ccf_batch_2048_pairs_K512_rect_mixed",
                         "r1": "acf_regular_n256000_K366_gauss+rect_fp64",
-                        "r2": "acf_regular_batch_4096_K366_rect_fp64"}[args.workload],
+                        "r2": "acf_regular_batch_4096_K366_rect_fp64",
+                        "m1": "ccf_resample_R100_n2e4x2_K401_gauss_mixed"}[args.workload],
            "lag_pairs_per_step": int(work), "series_per_step": int(nser)}
     out = {
         "metric": METRIC,

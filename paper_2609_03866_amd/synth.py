@@ -339,8 +339,9 @@ def resample_draws(rng, n, R, flux=True, bootstrap=True):
 def m1(seed=13, n=20_000, R=100, K=401):
     """Monte-Carlo error bars of a c2-shaped CCF: two seasonal series of n
     samples (DRW driver, delayed top-hat response), measurement errors sd
-    0.05 on both; R replicates with flux randomization and bootstrap
-    resampling; lags -200..200 d, Gaussian, h = 0.5 d."""
+    0.05 on both (ex, ey: the flux-randomization scale); R replicates with
+    flux randomization and bootstrap resampling; lags -200..200 d, Gaussian,
+    h = 0.5 d."""
     d = c2(seed, n=n, kernel="gaussian")
     rng = rng_for(seed + 1000)
     nx, ny = d["t"].size, d["s"].size
