@@ -240,7 +240,9 @@ int ncf_ccf_regular_batch(int64_t npair, const int64_t* offx, const double* tx, 
  *  - err (nullable) weights the estimator as in ncf_acf; it is not used to
  *    perturb the values (pass it as sigma too for that).
  * The replicates use the precision and method of the options, as ncf_acf
- * does. Arrays follow NCF_DEVICE_POINTERS (then t, x, err, sigma, z, mult,
+ * does; with the default method their Gaussian pair sums (weighted by the
+ * multiplicities) come from the spectral route, with the direct fallback
+ * of NCF_AUTO for lags with few pairs. Arrays follow NCF_DEVICE_POINTERS (then t, x, err, sigma, z, mult,
  * lags, c_mean, c_sd and c_rep are device arrays); status is a HOST array.
  *   c_mean, c_sd  K outputs each (NaN where fewer than 1 / 2 replicates
  *                 succeed)

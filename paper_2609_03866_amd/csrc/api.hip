@@ -299,6 +299,9 @@ struct Job {
     std::vector<std::function<int(hipStream_t)>>* rec = nullptr;
     bool plan_build = false;   // statuses are those of the host checks only
     Tune tune;
+    // the caller does not read b (replicates): weighted Gaussian calls may take
+    // the weighted pair sum B from the spectral route
+    bool no_b = false;
     // regular-lattice estimators: lattice step per problem
     bool regular = false;
     std::vector<double> dt;
@@ -891,7 +894,11 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     // Gaussian default: numerator and pair count both by the spectral route
     // (unit-weight channel); lags whose spectral b is small against the
     // reference are re-evaluated by the direct window scan.
-    const bool spec_b = spectral && !rect && J.opt.method == NCF_AUTO && !weighted;
+    // Weighted calls need the unweighted b besides B, so they take the window
+    // scan, unless b is not read (then the channel carries the weights and
+    // yields B; b is reported equal to B).
+    const bool spec_b = spectral && !rect && J.opt.method == NCF_AUTO && (!weighted || J.no_b);
+    const bool spec_w = spec_b && weighted;
     // Mixed: the FP32 transforms leave |dN|, |db| ~ 7e-7 b_ref on every lag, so
     // |dc| ~ 2 * 7e-7 b_ref / b stays below 1e-5 for b >= 0.1 b_ref. FP64: the
     // limit is the 6h truncation of the window scan, whose effect is
@@ -1245,6 +1252,10 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         T.gridb = gridbs[i];
         T.with_b = spec_b ? 1 : 0;
         T.bspec = bspec[i];
+        if (spec_w) {
+            T.w0 = d0.w64;
+            T.w1 = J.ccf ? sdesc[J.set[1].sd0 + P.prob].w64 : nullptr;
+        }
         T.tile0 = ntiles;
         T.ntiles = P.g.N / 4096;
         T.tile_rng = d_rng ? d_rng + kTileRec * ntiles : nullptr;
@@ -1282,7 +1293,8 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             hT.rinfo[6 * i + 1 + q] = lg;
         }
         hT.rinfo[6 * i + 5] = lgN;
-        spread_bytes += (double)(T.n0 + T.n1) * 12.0 + (double)T.N * csz * (two_grids ? 2 : 1);
+        spread_bytes += (double)(T.n0 + T.n1) * (spec_w ? 20.0 : 12.0) +
+                        (double)T.N * csz * (two_grids ? 2 : 1);
     }
     // forward table: per size group, its grids then (CCF with b) its unit grids
     std::vector<std::pair<int, int>> fwd_groups;
@@ -1343,8 +1355,8 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
                 return launch_tile_bounds(stk, dch, nch, smap, s, tb_bytes);
             }));
         NCF_TRY(emit(J, [=](hipStream_t s) {
-            return launch_spread(stk, tile0, nts, ntiles, rec_all, 4096, ccf, spec_b, fp64, s,
-                                 spread_bytes);
+            return launch_spread(stk, tile0, nts, ntiles, rec_all, 4096, ccf, spec_b, spec_w, fp64,
+                                 s, spread_bytes);
         }));
         for (size_t q = 0; q < groups.size(); ++q) {
             const FftPlan fp = plans[splans[groups[q].first].g.N];
@@ -1403,7 +1415,8 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     const int ntw2 = (int)W2.plans.size();
     J.info_window_items += W2.nitems;
     J.info_window_launches += ntw2 > 0 ? 1 : 0;
-    const uint32_t wflags2 = (fp64 ? (uint32_t)WIN_EXP64 : 0u) | (uint32_t)WIN_NUMER;
+    const uint32_t wflags2 = (fp64 ? (uint32_t)WIN_EXP64 : 0u) | (uint32_t)WIN_NUMER |
+                             (weighted ? (uint32_t)WIN_WEIGHTED : 0u);
 
     // fallback workspace and the output tables
     auto layout3 = [&](Arena& ar) {
@@ -2006,6 +2019,7 @@ int resample_impl(bool ccf, const ResampleSet* in, int64_t R, int64_t K, const d
     J.b = brep;
     J.count = nullptr;
     J.status = rstat.data();
+    J.no_b = true;
     NCF_TRY(setup_job(J, ccf, R, offs[0].data(), ccf ? offs[1].data() : nullptr, R * in[0].n,
                       ccf ? R * in[1].n : 0, kern, hs.data(), K, dlags));
     const double* tin[2] = {D[0].t, ccf ? D[1].t : nullptr};
@@ -2696,7 +2710,7 @@ int ncf_diag_type1(int64_t n, const double* t, const double* v, double t_ref, do
     NCF_TRY_HIP(hipMemcpy(dg, &grid, sizeof(void*), hipMemcpyHostToDevice));
     int rc = launch_tile_bounds(dtask, dch, (int)hch.size(), dmap, st, 8.0 * n);
     if (rc == NCF_OK)
-        rc = launch_spread(dtask, dtile0, 1, T.ntiles, rng, 4096, false, false, fp64, st, 0.0);
+        rc = launch_spread(dtask, dtile0, 1, T.ntiles, rng, 4096, false, false, false, fp64, st, 0.0);
     FftPlan plan;
     if (rc == NCF_OK) rc = fft_plan(N, fp64, &plan, st);
     if (rc == NCF_OK) rc = fft_exec(plan, dg, 1, +1, fp64, st);

@@ -286,6 +286,8 @@ struct SpecTask {
     int32_t pad2;
     void* gridb;           // CCF with_b: unit-weight grid (series 1 real, series 2 imaginary)
     double* bspec;         // with_b: K_eval results b(tau)
+    const double* w0;      // with_b, weighted calls: sample weights of set 0 / set 1 spread
+    const double* w1;      //   into the pair-count channel (null: unit weights)
 };
 
 // Spreading tile records: p0, p1 of set 0, p0, p1 of set 1, task index,
@@ -301,9 +303,11 @@ int launch_tile_bounds(const SpecTask* d_tasks, const Chunk* d_chunks, int nchun
 // All tasks of one launch share the mode (ACF/CCF, unit-weight channel).
 // d_tile_rec: the tile records of all tasks (contiguous, in tile order) from
 // launch_tile_bounds, or null to search the ranges in each workgroup.
+// weighted: the pair-count channel (with_b) carries the sample weights, so
+// it yields the weighted pair sum B instead of the unweighted b.
 int launch_spread(const SpecTask* d_tasks, const int64_t* d_tile0, int ntasks, int64_t ntiles,
-                  const int64_t* d_tile_rec, int tile, bool ccf, bool with_b, bool fp64,
-                  hipStream_t st, double bytes);
+                  const int64_t* d_tile_rec, int tile, bool ccf, bool with_b, bool weighted,
+                  bool fp64, hipStream_t st, double bytes);
 int launch_interp(const SpecTask* d_tasks, int ntasks, const int64_t* d_k0, int64_t total_k,
                   bool fp64, hipStream_t st);
 

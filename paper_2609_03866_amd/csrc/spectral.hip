@@ -152,16 +152,19 @@ struct PtsLds {
             int cell[kPtsChunk];  // cell index relative to the tile start
             R frac[kPtsChunk];    // fraction in [0, 1)
             R val[kPtsChunk];
+            R wgt[kPtsChunk];     // sample weights (weighted pair-count channel)
         };
         typename Cplx<R>::T out[kTile / 2 + kTile / 32];
     };
 };
 
-// Accumulate one point set into the thread's 16 cells.
-template <typename R, bool UNIT>
+// Accumulate one point set into the thread's 16 cells. UNIT: also the
+// pair-count channel, with unit weights or (WGT) the sample weights wd.
+template <typename R, bool UNIT, bool WGT>
 __device__ void gather_set(R (&acc)[kCellsPerThread], R (&accu)[kCellsPerThread], PtsLds<R>& P,
-                           const double* t, const float* vf, const double* vd, int64_t p0,
-                           int64_t p1, int64_t c0, double t_ref, double scale, R W, R k2) {
+                           const double* t, const float* vf, const double* vd, const double* wd,
+                           int64_t p0, int64_t p1, int64_t c0, double t_ref, double scale, R W,
+                           R k2) {
     const int tid = threadIdx.x;
     const int cb = tid * kCellsPerThread;  // first own cell, relative to tile
     for (int64_t base = p0; base < p1; base += kPtsChunk) {
@@ -174,6 +177,7 @@ __device__ void gather_set(R (&acc)[kCellsPerThread], R (&accu)[kCellsPerThread]
             P.cell[i] = (int)((int64_t)cf - c0);
             P.frac[i] = (R)(u - cf);
             P.val[i] = vd ? (R)gbl(vd)[base + i] : (R)gbl(vf)[base + i];
+            if (WGT) P.wgt[i] = wd ? (R)gbl(wd)[base + i] : (R)1;
         }
         __syncthreads();
         // first staged point whose cell can reach cell cb: cell >= cb - W - 1
@@ -192,6 +196,7 @@ __device__ void gather_set(R (&acc)[kCellsPerThread], R (&accu)[kCellsPerThread]
             if (ci > need_hi) break;
             const R fr = P.frac[i];
             const R vv = P.val[i];
+            const R ww = WGT ? P.wgt[i] : (R)1;
 #pragma unroll
             for (int q = 0; q < kCellsPerThread; ++q) {
                 const R d = (R)(ci - (cb + q)) + fr;
@@ -202,15 +207,16 @@ __device__ void gather_set(R (&acc)[kCellsPerThread], R (&accu)[kCellsPerThread]
                     else
                         e = exp(d * d * k2);
                     acc[q] += e * vv;
-                    if (UNIT) accu[q] += e;  // unit weights: pair-count channel
+                    if (UNIT) accu[q] += WGT ? e * ww : e;  // pair-count channel
                 }
             }
         }
     }
 }
 
-// MODE: bit 1 CCF (two point sets), bit 0 unit-weight channel; fixed per
-// launch, so accumulators that a mode does not use cost no registers.
+// MODE: bit 1 CCF (two point sets), bit 0 pair-count channel, bit 2 sample
+// weights in that channel; fixed per launch, so accumulators that a mode
+// does not use cost no registers.
 template <typename R, int MODE>
 __global__ void __launch_bounds__(kThreads)
 k_spread(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ tile0, int ntasks,
@@ -218,6 +224,7 @@ k_spread(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ tile0, 
     using C2 = typename Cplx<R>::T;
     constexpr bool CCF = (MODE & 2) != 0;
     constexpr bool WB = (MODE & 1) != 0;
+    constexpr bool WGT = WB && (MODE & 4) != 0;
     __shared__ PtsLds<R> P;
     const int64_t g = blockIdx.x;
     (void)nblocks;
@@ -281,19 +288,19 @@ k_spread(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ tile0, 
     for (int q = 0; q < kCellsPerThread; ++q) re[q] = im[q] = u0[q] = u1[q] = (R)0;
     if constexpr (!CCF) {
         // ACF: values in the real channel, unit weights (with_b) in the imaginary one
-        gather_set<R, WB>(re, im, P, T.t0, T.v0f, T.v0d, rng[0], rng[1], c0, T.t_ref, scale, W,
-                          k2);
+        gather_set<R, WB, WGT>(re, im, P, T.t0, T.v0f, T.v0d, T.w0, rng[0], rng[1], c0, T.t_ref,
+                               scale, W, k2);
     } else if constexpr (WB) {
         // CCF: grid = series 1 values + i series 2 values; gridb = the same with unit weights
-        gather_set<R, true>(re, u0, P, T.t0, T.v0f, T.v0d, rng[0], rng[1], c0, T.t_ref, scale, W,
-                            k2);
-        gather_set<R, true>(im, u1, P, T.t1, T.v1f, T.v1d, rng[2], rng[3], c0, T.t_ref, scale, W,
-                            k2);
+        gather_set<R, true, WGT>(re, u0, P, T.t0, T.v0f, T.v0d, T.w0, rng[0], rng[1], c0, T.t_ref,
+                                 scale, W, k2);
+        gather_set<R, true, WGT>(im, u1, P, T.t1, T.v1f, T.v1d, T.w1, rng[2], rng[3], c0, T.t_ref,
+                                 scale, W, k2);
     } else {
-        gather_set<R, false>(re, u0, P, T.t0, T.v0f, T.v0d, rng[0], rng[1], c0, T.t_ref, scale, W,
-                             k2);
-        gather_set<R, false>(im, u1, P, T.t1, T.v1f, T.v1d, rng[2], rng[3], c0, T.t_ref, scale, W,
-                             k2);
+        gather_set<R, false, false>(re, u0, P, T.t0, T.v0f, T.v0d, nullptr, rng[0], rng[1], c0,
+                                    T.t_ref, scale, W, k2);
+        gather_set<R, false, false>(im, u1, P, T.t1, T.v1f, T.v1d, nullptr, rng[2], rng[3], c0,
+                                    T.t_ref, scale, W, k2);
     }
     // stage the tile through LDS for a coalesced write (two halves, so the
     // staging fits the point buffer); one pad slot per 16 cells keeps the
@@ -603,24 +610,27 @@ int launch_tile_bounds(const SpecTask* d_tasks, const Chunk* d_chunks, int nchun
 template <typename R>
 void (*spread_kernel(int mode))(const SpecTask*, const int64_t*, int, int64_t, int64_t,
                                 const int64_t*) {
-    switch (mode & 3) {
+    switch (mode & 7) {
         case 0: return k_spread<R, 0>;
         case 1: return k_spread<R, 1>;
         case 2: return k_spread<R, 2>;
-        default: return k_spread<R, 3>;
+        case 3: return k_spread<R, 3>;
+        case 5: return k_spread<R, 5>;
+        case 7: return k_spread<R, 7>;
+        default: return nullptr;  // weights without the pair-count channel
     }
 }
 
 int launch_spread(const SpecTask* d_tasks, const int64_t* d_tile0, int ntasks, int64_t ntiles,
-                  const int64_t* d_tile_rec, int tile, bool ccf, bool with_b, bool fp64,
-                  hipStream_t st, double bytes) {
-    if (tile != kTile) {
+                  const int64_t* d_tile_rec, int tile, bool ccf, bool with_b, bool weighted,
+                  bool fp64, hipStream_t st, double bytes) {
+    if (tile != kTile || (weighted && !with_b)) {
         set_error("spread tile mismatch");
         return NCF_E_UNSUPPORTED;
     }
     if (ntiles <= 0) return NCF_OK;
     const int64_t nblocks = round_up(ntiles, kXcds);
-    const int mode = (ccf ? 2 : 0) | (with_b ? 1 : 0);
+    const int mode = (ccf ? 2 : 0) | (with_b ? 1 : 0) | (weighted ? 4 : 0);
     ProfScope p(st, fp64 ? "spread_f64" : "spread_f32", bytes, "bytes");
     if (fp64)
         hipLaunchKernelGGL(spread_kernel<double>(mode), dim3((unsigned)nblocks), dim3(kThreads),
