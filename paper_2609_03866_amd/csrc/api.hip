@@ -894,11 +894,12 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     // Gaussian default: numerator and pair count both by the spectral route
     // (unit-weight channel); lags whose spectral b is small against the
     // reference are re-evaluated by the direct window scan.
-    // Weighted calls need the unweighted b besides B, so they take the window
-    // scan, unless b is not read (then the channel carries the weights and
-    // yields B; b is reported equal to B).
-    const bool spec_b = spectral && !rect && J.opt.method == NCF_AUTO && (!weighted || J.no_b);
+    // Weighted calls: the pair-count channel carries the weights and yields
+    // B; one more channel with unit weights yields the unweighted b, unless
+    // the caller does not read b (then b is reported equal to B).
+    const bool spec_b = spectral && !rect && J.opt.method == NCF_AUTO;
     const bool spec_w = spec_b && weighted;
+    const bool spec_unw = spec_w && !J.no_b;
     // Mixed: the FP32 transforms leave |dN|, |db| ~ 7e-7 b_ref on every lag, so
     // |dc| ~ 2 * 7e-7 b_ref / b stays below 1e-5 for b >= 0.1 b_ref. FP64: the
     // limit is the 6h truncation of the window scan, whose effect is
@@ -1114,11 +1115,16 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     J.info_window_items = W1.nitems;
     J.info_window_launches = ntw > 0 ? 1 : 0;
     const size_t csz = fp64 ? 16 : 8;
-    const bool two_grids = spec_b && J.ccf;
+    // second grid: the CCF pair-count channels, or the ACF unit channel of a
+    // weighted call; third grid: the CCF unit channels of a weighted call
+    const bool two_grids = (spec_b && J.ccf) || spec_unw;
+    const bool three_grids = spec_unw && J.ccf;
+    const int nfwd = 1 + (two_grids ? 1 : 0) + (three_grids ? 1 : 0);
 
     // ------------------------------------------------ phase 2 device workspace
-    std::vector<void*> grids(nts), gridbs(nts, nullptr);
-    std::vector<double*> numer(nts), bspec(nts, nullptr), spart(nts, nullptr);
+    std::vector<void*> grids(nts), gridbs(nts, nullptr), gridcs(nts, nullptr);
+    std::vector<double*> numer(nts), bspec(nts, nullptr), spart(nts, nullptr),
+        bunw(nts, nullptr);
     int64_t ntiles_all = 0;
     for (int i = 0; i < nts; ++i) ntiles_all += splans[i].g.N / 4096;
     // sample ranges of the spreading tiles: one pass over the samples when
@@ -1138,13 +1144,17 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         double* numer_all = ar.take<double>((size_t)std::max(nts, 1) * std::max(Keval, 1));
         double* bspec_all =
             spec_b ? ar.take<double>((size_t)std::max(nts, 1) * std::max(Keval, 1)) : nullptr;
+        double* bunw_all =
+            spec_unw ? ar.take<double>((size_t)std::max(nts, 1) * std::max(Keval, 1)) : nullptr;
         d_rng = (nts > 0 && bounds_pass) ? ar.take<int64_t>(kTileRec * (size_t)ntiles_all)
                                          : nullptr;
         for (int i = 0; i < nts; ++i) {
             grids[i] = ar.take<char>((size_t)splans[i].g.N * csz);
             if (two_grids) gridbs[i] = ar.take<char>((size_t)splans[i].g.N * csz);
+            if (three_grids) gridcs[i] = ar.take<char>((size_t)splans[i].g.N * csz);
             numer[i] = numer_all + (size_t)i * std::max(Keval, 1);
             if (spec_b) bspec[i] = bspec_all + (size_t)i * std::max(Keval, 1);
+            if (spec_unw) bunw[i] = bunw_all + (size_t)i * std::max(Keval, 1);
             if (J.ccf) spart[i] = ar.take<double>(4 * (splans[i].g.N / 4096));
         }
         if (J.dev_ptrs) {
@@ -1192,8 +1202,8 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         dT.smap = tb.take<int32_t>(nsd, &hT.smap);
         dT.rinfo = tb.take<int32_t>(6 * (size_t)nts, &hT.rinfo);
         dT.ev = tb.take<double>(Keval, &hT.ev);
-        dT.gfwd = tb.take<void*>(2 * (size_t)nts, &hT.gfwd);
-        dT.ginv = tb.take<void*>(nts, &hT.ginv);
+        dT.gfwd = tb.take<void*>(3 * (size_t)nts, &hT.gfwd);
+        dT.ginv = tb.take<void*>(2 * (size_t)nts, &hT.ginv);
     };
     Tables t2;
     take2(t2);
@@ -1250,6 +1260,8 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         T.ccf = J.ccf ? 1 : 0;
         T.grid = grids[i];
         T.gridb = gridbs[i];
+        T.gridc = gridcs[i];
+        T.bunw = bunw[i];
         T.with_b = spec_b ? 1 : 0;
         T.bspec = bspec[i];
         if (spec_w) {
@@ -1294,19 +1306,31 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         }
         hT.rinfo[6 * i + 5] = lgN;
         spread_bytes += (double)(T.n0 + T.n1) * (spec_w ? 20.0 : 12.0) +
-                        (double)T.N * csz * (two_grids ? 2 : 1);
+                        (double)T.N * csz * nfwd;
     }
-    // forward table: per size group, its grids then (CCF with b) its unit grids
-    std::vector<std::pair<int, int>> fwd_groups;
+    // forward table: per size group, its grids, then its second grids (CCF
+    // pair-count channels, or the ACF unit channels of a weighted call), then
+    // its third grids (CCF unit channels of a weighted call)
+    std::vector<std::pair<int, int>> fwd_groups, inv_groups;
     {
         int o = 0;
         for (auto& gq : groups) {
-            fwd_groups.push_back({o, gq.second * (two_grids ? 2 : 1)});
+            fwd_groups.push_back({o, gq.second * nfwd});
             for (int i = gq.first; i < gq.first + gq.second; ++i) hT.gfwd[o++] = grids[i];
             if (two_grids)
                 for (int i = gq.first; i < gq.first + gq.second; ++i) hT.gfwd[o++] = gridbs[i];
+            if (three_grids)
+                for (int i = gq.first; i < gq.first + gq.second; ++i) hT.gfwd[o++] = gridcs[i];
         }
-        for (int i = 0; i < nts; ++i) hT.ginv[i] = grids[i];
+        // inverse table: per size group, its grids then (weighted with b) the
+        // b spectra in gridb
+        int oi = 0;
+        for (auto& gq : groups) {
+            inv_groups.push_back({oi, gq.second * (spec_unw ? 2 : 1)});
+            for (int i = gq.first; i < gq.first + gq.second; ++i) hT.ginv[oi++] = grids[i];
+            if (spec_unw)
+                for (int i = gq.first; i < gq.first + gq.second; ++i) hT.ginv[oi++] = gridbs[i];
+        }
     }
     if (nts > 0) {
         hT.tile0[nts] = ntiles;
@@ -1343,7 +1367,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         const SpecTask* stk = dT.st;
         const int64_t *tile0 = dT.tile0, *pos0 = dT.pos0, *sk0 = dT.sk0;
         const int64_t* rinfo = (const int64_t*)dT.rinfo;
-        const double pbytes = (two_grids ? 3.0 : 2.0) * total_pos * csz;
+        const double pbytes = (nfwd + 1.0 + (spec_unw ? 1.0 : 0.0)) * total_pos * csz;
         const int64_t nkeval = (int64_t)nts * Keval;
         const bool ccf = J.ccf;
         const int32_t* smap = dT.smap;
@@ -1355,8 +1379,8 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
                 return launch_tile_bounds(stk, dch, nch, smap, s, tb_bytes);
             }));
         NCF_TRY(emit(J, [=](hipStream_t s) {
-            return launch_spread(stk, tile0, nts, ntiles, rec_all, 4096, ccf, spec_b, spec_w, fp64,
-                                 s, spread_bytes);
+            return launch_spread(stk, tile0, nts, ntiles, rec_all, 4096, ccf, spec_b, spec_w,
+                                 spec_unw, fp64, s, spread_bytes);
         }));
         for (size_t q = 0; q < groups.size(); ++q) {
             const FftPlan fp = plans[splans[groups[q].first].g.N];
@@ -1365,12 +1389,13 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             NCF_TRY(emit(J, [=](hipStream_t s) { return fft_exec(fp, gp, cnt, +1, fp64, s); }));
         }
         NCF_TRY(emit(J, [=](hipStream_t s) {
-            return launch_product(stk, pos0, nts, total_pos, rinfo, ccf, spec_b, fp64, s, pbytes);
+            return launch_product(stk, pos0, nts, total_pos, rinfo, ccf, spec_b, spec_unw, fp64, s,
+                                  pbytes);
         }));
-        for (auto& gq : groups) {
-            const FftPlan fp = plans[splans[gq.first].g.N];
-            void* const* gp = dT.ginv + gq.first;
-            const int cnt = gq.second;
+        for (size_t q = 0; q < groups.size(); ++q) {
+            const FftPlan fp = plans[splans[groups[q].first].g.N];
+            void* const* gp = dT.ginv + inv_groups[q].first;
+            const int cnt = inv_groups[q].second;
             NCF_TRY(emit(J, [=](hipStream_t s) { return fft_exec(fp, gp, cnt, -1, fp64, s); }));
         }
         NCF_TRY(emit(J, [=](hipStream_t s) { return launch_interp(stk, nts, sk0, nkeval, fp64, s); }));
@@ -1523,6 +1548,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
                     const int i = spec_of[p];
                     T.numer = numer[i];
                     T.bspec = bspec[i];
+                    T.bunw = bunw[i];
                     T.scale_part = spart[i];
                     T.nscale_part = splans[i].g.N / 4096;
                 }
@@ -2710,7 +2736,8 @@ int ncf_diag_type1(int64_t n, const double* t, const double* v, double t_ref, do
     NCF_TRY_HIP(hipMemcpy(dg, &grid, sizeof(void*), hipMemcpyHostToDevice));
     int rc = launch_tile_bounds(dtask, dch, (int)hch.size(), dmap, st, 8.0 * n);
     if (rc == NCF_OK)
-        rc = launch_spread(dtask, dtile0, 1, T.ntiles, rng, 4096, false, false, false, fp64, st, 0.0);
+        rc = launch_spread(dtask, dtile0, 1, T.ntiles, rng, 4096, false, false, false, false, fp64,
+                           st, 0.0);
     FftPlan plan;
     if (rc == NCF_OK) rc = fft_plan(N, fp64, &plan, st);
     if (rc == NCF_OK) rc = fft_exec(plan, dg, 1, +1, fp64, st);

@@ -288,6 +288,11 @@ struct SpecTask {
     double* bspec;         // with_b: K_eval results b(tau)
     const double* w0;      // with_b, weighted calls: sample weights of set 0 / set 1 spread
     const double* w1;      //   into the pair-count channel (null: unit weights)
+    // weighted calls that also need the unweighted pair count b: one more
+    // channel with unit weights (ACF: gridb; CCF: gridc); after the product
+    // gridb holds the spectrum of b and bunw receives b(tau) at the lags
+    void* gridc;
+    double* bunw;
 };
 
 // Spreading tile records: p0, p1 of set 0, p0, p1 of set 1, task index,
@@ -304,10 +309,11 @@ int launch_tile_bounds(const SpecTask* d_tasks, const Chunk* d_chunks, int nchun
 // d_tile_rec: the tile records of all tasks (contiguous, in tile order) from
 // launch_tile_bounds, or null to search the ranges in each workgroup.
 // weighted: the pair-count channel (with_b) carries the sample weights, so
-// it yields the weighted pair sum B instead of the unweighted b.
+// it yields the weighted pair sum B instead of the unweighted b; unw: one
+// more channel with unit weights for b (SpecTask::gridc / gridb).
 int launch_spread(const SpecTask* d_tasks, const int64_t* d_tile0, int ntasks, int64_t ntiles,
                   const int64_t* d_tile_rec, int tile, bool ccf, bool with_b, bool weighted,
-                  bool fp64, hipStream_t st, double bytes);
+                  bool unw, bool fp64, hipStream_t st, double bytes);
 int launch_interp(const SpecTask* d_tasks, int ntasks, const int64_t* d_k0, int64_t total_k,
                   bool fp64, hipStream_t st);
 
@@ -345,9 +351,11 @@ int64_t fft_position(const FftPlan& plan, int64_t k);
 // A5 spectral product (in place, digit-reversed order)
 // All tasks of one launch share the mode: ACF or CCF, with or without the
 // unit-weight (pair-count) channel.
+// unw: the unit channel (gridb for the ACF, gridc for the CCF) also gives the
+// spectrum of the unweighted pair count, written to gridb.
 int launch_product(const SpecTask* d_tasks, const int64_t* d_pos0, int ntasks, int64_t total,
-                   const int64_t* d_radix_info, bool ccf, bool with_b, bool fp64, hipStream_t st,
-                   double bytes);
+                   const int64_t* d_radix_info, bool ccf, bool with_b, bool unw, bool fp64,
+                   hipStream_t st, double bytes);
 
 // ------------------------------------------- regular-lattice estimators
 // Series whose times sit on a common lattice t_ref + m dt: the pair lags are
@@ -418,7 +426,9 @@ struct NormTask {
     int32_t spectral;     // numerator from the spectral route
     int32_t spec_b;       // pair counts from the spectral route too (else window sums)
     int32_t pad3;
-    const double* bspec;  // spectral b per requested lag (+ lag 0 last for ACF)
+    const double* bspec;  // spectral b per requested lag (+ lag 0 last for ACF); with
+                          // weights the weighted pair sum B
+    const double* bunw;   // weighted calls: spectral unweighted b per lag, or null
     const int32_t* fb_row;  // requested lag -> row of the direct fallback sums, -1 if none
     const double* fb_sums;  // direct window sums [rows][4] of the fallback lags
     double beta;          // fallback threshold (window-b path): b < beta * b_ref

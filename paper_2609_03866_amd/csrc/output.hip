@@ -128,7 +128,7 @@ k_normalize(const NormTask* __restrict__ tasks, const IoBlock* __restrict__ io) 
         } else if (T.spectral && T.spec_b) {
             num = T.numer[k];
             den = T.bspec[k];
-            bout = T.bspec[k];
+            bout = T.bunw ? T.bunw[k] : T.bspec[k];
         } else {
             const double* w = T.wsums + 4 * (int64_t)T.perm[k];
             // an empty window has numerator exactly 0; a window with few

@@ -159,12 +159,13 @@ struct PtsLds {
 };
 
 // Accumulate one point set into the thread's 16 cells. UNIT: also the
-// pair-count channel, with unit weights or (WGT) the sample weights wd.
-template <typename R, bool UNIT, bool WGT>
-__device__ void gather_set(R (&acc)[kCellsPerThread], R (&accu)[kCellsPerThread], PtsLds<R>& P,
-                           const double* t, const float* vf, const double* vd, const double* wd,
-                           int64_t p0, int64_t p1, int64_t c0, double t_ref, double scale, R W,
-                           R k2) {
+// pair-count channel, with unit weights or (WGT) the sample weights wd;
+// UNW (with WGT): a third channel with unit weights.
+template <typename R, bool UNIT, bool WGT, bool UNW>
+__device__ void gather_set(R (&acc)[kCellsPerThread], R (&accu)[kCellsPerThread],
+                           R (&accn)[kCellsPerThread], PtsLds<R>& P, const double* t,
+                           const float* vf, const double* vd, const double* wd, int64_t p0,
+                           int64_t p1, int64_t c0, double t_ref, double scale, R W, R k2) {
     const int tid = threadIdx.x;
     const int cb = tid * kCellsPerThread;  // first own cell, relative to tile
     for (int64_t base = p0; base < p1; base += kPtsChunk) {
@@ -208,6 +209,7 @@ __device__ void gather_set(R (&acc)[kCellsPerThread], R (&accu)[kCellsPerThread]
                         e = exp(d * d * k2);
                     acc[q] += e * vv;
                     if (UNIT) accu[q] += WGT ? e * ww : e;  // pair-count channel
+                    if (UNW) accn[q] += e;                  // unweighted pair count
                 }
             }
         }
@@ -215,8 +217,12 @@ __device__ void gather_set(R (&acc)[kCellsPerThread], R (&accu)[kCellsPerThread]
 }
 
 // MODE: bit 1 CCF (two point sets), bit 0 pair-count channel, bit 2 sample
-// weights in that channel; fixed per launch, so accumulators that a mode
-// does not use cost no registers.
+// weights in that channel, bit 3 (with bits 0 and 2) one more channel with
+// unit weights for the unweighted pair count; fixed per launch, so
+// accumulators that a mode does not use cost no registers.
+//   ACF: grid = values + i (weights or units); bit 3: gridb = units
+//   CCF: grid = x values + i y values; gridb = pair-count channels of x and
+//        y; bit 3: gridc = unit channels of x and y
 template <typename R, int MODE>
 __global__ void __launch_bounds__(kThreads)
 k_spread(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ tile0, int ntasks,
@@ -225,6 +231,9 @@ k_spread(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ tile0, 
     constexpr bool CCF = (MODE & 2) != 0;
     constexpr bool WB = (MODE & 1) != 0;
     constexpr bool WGT = WB && (MODE & 4) != 0;
+    constexpr bool UNW = WGT && (MODE & 8) != 0;
+    // grids written: grid, gridb (CCF pair channels or ACF units), gridc
+    constexpr int ngrids = CCF ? 1 + (WB ? 1 : 0) + (UNW ? 1 : 0) : 1 + (UNW ? 1 : 0);
     __shared__ PtsLds<R> P;
     const int64_t g = blockIdx.x;
     (void)nblocks;
@@ -271,9 +280,9 @@ k_spread(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ tile0, 
     // a tile no sample reaches (lag padding, seasonal gaps): coalesced zeros,
     // no staging
     if (rng[0] >= rng[1] && rng[2] >= rng[3]) {
-        constexpr int ngz = (CCF && WB) ? 2 : 1;
-        for (int gsel = 0; gsel < ngz; ++gsel) {
-            const gptr<R> grid = gbl(reinterpret_cast<R*>(gsel == 0 ? T.grid : T.gridb) + 2 * c0);
+        for (int gsel = 0; gsel < ngrids; ++gsel) {
+            void* gp = gsel == 0 ? T.grid : gsel == 1 ? T.gridb : T.gridc;
+            const gptr<R> grid = gbl(reinterpret_cast<R*>(gp) + 2 * c0);
             for (int i = threadIdx.x; i < 2 * kTile; i += kThreads) grid[i] = (R)0;
         }
         return;
@@ -284,23 +293,26 @@ k_spread(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ tile0, 
     const R k2 = sizeof(R) == 4 ? (R)(-0.72134752044448170 / (T.s * T.s))
                                 : (R)(-0.5 / (T.s * T.s));
     R re[kCellsPerThread], im[kCellsPerThread], u0[kCellsPerThread], u1[kCellsPerThread];
+    R n0[kCellsPerThread], n1[kCellsPerThread];
 #pragma unroll
-    for (int q = 0; q < kCellsPerThread; ++q) re[q] = im[q] = u0[q] = u1[q] = (R)0;
+    for (int q = 0; q < kCellsPerThread; ++q) re[q] = im[q] = u0[q] = u1[q] = n0[q] = n1[q] = (R)0;
     if constexpr (!CCF) {
-        // ACF: values in the real channel, unit weights (with_b) in the imaginary one
-        gather_set<R, WB, WGT>(re, im, P, T.t0, T.v0f, T.v0d, T.w0, rng[0], rng[1], c0, T.t_ref,
-                               scale, W, k2);
+        // ACF: values in the real channel, pair-count weights (with_b) in the
+        // imaginary one, units in n0 (UNW)
+        gather_set<R, WB, WGT, UNW>(re, im, n0, P, T.t0, T.v0f, T.v0d, T.w0, rng[0], rng[1], c0,
+                                    T.t_ref, scale, W, k2);
     } else if constexpr (WB) {
-        // CCF: grid = series 1 values + i series 2 values; gridb = the same with unit weights
-        gather_set<R, true, WGT>(re, u0, P, T.t0, T.v0f, T.v0d, T.w0, rng[0], rng[1], c0, T.t_ref,
-                                 scale, W, k2);
-        gather_set<R, true, WGT>(im, u1, P, T.t1, T.v1f, T.v1d, T.w1, rng[2], rng[3], c0, T.t_ref,
-                                 scale, W, k2);
+        // CCF: grid = series 1 values + i series 2 values; gridb = the same
+        // with the pair-count weights; gridc = units (UNW)
+        gather_set<R, true, WGT, UNW>(re, u0, n0, P, T.t0, T.v0f, T.v0d, T.w0, rng[0], rng[1],
+                                      c0, T.t_ref, scale, W, k2);
+        gather_set<R, true, WGT, UNW>(im, u1, n1, P, T.t1, T.v1f, T.v1d, T.w1, rng[2], rng[3],
+                                      c0, T.t_ref, scale, W, k2);
     } else {
-        gather_set<R, false, false>(re, u0, P, T.t0, T.v0f, T.v0d, nullptr, rng[0], rng[1], c0,
-                                    T.t_ref, scale, W, k2);
-        gather_set<R, false, false>(im, u1, P, T.t1, T.v1f, T.v1d, nullptr, rng[2], rng[3], c0,
-                                    T.t_ref, scale, W, k2);
+        gather_set<R, false, false, false>(re, u0, n0, P, T.t0, T.v0f, T.v0d, nullptr, rng[0],
+                                           rng[1], c0, T.t_ref, scale, W, k2);
+        gather_set<R, false, false, false>(im, u1, n1, P, T.t1, T.v1f, T.v1d, nullptr, rng[2],
+                                           rng[3], c0, T.t_ref, scale, W, k2);
     }
     // stage the tile through LDS for a coalesced write (two halves, so the
     // staging fits the point buffer); one pad slot per 16 cells keeps the
@@ -308,9 +320,9 @@ k_spread(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ tile0, 
     static_assert(sizeof(PtsLds<R>) >= sizeof(C2) * (kTile / 2 + kTile / 32),
                   "LDS staging too small");
     C2* out = P.out;
-    constexpr int ngrids = (CCF && WB) ? 2 : 1;
     for (int gsel = 0; gsel < ngrids; ++gsel) {
-        const gptr<R> grid = gbl(reinterpret_cast<R*>(gsel == 0 ? T.grid : T.gridb) + 2 * c0);
+        void* gp = gsel == 0 ? T.grid : gsel == 1 ? T.gridb : T.gridc;
+        const gptr<R> grid = gbl(reinterpret_cast<R*>(gp) + 2 * c0);
         for (int half = 0; half < 2; ++half) {
             __syncthreads();
             const int hbase = half * (kTile / 2);
@@ -319,8 +331,16 @@ k_spread(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ tile0, 
 #pragma unroll
                 for (int q = 0; q < kCellsPerThread; ++q) {
                     C2 v;
-                    v.x = gsel == 0 ? re[q] : u0[q];
-                    v.y = gsel == 0 ? im[q] : u1[q];
+                    if (gsel == 0) {
+                        v.x = re[q];
+                        v.y = im[q];
+                    } else if (CCF && gsel == 1) {
+                        v.x = u0[q];
+                        v.y = u1[q];
+                    } else {  // units: ACF gridb, CCF gridc
+                        v.x = n0[q];
+                        v.y = CCF ? n1[q] : (R)0;
+                    }
                     out[tb + q + (tb >> 4)] = v;
                 }
             }
@@ -371,6 +391,7 @@ template <typename R>
 struct ProductCtx {
     gptr<R> Z;
     gptr<R> U;
+    gptr<R> C;  // unit channel of a weighted CCF (gridc)
     int64_t N, M;
     double L, h, s;
     int32_t kern;
@@ -379,12 +400,13 @@ struct ProductCtx {
 // Product at one owned position p (partner pp = position of -k); z*/u* are
 // the values loaded at p and pp. Writes Z[p] (and Z[pp]) and adds the lag-0
 // partial sums.
-template <typename R, bool CCF, bool WB>
-__device__ __forceinline__ void product_item(const ProductCtx<R>& X, const RadixInfo& ri,
-                                             int64_t p, int64_t pp, typename Cplx<R>::T a,
-                                             typename Cplx<R>::T b, typename Cplx<R>::T va,
-                                             typename Cplx<R>::T vb, double (&sacc)[4]) {
-    using C2 = typename Cplx<R>::T;
+// The per-mode factors at the frequency of position p: f3 = phihat(m/L) /
+// (L Psi^3) for the product spectra and f2 = phihat(m/L) / (L Psi^2) for the
+// CCF lag-0 sums, with Psi(m/N) = sqrt(2 pi) s exp(-2 pi^2 s^2 m^2 / N^2);
+// both zero beyond the retained modes.
+template <typename R, bool CCF>
+__device__ __forceinline__ void product_factors(const ProductCtx<R>& X, const RadixInfo& ri,
+                                                int64_t p, double& f3, double& f2) {
     const int64_t N = X.N;
     const int64_t k = freq_of_pos(p, ri);
     const int64_t m = k <= N / 2 ? k : k - N;
@@ -392,10 +414,9 @@ __device__ __forceinline__ void product_item(const ProductCtx<R>& X, const Radix
     const double Nd = (double)N;
     const double L = X.L, h = X.h, s = X.s;
     const bool keep = (m <= X.M && m >= -X.M);
-    // phihat(m/L) / (L Psi^3) and phihat(m/L) / (L Psi^2) with
-    // Psi(m/N) = sqrt(2 pi) s exp(-2 pi^2 s^2 m^2 / N^2)
     const double a_psi = 2.0 * M_PI * M_PI * s * s * md * md / (Nd * Nd);
-    double f3 = 0.0, f2 = 0.0;
+    f3 = 0.0;
+    f2 = 0.0;
     if (keep) {
         const double c3 = 1.0 / (L * 15.749609945722419 * s * s * s);
         const double c2 = 1.0 / (L * 6.283185307179586 * s * s);
@@ -414,6 +435,16 @@ __device__ __forceinline__ void product_item(const ProductCtx<R>& X, const Radix
             f2 = c2 * ker * exp(2.0 * a_psi);
         }
     }
+}
+
+template <typename R, bool CCF, bool WB>
+__device__ __forceinline__ void product_item(const ProductCtx<R>& X, const RadixInfo& ri,
+                                             int64_t p, int64_t pp, typename Cplx<R>::T a,
+                                             typename Cplx<R>::T b, typename Cplx<R>::T va,
+                                             typename Cplx<R>::T vb, double (&sacc)[4]) {
+    using C2 = typename Cplx<R>::T;
+    double f3, f2;
+    product_factors<R, CCF>(X, ri, p, f3, f2);
     if (!CCF && !WB) {
         const double pw = (double)a.x * a.x + (double)a.y * a.y;
         C2 o;
@@ -464,6 +495,35 @@ __device__ __forceinline__ void product_item(const ProductCtx<R>& X, const Radix
     if (pp != p) cst(X.Z, pp, oc);
 }
 
+// Unweighted pair-count spectrum of a weighted call from its unit channel
+// (values c at p and d at pp): ACF gridb = units + i 0, |U|^2; CCF gridc =
+// x units + i y units, conj(U_x) U_y. Written to gridb (X.U) as G_b at p
+// and conj(G_b) at pp, after the thread's loads of gridb.
+template <typename R, bool CCF>
+__device__ __forceinline__ void unit_item(const ProductCtx<R>& X, const RadixInfo& ri, int64_t p,
+                                          int64_t pp, typename Cplx<R>::T c,
+                                          typename Cplx<R>::T d) {
+    using C2 = typename Cplx<R>::T;
+    double f3, f2;
+    product_factors<R, false>(X, ri, p, f3, f2);
+    C2 o, oc;
+    if (!CCF) {
+        const double ur = 0.5 * ((double)c.x + d.x), ui = 0.5 * ((double)c.y - d.y);
+        o.x = (R)(f3 * (ur * ur + ui * ui));
+        o.y = (R)0;
+        oc = o;
+    } else {
+        const double xr = 0.5 * ((double)c.x + d.x), xi = 0.5 * ((double)c.y - d.y);
+        const double yr = 0.5 * ((double)c.y + d.y), yi = -0.5 * ((double)c.x - d.x);
+        o.x = (R)(f3 * (xr * yr + xi * yi));
+        o.y = (R)(f3 * (xr * yi - xi * yr));
+        oc.x = o.x;
+        oc.y = -o.y;
+    }
+    cst(X.U, p, o);
+    if (pp != p) cst(X.U, pp, oc);
+}
+
 // In-place product on the digit-reversed spectrum. Without the unit-weight
 // channel: ACF -> phihat |X|^2 / (L Psi^3); CCF -> phihat conj(X) Y / (L Psi^3)
 // after unpacking X, Y from the packed grid. With it (with_b) the same
@@ -486,6 +546,7 @@ k_product(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pos0, 
     const int64_t N = T.N;
     const gptr<R> Z = gbl(reinterpret_cast<R*>(T.grid));
     const gptr<R> U = gbl(reinterpret_cast<R*>(T.gridb));
+    const gptr<R> Cg = gbl(reinterpret_cast<R*>(T.gridc));
     double sacc[4] = {0.0, 0.0, 0.0, 0.0};
     // Each (m, -m) pair is handled by the thread that owns the position of
     // its frequency k in [0, N/2]. The top bit of k is bit 11 of the position
@@ -495,14 +556,15 @@ k_product(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pos0, 
     // pairs are disjoint, so nothing is read after being written.
     constexpr bool CCF = (MODE & 2) != 0;
     constexpr bool WB = (MODE & 1) != 0;
+    constexpr bool UNW = WB && (MODE & 4) != 0;  // unweighted pair count of a weighted call
     constexpr bool two = CCF || WB;    // pairs (m, -m) needed
-    constexpr bool unit = CCF && WB;   // second (unit-weight) grid
+    constexpr bool unit = CCF && WB;   // second (pair-count) grid of a CCF
     const int64_t tb = gb - T.pos0;    // first position of the tile in its grid
     constexpr int kIt = kTile / 2 / kThreads;
-    const ProductCtx<R> X{Z, U, N, T.M, T.L, T.h, T.s, T.kern};
+    const ProductCtx<R> X{Z, U, Cg, N, T.M, T.L, T.h, T.s, T.kern};
     for (int half = 0; half < (two ? 1 : 2); ++half) {
         int64_t pb[kIt];
-        C2 za[kIt], zb[kIt], ua[kIt], ub[kIt];
+        C2 za[kIt], zb[kIt], ua[kIt], ub[kIt], na[kIt], nb[kIt];
         const int64_t p0 = tb + half * (kTile / 2) + threadIdx.x;
 #pragma unroll
         for (int it = 0; it < kIt; ++it) {
@@ -516,12 +578,17 @@ k_product(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pos0, 
                 ua[it] = cld<C2>(U, p);
                 ub[it] = cld<C2>(U, pb[it]);
             }
+            if constexpr (UNW) {  // unit channel: ACF gridb, CCF gridc
+                na[it] = cld<C2>(CCF ? Cg : U, p);
+                nb[it] = cld<C2>(CCF ? Cg : U, pb[it]);
+            }
         }
 #pragma unroll
         for (int it = 0; it < kIt; ++it) {
             const int64_t p = p0 + it * kThreads;
             product_item<R, CCF, WB>(X, ri, p, two ? pb[it] : p, za[it], two ? zb[it] : za[it],
                                      unit ? ua[it] : za[it], unit ? ub[it] : za[it], sacc);
+            if constexpr (UNW) unit_item<R, CCF>(X, ri, p, pb[it], na[it], nb[it]);
         }
     }
     if (two && tb == 0 && threadIdx.x == 0) {  // k = N/2, its own partner
@@ -529,7 +596,13 @@ k_product(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pos0, 
         const int64_t pp = pos_of_freq((N - freq_of_pos(p, ri)) & (N - 1), ri);
         const C2 a = cld<C2>(Z, p), b = cld<C2>(Z, pp);
         const C2 c = unit ? cld<C2>(U, p) : a, d = unit ? cld<C2>(U, pp) : a;
+        C2 e = a, f = a;
+        if (UNW) {
+            e = cld<C2>(CCF ? Cg : U, p);
+            f = cld<C2>(CCF ? Cg : U, pp);
+        }
         product_item<R, CCF, WB>(X, ri, p, pp, a, b, c, d, sacc);
+        if (UNW) unit_item<R, CCF>(X, ri, p, pp, e, f);
     }
     if (CCF) {
 #pragma unroll
@@ -569,9 +642,10 @@ __global__ void k_interp(const SpecTask* __restrict__ tasks, int ntasks, const i
     const double fr = u - cf;
     const int64_t cell = (int64_t)cf;
     const C2* G = reinterpret_cast<const C2*>(T.grid);
+    const C2* Gb = reinterpret_cast<const C2*>(T.gridb);  // b spectrum (weighted calls)
     const int wi = (int)ceil(T.W);
     const double kk = -0.5 / (T.s * T.s);
-    double acc = 0.0, accb = 0.0;
+    double acc = 0.0, accb = 0.0, accn = 0.0;
     for (int q = -wi - 1; q <= wi + 1; ++q) {
         const double d = fr - (double)q;  // u - (cell + q)
         if (d > T.W || d < -T.W) continue;
@@ -580,9 +654,11 @@ __global__ void k_interp(const SpecTask* __restrict__ tasks, int ntasks, const i
         const C2 gv = G[c];
         acc += (double)gv.x * wgt;
         accb += (double)gv.y * wgt;
+        if (T.bunw) accn += (double)Gb[c].x * wgt;
     }
     T.numer[k] = acc;
     if (T.with_b) T.bspec[k] = accb;
+    if (T.bunw) T.bunw[k] = accn;
 }
 
 }  // namespace
@@ -610,27 +686,29 @@ int launch_tile_bounds(const SpecTask* d_tasks, const Chunk* d_chunks, int nchun
 template <typename R>
 void (*spread_kernel(int mode))(const SpecTask*, const int64_t*, int, int64_t, int64_t,
                                 const int64_t*) {
-    switch (mode & 7) {
+    switch (mode & 15) {
         case 0: return k_spread<R, 0>;
         case 1: return k_spread<R, 1>;
         case 2: return k_spread<R, 2>;
         case 3: return k_spread<R, 3>;
         case 5: return k_spread<R, 5>;
         case 7: return k_spread<R, 7>;
-        default: return nullptr;  // weights without the pair-count channel
+        case 13: return k_spread<R, 13>;
+        case 15: return k_spread<R, 15>;
+        default: return nullptr;  // weights or units without the pair-count channel
     }
 }
 
 int launch_spread(const SpecTask* d_tasks, const int64_t* d_tile0, int ntasks, int64_t ntiles,
                   const int64_t* d_tile_rec, int tile, bool ccf, bool with_b, bool weighted,
-                  bool fp64, hipStream_t st, double bytes) {
-    if (tile != kTile || (weighted && !with_b)) {
+                  bool unw, bool fp64, hipStream_t st, double bytes) {
+    if (tile != kTile || (weighted && !with_b) || (unw && !weighted)) {
         set_error("spread tile mismatch");
         return NCF_E_UNSUPPORTED;
     }
     if (ntiles <= 0) return NCF_OK;
     const int64_t nblocks = round_up(ntiles, kXcds);
-    const int mode = (ccf ? 2 : 0) | (with_b ? 1 : 0) | (weighted ? 4 : 0);
+    const int mode = (ccf ? 2 : 0) | (with_b ? 1 : 0) | (weighted ? 4 : 0) | (unw ? 8 : 0);
     ProfScope p(st, fp64 ? "spread_f64" : "spread_f32", bytes, "bytes");
     if (fp64)
         hipLaunchKernelGGL(spread_kernel<double>(mode), dim3((unsigned)nblocks), dim3(kThreads),
@@ -645,20 +723,27 @@ int launch_spread(const SpecTask* d_tasks, const int64_t* d_tile0, int ntasks, i
 template <typename R>
 void (*product_kernel(int mode))(const SpecTask*, const int64_t*, int, int64_t,
                                   const RadixInfo*) {
-    switch (mode & 3) {
+    switch (mode & 7) {
         case 0: return k_product<R, 0>;
         case 1: return k_product<R, 1>;
         case 2: return k_product<R, 2>;
-        default: return k_product<R, 3>;
+        case 3: return k_product<R, 3>;
+        case 5: return k_product<R, 5>;
+        case 7: return k_product<R, 7>;
+        default: return nullptr;  // a unit channel needs the pair-count channel
     }
 }
 
 int launch_product(const SpecTask* d_tasks, const int64_t* d_pos0, int ntasks, int64_t total,
-                   const int64_t* d_radix_info, bool ccf, bool with_b, bool fp64, hipStream_t st,
-                   double bytes) {
+                   const int64_t* d_radix_info, bool ccf, bool with_b, bool unw, bool fp64,
+                   hipStream_t st, double bytes) {
     if (total <= 0) return NCF_OK;
+    if (unw && !with_b) {
+        set_error("product: unit channel without the pair-count channel");
+        return NCF_E_UNSUPPORTED;
+    }
     const RadixInfo* ri = reinterpret_cast<const RadixInfo*>(d_radix_info);
-    const int mode = (ccf ? 2 : 0) | (with_b ? 1 : 0);
+    const int mode = (ccf ? 2 : 0) | (with_b ? 1 : 0) | (unw ? 4 : 0);
     ProfScope p(st, fp64 ? "product_f64" : "product_f32", bytes, "bytes");
     if (fp64)
         hipLaunchKernelGGL(product_kernel<double>(mode), dim3((unsigned)ceil_div(total, kTile)),

@@ -111,6 +111,9 @@ def test_ties_negative_repeated_unsorted_lags():
 
 
 def test_weighted_mode_matches_oracle():
+    # Gaussian with errors: spectral numerator, weighted pair sum B (weights
+    # channel) and unweighted b (unit channel), direct fallback where B is
+    # small; tolerances of the unweighted auto path
     d = synth.small("c4", seed=2)
     i0, i1 = d["offs"][3], d["offs"][4]
     t, x, e = d["t"][i0:i1], d["x"][i0:i1], d["err_values"][i0:i1]
@@ -118,8 +121,40 @@ def test_weighted_mode_matches_oracle():
     for kern in ("gaussian", "rectangle"):
         st, oc, ob, on = O.acf(t, x, lags, kern, 0.5, err=e)
         assert st == 0
-        c, b, n, _ = ncf.acf(t, x, lags, kern, 0.5, err=e)
-        _check(c, b, n, oc, ob, on, kern, 1e-5 if kern == "gaussian" else 1e-9, 1e-6)
+        for prec, ctol, btol in (("mixed", 1e-5, ("ref", 1e-5)), ("fp64", 5e-8, 2e-8)):
+            c, b, n, _ = ncf.acf(t, x, lags, kern, 0.5, err=e, precision=prec)
+            if kern == "rectangle":
+                ctol = 1e-9
+            _check(c, b, n, oc, ob, on, kern, ctol, btol)
+
+
+@pytest.mark.parametrize("prec,ctol,btol", [("mixed", 1e-5, ("ref", 1e-5)),
+                                            ("fp64", 5e-8, 2e-8)])
+@pytest.mark.parametrize("which", ["both", "x", "y"])
+def test_weighted_ccf_gaussian(which, prec, ctol, btol):
+    d = synth.small("c2", seed=5)
+    rng = synth.rng_for(6)
+    ex = rng.uniform(0.5, 2.0, d["t"].size) if which in ("both", "x") else None
+    ey = rng.uniform(0.5, 2.0, d["s"].size) if which in ("both", "y") else None
+    st, oc, ob, on = O.ccf(d["t"], d["x"], d["s"], d["y"], d["lags"], "gaussian", d["h"],
+                           ex=ex, ey=ey)
+    assert st == 0
+    c, b, n, _ = ncf.ccf(d["t"], d["x"], d["s"], d["y"], d["lags"], "gaussian", d["h"], ex=ex,
+                         ey=ey, precision=prec)
+    _check(c, b, n, oc, ob, on, "gaussian", ctol, btol)
+
+
+def test_weighted_batch_gaussian():
+    d = synth.small("c4", seed=3)
+    offs, t, x, e = d["offs"], d["t"], d["x"], d["err_values"]
+    lags = d["lags"]
+    c, b, n, st, rc = ncf.acf_batch(offs, t, x, lags, "gaussian", d["h"], err=e)
+    assert rc == 0
+    for i in range(offs.size - 1):
+        sl = slice(offs[i], offs[i + 1])
+        s_, oc, ob, on = O.acf(t[sl], x[sl], lags, "gaussian", d["h"][i], err=e[sl])
+        assert s_ == 0
+        _check(c[i], b[i], n[i], oc, ob, on, "gaussian", 1e-5, ("ref", 1e-5))
 
 
 def test_status_codes_on_gpu():
