@@ -56,6 +56,8 @@ def make_workload(name):
         return [synth.c3()]
     if name == "c4":
         return [synth.c4()]
+    if name == "c4w":
+        return [synth.c4(with_err=True)]
     if name == "c5":
         return [synth.c5()]
     if name == "r1":
@@ -485,6 +487,7 @@ def main():
                         "c2": "ccf_n1e5x2_K401_gauss+rect_mixed",
                         "c3": "acf_n1e7_K4096_gauss_mixed",
                         "c4": "acf_batch_10000_curves_K256_gauss_mixed",
+                        "c4w": "acf_batch_10000_curves_K256_gauss_mixed_weighted_by_errors",
                         "c5": "ccf_batch_2048_pairs_K512_rect_mixed",
                         "r1": "acf_regular_n256000_K366_gauss+rect_fp64",
                         "r2": "acf_regular_batch_4096_K366_rect_fp64",
