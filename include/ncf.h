@@ -79,11 +79,13 @@ typedef enum { NCF_GAUSSIAN = 0, NCF_RECTANGLE = 1 } ncf_kernel_t;
 typedef enum { NCF_MIXED = 0, NCF_FP64 = 1 } ncf_precision_t;
 
 /* NCF_AUTO: Gaussian numerator by the spectral (Wiener-Khinchin + NUFFT)
- *   route (Sec. 2.6). Without errors the Gaussian pair count b takes the
- *   same route with unit values, and lags whose spectral b falls below a
- *   fraction beta of the reference (b(0) for the ACF, the largest requested
- *   lag's b for the CCF; beta = 0.1 mixed, 0.01 FP64) are summed directly by
- *   the window scan. With errors, b comes from the window scan. Rectangle:
+ *   route (Sec. 2.6), unless the call is small enough that the direct window
+ *   sums cost less (then as NCF_DIRECT; see NCF_SPECTRAL_ALWAYS). The Gaussian
+ *   pair count b takes the same route with unit values (with errors: the
+ *   weighted pair sum B with the weights, and b with unit values), and lags
+ *   whose spectral b (B) falls below a fraction beta of the reference (b(0)
+ *   for the ACF, the largest requested lag's b for the CCF; beta = 0.1 mixed,
+ *   0.01 FP64) are summed directly by the window scan. Rectangle:
  *   numerator by prefix sums over the window (Algorithm "CorrSum,
  *   rectangle") and exact pair counts from the window scan.
  * NCF_SPECTRAL: Gaussian numerator by the spectral route, pair counts by the
@@ -108,6 +110,11 @@ typedef enum { NCF_AUTO = 0, NCF_SPECTRAL = 1, NCF_DIRECT = 2 } ncf_method_t;
  * fastest. Results may differ from an untuned plan at the rounding level
  * (another grid size or FFT order); building takes several plan builds. */
 #define NCF_PLAN_AUTOTUNE 0x8u
+/* NCF_AUTO with the Gaussian kernel normally picks, per call, the direct
+ * window sums when their estimated work is below the spectral pipeline's
+ * (small problems; the paper's K* crossover). With this flag it always takes
+ * the spectral route. */
+#define NCF_SPECTRAL_ALWAYS 0x10u
 
 typedef struct {
     uint32_t struct_size; /* sizeof(ncf_options_t) */

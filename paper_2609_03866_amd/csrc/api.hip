@@ -715,7 +715,7 @@ int run_regular(Job& J, const std::vector<SeriesDesc>& sdesc,
 int run_job(Job& J, const double* const* tin, const double* const* xin,
             const double* const* ein) {
     const bool fp64 = J.opt.precision == NCF_FP64;
-    const bool spectral = use_spectral(J);
+    bool spectral = use_spectral(J);  // may turn to the window route after phase 1
     const bool rect = J.kern == NCF_RECTANGLE;
     const int nsets = J.ccf ? 2 : 1;
     bool weighted = false;
@@ -891,6 +891,43 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     const int64_t K = J.K;
     double maxlag = 0.0;
     for (double v : J.lags) maxlag = std::max(maxlag, std::fabs(v));
+    // NCF_AUTO, Gaussian: the real-space route (direct window sums) when its
+    // work is below the spectral pipeline's, the paper's K* crossover
+    // (Sec. "Choosing an estimator"). Window cost: windows x (8 + 8 x samples
+    // per window) lane-ops at the scan's measured rate (5e12/s mixed, 2e12/s
+    // FP64); spectral cost: about 11 passes over the grids at 4 TB/s plus
+    // 30 us for its extra launches and the fallback round trip.
+    if (spectral && J.opt.method == NCF_AUTO && J.kern == NCF_GAUSSIAN &&
+        !(J.opt.flags & NCF_SPECTRAL_ALWAYS)) {
+        const double rows = (double)(J.ccf ? K : K + 1);
+        const double rate = fp64 ? 2e12 : 5e12;
+        const double csz_b = fp64 ? 16.0 : 8.0;
+        double direct_s = 0.0, spec_s = 30e-6;
+        for (int64_t p = 0; p < J.nprob; ++p) {
+            if (pstat[p] != NCF_OK) continue;
+            const SeriesStat& s0 = stat_of(0, p);
+            const double n0 = (double)(J.set[0].offs[p + 1] - J.set[0].offs[p]);
+            const double n1 = J.ccf ? (double)(J.set[1].offs[p + 1] - J.set[1].offs[p]) : n0;
+            const double dens = (n0 - 1.0) / std::max(s0.tmax - s0.tmin, 1e-300);
+            const double pts = dens * 12.0 * J.h[p];
+            const double windows = n1 * rows + (J.ccf ? n0 + n1 : 0.0);
+            direct_s += windows * (8.0 + 8.0 * pts) / rate;
+            double tmin = s0.tmin, tmax = s0.tmax;
+            if (J.ccf) {
+                tmin = std::min(tmin, stat_of(1, p).tmin);
+                tmax = std::max(tmax, stat_of(1, p).tmax);
+            }
+            SpecGeom g;
+            if (plan_grid(J, tmin, tmax, maxlag, J.h[p], &g) != NCF_OK) {
+                clear_error();
+                direct_s = 0.0;  // no grid fits: the window route
+                break;
+            }
+            spec_s += 11.0 * (double)g.N * csz_b * (J.ccf ? 2.0 : 1.0) / 4e12 +
+                      (n0 + (J.ccf ? n1 : 0.0)) * 12.0 / 4e12;
+        }
+        if (direct_s < spec_s) spectral = false;
+    }
     // Gaussian default: numerator and pair count both by the spectral route
     // (unit-weight channel); lags whose spectral b is small against the
     // reference are re-evaluated by the direct window scan.

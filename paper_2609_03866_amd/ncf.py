@@ -22,6 +22,7 @@ DEVICE_POINTERS = 0x1
 PLAN_NO_GRAPH = 0x2
 WINDOW_QUEUE = 0x4
 PLAN_AUTOTUNE = 0x8
+SPECTRAL_ALWAYS = 0x10
 
 OK = 0
 E_INVALID_ARG = -1
@@ -162,7 +163,8 @@ class _Marshal:
         return a, a.ctypes.data
 
 
-def _options(precision, method, tol, sigma, grid_size, device, stream, window_queue=False):
+def _options(precision, method, tol, sigma, grid_size, device, stream, window_queue=False,
+             spectral_always=False):
     o = Options()
     lib().ncf_options_init(ctypes.byref(o))
     o.precision = {"mixed": MIXED, "fp64": FP64}.get(precision, precision) \
@@ -178,6 +180,8 @@ def _options(precision, method, tol, sigma, grid_size, device, stream, window_qu
         o.stream = stream if stream is not None else torch.cuda.current_stream().cuda_stream
     if window_queue:
         o.flags |= WINDOW_QUEUE
+    if spectral_always:
+        o.flags |= SPECTRAL_ALWAYS
     return o
 
 
@@ -189,7 +193,7 @@ def _check(rc, allow=()):
 
 def acf(t, x, lags, kernel="gaussian", h=1.0, err=None, precision="mixed", method="auto",
         tol=0.0, sigma=0.0, grid_size=0, with_count=True, raise_on_error=True, stream=None,
-        window_queue=False):
+        window_queue=False, spectral_always=False):
     """ncf_acf. Returns (c, b, count, status). numpy in -> numpy out; torch CUDA
     tensors in -> torch CUDA tensors out (stream-ordered on `stream`)."""
     dev = t.device if _is_torch(t) else None
@@ -199,7 +203,8 @@ def acf(t, x, lags, kernel="gaussian", h=1.0, err=None, precision="mixed", metho
     b, pb = m.out(K, np.float64)
     cnt, pn = m.out(K, np.int64) if with_count else (None, None)
     n = int(t.numel() if _is_torch(t) else np.asarray(t).size)
-    o = _options(precision, method, tol, sigma, grid_size, dev, stream, window_queue)
+    o = _options(precision, method, tol, sigma, grid_size, dev, stream, window_queue,
+                 spectral_always)
     rc = lib().ncf_acf(n, m.inp(t), m.inp(x), m.inp(err), K, m.inp(lags), _kern(kernel),
                        float(h), pc, pb, pn, ctypes.byref(o))
     if raise_on_error:
@@ -209,7 +214,7 @@ def acf(t, x, lags, kernel="gaussian", h=1.0, err=None, precision="mixed", metho
 
 def ccf(t, x, s, y, lags, kernel="gaussian", h=1.0, ex=None, ey=None, precision="mixed",
         method="auto", tol=0.0, sigma=0.0, grid_size=0, with_count=True, raise_on_error=True,
-        stream=None, window_queue=False):
+        stream=None, window_queue=False, spectral_always=False):
     """ncf_ccf (lag +tau: series 2 (s, y) lags series 1 (t, x) by tau)."""
     dev = t.device if _is_torch(t) else None
     m = _Marshal(dev)
@@ -219,7 +224,8 @@ def ccf(t, x, s, y, lags, kernel="gaussian", h=1.0, ex=None, ey=None, precision=
     cnt, pn = m.out(K, np.int64) if with_count else (None, None)
     nx = int(t.numel() if _is_torch(t) else np.asarray(t).size)
     ny = int(s.numel() if _is_torch(s) else np.asarray(s).size)
-    o = _options(precision, method, tol, sigma, grid_size, dev, stream, window_queue)
+    o = _options(precision, method, tol, sigma, grid_size, dev, stream, window_queue,
+                 spectral_always)
     rc = lib().ncf_ccf(nx, m.inp(t), m.inp(x), m.inp(ex), ny, m.inp(s), m.inp(y), m.inp(ey), K,
                        m.inp(lags), _kern(kernel), float(h), pc, pb, pn, ctypes.byref(o))
     if raise_on_error:
@@ -229,7 +235,7 @@ def ccf(t, x, s, y, lags, kernel="gaussian", h=1.0, ex=None, ey=None, precision=
 
 def acf_batch(offs, t, x, lags, kernel="gaussian", h=1.0, err=None, precision="mixed",
               method="auto", tol=0.0, sigma=0.0, grid_size=0, with_count=True,
-              raise_on_error=True, stream=None, window_queue=False):
+              raise_on_error=True, stream=None, window_queue=False, spectral_always=False):
     """ncf_acf_batch over CSR series. Returns (c[nser, K], b, count, status[nser], rc)."""
     offs = np.ascontiguousarray(offs, dtype=np.int64)
     nser = offs.size - 1
@@ -241,7 +247,8 @@ def acf_batch(offs, t, x, lags, kernel="gaussian", h=1.0, err=None, precision="m
     b, pb = m.out(nser * K, np.float64)
     cnt, pn = m.out(nser * K, np.int64) if with_count else (None, None)
     st = np.zeros(nser, dtype=np.int32)
-    o = _options(precision, method, tol, sigma, grid_size, dev, stream, window_queue)
+    o = _options(precision, method, tol, sigma, grid_size, dev, stream, window_queue,
+                 spectral_always)
     rc = lib().ncf_acf_batch(nser, offs.ctypes.data, m.inp(t), m.inp(x), m.inp(err), K,
                              m.inp(lags), _kern(kernel), hs.ctypes.data, pc, pb, pn,
                              st.ctypes.data, ctypes.byref(o))
@@ -253,7 +260,8 @@ def acf_batch(offs, t, x, lags, kernel="gaussian", h=1.0, err=None, precision="m
 
 def ccf_batch(offx, t, x, offy, s, y, lags, kernel="gaussian", h=1.0, ex=None, ey=None,
               precision="mixed", method="auto", tol=0.0, sigma=0.0, grid_size=0,
-              with_count=True, raise_on_error=True, stream=None, window_queue=False):
+              with_count=True, raise_on_error=True, stream=None, window_queue=False,
+              spectral_always=False):
     """ncf_ccf_batch over CSR series pairs."""
     offx = np.ascontiguousarray(offx, dtype=np.int64)
     offy = np.ascontiguousarray(offy, dtype=np.int64)
@@ -266,7 +274,8 @@ def ccf_batch(offx, t, x, offy, s, y, lags, kernel="gaussian", h=1.0, ex=None, e
     b, pb = m.out(npair * K, np.float64)
     cnt, pn = m.out(npair * K, np.int64) if with_count else (None, None)
     st = np.zeros(npair, dtype=np.int32)
-    o = _options(precision, method, tol, sigma, grid_size, dev, stream, window_queue)
+    o = _options(precision, method, tol, sigma, grid_size, dev, stream, window_queue,
+                 spectral_always)
     rc = lib().ncf_ccf_batch(npair, offx.ctypes.data, m.inp(t), m.inp(x), m.inp(ex),
                              offy.ctypes.data, m.inp(s), m.inp(y), m.inp(ey), K, m.inp(lags),
                              _kern(kernel), hs.ctypes.data, pc, pb, pn, st.ctypes.data,
@@ -488,8 +497,9 @@ class Plan:
 
 
 def _plan_options(precision, method, tol, sigma, grid_size, dev, stream, graph,
-                  window_queue=False, autotune=False):
-    o = _options(precision, method, tol, sigma, grid_size, dev, stream, window_queue)
+                  window_queue=False, autotune=False, spectral_always=False):
+    o = _options(precision, method, tol, sigma, grid_size, dev, stream, window_queue,
+                 spectral_always)
     if not graph:
         o.flags |= PLAN_NO_GRAPH
     if autotune:
@@ -499,7 +509,7 @@ def _plan_options(precision, method, tol, sigma, grid_size, dev, stream, graph,
 
 def plan_acf(offs, t, lags, kernel="gaussian", h=1.0, err=None, precision="mixed",
              method="auto", tol=0.0, sigma=0.0, grid_size=0, graph=True, stream=None,
-             window_queue=False, autotune=False):
+             window_queue=False, autotune=False, spectral_always=False):
     """ncf_plan_acf over CSR series (times fixed, values given per execute)."""
     offs = np.ascontiguousarray(offs, dtype=np.int64)
     nser = offs.size - 1
@@ -508,7 +518,7 @@ def plan_acf(offs, t, lags, kernel="gaussian", h=1.0, err=None, precision="mixed
     m = _Marshal(dev)
     K = int(lags.numel() if _is_torch(lags) else np.asarray(lags).size)
     o = _plan_options(precision, method, tol, sigma, grid_size, dev, stream, graph,
-                      window_queue, autotune)
+                      window_queue, autotune, spectral_always)
     hp = ctypes.c_void_p()
     _check(lib().ncf_plan_acf(nser, offs.ctypes.data, m.inp(t), m.inp(err), K, m.inp(lags),
                               _kern(kernel), hs.ctypes.data, ctypes.byref(o), ctypes.byref(hp)))
@@ -517,7 +527,7 @@ def plan_acf(offs, t, lags, kernel="gaussian", h=1.0, err=None, precision="mixed
 
 def plan_ccf(offx, t, offy, s, lags, kernel="gaussian", h=1.0, ex=None, ey=None,
              precision="mixed", method="auto", tol=0.0, sigma=0.0, grid_size=0, graph=True,
-             stream=None, window_queue=False, autotune=False):
+             stream=None, window_queue=False, autotune=False, spectral_always=False):
     """ncf_plan_ccf over CSR series pairs."""
     offx = np.ascontiguousarray(offx, dtype=np.int64)
     offy = np.ascontiguousarray(offy, dtype=np.int64)
@@ -527,7 +537,7 @@ def plan_ccf(offx, t, offy, s, lags, kernel="gaussian", h=1.0, ex=None, ey=None,
     m = _Marshal(dev)
     K = int(lags.numel() if _is_torch(lags) else np.asarray(lags).size)
     o = _plan_options(precision, method, tol, sigma, grid_size, dev, stream, graph,
-                      window_queue, autotune)
+                      window_queue, autotune, spectral_always)
     hp = ctypes.c_void_p()
     _check(lib().ncf_plan_ccf(npair, offx.ctypes.data, m.inp(t), m.inp(ex), offy.ctypes.data,
                               m.inp(s), m.inp(ey), K, m.inp(lags), _kern(kernel),

@@ -23,6 +23,22 @@ from paper_2609_03866_amd import ncf, synth
 pytestmark = pytest.mark.gpu
 
 
+@pytest.fixture(autouse=True)
+def _spectral_route(monkeypatch):
+    """NCF_AUTO here always takes the spectral route (NCF_SPECTRAL_ALWAYS), so
+    these small cases test it; the automatic choice of the direct window sums
+    for small calls is tested in test_gpu_route.py."""
+    orig = ncf._options
+
+    def opts(*a, **k):
+        o = orig(*a, **k)
+        o.flags |= ncf.SPECTRAL_ALWAYS
+        return o
+
+    monkeypatch.setattr(ncf, "_options", opts)
+
+
+
 def _orc_acf(d, lags=None, kernel=None, err=None, h=None):
     lags = d["lags"] if lags is None else lags
     st, c, b, n = O.acf(d["t"], d["x"], lags, kernel or d["kernel"], d["h"] if h is None else h,

@@ -14,6 +14,22 @@ from paper_2609_03866_amd import ncf, synth
 pytestmark = pytest.mark.gpu
 
 
+@pytest.fixture(autouse=True)
+def _spectral_route(monkeypatch):
+    """NCF_AUTO here always takes the spectral route (NCF_SPECTRAL_ALWAYS), so
+    these small cases test it; the automatic choice of the direct window sums
+    for small calls is tested in test_gpu_route.py."""
+    orig = ncf._options
+
+    def opts(*a, **k):
+        o = orig(*a, **k)
+        o.flags |= ncf.SPECTRAL_ALWAYS
+        return o
+
+    monkeypatch.setattr(ncf, "_options", opts)
+
+
+
 def _values_acf(d, seed):
     """New values at the plan's times: an OU series per curve plus noise."""
     rng = synth.rng_for(1000 + seed)
