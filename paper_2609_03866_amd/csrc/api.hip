@@ -272,6 +272,7 @@ struct Tune {
     FftVariant fft;      // radix split and strided-pass tile of the FFTs
     int jscale = 0;      // window tiles (outer samples per workgroup) times 2^jscale
     bool queue = false;  // window scans by work-queue dispatch
+    bool no_mid = false; // separate last FFT pass, product and first inverse pass
 };
 
 struct Job {
@@ -1217,7 +1218,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         int64_t *item0, *wk0, *r0;
         double* dl;
         SpecTask* st;
-        int64_t *tile0, *pos0, *sk0;
+        int64_t *tile0, *pos0, *sk0, *pair0;
         int32_t* smap;
         int32_t* rinfo;
         double* ev;
@@ -1235,6 +1236,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         dT.st = tb.take<SpecTask>(nts, &hT.st);
         dT.tile0 = tb.take<int64_t>(nts + 1, &hT.tile0);
         dT.pos0 = tb.take<int64_t>(nts + 1, &hT.pos0);
+        dT.pair0 = tb.take<int64_t>(nts + 1, &hT.pair0);
         dT.sk0 = tb.take<int64_t>(nts + 1, &hT.sk0);
         dT.smap = tb.take<int32_t>(nsd, &hT.smap);
         dT.rinfo = tb.take<int32_t>(6 * (size_t)nts, &hT.rinfo);
@@ -1267,7 +1269,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
 
     // spectral tables
     std::map<int64_t, FftPlan> plans;
-    int64_t total_pos = 0, ntiles = 0, total_samp = 0;
+    int64_t total_pos = 0, ntiles = 0, total_samp = 0, total_pairs = 0;
     for (int q = 0; q < nsd; ++q) hT.smap[q] = -1;
     double spread_bytes = 0.0;
     std::vector<std::pair<int, int>> groups;  // (first task, count) per grid size
@@ -1321,6 +1323,8 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         hT.st[i] = T;
         hT.tile0[i] = T.tile0;
         hT.pos0[i] = T.pos0;
+        hT.pair0[i] = total_pairs;
+        total_pairs += mid_pairs(T.N);
         hT.sk0[i] = (int64_t)i * Keval;
         if (i == 0 || splans[i].g.N != splans[i - 1].g.N)
             groups.push_back({i, 1});
@@ -1372,6 +1376,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     if (nts > 0) {
         hT.tile0[nts] = ntiles;
         hT.pos0[nts] = total_pos;
+        hT.pair0[nts] = total_pairs;
         hT.sk0[nts] = (int64_t)nts * Keval;
         for (int64_t k = 0; k < K; ++k) hT.ev[k] = J.lags[k];
         if (!J.ccf) hT.ev[K] = 0.0;
@@ -1419,21 +1424,39 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             return launch_spread(stk, tile0, nts, ntiles, rec_all, 4096, ccf, spec_b, spec_w,
                                  spec_unw, fp64, s, spread_bytes);
         }));
+        // the forward last pass, the product and the inverse first pass run
+        // fused over tile pairs where the mode fits the LDS of one workgroup
+        const bool fuse = !J.tune.no_mid && mid_supported(J.ccf, spec_b, spec_unw, fp64);
         for (size_t q = 0; q < groups.size(); ++q) {
             const FftPlan fp = plans[splans[groups[q].first].g.N];
             void* const* gp = dT.gfwd + fwd_groups[q].first;
             const int cnt = fwd_groups[q].second;
-            NCF_TRY(emit(J, [=](hipStream_t s) { return fft_exec(fp, gp, cnt, +1, fp64, s); }));
+            NCF_TRY(emit(J, [=](hipStream_t s) {
+                return fft_exec(fp, gp, cnt, +1, fp64, s, fuse);
+            }));
         }
-        NCF_TRY(emit(J, [=](hipStream_t s) {
-            return launch_product(stk, pos0, nts, total_pos, rinfo, ccf, spec_b, spec_unw, fp64, s,
-                                  pbytes);
-        }));
+        if (fuse) {
+            const int64_t* pair0 = dT.pair0;
+            const int64_t npairs = total_pairs;
+            const void* wsmall = plans.begin()->second.small;
+            const double mbytes = (double)(nfwd + 1) * total_pos * csz;
+            NCF_TRY(emit(J, [=](hipStream_t s) {
+                return launch_mid(stk, pair0, nts, npairs, rinfo, wsmall, ccf, spec_b, fp64, s,
+                                  mbytes);
+            }));
+        } else {
+            NCF_TRY(emit(J, [=](hipStream_t s) {
+                return launch_product(stk, pos0, nts, total_pos, rinfo, ccf, spec_b, spec_unw,
+                                      fp64, s, pbytes);
+            }));
+        }
         for (size_t q = 0; q < groups.size(); ++q) {
             const FftPlan fp = plans[splans[groups[q].first].g.N];
             void* const* gp = dT.ginv + inv_groups[q].first;
             const int cnt = inv_groups[q].second;
-            NCF_TRY(emit(J, [=](hipStream_t s) { return fft_exec(fp, gp, cnt, -1, fp64, s); }));
+            NCF_TRY(emit(J, [=](hipStream_t s) {
+                return fft_exec(fp, gp, cnt, -1, fp64, s, fuse);
+            }));
         }
         NCF_TRY(emit(J, [=](hipStream_t s) { return launch_interp(stk, nts, sk0, nkeval, fp64, s); }));
     }
@@ -2412,6 +2435,11 @@ int plan_create(Job& J, const double* const* tin, const double* const* ein, ncf_
             if (rc == NCF_OK && !fp64 && !J.regular) {
                 Tune t = best->tune;
                 t.fft.lgt_strided = 12;
+                rc = attempt(t);
+            }
+            if (rc == NCF_OK && !J.regular) {  // separate last pass and product
+                Tune t = best->tune;
+                t.no_mid = true;
                 rc = attempt(t);
             }
         }

@@ -108,14 +108,18 @@ struct RadixInfo {
 };
 
 __device__ __forceinline__ int64_t freq_of_pos(int64_t p, const RadixInfo& ri) {
-    // p = sum_i d_i * 2^(lgN - B_i), k = sum_i d_i * 2^(B_{i-1})
+    // p = sum_i d_i * 2^(lgN - B_i), k = sum_i d_i * 2^(B_{i-1}); at most four
+    // passes, unrolled so that the radix table stays in registers
     int64_t k = 0;
     int B = 0;
-    for (int i = 0; i < ri.npass; ++i) {
-        const int lg = ri.lg[i];
-        const int64_t d = (p >> (ri.lgN - B - lg)) & ((1LL << lg) - 1);
-        k |= d << B;
-        B += lg;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (i < ri.npass) {
+            const int lg = ri.lg[i];
+            const int64_t d = (p >> (ri.lgN - B - lg)) & ((1LL << lg) - 1);
+            k |= d << B;
+            B += lg;
+        }
     }
     return k;
 }
@@ -123,11 +127,14 @@ __device__ __forceinline__ int64_t freq_of_pos(int64_t p, const RadixInfo& ri) {
 __device__ __forceinline__ int64_t pos_of_freq(int64_t k, const RadixInfo& ri) {
     int64_t p = 0;
     int B = 0;
-    for (int i = 0; i < ri.npass; ++i) {
-        const int lg = ri.lg[i];
-        const int64_t d = (k >> B) & ((1LL << lg) - 1);
-        p |= d << (ri.lgN - B - lg);
-        B += lg;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (i < ri.npass) {
+            const int lg = ri.lg[i];
+            const int64_t d = (k >> B) & ((1LL << lg) - 1);
+            p |= d << (ri.lgN - B - lg);
+            B += lg;
+        }
     }
     return p;
 }
@@ -343,8 +350,10 @@ int fft_plan(int64_t N, bool fp64, FftPlan* plan, hipStream_t st,
              const FftVariant& v = FftVariant{});
 // Batched transform of `count` grids of the same N laid out at `grids[i]`.
 // sign +1: natural -> digit-reversed; sign -1: digit-reversed -> natural.
+// skip_tile_pass: leave out the radix-4096 pass (the last of sign +1, the
+// first of sign -1), which launch_mid performs.
 int fft_exec(const FftPlan& plan, void* const* d_grids, int count, int sign, bool fp64,
-             hipStream_t st);
+             hipStream_t st, bool skip_tile_pass = false);
 // storage position of frequency k after the sign +1 transform
 int64_t fft_position(const FftPlan& plan, int64_t k);
 
@@ -416,6 +425,18 @@ int launch_reg_product(const RegTask* d_tasks, const int64_t* d_pos0, int ntasks
 // Lag filter, normalization and outputs (request order) of every task.
 int launch_reg_finish(const RegTask* d_tasks, int ntasks, const double* d_lags, int64_t K,
                       int mode, int kern, const IoBlock* io, hipStream_t st);
+
+// Fused forward last FFT pass (radix 4096), product and inverse first pass
+// over pairs of 4096-position tiles (the tiles of frequencies k and -k), all
+// tasks in one launch; replaces the last forward pass, launch_product and
+// the first inverse pass for the modes mid_supported accepts (no unit
+// channel; LDS for two or four tiles within 160 KB). d_pair0: prefix of
+// mid_pairs(N) over the tasks; wsmall: the FFT's w_4096 table.
+bool mid_supported(bool ccf, bool with_b, bool unw, bool fp64);
+int64_t mid_pairs(int64_t N);
+int launch_mid(const SpecTask* d_tasks, const int64_t* d_pair0, int ntasks, int64_t npairs,
+               const int64_t* d_radix_info, const void* wsmall, bool ccf, bool with_b, bool fp64,
+               hipStream_t st, double bytes);
 
 // ------------------------------------------------------------ A8 output
 struct NormTask {

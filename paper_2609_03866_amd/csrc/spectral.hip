@@ -26,6 +26,7 @@
 // coalesced write per cell; deterministic.
 #include <algorithm>
 
+#include "fft_tile.h"
 #include "internal.h"
 
 namespace ncf {
@@ -438,19 +439,18 @@ __device__ __forceinline__ void product_factors(const ProductCtx<R>& X, const Ra
 }
 
 template <typename R, bool CCF, bool WB>
-__device__ __forceinline__ void product_item(const ProductCtx<R>& X, const RadixInfo& ri,
+__device__ __forceinline__ void product_math(const ProductCtx<R>& X, const RadixInfo& ri,
                                              int64_t p, int64_t pp, typename Cplx<R>::T a,
                                              typename Cplx<R>::T b, typename Cplx<R>::T va,
-                                             typename Cplx<R>::T vb, double (&sacc)[4]) {
-    using C2 = typename Cplx<R>::T;
+                                             typename Cplx<R>::T vb, double (&sacc)[4],
+                                             typename Cplx<R>::T& o, typename Cplx<R>::T& oc) {
     double f3, f2;
     product_factors<R, CCF>(X, ri, p, f3, f2);
-    if (!CCF && !WB) {
+    if (!CCF && !WB) {  // each position on its own: f3 |Z|^2 (oc unused)
         const double pw = (double)a.x * a.x + (double)a.y * a.y;
-        C2 o;
         o.x = (R)(f3 * pw);
         o.y = (R)0;
-        cst(X.Z, p, o);
+        oc = o;
         return;
     }
     // the two real sequences packed in Z: A = (Z_m + conj Z_-m)/2,
@@ -458,7 +458,6 @@ __device__ __forceinline__ void product_item(const ProductCtx<R>& X, const Radix
     const double ar = 0.5 * ((double)a.x + b.x), ai = 0.5 * ((double)a.y - b.y);
     const double br = 0.5 * ((double)a.y + b.y), bi = -0.5 * ((double)a.x - b.x);
     const double mult = (pp != p) ? 2.0 : 1.0;
-    C2 o, oc;
     if (!CCF) {
         // ACF with b: A = X (values), B = W (unit weights); G_N = |X|^2, G_B = |W|^2
         const double gn = ar * ar + ai * ai, gbb = br * br + bi * bi;
@@ -491,8 +490,17 @@ __device__ __forceinline__ void product_item(const ProductCtx<R>& X, const Radix
             oc.y = (R)(f3 * (hr - gi));
         }
     }
+}
+
+template <typename R, bool CCF, bool WB>
+__device__ __forceinline__ void product_item(const ProductCtx<R>& X, const RadixInfo& ri,
+                                             int64_t p, int64_t pp, typename Cplx<R>::T a,
+                                             typename Cplx<R>::T b, typename Cplx<R>::T va,
+                                             typename Cplx<R>::T vb, double (&sacc)[4]) {
+    typename Cplx<R>::T o, oc;
+    product_math<R, CCF, WB>(X, ri, p, pp, a, b, va, vb, sacc, o, oc);
     cst(X.Z, p, o);
-    if (pp != p) cst(X.Z, pp, oc);
+    if ((CCF || WB) && pp != p) cst(X.Z, pp, oc);
 }
 
 // Unweighted pair-count spectrum of a weighted call from its unit channel
@@ -661,6 +669,150 @@ __global__ void k_interp(const SpecTask* __restrict__ tasks, int ntasks, const i
     if (T.bunw) T.bunw[k] = accn;
 }
 
+
+// ------------------------------------------- fused last pass + product
+
+// The forward transform's last pass (radix 4096) works on contiguous
+// 4096-position tiles, and so does the inverse transform's first pass. All
+// positions of one tile share the frequency bits below the last digit,
+// k_low, and the partners -k of its frequencies all lie in the tile of
+// -k_low. A workgroup therefore takes such a pair of tiles (one tile when
+// k_low = -k_low: k_low = 0 or half the range), runs the forward last pass
+// of both into LDS, forms the products there, and runs the inverse first
+// pass of both back to HBM: two sweeps over the grids fewer than separate
+// passes and a product kernel.
+//
+// Pair q of a grid with 2^m tiles: q = 0 -> k_low = 0; q = 1 -> k_low =
+// 2^(m-1); q >= 2 -> k_low = q - 1 with partner 2^m - k_low.
+__device__ __forceinline__ void mid_pair(int64_t q, const RadixInfo& ri, int64_t& tA,
+                                         int64_t& tB, int64_t& klow) {
+    const int m = ri.lgN - 12;
+    int64_t kl = 0, kp = 0;
+    if (m > 0 && q == 1) {
+        kl = 1LL << (m - 1);
+        kp = kl;
+    } else if (m > 0 && q >= 2) {
+        kl = q - 1;
+        kp = (1LL << m) - kl;
+    }
+    tA = pos_of_freq(kl, ri) >> 12;
+    tB = pos_of_freq(kp, ri) >> 12;
+    klow = kl;
+}
+
+constexpr int kMidPad = 4096 + 4096 / 16;  // one padded LDS tile (fftk::lds_pad)
+
+extern __shared__ char g_mid_lds[];
+
+// MODE: bit 1 CCF, bit 0 pair-count channel (gridb for the CCF); as k_product
+// without the unit channel.
+template <typename R, int MODE>
+__global__ void __launch_bounds__(kThreads)
+k_mid(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pair0, int ntasks,
+      const RadixInfo* __restrict__ rinfo, const void* wsmall) {
+    using C2 = typename Cplx<R>::T;
+    constexpr bool CCF = (MODE & 2) != 0;
+    constexpr bool WB = (MODE & 1) != 0;
+    constexpr bool TWO = CCF && WB;  // the CCF pair-count grid is read too
+    __shared__ double red[4][kThreads];
+    C2* A = reinterpret_cast<C2*>(g_mid_lds);  // grid tile tA
+    C2* Bt = A + kMidPad;                       // grid tile tB
+    C2* UA = Bt + kMidPad;                      // (TWO) gridb tile tA
+    C2* UB = UA + kMidPad;                      // (TWO) gridb tile tB
+    const int64_t blk = blockIdx.x;
+    const int ti = ntasks == 1 ? 0 : (int)wave_search<int64_t>(pair0, ntasks, blk, true) - 1;
+    const SpecTask& T = tasks[ti];
+    const RadixInfo ri = rinfo[ti];
+    const int64_t N = T.N;
+    int64_t tA, tB, kl;
+    mid_pair(blk - pair0[ti], ri, tA, tB, kl);
+    const bool self = tA == tB;
+    C2* const Z = reinterpret_cast<C2*>(T.grid);
+    C2* const U = reinterpret_cast<C2*>(T.gridb);
+    fftk::PassArgs a{};
+    a.N = N;
+    a.S = 1;
+    a.B = 4096;
+    a.sign = +1;
+    a.wsmall = wsmall;
+    // forward last pass of the tiles, into LDS
+    fftk::run_stages_io<12, 0, 1, 12, true, false>(a, A, Z + tA * 4096, 0);
+    if (!self) fftk::run_stages_io<12, 0, 1, 12, true, false>(a, Bt, Z + tB * 4096, 0);
+    if (TWO) {
+        fftk::run_stages_io<12, 0, 1, 12, true, false>(a, UA, U + tA * 4096, 0);
+        if (!self) fftk::run_stages_io<12, 0, 1, 12, true, false>(a, UB, U + tB * 4096, 0);
+    }
+    C2* const PB = self ? A : Bt;
+    C2* const PUB = self ? UA : UB;
+    // products: position r of tile tA pairs with r' of tile tB (k_low = 0:
+    // r' = -r mod 4096; else r' = 4095 - r)
+    const ProductCtx<R> X{gbl(reinterpret_cast<R*>(T.grid)), gbl(reinterpret_cast<R*>(T.gridb)),
+                          gbl(reinterpret_cast<R*>(T.gridc)), N, T.M, T.L, T.h, T.s, T.kern};
+    double sacc[4] = {0.0, 0.0, 0.0, 0.0};
+    constexpr bool pairs = CCF || WB;
+    // a pair of distinct tiles: every r of tA; one tile: r in [0, 2048)
+    // (partners in the upper half), plus r = 2048 when it is its own partner
+    const int nown = (!pairs || !self) ? 4096 : 2048;
+    for (int r = threadIdx.x; r < nown; r += kThreads) {
+        const int rp = kl == 0 ? ((4096 - r) & 4095) : (4095 - r);
+        const int64_t p = tA * 4096 + r, pp = tB * 4096 + rp;
+        const C2 za = A[fftk::lds_pad(r)];
+        const C2 zb = PB[fftk::lds_pad(rp)];
+        C2 ua = za, ub = za;
+        if (TWO) {
+            ua = UA[fftk::lds_pad(r)];
+            ub = PUB[fftk::lds_pad(rp)];
+        }
+        C2 o, oc;
+        product_math<R, CCF, WB>(X, ri, p, pairs ? pp : p, za, pairs ? zb : za, ua, ub, sacc, o,
+                                 oc);
+        A[fftk::lds_pad(r)] = o;
+        if (pairs && pp != p) PB[fftk::lds_pad(rp)] = oc;
+    }
+    if (!pairs && !self) {  // each position on its own: the second tile too
+        for (int r = threadIdx.x; r < 4096; r += kThreads) {
+            const int64_t p = tB * 4096 + r;
+            const C2 za = Bt[fftk::lds_pad(r)];
+            C2 o, oc;
+            product_math<R, CCF, WB>(X, ri, p, p, za, za, za, za, sacc, o, oc);
+            Bt[fftk::lds_pad(r)] = o;
+        }
+    }
+    if (pairs && self && kl == 0 && threadIdx.x == 0) {  // k = N/2 at r = 2048
+        const int r = 2048;
+        const int64_t p = tA * 4096 + r;
+        const C2 za = A[fftk::lds_pad(r)];
+        const C2 ua = TWO ? UA[fftk::lds_pad(r)] : za;
+        C2 o, oc;
+        product_math<R, CCF, WB>(X, ri, p, p, za, za, ua, ua, sacc, o, oc);
+        A[fftk::lds_pad(r)] = o;
+    }
+    __syncthreads();
+    // inverse first pass of the product tiles, to HBM
+    a.sign = -1;
+    fftk::run_stages_io<12, 0, 1, 12, false, true>(a, A, Z + tA * 4096, 0);
+    if (!self) fftk::run_stages_io<12, 0, 1, 12, false, true>(a, Bt, Z + tB * 4096, 0);
+    if (CCF) {  // lag-0 partial sums: the pair's in the slot of tile tA, 0 in tB's
+#pragma unroll
+        for (int q = 0; q < 4; ++q) red[q][threadIdx.x] = sacc[q];
+        __syncthreads();
+        for (int off = kThreads / 2; off > 0; off >>= 1) {
+            if (threadIdx.x < off) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + off];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                T.scale_part[4 * tA + q] = red[q][0];
+                if (!self) T.scale_part[4 * tB + q] = 0.0;
+            }
+        }
+    }
+}
+
 }  // namespace
 
 SpreadParams spread_params(double sigma, double eps) {
@@ -767,6 +919,62 @@ int launch_interp(const SpecTask* d_tasks, int ntasks, const int64_t* d_k0, int6
                            st, d_tasks, ntasks, d_k0, total_k);
     NCF_CHECK_LAUNCH();
     return NCF_OK;
+}
+
+}  // namespace ncf
+
+namespace ncf {
+
+bool mid_supported(bool ccf, bool with_b, bool unw, bool fp64) {
+    if (unw) return false;
+    const int tiles = (ccf && with_b) ? 4 : 2;
+    const size_t csz = fp64 ? 16 : 8;
+    return (size_t)tiles * kMidPad * csz <= 160 * 1024;
+}
+
+int64_t mid_pairs(int64_t N) { return N <= 4096 ? 1 : N / 8192 + 1; }
+
+template <typename R, int MODE>
+static int launch_mid_t(const SpecTask* d_tasks, const int64_t* d_pair0, int ntasks,
+                        int64_t npairs, const RadixInfo* ri, const void* wsmall, hipStream_t st) {
+    constexpr bool TWO = (MODE & 3) == 3;
+    const size_t lds = (size_t)(TWO ? 4 : 2) * kMidPad * sizeof(typename Cplx<R>::T);
+    static bool attr_set = false;
+    if (!attr_set) {
+        NCF_TRY_HIP(hipFuncSetAttribute((const void*)k_mid<R, MODE>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_mid<R, MODE>), dim3((unsigned)npairs), dim3(kThreads), lds, st, d_tasks,
+                       d_pair0, ntasks, ri, wsmall);
+    NCF_CHECK_LAUNCH();
+    return NCF_OK;
+}
+
+int launch_mid(const SpecTask* d_tasks, const int64_t* d_pair0, int ntasks, int64_t npairs,
+               const int64_t* d_radix_info, const void* wsmall, bool ccf, bool with_b, bool fp64,
+               hipStream_t st, double bytes) {
+    if (npairs <= 0) return NCF_OK;
+    if (!mid_supported(ccf, with_b, false, fp64)) {
+        set_error("fused last pass: mode not covered");
+        return NCF_E_UNSUPPORTED;
+    }
+    const RadixInfo* ri = reinterpret_cast<const RadixInfo*>(d_radix_info);
+    const int mode = (ccf ? 2 : 0) | (with_b ? 1 : 0);
+    ProfScope p(st, fp64 ? "mid_f64" : "mid_f32", bytes, "bytes");
+    if (fp64) {
+        switch (mode) {
+            case 0: return launch_mid_t<double, 0>(d_tasks, d_pair0, ntasks, npairs, ri, wsmall, st);
+            case 1: return launch_mid_t<double, 1>(d_tasks, d_pair0, ntasks, npairs, ri, wsmall, st);
+            default: return launch_mid_t<double, 2>(d_tasks, d_pair0, ntasks, npairs, ri, wsmall, st);
+        }
+    }
+    switch (mode) {
+        case 0: return launch_mid_t<float, 0>(d_tasks, d_pair0, ntasks, npairs, ri, wsmall, st);
+        case 1: return launch_mid_t<float, 1>(d_tasks, d_pair0, ntasks, npairs, ri, wsmall, st);
+        case 2: return launch_mid_t<float, 2>(d_tasks, d_pair0, ntasks, npairs, ri, wsmall, st);
+        default: return launch_mid_t<float, 3>(d_tasks, d_pair0, ntasks, npairs, ri, wsmall, st);
+    }
 }
 
 }  // namespace ncf
