@@ -241,9 +241,10 @@ __device__ __forceinline__ int lds_pad(int e) { return e + (e >> 4); }
 // One Stockham stage of radix RADIX over the tile's C columns of length R.
 // Each thread owns 16 / RADIX butterflies (16 elements). Inputs come from
 // `src` (global or LDS view), outputs go to `dst`.
+// tid: the thread's index among the 2^(LGT-4) threads of the tile.
 template <int RADIX, bool FROM_GLOBAL, bool TO_GLOBAL, int LGR, int NS, int LGT, typename C2>
-__device__ __forceinline__ void stockham_stage(const PassArgs& a, C2* lds, C2* gbase,
-                                               int64_t s0) {
+__device__ __forceinline__ void stockham_stage(const PassArgs& a, C2* lds, C2* gbase, int64_t s0,
+                                               int tid) {
     constexpr int kThreads = 1 << (LGT - 4);  // 16 elements per thread
     constexpr int NB = 16 / RADIX;  // butterflies per thread
     constexpr int lgC = LGT - LGR;
@@ -251,7 +252,6 @@ __device__ __forceinline__ void stockham_stage(const PassArgs& a, C2* lds, C2* g
     constexpr int C = 1 << lgC;
     constexpr int Rr = R / RADIX;
     constexpr int Ns = NS;
-    const int tid = threadIdx.x;
     C2 v[16];
     int jj[NB], cc[NB];
 #pragma unroll
@@ -334,7 +334,8 @@ __device__ __forceinline__ void run_stages(const PassArgs& a, C2* lds, C2* gbase
     constexpr int nst = n16 + (rem ? 1 : 0);
     if constexpr (ST < nst) {
         constexpr int RX = ST < n16 ? 16 : (1 << rem);
-        stockham_stage<RX, ST == 0, ST == nst - 1, LGR, NS, LGT>(a, lds, gbase, s0);
+        stockham_stage<RX, ST == 0, ST == nst - 1, LGR, NS, LGT>(a, lds, gbase, s0,
+                                                                  (int)threadIdx.x);
         run_stages<LGR, ST + 1, NS * RX, LGT>(a, lds, gbase, s0);
     }
 }
@@ -343,15 +344,31 @@ __device__ __forceinline__ void run_stages(const PassArgs& a, C2* lds, C2* gbase
 // of the first stage (global memory or LDS) and the destination of the last
 // (global memory or LDS) chosen at compile time.
 template <int LGR, int ST, int NS, int LGT, bool G_IN, bool G_OUT, typename C2>
-__device__ __forceinline__ void run_stages_io(const PassArgs& a, C2* lds, C2* gbase, int64_t s0) {
+__device__ __forceinline__ void run_stages_io(const PassArgs& a, C2* lds, C2* gbase, int64_t s0,
+                                              int tid) {
     constexpr int n16 = LGR / 4;
     constexpr int rem = LGR % 4;
     constexpr int nst = n16 + (rem ? 1 : 0);
     if constexpr (ST < nst) {
         constexpr int RX = ST < n16 ? 16 : (1 << rem);
         stockham_stage<RX, G_IN && ST == 0, G_OUT && ST == nst - 1, LGR, NS, LGT>(a, lds, gbase,
-                                                                                   s0);
-        run_stages_io<LGR, ST + 1, NS * RX, LGT, G_IN, G_OUT>(a, lds, gbase, s0);
+                                                                                   s0, tid);
+        run_stages_io<LGR, ST + 1, NS * RX, LGT, G_IN, G_OUT>(a, lds, gbase, s0, tid);
+    }
+}
+
+// The workgroup barriers of run_stages_io without its work: threads with no
+// tile to transform call this so that the barriers stay matched.
+template <int LGR, int ST, bool G_IN, bool G_OUT>
+__device__ __forceinline__ void run_stages_idle() {
+    constexpr int n16 = LGR / 4;
+    constexpr int rem = LGR % 4;
+    constexpr int nst = n16 + (rem ? 1 : 0);
+    if constexpr (ST < nst) {
+        constexpr bool from_g = G_IN && ST == 0, to_g = G_OUT && ST == nst - 1;
+        if (!from_g || to_g) __syncthreads();
+        if (!to_g) __syncthreads();
+        run_stages_idle<LGR, ST + 1, G_IN, G_OUT>();
     }
 }
 

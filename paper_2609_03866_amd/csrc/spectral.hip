@@ -705,16 +705,21 @@ constexpr int kMidPad = 4096 + 4096 / 16;  // one padded LDS tile (fftk::lds_pad
 extern __shared__ char g_mid_lds[];
 
 // MODE: bit 1 CCF, bit 0 pair-count channel (gridb for the CCF); as k_product
-// without the unit channel.
+// without the unit channel. 512 threads: the two halves transform the two
+// tiles at the same time (in a one-tile pair the second half only keeps the
+// barriers); all threads share the products.
+constexpr int kMidThreads = 512;
+
 template <typename R, int MODE>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kMidThreads)
 k_mid(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pair0, int ntasks,
       const RadixInfo* __restrict__ rinfo, const void* wsmall) {
     using C2 = typename Cplx<R>::T;
     constexpr bool CCF = (MODE & 2) != 0;
     constexpr bool WB = (MODE & 1) != 0;
     constexpr bool TWO = CCF && WB;  // the CCF pair-count grid is read too
-    __shared__ double red[4][kThreads];
+    constexpr int kWaves = kMidThreads / 64;
+    __shared__ double red[4][kWaves];
     C2* A = reinterpret_cast<C2*>(g_mid_lds);  // grid tile tA
     C2* Bt = A + kMidPad;                       // grid tile tB
     C2* UA = Bt + kMidPad;                      // (TWO) gridb tile tA
@@ -729,6 +734,12 @@ k_mid(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pair0, int
     const bool self = tA == tB;
     C2* const Z = reinterpret_cast<C2*>(T.grid);
     C2* const U = reinterpret_cast<C2*>(T.gridb);
+    const int half = threadIdx.x >> 8;  // wave-uniform
+    const int lt = threadIdx.x & 255;
+    const bool act = half == 0 || !self;
+    C2* const myZ = half ? Bt : A;
+    C2* const myU = half ? UB : UA;
+    const int64_t myT = half ? tB : tA;
     fftk::PassArgs a{};
     a.N = N;
     a.S = 1;
@@ -736,11 +747,15 @@ k_mid(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pair0, int
     a.sign = +1;
     a.wsmall = wsmall;
     // forward last pass of the tiles, into LDS
-    fftk::run_stages_io<12, 0, 1, 12, true, false>(a, A, Z + tA * 4096, 0);
-    if (!self) fftk::run_stages_io<12, 0, 1, 12, true, false>(a, Bt, Z + tB * 4096, 0);
+    if (act)
+        fftk::run_stages_io<12, 0, 1, 12, true, false>(a, myZ, Z + myT * 4096, 0, lt);
+    else
+        fftk::run_stages_idle<12, 0, true, false>();
     if (TWO) {
-        fftk::run_stages_io<12, 0, 1, 12, true, false>(a, UA, U + tA * 4096, 0);
-        if (!self) fftk::run_stages_io<12, 0, 1, 12, true, false>(a, UB, U + tB * 4096, 0);
+        if (act)
+            fftk::run_stages_io<12, 0, 1, 12, true, false>(a, myU, U + myT * 4096, 0, lt);
+        else
+            fftk::run_stages_idle<12, 0, true, false>();
     }
     C2* const PB = self ? A : Bt;
     C2* const PUB = self ? UA : UB;
@@ -753,7 +768,7 @@ k_mid(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pair0, int
     // a pair of distinct tiles: every r of tA; one tile: r in [0, 2048)
     // (partners in the upper half), plus r = 2048 when it is its own partner
     const int nown = (!pairs || !self) ? 4096 : 2048;
-    for (int r = threadIdx.x; r < nown; r += kThreads) {
+    for (int r = threadIdx.x; r < nown; r += kMidThreads) {
         const int rp = kl == 0 ? ((4096 - r) & 4095) : (4095 - r);
         const int64_t p = tA * 4096 + r, pp = tB * 4096 + rp;
         const C2 za = A[fftk::lds_pad(r)];
@@ -770,7 +785,7 @@ k_mid(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pair0, int
         if (pairs && pp != p) PB[fftk::lds_pad(rp)] = oc;
     }
     if (!pairs && !self) {  // each position on its own: the second tile too
-        for (int r = threadIdx.x; r < 4096; r += kThreads) {
+        for (int r = threadIdx.x; r < 4096; r += kMidThreads) {
             const int64_t p = tB * 4096 + r;
             const C2 za = Bt[fftk::lds_pad(r)];
             C2 o, oc;
@@ -790,23 +805,26 @@ k_mid(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pair0, int
     __syncthreads();
     // inverse first pass of the product tiles, to HBM
     a.sign = -1;
-    fftk::run_stages_io<12, 0, 1, 12, false, true>(a, A, Z + tA * 4096, 0);
-    if (!self) fftk::run_stages_io<12, 0, 1, 12, false, true>(a, Bt, Z + tB * 4096, 0);
+    if (act)
+        fftk::run_stages_io<12, 0, 1, 12, false, true>(a, myZ, Z + myT * 4096, 0, lt);
+    else
+        fftk::run_stages_idle<12, 0, false, true>();
     if (CCF) {  // lag-0 partial sums: the pair's in the slot of tile tA, 0 in tB's
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) red[q][threadIdx.x] = sacc[q];
-        __syncthreads();
-        for (int off = kThreads / 2; off > 0; off >>= 1) {
-            if (threadIdx.x < off) {
+        for (int q = 0; q < 4; ++q) {
+            double v = sacc[q];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + off];
-            }
-            __syncthreads();
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            if (lane == 0) red[q][wave] = v;
         }
+        __syncthreads();
         if (threadIdx.x == 0) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                T.scale_part[4 * tA + q] = red[q][0];
+                double v = 0.0;
+                for (int w = 0; w < kWaves; ++w) v += red[q][w];
+                T.scale_part[4 * tA + q] = v;
                 if (!self) T.scale_part[4 * tB + q] = 0.0;
             }
         }
@@ -945,8 +963,8 @@ static int launch_mid_t(const SpecTask* d_tasks, const int64_t* d_pair0, int nta
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_mid<R, MODE>), dim3((unsigned)npairs), dim3(kThreads), lds, st, d_tasks,
-                       d_pair0, ntasks, ri, wsmall);
+    hipLaunchKernelGGL((k_mid<R, MODE>), dim3((unsigned)npairs), dim3(kMidThreads), lds, st,
+                       d_tasks, d_pair0, ntasks, ri, wsmall);
     NCF_CHECK_LAUNCH();
     return NCF_OK;
 }
