@@ -53,6 +53,11 @@ int ncf_diag_spread_params(double sigma, double eps, double* out);
  * kernel is launched on. Enabling clears the accumulated records. */
 void ncf_profile_enable(int on);
 
+/* Restrict the timing to launches of one kernel name (as reported by
+ * ncf_profile_read); NULL or "" times every kernel. Each timed launch records
+ * two events on its stream, from a pool the library keeps for reuse. */
+void ncf_profile_filter(const char* name);
+
 typedef struct {
     char name[48];     /* kernel name */
     int64_t launches;  /* number of timed launches */

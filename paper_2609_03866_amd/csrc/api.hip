@@ -64,7 +64,9 @@ struct Pending {
 };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
+std::string g_prof_only;            // empty: every kernel; else only this name
 std::vector<Pending> g_pending;
+std::vector<hipEvent_t> g_ev_free;  // events kept for reuse (no create per launch)
 std::map<std::string, ProfRec> g_prof;
 
 void prof_flush_locked() {
@@ -77,10 +79,21 @@ void prof_flush_locked() {
         r.ms += ms;
         r.work += p.work;
         r.unit = p.unit;
-        (void)hipEventDestroy(p.e0);
-        (void)hipEventDestroy(p.e1);
+        g_ev_free.push_back(p.e0);
+        g_ev_free.push_back(p.e1);
     }
     g_pending.clear();
+}
+
+hipEvent_t prof_event_locked() {
+    if (!g_ev_free.empty()) {
+        hipEvent_t e = g_ev_free.back();
+        g_ev_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
 }
 
 }  // namespace
@@ -93,17 +106,25 @@ ProfScope::ProfScope(hipStream_t s, const char* n, double w, const char* u)
     : stream(s), name(n), work(w), unit(u), ev0(nullptr) {
     if (!g_prof_on || g_capturing) return;
     hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return;
+    {
+        std::lock_guard<std::mutex> lock(g_prof_mu);
+        if (!g_prof_only.empty() && g_prof_only != n) return;
+        e = prof_event_locked();
+    }
+    if (!e) return;
     (void)hipEventRecord(e, stream);
     ev0 = e;
 }
 
 ProfScope::~ProfScope() {
     if (!ev0) return;
-    hipEvent_t e1;
-    if (hipEventCreate(&e1) != hipSuccess) return;
-    (void)hipEventRecord(e1, stream);
     std::lock_guard<std::mutex> lock(g_prof_mu);
+    hipEvent_t e1 = prof_event_locked();
+    if (!e1) {
+        g_ev_free.push_back((hipEvent_t)ev0);
+        return;
+    }
+    (void)hipEventRecord(e1, stream);
     g_pending.push_back({name, (hipEvent_t)ev0, e1, work, unit});
 }
 
@@ -2847,6 +2868,11 @@ void ncf_profile_enable(int on) {
         g_prof.clear();
     }
     g_prof_on = on != 0;
+}
+
+void ncf_profile_filter(const char* name) {
+    std::lock_guard<std::mutex> lock(g_prof_mu);
+    g_prof_only = name ? name : "";
 }
 
 int ncf_profile_read(ncf_profile_record_t* out, int max) {

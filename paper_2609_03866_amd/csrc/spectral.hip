@@ -357,21 +357,13 @@ k_spread(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ tile0, 
 
 // ---------------------------------------------------------------- product
 
-// exp(x) to ~1 FP32 ulp for any x in range: x log2(e) is split in FP64 into
-// an integer part (applied exactly) and a fraction in [0, 1) for exp2.
-__device__ __forceinline__ double exp_split(double x) {
-    const double y = x * 1.4426950408889634;
-    const double n = floor(y);
-    const float f = (float)(y - n);
-    return ldexp((double)__builtin_amdgcn_exp2f(f), (int)n);
-}
 
 template <typename R>
 __device__ __forceinline__ double lag_kernel_ft(int kern, double f, double h) {
     if (kern == NCF_GAUSSIAN) return exp(-2.0 * M_PI * M_PI * h * h * f * f);
     // box of half-width h: integral_{-h}^{h} exp(2 pi i f d) dd = sin(2 pi h f) / (pi f)
     if (f == 0.0) return 2.0 * h;
-    return sin(2.0 * M_PI * h * f) / (M_PI * f);
+    return sinpi(2.0 * h * f) / (M_PI * f);
 }
 
 // complex element i of a global-memory grid of R pairs
@@ -396,46 +388,67 @@ struct ProductCtx {
     int64_t N, M;
     double L, h, s;
     int32_t kern;
+    // per-mode factors f3 = phihat(m/L) / (L Psi^3) and f2 = phihat(m/L) /
+    // (L Psi^2) with Psi(m/N) = sqrt(2 pi) s exp(-2 pi^2 s^2 m^2 / N^2):
+    double c3, c2;  // 1 / (L (2 pi)^(3/2) s^3), 1 / (L 2 pi s^2)
+    double psi;     // 2 pi^2 s^2 / N^2, the exponent of 1/Psi per m^2
+    double e3, e2;  // Gaussian lag kernel: exponents of f3, f2 per m^2
+                    // (base 2 for FP32 grids, base e for FP64 grids)
 };
 
-// Product at one owned position p (partner pp = position of -k); z*/u* are
-// the values loaded at p and pp. Writes Z[p] (and Z[pp]) and adds the lag-0
-// partial sums.
-// The per-mode factors at the frequency of position p: f3 = phihat(m/L) /
-// (L Psi^3) for the product spectra and f2 = phihat(m/L) / (L Psi^2) for the
-// CCF lag-0 sums, with Psi(m/N) = sqrt(2 pi) s exp(-2 pi^2 s^2 m^2 / N^2);
-// both zero beyond the retained modes.
+template <typename R>
+__device__ __forceinline__ ProductCtx<R> product_ctx(gptr<R> Z, gptr<R> U, gptr<R> C,
+                                                     const SpecTask& T) {
+    ProductCtx<R> X{Z, U, C, T.N, T.M, T.L, T.h, T.s, T.kern, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const double s = T.s, L = T.L, Nd = (double)T.N, h = T.h;
+    X.c3 = 1.0 / (L * 15.749609945722419 * s * s * s);
+    X.c2 = 1.0 / (L * 6.283185307179586 * s * s);
+    X.psi = 2.0 * M_PI * M_PI * s * s / (Nd * Nd);
+    const double ker = 2.0 * M_PI * M_PI * h * h / (L * L);  // of phihat per m^2
+    const double base = sizeof(R) == 4 ? 1.4426950408889634 : 1.0;
+    X.e3 = (3.0 * X.psi - ker) * base;
+    X.e2 = (2.0 * X.psi - ker) * base;
+    return X;
+}
+
+// 2^y to ~1 FP32 ulp for any y in range: y is split in FP64 into an integer
+// part (applied exactly) and a fraction in [0, 1) for the FP32 exp2.
+__device__ __forceinline__ double exp2_split(double y) {
+    const double n = floor(y);
+    return ldexp((double)__builtin_amdgcn_exp2f((float)(y - n)), (int)n);
+}
+
+// The factors at signed mode m (|m| <= N/2); both zero beyond the retained
+// modes.
+template <typename R, bool CCF>
+__device__ __forceinline__ void product_factors_m(const ProductCtx<R>& X, int64_t m, double& f3,
+                                                  double& f2) {
+    f3 = 0.0;
+    f2 = 0.0;
+    if (m > X.M || m < -X.M) return;
+    const double md = (double)m;
+    const double m2 = md * md;
+    if (X.kern == NCF_GAUSSIAN) {
+        if (sizeof(R) == 4) {
+            f3 = X.c3 * exp2_split(X.e3 * m2);
+            if (CCF) f2 = X.c2 * exp2_split(X.e2 * m2);
+        } else {
+            f3 = X.c3 * exp(X.e3 * m2);
+            if (CCF) f2 = X.c2 * exp(X.e2 * m2);
+        }
+    } else {
+        const double ker = lag_kernel_ft<R>(X.kern, md / X.L, X.h);
+        f3 = X.c3 * ker * exp(3.0 * X.psi * m2);
+        if (CCF) f2 = X.c2 * ker * exp(2.0 * X.psi * m2);
+    }
+}
+
+// The factors at the frequency of digit-reversed position p.
 template <typename R, bool CCF>
 __device__ __forceinline__ void product_factors(const ProductCtx<R>& X, const RadixInfo& ri,
                                                 int64_t p, double& f3, double& f2) {
-    const int64_t N = X.N;
     const int64_t k = freq_of_pos(p, ri);
-    const int64_t m = k <= N / 2 ? k : k - N;
-    const double md = (double)m;
-    const double Nd = (double)N;
-    const double L = X.L, h = X.h, s = X.s;
-    const bool keep = (m <= X.M && m >= -X.M);
-    const double a_psi = 2.0 * M_PI * M_PI * s * s * md * md / (Nd * Nd);
-    f3 = 0.0;
-    f2 = 0.0;
-    if (keep) {
-        const double c3 = 1.0 / (L * 15.749609945722419 * s * s * s);
-        const double c2 = 1.0 / (L * 6.283185307179586 * s * s);
-        if (X.kern == NCF_GAUSSIAN) {
-            const double a_h = 2.0 * M_PI * M_PI * h * h * (md / L) * (md / L);
-            if (sizeof(R) == 4) {
-                f3 = c3 * exp_split(3.0 * a_psi - a_h);
-                if (CCF) f2 = c2 * exp_split(2.0 * a_psi - a_h);
-            } else {
-                f3 = c3 * exp(3.0 * a_psi - a_h);
-                if (CCF) f2 = c2 * exp(2.0 * a_psi - a_h);
-            }
-        } else {
-            const double ker = lag_kernel_ft<R>(X.kern, md / L, h);
-            f3 = c3 * ker * exp(3.0 * a_psi);
-            f2 = c2 * ker * exp(2.0 * a_psi);
-        }
-    }
+    product_factors_m<R, CCF>(X, k <= X.N / 2 ? k : k - X.N, f3, f2);
 }
 
 template <typename R, bool CCF, bool WB>
@@ -569,7 +582,7 @@ k_product(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pos0, 
     constexpr bool unit = CCF && WB;   // second (pair-count) grid of a CCF
     const int64_t tb = gb - T.pos0;    // first position of the tile in its grid
     constexpr int kIt = kTile / 2 / kThreads;
-    const ProductCtx<R> X{Z, U, Cg, N, T.M, T.L, T.h, T.s, T.kern};
+    const ProductCtx<R> X = product_ctx<R>(Z, U, Cg, T);
     for (int half = 0; half < (two ? 1 : 2); ++half) {
         int64_t pb[kIt];
         C2 za[kIt], zb[kIt], ua[kIt], ub[kIt], na[kIt], nb[kIt];
@@ -685,7 +698,7 @@ __global__ void k_interp(const SpecTask* __restrict__ tasks, int ntasks, const i
 // Pair q of a grid with 2^m tiles: q = 0 -> k_low = 0; q = 1 -> k_low =
 // 2^(m-1); q >= 2 -> k_low = q - 1 with partner 2^m - k_low.
 __device__ __forceinline__ void mid_pair(int64_t q, const RadixInfo& ri, int64_t& tA,
-                                         int64_t& tB, int64_t& klow) {
+                                         int64_t& tB, int64_t& klow, int64_t& kpart) {
     const int m = ri.lgN - 12;
     int64_t kl = 0, kp = 0;
     if (m > 0 && q == 1) {
@@ -698,6 +711,53 @@ __device__ __forceinline__ void mid_pair(int64_t q, const RadixInfo& ri, int64_t
     tA = pos_of_freq(kl, ri) >> 12;
     tB = pos_of_freq(kp, ri) >> 12;
     klow = kl;
+    kpart = kp;
+}
+
+// The product of the fused kernel in the grid's precision R. The factors
+// (FP64) are rounded to R once per position, with the 1/2 of each unpacked
+// spectrum folded in; the lag-0 partial sums accumulate in FP64. `paired`:
+// the partner is another position (each term counts twice in the sums).
+template <typename R, bool CCF, bool WB, typename C2>
+__device__ __forceinline__ void mid_math(double f3d, double f2d, bool paired, C2 a, C2 b, C2 va,
+                                         C2 vb, double (&sacc)[4], C2& o, C2& oc) {
+    if (!CCF && !WB) {  // f3 |Z|^2
+        o.x = (R)f3d * (a.x * a.x + a.y * a.y);
+        o.y = (R)0;
+        oc = o;
+        return;
+    }
+    const R q = (R)(0.25 * f3d);
+    // twice the unpacked spectra: 2A = Z_m + conj Z_-m, 2B = (Z_m - conj Z_-m)/i
+    const R ar = a.x + b.x, ai = a.y - b.y;
+    const R br = a.y + b.y, bi = b.x - a.x;
+    if (!CCF) {  // |X|^2 + i |W|^2
+        o.x = q * (ar * ar + ai * ai);
+        o.y = q * (br * br + bi * bi);
+        oc = o;
+        return;
+    }
+    const double w = (paired ? 0.5 : 0.25) * f2d;
+    sacc[0] += w * (double)(ar * ar + ai * ai);
+    sacc[1] += w * (double)(br * br + bi * bi);
+    const R gr = ar * br + ai * bi, gi = ar * bi - ai * br;  // 4 conj(X) Y
+    if (!WB) {
+        o.x = q * gr;
+        o.y = q * gi;
+        oc.x = o.x;
+        oc.y = -o.y;
+        return;
+    }
+    const R xr = va.x + vb.x, xi = va.y - vb.y;
+    const R yr = va.y + vb.y, yi = vb.x - va.x;
+    const R hr = xr * yr + xi * yi, hi = xr * yi - xi * yr;  // 4 conj(U_x) U_y
+    sacc[2] += w * (double)(xr * xr + xi * xi);
+    sacc[3] += w * (double)(yr * yr + yi * yi);
+    // G_N + i G_B at m, conj(G_N) + i conj(G_B) at -m
+    o.x = q * (gr - hi);
+    o.y = q * (gi + hr);
+    oc.x = q * (gr + hi);
+    oc.y = q * (hr - gi);
 }
 
 constexpr int kMidPad = 4096 + 4096 / 16;  // one padded LDS tile (fftk::lds_pad)
@@ -729,8 +789,8 @@ k_mid(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pair0, int
     const SpecTask& T = tasks[ti];
     const RadixInfo ri = rinfo[ti];
     const int64_t N = T.N;
-    int64_t tA, tB, kl;
-    mid_pair(blk - pair0[ti], ri, tA, tB, kl);
+    int64_t tA, tB, kl, kp;
+    mid_pair(blk - pair0[ti], ri, tA, tB, kl, kp);
     const bool self = tA == tB;
     C2* const Z = reinterpret_cast<C2*>(T.grid);
     C2* const U = reinterpret_cast<C2*>(T.gridb);
@@ -761,16 +821,20 @@ k_mid(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pair0, int
     C2* const PUB = self ? UA : UB;
     // products: position r of tile tA pairs with r' of tile tB (k_low = 0:
     // r' = -r mod 4096; else r' = 4095 - r)
-    const ProductCtx<R> X{gbl(reinterpret_cast<R*>(T.grid)), gbl(reinterpret_cast<R*>(T.gridb)),
-                          gbl(reinterpret_cast<R*>(T.gridc)), N, T.M, T.L, T.h, T.s, T.kern};
+    const ProductCtx<R> X =
+        product_ctx<R>(gbl(reinterpret_cast<R*>(T.grid)), gbl(reinterpret_cast<R*>(T.gridb)),
+                       gbl(reinterpret_cast<R*>(T.gridc)), T);
     double sacc[4] = {0.0, 0.0, 0.0, 0.0};
     constexpr bool pairs = CCF || WB;
+    // position r of a tile holds frequency k_low + r 2^(lgN - 12)
+    const int lgs = ri.lgN - 12;
+    auto mode_of = [&](int64_t k) { return k <= N / 2 ? k : k - N; };
     // a pair of distinct tiles: every r of tA; one tile: r in [0, 2048)
     // (partners in the upper half), plus r = 2048 when it is its own partner
     const int nown = (!pairs || !self) ? 4096 : 2048;
     for (int r = threadIdx.x; r < nown; r += kMidThreads) {
         const int rp = kl == 0 ? ((4096 - r) & 4095) : (4095 - r);
-        const int64_t p = tA * 4096 + r, pp = tB * 4096 + rp;
+        const bool paired = pairs && (tA != tB || rp != r);
         const C2 za = A[fftk::lds_pad(r)];
         const C2 zb = PB[fftk::lds_pad(rp)];
         C2 ua = za, ub = za;
@@ -778,28 +842,31 @@ k_mid(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pair0, int
             ua = UA[fftk::lds_pad(r)];
             ub = PUB[fftk::lds_pad(rp)];
         }
+        double f3, f2;
+        product_factors_m<R, CCF>(X, mode_of(kl + ((int64_t)r << lgs)), f3, f2);
         C2 o, oc;
-        product_math<R, CCF, WB>(X, ri, p, pairs ? pp : p, za, pairs ? zb : za, ua, ub, sacc, o,
-                                 oc);
+        mid_math<R, CCF, WB>(f3, f2, paired, za, pairs ? zb : za, ua, ub, sacc, o, oc);
         A[fftk::lds_pad(r)] = o;
-        if (pairs && pp != p) PB[fftk::lds_pad(rp)] = oc;
+        if (paired) PB[fftk::lds_pad(rp)] = oc;
     }
     if (!pairs && !self) {  // each position on its own: the second tile too
         for (int r = threadIdx.x; r < 4096; r += kMidThreads) {
-            const int64_t p = tB * 4096 + r;
             const C2 za = Bt[fftk::lds_pad(r)];
+            double f3, f2;
+            product_factors_m<R, CCF>(X, mode_of(kp + ((int64_t)r << lgs)), f3, f2);
             C2 o, oc;
-            product_math<R, CCF, WB>(X, ri, p, p, za, za, za, za, sacc, o, oc);
+            mid_math<R, CCF, WB>(f3, f2, false, za, za, za, za, sacc, o, oc);
             Bt[fftk::lds_pad(r)] = o;
         }
     }
     if (pairs && self && kl == 0 && threadIdx.x == 0) {  // k = N/2 at r = 2048
         const int r = 2048;
-        const int64_t p = tA * 4096 + r;
         const C2 za = A[fftk::lds_pad(r)];
         const C2 ua = TWO ? UA[fftk::lds_pad(r)] : za;
+        double f3, f2;
+        product_factors_m<R, CCF>(X, mode_of((int64_t)r << lgs), f3, f2);
         C2 o, oc;
-        product_math<R, CCF, WB>(X, ri, p, p, za, za, ua, ua, sacc, o, oc);
+        mid_math<R, CCF, WB>(f3, f2, false, za, za, ua, ua, sacc, o, oc);
         A[fftk::lds_pad(r)] = o;
     }
     __syncthreads();

@@ -115,6 +115,7 @@ def lib():
         L.ncf_plan_destroy.argtypes = [_P]
         L.ncf_plan_info.argtypes = [_P, _P]
         L.ncf_profile_enable.argtypes = [ctypes.c_int]
+        L.ncf_profile_filter.argtypes = [ctypes.c_char_p]
         L.ncf_profile_read.argtypes = [_P, ctypes.c_int]
         _lib = L
     return _lib
@@ -618,6 +619,11 @@ def diag_spread_params(sigma, eps):
 
 def profile_enable(on=True):
     lib().ncf_profile_enable(1 if on else 0)
+
+
+def profile_filter(name=None):
+    """Time only launches of kernel `name` (None: every kernel)."""
+    lib().ncf_profile_filter(name.encode() if name else None)
 
 
 def profile_read():

@@ -26,8 +26,8 @@ def _declared():
 def test_headers_declare_entry_points():
     names = _declared()
     for required in ("ncf_acf", "ncf_ccf", "ncf_acf_batch", "ncf_ccf_batch", "ncf_last_error",
-                     "ncf_diag_fft", "ncf_diag_type1", "ncf_profile_read", "ncf_acf_regular",
-                     "ncf_ccf_regular", "ncf_acf_regular_batch", "ncf_ccf_regular_batch",
+                     "ncf_diag_fft", "ncf_diag_type1", "ncf_profile_read", "ncf_profile_filter",
+                     "ncf_acf_regular", "ncf_ccf_regular", "ncf_acf_regular_batch", "ncf_ccf_regular_batch",
                      "ncf_acf_resample", "ncf_ccf_resample"):
         assert required in names
 
