@@ -1245,7 +1245,11 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         double* ev;
         void** gfwd;
         void** ginv;
+        int32_t* rowk;   // evaluation index of each window row (-1: none)
+        uint64_t* mask;  // fallback flags, written on the device and read back
     } dT{}, hT{};
+    const int fwords = (int)ceil_div(std::max(Krow, 1), 64);
+    const bool flag_pass = spec_b && nts > 0 && K > 0;
     size_t ndl = 0;
     for (auto& P : W1.plans) ndl += P.dl.size();
     auto take2 = [&](Tables& tb) {
@@ -1264,6 +1268,8 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         dT.ev = tb.take<double>(Keval, &hT.ev);
         dT.gfwd = tb.take<void*>(3 * (size_t)nts, &hT.gfwd);
         dT.ginv = tb.take<void*>(2 * (size_t)nts, &hT.ginv);
+        dT.rowk = tb.take<int32_t>(flag_pass ? Krow : 0, &hT.rowk);
+        dT.mask = tb.take<uint64_t>(flag_pass ? (size_t)nts * fwords : 0, &hT.mask);
     };
     Tables t2;
     take2(t2);
@@ -1402,6 +1408,8 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         for (int64_t k = 0; k < K; ++k) hT.ev[k] = J.lags[k];
         if (!J.ccf) hT.ev[K] = 0.0;
     }
+    if (flag_pass)
+        for (int r = 0; r < Krow; ++r) hT.rowk[r] = rows[r].second;
     NCF_TRY_HIP(hipMemcpyAsync(stg2->d, stg2->h, t2.off, hipMemcpyHostToDevice, J.st));
 
     // ------------------------------------------------ A7 window scan
@@ -1490,29 +1498,24 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     for (int i = 0; i < nts; ++i) spec_of[splans[i].prob] = i;
     std::vector<std::vector<int>> flagged(J.nprob);  // requested lag indices
     WinLaunch W2;
-    if (spec_b && nts > 0 && K > 0) {
-        // the spectral b values of all problems are contiguous in the arena
-        std::vector<double> hb((size_t)nts * Keval);
-        NCF_TRY_HIP(hipMemcpyAsync(hb.data(), bspec[0], sizeof(double) * Keval * nts,
+    if (flag_pass) {
+        // flags computed on the device from the spectral b values (contiguous
+        // over the problems); only the bit masks come back
+        NCF_TRY(launch_fallback_flags(bspec[0], nts, Keval, (int)K, J.ccf, dT.rowk, Krow, beta,
+                                      dT.mask, J.st));
+        NCF_TRY_HIP(hipMemcpyAsync(hT.mask, dT.mask, sizeof(uint64_t) * (size_t)nts * fwords,
                                    hipMemcpyDeviceToHost, J.st));
         NCF_TRY_HIP(hipStreamSynchronize(J.st));
         for (int i = 0; i < nts; ++i) {
             const int64_t p = splans[i].prob;
-            const double* bb = hb.data() + (size_t)i * Keval;
-            double bref = 0.0;
-            if (!J.ccf)
-                bref = bb[K];
-            else
-                for (int64_t k = 0; k < K; ++k) bref = std::max(bref, bb[k]);
+            const uint64_t* mw = hT.mask + (size_t)i * fwords;
             std::vector<double> dl;
-            for (int r = 0; r < Krow; ++r) {
-                const int k = rows[r].second;
-                if (k < 0) continue;
-                if (!(bb[k] >= beta * bref) || !(bref > 0.0)) {
-                    flagged[p].push_back(k);
+            for (int w = 0; w < fwords; ++w)
+                for (uint64_t m = mw[w]; m; m &= m - 1) {
+                    const int r = w * 64 + __builtin_ctzll(m);
+                    flagged[p].push_back(rows[r].second);
                     dl.push_back(delta[r]);
                 }
-            }
             if (!dl.empty())
                 W2.plans.push_back({0, J.ccf ? 1 : 0, p, 3, dl});
         }

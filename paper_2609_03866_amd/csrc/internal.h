@@ -321,6 +321,14 @@ int launch_tile_bounds(const SpecTask* d_tasks, const Chunk* d_chunks, int nchun
 int launch_spread(const SpecTask* d_tasks, const int64_t* d_tile0, int ntasks, int64_t ntiles,
                   const int64_t* d_tile_rec, int tile, bool ccf, bool with_b, bool weighted,
                   bool unw, bool fp64, hipStream_t st, double bytes);
+// Bit masks of the window rows whose spectral pair count falls back to the
+// direct sums (b below beta times the problem's reference): bspec holds the
+// problems' Keval evaluations contiguously, rowk the evaluation index of each
+// of the Krow window rows (-1: none); mask gets ceil(Krow / 64) words per
+// problem.
+int launch_fallback_flags(const double* bspec, int64_t nprob, int Keval, int K, bool ccf,
+                          const int32_t* rowk, int Krow, double beta, uint64_t* mask,
+                          hipStream_t st);
 int launch_interp(const SpecTask* d_tasks, int ntasks, const int64_t* d_k0, int64_t total_k,
                   bool fp64, hipStream_t st);
 

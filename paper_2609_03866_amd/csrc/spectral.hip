@@ -898,6 +898,46 @@ k_mid(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pair0, int
     }
 }
 
+// Fallback flags of the spectral pair counts, one workgroup per problem:
+// window row r is flagged when its spectral b (evaluation index rowk[r]; -1:
+// no requested lag) is below beta times the reference (ACF: the lag-0 entry;
+// CCF: the largest over the requested lags, NaN ignored, at least 0), or when
+// the reference is not positive. Bit r % 64 of mask[i * words + r / 64].
+constexpr int kFlagThreads = 256;
+
+__global__ void __launch_bounds__(kFlagThreads)
+k_fallback_flags(const double* __restrict__ bspec, int Keval, int K, int ccf,
+                 const int32_t* __restrict__ rowk, int Krow, double beta, int words,
+                 uint64_t* __restrict__ mask) {
+    const int64_t i = blockIdx.x;
+    const gptr<const double> bb = gbl(bspec) + i * Keval;
+    __shared__ double red[kFlagThreads / 64];
+    double bref;
+    if (ccf) {
+        double m = 0.0;
+        for (int k = threadIdx.x; k < K; k += kFlagThreads) m = fmax(m, bb[k]);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+        __syncthreads();
+        bref = red[0];
+#pragma unroll
+        for (int w = 1; w < kFlagThreads / 64; ++w) bref = fmax(bref, red[w]);
+    } else {
+        bref = bb[K];
+    }
+    for (int r0 = 0; r0 < Krow; r0 += kFlagThreads) {
+        const int r = r0 + (int)threadIdx.x;
+        bool f = false;
+        if (r < Krow) {
+            const int k = gbl(rowk)[r];
+            if (k >= 0) f = !(bb[k] >= beta * bref) || !(bref > 0.0);
+        }
+        const unsigned long long bits = __ballot(f);
+        if ((threadIdx.x & 63) == 0 && r < Krow) gbl(mask)[i * words + r / 64] = bits;
+    }
+}
+
 }  // namespace
 
 SpreadParams spread_params(double sigma, double eps) {
@@ -988,6 +1028,21 @@ int launch_product(const SpecTask* d_tasks, const int64_t* d_pos0, int ntasks, i
     else
         hipLaunchKernelGGL(product_kernel<float>(mode), dim3((unsigned)ceil_div(total, kTile)),
                            dim3(kThreads), 0, st, d_tasks, d_pos0, ntasks, total, ri);
+    NCF_CHECK_LAUNCH();
+    return NCF_OK;
+}
+
+int launch_fallback_flags(const double* bspec, int64_t nprob, int Keval, int K, bool ccf,
+                          const int32_t* rowk, int Krow, double beta, uint64_t* mask,
+                          hipStream_t st) {
+    if (nprob <= 0 || Krow <= 0) return NCF_OK;
+    if (nprob > INT32_MAX) {
+        set_error("fallback flags: %lld problems", (long long)nprob);
+        return NCF_E_INVALID_ARG;
+    }
+    ProfScope p(st, "fallback_flags", 0.0, "bytes");
+    hipLaunchKernelGGL(k_fallback_flags, dim3((unsigned)nprob), dim3(kFlagThreads), 0, st, bspec,
+                       Keval, K, ccf ? 1 : 0, rowk, Krow, beta, (int)ceil_div(Krow, 64), mask);
     NCF_CHECK_LAUNCH();
     return NCF_OK;
 }

@@ -252,6 +252,29 @@ def test_sparse_lags_take_the_direct_fallback(prec, method, ctol, btol):
 
 
 @pytest.mark.parametrize("prec,method,ctol,btol", MODES)
+def test_batch_fallback_sets_differ_per_series(prec, method, ctol, btol):
+    # the fallback lags are flagged per series on the device (one bit per
+    # lag row, 64 rows to a word): series of different spans flag different
+    # lag sets, among them sets that start and end inside a word and span
+    # several words (200 lags: 4 words)
+    rng = synth.rng_for(36)
+    ts, xs = [], []
+    for span_frac in (0.25, 0.6, 1.0, 0.4):
+        t = np.sort(rng.uniform(0.0, 200.0 * span_frac, int(300 * span_frac) + 40))
+        ts.append(t)
+        xs.append(synth.ou_at_times(rng, t, 6.0) + 0.2 * rng.standard_normal(t.size))
+    offs = np.concatenate([[0], np.cumsum([t.size for t in ts])])
+    lags = np.arange(0.0, 200.0)
+    c, b, n, st, rc = ncf.acf_batch(offs, np.concatenate(ts), np.concatenate(xs), lags,
+                                    "gaussian", 0.5, precision=prec, method=method)
+    assert rc == 0 and np.all(st == 0)
+    for i, (t, x) in enumerate(zip(ts, xs)):
+        ost, oc, ob, on = O.acf(t, x, lags, "gaussian", 0.5)
+        assert ost == 0
+        _check(c[i], b[i], n[i], oc, ob, on, "gaussian", ctol, btol)
+
+
+@pytest.mark.parametrize("prec,method,ctol,btol", MODES)
 def test_ccf_with_partly_empty_lags(prec, method, ctol, btol):
     # series 2 covers only part of series 1's span: lags beyond the overlap
     # have no pairs at all, lags at its edge only a few
