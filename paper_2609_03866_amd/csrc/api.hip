@@ -1498,6 +1498,20 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     for (int i = 0; i < nts; ++i) spec_of[splans[i].prob] = i;
     std::vector<std::vector<int>> flagged(J.nprob);  // requested lag indices
     WinLaunch W2;
+    // Phase 3 (fallback window scans, normalization, outputs) is enqueued by
+    // enqueue_phase3 below; for the spectral pair counts of a one-shot call
+    // it is first enqueued speculatively with no fallback lags, together
+    // with the readback of the fallback flags: when no lag is flagged (the
+    // common case) those outputs are final and the call ends on one round
+    // trip; otherwise phase 3 runs again with the flagged lags and rewrites
+    // every output. Only calls of a few problems speculate: in large batches
+    // some series nearly always has a flagged lag, and phase 3 would be
+    // planned and uploaded twice. Recorded launch sequences (plans) take the
+    // final path only.
+    constexpr int64_t kSpeculateMaxProblems = 8;
+    const bool speculate = flag_pass && !J.rec && J.nprob <= kSpeculateMaxProblems;
+    int32_t* h_fstat = nullptr;
+    std::function<int()> enqueue_phase3;
     if (flag_pass) {
         // flags computed on the device from the spectral b values (contiguous
         // over the problems); only the bit masks come back
@@ -1505,7 +1519,8 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
                                       dT.mask, J.st));
         NCF_TRY_HIP(hipMemcpyAsync(hT.mask, dT.mask, sizeof(uint64_t) * (size_t)nts * fwords,
                                    hipMemcpyDeviceToHost, J.st));
-        NCF_TRY_HIP(hipStreamSynchronize(J.st));
+    }
+    auto read_flags = [&]() {
         for (int i = 0; i < nts; ++i) {
             const int64_t p = splans[i].prob;
             const uint64_t* mw = hT.mask + (size_t)i * fwords;
@@ -1519,176 +1534,195 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             if (!dl.empty())
                 W2.plans.push_back({0, J.ccf ? 1 : 0, p, 3, dl});
         }
-        plan_window(W2);
-    }
-    const int ntw2 = (int)W2.plans.size();
-    J.info_window_items += W2.nitems;
-    J.info_window_launches += ntw2 > 0 ? 1 : 0;
-    const uint32_t wflags2 = (fp64 ? (uint32_t)WIN_EXP64 : 0u) | (uint32_t)WIN_NUMER |
-                             (weighted ? (uint32_t)WIN_WEIGHTED : 0u);
+    };
+    enqueue_phase3 = [&]() -> int {
+        const int ntw2 = (int)W2.plans.size();
+        const uint32_t wflags2 = (fp64 ? (uint32_t)WIN_EXP64 : 0u) | (uint32_t)WIN_NUMER |
+                                 (weighted ? (uint32_t)WIN_WEIGHTED : 0u);
 
-    // fallback workspace and the output tables
-    auto layout3 = [&](Arena& ar) {
-        for (int i = 0; i < ntw2; ++i) {
-            WinTask& T = W2.wt[i];
-            T.part = ar.take<double>((size_t)T.n_jt * T.K * 4);
-            T.part2 = ar.take<double>((size_t)ceil_div(T.n_jt, kWinJc) * T.K * 4);
-            T.sums = ar.take<double>((size_t)T.K * 4);
-        }
-    };
-    Arena a3;
-    layout3(a3);
-    if (ntw2 > 0) {
-        void* ws3 = nullptr;
-        NCF_TRY(ensure_ws(R, 2, a3.off + 256, &ws3));
-        a3 = Arena{(char*)ws3, 0};
-        layout3(a3);
-    }
-    struct T3 {
-        WinTask* wt;
-        int64_t *item0, *wk0, *r0;
-        double* dl;
-        int32_t* fbrow;
-        int32_t* perm;
-        NormTask* nt;
-        int32_t* status;
-        IoBlock* io;
-    } dU{}, hU{};
-    size_t ndl2 = 0;
-    for (auto& P : W2.plans) ndl2 += P.dl.size();
-    const bool any_fb = ntw2 > 0;
-    auto take3 = [&](Tables& tb) {
-        dU.wt = tb.take<WinTask>(ntw2, &hU.wt);
-        dU.item0 = tb.take<int64_t>(ntw2 + 1, &hU.item0);
-        dU.wk0 = tb.take<int64_t>(ntw2 + 1, &hU.wk0);
-        dU.r0 = tb.take<int64_t>(ntw2 + 1, &hU.r0);
-        dU.dl = tb.take<double>(ndl2, &hU.dl);
-        dU.fbrow = tb.take<int32_t>(any_fb ? (size_t)J.nprob * K : 1, &hU.fbrow);
-        dU.perm = tb.take<int32_t>(K, &hU.perm);
-        dU.nt = tb.take<NormTask>(J.nprob, &hU.nt);
-        dU.status = tb.take<int32_t>(J.nprob, &hU.status);
-        dU.io = tb.take<IoBlock>(1, &hU.io);
-    };
-    Tables t3;
-    take3(t3);
-    Staging* stg3 = nullptr;
-    NCF_TRY(ensure_stage(R, 2, t3.off, &stg3));
-    t3 = Tables{stg3->h, stg3->d, 0};
-    take3(t3);
-    std::vector<int> fb_task(J.nprob, -1);
-    {
-        size_t o = 0;
-        for (int i = 0; i < ntw2; ++i) {
-            std::memcpy(hU.dl + o, W2.plans[i].dl.data(), sizeof(double) * W2.plans[i].dl.size());
-            W2.wt[i].delta = dU.dl + o;
-            o += W2.plans[i].dl.size();
-            fb_task[W2.plans[i].prob] = i;
-        }
-        if (ntw2) {
-            std::memcpy(hU.wt, W2.wt.data(), sizeof(WinTask) * ntw2);
-            std::memcpy(hU.item0, W2.item0.data(), sizeof(int64_t) * (ntw2 + 1));
-            std::memcpy(hU.wk0, W2.wk0.data(), sizeof(int64_t) * (ntw2 + 1));
-            std::memcpy(hU.r0, W2.r0.data(), sizeof(int64_t) * (ntw2 + 1));
-        }
-        if (any_fb) {
-            for (int64_t i = 0; i < J.nprob * K; ++i) hU.fbrow[i] = -1;
-            // flagged lags are in sorted-row order; their fallback row is their rank
-            for (int64_t p = 0; p < J.nprob; ++p)
-                for (size_t q = 0; q < flagged[p].size(); ++q)
-                    hU.fbrow[p * K + flagged[p][q]] = (int32_t)q;
-        }
-    }
-    // normalization tables
-    std::memcpy(hU.perm, perm.data(), sizeof(int32_t) * K);
-    {
-        std::vector<int> main_t(J.nprob, -1), selfx(J.nprob, -1), selfy(J.nprob, -1);
-        for (int i = 0; i < ntw; ++i) {
-            const WinPlan& P = W1.plans[i];
-            (P.role == 0 ? main_t : P.role == 1 ? selfx : selfy)[P.prob] = i;
-        }
-        for (int64_t p = 0; p < J.nprob; ++p) {
-            NormTask T{};
-            T.ccf = J.ccf ? 1 : 0;
-            T.K = (int32_t)K;
-            T.perm = dU.perm;
-            T.row0 = row0;
-            T.spectral = spectral ? 1 : 0;
-            T.spec_b = spec_b ? 1 : 0;
-            T.weighted = weighted ? 1 : 0;
-            T.is_rect = rect ? 1 : 0;
-            T.beta = beta;
-            T.out_off = p * K;
-            T.index = p;
-            T.st0 = d_stats + J.set[0].sd0 + p;
-            T.st1 = J.ccf ? d_stats + J.set[1].sd0 + p : nullptr;
-            hU.status[p] = pstat[p];
-            if (pstat[p] == NCF_OK) {
-                if (main_t[p] >= 0) T.wsums = W1.wt[main_t[p]].sums;
-                if (J.ccf && selfx[p] >= 0) {
-                    T.self_x = W1.wt[selfx[p]].sums;
-                    T.self_y = W1.wt[selfy[p]].sums;
-                }
-                if (spectral) {
-                    const int i = spec_of[p];
-                    T.numer = numer[i];
-                    T.bspec = bspec[i];
-                    T.bunw = bunw[i];
-                    T.scale_part = spart[i];
-                    T.nscale_part = splans[i].g.N / 4096;
-                }
-                if (fb_task[p] >= 0) {
-                    T.fb_row = dU.fbrow + p * K;
-                    T.fb_sums = W2.wt[fb_task[p]].sums;
-                }
-            } else {
-                T.skip = 1;  // outputs: c = NaN, b = 0, count = 0
-                T.skip_status = pstat[p];
+        // fallback workspace and the output tables
+        auto layout3 = [&](Arena& ar) {
+            for (int i = 0; i < ntw2; ++i) {
+                WinTask& T = W2.wt[i];
+                T.part = ar.take<double>((size_t)T.n_jt * T.K * 4);
+                T.part2 = ar.take<double>((size_t)ceil_div(T.n_jt, kWinJc) * T.K * 4);
+                T.sums = ar.take<double>((size_t)T.K * 4);
             }
-            hU.nt[p] = T;
+        };
+        Arena a3;
+        layout3(a3);
+        if (ntw2 > 0) {
+            void* ws3 = nullptr;
+            NCF_TRY(ensure_ws(R, 2, a3.off + 256, &ws3));
+            a3 = Arena{(char*)ws3, 0};
+            layout3(a3);
         }
-    }
-    // caller arrays of the normalization (one-shot calls)
-    hU.io->x[0] = J.set[0].x;
-    hU.io->x[1] = J.ccf ? J.set[1].x : nullptr;
-    hU.io->c = d_c;
-    hU.io->b = d_b;
-    hU.io->count = d_cnt;
-    hU.io->status = dU.status;
-    NCF_TRY_HIP(hipMemcpyAsync(stg3->d, stg3->h, t3.off, hipMemcpyHostToDevice, J.st));
-    if (ntw2 > 0) {
-        const WinTask* wt = dU.wt;
-        const int64_t *it0 = dU.item0, *wk0 = dU.wk0, *r0 = dU.r0;
-        const int64_t nitems = W2.nitems, rows = W2.total_rows, nred1 = W2.nred1;
-        const int cap = W2.cap, jmax = W2.jmax;
-        const double work = W2.work;
-        unsigned long long* q = qbase ? qbase + 2 : nullptr;
-        NCF_TRY(emit(J, [=](hipStream_t s) {
-            return launch_window(wt, it0, ntw2, nitems, wflags2, cap, jmax, q, s, work);
-        }));
-        NCF_TRY(emit(J, [=](hipStream_t s) {
-            return launch_window_reduce(wt, ntw2, rows, wk0, r0, nred1, wflags2, s);
-        }));
-    }
+        struct T3 {
+            WinTask* wt;
+            int64_t *item0, *wk0, *r0;
+            double* dl;
+            int32_t* fbrow;
+            int32_t* perm;
+            NormTask* nt;
+            int32_t* status;
+            IoBlock* io;
+        } dU{}, hU{};
+        size_t ndl2 = 0;
+        for (auto& P : W2.plans) ndl2 += P.dl.size();
+        const bool any_fb = ntw2 > 0;
+        auto take3 = [&](Tables& tb) {
+            dU.wt = tb.take<WinTask>(ntw2, &hU.wt);
+            dU.item0 = tb.take<int64_t>(ntw2 + 1, &hU.item0);
+            dU.wk0 = tb.take<int64_t>(ntw2 + 1, &hU.wk0);
+            dU.r0 = tb.take<int64_t>(ntw2 + 1, &hU.r0);
+            dU.dl = tb.take<double>(ndl2, &hU.dl);
+            dU.fbrow = tb.take<int32_t>(any_fb ? (size_t)J.nprob * K : 1, &hU.fbrow);
+            dU.perm = tb.take<int32_t>(K, &hU.perm);
+            dU.nt = tb.take<NormTask>(J.nprob, &hU.nt);
+            dU.status = tb.take<int32_t>(J.nprob, &hU.status);
+            dU.io = tb.take<IoBlock>(1, &hU.io);
+        };
+        Tables t3;
+        take3(t3);
+        Staging* stg3 = nullptr;
+        NCF_TRY(ensure_stage(R, 2, t3.off, &stg3));
+        t3 = Tables{stg3->h, stg3->d, 0};
+        take3(t3);
+        std::vector<int> fb_task(J.nprob, -1);
+        {
+            size_t o = 0;
+            for (int i = 0; i < ntw2; ++i) {
+                std::memcpy(hU.dl + o, W2.plans[i].dl.data(), sizeof(double) * W2.plans[i].dl.size());
+                W2.wt[i].delta = dU.dl + o;
+                o += W2.plans[i].dl.size();
+                fb_task[W2.plans[i].prob] = i;
+            }
+            if (ntw2) {
+                std::memcpy(hU.wt, W2.wt.data(), sizeof(WinTask) * ntw2);
+                std::memcpy(hU.item0, W2.item0.data(), sizeof(int64_t) * (ntw2 + 1));
+                std::memcpy(hU.wk0, W2.wk0.data(), sizeof(int64_t) * (ntw2 + 1));
+                std::memcpy(hU.r0, W2.r0.data(), sizeof(int64_t) * (ntw2 + 1));
+            }
+            if (any_fb) {
+                for (int64_t i = 0; i < J.nprob * K; ++i) hU.fbrow[i] = -1;
+                // flagged lags are in sorted-row order; their fallback row is their rank
+                for (int64_t p = 0; p < J.nprob; ++p)
+                    for (size_t q = 0; q < flagged[p].size(); ++q)
+                        hU.fbrow[p * K + flagged[p][q]] = (int32_t)q;
+            }
+        }
+        // normalization tables
+        std::memcpy(hU.perm, perm.data(), sizeof(int32_t) * K);
+        {
+            std::vector<int> main_t(J.nprob, -1), selfx(J.nprob, -1), selfy(J.nprob, -1);
+            for (int i = 0; i < ntw; ++i) {
+                const WinPlan& P = W1.plans[i];
+                (P.role == 0 ? main_t : P.role == 1 ? selfx : selfy)[P.prob] = i;
+            }
+            for (int64_t p = 0; p < J.nprob; ++p) {
+                NormTask T{};
+                T.ccf = J.ccf ? 1 : 0;
+                T.K = (int32_t)K;
+                T.perm = dU.perm;
+                T.row0 = row0;
+                T.spectral = spectral ? 1 : 0;
+                T.spec_b = spec_b ? 1 : 0;
+                T.weighted = weighted ? 1 : 0;
+                T.is_rect = rect ? 1 : 0;
+                T.beta = beta;
+                T.out_off = p * K;
+                T.index = p;
+                T.st0 = d_stats + J.set[0].sd0 + p;
+                T.st1 = J.ccf ? d_stats + J.set[1].sd0 + p : nullptr;
+                hU.status[p] = pstat[p];
+                if (pstat[p] == NCF_OK) {
+                    if (main_t[p] >= 0) T.wsums = W1.wt[main_t[p]].sums;
+                    if (J.ccf && selfx[p] >= 0) {
+                        T.self_x = W1.wt[selfx[p]].sums;
+                        T.self_y = W1.wt[selfy[p]].sums;
+                    }
+                    if (spectral) {
+                        const int i = spec_of[p];
+                        T.numer = numer[i];
+                        T.bspec = bspec[i];
+                        T.bunw = bunw[i];
+                        T.scale_part = spart[i];
+                        T.nscale_part = splans[i].g.N / 4096;
+                    }
+                    if (fb_task[p] >= 0) {
+                        T.fb_row = dU.fbrow + p * K;
+                        T.fb_sums = W2.wt[fb_task[p]].sums;
+                    }
+                } else {
+                    T.skip = 1;  // outputs: c = NaN, b = 0, count = 0
+                    T.skip_status = pstat[p];
+                }
+                hU.nt[p] = T;
+            }
+        }
+        // caller arrays of the normalization (one-shot calls)
+        hU.io->x[0] = J.set[0].x;
+        hU.io->x[1] = J.ccf ? J.set[1].x : nullptr;
+        hU.io->c = d_c;
+        hU.io->b = d_b;
+        hU.io->count = d_cnt;
+        hU.io->status = dU.status;
+        NCF_TRY_HIP(hipMemcpyAsync(stg3->d, stg3->h, t3.off, hipMemcpyHostToDevice, J.st));
+        if (ntw2 > 0) {
+            const WinTask* wt = dU.wt;
+            const int64_t *it0 = dU.item0, *wk0 = dU.wk0, *r0 = dU.r0;
+            const int64_t nitems = W2.nitems, rows = W2.total_rows, nred1 = W2.nred1;
+            const int cap = W2.cap, jmax = W2.jmax;
+            const double work = W2.work;
+            unsigned long long* q = qbase ? qbase + 2 : nullptr;
+            NCF_TRY(emit(J, [=](hipStream_t s) {
+                return launch_window(wt, it0, ntw2, nitems, wflags2, cap, jmax, q, s, work);
+            }));
+            NCF_TRY(emit(J, [=](hipStream_t s) {
+                return launch_window_reduce(wt, ntw2, rows, wk0, r0, nred1, wflags2, s);
+            }));
+        }
 
-    // ------------------------------------------------ A8 normalization, outputs
-    {
-        const NormTask* nt = dU.nt;
-        const int np = (int)J.nprob;
-        const IoBlock* io = J.io_fixed ? J.io_fixed : dU.io;
-        NCF_TRY(emit(J, [=](hipStream_t s) { return launch_normalize(nt, np, io, s); }));
+        // ------------------------------------------------ A8 normalization, outputs
+        {
+            const NormTask* nt = dU.nt;
+            const int np = (int)J.nprob;
+            const IoBlock* io = J.io_fixed ? J.io_fixed : dU.io;
+            NCF_TRY(emit(J, [=](hipStream_t s) { return launch_normalize(nt, np, io, s); }));
+        }
+        h_fstat = hU.status;  // pinned; its upload was enqueued before
+        NCF_TRY_HIP(hipMemcpyAsync(h_fstat, J.io_fixed ? J.io_status : dU.status,
+                                   sizeof(int32_t) * J.nprob, hipMemcpyDeviceToHost, J.st));
+        if (!J.dev_ptrs && K > 0) {
+            NCF_TRY_HIP(hipMemcpyAsync(J.c, d_c, sizeof(double) * J.nprob * K, hipMemcpyDeviceToHost,
+                                       J.st));
+            NCF_TRY_HIP(hipMemcpyAsync(J.b, d_b, sizeof(double) * J.nprob * K, hipMemcpyDeviceToHost,
+                                       J.st));
+            if (J.count)
+                NCF_TRY_HIP(hipMemcpyAsync(J.count, d_cnt, sizeof(int64_t) * J.nprob * K,
+                                           hipMemcpyDeviceToHost, J.st));
+        }
+        return NCF_OK;
+    };
+    if (speculate) {
+        NCF_TRY(enqueue_phase3());
+        NCF_TRY_HIP(hipStreamSynchronize(J.st));
+        read_flags();
+        if (W2.plans.empty()) {
+            if (g_prof_on) {
+                std::lock_guard<std::mutex> lock(g_prof_mu);
+                prof_flush_locked();
+            }
+            return finish_status(J, pstat, h_fstat);
+        }
+    } else if (flag_pass) {
+        NCF_TRY_HIP(hipStreamSynchronize(J.st));
+        read_flags();
     }
-    int32_t* h_fstat = hU.status;  // pinned; its upload was enqueued before
-    NCF_TRY_HIP(hipMemcpyAsync(h_fstat, J.io_fixed ? J.io_status : dU.status,
-                               sizeof(int32_t) * J.nprob, hipMemcpyDeviceToHost, J.st));
-    if (!J.dev_ptrs && K > 0) {
-        NCF_TRY_HIP(hipMemcpyAsync(J.c, d_c, sizeof(double) * J.nprob * K, hipMemcpyDeviceToHost,
-                                   J.st));
-        NCF_TRY_HIP(hipMemcpyAsync(J.b, d_b, sizeof(double) * J.nprob * K, hipMemcpyDeviceToHost,
-                                   J.st));
-        if (J.count)
-            NCF_TRY_HIP(hipMemcpyAsync(J.count, d_cnt, sizeof(int64_t) * J.nprob * K,
-                                       hipMemcpyDeviceToHost, J.st));
-    }
+    if (!W2.plans.empty()) plan_window(W2);
+    J.info_window_items += W2.nitems;
+    J.info_window_launches += W2.plans.empty() ? 0 : 1;
+    NCF_TRY(enqueue_phase3());
     NCF_TRY_HIP(hipStreamSynchronize(J.st));
     if (g_prof_on) {
         std::lock_guard<std::mutex> lock(g_prof_mu);
