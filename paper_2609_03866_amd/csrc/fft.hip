@@ -43,7 +43,9 @@ k_fft_pass(PassArgs a) {
     constexpr int lgC = LGT - LGR;
     constexpr int kElems = 1 << LGT;
     __shared__ C2 buf[kElems + kElems / 16];
-    const int64_t wg = blockIdx.x;
+    // XCD-aware order: each XCD takes a contiguous run of tiles (adjacent
+    // column chunks of the same rows)
+    const int64_t wg = xcd_remap(blockIdx.x, a.nblocks);
     if (wg >= a.ntiles) return;
     const int64_t gidx = wg / a.tiles_per_grid;
     const int64_t tile = wg % a.tiles_per_grid;
