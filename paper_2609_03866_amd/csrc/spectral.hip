@@ -193,25 +193,29 @@ __device__ void gather_set(R (&acc)[kCellsPerThread], R (&accu)[kCellsPerThread]
             else
                 hi = mid;
         }
+        const R W2 = W * W;
         for (int i = lo; i < np; ++i) {
             const int ci = P.cell[i];
             if (ci > need_hi) break;
             const R fr = P.frac[i];
             const R vv = P.val[i];
             const R ww = WGT ? P.wgt[i] : (R)1;
+            // offset of the point from the thread's first cell, as an exact
+            // integer in R; cell q is at d = (m0 - q) + fr (m0 - q exact)
+            const R m0 = (R)(ci - cb);
 #pragma unroll
             for (int q = 0; q < kCellsPerThread; ++q) {
-                const R d = (R)(ci - (cb + q)) + fr;
-                if (d <= W && d >= -W) {
-                    R e;
-                    if constexpr (sizeof(R) == 4)
-                        e = __builtin_amdgcn_exp2f(d * d * k2);
-                    else
-                        e = exp(d * d * k2);
-                    acc[q] += e * vv;
-                    if (UNIT) accu[q] += WGT ? e * ww : e;  // pair-count channel
-                    if (UNW) accn[q] += e;                  // unweighted pair count
-                }
+                const R d = (m0 - (R)q) + fr;
+                const R d2 = d * d;
+                R e;
+                if constexpr (sizeof(R) == 4)
+                    e = __builtin_amdgcn_exp2f(d2 * k2);
+                else
+                    e = exp(d2 * k2);
+                e = d2 <= W2 ? e : (R)0;  // the kernel's support |d| <= W
+                acc[q] += e * vv;
+                if (UNIT) accu[q] += WGT ? e * ww : e;  // pair-count channel
+                if (UNW) accn[q] += e;                  // unweighted pair count
             }
         }
     }
