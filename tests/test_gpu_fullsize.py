@@ -1,0 +1,126 @@
+"""GPU parity at the benchmark workloads' full sizes, in the call shape the
+benchmark times: one call over the whole batch with the inputs resident on
+the device (torch tensors, device pointers). The oracle computes a sample of
+the outputs one by one: the largest and the smallest series (pairs) of the
+batch and a few drawn at random, and for the replicate error bars three of
+the replicates. Tolerances are those of the single-call parity tests: mixed
+precision |dc| <= 1e-5 and pair counts within 1e-5 of the largest; rectangle
+and lattice counts exact.
+
+Generating c4 and c5 takes most of these tests' time (about a minute each on
+the host): the series are made by the same generators as the benchmark's.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2609_03866_amd import ncf, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), device=torch.device("cuda:0"))
+
+
+def _host(a):
+    import torch
+    torch.cuda.synchronize()
+    return a.cpu().numpy()
+
+
+def _sample(sizes, n_random, seed):
+    order = np.argsort(sizes, kind="stable")
+    rng = synth.rng_for(seed)
+    pick = {int(order[0]), int(order[-1])}
+    pick.update(int(i) for i in rng.choice(len(sizes), n_random, replace=False))
+    return sorted(pick)
+
+
+def _check_gauss(c, b, oc, ob):
+    assert np.all(np.isfinite(c))
+    err = np.max(np.abs(c - oc))
+    assert err <= 1e-5, f"max |dc| = {err:.3e}"
+    np.testing.assert_allclose(b, ob, rtol=0, atol=1e-5 * np.max(ob))
+
+
+def _check_exact(c, b, n, oc, on, ctol):
+    assert np.all(np.isfinite(c))
+    err = np.max(np.abs(c - oc))
+    assert err <= ctol, f"max |dc| = {err:.3e}"
+    np.testing.assert_array_equal(n, on)
+    np.testing.assert_array_equal(b, np.maximum(on.astype(float), 1e-16))
+
+
+def test_c4_full_size_sampled_series():
+    # 10,000 light curves of 100 to 5e4 samples, 256 lags, Gaussian, mixed
+    d = synth.c4()
+    offs = d["offs"]
+    c, b, n, st, rc = ncf.acf_batch(offs, _dev(d["t"]), _dev(d["x"]), _dev(d["lags"]),
+                                    "gaussian", d["h"])
+    c, b = _host(c), _host(b)
+    assert rc == 0 and np.all(np.asarray(st) == 0)
+    for i in _sample(np.diff(offs), 4, 41):
+        sl = slice(offs[i], offs[i + 1])
+        ost, oc, ob, _ = O.acf(d["t"][sl], d["x"][sl], d["lags"], "gaussian", d["h"][i])
+        assert ost == 0
+        _check_gauss(c[i], b[i], oc, ob)
+
+
+def test_c5_full_size_sampled_pairs():
+    # 2,048 pairs of 1e3 to 2e5 samples, 512 lags, rectangle: exact counts
+    d = synth.c5()
+    offx, offy = d["offx"], d["offy"]
+    c, b, n, st, rc = ncf.ccf_batch(offx, _dev(d["t"]), _dev(d["x"]), offy, _dev(d["s"]),
+                                    _dev(d["y"]), _dev(d["lags"]), "rectangle", d["h"])
+    c, b, n = _host(c), _host(b), _host(n)
+    assert rc == 0 and np.all(np.asarray(st) == 0)
+    sizes = np.diff(offx) + np.diff(offy)
+    for p in _sample(sizes, 2, 42):
+        sx, sy = slice(offx[p], offx[p + 1]), slice(offy[p], offy[p + 1])
+        ost, oc, _, on = O.ccf(d["t"][sx], d["x"][sx], d["s"][sy], d["y"][sy], d["lags"],
+                               "rectangle", d["h"][p])
+        assert ost == 0
+        _check_exact(c[p], b[p], n[p], oc, on, 1e-9)
+
+
+def test_r2_full_size_sampled_series():
+    # 4,096 lattice series of 1e3 to 1e5 samples, 366 lags, rectangle, FP64
+    # classic-FFT route
+    d = synth.r2()
+    offs = d["offs"]
+    c, b, n, st, rc = ncf.acf_regular_batch(offs, _dev(d["t"]), _dev(d["x"]), _dev(d["lags"]),
+                                            d["dt"], d["kernel"], d["h"])
+    c, b, n = _host(c), _host(b), _host(n)
+    assert rc == 0 and np.all(np.asarray(st) == 0)
+    for i in _sample(np.diff(offs), 4, 43):
+        sl = slice(offs[i], offs[i + 1])
+        ost, oc, _, on = O.acf_regular(d["t"][sl], d["x"][sl], d["lags"], d["dt"][i],
+                                       d["kernel"], d["h"][i])
+        assert ost == 0
+        _check_exact(c[i], b[i], n[i], oc, on, 1e-9)
+
+
+def test_m1_full_size_sampled_replicates():
+    # 100 replicates (flux randomization + bootstrap) of a 2 x 2e4-sample CCF
+    d = synth.m1()
+    cm, cs, crep, st, rc = ncf.ccf_resample(
+        _dev(d["t"]), _dev(d["x"]), _dev(d["s"]), _dev(d["y"]), _dev(d["lags"]), "gaussian",
+        d["h"], sx=_dev(d["ex"]), sy=_dev(d["ey"]), zx=_dev(d["zx"]), zy=_dev(d["zy"]),
+        multx=_dev(d["multx"]), multy=_dev(d["multy"]), with_reps=True)
+    cm, cs, crep = _host(cm), _host(cs), _host(crep)
+    st = np.asarray(st)
+    assert rc == 0 and np.all(st == 0)
+    for r in (0, 57, d["R"] - 1):
+        sl = slice(r, r + 1)
+        ost, oc, _, _ = O.ccf_resample(d["t"], d["x"], d["s"], d["y"], d["lags"], "gaussian",
+                                       d["h"], sx=d["ex"], sy=d["ey"], zx=d["zx"][sl],
+                                       zy=d["zy"][sl], multx=d["multx"][sl],
+                                       multy=d["multy"][sl])
+        assert ost[0] == 0
+        err = np.max(np.abs(crep[r] - oc[0]))
+        assert err <= 1e-5, f"replicate {r}: max |dc| = {err:.3e}"
+    # per-lag statistics of the replicates as returned
+    np.testing.assert_allclose(cm, crep.mean(axis=0), rtol=0, atol=1e-12)
+    np.testing.assert_allclose(cs, crep.std(axis=0, ddof=1), rtol=0, atol=1e-12)
