@@ -108,27 +108,39 @@ k_tile_bounds(const SpecTask* __restrict__ tasks, const Chunk* __restrict__ chun
     const int64_t nt = T.ntiles;
     const gptr<int64_t> rec = gbl(T.tile_rng);  // [tile][kTileRec]
     const int lane = threadIdx.x & 63;
-    for (int64_t b = ch.begin; b < ch.end; b += kThreads) {
-        const int64_t i = b + threadIdx.x;
-        const bool live = i < ch.end;
-        int64_t a1 = 0, b1 = 0;
-        if (live) tile_reach((t[i] - T.t_ref) * sc, reach, a1, b1);
-        // the previous sample's A, B from the neighbouring lane (same chunk,
-        // consecutive samples), recomputed by the first lane of each wave
-        int64_t a0 = __shfl_up(a1, 1), b0 = __shfl_up(b1, 1);
-        if (!live) continue;
-        if (i == 0) {
-            a0 = -1;
-            b0 = -1;
-        } else if (lane == 0) {
-            tile_reach((t[i - 1] - T.t_ref) * sc, reach, a0, b0);
+    // kUnroll rows of the chunk per round: their loads are issued together
+    constexpr int kUnroll = 4;
+    for (int64_t b = ch.begin; b < ch.end; b += kThreads * kUnroll) {
+        double tv[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int64_t i = b + u * kThreads + threadIdx.x;
+            tv[u] = i < ch.end ? t[i] : 0.0;
         }
-        for (int64_t q = max(a0 + 1, (int64_t)0); q <= min(a1, nt - 1); ++q) {
-            rec[kTileRec * q + 2 * set] = i;
-            if (set == 0) rec[kTileRec * q + 4] = task;
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int64_t i = b + u * kThreads + threadIdx.x;
+            const bool live = i < ch.end;
+            int64_t a1 = 0, b1 = 0;
+            if (live) tile_reach((tv[u] - T.t_ref) * sc, reach, a1, b1);
+            // the previous sample's A, B from the neighbouring lane (same
+            // chunk, consecutive samples), recomputed by the first lane of
+            // each wave
+            int64_t a0 = __shfl_up(a1, 1), b0 = __shfl_up(b1, 1);
+            if (!live) continue;
+            if (i == 0) {
+                a0 = -1;
+                b0 = -1;
+            } else if (lane == 0) {
+                tile_reach((t[i - 1] - T.t_ref) * sc, reach, a0, b0);
+            }
+            for (int64_t q = max(a0 + 1, (int64_t)0); q <= min(a1, nt - 1); ++q) {
+                rec[kTileRec * q + 2 * set] = i;
+                if (set == 0) rec[kTileRec * q + 4] = task;
+            }
+            for (int64_t q = max(b0, (int64_t)0); q <= min(b1 - 1, nt - 1); ++q)
+                rec[kTileRec * q + 2 * set + 1] = i;
         }
-        for (int64_t q = max(b0, (int64_t)0); q <= min(b1 - 1, nt - 1); ++q)
-            rec[kTileRec * q + 2 * set + 1] = i;
     }
     // tiles past the last sample's reach: bound n, filled by the workgroup
     // that holds the last sample, all threads together
@@ -902,10 +914,11 @@ k_mid(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pair0, int
     }
 }
 
-// Fallback flags of the spectral pair counts, one workgroup per problem:
-// window row r is flagged when its spectral b (evaluation index rowk[r]; -1:
-// no requested lag) is below beta times the reference (ACF: the lag-0 entry;
-// CCF: the largest over the requested lags, NaN ignored, at least 0), or when
+// Fallback flags of the spectral pair counts; workgroup b = i chunks + g
+// takes rows [256 g, 256 g + 256) of problem i: window row r is flagged when its
+// spectral b (evaluation index rowk[r]; -1: no requested lag) is below beta
+// times the reference (ACF: the lag-0 entry; CCF: the largest over the
+// requested lags, NaN ignored, at least 0; each workgroup forms it), or when
 // the reference is not positive. Bit r % 64 of mask[i * words + r / 64].
 constexpr int kFlagThreads = 256;
 
@@ -913,7 +926,9 @@ __global__ void __launch_bounds__(kFlagThreads)
 k_fallback_flags(const double* __restrict__ bspec, int Keval, int K, int ccf,
                  const int32_t* __restrict__ rowk, int Krow, double beta, int words,
                  uint64_t* __restrict__ mask) {
-    const int64_t i = blockIdx.x;
+    const int chunks = (Krow + kFlagThreads - 1) / kFlagThreads;
+    const int64_t i = (int64_t)blockIdx.x / chunks;
+    const int g = (int)((int64_t)blockIdx.x % chunks);
     const gptr<const double> bb = gbl(bspec) + i * Keval;
     __shared__ double red[kFlagThreads / 64];
     double bref;
@@ -930,8 +945,8 @@ k_fallback_flags(const double* __restrict__ bspec, int Keval, int K, int ccf,
     } else {
         bref = bb[K];
     }
-    for (int r0 = 0; r0 < Krow; r0 += kFlagThreads) {
-        const int r = r0 + (int)threadIdx.x;
+    {
+        const int r = g * kFlagThreads + (int)threadIdx.x;
         bool f = false;
         if (r < Krow) {
             const int k = gbl(rowk)[r];
@@ -1040,12 +1055,13 @@ int launch_fallback_flags(const double* bspec, int64_t nprob, int Keval, int K, 
                           const int32_t* rowk, int Krow, double beta, uint64_t* mask,
                           hipStream_t st) {
     if (nprob <= 0 || Krow <= 0) return NCF_OK;
-    if (nprob > INT32_MAX) {
-        set_error("fallback flags: %lld problems", (long long)nprob);
-        return NCF_E_INVALID_ARG;
+    const int64_t blocks = nprob * ceil_div(Krow, kFlagThreads);
+    if (blocks > INT32_MAX) {
+        set_error("fallback flags: %lld workgroups", (long long)blocks);
+        return NCF_E_UNSUPPORTED;
     }
     ProfScope p(st, "fallback_flags", 0.0, "bytes");
-    hipLaunchKernelGGL(k_fallback_flags, dim3((unsigned)nprob), dim3(kFlagThreads), 0, st, bspec,
+    hipLaunchKernelGGL(k_fallback_flags, dim3((unsigned)blocks), dim3(kFlagThreads), 0, st, bspec,
                        Keval, K, ccf ? 1 : 0, rowk, Krow, beta, (int)ceil_div(Krow, 64), mask);
     NCF_CHECK_LAUNCH();
     return NCF_OK;
