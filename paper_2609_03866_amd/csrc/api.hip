@@ -919,6 +919,10 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     // per window) lane-ops at the scan's measured rate (5e12/s mixed, 2e12/s
     // FP64); spectral cost: about 11 passes over the grids at 4 TB/s plus
     // 30 us for its extra launches and the fallback round trip.
+    // grid geometry per problem, planned once (the route choice and the
+    // spectral planning below both use it)
+    std::vector<SpecGeom> geom((size_t)J.nprob);
+    std::vector<char> have_geom((size_t)J.nprob, 0);
     if (spectral && J.opt.method == NCF_AUTO && J.kern == NCF_GAUSSIAN &&
         !(J.opt.flags & NCF_SPECTRAL_ALWAYS)) {
         const double rows = (double)(J.ccf ? K : K + 1);
@@ -939,12 +943,13 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
                 tmin = std::min(tmin, stat_of(1, p).tmin);
                 tmax = std::max(tmax, stat_of(1, p).tmax);
             }
-            SpecGeom g;
+            SpecGeom& g = geom[p];
             if (plan_grid(J, tmin, tmax, maxlag, J.h[p], &g) != NCF_OK) {
                 clear_error();
                 direct_s = 0.0;  // no grid fits: the window route
                 break;
             }
+            have_geom[p] = 1;
             spec_s += 11.0 * (double)g.N * csz_b * (J.ccf ? 2.0 : 1.0) / 4e12 +
                       (n0 + (J.ccf ? n1 : 0.0)) * 12.0 / 4e12;
         }
@@ -1160,7 +1165,10 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             }
             SpecPlan sp;
             sp.prob = p;
-            NCF_TRY(plan_grid(J, tmin, tmax, maxlag, J.h[p], &sp.g));
+            if (have_geom[p])
+                sp.g = geom[p];
+            else
+                NCF_TRY(plan_grid(J, tmin, tmax, maxlag, J.h[p], &sp.g));
             splans.push_back(sp);
         }
         std::stable_sort(splans.begin(), splans.end(),
@@ -1357,22 +1365,29 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             groups.push_back({i, 1});
         else
             groups.back().second++;
-        if (!plans.count(T.N)) {
-            FftPlan fp;
-            NCF_TRY(fft_plan(T.N, fp64, &fp, J.st, J.tune.fft));
-            plans[T.N] = fp;
+        // tasks are sorted by grid size: the plan and radix record of the
+        // previous task serve while the size repeats
+        if (i == 0 || T.N != splans[i - 1].g.N) {
+            auto it = plans.find(T.N);
+            if (it == plans.end()) {
+                FftPlan fp;
+                NCF_TRY(fft_plan(T.N, fp64, &fp, J.st, J.tune.fft));
+                it = plans.emplace(T.N, fp).first;
+            }
+            const FftPlan& fp = it->second;
+            int lgN = 0;
+            while ((1LL << lgN) < T.N) ++lgN;
+            hT.rinfo[6 * i + 0] = fp.npass;
+            for (int q = 0; q < 4; ++q) {
+                int lg = 0;
+                if (q < fp.npass)
+                    while ((1 << lg) < fp.radix[q]) ++lg;
+                hT.rinfo[6 * i + 1 + q] = lg;
+            }
+            hT.rinfo[6 * i + 5] = lgN;
+        } else {
+            std::memcpy(hT.rinfo + 6 * i, hT.rinfo + 6 * (i - 1), 6 * sizeof(int32_t));
         }
-        const FftPlan& fp = plans[T.N];
-        int lgN = 0;
-        while ((1LL << lgN) < T.N) ++lgN;
-        hT.rinfo[6 * i + 0] = fp.npass;
-        for (int q = 0; q < 4; ++q) {
-            int lg = 0;
-            if (q < fp.npass)
-                while ((1 << lg) < fp.radix[q]) ++lg;
-            hT.rinfo[6 * i + 1 + q] = lg;
-        }
-        hT.rinfo[6 * i + 5] = lgN;
         spread_bytes += (double)(T.n0 + T.n1) * (spec_w ? 20.0 : 12.0) +
                         (double)T.N * csz * nfwd;
     }
@@ -1532,7 +1547,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
                     dl.push_back(delta[r]);
                 }
             if (!dl.empty())
-                W2.plans.push_back({0, J.ccf ? 1 : 0, p, 3, dl});
+                W2.plans.push_back({0, J.ccf ? 1 : 0, p, 3, std::move(dl)});
         }
     };
     enqueue_phase3 = [&]() -> int {
@@ -1576,7 +1591,8 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             dU.wk0 = tb.take<int64_t>(ntw2 + 1, &hU.wk0);
             dU.r0 = tb.take<int64_t>(ntw2 + 1, &hU.r0);
             dU.dl = tb.take<double>(ndl2, &hU.dl);
-            dU.fbrow = tb.take<int32_t>(any_fb ? (size_t)J.nprob * K : 1, &hU.fbrow);
+            // fallback rows: K entries per problem with fallback lags
+            dU.fbrow = tb.take<int32_t>(any_fb ? (size_t)ntw2 * K : 1, &hU.fbrow);
             dU.perm = tb.take<int32_t>(K, &hU.perm);
             dU.nt = tb.take<NormTask>(J.nprob, &hU.nt);
             dU.status = tb.take<int32_t>(J.nprob, &hU.status);
@@ -1604,11 +1620,13 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
                 std::memcpy(hU.r0, W2.r0.data(), sizeof(int64_t) * (ntw2 + 1));
             }
             if (any_fb) {
-                for (int64_t i = 0; i < J.nprob * K; ++i) hU.fbrow[i] = -1;
+                for (int64_t i = 0; i < (int64_t)ntw2 * K; ++i) hU.fbrow[i] = -1;
                 // flagged lags are in sorted-row order; their fallback row is their rank
-                for (int64_t p = 0; p < J.nprob; ++p)
+                for (int i = 0; i < ntw2; ++i) {
+                    const int64_t p = W2.plans[i].prob;
                     for (size_t q = 0; q < flagged[p].size(); ++q)
-                        hU.fbrow[p * K + flagged[p][q]] = (int32_t)q;
+                        hU.fbrow[(int64_t)i * K + flagged[p][q]] = (int32_t)q;
+                }
             }
         }
         // normalization tables
@@ -1650,7 +1668,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
                         T.nscale_part = splans[i].g.N / 4096;
                     }
                     if (fb_task[p] >= 0) {
-                        T.fb_row = dU.fbrow + p * K;
+                        T.fb_row = dU.fbrow + (int64_t)fb_task[p] * K;
                         T.fb_sums = W2.wt[fb_task[p]].sums;
                     }
                 } else {
