@@ -84,6 +84,12 @@ k_reg_fill(const RegTask* __restrict__ tasks, const int64_t* __restrict__ blk0, 
         for (int ch = 0; ch < NCH; ++ch) cell[ch][c] = 0.0;
     __syncthreads();
     bool bad = false;
+    // lattice index of a time: rint((t - t_ref) / dt), formed with the
+    // reciprocal; an accepted time lies within tol = 1e-6 dt of its lattice
+    // point, so the quotient is never near a half-integer and both forms give
+    // the same index (a time near a half-point is rejected either way)
+    const double inv_dt = 1.0 / T.dt;
+    auto lat = [&](double tv) { return rint((tv - T.t_ref) * inv_dt); };
 #pragma unroll
     for (int s = 0; s < (CCF ? 2 : 1); ++s) {
         const gptr<const double> t = gbl(T.t[s]);
@@ -97,17 +103,17 @@ k_reg_fill(const RegTask* __restrict__ tasks, const int64_t* __restrict__ blk0, 
         const int chn = CCF ? (WT ? 4 + s : 2 + s) : (WT ? 2 : 1);
         for (int64_t i = i0 + tid; i < i1; i += kThreads) {
             const double tv = t[i];
-            const double mr = rint((tv - T.t_ref) / T.dt);
+            const double mr = lat(tv);
             const double cd = mr - (double)a0;
             if (!(fabs(tv - (T.t_ref + mr * T.dt)) <= T.tol) || !(cd >= 0.0) ||
                 !(cd < (double)kRegCells)) {
                 bad = true;
                 continue;
             }
-            if (i > i0 && rint((t[i - 1] - T.t_ref) / T.dt) == mr) continue;  // not first
+            if (i > i0 && lat(t[i - 1]) == mr) continue;  // not first
             double sv = 0.0, sw = 0.0, sn = 0.0;
             for (int64_t j = i; j < i1; ++j) {
-                if (j > i && rint((t[j] - T.t_ref) / T.dt) != mr) break;
+                if (j > i && lat(t[j]) != mr) break;
                 sv += v[j];
                 if (WT) sw += wp ? w[j] : 1.0;
                 sn += 1.0;
