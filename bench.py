@@ -303,8 +303,8 @@ def main():
     global WINDOW_QUEUE
     WINDOW_QUEUE = args.window_queue
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                          "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        print(json.dumps({"error": "ncf runs on one GPU; --gpus must be 1 "
+                          "(sharding across GPUs is not implemented)"}))
         sys.exit(2)
 
     import torch
