@@ -215,6 +215,8 @@ struct AccR {
     int bytes;  // sum over j of (hi - lo) * 8
 };
 
+constexpr int kRectAdv = 3;  // reads past the staged times land on the 8 sentinels
+
 template <bool NUMER, bool WTD>
 __device__ __forceinline__ void scan_rect(AccR& acc, int o_t, int dp, int o_o, int len, int ja,
                                           int jb, double delta, double W) {
@@ -263,17 +265,20 @@ __device__ __forceinline__ void scan_rect(AccR& acc, int o_t, int dp, int o_o, i
         const double c = s + delta;
         const double lk = c - W;
         const double hk = c + W;
+        // kRectAdv-wide checks (measured: 3 beats 2, 4 and 6 on c2 and c5)
         for (;;) {
-            const double x0 = plo[0], x1 = plo[1], x2 = plo[2], x3 = plo[3];
-            const int a = (x0 < lk) + (x1 < lk) + (x2 < lk) + (x3 < lk);
+            int a = 0;
+#pragma unroll
+            for (int q = 0; q < kRectAdv; ++q) a += plo[q] < lk;
             plo += a;
-            if (a < 4) break;
+            if (a < kRectAdv) break;
         }
         for (;;) {
-            const double x0 = phi[0], x1 = phi[1], x2 = phi[2], x3 = phi[3];
-            const int a = (x0 <= hk) + (x1 <= hk) + (x2 <= hk) + (x3 <= hk);
+            int a = 0;
+#pragma unroll
+            for (int q = 0; q < kRectAdv; ++q) a += phi[q] <= hk;
             phi += a;
-            if (a < 4) break;
+            if (a < kRectAdv) break;
         }
         acc.bytes += (int)((const char*)phi - (const char*)plo);
         if (NUMER) acc.C += vo * (phi[dp] - plo[dp]);
