@@ -120,16 +120,18 @@ __device__ __forceinline__ int upper_idx(const V& v, int lo, int hi, double key)
 }
 
 // Advance a pointer over sorted samples while T(p) < key (or <= key):
-// four independent reads per round; sorted order makes the passing samples
-// a prefix of the four.
+// kAdv independent reads per round; sorted order makes the passing samples a
+// prefix of them.
+constexpr int kAdv = 3;
+
 template <bool LE, typename V>
 __device__ __forceinline__ int advance(const V& v, int p, double key) {
     for (;;) {
-        const double x0 = v.T(p), x1 = v.T(p + 1), x2 = v.T(p + 2), x3 = v.T(p + 3);
-        const int a = LE ? (x0 <= key) + (x1 <= key) + (x2 <= key) + (x3 <= key)
-                         : (x0 < key) + (x1 < key) + (x2 < key) + (x3 < key);
+        int a = 0;
+#pragma unroll
+        for (int q = 0; q < kAdv; ++q) a += LE ? (v.T(p + q) <= key) : (v.T(p + q) < key);
         p += a;
-        if (a < 4) return p;
+        if (a < kAdv) return p;
     }
 }
 
