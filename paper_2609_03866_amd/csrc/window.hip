@@ -267,20 +267,19 @@ __device__ __forceinline__ void scan_rect(AccR& acc, int o_t, int dp, int o_o, i
         const double c = s + delta;
         const double lk = c - W;
         const double hk = c + W;
-        // kRectAdv-wide checks (measured: 3 beats 2, 4 and 6 on c2 and c5)
+        // kRectAdv-wide checks of both bounds per round (measured: 3 beats
+        // 2, 4 and 6 on c2 and c5); a bound that has stopped re-checks its
+        // own position and stays
         for (;;) {
-            int a = 0;
+            int a = 0, b = 0;
 #pragma unroll
-            for (int q = 0; q < kRectAdv; ++q) a += plo[q] < lk;
+            for (int q = 0; q < kRectAdv; ++q) {
+                a += plo[q] < lk;
+                b += phi[q] <= hk;
+            }
             plo += a;
-            if (a < kRectAdv) break;
-        }
-        for (;;) {
-            int a = 0;
-#pragma unroll
-            for (int q = 0; q < kRectAdv; ++q) a += phi[q] <= hk;
-            phi += a;
-            if (a < kRectAdv) break;
+            phi += b;
+            if (a < kRectAdv && b < kRectAdv) break;
         }
         acc.bytes += (int)((const char*)phi - (const char*)plo);
         if (NUMER) acc.C += vo * (phi[dp] - plo[dp]);
