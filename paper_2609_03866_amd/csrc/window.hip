@@ -217,7 +217,7 @@ struct AccR {
     int bytes;  // sum over j of (hi - lo) * 8
 };
 
-constexpr int kRectAdv = 3;  // reads past the staged times land on the 8 sentinels
+constexpr int kRectAdv = 1;  // reads past the staged times land on the 8 sentinels
 
 template <bool NUMER, bool WTD>
 __device__ __forceinline__ void scan_rect(AccR& acc, int o_t, int dp, int o_o, int len, int ja,
@@ -267,8 +267,9 @@ __device__ __forceinline__ void scan_rect(AccR& acc, int o_t, int dp, int o_o, i
         const double c = s + delta;
         const double lk = c - W;
         const double hk = c + W;
-        // kRectAdv-wide checks of both bounds per round (measured: 3 beats
-        // 2, 4 and 6 on c2 and c5); a bound that has stopped re-checks its
+        // both bounds advance in one loop, kRectAdv samples per round each
+        // (measured on c2 and c5: 1 beats 2 and 3; separate loops with 2, 3,
+        // 4 or 6 are slower still); a bound that has stopped re-checks its
         // own position and stays
         for (;;) {
             int a = 0, b = 0;
