@@ -171,13 +171,17 @@ __device__ __forceinline__ void scan_lane(Acc& acc, const V& v, int ja, int jb, 
             hi = advance<false>(v, hi, hk);
             double bj = 0.0, Cj = 0.0, Bj = 0.0;
             float bf = 0.0f;
-            for (int i = lo; i < hi; i += 4) {
-                double dd[4];
+            // window points per round (reads past the window land on staged
+            // samples or the sentinels); measured: one for the FP32
+            // exponential, four for the FP64 one
+            constexpr int kPts = E64 ? 4 : 1;
+            for (int i = lo; i < hi; i += kPts) {
+                double dd[kPts];
 #pragma unroll
-                for (int m = 0; m < 4; ++m) dd[m] = v.T(i + m) - c;  // FP64 difference
+                for (int m = 0; m < kPts; ++m) dd[m] = v.T(i + m) - c;  // FP64 difference
 #pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    if (i + m < hi) {
+                for (int m = 0; m < kPts; ++m) {
+                    if (kPts == 1 || i + m < hi) {
                         if (E64) {
                             const double z = dd[m] * inv_h;
                             const double e = exp(-0.5 * z * z);
