@@ -163,6 +163,22 @@ class _Marshal:
         self.keep.append(a)
         return a, a.ctypes.data
 
+    def outs(self, n, with_count):
+        """The c, b (float64) and count (int64, optional) outputs of n
+        entries each; on the device one allocation holds all three."""
+        if not self.device:
+            c, pc = self.out(n, np.float64)
+            b, pb = self.out(n, np.float64)
+            cnt, pn = self.out(n, np.int64) if with_count else (None, None)
+            return c, pc, b, pb, cnt, pn
+        import torch
+        buf = torch.empty((3 if with_count else 2) * n, dtype=torch.float64, device=self.device)
+        self.keep.append(buf)
+        c, b = buf[:n], buf[n:2 * n]
+        cnt = buf[2 * n:].view(torch.int64) if with_count else None
+        return (c, c.data_ptr(), b, b.data_ptr(), cnt,
+                cnt.data_ptr() if with_count else None)
+
 
 def _options(precision, method, tol, sigma, grid_size, device, stream, window_queue=False,
              spectral_always=False):
@@ -200,9 +216,7 @@ def acf(t, x, lags, kernel="gaussian", h=1.0, err=None, precision="mixed", metho
     dev = t.device if _is_torch(t) else None
     m = _Marshal(dev)
     K = int(lags.numel() if _is_torch(lags) else np.asarray(lags).size)
-    c, pc = m.out(K, np.float64)
-    b, pb = m.out(K, np.float64)
-    cnt, pn = m.out(K, np.int64) if with_count else (None, None)
+    c, pc, b, pb, cnt, pn = m.outs(K, with_count)
     n = int(t.numel() if _is_torch(t) else np.asarray(t).size)
     o = _options(precision, method, tol, sigma, grid_size, dev, stream, window_queue,
                  spectral_always)
@@ -220,9 +234,7 @@ def ccf(t, x, s, y, lags, kernel="gaussian", h=1.0, ex=None, ey=None, precision=
     dev = t.device if _is_torch(t) else None
     m = _Marshal(dev)
     K = int(lags.numel() if _is_torch(lags) else np.asarray(lags).size)
-    c, pc = m.out(K, np.float64)
-    b, pb = m.out(K, np.float64)
-    cnt, pn = m.out(K, np.int64) if with_count else (None, None)
+    c, pc, b, pb, cnt, pn = m.outs(K, with_count)
     nx = int(t.numel() if _is_torch(t) else np.asarray(t).size)
     ny = int(s.numel() if _is_torch(s) else np.asarray(s).size)
     o = _options(precision, method, tol, sigma, grid_size, dev, stream, window_queue,
@@ -244,9 +256,7 @@ def acf_batch(offs, t, x, lags, kernel="gaussian", h=1.0, err=None, precision="m
     dev = t.device if _is_torch(t) else None
     m = _Marshal(dev)
     K = int(lags.numel() if _is_torch(lags) else np.asarray(lags).size)
-    c, pc = m.out(nser * K, np.float64)
-    b, pb = m.out(nser * K, np.float64)
-    cnt, pn = m.out(nser * K, np.int64) if with_count else (None, None)
+    c, pc, b, pb, cnt, pn = m.outs(nser * K, with_count)
     st = np.zeros(nser, dtype=np.int32)
     o = _options(precision, method, tol, sigma, grid_size, dev, stream, window_queue,
                  spectral_always)
@@ -271,9 +281,7 @@ def ccf_batch(offx, t, x, offy, s, y, lags, kernel="gaussian", h=1.0, ex=None, e
     dev = t.device if _is_torch(t) else None
     m = _Marshal(dev)
     K = int(lags.numel() if _is_torch(lags) else np.asarray(lags).size)
-    c, pc = m.out(npair * K, np.float64)
-    b, pb = m.out(npair * K, np.float64)
-    cnt, pn = m.out(npair * K, np.int64) if with_count else (None, None)
+    c, pc, b, pb, cnt, pn = m.outs(npair * K, with_count)
     st = np.zeros(npair, dtype=np.int32)
     o = _options(precision, method, tol, sigma, grid_size, dev, stream, window_queue,
                  spectral_always)
@@ -296,9 +304,7 @@ def acf_regular(t, x, lags, dt, kernel="gaussian", h=1.0, err=None, with_count=T
     dev = t.device if _is_torch(t) else None
     m = _Marshal(dev)
     K = int(lags.numel() if _is_torch(lags) else np.asarray(lags).size)
-    c, pc = m.out(K, np.float64)
-    b, pb = m.out(K, np.float64)
-    cnt, pn = m.out(K, np.int64) if with_count else (None, None)
+    c, pc, b, pb, cnt, pn = m.outs(K, with_count)
     n = int(t.numel() if _is_torch(t) else np.asarray(t).size)
     o = _options("fp64", "auto", 0.0, 0.0, 0, dev, stream)
     rc = lib().ncf_acf_regular(n, m.inp(t), m.inp(x), m.inp(err), float(dt), K, m.inp(lags),
@@ -314,9 +320,7 @@ def ccf_regular(t, x, s, y, lags, dt, kernel="gaussian", h=1.0, ex=None, ey=None
     dev = t.device if _is_torch(t) else None
     m = _Marshal(dev)
     K = int(lags.numel() if _is_torch(lags) else np.asarray(lags).size)
-    c, pc = m.out(K, np.float64)
-    b, pb = m.out(K, np.float64)
-    cnt, pn = m.out(K, np.int64) if with_count else (None, None)
+    c, pc, b, pb, cnt, pn = m.outs(K, with_count)
     nx = int(t.numel() if _is_torch(t) else np.asarray(t).size)
     ny = int(s.numel() if _is_torch(s) else np.asarray(s).size)
     o = _options("fp64", "auto", 0.0, 0.0, 0, dev, stream)
@@ -338,9 +342,7 @@ def acf_regular_batch(offs, t, x, lags, dt, kernel="gaussian", h=1.0, err=None,
     dev = t.device if _is_torch(t) else None
     m = _Marshal(dev)
     K = int(lags.numel() if _is_torch(lags) else np.asarray(lags).size)
-    c, pc = m.out(nser * K, np.float64)
-    b, pb = m.out(nser * K, np.float64)
-    cnt, pn = m.out(nser * K, np.int64) if with_count else (None, None)
+    c, pc, b, pb, cnt, pn = m.outs(nser * K, with_count)
     st = np.zeros(nser, dtype=np.int32)
     o = _options("fp64", "auto", 0.0, 0.0, 0, dev, stream)
     rc = lib().ncf_acf_regular_batch(nser, offs.ctypes.data, m.inp(t), m.inp(x), m.inp(err),
@@ -363,9 +365,7 @@ def ccf_regular_batch(offx, t, x, offy, s, y, lags, dt, kernel="gaussian", h=1.0
     dev = t.device if _is_torch(t) else None
     m = _Marshal(dev)
     K = int(lags.numel() if _is_torch(lags) else np.asarray(lags).size)
-    c, pc = m.out(npair * K, np.float64)
-    b, pb = m.out(npair * K, np.float64)
-    cnt, pn = m.out(npair * K, np.int64) if with_count else (None, None)
+    c, pc, b, pb, cnt, pn = m.outs(npair * K, with_count)
     st = np.zeros(npair, dtype=np.int32)
     o = _options("fp64", "auto", 0.0, 0.0, 0, dev, stream)
     rc = lib().ncf_ccf_regular_batch(npair, offx.ctypes.data, m.inp(t), m.inp(x), m.inp(ex),
@@ -460,9 +460,7 @@ class Plan:
             raise ValueError("plan is closed")
         m = _Marshal(self.device)
         n = self.nprob * self.K
-        c, pc = m.out(n, np.float64)
-        b, pb = m.out(n, np.float64)
-        cnt, pn = m.out(n, np.int64) if with_count else (None, None)
+        c, pc, b, pb, cnt, pn = m.outs(n, with_count)
         if self.device:
             import torch
             st = torch.zeros(self.nprob, dtype=torch.int32, device=self.device)
