@@ -776,7 +776,9 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     const int nch = (int)chunks.size();
 
     // device workspace of phase 1: inputs (host mode), derived arrays, partials
-    auto layout1 = [&](Arena& ar, double** d_cpart, double** d_ctot, SeriesStat** d_stats) {
+    const bool lags_with_stats = J.lags_dev && !J.rec;
+    auto layout1 = [&](Arena& ar, double** d_cpart, double** d_ctot, SeriesStat** d_stats,
+                       double** d_lagc) {
         for (int si = 0; si < nsets; ++si) {
             SeriesSet& S = J.set[si];
             if (J.dev_ptrs) {
@@ -797,16 +799,24 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         *d_cpart = ar.take<double>(4 * (size_t)nch);
         *d_ctot = ar.take<double>(2 * (size_t)nch);
         *d_stats = ar.take<SeriesStat>(nsd);
+        // device lags of a one-shot call: copied next to the statistics by
+        // the moments launch, so one readback brings both (recorded launches
+        // must not keep the caller's lag pointer: they copy them apart)
+        *d_lagc = ar.take<double>(lags_with_stats ? J.K : 0);
     };
-    double *d_cpart, *d_ctot;
+    double *d_cpart, *d_ctot, *d_lagc;
     SeriesStat* d_stats;
     Arena a1;
-    layout1(a1, &d_cpart, &d_ctot, &d_stats);
+    layout1(a1, &d_cpart, &d_ctot, &d_stats, &d_lagc);
     Resources& R = *J.res;
     void* ws1 = nullptr;
     NCF_TRY(ensure_ws(R, 0, a1.off + 256, &ws1));
     a1 = Arena{(char*)ws1, 0};
-    layout1(a1, &d_cpart, &d_ctot, &d_stats);
+    layout1(a1, &d_cpart, &d_ctot, &d_stats, &d_lagc);
+    // bytes from the statistics to the end of the lag copy (the readback)
+    const size_t stat_span = lags_with_stats
+                                 ? (size_t)((char*)(d_lagc + J.K) - (char*)d_stats)
+                                 : sizeof(SeriesStat) * nsd;
     if (!J.dev_ptrs) {
         for (int si = 0; si < nsets; ++si) {
             SeriesSet& S = J.set[si];
@@ -841,13 +851,13 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         SeriesDesc* hs;
         Chunk* hc;
         IoBlock* hio;
-        SeriesStat* hst;
+        char* hst;
         t1.take<SeriesDesc>(nsd, &hs);
         t1.take<Chunk>(nch, &hc);
         t1.take<IoBlock>(1, &hio);
-        t1.take<SeriesStat>(nsd, &hst);
+        t1.take<char>(stat_span, &hst);
         double* hl;
-        t1.take<double>(J.lags_dev ? J.K : 0, &hl);
+        t1.take<double>(J.lags_dev && !lags_with_stats ? J.K : 0, &hl);
     }
     NCF_TRY(ensure_stage(R, 0, t1.off, &stg1));
     t1 = Tables{stg1->h, stg1->d, 0};
@@ -858,9 +868,14 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     SeriesDesc* d_sd = t1.take<SeriesDesc>(nsd, &h_sd);
     Chunk* d_ch = t1.take<Chunk>(nch, &h_ch);
     IoBlock* d_io1 = t1.take<IoBlock>(1, &h_io1);
-    t1.take<SeriesStat>(nsd, &h_stats);  // host landing area of the statistics
+    // host landing area of the statistics (and of the lag copy behind them,
+    // laid out as on the device)
+    char* h_span;
+    t1.take<char>(stat_span, &h_span);
+    h_stats = reinterpret_cast<SeriesStat*>(h_span);
     double* h_lags;
-    t1.take<double>(J.lags_dev ? J.K : 0, &h_lags);  // and of device lags
+    t1.take<double>(J.lags_dev && !lags_with_stats ? J.K : 0, &h_lags);  // device lags apart
+    if (lags_with_stats) h_lags = reinterpret_cast<double*>(h_span + ((char*)d_lagc - (char*)d_stats));
     std::memcpy(h_sd, sdesc.data(), sizeof(SeriesDesc) * nsd);
     std::memcpy(h_ch, chunks.data(), sizeof(Chunk) * nch);
     *h_io1 = IoBlock{};
@@ -877,10 +892,14 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     ma.stats = d_stats;
     ma.io = J.io_fixed ? J.io_fixed : d_io1;
     ma.prefix = need_prefix ? 1 : 0;
+    if (lags_with_stats) {
+        ma.lag_src = J.lags_dev;
+        ma.lag_dst = d_lagc;
+        ma.nlag = J.K;
+    }
     NCF_TRY(emit(J, [ma](hipStream_t s) { return launch_moments(ma, s); }));
-    NCF_TRY_HIP(hipMemcpyAsync(h_stats, d_stats, sizeof(SeriesStat) * nsd, hipMemcpyDeviceToHost,
-                               J.st));
-    if (J.lags_dev)
+    NCF_TRY_HIP(hipMemcpyAsync(h_span, d_stats, stat_span, hipMemcpyDeviceToHost, J.st));
+    if (J.lags_dev && !lags_with_stats)
         NCF_TRY_HIP(hipMemcpyAsync(h_lags, J.lags_dev, sizeof(double) * J.K,
                                    hipMemcpyDeviceToHost, J.st));
     NCF_TRY_HIP(hipStreamSynchronize(J.st));
@@ -1258,6 +1277,46 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     } dT{}, hT{};
     const int fwords = (int)ceil_div(std::max(Krow, 1), 64);
     const bool flag_pass = spec_b && nts > 0 && K > 0;
+    // Phase 3 (fallback window scans, normalization, outputs). For the
+    // spectral pair counts of a one-shot call it is first enqueued
+    // speculatively with no fallback lags, behind the fallback flags: when no
+    // lag is flagged (the common case) those outputs are final and the call
+    // ends on one round trip; otherwise phase 3 runs again with the flagged
+    // lags and rewrites every output. Only calls of a few problems
+    // speculate: in large batches some series nearly always has a flagged
+    // lag, and phase 3 would be planned and uploaded twice. Recorded launch
+    // sequences (plans) take the final path only. When phase 3 does not wait
+    // for the flags (no spectral pair counts, or speculation) its tables
+    // travel in the phase-2 upload (merge3), and with speculation the flag
+    // masks and the statuses, adjacent in the staging, come back in one copy
+    // (combine).
+    constexpr int64_t kSpeculateMaxProblems = 8;
+    const bool speculate = flag_pass && !J.rec && J.nprob <= kSpeculateMaxProblems;
+    const bool merge3 = !flag_pass || speculate;
+    const bool combine = speculate && !J.io_fixed;
+    struct T3 {
+        int32_t* status;  // first: right after the flag masks when merged
+        WinTask* wt;
+        int64_t *item0, *wk0, *r0;
+        double* dl;
+        int32_t* fbrow;
+        int32_t* perm;
+        NormTask* nt;
+        IoBlock* io;
+    } dU{}, hU{};
+    auto take3 = [&](Tables& tb, int ntw2, size_t ndl2, bool any_fb) {
+        dU.status = tb.take<int32_t>(J.nprob, &hU.status);
+        dU.wt = tb.take<WinTask>(ntw2, &hU.wt);
+        dU.item0 = tb.take<int64_t>(ntw2 + 1, &hU.item0);
+        dU.wk0 = tb.take<int64_t>(ntw2 + 1, &hU.wk0);
+        dU.r0 = tb.take<int64_t>(ntw2 + 1, &hU.r0);
+        dU.dl = tb.take<double>(ndl2, &hU.dl);
+        // fallback rows: K entries per problem with fallback lags
+        dU.fbrow = tb.take<int32_t>(any_fb ? (size_t)ntw2 * K : 1, &hU.fbrow);
+        dU.perm = tb.take<int32_t>(K, &hU.perm);
+        dU.nt = tb.take<NormTask>(J.nprob, &hU.nt);
+        dU.io = tb.take<IoBlock>(1, &hU.io);
+    };
     size_t ndl = 0;
     for (auto& P : W1.plans) ndl += P.dl.size();
     auto take2 = [&](Tables& tb) {
@@ -1278,6 +1337,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         dT.ginv = tb.take<void*>(2 * (size_t)nts, &hT.ginv);
         dT.rowk = tb.take<int32_t>(flag_pass ? Krow : 0, &hT.rowk);
         dT.mask = tb.take<uint64_t>(flag_pass ? (size_t)nts * fwords : 0, &hT.mask);
+        if (merge3) take3(tb, 0, 0, false);  // phase 3 without fallback lags
     };
     Tables t2;
     take2(t2);
@@ -1425,87 +1485,6 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     }
     if (flag_pass)
         for (int r = 0; r < Krow; ++r) hT.rowk[r] = rows[r].second;
-    NCF_TRY_HIP(hipMemcpyAsync(stg2->d, stg2->h, t2.off, hipMemcpyHostToDevice, J.st));
-
-    // ------------------------------------------------ A7 window scan
-    // work-queue dispatch of the window scans (scheduling option)
-    unsigned long long* qbase = nullptr;
-    if ((J.opt.flags & NCF_WINDOW_QUEUE) || J.tune.queue) NCF_TRY(ensure_queue(R, &qbase));
-    {
-        const WinTask* wt = dT.wt;
-        const int64_t *it0 = dT.item0, *wk0 = dT.wk0, *r0 = dT.r0;
-        const int64_t nitems = W1.nitems, rows = W1.total_rows, nred1 = W1.nred1;
-        const int cap = W1.cap, jmax = W1.jmax;
-        const double work = W1.work;
-        unsigned long long* q = qbase;
-        if (ntw > 0) {
-            NCF_TRY(emit(J, [=](hipStream_t s) {
-                return launch_window(wt, it0, ntw, nitems, wflags, cap, jmax, q, s, work);
-            }));
-            NCF_TRY(emit(J, [=](hipStream_t s) {
-                return launch_window_reduce(wt, ntw, rows, wk0, r0, nred1, wflags, s);
-            }));
-        }
-    }
-
-    // ------------------------------------------------ A2-A6 spectral route
-    if (nts > 0) {
-        const SpecTask* stk = dT.st;
-        const int64_t *tile0 = dT.tile0, *pos0 = dT.pos0, *sk0 = dT.sk0;
-        const int64_t* rinfo = (const int64_t*)dT.rinfo;
-        const double pbytes = (nfwd + 1.0 + (spec_unw ? 1.0 : 0.0)) * total_pos * csz;
-        const int64_t nkeval = (int64_t)nts * Keval;
-        const bool ccf = J.ccf;
-        const int32_t* smap = dT.smap;
-        const int64_t* rec_all = d_rng;
-        const Chunk* dch = d_ch;
-        const double tb_bytes = 8.0 * (double)total_samp;
-        if (bounds_pass)
-            NCF_TRY(emit(J, [=](hipStream_t s) {
-                return launch_tile_bounds(stk, dch, nch, smap, s, tb_bytes);
-            }));
-        NCF_TRY(emit(J, [=](hipStream_t s) {
-            return launch_spread(stk, tile0, nts, ntiles, rec_all, 4096, ccf, spec_b, spec_w,
-                                 spec_unw, fp64, s, spread_bytes);
-        }));
-        // the forward last pass, the product and the inverse first pass run
-        // fused over tile pairs where the mode fits the LDS of one workgroup
-        const bool fuse = !J.tune.no_mid && mid_supported(J.ccf, spec_b, spec_unw, fp64);
-        for (size_t q = 0; q < groups.size(); ++q) {
-            const FftPlan fp = plans[splans[groups[q].first].g.N];
-            void* const* gp = dT.gfwd + fwd_groups[q].first;
-            const int cnt = fwd_groups[q].second;
-            NCF_TRY(emit(J, [=](hipStream_t s) {
-                return fft_exec(fp, gp, cnt, +1, fp64, s, fuse);
-            }));
-        }
-        if (fuse) {
-            const int64_t* pair0 = dT.pair0;
-            const int64_t npairs = total_pairs;
-            const void* wsmall = plans.begin()->second.small;
-            const double mbytes = (double)(nfwd + 1) * total_pos * csz;
-            NCF_TRY(emit(J, [=](hipStream_t s) {
-                return launch_mid(stk, pair0, nts, npairs, rinfo, wsmall, ccf, spec_b, fp64, s,
-                                  mbytes);
-            }));
-        } else {
-            NCF_TRY(emit(J, [=](hipStream_t s) {
-                return launch_product(stk, pos0, nts, total_pos, rinfo, ccf, spec_b, spec_unw,
-                                      fp64, s, pbytes);
-            }));
-        }
-        for (size_t q = 0; q < groups.size(); ++q) {
-            const FftPlan fp = plans[splans[groups[q].first].g.N];
-            void* const* gp = dT.ginv + inv_groups[q].first;
-            const int cnt = inv_groups[q].second;
-            NCF_TRY(emit(J, [=](hipStream_t s) {
-                return fft_exec(fp, gp, cnt, -1, fp64, s, fuse);
-            }));
-        }
-        NCF_TRY(emit(J, [=](hipStream_t s) { return launch_interp(stk, nts, sk0, nkeval, fp64, s); }));
-    }
-
-    // ------------------------------------------------ direct fallback (spectral b)
     // lags whose spectral pair count is below beta times the reference
     // (lag 0 for the ACF, the largest requested lag for the CCF) are summed
     // directly: their spectral value is dominated by rounding noise
@@ -1513,97 +1492,9 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     for (int i = 0; i < nts; ++i) spec_of[splans[i].prob] = i;
     std::vector<std::vector<int>> flagged(J.nprob);  // requested lag indices
     WinLaunch W2;
-    // Phase 3 (fallback window scans, normalization, outputs) is enqueued by
-    // enqueue_phase3 below; for the spectral pair counts of a one-shot call
-    // it is first enqueued speculatively with no fallback lags, together
-    // with the readback of the fallback flags: when no lag is flagged (the
-    // common case) those outputs are final and the call ends on one round
-    // trip; otherwise phase 3 runs again with the flagged lags and rewrites
-    // every output. Only calls of a few problems speculate: in large batches
-    // some series nearly always has a flagged lag, and phase 3 would be
-    // planned and uploaded twice. Recorded launch sequences (plans) take the
-    // final path only.
-    constexpr int64_t kSpeculateMaxProblems = 8;
-    const bool speculate = flag_pass && !J.rec && J.nprob <= kSpeculateMaxProblems;
-    int32_t* h_fstat = nullptr;
-    std::function<int()> enqueue_phase3;
-    if (flag_pass) {
-        // flags computed on the device from the spectral b values (contiguous
-        // over the problems); only the bit masks come back
-        NCF_TRY(launch_fallback_flags(bspec[0], nts, Keval, (int)K, J.ccf, dT.rowk, Krow, beta,
-                                      dT.mask, J.st));
-        NCF_TRY_HIP(hipMemcpyAsync(hT.mask, dT.mask, sizeof(uint64_t) * (size_t)nts * fwords,
-                                   hipMemcpyDeviceToHost, J.st));
-    }
-    auto read_flags = [&]() {
-        for (int i = 0; i < nts; ++i) {
-            const int64_t p = splans[i].prob;
-            const uint64_t* mw = hT.mask + (size_t)i * fwords;
-            std::vector<double> dl;
-            for (int w = 0; w < fwords; ++w)
-                for (uint64_t m = mw[w]; m; m &= m - 1) {
-                    const int r = w * 64 + __builtin_ctzll(m);
-                    flagged[p].push_back(rows[r].second);
-                    dl.push_back(delta[r]);
-                }
-            if (!dl.empty())
-                W2.plans.push_back({0, J.ccf ? 1 : 0, p, 3, std::move(dl)});
-        }
-    };
-    enqueue_phase3 = [&]() -> int {
-        const int ntw2 = (int)W2.plans.size();
-        const uint32_t wflags2 = (fp64 ? (uint32_t)WIN_EXP64 : 0u) | (uint32_t)WIN_NUMER |
-                                 (weighted ? (uint32_t)WIN_WEIGHTED : 0u);
-
-        // fallback workspace and the output tables
-        auto layout3 = [&](Arena& ar) {
-            for (int i = 0; i < ntw2; ++i) {
-                WinTask& T = W2.wt[i];
-                T.part = ar.take<double>((size_t)T.n_jt * T.K * 4);
-                T.part2 = ar.take<double>((size_t)ceil_div(T.n_jt, kWinJc) * T.K * 4);
-                T.sums = ar.take<double>((size_t)T.K * 4);
-            }
-        };
-        Arena a3;
-        layout3(a3);
-        if (ntw2 > 0) {
-            void* ws3 = nullptr;
-            NCF_TRY(ensure_ws(R, 2, a3.off + 256, &ws3));
-            a3 = Arena{(char*)ws3, 0};
-            layout3(a3);
-        }
-        struct T3 {
-            WinTask* wt;
-            int64_t *item0, *wk0, *r0;
-            double* dl;
-            int32_t* fbrow;
-            int32_t* perm;
-            NormTask* nt;
-            int32_t* status;
-            IoBlock* io;
-        } dU{}, hU{};
-        size_t ndl2 = 0;
-        for (auto& P : W2.plans) ndl2 += P.dl.size();
-        const bool any_fb = ntw2 > 0;
-        auto take3 = [&](Tables& tb) {
-            dU.wt = tb.take<WinTask>(ntw2, &hU.wt);
-            dU.item0 = tb.take<int64_t>(ntw2 + 1, &hU.item0);
-            dU.wk0 = tb.take<int64_t>(ntw2 + 1, &hU.wk0);
-            dU.r0 = tb.take<int64_t>(ntw2 + 1, &hU.r0);
-            dU.dl = tb.take<double>(ndl2, &hU.dl);
-            // fallback rows: K entries per problem with fallback lags
-            dU.fbrow = tb.take<int32_t>(any_fb ? (size_t)ntw2 * K : 1, &hU.fbrow);
-            dU.perm = tb.take<int32_t>(K, &hU.perm);
-            dU.nt = tb.take<NormTask>(J.nprob, &hU.nt);
-            dU.status = tb.take<int32_t>(J.nprob, &hU.status);
-            dU.io = tb.take<IoBlock>(1, &hU.io);
-        };
-        Tables t3;
-        take3(t3);
-        Staging* stg3 = nullptr;
-        NCF_TRY(ensure_stage(R, 2, t3.off, &stg3));
-        t3 = Tables{stg3->h, stg3->d, 0};
-        take3(t3);
+    // phase-3 tables (laid out in dU / hU): the fallback window tasks of W2
+    // (ntw2 of them), the normalization tasks, statuses and the I/O block
+    auto fill3 = [&](int ntw2, bool any_fb) {
         std::vector<int> fb_task(J.nprob, -1);
         {
             size_t o = 0;
@@ -1685,7 +1576,120 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         hU.io->b = d_b;
         hU.io->count = d_cnt;
         hU.io->status = dU.status;
-        NCF_TRY_HIP(hipMemcpyAsync(stg3->d, stg3->h, t3.off, hipMemcpyHostToDevice, J.st));
+    };
+    if (merge3) fill3(0, false);
+    NCF_TRY_HIP(hipMemcpyAsync(stg2->d, stg2->h, t2.off, hipMemcpyHostToDevice, J.st));
+
+    // ------------------------------------------------ A7 window scan
+    // work-queue dispatch of the window scans (scheduling option)
+    unsigned long long* qbase = nullptr;
+    if ((J.opt.flags & NCF_WINDOW_QUEUE) || J.tune.queue) NCF_TRY(ensure_queue(R, &qbase));
+    {
+        const WinTask* wt = dT.wt;
+        const int64_t *it0 = dT.item0, *wk0 = dT.wk0, *r0 = dT.r0;
+        const int64_t nitems = W1.nitems, rows = W1.total_rows, nred1 = W1.nred1;
+        const int cap = W1.cap, jmax = W1.jmax;
+        const double work = W1.work;
+        unsigned long long* q = qbase;
+        if (ntw > 0) {
+            NCF_TRY(emit(J, [=](hipStream_t s) {
+                return launch_window(wt, it0, ntw, nitems, wflags, cap, jmax, q, s, work);
+            }));
+            NCF_TRY(emit(J, [=](hipStream_t s) {
+                return launch_window_reduce(wt, ntw, rows, wk0, r0, nred1, wflags, s);
+            }));
+        }
+    }
+
+    // ------------------------------------------------ A2-A6 spectral route
+    if (nts > 0) {
+        const SpecTask* stk = dT.st;
+        const int64_t *tile0 = dT.tile0, *pos0 = dT.pos0, *sk0 = dT.sk0;
+        const int64_t* rinfo = (const int64_t*)dT.rinfo;
+        const double pbytes = (nfwd + 1.0 + (spec_unw ? 1.0 : 0.0)) * total_pos * csz;
+        const int64_t nkeval = (int64_t)nts * Keval;
+        const bool ccf = J.ccf;
+        const int32_t* smap = dT.smap;
+        const int64_t* rec_all = d_rng;
+        const Chunk* dch = d_ch;
+        const double tb_bytes = 8.0 * (double)total_samp;
+        if (bounds_pass)
+            NCF_TRY(emit(J, [=](hipStream_t s) {
+                return launch_tile_bounds(stk, dch, nch, smap, s, tb_bytes);
+            }));
+        NCF_TRY(emit(J, [=](hipStream_t s) {
+            return launch_spread(stk, tile0, nts, ntiles, rec_all, 4096, ccf, spec_b, spec_w,
+                                 spec_unw, fp64, s, spread_bytes);
+        }));
+        // the forward last pass, the product and the inverse first pass run
+        // fused over tile pairs where the mode fits the LDS of one workgroup
+        const bool fuse = !J.tune.no_mid && mid_supported(J.ccf, spec_b, spec_unw, fp64);
+        for (size_t q = 0; q < groups.size(); ++q) {
+            const FftPlan fp = plans[splans[groups[q].first].g.N];
+            void* const* gp = dT.gfwd + fwd_groups[q].first;
+            const int cnt = fwd_groups[q].second;
+            NCF_TRY(emit(J, [=](hipStream_t s) {
+                return fft_exec(fp, gp, cnt, +1, fp64, s, fuse);
+            }));
+        }
+        if (fuse) {
+            const int64_t* pair0 = dT.pair0;
+            const int64_t npairs = total_pairs;
+            const void* wsmall = plans.begin()->second.small;
+            const double mbytes = (double)(nfwd + 1) * total_pos * csz;
+            NCF_TRY(emit(J, [=](hipStream_t s) {
+                return launch_mid(stk, pair0, nts, npairs, rinfo, wsmall, ccf, spec_b, fp64, s,
+                                  mbytes);
+            }));
+        } else {
+            NCF_TRY(emit(J, [=](hipStream_t s) {
+                return launch_product(stk, pos0, nts, total_pos, rinfo, ccf, spec_b, spec_unw,
+                                      fp64, s, pbytes);
+            }));
+        }
+        for (size_t q = 0; q < groups.size(); ++q) {
+            const FftPlan fp = plans[splans[groups[q].first].g.N];
+            void* const* gp = dT.ginv + inv_groups[q].first;
+            const int cnt = inv_groups[q].second;
+            NCF_TRY(emit(J, [=](hipStream_t s) {
+                return fft_exec(fp, gp, cnt, -1, fp64, s, fuse);
+            }));
+        }
+        NCF_TRY(emit(J, [=](hipStream_t s) { return launch_interp(stk, nts, sk0, nkeval, fp64, s); }));
+    }
+
+    // ------------------------------------------------ direct fallback (spectral b)
+    int32_t* h_fstat = nullptr;
+    if (flag_pass) {
+        // flags computed on the device from the spectral b values (contiguous
+        // over the problems); only the bit masks come back
+        NCF_TRY(launch_fallback_flags(bspec[0], nts, Keval, (int)K, J.ccf, dT.rowk, Krow, beta,
+                                      dT.mask, J.st));
+        if (!combine)
+            NCF_TRY_HIP(hipMemcpyAsync(hT.mask, dT.mask, sizeof(uint64_t) * (size_t)nts * fwords,
+                                       hipMemcpyDeviceToHost, J.st));
+    }
+    auto read_flags = [&]() {
+        for (int i = 0; i < nts; ++i) {
+            const int64_t p = splans[i].prob;
+            const uint64_t* mw = hT.mask + (size_t)i * fwords;
+            std::vector<double> dl;
+            for (int w = 0; w < fwords; ++w)
+                for (uint64_t m = mw[w]; m; m &= m - 1) {
+                    const int r = w * 64 + __builtin_ctzll(m);
+                    flagged[p].push_back(rows[r].second);
+                    dl.push_back(delta[r]);
+                }
+            if (!dl.empty())
+                W2.plans.push_back({0, J.ccf ? 1 : 0, p, 3, std::move(dl)});
+        }
+    };
+    // phase-3 launches on the tables in dU: the fallback window scans, the
+    // normalization, and the copies of the statuses (with the flag masks in
+    // front when with_masks) and of host-memory outputs
+    auto launch3 = [&](int ntw2, bool with_masks) -> int {
+        const uint32_t wflags2 = (fp64 ? (uint32_t)WIN_EXP64 : 0u) | (uint32_t)WIN_NUMER |
+                                 (weighted ? (uint32_t)WIN_WEIGHTED : 0u);
         if (ntw2 > 0) {
             const WinTask* wt = dU.wt;
             const int64_t *it0 = dU.item0, *wk0 = dU.wk0, *r0 = dU.r0;
@@ -1708,9 +1712,15 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             const IoBlock* io = J.io_fixed ? J.io_fixed : dU.io;
             NCF_TRY(emit(J, [=](hipStream_t s) { return launch_normalize(nt, np, io, s); }));
         }
-        h_fstat = hU.status;  // pinned; its upload was enqueued before
-        NCF_TRY_HIP(hipMemcpyAsync(h_fstat, J.io_fixed ? J.io_status : dU.status,
-                                   sizeof(int32_t) * J.nprob, hipMemcpyDeviceToHost, J.st));
+        h_fstat = hU.status;  // pinned
+        if (with_masks) {
+            const size_t bytes =
+                (size_t)((const char*)(dU.status + J.nprob) - (const char*)dT.mask);
+            NCF_TRY_HIP(hipMemcpyAsync(hT.mask, dT.mask, bytes, hipMemcpyDeviceToHost, J.st));
+        } else {
+            NCF_TRY_HIP(hipMemcpyAsync(h_fstat, J.io_fixed ? J.io_status : dU.status,
+                                       sizeof(int32_t) * J.nprob, hipMemcpyDeviceToHost, J.st));
+        }
         if (!J.dev_ptrs && K > 0) {
             NCF_TRY_HIP(hipMemcpyAsync(J.c, d_c, sizeof(double) * J.nprob * K, hipMemcpyDeviceToHost,
                                        J.st));
@@ -1722,31 +1732,65 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         }
         return NCF_OK;
     };
+    // phase 3 with its own tables and upload (the fallback tasks of W2)
+    auto separate3 = [&]() -> int {
+        const int ntw2 = (int)W2.plans.size();
+        // fallback workspace and the output tables
+        auto layout3 = [&](Arena& ar) {
+            for (int i = 0; i < ntw2; ++i) {
+                WinTask& T = W2.wt[i];
+                T.part = ar.take<double>((size_t)T.n_jt * T.K * 4);
+                T.part2 = ar.take<double>((size_t)ceil_div(T.n_jt, kWinJc) * T.K * 4);
+                T.sums = ar.take<double>((size_t)T.K * 4);
+            }
+        };
+        Arena a3;
+        layout3(a3);
+        if (ntw2 > 0) {
+            void* ws3 = nullptr;
+            NCF_TRY(ensure_ws(R, 2, a3.off + 256, &ws3));
+            a3 = Arena{(char*)ws3, 0};
+            layout3(a3);
+        }
+        size_t ndl2 = 0;
+        for (auto& P : W2.plans) ndl2 += P.dl.size();
+        const bool any_fb = ntw2 > 0;
+        Tables t3;
+        take3(t3, ntw2, ndl2, any_fb);
+        Staging* stg3 = nullptr;
+        NCF_TRY(ensure_stage(R, 2, t3.off, &stg3));
+        t3 = Tables{stg3->h, stg3->d, 0};
+        take3(t3, ntw2, ndl2, any_fb);
+        fill3(ntw2, any_fb);
+        NCF_TRY_HIP(hipMemcpyAsync(stg3->d, stg3->h, t3.off, hipMemcpyHostToDevice, J.st));
+        return launch3(ntw2, false);
+    };
+    auto done = [&]() -> int {
+        NCF_TRY_HIP(hipStreamSynchronize(J.st));
+        if (g_prof_on) {
+            std::lock_guard<std::mutex> lock(g_prof_mu);
+            prof_flush_locked();
+        }
+        return finish_status(J, pstat, h_fstat);
+    };
+    if (!flag_pass) {  // tables uploaded with phase 2
+        NCF_TRY(launch3(0, false));
+        return done();
+    }
     if (speculate) {
-        NCF_TRY(enqueue_phase3());
+        NCF_TRY(launch3(0, combine));
         NCF_TRY_HIP(hipStreamSynchronize(J.st));
         read_flags();
-        if (W2.plans.empty()) {
-            if (g_prof_on) {
-                std::lock_guard<std::mutex> lock(g_prof_mu);
-                prof_flush_locked();
-            }
-            return finish_status(J, pstat, h_fstat);
-        }
-    } else if (flag_pass) {
+        if (W2.plans.empty()) return done();
+    } else {
         NCF_TRY_HIP(hipStreamSynchronize(J.st));
         read_flags();
     }
     if (!W2.plans.empty()) plan_window(W2);
     J.info_window_items += W2.nitems;
     J.info_window_launches += W2.plans.empty() ? 0 : 1;
-    NCF_TRY(enqueue_phase3());
-    NCF_TRY_HIP(hipStreamSynchronize(J.st));
-    if (g_prof_on) {
-        std::lock_guard<std::mutex> lock(g_prof_mu);
-        prof_flush_locked();
-    }
-    return finish_status(J, pstat, h_fstat);
+    NCF_TRY(separate3());
+    return done();
 }
 
 // ---------------------------------------------------------- entry helpers

@@ -196,6 +196,9 @@ struct MomentsArgs {
     const IoBlock* io;       // value arrays
     int32_t prefix;          // any series has prefix outputs
     int32_t pad;
+    const double* lag_src;   // optional: lags copied to lag_dst by the finalize
+    double* lag_dst;         // kernel (next to the statistics, one readback)
+    int64_t nlag;
 };
 
 int launch_moments(const MomentsArgs& a, hipStream_t st);

@@ -139,6 +139,8 @@ k_series_finalize(MomentsArgs a) {
     __shared__ int shf[kWaves];
     const int s = blockIdx.x;
     const int tid = threadIdx.x;
+    if (s == 0 && a.lag_src)
+        for (int64_t i = tid; i < a.nlag; i += kThreads) gbl(a.lag_dst)[i] = gbl(a.lag_src)[i];
     const int lane = tid & 63, wave = tid >> 6;
     const SeriesDesc sd = a.series[s];
     double sw = 0.0, mean = 0.0, m2 = 0.0;
