@@ -208,9 +208,13 @@ __device__ __forceinline__ double wave_scan(double v) {
 }
 
 // Standardize one chunk and write the chunk-local inclusive prefix sums.
+// A thread holds the samples tid + k * kThreads (k < kPer) of its chunk: all
+// loads are issued before any store, and the prefix of sample (k, wave, lane)
+// is the carry of the preceding rows k, plus the totals of the preceding
+// waves of row k, plus the lane's inclusive wave scan (one barrier).
 __global__ void __launch_bounds__(kThreads)
 k_standardize(MomentsArgs a) {
-    __shared__ double shv[2][kWaves];
+    __shared__ double shv[2][kPer][kWaves];
     const Chunk ch = a.chunks[blockIdx.x];
     const SeriesDesc sd = a.series[ch.series];
     const SeriesStat st = a.stats[ch.series];
@@ -221,49 +225,67 @@ k_standardize(MomentsArgs a) {
     const bool ok = st.status == NCF_OK;
     const double mean = st.mean;
     const double inv_sd = ok ? 1.0 / st.sd : 0.0;
-    const bool do_prefix = sd.pv != nullptr;
-    double carry_v = 0.0, carry_w = 0.0;
-    // prefix index of sample i within the series' prefix array: i + 1
-    for (int64_t base = ch.begin; base < ch.end; base += kThreads) {
-        int64_t i = base + tid;
-        double v = 0.0, w = 0.0;
+    double v[kPer], w[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int64_t i = ch.begin + tid + (int64_t)k * kThreads;
+        v[k] = 0.0;
+        w[k] = 0.0;
         if (i < ch.end) {
-            w = 1.0;
+            double wk = 1.0;
             if (sd.err) {
-                double e = er[i];
-                w = sd.wmode ? e : 1.0 / (e * e);
+                const double e = er[i];
+                wk = sd.wmode ? e : 1.0 / (e * e);
             }
-            v = ok ? w * ((X[i] - mean) * inv_sd) : 0.0;
-            if (sd.v32) gbl(sd.v32)[i] = (float)v;
-            if (sd.v64) gbl(sd.v64)[i] = v;
-            if (sd.w64) gbl(sd.w64)[i] = w;
-        }
-        if (do_prefix) {
-            // inclusive scan: within each wave by shuffles, then the totals
-            // of the preceding waves in index order
-            const double sv = wave_scan(v), swt = wave_scan(w);
-            if (lane == 63) {
-                shv[0][wave] = sv;
-                shv[1][wave] = swt;
-            }
-            __syncthreads();
-            double ov = carry_v, ow = carry_w;
-            for (int q = 0; q < wave; ++q) {
-                ov += shv[0][q];
-                ow += shv[1][q];
-            }
-            if (i < ch.end) {
-                gbl(sd.pv)[i + 1] = ov + sv;
-                if (sd.pw) gbl(sd.pw)[i + 1] = ow + swt;
-            }
-            for (int q = 0; q < kWaves; ++q) {
-                carry_v += shv[0][q];
-                carry_w += shv[1][q];
-            }
-            __syncthreads();
+            w[k] = wk;
+            v[k] = X[i];
         }
     }
-    if (do_prefix && tid == 0) {
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int64_t i = ch.begin + tid + (int64_t)k * kThreads;
+        if (i < ch.end) {
+            v[k] = ok ? w[k] * ((v[k] - mean) * inv_sd) : 0.0;
+            if (sd.v32) gbl(sd.v32)[i] = (float)v[k];
+            if (sd.v64) gbl(sd.v64)[i] = v[k];
+            if (sd.w64) gbl(sd.w64)[i] = w[k];
+        }
+    }
+    if (sd.pv == nullptr) return;
+    // prefix index of sample i within the series' prefix array: i + 1
+    const bool scan_w = sd.pw != nullptr;  // weight prefix only with weights
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) v[k] = wave_scan(v[k]);
+    if (scan_w)
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) w[k] = wave_scan(w[k]);
+    if (lane == 63)
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            shv[0][k][wave] = v[k];
+            shv[1][k][wave] = w[k];
+        }
+    __syncthreads();
+    double carry_v = 0.0, carry_w = 0.0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int64_t i = ch.begin + tid + (int64_t)k * kThreads;
+        double ov = carry_v, ow = carry_w;
+        for (int q = 0; q < wave; ++q) {
+            ov += shv[0][k][q];
+            ow += shv[1][k][q];
+        }
+        if (i < ch.end) {
+            gbl(sd.pv)[i + 1] = ov + v[k];
+            if (sd.pw) gbl(sd.pw)[i + 1] = ow + w[k];
+        }
+#pragma unroll
+        for (int q = 0; q < kWaves; ++q) {
+            carry_v += shv[0][k][q];
+            carry_w += shv[1][k][q];
+        }
+    }
+    if (tid == 0) {
         a.chunk_tot[2 * (int64_t)blockIdx.x] = carry_v;
         a.chunk_tot[2 * (int64_t)blockIdx.x + 1] = carry_w;
         if (ch.begin == 0) {
@@ -274,14 +296,15 @@ k_standardize(MomentsArgs a) {
 }
 
 // Exclusive scan of chunk totals per series (in place: chunk_tot becomes the
-// offset to add to each chunk). One workgroup per series: per-thread runs,
-// then a fixed-order scan of the run totals.
+// offset to add to each chunk). One workgroup per series: per-thread runs in
+// order, then a scan of the run totals (wave scans, then the totals of the
+// preceding waves).
 __global__ void __launch_bounds__(kThreads)
 k_chunk_offsets(MomentsArgs a) {
-    __shared__ double shv[kThreads];
-    __shared__ double shw[kThreads];
+    __shared__ double shv[2][kWaves];
     const int s = blockIdx.x;
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
     const SeriesDesc sd = a.series[s];
     if (!sd.pv) return;
     const int per = (sd.nchunk + kThreads - 1) / kThreads;
@@ -292,21 +315,22 @@ k_chunk_offsets(MomentsArgs a) {
         tv += p[0];
         tw += p[1];
     }
-    shv[tid] = tv;
-    shw[tid] = tw;
-    __syncthreads();
-    if (tid == 0) {  // exclusive scan of 256 run totals, in order
-        double cv = 0.0, cw = 0.0;
-        for (int i = 0; i < kThreads; ++i) {
-            const double v = shv[i], w = shw[i];
-            shv[i] = cv;
-            shw[i] = cw;
-            cv += v;
-            cw += w;
-        }
+    const double iv = wave_scan(tv), iw = wave_scan(tw);
+    if (lane == 63) {
+        shv[0][wave] = iv;
+        shv[1][wave] = iw;
     }
     __syncthreads();
-    double cv = shv[tid], cw = shw[tid];
+    double ev = __shfl_up(iv, 1), ew = __shfl_up(iw, 1);  // exclusive within the wave
+    double cv = 0.0, cw = 0.0;
+    for (int q = 0; q < wave; ++q) {
+        cv += shv[0][q];
+        cw += shv[1][q];
+    }
+    if (lane > 0) {
+        cv += ev;
+        cw += ew;
+    }
     for (int c = c0; c < c1; ++c) {
         double* p = a.chunk_tot + 2 * (int64_t)(sd.chunk0 + c);
         const double v = p[0], w = p[1];
@@ -317,17 +341,35 @@ k_chunk_offsets(MomentsArgs a) {
     }
 }
 
+// Add the chunk's offset to its prefix sums (a chunk holds at most kPer
+// samples per thread): loads first, then stores.
 __global__ void __launch_bounds__(kThreads)
 k_prefix_add(MomentsArgs a) {
     const Chunk ch = a.chunks[blockIdx.x];
     const SeriesDesc sd = a.series[ch.series];
     if (!sd.pv) return;
+    if (ch.begin == 0) return;  // first chunk: offset 0
     const double ov = a.chunk_tot[2 * (int64_t)blockIdx.x];
     const double ow = a.chunk_tot[2 * (int64_t)blockIdx.x + 1];
-    if (ch.begin == 0) return;  // first chunk: offset 0
-    for (int64_t i = ch.begin + threadIdx.x; i < ch.end; i += kThreads) {
-        sd.pv[i + 1] += ov;
-        if (sd.pw) sd.pw[i + 1] += ow;
+    const gptr<double> pv = gbl(sd.pv), pw = gbl(sd.pw);
+    double v[kPer], w[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int64_t i = ch.begin + threadIdx.x + (int64_t)k * kThreads;
+        v[k] = 0.0;
+        w[k] = 0.0;
+        if (i < ch.end) {
+            v[k] = pv[i + 1];
+            if (sd.pw) w[k] = pw[i + 1];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int64_t i = ch.begin + threadIdx.x + (int64_t)k * kThreads;
+        if (i < ch.end) {
+            pv[i + 1] = v[k] + ov;
+            if (sd.pw) pw[i + 1] = w[k] + ow;
+        }
     }
 }
 
