@@ -74,7 +74,11 @@ extern "C" {
 typedef enum { NCF_GAUSSIAN = 0, NCF_RECTANGLE = 1 } ncf_kernel_t;
 
 /* NCF_MIXED: FP32 spreading / FFT / kernel weights with FP64 positions,
- * phases, moments, prefix sums and accumulators.
+ * phases, moments, prefix sums and accumulators. c is divided by the lag-0
+ * scale (ACF r(0), CCF sqrt(r_x(0) r_y(0)) of the standardized values), which
+ * is of order 1 unless the kernel spans much of a short series and the lag-0
+ * sums cancel; the Gaussian kernel's scale then carries a relative error of
+ * about 1e-6 / r(0) in this mode: use NCF_FP64 for such near-degenerate series.
  * NCF_FP64: every step in FP64. */
 typedef enum { NCF_MIXED = 0, NCF_FP64 = 1 } ncf_precision_t;
 
@@ -83,13 +87,17 @@ typedef enum { NCF_MIXED = 0, NCF_FP64 = 1 } ncf_precision_t;
  *   sums cost less (then as NCF_DIRECT; see NCF_SPECTRAL_ALWAYS). The Gaussian
  *   pair count b takes the same route with unit values (with errors: the
  *   weighted pair sum B with the weights, and b with unit values), and lags
- *   whose spectral b (B) falls below a fraction beta of the reference (b(0)
- *   for the ACF, the largest requested lag's b for the CCF; beta = 0.1 mixed,
- *   0.01 FP64) are summed directly by the window scan. Rectangle:
+ *   whose spectral b (B), times min(1, s) with s the lag-0 scale (ACF r(0),
+ *   CCF sqrt(r_x(0) r_y(0)), below 1 when the lag-0 sums of the standardized
+ *   values cancel), falls below a fraction beta of the reference (b(0) for
+ *   the ACF, sqrt(b_xx(0) b_yy(0)) of the two series for the CCF: both bound
+ *   b at every lag, requested or not; beta = 0.1 mixed, 0.01 FP64) are
+ *   summed directly by the window scan. Rectangle:
  *   numerator by prefix sums over the window (Algorithm "CorrSum,
  *   rectangle") and exact pair counts from the window scan.
  * NCF_SPECTRAL: Gaussian numerator by the spectral route, pair counts by the
- *   window scan; for the rectangle kernel the spectral route with the box
+ *   window scan, and the direct numerator at lags where b min(1, s) is below
+ *   beta times the same reference; for the rectangle kernel the spectral route with the box
  *   kernel's Fourier transform (diagnostic: its truncation error decays only
  *   as 1/f).
  * NCF_DIRECT: numerator and pair counts by the window scan (real-space

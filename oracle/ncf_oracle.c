@@ -58,6 +58,11 @@
 #define ORC_RECTANGLE 1
 
 static const double ORC_FLOOR = 1e-16;
+/* A lag-0 scale at or below this is degenerate. For standardized values r(0)
+ * is of order 1; a kernel wide enough to hold every pair of a short series
+ * makes the lag-0 sum (sum of z)^2 = 0 in exact arithmetic, and its rounded
+ * value (~1e-16, either sign) must not decide the status. */
+static const double ORC_MIN_SCALE = 1e-12;
 
 /* ---------------------------------------------------------------- checks */
 
@@ -333,7 +338,7 @@ static int acf_impl(int64_t n, const double* t, const double* x, const double* e
     window_sums(kernel, +1, n, t, v, w, n, t, v, w, m, m, dt, K + 1, ev, h, C, B, bb, cnt,
                 nthreads, brute);
     double r0 = C[0] / floor_b(B[0]);
-    if (!(r0 > 0.0) || !isfinite(r0)) {
+    if (!(r0 > ORC_MIN_SCALE) || !isfinite(r0)) {
         for (int64_t k = 0; k < K; ++k) {
             c[k] = NAN;
             if (b_out) b_out[k] = floor_b(bb[k + 1]);
@@ -425,7 +430,8 @@ static int ccf_impl(int64_t nx, const double* t, const double* x, const double* 
                 &ns, nthreads, brute);
     double scale_y = Cs / floor_b(Bs);
     double prod = scale_x * scale_y;
-    int degenerate = !(prod > 0.0) || !isfinite(prod);
+    int degenerate = !(fabs(scale_x) > ORC_MIN_SCALE) || !(fabs(scale_y) > ORC_MIN_SCALE) ||
+                     !(prod > 0.0) || !isfinite(prod);
     double scale = degenerate ? NAN : sqrt(prod);
     for (int64_t k = 0; k < K; ++k) {
         double r = C[k] / floor_b(B[k]);

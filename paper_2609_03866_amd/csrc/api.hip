@@ -1486,7 +1486,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     if (flag_pass)
         for (int r = 0; r < Krow; ++r) hT.rowk[r] = rows[r].second;
     // lags whose spectral pair count is below beta times the reference
-    // (lag 0 for the ACF, the largest requested lag for the CCF) are summed
+    // (b(0) for the ACF, sqrt(B_xx(0) B_yy(0)) for the CCF) are summed
     // directly: their spectral value is dominated by rounding noise
     std::vector<int> spec_of(J.nprob, -1);
     for (int i = 0; i < nts; ++i) spec_of[splans[i].prob] = i;
@@ -1663,8 +1663,8 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     if (flag_pass) {
         // flags computed on the device from the spectral b values (contiguous
         // over the problems); only the bit masks come back
-        NCF_TRY(launch_fallback_flags(bspec[0], nts, Keval, (int)K, J.ccf, dT.rowk, Krow, beta,
-                                      dT.mask, J.st));
+        NCF_TRY(launch_fallback_flags(dT.st, bspec[0], nts, Keval, (int)K, J.ccf, dT.rowk, Krow,
+                                      beta, dT.mask, J.st));
         if (!combine)
             NCF_TRY_HIP(hipMemcpyAsync(hT.mask, dT.mask, sizeof(uint64_t) * (size_t)nts * fwords,
                                        hipMemcpyDeviceToHost, J.st));

@@ -171,6 +171,11 @@ struct SeriesDesc {
     int32_t wmode;    // 1: err holds sample weights w >= 0 directly (else errors, w = 1/err^2)
 };
 
+// Smallest lag-0 scale that is not degenerate: r(0) of standardized values
+// is of order 1, and when a kernel holds every pair of a short series the
+// lag-0 sum (sum of z)^2 is 0 exactly, so its rounding (either sign) must not
+// decide the status. CCF: each series' r(0) in magnitude, and the product > 0.
+constexpr double kMinScale = 1e-12;
 constexpr int64_t kMomentChunk = 2048;  // samples per moments chunk (8 per thread)
 
 struct Chunk {
@@ -325,13 +330,14 @@ int launch_spread(const SpecTask* d_tasks, const int64_t* d_tile0, int ntasks, i
                   const int64_t* d_tile_rec, int tile, bool ccf, bool with_b, bool weighted,
                   bool unw, bool fp64, hipStream_t st, double bytes);
 // Bit masks of the window rows whose spectral pair count falls back to the
-// direct sums (b below beta times the problem's reference): bspec holds the
-// problems' Keval evaluations contiguously, rowk the evaluation index of each
-// of the Krow window rows (-1: none); mask gets ceil(Krow / 64) words per
-// problem.
-int launch_fallback_flags(const double* bspec, int64_t nprob, int Keval, int K, bool ccf,
-                          const int32_t* rowk, int Krow, double beta, uint64_t* mask,
-                          hipStream_t st);
+// direct sums (b below beta times the problem's reference: b(0) for the ACF,
+// sqrt(B_xx(0) B_yy(0)) from the tasks' product partials for the CCF): bspec
+// holds the problems' Keval evaluations contiguously (problem i is task i),
+// rowk the evaluation index of each of the Krow window rows (-1: none); mask
+// gets ceil(Krow / 64) words per problem.
+int launch_fallback_flags(const SpecTask* d_tasks, const double* bspec, int64_t nprob,
+                          int Keval, int K, bool ccf, const int32_t* rowk, int Krow, double beta,
+                          uint64_t* mask, hipStream_t st);
 int launch_interp(const SpecTask* d_tasks, int ntasks, const int64_t* d_k0, int64_t total_k,
                   bool fp64, hipStream_t st);
 

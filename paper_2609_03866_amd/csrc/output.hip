@@ -25,7 +25,6 @@ __device__ __forceinline__ double fl(double v) { return v > kFloor ? v : kFloor;
 __global__ void __launch_bounds__(kThreads)
 k_normalize(const NormTask* __restrict__ tasks, const IoBlock* __restrict__ io) {
     __shared__ double red[4][kThreads];
-    __shared__ double redm[kThreads];
     __shared__ double sh_scale, sh_bref;
     const NormTask& T = tasks[blockIdx.x];
     const int tid = threadIdx.x;
@@ -47,8 +46,15 @@ k_normalize(const NormTask* __restrict__ tasks, const IoBlock* __restrict__ io) 
         return;
     }
     const int bq = T.weighted ? 1 : 2;  // which window sum is the denominator B
+    // lag-0 scale: from the direct window sums where the call has them (the
+    // direct path, and the Gaussian spectral numerator with window pair
+    // counts: there the lag-0 sums of a short series under a wide kernel can
+    // cancel, and the transforms' rounding error would not), else from the
+    // spectral lag-0 values (spectral pair counts; the rectangle kernel on
+    // the spectral route, whose window pass sums no numerator)
+    const bool spec_scale = T.spectral && (T.spec_b || T.is_rect);
     // spectral lag-0 sums (CCF): S_xx, S_yy and, with spectral b, B_xx, B_yy
-    if (T.ccf && T.spectral) {
+    if (T.ccf && spec_scale) {
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         for (int64_t i = tid; i < T.nscale_part; i += kThreads)
             for (int q = 0; q < 4; ++q) acc[q] += T.scale_part[4 * i + q];
@@ -60,22 +66,9 @@ k_normalize(const NormTask* __restrict__ tasks, const IoBlock* __restrict__ io) 
             __syncthreads();
         }
     }
-    // reference pair count of the window-b spectral path (ACF: lag 0, CCF:
-    // the largest requested lag)
-    const bool sel_window = T.spectral && !T.spec_b;
-    if (sel_window) {
-        double m = 0.0;
-        if (T.ccf)
-            for (int k = tid; k < T.K; k += kThreads) m = fmax(m, T.wsums[4 * T.perm[k] + bq]);
-        redm[tid] = m;
-        __syncthreads();
-        for (int off = kThreads / 2; off > 0; off >>= 1) {
-            if (tid < off) redm[tid] = fmax(redm[tid], redm[tid + off]);
-            __syncthreads();
-        }
-        if (tid == 0) sh_bref = T.ccf ? redm[0] : T.wsums[4 * T.row0 + bq];
-        __syncthreads();
-    }
+    // Gaussian spectral numerator with window pair counts: the direct
+    // numerator where b is small
+    const bool sel_window = T.spectral && !T.spec_b && !T.is_rect;
     if (tid == 0) {
         double scale;
         if (T.ccf) {
@@ -85,7 +78,7 @@ k_normalize(const NormTask* __restrict__ tasks, const IoBlock* __restrict__ io) 
                 cy = red[1][0];
                 bx = red[2][0];
                 by = red[3][0];
-            } else if (T.spectral) {
+            } else if (spec_scale) {
                 cx = red[0][0];
                 cy = red[1][0];
                 bx = T.self_x[bq];
@@ -96,22 +89,37 @@ k_normalize(const NormTask* __restrict__ tasks, const IoBlock* __restrict__ io) 
                 bx = T.self_x[bq];
                 by = T.self_y[bq];
             }
-            const double prod = (cx / fl(bx)) * (cy / fl(by));
-            scale = (prod > 0.0 && isfinite(prod)) ? sqrt(prod) : NAN;
+            const double sx = cx / fl(bx), sy = cy / fl(by), prod = sx * sy;
+            scale = (fabs(sx) > kMinScale && fabs(sy) > kMinScale && prod > 0.0 &&
+                     isfinite(prod))
+                        ? sqrt(prod)
+                        : NAN;
         } else {
             double c0, b0;
             if (T.spectral && T.spec_b) {
                 c0 = T.numer[T.K];
                 b0 = T.bspec[T.K];
             } else {
-                c0 = T.spectral ? T.numer[T.K] : T.wsums[4 * T.row0 + 0];
+                c0 = spec_scale ? T.numer[T.K] : T.wsums[4 * T.row0 + 0];
                 b0 = T.wsums[4 * T.row0 + bq];
             }
             const double r0 = c0 / fl(b0);
-            scale = (r0 > 0.0 && isfinite(r0)) ? r0 : NAN;
+            scale = (r0 > kMinScale && isfinite(r0)) ? r0 : NAN;
         }
         sh_scale = scale;
         *out_st = (scale == scale) ? NCF_OK : NCF_E_DEGENERATE;
+        if (sel_window) {
+            // reference pair count of the window-b spectral path, a bound of
+            // the pair sum over every lag: ACF b(0); CCF sqrt(B_xx(0) B_yy(0))
+            // from the two series' lag-0 window sums (Cauchy-Schwarz: the
+            // Gaussian lag kernel is a self-convolution); it sets the scale of
+            // the spectral numerator's rounding error, which the division by
+            // a lag-0 scale below 1 amplifies: a lag takes the direct
+            // numerator when b min(1, scale) < beta b_ref
+            const double bref =
+                T.ccf ? sqrt(T.self_x[bq] * T.self_y[bq]) : T.wsums[4 * T.row0 + bq];
+            sh_bref = bref / (scale > 0.0 ? fmin(1.0, scale) : 1.0);
+        }
     }
     __syncthreads();
     const double scale = sh_scale;
@@ -135,7 +143,7 @@ k_normalize(const NormTask* __restrict__ tasks, const IoBlock* __restrict__ io) 
             // pairs takes the direct numerator (the spectral value there is
             // rounding noise that a small denominator would amplify)
             const bool empty = __double_as_longlong(w[3]) == 0;
-            const bool direct = !T.spectral || (w[bq] < T.beta * sh_bref);
+            const bool direct = !T.spectral || (sel_window && w[bq] < T.beta * sh_bref);
             num = empty ? 0.0 : (direct ? w[0] : T.numer[k]);
             den = w[bq];
             bout = w[2];

@@ -401,13 +401,15 @@ k_reg_finish(const RegTask* __restrict__ tasks, int nkb, const double* __restric
         double c0, b0;
         block_window<MODE, KERN>(T, main_slots<MODE>(), 0.0, false, red, &c0, &b0);
         const double r0 = c0 / fl(b0);
-        scale = (r0 > 0.0 && isfinite(r0)) ? r0 : NAN;
+        scale = (r0 > kMinScale && isfinite(r0)) ? r0 : NAN;
     } else {
         double cx, bx, cy, by;
         block_window<MODE, KERN>(T, self_slots<MODE>(false), 0.0, false, red, &cx, &bx);
         block_window<MODE, KERN>(T, self_slots<MODE>(true), 0.0, false, red, &cy, &by);
-        const double prod = (cx / fl(bx)) * (cy / fl(by));
-        scale = (prod > 0.0 && isfinite(prod)) ? sqrt(prod) : NAN;
+        const double sx = cx / fl(bx), sy = cy / fl(by), prod = sx * sy;
+        scale = (fabs(sx) > kMinScale && fabs(sy) > kMinScale && prod > 0.0 && isfinite(prod))
+                    ? sqrt(prod)
+                    : NAN;
     }
     if (kb == 0 && tid == 0) io->status[T.index] = (scale == scale) ? NCF_OK : NCF_E_DEGENERATE;
     if (k >= K) return;

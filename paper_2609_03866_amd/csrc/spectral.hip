@@ -917,40 +917,72 @@ k_mid(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pair0, int
 // Fallback flags of the spectral pair counts; workgroup b = i chunks + g
 // takes rows [256 g, 256 g + 256) of problem i: window row r is flagged when its
 // spectral b (evaluation index rowk[r]; -1: no requested lag) is below beta
-// times the reference (ACF: the lag-0 entry; CCF: the largest over the
-// requested lags, NaN ignored, at least 0; each workgroup forms it), or when
-// the reference is not positive. Bit r % 64 of mask[i * words + r / 64].
+// times the reference, or when the reference is not positive. Bit r % 64 of
+// mask[i * words + r / 64].
+//
+// The reference bounds the pair sum at every lag and sets the scale of the
+// transforms' rounding error. ACF: b(0), the lag-0 entry. CCF:
+// sqrt(B_xx(0) B_yy(0)), the two series' lag-0 pair sums, which the product
+// kernel leaves as Parseval partials (entries 2 and 3 of each of the task's
+// N / 4096 records; each workgroup adds them in a fixed order). The Gaussian
+// lag kernel is the self-convolution of a narrower Gaussian, so by
+// Cauchy-Schwarz no lag of the CCF exceeds that bound, whether requested or
+// not; the largest requested b would miss a peak between or beyond the
+// requested lags.
+//
+// The output divides by the lag-0 scale s (ACF r(0) = N(0) / b(0); CCF
+// sqrt(r_x(0) r_y(0)) from the partials' S and B entries), which for
+// standardized values is near 1 unless the lag kernel spans much of a short
+// series and the lag-0 sums cancel; then the rounding error, which does not
+// cancel, is amplified by 1 / s. A row is therefore compared as
+// b min(1, s) against beta times the reference (s not positive or NaN: the
+// output is NaN with a status, and the factor is taken as 1).
 constexpr int kFlagThreads = 256;
 
 __global__ void __launch_bounds__(kFlagThreads)
-k_fallback_flags(const double* __restrict__ bspec, int Keval, int K, int ccf,
-                 const int32_t* __restrict__ rowk, int Krow, double beta, int words,
-                 uint64_t* __restrict__ mask) {
+k_fallback_flags(const SpecTask* __restrict__ tasks, const double* __restrict__ bspec, int Keval,
+                 int K, int ccf, const int32_t* __restrict__ rowk, int Krow, double beta,
+                 int words, uint64_t* __restrict__ mask) {
     const int chunks = (Krow + kFlagThreads - 1) / kFlagThreads;
     const int64_t i = (int64_t)blockIdx.x / chunks;
     const int g = (int)((int64_t)blockIdx.x % chunks);
     const gptr<const double> bb = gbl(bspec) + i * Keval;
-    __shared__ double red[kFlagThreads / 64];
-    double bref;
+    __shared__ double red[4][kFlagThreads / 64];
+    double bref, scale;
     if (ccf) {
-        double m = 0.0;
-        for (int k = threadIdx.x; k < K; k += kFlagThreads) m = fmax(m, bb[k]);
+        const int64_t nrec = tasks[i].N / 4096;
+        const gptr<const double> sp = gbl(tasks[i].scale_part);
+        double v[4] = {0.0, 0.0, 0.0, 0.0};  // S_xx, S_yy, B_xx, B_yy
+        for (int64_t r = threadIdx.x; r < nrec; r += kFlagThreads)
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+            for (int q = 0; q < 4; ++q) v[q] += sp[4 * r + q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] += __shfl_xor(v[q], off);
+        if ((threadIdx.x & 63) == 0)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) red[q][threadIdx.x >> 6] = v[q];
         __syncthreads();
-        bref = red[0];
 #pragma unroll
-        for (int w = 1; w < kFlagThreads / 64; ++w) bref = fmax(bref, red[w]);
+        for (int q = 0; q < 4; ++q) {
+            v[q] = red[q][0];
+#pragma unroll
+            for (int w = 1; w < kFlagThreads / 64; ++w) v[q] += red[q][w];
+        }
+        bref = sqrt(v[2] * v[3]);
+        scale = sqrt((v[0] / v[2]) * (v[1] / v[3]));
     } else {
         bref = bb[K];
+        scale = gbl(tasks[i].numer)[K] / bref;
     }
+    const double gs = scale > 0.0 ? fmin(1.0, scale) : 1.0;
     {
         const int r = g * kFlagThreads + (int)threadIdx.x;
         bool f = false;
         if (r < Krow) {
             const int k = gbl(rowk)[r];
-            if (k >= 0) f = !(bb[k] >= beta * bref) || !(bref > 0.0);
+            if (k >= 0) f = !(bb[k] * gs >= beta * bref) || !(bref > 0.0);
         }
         const unsigned long long bits = __ballot(f);
         if ((threadIdx.x & 63) == 0 && r < Krow) gbl(mask)[i * words + r / 64] = bits;
@@ -1051,9 +1083,9 @@ int launch_product(const SpecTask* d_tasks, const int64_t* d_pos0, int ntasks, i
     return NCF_OK;
 }
 
-int launch_fallback_flags(const double* bspec, int64_t nprob, int Keval, int K, bool ccf,
-                          const int32_t* rowk, int Krow, double beta, uint64_t* mask,
-                          hipStream_t st) {
+int launch_fallback_flags(const SpecTask* d_tasks, const double* bspec, int64_t nprob,
+                          int Keval, int K, bool ccf, const int32_t* rowk, int Krow, double beta,
+                          uint64_t* mask, hipStream_t st) {
     if (nprob <= 0 || Krow <= 0) return NCF_OK;
     const int64_t blocks = nprob * ceil_div(Krow, kFlagThreads);
     if (blocks > INT32_MAX) {
@@ -1061,8 +1093,9 @@ int launch_fallback_flags(const double* bspec, int64_t nprob, int Keval, int K, 
         return NCF_E_UNSUPPORTED;
     }
     ProfScope p(st, "fallback_flags", 0.0, "bytes");
-    hipLaunchKernelGGL(k_fallback_flags, dim3((unsigned)blocks), dim3(kFlagThreads), 0, st, bspec,
-                       Keval, K, ccf ? 1 : 0, rowk, Krow, beta, (int)ceil_div(Krow, 64), mask);
+    hipLaunchKernelGGL(k_fallback_flags, dim3((unsigned)blocks), dim3(kFlagThreads), 0, st,
+                       d_tasks, bspec, Keval, K, ccf ? 1 : 0, rowk, Krow, beta,
+                       (int)ceil_div(Krow, 64), mask);
     NCF_CHECK_LAUNCH();
     return NCF_OK;
 }

@@ -2,7 +2,9 @@
 
 Tolerances (|delta c| absolute per lag, b relative):
   * mixed precision, Gaussian, spectral numerator and pair count: c 1e-5,
-    |delta b| <= 1e-5 b_ref (b_ref = the largest pair count of the call):
+    |delta b| <= 1e-5 b_ref (b_ref = the largest pair count of the call;
+    the fallback rule's own reference is b(0) for the ACF and
+    sqrt(b_xx(0) b_yy(0)) for the CCF, both at least as large):
     the FP32 transforms leave an absolute error of about log2(N) eps32 b_ref
     on every lag, and lags with b < 0.1 b_ref are summed directly (FP64:
     b < 1e-2 b_ref);

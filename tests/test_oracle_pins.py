@@ -354,3 +354,28 @@ def test_status_codes():
     tt = t.copy()
     tt[4] = tt[3]  # ties are allowed
     assert O.acf(tt, x, lags, "r", 0.5)[0] == 0
+
+
+@pytest.mark.parametrize("n", [2, 3, 7, 40])
+def test_window_holding_every_pair_is_degenerate(n):
+    # Rectangle window wider than the series: every pair is in it, so the
+    # lag-0 sum of the standardized values is (sum of z)^2 = 0 in exact
+    # arithmetic, whatever the values; its rounded value has either sign.
+    # The status is degenerate (scale at or below 1e-12) in every case, for
+    # the ACF and for a CCF with such a series on either side.
+    rng = synth.rng_for(900 + n)
+    for _ in range(20):
+        t = np.sort(rng.uniform(0.0, 100.0, n))
+        x = rng.normal(size=n)
+        st, c, _, _ = O.acf(t, x, np.array([0.0, 5.0]), "r", 1000.0)
+        assert st == O.E_DEGENERATE and np.all(np.isnan(c))
+        s = np.sort(rng.uniform(0.0, 100.0, 50))
+        y = rng.normal(size=50)
+        st, c, _, _ = O.ccf(t, x, s, y, np.array([0.0]), "r", 1000.0)
+        assert st == O.E_DEGENERATE
+        st, c, _, _ = O.ccf(s, y, t, x, np.array([0.0]), "r", 1000.0)
+        assert st == O.E_DEGENERATE
+    # a window of the same series' nearest pairs only is not degenerate
+    t = np.arange(float(n))
+    x = rng.normal(size=n)
+    assert O.acf(t, x, np.array([0.0]), "r", 0.5)[0] == 0
