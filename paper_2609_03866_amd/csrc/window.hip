@@ -170,7 +170,6 @@ __device__ __forceinline__ void scan_lane(Acc& acc, const V& v, int ja, int jb, 
         } else {
             hi = advance<false>(v, hi, hk);
             double bj = 0.0, Cj = 0.0, Bj = 0.0;
-            float bf = 0.0f;
             // window points per round (reads past the window land on staged
             // samples or the sentinels); measured: one for the FP32
             // exponential, four for the FP64 one
@@ -194,14 +193,15 @@ __device__ __forceinline__ void scan_lane(Acc& acc, const V& v, int ja, int jb, 
                             const float e =
                                 __builtin_amdgcn_ldexpf(__builtin_amdgcn_exp2f((float)(a - n)),
                                                         (int)n);
-                            bf += e;
+                            bj += (double)e;  // FP64 sum: windows of bursty
+                                              // samples hold thousands of points
                             if (NUMER) Cj += (double)e * v.A1(i + m);
                             if (WTD) Bj += (double)e * v.A2(i + m);
                         }
                     }
                 }
             }
-            acc.b += E64 ? bj : (double)bf;
+            acc.b += bj;
             acc.n += hi - lo;
             if (NUMER) acc.C += Cj * v.VO(j);
             if (WTD) acc.B += Bj * v.WO(j);
