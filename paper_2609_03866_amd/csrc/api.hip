@@ -1663,8 +1663,9 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     if (flag_pass) {
         // flags computed on the device from the spectral b values (contiguous
         // over the problems); only the bit masks come back
-        NCF_TRY(launch_fallback_flags(dT.st, bspec[0], nts, Keval, (int)K, J.ccf, dT.rowk, Krow,
-                                      beta, dT.mask, J.st));
+        // a plan's fallback lags must not depend on the placeholder values
+        NCF_TRY(launch_fallback_flags(dT.st, bspec[0], nts, Keval, (int)K, J.ccf, !J.rec,
+                                      dT.rowk, Krow, beta, dT.mask, J.st));
         if (!combine)
             NCF_TRY_HIP(hipMemcpyAsync(hT.mask, dT.mask, sizeof(uint64_t) * (size_t)nts * fwords,
                                        hipMemcpyDeviceToHost, J.st));

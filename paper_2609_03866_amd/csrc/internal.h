@@ -334,10 +334,12 @@ int launch_spread(const SpecTask* d_tasks, const int64_t* d_tile0, int ntasks, i
 // sqrt(B_xx(0) B_yy(0)) from the tasks' product partials for the CCF): bspec
 // holds the problems' Keval evaluations contiguously (problem i is task i),
 // rowk the evaluation index of each of the Krow window rows (-1: none); mask
-// gets ceil(Krow / 64) words per problem.
+// gets ceil(Krow / 64) words per problem. use_scale: compare b times
+// min(1, lag-0 scale) (one-shot calls); plans, whose fallback lags are fixed
+// on placeholder values, pass false.
 int launch_fallback_flags(const SpecTask* d_tasks, const double* bspec, int64_t nprob,
-                          int Keval, int K, bool ccf, const int32_t* rowk, int Krow, double beta,
-                          uint64_t* mask, hipStream_t st);
+                          int Keval, int K, bool ccf, bool use_scale, const int32_t* rowk,
+                          int Krow, double beta, uint64_t* mask, hipStream_t st);
 int launch_interp(const SpecTask* d_tasks, int ntasks, const int64_t* d_k0, int64_t total_k,
                   bool fp64, hipStream_t st);
 

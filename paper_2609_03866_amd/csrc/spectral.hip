@@ -936,13 +936,15 @@ k_mid(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pair0, int
 // series and the lag-0 sums cancel; then the rounding error, which does not
 // cancel, is amplified by 1 / s. A row is therefore compared as
 // b min(1, s) against beta times the reference (s not positive or NaN: the
-// output is NaN with a status, and the factor is taken as 1).
+// output is NaN with a status, and the factor is taken as 1). Plans fix
+// their fallback lags when built, on placeholder values, so they must not
+// depend on values: with use_scale = 0 the factor is 1.
 constexpr int kFlagThreads = 256;
 
 __global__ void __launch_bounds__(kFlagThreads)
 k_fallback_flags(const SpecTask* __restrict__ tasks, const double* __restrict__ bspec, int Keval,
-                 int K, int ccf, const int32_t* __restrict__ rowk, int Krow, double beta,
-                 int words, uint64_t* __restrict__ mask) {
+                 int K, int ccf, int use_scale, const int32_t* __restrict__ rowk, int Krow,
+                 double beta, int words, uint64_t* __restrict__ mask) {
     const int chunks = (Krow + kFlagThreads - 1) / kFlagThreads;
     const int64_t i = (int64_t)blockIdx.x / chunks;
     const int g = (int)((int64_t)blockIdx.x % chunks);
@@ -976,7 +978,7 @@ k_fallback_flags(const SpecTask* __restrict__ tasks, const double* __restrict__ 
         bref = bb[K];
         scale = gbl(tasks[i].numer)[K] / bref;
     }
-    const double gs = scale > 0.0 ? fmin(1.0, scale) : 1.0;
+    const double gs = (use_scale && scale > 0.0) ? fmin(1.0, scale) : 1.0;
     {
         const int r = g * kFlagThreads + (int)threadIdx.x;
         bool f = false;
@@ -1084,8 +1086,8 @@ int launch_product(const SpecTask* d_tasks, const int64_t* d_pos0, int ntasks, i
 }
 
 int launch_fallback_flags(const SpecTask* d_tasks, const double* bspec, int64_t nprob,
-                          int Keval, int K, bool ccf, const int32_t* rowk, int Krow, double beta,
-                          uint64_t* mask, hipStream_t st) {
+                          int Keval, int K, bool ccf, bool use_scale, const int32_t* rowk,
+                          int Krow, double beta, uint64_t* mask, hipStream_t st) {
     if (nprob <= 0 || Krow <= 0) return NCF_OK;
     const int64_t blocks = nprob * ceil_div(Krow, kFlagThreads);
     if (blocks > INT32_MAX) {
@@ -1094,8 +1096,8 @@ int launch_fallback_flags(const SpecTask* d_tasks, const double* bspec, int64_t 
     }
     ProfScope p(st, "fallback_flags", 0.0, "bytes");
     hipLaunchKernelGGL(k_fallback_flags, dim3((unsigned)blocks), dim3(kFlagThreads), 0, st,
-                       d_tasks, bspec, Keval, K, ccf ? 1 : 0, rowk, Krow, beta,
-                       (int)ceil_div(Krow, 64), mask);
+                       d_tasks, bspec, Keval, K, ccf ? 1 : 0, use_scale ? 1 : 0, rowk, Krow,
+                       beta, (int)ceil_div(Krow, 64), mask);
     NCF_CHECK_LAUNCH();
     return NCF_OK;
 }

@@ -229,9 +229,8 @@ def test_random_single_call(seed):
     _compare(what, kernel, prec, method, spec_always, got, want, sides)
 
 
-@pytest.mark.parametrize("seed", range(10))
-def test_random_batch(seed):
-    rng = synth.rng_for(7100 + seed)
+def _batch_case(seed):
+    rng = synth.rng_for(seed)
     is_ccf = bool(rng.integers(0, 2))
     kernel = ("gaussian", "rectangle")[int(rng.integers(0, 2))]
     pattern = PATTERNS[int(rng.integers(0, len(PATTERNS)))]
@@ -244,37 +243,85 @@ def test_random_batch(seed):
     nx = np.array([a[0].size for a in sx])
     h = span / nx * np.exp(rng.uniform(np.log(0.2), np.log(20.0), nser))
     offx = np.concatenate([[0], np.cumsum(nx)]).astype(np.int64)
-    t = np.concatenate([a[0] for a in sx])
-    x = np.concatenate([a[1] for a in sx])
-    what = (f"seed {seed}: {'ccf' if is_ccf else 'acf'} batch of {nser} {kernel} {prec} "
-            f"{method} spectral_always={spec_always} {pattern} K={lags.size} lengths={nx.tolist()}")
-    print(what, flush=True)
+    d = dict(rng=rng, is_ccf=is_ccf, kernel=kernel, pattern=pattern, nser=nser, lags=lags,
+             prec=prec, method=method, spec_always=spec_always, sx=sx, sy=sy, h=h, offx=offx,
+             t=np.concatenate([a[0] for a in sx]), x=np.concatenate([a[1] for a in sx]))
     if is_ccf:
         ny = np.array([a[0].size for a in sy])
-        offy = np.concatenate([[0], np.cumsum(ny)]).astype(np.int64)
-        s = np.concatenate([a[0] for a in sy])
-        y = np.concatenate([a[1] for a in sy])
-        c, b, cnt, st, rc = ncf.ccf_batch(offx, t, x, offy, s, y, lags, kernel, h,
-                                          precision=prec, method=method,
-                                          spectral_always=spec_always, raise_on_error=False)
-    else:
-        c, b, cnt, st, rc = ncf.acf_batch(offx, t, x, lags, kernel, h, precision=prec,
-                                          method=method, spectral_always=spec_always,
-                                          raise_on_error=False)
+        d["offy"] = np.concatenate([[0], np.cumsum(ny)]).astype(np.int64)
+        d["s"] = np.concatenate([a[0] for a in sy])
+        d["y"] = np.concatenate([a[1] for a in sy])
+    d["what"] = (f"{'ccf' if is_ccf else 'acf'} batch of {nser} {kernel} {prec} {method} "
+                 f"spectral_always={spec_always} {pattern} K={lags.size} "
+                 f"lengths={nx.tolist()}")
+    return d
+
+
+def _compare_batch(what, d, out, sx, sy):
+    """out = (c, b, count, status, rc) of a batch call or plan execution whose
+    values are those of sx (and sy)."""
+    c, b, cnt, st, rc = out
     st = np.asarray(st)
     # the call's code is the first failing series' status
     bad = np.flatnonzero(st != 0)
     assert rc == (st[bad[0]] if bad.size else 0), what
-    for i in range(nser):
-        if is_ccf:
+    kernel, lags, h = d["kernel"], d["lags"], d["h"]
+    for i in range(d["nser"]):
+        if d["is_ccf"]:
             ost, oc, ob, on = O.ccf(sx[i][0], sx[i][1], sy[i][0], sy[i][1], lags, kernel, h[i])
         else:
             ost, oc, ob, on = O.acf(sx[i][0], sx[i][1], lags, kernel, h[i])
         sides = [(sx[i][0], sx[i][1], None, h[i])]
-        if is_ccf:
+        if d["is_ccf"]:
             sides.append((sy[i][0], sy[i][1], None, h[i]))
-        _compare(f"{what} [series {i}]", kernel, prec, method, spec_always,
+        _compare(f"{what} [series {i}]", kernel, d["prec"], d["method"], d["spec_always"],
                  (c[i], b[i], cnt[i], st[i]), (ost, oc, ob, on), sides)
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_random_batch(seed):
+    d = _batch_case(7100 + seed)
+    what = f"seed {seed}: {d['what']}"
+    print(what, flush=True)
+    kw = dict(precision=d["prec"], method=d["method"], spectral_always=d["spec_always"],
+              raise_on_error=False)
+    if d["is_ccf"]:
+        out = ncf.ccf_batch(d["offx"], d["t"], d["x"], d["offy"], d["s"], d["y"], d["lags"],
+                            d["kernel"], d["h"], **kw)
+    else:
+        out = ncf.acf_batch(d["offx"], d["t"], d["x"], d["lags"], d["kernel"], d["h"], **kw)
+    _compare_batch(what, d, out, d["sx"], d["sy"])
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_random_plan(seed):
+    # a plan fixes the times (and the fallback lags); it is executed on the
+    # case's values and then on fresh values of the same lengths
+    d = _batch_case(7200 + seed)
+    graph = bool(d["rng"].integers(0, 2))
+    what = f"seed {seed}: plan (graph={graph}) of {d['what']}"
+    print(what, flush=True)
+    kw = dict(precision=d["prec"], method=d["method"], spectral_always=d["spec_always"],
+              graph=graph)
+    if d["is_ccf"]:
+        plan = ncf.plan_ccf(d["offx"], d["t"], d["offy"], d["s"], d["lags"], d["kernel"],
+                            d["h"], **kw)
+    else:
+        plan = ncf.plan_acf(d["offx"], d["t"], d["lags"], d["kernel"], d["h"], **kw)
+    try:
+        sx, sy = d["sx"], d["sy"]
+        for rep in range(2):
+            x = np.concatenate([a[1] for a in sx])
+            y = np.concatenate([a[1] for a in sy]) if d["is_ccf"] else None
+            out = plan.execute(x, y, raise_on_error=False)
+            _compare_batch(f"{what} [execution {rep}]", d, out, sx, sy)
+            rng = d["rng"]
+            sx = [(a[0], rng.normal(size=a[0].size).cumsum() * 0.1 + rng.normal(size=a[0].size))
+                  for a in sx]
+            if d["is_ccf"]:
+                sy = [(a[0], rng.normal(size=a[0].size)) for a in sy]
+    finally:
+        plan.close()
 
 
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
