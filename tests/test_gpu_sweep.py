@@ -324,6 +324,79 @@ def test_random_plan(seed):
         plan.close()
 
 
+def _regular_case(seed):
+    rng = synth.rng_for(seed)
+    is_ccf = bool(rng.integers(0, 2))
+    kernel = ("gaussian", "rectangle")[int(rng.integers(0, 2))]
+    dt = (1.0, 0.5, 0.1, 0.25, 1.0 / 3.0, 0.01)[int(rng.integers(0, 6))]
+    keep = rng.uniform(0.05, 1.0)
+    dup = (0.0, 0.05, 0.2)[int(rng.integers(0, 3))]
+    t0 = rng.uniform(-100.0, 100.0)
+    nser = int(rng.integers(1, 9))
+    series = []
+    for _ in range(nser * (2 if is_ccf else 1)):
+        n = _length(rng)
+        t = synth.lattice_times(rng, n, dt=dt, keep=keep, t0=t0, dup_frac=dup)
+        t = t + int(rng.integers(0, 50)) * dt  # both series of a pair on one lattice
+        series.append((t, rng.normal(size=n).cumsum() * 0.1 + rng.normal(size=n)))
+    sx = series[:nser]
+    sy = series[nser:] if is_ccf else None
+    span = max(max(a[0][-1] - a[0][0] for a in series), dt)
+    lags = _lags(rng, span)
+    h = dt * np.exp(rng.uniform(np.log(0.3), np.log(20.0), nser))
+    return is_ccf, kernel, dt, keep, dup, sx, sy, lags, h
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_random_regular(seed):
+    # lattice family (classic FFT in FP64): c within 1e-9, counts exact,
+    # Gaussian b within 1e-10 relative (or the summation bound), plus the
+    # near-degenerate scale term; single calls for one series, batches
+    # otherwise
+    is_ccf, kernel, dt, keep, dup, sx, sy, lags, h = _regular_case(7300 + seed)
+    nser = len(sx)
+    what = (f"seed {seed}: regular {'ccf' if is_ccf else 'acf'} x{nser} {kernel} dt={dt:.4g} "
+            f"keep={keep:.2f} dup={dup} K={lags.size} lengths={[a[0].size for a in sx]}")
+    print(what, flush=True)
+    if nser == 1:
+        if is_ccf:
+            c, b, cnt, rc = ncf.ccf_regular(sx[0][0], sx[0][1], sy[0][0], sy[0][1], lags, dt,
+                                            kernel, h[0], raise_on_error=False)
+        else:
+            c, b, cnt, rc = ncf.acf_regular(sx[0][0], sx[0][1], lags, dt, kernel, h[0],
+                                            raise_on_error=False)
+        c, b, cnt, st = [c], [b], [cnt], [rc]
+    else:
+        offx = np.concatenate([[0], np.cumsum([a[0].size for a in sx])]).astype(np.int64)
+        t = np.concatenate([a[0] for a in sx])
+        x = np.concatenate([a[1] for a in sx])
+        if is_ccf:
+            offy = np.concatenate([[0], np.cumsum([a[0].size for a in sy])]).astype(np.int64)
+            c, b, cnt, st, rc = ncf.ccf_regular_batch(
+                offx, t, x, offy, np.concatenate([a[0] for a in sy]),
+                np.concatenate([a[1] for a in sy]), lags, dt, kernel, h, raise_on_error=False)
+        else:
+            c, b, cnt, st, rc = ncf.acf_regular_batch(offx, t, x, lags, dt, kernel, h,
+                                                      raise_on_error=False)
+    for i in range(nser):
+        if is_ccf:
+            ost, oc, ob, on = O.ccf_regular(sx[i][0], sx[i][1], sy[i][0], sy[i][1], lags, dt,
+                                            kernel, h[i])
+            sides = [sx[i], sy[i]]
+        else:
+            ost, oc, ob, on = O.acf_regular(sx[i][0], sx[i][1], lags, dt, kernel, h[i])
+            sides = [sx[i]]
+        w = f"{what} [series {i}]"
+        assert st[i] == ost, f"{w}: status {st[i]}, oracle {ost}"
+        if ost != 0:
+            continue
+        lag0 = [_lag0_r(tt, xx, h[i], kernel) for (tt, xx) in sides]
+        g = min(1.0, min(r for r, _ in lag0))
+        nsum = max(int(np.max(on)) if on.size else 0, max(n for _, n in lag0))
+        ctol = 1e-9 + 1e-15 * (1.0 + np.abs(oc)) / g
+        _check(w, c[i], b[i], cnt[i], oc, ob, on, kernel, ctol, max(1e-10, 4e-16 * nsum))
+
+
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
 @pytest.mark.parametrize("method", ["auto", "direct"])
 def test_window_holding_every_pair_is_degenerate(prec, method):
