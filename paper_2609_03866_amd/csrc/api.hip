@@ -792,9 +792,13 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             }
             S.v32 = v32_needed ? ar.take<float>(S.ntot) : nullptr;
             S.v64 = v64_needed ? ar.take<double>(S.ntot) : nullptr;
-            S.w64 = ein[si] ? ar.take<double>(S.ntot) : nullptr;
+            // weights (and their prefix sums) for every set of a weighted
+            // call: a set without errors gets unit weights, since the pair
+            // weight w_i w_j of a CCF with errors on one side only needs
+            // both (the window passes read both arrays)
+            S.w64 = weighted ? ar.take<double>(S.ntot) : nullptr;
             S.pv = need_prefix ? ar.take<double>(S.ntot + S.nser) : nullptr;
-            S.pw = (need_prefix && ein[si]) ? ar.take<double>(S.ntot + S.nser) : nullptr;
+            S.pw = (need_prefix && weighted) ? ar.take<double>(S.ntot + S.nser) : nullptr;
         }
         *d_cpart = ar.take<double>(4 * (size_t)nch);
         *d_ctot = ar.take<double>(2 * (size_t)nch);
@@ -1150,6 +1154,22 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         W.item0[ntw] = W.nitems;
         W.wk0[ntw] = W.total_rows;
         W.r0[ntw] = W.nred1;
+    };
+
+    // every array that a window pass reads must exist: checked on the host
+    // before the launch, since a missing one would be read on the device
+    auto check_win = [&](const WinLaunch& W, uint32_t f) -> int {
+        const bool numer = (f & WIN_NUMER) != 0, wtd = (f & WIN_WEIGHTED) != 0;
+        for (const WinTask& T : W.wt) {
+            bool ok = T.t != nullptr && T.s != nullptr;
+            if (numer) ok = ok && (rect ? T.pv != nullptr : T.v != nullptr) && T.vo != nullptr;
+            if (wtd) ok = ok && (rect ? T.pw != nullptr : T.w != nullptr) && T.wo != nullptr;
+            if (!ok) {
+                set_error("window pass: a task lacks one of its input arrays");
+                return NCF_E_INVALID_ARG;
+            }
+        }
+        return NCF_OK;
     };
 
     WinLaunch W1;
@@ -1592,6 +1612,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         const double work = W1.work;
         unsigned long long* q = qbase;
         if (ntw > 0) {
+            NCF_TRY(check_win(W1, wflags));
             NCF_TRY(emit(J, [=](hipStream_t s) {
                 return launch_window(wt, it0, ntw, nitems, wflags, cap, jmax, q, s, work);
             }));
@@ -1698,6 +1719,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             const int cap = W2.cap, jmax = W2.jmax;
             const double work = W2.work;
             unsigned long long* q = qbase ? qbase + 2 : nullptr;
+            NCF_TRY(check_win(W2, wflags2));
             NCF_TRY(emit(J, [=](hipStream_t s) {
                 return launch_window(wt, it0, ntw2, nitems, wflags2, cap, jmax, q, s, work);
             }));

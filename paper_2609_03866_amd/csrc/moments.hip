@@ -225,6 +225,12 @@ k_standardize(MomentsArgs a) {
     const bool ok = st.status == NCF_OK;
     const double mean = st.mean;
     const double inv_sd = ok ? 1.0 / st.sd : 0.0;
+    // weights scaled to mean 1 over the series: the estimator is invariant
+    // (C, B and the series' lag-0 sums scale together), and the spectral
+    // route packs two series' grids into one FP32 transform, whose rounding
+    // is relative to the larger of the two (weights of 1/err^2 with err =
+    // 0.05 against unit weights: 400 times the error on the smaller one)
+    const double wscale = (sd.err && ok && st.sw > 0.0) ? (double)sd.n / st.sw : 1.0;
     double v[kPer], w[kPer];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
@@ -235,7 +241,7 @@ k_standardize(MomentsArgs a) {
             double wk = 1.0;
             if (sd.err) {
                 const double e = er[i];
-                wk = sd.wmode ? e : 1.0 / (e * e);
+                wk = (sd.wmode ? e : 1.0 / (e * e)) * wscale;
             }
             w[k] = wk;
             v[k] = X[i];

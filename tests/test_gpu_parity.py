@@ -357,3 +357,28 @@ def test_c3_full_size_sampled_lags():
     pick = np.array([0, 1, 2, 7, 31, 365, 1000, 2047, 4095])
     oc, ob, on = _orc_acf(d, lags=d["lags"][pick])
     _check(c[pick], b[pick], n[pick], oc, ob, on, "gaussian", 1e-5, 1e-6)
+
+
+@pytest.mark.parametrize("side", ["x", "y"])
+@pytest.mark.parametrize("kernel,prec,method,ctol,btol", [
+    ("rectangle", "mixed", "auto", 1e-9, 0),
+    ("rectangle", "fp64", "direct", 1e-9, 0),
+    ("gaussian", "mixed", "direct", 1e-5, 1e-6),
+    ("gaussian", "fp64", "direct", 1e-11, 1e-12),
+    ("gaussian", "mixed", "auto", 1e-5, ("ref", 1e-5)),
+])
+def test_ccf_weights_on_one_side(side, kernel, prec, method, ctol, btol):
+    # errors on one series only: the other takes unit weights in the pair
+    # weight w_i w_j, on every route (the window passes read both series'
+    # weights and weight prefix sums)
+    d = synth.small("c2", seed=8)
+    rng = synth.rng_for(9)
+    ex = rng.uniform(0.5, 2.0, d["t"].size) if side == "x" else None
+    ey = rng.uniform(0.5, 2.0, d["s"].size) if side == "y" else None
+    h = d["h"] if kernel == "gaussian" else 0.5
+    st, oc, ob, on = O.ccf(d["t"], d["x"], d["s"], d["y"], d["lags"], kernel, h, ex=ex, ey=ey)
+    assert st == 0
+    c, b, n, s = ncf.ccf(d["t"], d["x"], d["s"], d["y"], d["lags"], kernel, h, ex=ex, ey=ey,
+                         precision=prec, method=method)
+    assert s == 0
+    _check(c, b, n, oc, ob, on, kernel, ctol, btol)

@@ -122,3 +122,21 @@ def test_resample_device_pointers():
     torch.cuda.synchronize()
     assert rc == 0
     _cmp(crep.cpu().numpy(), cm.cpu().numpy(), cs.cpu().numpy(), *o, st, 1e-5)
+
+
+@pytest.mark.parametrize("kernel", ["rectangle", "gaussian"])
+@pytest.mark.parametrize("prec,method,tol", MODES)
+def test_ccf_resample_errors_on_one_side(kernel, prec, method, tol):
+    # flux randomization of both series, weights from errors on series 2
+    # only: series 1 takes unit weights in the pair weight (the window passes
+    # read both series' weights)
+    d = synth.small("m1", seed=3)
+    args = dict(ex=None, ey=d["ey"], sx=d["ex"], sy=d["ey"], zx=d["zx"], zy=d["zy"])
+    h = d["h"] if kernel == "gaussian" else 0.5
+    o_st, o_crep, o_cm, o_cs = O.ccf_resample(d["t"], d["x"], d["s"], d["y"], d["lags"], kernel,
+                                              h, **args)
+    cm, cs, crep, st, rc = ncf.ccf_resample(d["t"], d["x"], d["s"], d["y"], d["lags"], kernel,
+                                            h, with_reps=True, precision=prec, method=method,
+                                            **args)
+    assert rc == 0
+    _cmp(crep, cm, cs, o_st, o_crep, o_cm, o_cs, st, 1e-9 if kernel == "rectangle" else tol)
