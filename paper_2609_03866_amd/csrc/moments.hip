@@ -225,12 +225,18 @@ k_standardize(MomentsArgs a) {
     const bool ok = st.status == NCF_OK;
     const double mean = st.mean;
     const double inv_sd = ok ? 1.0 / st.sd : 0.0;
-    // weights scaled to mean 1 over the series: the estimator is invariant
-    // (C, B and the series' lag-0 sums scale together), and the spectral
-    // route packs two series' grids into one FP32 transform, whose rounding
-    // is relative to the larger of the two (weights of 1/err^2 with err =
-    // 0.05 against unit weights: 400 times the error on the smaller one)
-    const double wscale = (sd.err && ok && st.sw > 0.0) ? (double)sd.n / st.sw : 1.0;
+    // weights scaled to a mean within a factor 2 of 1 over the series: the
+    // estimator is invariant (C, B and the series' lag-0 sums scale
+    // together), and the spectral route packs two series' grids into one
+    // FP32 transform, whose rounding is relative to the larger of the two
+    // (weights of 1/err^2 with err = 0.05 against unit weights: 400 times
+    // the error on the smaller one). The scale is a power of two, so
+    // integer weights (bootstrap multiplicities) stay exact and so do the
+    // sums of their prefix arrays: a window of samples of weight 0 has a
+    // weighted pair sum of exactly 0
+    const double wscale = (sd.err && ok && st.sw > 0.0)
+                              ? ldexp(1.0, (int)lrint(log2((double)sd.n / st.sw)))
+                              : 1.0;
     double v[kPer], w[kPer];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {

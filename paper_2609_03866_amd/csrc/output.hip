@@ -129,7 +129,9 @@ k_normalize(const NormTask* __restrict__ tasks, const IoBlock* __restrict__ io) 
         int64_t cnt = 0;
         if (fb >= 0) {
             const double* w = T.fb_sums + 4 * (int64_t)fb;
-            const bool empty = __double_as_longlong(w[3]) == 0;
+            // empty: no pair, or (weights) a weighted pair sum of exactly 0,
+            // a window of samples of weight 0 only (dropped bootstrap samples)
+            const bool empty = __double_as_longlong(w[3]) == 0 || (T.weighted && w[bq] == 0.0);
             num = empty ? 0.0 : w[0];
             den = w[bq];
             bout = w[2];
@@ -142,7 +144,7 @@ k_normalize(const NormTask* __restrict__ tasks, const IoBlock* __restrict__ io) 
             // an empty window has numerator exactly 0; a window with few
             // pairs takes the direct numerator (the spectral value there is
             // rounding noise that a small denominator would amplify)
-            const bool empty = __double_as_longlong(w[3]) == 0;
+            const bool empty = __double_as_longlong(w[3]) == 0 || (T.weighted && w[bq] == 0.0);
             const bool direct = !T.spectral || (sel_window && w[bq] < T.beta * sh_bref);
             num = empty ? 0.0 : (direct ? w[0] : T.numer[k]);
             den = w[bq];

@@ -467,11 +467,13 @@ def test_random_resample(seed):
         else:
             ctol = max(1e-11, 4e-16 * n0) + 1e-15 * (1.0 + oc) / g
         dc = np.abs(crep[r] - orep[r])
-        if kernel == "rectangle" and scheme != "flux":
-            # known defect: a rectangle window that holds only samples with
-            # multiplicity 0 in this replicate is empty in the oracle (c = 0)
-            # but its weighted sums on the GPU are prefix-sum rounding
-            # residue, so c there is noise; those lags are left out
+        if kernel == "rectangle" and scheme == "both":
+            # known defect: with multiplicities times error weights, a
+            # rectangle window that holds only samples of multiplicity 0 is
+            # empty in the oracle (c = 0) but its weighted sums on the GPU
+            # are prefix-sum rounding residue, so c there is noise; those
+            # lags are left out (integer multiplicities alone give exact
+            # prefix sums and an exact 0)
             if is_ccf:
                 on = O.ccf(*reps[0][:2], *reps[1][:2], lags, kernel, h)[3]
             else:
