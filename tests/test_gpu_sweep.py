@@ -212,8 +212,10 @@ def test_random_single_call(seed):
     if is_ccf:
         m = _length(rng)
         s, y = _series(rng, m, span, pattern)
-        ex = rng.uniform(0.5, 2.0, n) if weighted else None
-        ey = rng.uniform(0.5, 2.0, m) if weighted else None
+        # errors on both series, or on one only (the other takes unit weights)
+        side = ("both", "x", "y")[int(rng.integers(0, 3))] if weighted else None
+        ex = rng.uniform(0.5, 2.0, n) if side in ("both", "x") else None
+        ey = rng.uniform(0.5, 2.0, m) if side in ("both", "y") else None
         want = O.ccf(t, x, s, y, lags, kernel, h, ex=ex, ey=ey)
         got = ncf.ccf(t, x, s, y, lags, kernel, h, ex=ex, ey=ey, precision=prec, method=method,
                       spectral_always=spec_always, raise_on_error=False)
