@@ -1,15 +1,18 @@
 """Benchmark of the kernel-weighted correlation hot path on one MI355X.
 
-Default workload (``--workload c2``): the CCF of two irregular series of
-1e5 samples each with 401 lags over [-200, 200] d, Gaussian and rectangle
-kernels, mixed precision (FP32 spreading / FFT / kernel weights with FP64
-positions, phases, moments, prefix sums and accumulators). One step is one
-Gaussian CCF plus one rectangle CCF through the C ABI with the inputs
-resident in HBM. The metric is n*K lag-pairs per second with n = nx + ny
-per CCF (the paper's O((n1 + n2) K) unit of work).
+Default workload (``--workload c45``): the two batched workloads in one
+step, mixed precision (FP32 spreading / FFT / kernel weights with FP64
+positions, phases, moments, prefix sums and accumulators):
+  * the ACF of 10,000 light curves (lengths log-uniform in [100, 5e4],
+    seasonal sampling), 256 lags, Gaussian kernel, one batch call;
+  * the CCF of 2,048 series pairs (lengths log-uniform in [1e3, 2e5]),
+    512 lags over [-300, 300] d, rectangle kernel with exact pair counts,
+    one batch call.
+Inputs are resident in HBM. The metric is n*K lag-pairs per second (n = nx +
+ny per CCF: the paper's O((n1 + n2) K) unit of work) and series (pairs)
+completed per second.
 
-Other workloads (``--workload c1|c3|c4|c5``) are reported the same way and
-add series/s for the batched ones. ``r1`` and ``r2`` are regular-lattice
+Other workloads (``--workload c1|c2|c3|c4|c5``) are reported the same way. ``r1`` and ``r2`` are regular-lattice
 ACFs (the paper's regular-data benchmark: white noise on a 1-d lattice,
 366 integer lags) through the classic-FFT route in FP64, with the general
 NUFFT route (``nufft_gpu_path``) and the FP64 direct window sums timed on the
@@ -63,6 +66,8 @@ def make_workload(name):
         return [synth.c4(with_err=True)]
     if name == "c5":
         return [synth.c5()]
+    if name == "c45":
+        return [synth.c4(), synth.c5()]
     if name == "r1":
         return [synth.r1(kernel="gaussian"), synth.r1(kernel="rectangle")]
     if name == "r2":
@@ -232,6 +237,19 @@ def oracle_subset(d, max_series):
     return cs, ns, work, time.perf_counter() - t0, pick
 
 
+def sample_of(d, pick, max_series):
+    """What the oracle ran of one workload part."""
+    if d["kind"] in ("acf", "ccf"):
+        npick = pick.size
+        return (f"{d['name']}: whole problem" if npick == d["lags"].size else
+                f"{d['name']}: all samples, {npick} of {d['lags'].size} lags (evenly spaced)")
+    if d["kind"] == "ccf_resample":
+        return f"{d['name']}: first {min(max_series, d['R'])} replicates"
+    if d["kind"] == "acf_batch":
+        return f"{d['name']}: first {min(max_series, d['offs'].size - 1)} series of the batch"
+    return f"{d['name']}: first {min(max_series, d['offx'].size - 1)} pairs of the batch"
+
+
 def _host(a):
     return np.asarray(a.cpu() if hasattr(a, "cpu") else a)
 
@@ -285,7 +303,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c45")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU path")
     ap.add_argument("--no-plan", action="store_true", help="skip the plan replay timing")
@@ -384,6 +402,25 @@ def main():
         dt64 = (time.perf_counter() - t1) / n64
         fp64 = {"value": work / dt64, "ms_per_step": dt64 * 1e3, "path": "fp64 direct window sums"}
         log(f"[bench] fp64 direct: {dt64 * 1e3:.3f} ms/step")
+
+    # all-FP64 spectral path (complex128 grids and transforms, FP64 weights)
+    # on the same step: Gaussian workloads only (the rectangle numerator is
+    # the same FP64 window scan in every precision)
+    n64 = None
+    has_gauss = any(d["kernel"] == "gaussian" and d.get("dt") is None for d in host)
+    if not args.no_fp64 and has_gauss:
+        step("fp64", "auto")
+        torch.cuda.synchronize()
+        nn = max(2, args.steps // 4)
+        t1 = time.perf_counter()
+        for _ in range(nn):
+            resn64 = step("fp64", "auto")
+        torch.cuda.synchronize()
+        dtn64 = (time.perf_counter() - t1) / nn
+        n64 = {"value": work / dtn64, "ms_per_step": dtn64 * 1e3,
+               "path": "fp64 spectral (complex128 NUFFT numerator and pair counts, FP64 "
+                       "direct fallback lags)"}
+        log(f"[bench] fp64 spectral: {dtn64 * 1e3:.3f} ms/step")
 
     # regular-lattice workloads: the general (NUFFT, mixed precision) route on
     # the same data, the comparison of the paper's regular-data benchmark
@@ -493,15 +530,10 @@ def main():
             if fp64 is not None:
                 r64 = res64[i][2] if d["kind"] == "ccf_resample" else res64[i][0]
                 acc[key]["max_abs_dc_fp64_direct"] = max_dc(r64, cs, pick)
-        d0 = host[0]
-        if d0["kind"] in ("acf", "ccf"):
-            npick = picks[0].size
-            sample = ("whole workload" if npick == d0["lags"].size else
-                      f"all samples, {npick} of {d0['lags'].size} lags (evenly spaced)")
-        elif d0["kind"] == "ccf_resample":
-            sample = f"first {min(args.oracle_series, d0['R'])} replicates"
-        else:
-            sample = f"first {args.oracle_series} series of the batch"
+            if n64 is not None and d["kernel"] == "gaussian":
+                acc[key]["max_abs_dc_fp64_spectral"] = max_dc(resn64[i][0], cs, pick)
+            acc[key]["oracle_sample"] = sample_of(d, pick, args.oracle_series)
+        sample = "; ".join(sample_of(d, p, args.oracle_series) for d, p in zip(host, picks))
         cpu = {"value": orc_work / orc_time, "unit": "lag-pairs/s", "cores": cores,
                "kind": "oracle", "sample": sample, "seconds": orc_time,
                "runs": min(rates), "statistic": "median run"}
@@ -513,6 +545,8 @@ def main():
                         "c4": "acf_batch_10000_curves_K256_gauss_mixed",
                         "c4w": "acf_batch_10000_curves_K256_gauss_mixed_weighted_by_errors",
                         "c5": "ccf_batch_2048_pairs_K512_rect_mixed",
+                        "c45": "acf_batch_10000_curves_K256_gauss_mixed"
+                               "+ccf_batch_2048_pairs_K512_rect_exact_counts",
                         "r1": "acf_regular_n256000_K366_gauss+rect_fp64",
                         "r2": "acf_regular_batch_4096_K366_rect_fp64",
                         "m1": "ccf_resample_R100_n2e4x2_K401_gauss_mixed"}[args.workload],
@@ -533,6 +567,7 @@ def main():
         "config": cfg,
         "series_per_s": nser / dt,
         "fp64_gpu_path": fp64,
+        "fp64_spectral_gpu_path": n64,
         "nufft_gpu_path": nufft,
         "plan_replay": plan_rep,
         "accuracy_vs_oracle": acc,

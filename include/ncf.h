@@ -77,12 +77,16 @@ typedef enum { NCF_GAUSSIAN = 0, NCF_RECTANGLE = 1 } ncf_kernel_t;
  * phases, moments, prefix sums and accumulators. c is divided by the lag-0
  * scale (ACF r(0), CCF sqrt(r_x(0) r_y(0)) of the standardized values), which
  * is of order 1 unless the kernel spans much of a short series and the lag-0
- * sums cancel; the Gaussian kernel's scale then carries a relative error of
- * about 1e-6 / r(0) in this mode: use NCF_FP64 for such near-degenerate series.
+ * sums cancel; the FP32 weights and transforms leave a relative error of
+ * about 1e-6 / r(0) on it. So a Gaussian problem whose smaller lag-0 scale
+ * comes out below 0.1 is evaluated again in FP64 within the call (same
+ * method) and reports the FP64 result; see the plans for their handling.
  * NCF_FP64: every step in FP64. */
 typedef enum { NCF_MIXED = 0, NCF_FP64 = 1 } ncf_precision_t;
 
-/* NCF_AUTO: Gaussian numerator by the spectral (Wiener-Khinchin + NUFFT)
+/* Every method: a problem with a series of fewer than 32 samples takes the
+ * direct window sums (NCF_DIRECT), whatever the method and flags ask.
+ * NCF_AUTO: Gaussian numerator by the spectral (Wiener-Khinchin + NUFFT)
  *   route (Sec. 2.6), unless the call is small enough that the direct window
  *   sums cost less (then as NCF_DIRECT; see NCF_SPECTRAL_ALWAYS). The Gaussian
  *   pair count b takes the same route with unit values (with errors: the
@@ -312,7 +316,12 @@ int ncf_ccf_resample(int64_t nx, const double* tx, const double* x, const double
  *  - Executions of one plan are ordered on its stream; a plan must not be
  *    executed from two threads at once. Pair counts and fallback lags are
  *    those of the build, so results can differ from a batch call on the
- *    same inputs at the rounding level of the spectral pair count. */
+ *    same inputs at the rounding level of the spectral pair count.
+ *  - A plan replays fixed launches, so it cannot evaluate a problem again in
+ *    FP64 on its values: in NCF_MIXED with the Gaussian kernel, a problem
+ *    whose smaller lag-0 scale is below 0.1 on the executed values reports
+ *    NCF_E_UNSUPPORTED in `status` (c = NaN); build the plan with NCF_FP64
+ *    for such series. */
 typedef struct ncf_plan_s ncf_plan_t;
 
 /* Build an ACF plan for nser series (arguments as in ncf_acf_batch, without

@@ -281,6 +281,7 @@ struct SeriesSet {
     double* w64 = nullptr;
     double* pv = nullptr;  // ntot + nser entries (n + 1 per series)
     double* pw = nullptr;
+    double* pz = nullptr;  // prefix count of nonzero weights (weighted rectangle)
     int sd0 = 0;           // first descriptor of this set in the moments table
     bool shared_t = false; // every series of the set has the same times (t holds one copy)
     bool wmode = false;    // err holds sample weights (w >= 0) instead of errors
@@ -735,6 +736,97 @@ int run_regular(Job& J, const std::vector<SeriesDesc>& sdesc,
 }
 
 int run_job(Job& J, const double* const* tin, const double* const* xin,
+            const double* const* ein);
+
+// Problems of a finished mixed-precision call whose smallest lag-0 scale is
+// below kPromoteScale are evaluated again in FP64 (same method, one problem
+// per call on the call's stream), and their outputs and statuses replace
+// the mixed ones. They run in a workspace of their own: the call's arenas
+// still hold their inputs (device copies in host-pointer mode, replicate
+// series of the resampling calls).
+int promote_fp64(Job& J, const std::vector<int64_t>& probs, int32_t* h_fstat,
+                 const std::vector<SeriesStat>& stats) {
+    const int nsets = J.ccf ? 2 : 1;
+    const int64_t K = J.K;
+    Resources R2;
+    R2.exact = true;
+    double* dout = nullptr;
+    if (hipMalloc((void**)&dout, sizeof(double) * 2 * (size_t)std::max<int64_t>(K, 1)) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        set_error("workspace allocation for the FP64 re-evaluation failed");
+        return NCF_E_NOMEM;
+    }
+    int rc = NCF_OK;
+    for (int64_t p : probs) {
+        Job P;
+        P.ccf = J.ccf;
+        P.nprob = 1;
+        P.kern = J.kern;
+        P.h.assign(1, J.h[p]);
+        P.lags = J.lags;
+        P.K = K;
+        P.c = dout;
+        P.b = dout + std::max<int64_t>(K, 1);
+        P.count = nullptr;
+        int pst = NCF_OK;
+        P.status = &pst;
+        P.opt = J.opt;
+        P.opt.precision = NCF_FP64;
+        // the direct window sums (the real-space estimator itself) unless
+        // their work (windows x (8 + 8 x samples per window) lane-ops) would
+        // take more than about 10 ms; then the call's method in FP64
+        {
+            const SeriesStat& sw = stats[J.set[0].sd0 + p];
+            const int so = J.ccf ? 1 : 0;
+            const double nw = (double)(J.set[0].offs[p + 1] - J.set[0].offs[p]);
+            const double no = (double)(J.set[so].offs[p + 1] - J.set[so].offs[p]);
+            const double dens = (nw - 1.0) / std::max(sw.tmax - sw.tmin, 1e-300);
+            const double pts = std::min(dens * 12.0 * J.h[p], nw);
+            const double windows = no * (double)(K + 1) + (J.ccf ? nw + no : 0.0);
+            if (windows * (8.0 + 8.0 * pts) <= 2e10) P.opt.method = NCF_DIRECT;
+        }
+        P.opt.flags = (J.opt.flags & (NCF_SPECTRAL_ALWAYS | NCF_WINDOW_QUEUE)) | NCF_DEVICE_POINTERS;
+        P.dev_ptrs = true;
+        P.st = J.st;
+        P.res = &R2;
+        P.no_b = J.no_b;
+        const double* tin[2] = {nullptr, nullptr};
+        const double* xin[2] = {nullptr, nullptr};
+        const double* ein[2] = {nullptr, nullptr};
+        for (int si = 0; si < nsets; ++si) {
+            const SeriesSet& S = J.set[si];
+            const int64_t o = S.offs[p], n = S.offs[p + 1] - o;
+            SeriesSet& Q = P.set[si];
+            Q.ntot = n;
+            Q.nser = 1;
+            Q.offs = {0, n};
+            Q.wmode = S.wmode;
+            tin[si] = S.shared_t ? S.t : S.t + o;
+            xin[si] = S.x + o;
+            ein[si] = S.err ? S.err + o : nullptr;
+        }
+        rc = run_job(P, tin, xin, ein);
+        if (rc != NCF_OK && pst == NCF_OK) break;  // a call failure, not a series status
+        rc = NCF_OK;
+        h_fstat[p] = pst;
+        if (K > 0) {
+            const hipMemcpyKind kind = J.dev_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+            if (hipMemcpyAsync(J.c + p * K, P.c, sizeof(double) * K, kind, J.st) != hipSuccess ||
+                hipMemcpyAsync(J.b + p * K, P.b, sizeof(double) * K, kind, J.st) != hipSuccess) {
+                set_error("copy of the FP64 re-evaluation failed");
+                rc = NCF_E_DEVICE;
+                break;
+            }
+        }
+    }
+    (void)hipStreamSynchronize(J.st);
+    free_resources(R2);
+    (void)hipFree(dout);
+    return rc;
+}
+
+int run_job(Job& J, const double* const* tin, const double* const* xin,
             const double* const* ein) {
     const bool fp64 = J.opt.precision == NCF_FP64;
     bool spectral = use_spectral(J);  // may turn to the window route after phase 1
@@ -742,12 +834,25 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     const int nsets = J.ccf ? 2 : 1;
     bool weighted = false;
     for (int si = 0; si < nsets; ++si) weighted |= (ein[si] != nullptr);
+    // problems with a series shorter than kMinSpectralSamples take the direct
+    // window sums on every route (the spectral route makes no accuracy claim
+    // for them); the lengths are known from the offsets
+    std::vector<char> short_p((size_t)J.nprob, 0);
+    bool any_short = false;
+    for (int64_t p = 0; p < J.nprob; ++p) {
+        for (int si = 0; si < nsets; ++si)
+            if (J.set[si].offs[p + 1] - J.set[si].offs[p] < kMinSpectralSamples) short_p[p] = 1;
+        any_short |= short_p[p] != 0;
+    }
     const bool numer_in_window = !spectral;  // C from the window scan
     const bool need_v32 = spectral && !fp64;
     // FP64 values: FP64 spreading, and every Gaussian window pass (its direct
-    // numerator backs up the spectral one at lags with few pairs)
-    const bool need_v64 = (spectral && fp64) || numer_in_window || !rect;
-    const bool need_prefix = rect && numer_in_window && !J.regular;
+    // numerator backs up the spectral one at lags with few pairs), and the
+    // rectangle window numerator of the direct problems
+    const bool need_v64 = (spectral && fp64) || numer_in_window || !rect || any_short;
+    // prefix sums for the rectangle window pass: values (numerator in the
+    // window), weights and the nonzero-weight count (weighted calls)
+    const bool need_prefix = rect && !J.regular;
     const bool v32_needed = need_v32 && !J.regular;
     const bool v64_needed = need_v64 || J.regular;
 
@@ -799,9 +904,10 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             S.w64 = weighted ? ar.take<double>(S.ntot) : nullptr;
             S.pv = need_prefix ? ar.take<double>(S.ntot + S.nser) : nullptr;
             S.pw = (need_prefix && weighted) ? ar.take<double>(S.ntot + S.nser) : nullptr;
+            S.pz = (need_prefix && weighted) ? ar.take<double>(S.ntot + S.nser) : nullptr;
         }
         *d_cpart = ar.take<double>(4 * (size_t)nch);
-        *d_ctot = ar.take<double>(2 * (size_t)nch);
+        *d_ctot = ar.take<double>(3 * (size_t)nch);
         *d_stats = ar.take<SeriesStat>(nsd);
         // device lags of a one-shot call: copied next to the statistics by
         // the moments launch, so one readback brings both (recorded launches
@@ -847,6 +953,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             d.w64 = S.w64 ? S.w64 + o : nullptr;
             d.pv = S.pv ? S.pv + o + s : nullptr;
             d.pw = S.pw ? S.pw + o + s : nullptr;
+            d.pz = S.pz ? S.pz + o + s : nullptr;
         }
     }
     Staging* stg1 = nullptr;
@@ -978,6 +1085,13 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         }
         if (direct_s < spec_s) spectral = false;
     }
+    // per problem: the direct window sums (no spectral grid)
+    std::vector<char> direct_p((size_t)J.nprob, 0);
+    bool any_direct = false;
+    for (int64_t p = 0; p < J.nprob; ++p) {
+        direct_p[p] = (!spectral || short_p[p]) ? 1 : 0;
+        any_direct |= direct_p[p] != 0;
+    }
     // Gaussian default: numerator and pair count both by the spectral route
     // (unit-weight channel); lags whose spectral b is small against the
     // reference are re-evaluated by the direct window scan.
@@ -1023,8 +1137,8 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     if (fp64 && !rect) wflags |= WIN_EXP64;
     const bool wnumer = (wflags & WIN_NUMER) != 0;
 
-    // the rectangle prefix arrays exist only when the numerator is in the window
-    if (rect && !numer_in_window) wflags &= ~(uint32_t)WIN_NUMER;
+    // the rectangle window numerator is needed only by the direct problems
+    if (rect && !numer_in_window && !any_direct) wflags &= ~(uint32_t)WIN_NUMER;
 
     struct WinPlan {
         int wi_set, wo_set;  // window set, outer set (series index = problem)
@@ -1042,8 +1156,10 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         double work = 0.0;
     };
     auto plan_window = [&](WinLaunch& W) {
+        // staged window arrays: times, values (or their prefix), weights (or
+        // their prefix and, rectangle, the nonzero-weight count prefix)
         const int arrays = 1 + ((W.plans.empty() ? false : ((wflags & WIN_NUMER) != 0)) ? 1 : 0) +
-                           (weighted ? 1 : 0);
+                           (weighted ? (rect ? 2 : 1) : 0);
         const int jmax = 1024;
         const int budget = 40 * 1024 / 8;  // doubles
         int cap = (budget - jmax * arrays) / arrays - 8;
@@ -1076,10 +1192,12 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
                 T.vo = dO.v64;
             }
             if (weighted) {
-                if (rect)
+                if (rect) {
                     T.pw = dw.pw;
-                else
+                    T.pz = dw.pz;
+                } else {
                     T.w = dw.w64;
+                }
                 T.wo = dO.w64;
             }
             T.K = (int32_t)P.dl.size();
@@ -1163,7 +1281,9 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         for (const WinTask& T : W.wt) {
             bool ok = T.t != nullptr && T.s != nullptr;
             if (numer) ok = ok && (rect ? T.pv != nullptr : T.v != nullptr) && T.vo != nullptr;
-            if (wtd) ok = ok && (rect ? T.pw != nullptr : T.w != nullptr) && T.wo != nullptr;
+            if (wtd)
+                ok = ok && (rect ? (T.pw != nullptr && T.pz != nullptr) : T.w != nullptr) &&
+                     T.wo != nullptr;
             if (!ok) {
                 set_error("window pass: a task lacks one of its input arrays");
                 return NCF_E_INVALID_ARG;
@@ -1174,7 +1294,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
 
     WinLaunch W1;
     for (int64_t p = 0; p < J.nprob; ++p) {
-        if (pstat[p] != NCF_OK || spec_b) continue;
+        if (pstat[p] != NCF_OK || (spec_b && !direct_p[p])) continue;
         if (!J.ccf) {
             W1.plans.push_back({0, 0, p, 0, delta});
         } else {
@@ -1196,7 +1316,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     std::vector<SpecPlan> splans;
     if (spectral) {
         for (int64_t p = 0; p < J.nprob; ++p) {
-            if (pstat[p] != NCF_OK) continue;
+            if (pstat[p] != NCF_OK || direct_p[p]) continue;
             double tmin = stat_of(0, p).tmin, tmax = stat_of(0, p).tmax;
             if (J.ccf) {
                 tmin = std::min(tmin, stat_of(1, p).tmin);
@@ -1316,6 +1436,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     const bool combine = speculate && !J.io_fixed;
     struct T3 {
         int32_t* status;  // first: right after the flag masks when merged
+        double* rmin;     // smallest lag-0 scale per problem (comes back with the statuses)
         WinTask* wt;
         int64_t *item0, *wk0, *r0;
         double* dl;
@@ -1326,6 +1447,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     } dU{}, hU{};
     auto take3 = [&](Tables& tb, int ntw2, size_t ndl2, bool any_fb) {
         dU.status = tb.take<int32_t>(J.nprob, &hU.status);
+        dU.rmin = tb.take<double>(J.nprob, &hU.rmin);
         dU.wt = tb.take<WinTask>(ntw2, &hU.wt);
         dU.item0 = tb.take<int64_t>(ntw2 + 1, &hU.item0);
         dU.wk0 = tb.take<int64_t>(ntw2 + 1, &hU.wk0);
@@ -1549,13 +1671,20 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
                 (P.role == 0 ? main_t : P.role == 1 ? selfx : selfy)[P.prob] = i;
             }
             for (int64_t p = 0; p < J.nprob; ++p) {
+                const bool sp = spectral && !direct_p[p];
                 NormTask T{};
                 T.ccf = J.ccf ? 1 : 0;
                 T.K = (int32_t)K;
                 T.perm = dU.perm;
                 T.row0 = row0;
-                T.spectral = spectral ? 1 : 0;
-                T.spec_b = spec_b ? 1 : 0;
+                T.spectral = sp ? 1 : 0;
+                T.spec_b = (spec_b && sp) ? 1 : 0;
+                // mixed-precision Gaussian: the lag-0 scale decides whether the
+                // problem is evaluated again in FP64 (one-shot calls) or, in a
+                // plan execution, reported as unsupported
+                const bool promotable = !fp64 && !rect;
+                T.guard = (promotable && J.rec) ? 1 : 0;
+                T.rmin = (promotable && !J.rec) ? dU.rmin + p : nullptr;
                 T.weighted = weighted ? 1 : 0;
                 T.is_rect = rect ? 1 : 0;
                 T.beta = beta;
@@ -1570,7 +1699,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
                         T.self_x = W1.wt[selfx[p]].sums;
                         T.self_y = W1.wt[selfy[p]].sums;
                     }
-                    if (spectral) {
+                    if (sp) {
                         const int i = spec_of[p];
                         T.numer = numer[i];
                         T.bspec = bspec[i];
@@ -1681,6 +1810,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
 
     // ------------------------------------------------ direct fallback (spectral b)
     int32_t* h_fstat = nullptr;
+    double* h_rmin = nullptr;
     if (flag_pass) {
         // flags computed on the device from the spectral b values (contiguous
         // over the problems); only the bit masks come back
@@ -1736,13 +1866,19 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             NCF_TRY(emit(J, [=](hipStream_t s) { return launch_normalize(nt, np, io, s); }));
         }
         h_fstat = hU.status;  // pinned
+        h_rmin = (J.rec || fp64 || rect) ? nullptr : hU.rmin;  // written by promotable tasks only
         if (with_masks) {
             const size_t bytes =
-                (size_t)((const char*)(dU.status + J.nprob) - (const char*)dT.mask);
+                (size_t)((const char*)(dU.rmin + J.nprob) - (const char*)dT.mask);
             NCF_TRY_HIP(hipMemcpyAsync(hT.mask, dT.mask, bytes, hipMemcpyDeviceToHost, J.st));
+        } else if (J.io_fixed) {
+            NCF_TRY_HIP(hipMemcpyAsync(h_fstat, J.io_status, sizeof(int32_t) * J.nprob,
+                                       hipMemcpyDeviceToHost, J.st));
         } else {
-            NCF_TRY_HIP(hipMemcpyAsync(h_fstat, J.io_fixed ? J.io_status : dU.status,
-                                       sizeof(int32_t) * J.nprob, hipMemcpyDeviceToHost, J.st));
+            // statuses and the lag-0 scales behind them
+            const size_t bytes = (size_t)((const char*)(dU.rmin + J.nprob) -
+                                          (const char*)dU.status);
+            NCF_TRY_HIP(hipMemcpyAsync(h_fstat, dU.status, bytes, hipMemcpyDeviceToHost, J.st));
         }
         if (!J.dev_ptrs && K > 0) {
             NCF_TRY_HIP(hipMemcpyAsync(J.c, d_c, sizeof(double) * J.nprob * K, hipMemcpyDeviceToHost,
@@ -1793,6 +1929,15 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         if (g_prof_on) {
             std::lock_guard<std::mutex> lock(g_prof_mu);
             prof_flush_locked();
+        }
+        if (h_rmin && !J.plan_build) {
+            // problems whose lag-0 scale is small in mixed precision: again in FP64
+            std::vector<int64_t> again;
+            for (int64_t p = 0; p < J.nprob; ++p)
+                if ((h_fstat[p] == NCF_OK || h_fstat[p] == NCF_E_DEGENERATE) &&
+                    h_rmin[p] < kPromoteScale)
+                    again.push_back(p);
+            if (!again.empty()) NCF_TRY(promote_fp64(J, again, h_fstat, stats));
         }
         return finish_status(J, pstat, h_fstat);
     };

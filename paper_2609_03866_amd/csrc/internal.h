@@ -160,10 +160,11 @@ struct SeriesDesc {
     int64_t xoff;     // first value of this series in IoBlock::x[set]
     const double* err;
     float* v32;       // outputs, each may be null: w (x - mean)/sd in FP32 / FP64,
-    double* v64;      // weights, and FP64 prefix sums of v and w (n + 1 entries)
-    double* w64;
-    double* pv;
-    double* pw;
+    double* v64;      // weights, and FP64 prefix sums of v and w (n + 1 entries),
+    double* w64;      // and the prefix count of samples with a nonzero weight
+    double* pv;       // (exact integers in FP64: a window holding no sample of
+    double* pw;       // nonzero weight is empty whatever its weight prefix says)
+    double* pz;
     int64_t n;        // samples
     int32_t chunk0;   // first chunk of the series
     int32_t nchunk;   // chunks of the series
@@ -176,6 +177,16 @@ struct SeriesDesc {
 // lag-0 sum (sum of z)^2 is 0 exactly, so its rounding (either sign) must not
 // decide the status. CCF: each series' r(0) in magnitude, and the product > 0.
 constexpr double kMinScale = 1e-12;
+// Mixed precision, Gaussian kernel: a problem whose smallest lag-0 scale is
+// below this value is evaluated again in FP64. The FP32 kernel weights and
+// transforms leave an error of about 1e-6 relative on the lag-0 sums, and c
+// divides by the scale, so its error grows as 1/r(0) when the lag-0 sums
+// cancel (a kernel wide against the series).
+constexpr double kPromoteScale = 0.1;
+// Series shorter than this take the direct window sums on any route: with a
+// few samples under a wide kernel, the rounding of the transforms, measured
+// against the lag-0 pair sums, is far above its usual size.
+constexpr int64_t kMinSpectralSamples = 32;
 constexpr int64_t kMomentChunk = 2048;  // samples per moments chunk (8 per thread)
 
 struct Chunk {
@@ -196,7 +207,7 @@ struct MomentsArgs {
     const Chunk* chunks;
     int32_t nseries, nchunks;
     double* chunk_part;      // 4 doubles per chunk: sw, mean, M2, flags
-    double* chunk_tot;       // 2 doubles per chunk (v, w) totals for the prefix pass
+    double* chunk_tot;       // 3 doubles per chunk (v, w, nonzero-weight count) totals for the prefix pass
     SeriesStat* stats;       // nseries
     const IoBlock* io;       // value arrays
     int32_t prefix;          // any series has prefix outputs
@@ -239,6 +250,7 @@ struct WinTask {
     const double* w;     // FP64 weights or null
     const double* pv;    // prefix of v (n_win + 1) or null
     const double* pw;    // prefix of w (n_win + 1) or null
+    const double* pz;    // prefix count of nonzero weights (n_win + 1), weighted rectangle
     int64_t n_win;
     // outer array (series 2 of a CCF)
     const double* s;
@@ -251,7 +263,9 @@ struct WinTask {
     int32_t n_jt, n_kt;  // tiles
     double h;            // bandwidth
     double W;            // window half-width: 6h (Gaussian) or h (rectangle)
-    double* part;        // [n_jt][K][4] partial sums: C, B, b, count (count as bits)
+    double* part;        // [n_jt][K][4] partial sums: C, B, b, count (count as bits);
+                         // weighted rectangle: b holds the count of pairs of two
+                         // nonzero weights (the window is empty when it is 0)
     double* part2;       // [ceil(n_jt / 64)][K][4] first-level sums of part
     double* sums;        // [K][4] final sums
     int64_t item0;       // first work item of this task
@@ -465,7 +479,10 @@ struct NormTask {
     int32_t row0;         // ACF: row of lag 0 in the window sums
     int32_t spectral;     // numerator from the spectral route
     int32_t spec_b;       // pair counts from the spectral route too (else window sums)
-    int32_t pad3;
+    int32_t guard;        // plan execution in mixed precision (Gaussian): a lag-0 scale
+                          // below kPromoteScale reports NCF_E_UNSUPPORTED
+    double* rmin;         // or null: receives the problem's smallest lag-0 scale (ACF
+                          // r(0); CCF min(r_x(0), r_y(0))), +inf when it failed
     const double* bspec;  // spectral b per requested lag (+ lag 0 last for ACF); with
                           // weights the weighted pair sum B
     const double* bunw;   // weighted calls: spectral unweighted b per lag, or null

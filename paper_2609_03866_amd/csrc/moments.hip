@@ -214,7 +214,7 @@ __device__ __forceinline__ double wave_scan(double v) {
 // waves of row k, plus the lane's inclusive wave scan (one barrier).
 __global__ void __launch_bounds__(kThreads)
 k_standardize(MomentsArgs a) {
-    __shared__ double shv[2][kPer][kWaves];
+    __shared__ double shv[3][kPer][kWaves];
     const Chunk ch = a.chunks[blockIdx.x];
     const SeriesDesc sd = a.series[ch.series];
     const SeriesStat st = a.stats[ch.series];
@@ -266,43 +266,60 @@ k_standardize(MomentsArgs a) {
     if (sd.pv == nullptr) return;
     // prefix index of sample i within the series' prefix array: i + 1
     const bool scan_w = sd.pw != nullptr;  // weight prefix only with weights
+    // count of samples with a nonzero weight (weighted series): exact in
+    // FP64 whatever the weights are, so a window of zero-weight samples only
+    // is recognized as empty even where the weight prefix differences leave
+    // rounding residue
+    const bool scan_z = sd.pz != nullptr;
+    double z[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) z[k] = w[k] != 0.0 ? 1.0 : 0.0;
 #pragma unroll
     for (int k = 0; k < kPer; ++k) v[k] = wave_scan(v[k]);
     if (scan_w)
 #pragma unroll
         for (int k = 0; k < kPer; ++k) w[k] = wave_scan(w[k]);
+    if (scan_z)
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) z[k] = wave_scan(z[k]);
     if (lane == 63)
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             shv[0][k][wave] = v[k];
             shv[1][k][wave] = w[k];
+            shv[2][k][wave] = z[k];
         }
     __syncthreads();
-    double carry_v = 0.0, carry_w = 0.0;
+    double carry_v = 0.0, carry_w = 0.0, carry_z = 0.0;
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
         const int64_t i = ch.begin + tid + (int64_t)k * kThreads;
-        double ov = carry_v, ow = carry_w;
+        double ov = carry_v, ow = carry_w, oz = carry_z;
         for (int q = 0; q < wave; ++q) {
             ov += shv[0][k][q];
             ow += shv[1][k][q];
+            oz += shv[2][k][q];
         }
         if (i < ch.end) {
             gbl(sd.pv)[i + 1] = ov + v[k];
             if (sd.pw) gbl(sd.pw)[i + 1] = ow + w[k];
+            if (sd.pz) gbl(sd.pz)[i + 1] = oz + z[k];
         }
 #pragma unroll
         for (int q = 0; q < kWaves; ++q) {
             carry_v += shv[0][k][q];
             carry_w += shv[1][k][q];
+            carry_z += shv[2][k][q];
         }
     }
     if (tid == 0) {
-        a.chunk_tot[2 * (int64_t)blockIdx.x] = carry_v;
-        a.chunk_tot[2 * (int64_t)blockIdx.x + 1] = carry_w;
+        a.chunk_tot[3 * (int64_t)blockIdx.x] = carry_v;
+        a.chunk_tot[3 * (int64_t)blockIdx.x + 1] = carry_w;
+        a.chunk_tot[3 * (int64_t)blockIdx.x + 2] = carry_z;
         if (ch.begin == 0) {
             sd.pv[0] = 0.0;
             if (sd.pw) sd.pw[0] = 0.0;
+            if (sd.pz) sd.pz[0] = 0.0;
         }
     }
 }
@@ -313,7 +330,7 @@ k_standardize(MomentsArgs a) {
 // preceding waves).
 __global__ void __launch_bounds__(kThreads)
 k_chunk_offsets(MomentsArgs a) {
-    __shared__ double shv[2][kWaves];
+    __shared__ double shv[3][kWaves];
     const int s = blockIdx.x;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -321,35 +338,42 @@ k_chunk_offsets(MomentsArgs a) {
     if (!sd.pv) return;
     const int per = (sd.nchunk + kThreads - 1) / kThreads;
     const int c0 = tid * per, c1 = min(sd.nchunk, c0 + per);
-    double tv = 0.0, tw = 0.0;
+    double tv = 0.0, tw = 0.0, tz = 0.0;
     for (int c = c0; c < c1; ++c) {
-        const double* p = a.chunk_tot + 2 * (int64_t)(sd.chunk0 + c);
+        const double* p = a.chunk_tot + 3 * (int64_t)(sd.chunk0 + c);
         tv += p[0];
         tw += p[1];
+        tz += p[2];
     }
-    const double iv = wave_scan(tv), iw = wave_scan(tw);
+    const double iv = wave_scan(tv), iw = wave_scan(tw), iz = wave_scan(tz);
     if (lane == 63) {
         shv[0][wave] = iv;
         shv[1][wave] = iw;
+        shv[2][wave] = iz;
     }
     __syncthreads();
-    double ev = __shfl_up(iv, 1), ew = __shfl_up(iw, 1);  // exclusive within the wave
-    double cv = 0.0, cw = 0.0;
+    // exclusive within the wave
+    double ev = __shfl_up(iv, 1), ew = __shfl_up(iw, 1), ez = __shfl_up(iz, 1);
+    double cv = 0.0, cw = 0.0, cz = 0.0;
     for (int q = 0; q < wave; ++q) {
         cv += shv[0][q];
         cw += shv[1][q];
+        cz += shv[2][q];
     }
     if (lane > 0) {
         cv += ev;
         cw += ew;
+        cz += ez;
     }
     for (int c = c0; c < c1; ++c) {
-        double* p = a.chunk_tot + 2 * (int64_t)(sd.chunk0 + c);
-        const double v = p[0], w = p[1];
+        double* p = a.chunk_tot + 3 * (int64_t)(sd.chunk0 + c);
+        const double v = p[0], w = p[1], z = p[2];
         p[0] = cv;
         p[1] = cw;
+        p[2] = cz;
         cv += v;
         cw += w;
+        cz += z;
     }
 }
 
@@ -361,18 +385,21 @@ k_prefix_add(MomentsArgs a) {
     const SeriesDesc sd = a.series[ch.series];
     if (!sd.pv) return;
     if (ch.begin == 0) return;  // first chunk: offset 0
-    const double ov = a.chunk_tot[2 * (int64_t)blockIdx.x];
-    const double ow = a.chunk_tot[2 * (int64_t)blockIdx.x + 1];
-    const gptr<double> pv = gbl(sd.pv), pw = gbl(sd.pw);
-    double v[kPer], w[kPer];
+    const double ov = a.chunk_tot[3 * (int64_t)blockIdx.x];
+    const double ow = a.chunk_tot[3 * (int64_t)blockIdx.x + 1];
+    const double oz = a.chunk_tot[3 * (int64_t)blockIdx.x + 2];
+    const gptr<double> pv = gbl(sd.pv), pw = gbl(sd.pw), pz = gbl(sd.pz);
+    double v[kPer], w[kPer], z[kPer];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
         const int64_t i = ch.begin + threadIdx.x + (int64_t)k * kThreads;
         v[k] = 0.0;
         w[k] = 0.0;
+        z[k] = 0.0;
         if (i < ch.end) {
             v[k] = pv[i + 1];
             if (sd.pw) w[k] = pw[i + 1];
+            if (sd.pz) z[k] = pz[i + 1];
         }
     }
 #pragma unroll
@@ -381,6 +408,7 @@ k_prefix_add(MomentsArgs a) {
         if (i < ch.end) {
             pv[i + 1] = v[k] + ov;
             if (sd.pw) pw[i + 1] = w[k] + ow;
+            if (sd.pz) pz[i + 1] = z[k] + oz;
         }
     }
 }

@@ -42,7 +42,10 @@ k_normalize(const NormTask* __restrict__ tasks, const IoBlock* __restrict__ io) 
             out_b[k] = 0.0;
             if (out_n) out_n[k] = 0;
         }
-        if (tid == 0) *out_st = fail;
+        if (tid == 0) {
+            *out_st = fail;
+            if (T.rmin) *T.rmin = INFINITY;
+        }
         return;
     }
     const int bq = T.weighted ? 1 : 2;  // which window sum is the denominator B
@@ -70,7 +73,7 @@ k_normalize(const NormTask* __restrict__ tasks, const IoBlock* __restrict__ io) 
     // numerator where b is small
     const bool sel_window = T.spectral && !T.spec_b && !T.is_rect;
     if (tid == 0) {
-        double scale;
+        double scale, rmin;
         if (T.ccf) {
             double cx, cy, bx, by;
             if (T.spectral && T.spec_b) {
@@ -94,6 +97,7 @@ k_normalize(const NormTask* __restrict__ tasks, const IoBlock* __restrict__ io) 
                      isfinite(prod))
                         ? sqrt(prod)
                         : NAN;
+            rmin = fmin(sx, sy);
         } else {
             double c0, b0;
             if (T.spectral && T.spec_b) {
@@ -105,9 +109,21 @@ k_normalize(const NormTask* __restrict__ tasks, const IoBlock* __restrict__ io) 
             }
             const double r0 = c0 / fl(b0);
             scale = (r0 > kMinScale && isfinite(r0)) ? r0 : NAN;
+            rmin = r0;
         }
+        // a scale at or below kMinScale in mixed precision is also evaluated
+        // again in FP64 (rmin is kept): FP32 rounding may have decided it
+        int32_t st = (scale == scale) ? NCF_OK : NCF_E_DEGENERATE;
+        if (rmin != rmin) rmin = INFINITY;
+        if (st == NCF_OK && T.guard && rmin < kPromoteScale) {
+            // a plan replays fixed launches and cannot evaluate this problem
+            // again in FP64: its mixed-precision result is not reported
+            scale = NAN;
+            st = NCF_E_UNSUPPORTED;
+        }
+        if (T.rmin) *T.rmin = rmin;
         sh_scale = scale;
-        *out_st = (scale == scale) ? NCF_OK : NCF_E_DEGENERATE;
+        *out_st = st;
         if (sel_window) {
             // reference pair count of the window-b spectral path, a bound of
             // the pair sum over every lag: ACF b(0); CCF sqrt(B_xx(0) B_yy(0))
@@ -141,15 +157,21 @@ k_normalize(const NormTask* __restrict__ tasks, const IoBlock* __restrict__ io) 
             bout = T.bunw ? T.bunw[k] : T.bspec[k];
         } else {
             const double* w = T.wsums + 4 * (int64_t)T.perm[k];
-            // an empty window has numerator exactly 0; a window with few
-            // pairs takes the direct numerator (the spectral value there is
-            // rounding noise that a small denominator would amplify)
-            const bool empty = __double_as_longlong(w[3]) == 0 || (T.weighted && w[bq] == 0.0);
+            cnt = __double_as_longlong(w[3]);
+            // an empty window has numerator exactly 0: no pair, or (weights)
+            // no pair of two nonzero weights, a window of samples of weight 0
+            // only (dropped bootstrap samples). Gaussian: the weighted pair
+            // sum is then exactly 0 (a direct sum of zero terms); rectangle:
+            // the window pass counts those pairs exactly in w[2] (its weight
+            // prefix differences can leave rounding residue). A window with
+            // few pairs takes the direct numerator (the spectral value there
+            // is rounding noise that a small denominator would amplify)
+            const bool empty =
+                cnt == 0 || (T.weighted && (T.is_rect ? w[2] == 0.0 : w[bq] == 0.0));
             const bool direct = !T.spectral || (sel_window && w[bq] < T.beta * sh_bref);
             num = empty ? 0.0 : (direct ? w[0] : T.numer[k]);
             den = w[bq];
-            bout = w[2];
-            cnt = __double_as_longlong(w[3]);
+            bout = T.is_rect ? (double)cnt : w[2];
         }
         out_c[k] = (num / fl(den)) / scale;
         out_b[k] = fl(bout);

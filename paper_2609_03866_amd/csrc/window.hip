@@ -77,6 +77,7 @@ struct LdsView {
     __device__ __forceinline__ double T(int i) const { return g_win_lds[t0 + i]; }
     __device__ __forceinline__ double A1(int i) const { return g_win_lds[a10 + i]; }
     __device__ __forceinline__ double A2(int i) const { return g_win_lds[a20 + i]; }
+    __device__ __forceinline__ double A3(int) const { return 0.0; }  // rectangle only, global path
     __device__ __forceinline__ double S(int j) const { return g_win_lds[s0 + j]; }
     __device__ __forceinline__ double VO(int j) const { return g_win_lds[vo0 + j]; }
     __device__ __forceinline__ double WO(int j) const { return g_win_lds[wo0 + j]; }
@@ -85,11 +86,12 @@ struct LdsView {
 // Fallback when the window range does not fit in LDS: global memory with
 // explicit bounds.
 struct GlbView {
-    gdp t, a1, a2, s, vo, wo;
+    gdp t, a1, a2, a3, s, vo, wo;
     int len;
     __device__ __forceinline__ double T(int i) const { return i < len ? t[i] : kInf; }
     __device__ __forceinline__ double A1(int i) const { return a1[i]; }
     __device__ __forceinline__ double A2(int i) const { return a2[i]; }
+    __device__ __forceinline__ double A3(int i) const { return a3[i]; }
     __device__ __forceinline__ double S(int j) const { return s[j]; }
     __device__ __forceinline__ double VO(int j) const { return vo[j]; }
     __device__ __forceinline__ double WO(int j) const { return wo[j]; }
@@ -166,7 +168,12 @@ __device__ __forceinline__ void scan_lane(Acc& acc, const V& v, int ja, int jb, 
             hi = advance<true>(v, hi, hk);
             acc.n += hi - lo;
             if (NUMER) acc.C += v.VO(j) * (v.A1(hi) - v.A1(lo));
-            if (WTD) acc.B += v.WO(j) * (v.A2(hi) - v.A2(lo));
+            if (WTD) {
+                const double wo = v.WO(j);
+                acc.B += wo * (v.A2(hi) - v.A2(lo));
+                // pairs of two nonzero weights (exact integer count)
+                if (wo != 0.0) acc.b += v.A3(hi) - v.A3(lo);
+            }
         } else {
             hi = advance<false>(v, hi, hk);
             double bj = 0.0, Cj = 0.0, Bj = 0.0;
@@ -218,6 +225,7 @@ __device__ __forceinline__ void scan_lane(Acc& acc, const V& v, int ja, int jb, 
 // the numerator sums as scan_lane.
 struct AccR {
     double C, B;
+    double nz;  // weighted: pairs of two nonzero weights
     int bytes;  // sum over j of (hi - lo) * 8
 };
 
@@ -228,6 +236,7 @@ __device__ __forceinline__ void scan_rect(AccR& acc, int o_t, int dp, int o_o, i
                                           int jb, double delta, double W) {
     constexpr int QO = 1 + (NUMER ? 1 : 0) + (WTD ? 1 : 0);
     constexpr int QW = NUMER ? 2 : 1;  // PW array follows P when both exist
+    constexpr int QZ = QW + 1;         // then the nonzero-weight count prefix
     if (ja >= jb) return;
     const double* win = g_win_lds + o_t;
     const double* po = g_win_lds + o_o + QO * ja;
@@ -288,7 +297,10 @@ __device__ __forceinline__ void scan_rect(AccR& acc, int o_t, int dp, int o_o, i
         }
         acc.bytes += (int)((const char*)phi - (const char*)plo);
         if (NUMER) acc.C += vo * (phi[dp] - plo[dp]);
-        if (WTD) acc.B += wo * (phi[QW * dp] - plo[QW * dp]);
+        if (WTD) {
+            acc.B += wo * (phi[QW * dp] - plo[QW * dp]);
+            if (wo != 0.0) acc.nz += phi[QZ * dp] - plo[QZ * dp];
+        }
         po = pn;
         if (po == pend) break;
         s = s_n;
@@ -356,26 +368,31 @@ __device__ __forceinline__ void window_item(const WinTask* __restrict__ tasks,
     const double* A1g = RECT ? T.pv : T.v;
     const double* A2g = RECT ? T.pw : T.w;
     const int a_len = RECT ? len + 1 : len;  // prefix arrays need the entry at hi
-    // rectangle: times, prefix arrays (each cap + 8 long), then outer
-    // records (s[, vo][, wo])
-    constexpr int QR = 1 + (NUMER ? 1 : 0) + (WTD ? 1 : 0);
+    // rectangle: times, prefix arrays (each cap + 8 long: values, weights and
+    // the nonzero-weight count), then outer records (s[, vo][, wo])
+    constexpr int QW = NUMER ? 2 : 1;
+    constexpr int QR = 1 + (NUMER ? 1 : 0) + (WTD ? 2 : 0);
+    constexpr int QRO = 1 + (NUMER ? 1 : 0) + (WTD ? 1 : 0);
     const int o_rw = 0;
     const int dp = cap + 8;
     const int o_ro = QR * (cap + 8);
     const gdp gt = (gdp)T.t, gs = (gdp)T.s, gvo = (gdp)T.vo, gwo = (gdp)T.wo;
-    const gdp ga1 = (gdp)A1g, ga2 = (gdp)A2g;
+    const gdp ga1 = (gdp)A1g, ga2 = (gdp)A2g, ga3 = (gdp)T.pz;
     if (RECT && fits) {
         for (int i = tid; i < len + 8; i += kThreads) {
             double* r = g_win_lds + o_rw + i;
             r[0] = i < len ? gt[tlo + i] : kInf;
             if (NUMER) r[dp] = i <= len ? ga1[tlo + i] : 0.0;
-            if (WTD) r[(QR - 1) * dp] = i <= len ? ga2[tlo + i] : 0.0;
+            if (WTD) {
+                r[QW * dp] = i <= len ? ga2[tlo + i] : 0.0;
+                r[(QW + 1) * dp] = i <= len ? ga3[tlo + i] : 0.0;
+            }
         }
         for (int i = tid; i <= nj; i += kThreads) {
-            double* r = g_win_lds + o_ro + QR * i;
+            double* r = g_win_lds + o_ro + QRO * i;
             r[0] = i < nj ? gs[j0 + i] : 0.0;
             if (NUMER) r[1] = i < nj ? gvo[j0 + i] : 0.0;
-            if (WTD) r[QR - 1] = i < nj ? gwo[j0 + i] : 0.0;
+            if (WTD) r[QRO - 1] = i < nj ? gwo[j0 + i] : 0.0;
         }
     } else if (fits) {
         for (int i = tid; i < len + 8; i += kThreads)
@@ -408,10 +425,11 @@ __device__ __forceinline__ void window_item(const WinTask* __restrict__ tasks,
 
     Acc acc = {0.0, 0.0, 0.0, 0};
     if (RECT && fits) {
-        AccR ar = {0.0, 0.0, 0};
+        AccR ar = {0.0, 0.0, 0.0, 0};
         if (active) scan_rect<NUMER, WTD>(ar, o_rw, dp, o_ro, len, ja, jb, delta, W);
         acc.C = ar.C;
         acc.B = ar.B;
+        acc.b = ar.nz;
         acc.n = ar.bytes / (int)sizeof(double);
     } else if (active) {
         if (fits) {
@@ -421,6 +439,7 @@ __device__ __forceinline__ void window_item(const WinTask* __restrict__ tasks,
             GlbView v{(gdp)(T.t + tlo),
                       HAS_A1 ? (gdp)(A1g + tlo) : nullptr,
                       HAS_A2 ? (gdp)(A2g + tlo) : nullptr,
+                      (RECT && WTD) ? (gdp)(T.pz + tlo) : nullptr,
                       (gdp)(T.s + j0),
                       NUMER ? (gdp)(T.vo + j0) : nullptr,
                       WTD ? (gdp)(T.wo + j0) : nullptr,
@@ -572,8 +591,8 @@ __global__ void k_window_reduce(const WinTask* __restrict__ tasks, int ntasks,
         C *= norm;
         B *= norm;
         b *= norm;
-    } else {
-        b = (double)n;
+    } else if (!(flags & WIN_WEIGHTED)) {
+        b = (double)n;  // weighted: b holds the pairs of two nonzero weights
     }
     double* out = T.sums + (int64_t)k * 4;
     out[0] = C;
@@ -611,7 +630,7 @@ int launch_window_t(const WinTask* d_tasks, const int64_t* d_item0, int ntasks, 
     constexpr bool RECT = (F & WIN_RECT) != 0;
     constexpr bool NUMER = (F & WIN_NUMER) != 0;
     constexpr bool WTD = (F & WIN_WEIGHTED) != 0;
-    size_t stage = (size_t)(cap + 8) * (1 + (NUMER ? 1 : 0) + (WTD ? 1 : 0)) +
+    size_t stage = (size_t)(cap + 8) * (1 + (NUMER ? 1 : 0) + (WTD ? (RECT ? 2 : 1) : 0)) +
                    (size_t)(jmax + 2) * (1 + (NUMER ? 1 : 0) + (WTD ? 1 : 0));
     size_t red = 4 * kThreads;
     size_t bytes = (stage > red ? stage : red) * sizeof(double);

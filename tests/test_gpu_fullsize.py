@@ -1,7 +1,7 @@
 """GPU parity at the benchmark workloads' full sizes, in the call shape the
 benchmark times: one call over the whole batch with the inputs resident on
 the device (torch tensors, device pointers). The oracle computes a sample of
-the outputs one by one: the largest and the smallest series (pairs) of the
+the outputs one by one: the first 64 series (pairs), the largest and the smallest of the
 batch and a few drawn at random, and for the replicate error bars three of
 the replicates. Tolerances are those of the single-call parity tests: mixed
 precision |dc| <= 1e-5 and pair counts within 1e-5 of the largest; rectangle
@@ -53,23 +53,50 @@ def _check_exact(c, b, n, oc, on, ctol):
     np.testing.assert_array_equal(b, np.maximum(on.astype(float), 1e-16))
 
 
-def test_c4_full_size_sampled_series():
-    # 10,000 light curves of 100 to 5e4 samples, 256 lags, Gaussian, mixed
-    d = synth.c4()
+@pytest.fixture(scope="module")
+def c4_data():
+    return synth.c4()
+
+
+def test_c4_full_size_sampled_series(c4_data):
+    # 10,000 light curves of 100 to 5e4 samples, 256 lags, Gaussian, mixed:
+    # the first 64 curves (the benchmark's oracle sample) and the largest,
+    # the smallest and a few drawn at random
+    d = c4_data
     offs = d["offs"]
     c, b, n, st, rc = ncf.acf_batch(offs, _dev(d["t"]), _dev(d["x"]), _dev(d["lags"]),
                                     "gaussian", d["h"])
     c, b = _host(c), _host(b)
     assert rc == 0 and np.all(np.asarray(st) == 0)
-    for i in _sample(np.diff(offs), 4, 41):
+    for i in sorted(set(range(64)) | set(_sample(np.diff(offs), 4, 41))):
         sl = slice(offs[i], offs[i + 1])
         ost, oc, ob, _ = O.acf(d["t"][sl], d["x"][sl], d["lags"], "gaussian", d["h"][i])
         assert ost == 0
         _check_gauss(c[i], b[i], oc, ob)
 
 
+def test_c4_weighted_full_size_sampled_series(c4_data):
+    # the same batch weighted by its heteroscedastic errors (w = 1/err^2,
+    # four decades of weights): weighted spectral pair sums with the direct
+    # fallback, on twelve sampled curves
+    d = c4_data
+    offs, err = d["offs"], d["err_values"]
+    c, b, n, st, rc = ncf.acf_batch(offs, _dev(d["t"]), _dev(d["x"]), _dev(d["lags"]),
+                                    "gaussian", d["h"], err=_dev(err))
+    c, b = _host(c), _host(b)
+    assert rc == 0 and np.all(np.asarray(st) == 0)
+    for i in _sample(np.diff(offs), 10, 44):
+        sl = slice(offs[i], offs[i + 1])
+        ost, oc, ob, _ = O.acf(d["t"][sl], d["x"][sl], d["lags"], "gaussian", d["h"][i],
+                               err=err[sl])
+        assert ost == 0
+        _check_gauss(c[i], b[i], oc, ob)
+
+
 def test_c5_full_size_sampled_pairs():
-    # 2,048 pairs of 1e3 to 2e5 samples, 512 lags, rectangle: exact counts
+    # 2,048 pairs of 1e3 to 2e5 samples, 512 lags, rectangle: exact counts on
+    # the first 64 pairs (the subset the workload names) and the largest and
+    # the smallest pair
     d = synth.c5()
     offx, offy = d["offx"], d["offy"]
     c, b, n, st, rc = ncf.ccf_batch(offx, _dev(d["t"]), _dev(d["x"]), offy, _dev(d["s"]),
@@ -77,12 +104,15 @@ def test_c5_full_size_sampled_pairs():
     c, b, n = _host(c), _host(b), _host(n)
     assert rc == 0 and np.all(np.asarray(st) == 0)
     sizes = np.diff(offx) + np.diff(offy)
-    for p in _sample(sizes, 2, 42):
+    worst = 0.0
+    for p in sorted(set(range(64)) | set(_sample(sizes, 0, 42))):
         sx, sy = slice(offx[p], offx[p + 1]), slice(offy[p], offy[p + 1])
         ost, oc, _, on = O.ccf(d["t"][sx], d["x"][sx], d["s"][sy], d["y"][sy], d["lags"],
                                "rectangle", d["h"][p])
         assert ost == 0
         _check_exact(c[p], b[p], n[p], oc, on, 1e-9)
+        worst = max(worst, float(np.max(np.abs(c[p] - oc))))
+    print(f"c5 first 64 pairs: max |dc| = {worst:.3e}, counts exact")
 
 
 def test_r2_full_size_sampled_series():

@@ -352,11 +352,17 @@ def test_c1_full_size_both_precisions():
 
 
 def test_c3_full_size_sampled_lags():
+    # 1e7 samples, 4,096 lags: the mixed-precision product path and the
+    # all-FP64 spectral path (complex128 grids), each on 64 evenly spaced
+    # lags plus the sinusoids' periods, in one call over all 4,096 lags
     d = synth.c3()
-    c, b, n, _ = ncf.acf(d["t"], d["x"], d["lags"], "gaussian", d["h"])
-    pick = np.array([0, 1, 2, 7, 31, 365, 1000, 2047, 4095])
+    pick = np.unique(np.concatenate([np.linspace(0, 4095, 64).round().astype(int),
+                                     [1, 2, 7, 31, 365]]))
     oc, ob, on = _orc_acf(d, lags=d["lags"][pick])
+    c, b, n, _ = ncf.acf(d["t"], d["x"], d["lags"], "gaussian", d["h"])
     _check(c[pick], b[pick], n[pick], oc, ob, on, "gaussian", 1e-5, 1e-6)
+    c, b, n, _ = ncf.acf(d["t"], d["x"], d["lags"], "gaussian", d["h"], precision="fp64")
+    _check(c[pick], b[pick], n[pick], oc, ob, on, "gaussian", 5e-8, 2e-8)
 
 
 @pytest.mark.parametrize("side", ["x", "y"])

@@ -140,3 +140,60 @@ def test_ccf_resample_errors_on_one_side(kernel, prec, method, tol):
                                             **args)
     assert rc == 0
     _cmp(crep, cm, cs, o_st, o_crep, o_cm, o_cs, st, 1e-9 if kernel == "rectangle" else tol)
+
+
+def _dropped_run_series(rng, n, R, with_err, flux):
+    """A series on [0, 400] whose samples in [100, 300] have multiplicity 0 in
+    every replicate (the others 1..3): pairs of kept samples have lags in
+    [-100, 100] or 200 and more apart, so lags between about 101 and 199 hold
+    only dropped samples."""
+    t = np.sort(rng.uniform(0.0, 400.0, n))
+    x = rng.normal(size=n)
+    mult = rng.integers(1, 4, size=(R, n)).astype(np.int32)
+    mult[:, (t > 100.0) & (t < 300.0)] = 0
+    err = rng.uniform(0.5, 2.0, n) if with_err else None
+    z = rng.normal(size=(R, n)) if flux else None
+    sigma = np.full(n, 0.3) if flux else None
+    return t, x, err, sigma, z, mult
+
+
+@pytest.mark.parametrize("kernel", ["rectangle", "gaussian"])
+@pytest.mark.parametrize("with_err", [False, True])
+@pytest.mark.parametrize("flux", [False, True])
+@pytest.mark.parametrize("is_ccf", [False, True])
+def test_windows_of_dropped_samples_are_empty(kernel, with_err, flux, is_ccf):
+    # a window holding only samples of multiplicity 0 holds no pair of the
+    # replicate series: c = 0 exactly, whatever the weights (integer
+    # multiplicities, or multiplicities times 1/err^2, whose weight prefix
+    # differences leave rounding residue); the other lags match the oracle
+    rng = synth.rng_for(960 + 8 * is_ccf + 4 * flux + 2 * with_err + (kernel == "gaussian"))
+    R = 3
+    lags = np.arange(-20.0, 400.0, 5.0)
+    h = 0.5
+    X = _dropped_run_series(rng, 400, R, with_err, flux)
+    if is_ccf:
+        Y = _dropped_run_series(rng, 350, R, with_err, flux)
+        args = dict(ex=X[2], ey=Y[2], sx=X[3], sy=Y[3], zx=X[4], zy=Y[4], multx=X[5],
+                    multy=Y[5])
+        o_st, o_crep, _, _ = O.ccf_resample(X[0], X[1], Y[0], Y[1], lags, kernel, h, **args)
+    else:
+        args = dict(err=X[2], sigma=X[3], z=X[4], mult=X[5])
+        o_st, o_crep, _, _ = O.acf_resample(X[0], X[1], lags, kernel, h, **args)
+    assert np.all(o_st == 0)
+    gap = (lags > 101.0) & (lags < 199.0)
+    assert np.all(o_crep[:, gap] == 0.0)  # the oracle's replicates: empty windows
+    for prec, method, tol in MODES:
+        if is_ccf:
+            cm, cs, crep, st, rc = ncf.ccf_resample(X[0], X[1], Y[0], Y[1], lags, kernel, h,
+                                                    with_reps=True, precision=prec,
+                                                    method=method, **args)
+        else:
+            cm, cs, crep, st, rc = ncf.acf_resample(X[0], X[1], lags, kernel, h,
+                                                    with_reps=True, precision=prec,
+                                                    method=method, **args)
+        what = f"{kernel} {prec} {method} err={with_err} flux={flux} ccf={is_ccf}"
+        assert rc == 0 and np.all(np.asarray(st) == 0), what
+        assert np.all(crep[:, gap] == 0.0), f"{what}: |c| = {np.max(np.abs(crep[:, gap]))}"
+        np.testing.assert_array_equal(crep == 0.0, o_crep == 0.0, err_msg=what)
+        dc = np.max(np.abs(crep - o_crep))
+        assert dc <= (1e-9 if kernel == "rectangle" else tol), f"{what}: {dc}"

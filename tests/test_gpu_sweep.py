@@ -27,24 +27,21 @@ Near-degenerate lag-0 scales: c = r(tau) / s with s the lag-0 scale (ACF
 r(0), CCF sqrt(r_x(0) r_y(0))). When a kernel wide against a short series
 makes a lag-0 sum of standardized values cancel (r(0) << 1), the absolute
 error u of r(tau) and the relative error u / r_min of s (r_min the smaller
-r(0); u = 1e-6 with FP32 kernel weights or transforms, 1e-15 in FP64 sums,
-prefix sums included) both reach c divided by r_min. The mixed-precision
-c tolerance is 1e-5 + u (1 + |c|) (1 / g - 1) with g = min(1, r_min): the
-parity tolerance where r(0) is of order 1, growing as 1 / r(0) below it;
-FP64 and rectangle tolerances add u (1 + |c|) / g. r_min is computed here
-from the standardized values under the case's window. With FP32 Gaussian
-weights a lag-0 scale below 1e-6 cannot be told from a degenerate one (at or
-below 1e-12), so there either status is accepted.
+r(0); u = 1e-15 in FP64 sums, prefix sums included) both reach c divided by
+r_min: FP64 and rectangle tolerances add u (1 + |c|) / g with g = min(1,
+r_min). In mixed precision (u = 1e-6 with FP32 kernel weights or
+transforms) the library evaluates a Gaussian problem again in FP64 when its
+lag-0 scale is below 0.1, so the mixed tolerance is the plain 1e-5 and the
+statuses equal the oracle's. r_min is computed here from the standardized
+values under the case's window. Plan executions cannot re-evaluate: below
+0.1 (a band of +-10 % around it accepts either outcome) a mixed Gaussian
+problem reports NCF_E_UNSUPPORTED, or degenerate where the FP32 lag-0 sum
+rounds to zero.
 
-The spectral route forced onto a series of fewer than 32 samples (method
-"spectral", or the forced route of "auto") is outside the route's accuracy
-claim: with a few samples under a wide kernel the transforms' rounding,
-measured against the lag-0 pair sums that the fallback rule uses, grows
-well past its usual size (5,000-case runs saw |dc| from 2.4e-5 at 20
-samples to 1e-1 and more at 2 to 6 samples, at lags the rule serves
-spectrally), and a near-degenerate scale multiplies it further. The
-automatic route choice sends such calls to the direct sums. Forced, these
-cases are checked for statuses and finite values only.
+Series of fewer than 32 samples take the direct window sums on every route
+(the spectral route forced onto them, method "spectral" or the forced route
+of "auto", left transform rounding far above its usual size: up to 1e-1 at
+2 to 6 samples); they are checked at the parity tolerances.
 
 Sampling patterns: evenly random; seasonal (observable part of a 365-day
 cycle only); bursts (a few tight clusters holding most samples, so some
@@ -138,17 +135,20 @@ def _tols(kernel, prec, method, spec_always, oc, on, r_min, n_min, n0):
         return 1e-9 + 1e-15 * (1.0 + oc) / g, None
     if prec == "mixed":
         btol = ("ref", 1e-5) if method == "auto" else 1e-6
-        return 1e-5 + 1e-6 * (1.0 + oc) * (1.0 / g - 1.0), btol
+        return np.full(oc.shape, 1e-5), btol
     nsum = max(int(np.max(on)) if np.size(on) else 0, n0)
     if method == "direct":
         return max(1e-11, 4e-16 * nsum) + 1e-15 * (1.0 + oc) / g, max(1e-12, 4e-16 * nsum)
     return 4e-7 + 4e-16 * nsum + 1e-15 * (1.0 + oc) / g, 2e-7
 
 
-def _status_ok(gst, ost, kernel, prec, r_min):
+def _status_ok(gst, ost, kernel, prec, r_min, plan=False):
     if gst == ost:
         return True
-    return kernel == "gaussian" and prec == "mixed" and r_min < 1e-6
+    # plan execution, mixed Gaussian, small lag-0 scale: not re-evaluated in
+    # FP64 but reported (or degenerate where the FP32 lag-0 sum rounds to 0)
+    return (plan and kernel == "gaussian" and prec == "mixed" and ost == 0 and
+            r_min < 0.11 and gst in (ncf.E_UNSUPPORTED, ncf.E_DEGENERATE))
 
 
 def _check(what, c, b, n, oc, ob, on, kernel, ctol, btol):
@@ -166,7 +166,7 @@ def _check(what, c, b, n, oc, ob, on, kernel, ctol, btol):
         np.testing.assert_allclose(b, ob, rtol=btol, atol=0, err_msg=what)
 
 
-def _compare(what, kernel, prec, method, spec_always, got, want, sides):
+def _compare(what, kernel, prec, method, spec_always, got, want, sides, plan=False):
     """got = (c, b, count, status), want = the oracle's (status, c, b, count);
     sides = [(t, x, err), ...] the case's series."""
     c, b, cnt, gst = got
@@ -175,15 +175,13 @@ def _compare(what, kernel, prec, method, spec_always, got, want, sides):
     r_min = min(r for r, _ in lag0)
     n0 = max(n for _, n in lag0)
     n_min = min(t.size for (t, _, _, _) in sides)
-    assert _status_ok(gst, ost, kernel, prec, r_min), (
+    assert _status_ok(gst, ost, kernel, prec, r_min, plan), (
         f"{what}: status {gst}, oracle {ost} (r_min {r_min:.3e})")
-    forced = method == "spectral" or (method == "auto" and spec_always)
+    if plan and kernel == "gaussian" and prec == "mixed" and ost == 0:
+        # away from the band around 0.1 the plan's choice is fixed
+        if r_min < 0.09:
+            assert gst != 0, f"{what}: small lag-0 scale {r_min:.3e} reported as OK"
     if gst == 0 and ost == 0:
-        if kernel == "gaussian" and forced and n_min < 32:
-            # outside the spectral route's accuracy claim: statuses and
-            # finite values only
-            assert np.all(np.isfinite(np.asarray(c))) and np.all(np.isfinite(np.asarray(b))), what
-            return
         ctol, btol = _tols(kernel, prec, method, spec_always, oc, on, r_min, n_min, n0)
         _check(what, c, b, cnt, oc, ob, on, kernel, ctol, btol)
 
@@ -259,7 +257,7 @@ def _batch_case(seed):
     return d
 
 
-def _compare_batch(what, d, out, sx, sy):
+def _compare_batch(what, d, out, sx, sy, plan=False):
     """out = (c, b, count, status, rc) of a batch call or plan execution whose
     values are those of sx (and sy)."""
     c, b, cnt, st, rc = out
@@ -277,7 +275,7 @@ def _compare_batch(what, d, out, sx, sy):
         if d["is_ccf"]:
             sides.append((sy[i][0], sy[i][1], None, h[i]))
         _compare(f"{what} [series {i}]", kernel, d["prec"], d["method"], d["spec_always"],
-                 (c[i], b[i], cnt[i], st[i]), (ost, oc, ob, on), sides)
+                 (c[i], b[i], cnt[i], st[i]), (ost, oc, ob, on), sides, plan)
 
 
 @pytest.mark.parametrize("seed", range(10))
@@ -316,7 +314,7 @@ def test_random_plan(seed):
             x = np.concatenate([a[1] for a in sx])
             y = np.concatenate([a[1] for a in sy]) if d["is_ccf"] else None
             out = plan.execute(x, y, raise_on_error=False)
-            _compare_batch(f"{what} [execution {rep}]", d, out, sx, sy)
+            _compare_batch(f"{what} [execution {rep}]", d, out, sx, sy, plan=True)
             rng = d["rng"]
             sx = [(a[0], rng.normal(size=a[0].size).cumsum() * 0.1 + rng.normal(size=a[0].size))
                   for a in sx]
@@ -465,23 +463,14 @@ def test_random_resample(seed):
         if kernel == "rectangle":
             ctol = 1e-9 + 1e-15 * (1.0 + oc) / g
         elif prec == "mixed":
-            ctol = 1e-5 + 1e-6 * (1.0 + oc) * (1.0 / g - 1.0)
+            ctol = np.full(oc.shape, 1e-5)
         else:
             ctol = max(1e-11, 4e-16 * n0) + 1e-15 * (1.0 + oc) / g
         dc = np.abs(crep[r] - orep[r])
-        if kernel == "rectangle" and scheme == "both":
-            # known defect: with multiplicities times error weights, a
-            # rectangle window that holds only samples of multiplicity 0 is
-            # empty in the oracle (c = 0) but its weighted sums on the GPU
-            # are prefix-sum rounding residue, so c there is noise; those
-            # lags are left out (integer multiplicities alone give exact
-            # prefix sums and an exact 0)
-            if is_ccf:
-                on = O.ccf(*reps[0][:2], *reps[1][:2], lags, kernel, h)[3]
-            else:
-                on = O.acf(*reps[0][:2], lags, kernel, h)[3]
-            dc = np.where(on == 0, 0.0, dc)
         assert np.all(dc <= ctol), f"{w}: max |dc| = {np.max(dc):.3e}"
+        # windows that hold no pair of the replicate (only dropped samples,
+        # multiplicity 0): c is exactly 0 on both sides
+        assert np.all(crep[r][orep[r] == 0.0] == 0.0), f"{w}: empty window not 0"
     # returned statistics: those of the returned replicates (finite ones)
     ok = np.isfinite(crep)
     for k in range(lags.size):
