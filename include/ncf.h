@@ -179,6 +179,35 @@ int ncf_ccf_batch(int64_t npair, const int64_t* offx, const double* tx, const do
                   const double* ey, int64_t K, const double* lags, int kern, const double* h,
                   double* c, double* b, int64_t* count, int* status, const ncf_options_t* opt);
 
+/* Allocation-free cross-correlation, for callers that cannot allocate device
+ * memory during the call (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation). Arguments, outputs and errors as in
+ * ncf_ccf; the estimate is that of ncf_ccf with method NCF_DIRECT (the
+ * real-space window sums, exact rectangle counts; options->method and the
+ * scheduling flags are ignored, NCF_DEVICE_POINTERS and the stream are
+ * honoured).
+ *  - The call allocates no device or pinned host memory and frees none: its
+ *    workspace is a fixed 64 MiB array per device, held by the library from
+ *    its load until the process ends, and its small tables go through a
+ *    fixed 4 MiB host buffer. A call whose workspace would exceed them returns
+ *    NCF_E_UNSUPPORTED with a message (roughly: 16 B per sample for the
+ *    rectangle kernel, 8 B for the Gaussian, +16 B with host pointers, plus
+ *    about K x ny / 8 B of window partial sums; a 1e6 + 1e6-sample rectangle
+ *    CCF with 64 lags fits).
+ *  - Every call on a device shares that device's workspace, which keeps the
+ *    last call's contents; nothing in it needs to start at zero. Calls are
+ *    serialized by the library's lock and each returns when its kernels are
+ *    done, so two calls of one process do not overlap; work that overlapped
+ *    them on the device (e.g. replayed captures of an earlier call) would
+ *    race on the workspace.
+ *  - In NCF_MIXED with the Gaussian kernel, a problem whose smaller lag-0
+ *    scale is below 0.1 is not evaluated again in FP64 (that needs more
+ *    workspace): it returns NCF_E_UNSUPPORTED with c = NaN, as plans do. */
+int ncf_ccf_noalloc(int64_t nx, const double* tx, const double* x, const double* ex,
+                    int64_t ny, const double* ty, const double* y, const double* ey, int64_t K,
+                    const double* lags, int kern, double h, double* c, double* b,
+                    int64_t* count, const ncf_options_t* opt);
+
 /* ------------------------------------------------ regular-lattice family
  * Classic-FFT estimators for series sampled on a regular time lattice
  * (Sec. "Regularly-sampled data"; eq. wienerkhinchin of Sec. "Correlation

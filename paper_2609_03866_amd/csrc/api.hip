@@ -155,7 +155,22 @@ struct Resources {
     Staging stage[3];
     unsigned long long* queue = nullptr;  // work-queue counter pairs, zeroed once
     bool exact = false;  // plan: allocate what is asked, no growth slack
+    // allocation-free calls: every arena and staging buffer is carved, in
+    // order, from a fixed device region and a fixed host region; a request
+    // beyond them fails (nothing is allocated or freed)
+    char* fixed_dev = nullptr;
+    size_t fixed_cap = 0, fixed_off = 0;
+    char* fixed_host = nullptr;
+    size_t fixed_host_cap = 0, fixed_host_off = 0;
 };
+
+// Next `bytes` of a fixed region (256-byte aligned), or null when it is full.
+char* carve(char* base, size_t cap, size_t* off, size_t bytes) {
+    const size_t a = (*off + 255) & ~(size_t)255;
+    if (a > cap || bytes > cap - a) return nullptr;
+    *off = a + bytes;
+    return base + a;
+}
 
 constexpr int kQueuePairs = 4;
 
@@ -180,6 +195,19 @@ std::map<int, Resources> g_res;  // one-shot calls, per device
 
 int ensure_ws(Resources& R, int which, size_t bytes, void** out) {
     DevBuf& b = R.ws[which];
+    if (R.fixed_dev) {
+        char* p = carve(R.fixed_dev, R.fixed_cap, &R.fixed_off, bytes);
+        if (!p) {
+            set_error("the call needs more device workspace than the allocation-free "
+                      "entry point's fixed %zu bytes (%zu in use, %zu more asked)",
+                      R.fixed_cap, R.fixed_off, bytes);
+            return NCF_E_UNSUPPORTED;
+        }
+        b.ptr = p;
+        b.cap = bytes;
+        *out = p;
+        return NCF_OK;
+    }
     if (b.cap < bytes) {
         if (b.ptr) {
             NCF_TRY_HIP(hipDeviceSynchronize());
@@ -203,6 +231,21 @@ int ensure_ws(Resources& R, int which, size_t bytes, void** out) {
 
 int ensure_stage(Resources& R, int phase, size_t bytes, Staging** out) {
     Staging& S = R.stage[phase];
+    if (R.fixed_dev) {
+        char* d = carve(R.fixed_dev, R.fixed_cap, &R.fixed_off, bytes);
+        char* h = carve(R.fixed_host, R.fixed_host_cap, &R.fixed_host_off, bytes);
+        if (!d || !h) {
+            set_error("the call's tables (%zu bytes) do not fit the allocation-free entry "
+                      "point's fixed workspace",
+                      bytes);
+            return NCF_E_UNSUPPORTED;
+        }
+        S.h = h;
+        S.d = d;
+        S.cap = bytes;
+        *out = &S;
+        return NCF_OK;
+    }
     if (S.cap < bytes) {
         if (S.h) {
             NCF_TRY_HIP(hipDeviceSynchronize());
@@ -325,6 +368,9 @@ struct Job {
     // the caller does not read b (replicates): weighted Gaussian calls may take
     // the weighted pair sum B from the spectral route
     bool no_b = false;
+    // allocation-free call: no FP64 re-evaluation (it needs workspace); a
+    // near-degenerate mixed-precision problem is reported as plans do
+    bool no_alloc = false;
     // regular-lattice estimators: lattice step per problem
     bool regular = false;
     std::vector<double> dt;
@@ -1683,8 +1729,9 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
                 // problem is evaluated again in FP64 (one-shot calls) or, in a
                 // plan execution, reported as unsupported
                 const bool promotable = !fp64 && !rect;
-                T.guard = (promotable && J.rec) ? 1 : 0;
-                T.rmin = (promotable && !J.rec) ? dU.rmin + p : nullptr;
+                const bool fixed_launches = J.rec != nullptr || J.no_alloc;
+                T.guard = (promotable && fixed_launches) ? 1 : 0;
+                T.rmin = (promotable && !fixed_launches) ? dU.rmin + p : nullptr;
                 T.weighted = weighted ? 1 : 0;
                 T.is_rect = rect ? 1 : 0;
                 T.beta = beta;
@@ -1866,7 +1913,8 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             NCF_TRY(emit(J, [=](hipStream_t s) { return launch_normalize(nt, np, io, s); }));
         }
         h_fstat = hU.status;  // pinned
-        h_rmin = (J.rec || fp64 || rect) ? nullptr : hU.rmin;  // written by promotable tasks only
+        // written by promotable tasks only
+        h_rmin = (J.rec || J.no_alloc || fp64 || rect) ? nullptr : hU.rmin;
         if (with_masks) {
             const size_t bytes =
                 (size_t)((const char*)(dU.rmin + J.nprob) - (const char*)dT.mask);
@@ -2251,6 +2299,92 @@ int ncf_ccf(int64_t nx, const double* tx, const double* x, const double* ex, int
     int64_t ox[2] = {0, nx}, oy[2] = {0, ny};
     return ncf_ccf_batch(1, ox, tx, x, ex, oy, ty, y, ey, K, lags, kern, &h, c, b, count,
                          nullptr, opt);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ allocation-free entry point
+
+namespace ncf {
+namespace {
+
+// Device workspace of ncf_ccf_noalloc: one array per device, held by the
+// loaded code object until the process ends. Host code never passes its name
+// to a kernel or a copy: it takes the array's device address, per device,
+// from hipGetSymbolAddress and carves the call's arenas from that address.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+// host side of the call's table staging (uploads and readbacks of small
+// tables), shared by every device: calls hold the workspace lock
+constexpr size_t kScratchHostBytes = (size_t)4 << 20;
+alignas(256) char g_scratch_host[kScratchHostBytes];
+constexpr int kScratchDevices = 64;
+char* g_scratch_dev[kScratchDevices] = {};  // device address of `scratch`, per device
+
+// The device address of this device's `scratch` array (looked up once per
+// device, with that device current).
+int scratch_of_device(char** out) {
+    int dev = 0;
+    NCF_TRY_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kScratchDevices) {
+        set_error("device %d: the allocation-free entry point supports devices 0..%d", dev,
+                  kScratchDevices - 1);
+        return NCF_E_UNSUPPORTED;
+    }
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        NCF_TRY_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) {
+            set_error("no device address for the allocation-free workspace");
+            return NCF_E_DEVICE;
+        }
+        g_scratch_dev[dev] = (char*)p;
+    }
+    *out = g_scratch_dev[dev];
+    return NCF_OK;
+}
+
+}  // namespace
+}  // namespace ncf
+
+extern "C" {
+
+int ncf_ccf_noalloc(int64_t nx, const double* tx, const double* x, const double* ex,
+                    int64_t ny, const double* ty, const double* y, const double* ey, int64_t K,
+                    const double* lags, int kern, double h, double* c, double* b,
+                    int64_t* count, const ncf_options_t* opt) {
+    clear_error();
+    Job J;
+    NCF_TRY(common_checks(opt, &J.opt, kern));
+    if (nx < 2 || ny < 2 || !tx || !x || !ty || !y || (K > 0 && (!c || !b))) {
+        set_error("null argument, or nx or ny below 2");
+        return NCF_E_INVALID_ARG;
+    }
+    // the direct window sums, one launch per step, no queue counters
+    J.opt.method = NCF_DIRECT;
+    J.opt.flags &= NCF_DEVICE_POINTERS;
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    Resources R;
+    NCF_TRY(scratch_of_device(&R.fixed_dev));
+    R.fixed_cap = kScratchBytes;
+    R.fixed_host = g_scratch_host;
+    R.fixed_host_cap = kScratchHostBytes;
+    R.exact = true;
+    J.c = c;
+    J.b = b;
+    J.count = count;
+    J.no_alloc = true;
+    int64_t ox[2] = {0, nx}, oy[2] = {0, ny};
+    NCF_TRY(setup_job(J, true, 1, ox, oy, nx, ny, kern, &h, K, lags));
+    J.res = &R;
+    const double* tin[2] = {tx, ty};
+    const double* xin[2] = {x, y};
+    const double* ein[2] = {ex, ey};
+    const int rc = run_job(J, tin, xin, ein);
+    // a call that stopped early may still have work in flight on the
+    // workspace that the next call reuses
+    if (rc != NCF_OK) (void)hipStreamSynchronize(J.st);
+    return rc;
 }
 
 }  // extern "C"

@@ -80,6 +80,8 @@ def lib():
                               _P, _P]
         L.ncf_ccf.argtypes = [_I64, _P, _P, _P, _I64, _P, _P, _P, _I64, _P, ctypes.c_int,
                               ctypes.c_double, _P, _P, _P, _P]
+        L.ncf_ccf_noalloc.argtypes = [_I64, _P, _P, _P, _I64, _P, _P, _P, _I64, _P,
+                                      ctypes.c_int, ctypes.c_double, _P, _P, _P, _P]
         L.ncf_acf_batch.argtypes = [_I64, _P, _P, _P, _P, _I64, _P, ctypes.c_int, _P, _P, _P, _P,
                                     _P, _P]
         L.ncf_ccf_batch.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _I64, _P,
@@ -241,6 +243,25 @@ def ccf(t, x, s, y, lags, kernel="gaussian", h=1.0, ex=None, ey=None, precision=
                  spectral_always)
     rc = lib().ncf_ccf(nx, m.inp(t), m.inp(x), m.inp(ex), ny, m.inp(s), m.inp(y), m.inp(ey), K,
                        m.inp(lags), _kern(kernel), float(h), pc, pb, pn, ctypes.byref(o))
+    if raise_on_error:
+        _check(rc)
+    return c, b, cnt, rc
+
+
+def ccf_noalloc(t, x, s, y, lags, kernel="gaussian", h=1.0, ex=None, ey=None,
+                precision="mixed", with_count=True, raise_on_error=True, stream=None):
+    """ncf_ccf_noalloc: the direct window sums in the library's fixed
+    workspace (no device allocation by the library during the call)."""
+    dev = t.device if _is_torch(t) else None
+    m = _Marshal(dev)
+    K = int(lags.numel() if _is_torch(lags) else np.asarray(lags).size)
+    c, pc, b, pb, cnt, pn = m.outs(K, with_count)
+    nx = int(t.numel() if _is_torch(t) else np.asarray(t).size)
+    ny = int(s.numel() if _is_torch(s) else np.asarray(s).size)
+    o = _options(precision, "direct", 0.0, 0.0, 0, dev, stream)
+    rc = lib().ncf_ccf_noalloc(nx, m.inp(t), m.inp(x), m.inp(ex), ny, m.inp(s), m.inp(y),
+                               m.inp(ey), K, m.inp(lags), _kern(kernel), float(h), pc, pb, pn,
+                               ctypes.byref(o))
     if raise_on_error:
         _check(rc)
     return c, b, cnt, rc
