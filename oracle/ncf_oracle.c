@@ -33,12 +33,14 @@
  *        scale_x = C_xx(0)/max(B_xx(0),1e-16) on (t,x) with eps=+1, same for y
  *        (Algorithm "CCF via real-space kernel-weighted summation").
  *
- * The two-pointer scan follows the paper's PairCount / CorrSum loops: for
- * each lag the window [lo, hi) only advances as the centre increases. The
- * rectangle numerator is summed directly over the window (not by prefix
- * sums), so this file never uses the prefix-sum form the GPU path relies on.
- * A brute-force all-pairs mode evaluates the same predicates without any
- * scan.
+ * The sums are taken straight from the definition: for each lag and each
+ * outer sample j the window is the set of window samples i that satisfy the
+ * predicate above. Since the window times are sorted that set is one run of
+ * consecutive indices; its two ends are found by bisection on the predicate
+ * and every pair in the run is summed directly (the rectangle numerator too,
+ * never by prefix sums, so this file does not use the prefix-sum form the
+ * GPU path relies on). A brute-force all-pairs mode tests the predicate on
+ * every pair instead.
  */
 #include <math.h>
 #include <stdint.h>
@@ -132,40 +134,63 @@ typedef struct {
     double dt;
 } scan_args;
 
-/* Two-pointer window scan for one lag (PairCount / CorrSum loop body). */
+/* Bisection over a sorted array: the number of leading entries that satisfy
+ * a predicate that holds for a prefix of the array (true, ..., true, false,
+ * ..., false). `below(i)` is that predicate; `ctx` is passed through. */
+typedef int (*prefix_pred)(const void* ctx, int64_t i);
+
+static int64_t prefix_length(const void* ctx, int64_t n, prefix_pred below) {
+    int64_t lo = 0, hi = n; /* below(i) for i < lo; !below(i) for i >= hi */
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (below(ctx, mid))
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+typedef struct {
+    const double* t;
+    double key;
+} time_key;
+
+static int time_lt(const void* c, int64_t i) {
+    const time_key* k = (const time_key*)c;
+    return k->t[i] < k->key;
+}
+
+static int time_le(const void* c, int64_t i) {
+    const time_key* k = (const time_key*)c;
+    return k->t[i] <= k->key;
+}
+
+/* Window sums for one lag from the definition (eq. kernel_estimator with
+ * the window predicates of PairCount): for outer sample j with centre
+ * s_j + eps*tau, the window samples are those with t_i >= centre - W and
+ * t_i < centre + W (Gaussian, W = 6h) or t_i <= centre + h (rectangle).
+ * With t sorted they are the indices [lo, hi): lo counts the t_i below
+ * centre - W, hi those below centre + W (Gaussian) or at most centre + h
+ * (rectangle). */
 static void scan_one_lag(const scan_args* a, double tau, double* C, double* B, double* b,
                          int64_t* count) {
     double c_acc = 0.0, B_acc = 0.0, b_acc = 0.0;
     int64_t n_acc = 0;
-    int64_t lo = 0, hi = 0;
     const double e = (double)a->eps;
-    if (a->kernel == ORC_GAUSSIAN) {
-        const double W = 6.0 * a->h;
-        for (int64_t j = 0; j < a->n_out; ++j) {
-            double centre = a->s[j] + e * tau;
-            while (lo < a->n_win && a->t[lo] < centre - W) lo++;
-            while (hi < a->n_win && a->t[hi] < centre + W) hi++;
-            for (int64_t i = lo; i < hi; ++i) {
-                double wt = gauss_weight(a->t[i] - centre, a->h);
-                c_acc += wt * a->v_win[i] * a->v_out[j];
-                B_acc += wt * a->w_win[i] * a->w_out[j];
-                b_acc += wt;
-                n_acc += 1;
-            }
-        }
-    } else {
-        const double hw = a->h;
-        for (int64_t j = 0; j < a->n_out; ++j) {
-            double centre = a->s[j] + e * tau;
-            while (lo < a->n_win && a->t[lo] < centre - hw) lo++;
-            if (hi < lo) hi = lo;
-            while (hi < a->n_win && a->t[hi] <= centre + hw) hi++;
-            for (int64_t i = lo; i < hi; ++i) {
-                c_acc += a->v_win[i] * a->v_out[j];
-                B_acc += a->w_win[i] * a->w_out[j];
-                b_acc += 1.0;
-                n_acc += 1;
-            }
+    const int gauss = a->kernel == ORC_GAUSSIAN;
+    const double W = gauss ? 6.0 * a->h : a->h;
+    for (int64_t j = 0; j < a->n_out; ++j) {
+        const double centre = a->s[j] + e * tau;
+        time_key klo = {a->t, centre - W}, khi = {a->t, centre + W};
+        const int64_t lo = prefix_length(&klo, a->n_win, time_lt);
+        const int64_t hi = prefix_length(&khi, a->n_win, gauss ? time_lt : time_le);
+        for (int64_t i = lo; i < hi; ++i) {
+            const double wt = gauss ? gauss_weight(a->t[i] - centre, a->h) : 1.0;
+            c_acc += wt * a->v_win[i] * a->v_out[j];
+            B_acc += wt * a->w_win[i] * a->w_out[j];
+            b_acc += wt;
+            n_acc += 1;
         }
     }
     *C = c_acc;
@@ -189,6 +214,22 @@ static double snap_edge(double e) {
     return fabs(e - r) <= 1e-9 * fmax(1.0, fabs(e)) ? r : e;
 }
 
+typedef struct {
+    const int64_t* m;
+    int64_t mj;
+    double edge;
+} lattice_key;
+
+static int lattice_lt(const void* c, int64_t i) {
+    const lattice_key* k = (const lattice_key*)c;
+    return (double)(k->m[i] - k->mj) < k->edge;
+}
+
+static int lattice_le(const void* c, int64_t i) {
+    const lattice_key* k = (const lattice_key*)c;
+    return (double)(k->m[i] - k->mj) <= k->edge;
+}
+
 static void lattice_one_lag(const scan_args* a, double tau, double* C, double* B, double* b,
                             int64_t* count) {
     double c_acc = 0.0, B_acc = 0.0, b_acc = 0.0;
@@ -196,16 +237,15 @@ static void lattice_one_lag(const scan_args* a, double tau, double* C, double* B
     const double e = (double)a->eps;
     const int gauss = a->kernel == ORC_GAUSSIAN;
     const double W = gauss ? 6.0 * a->h : a->h;
-    const double lo = snap_edge((e * tau - W) / a->dt);
-    const double hi = snap_edge((e * tau + W) / a->dt);
-    int64_t i_lo = 0, i_hi = 0;
+    const double lo_edge = snap_edge((e * tau - W) / a->dt);
+    const double hi_edge = snap_edge((e * tau + W) / a->dt);
     for (int64_t j = 0; j < a->n_out; ++j) {
         const int64_t mj = a->m_out[j];
-        while (i_lo < a->n_win && (double)(a->m_win[i_lo] - mj) < lo) i_lo++;
-        if (i_hi < i_lo) i_hi = i_lo;
-        while (i_hi < a->n_win &&
-               (gauss ? (double)(a->m_win[i_hi] - mj) < hi : (double)(a->m_win[i_hi] - mj) <= hi))
-            i_hi++;
+        /* the lattice indices are sorted with the times: the window is
+         * again one run [i_lo, i_hi) of window samples */
+        lattice_key klo = {a->m_win, mj, lo_edge}, khi = {a->m_win, mj, hi_edge};
+        const int64_t i_lo = prefix_length(&klo, a->n_win, lattice_lt);
+        const int64_t i_hi = prefix_length(&khi, a->n_win, gauss ? lattice_lt : lattice_le);
         for (int64_t i = i_lo; i < i_hi; ++i) {
             const double q = (double)(a->m_win[i] - mj);
             const double wt = gauss ? gauss_weight(q * a->dt - e * tau, a->h) : 1.0;
@@ -252,8 +292,8 @@ static void brute_one_lag(const scan_args* a, double tau, double* C, double* B, 
     *count = n_acc;
 }
 
-/* Window sums for every lag; lags distributed over threads as the paper's
- * parallel-for over k. Outputs are raw (not floored). m_out/m_win: lattice
+/* Window sums for every lag; the lags are independent and shared out over
+ * threads. Outputs are raw (not floored). m_out/m_win: lattice
  * indices for the lattice reading, or NULL. */
 static int window_sums(int kernel, int eps, int64_t n_out, const double* s, const double* v_out,
                        const double* w_out, int64_t n_win, const double* t, const double* v_win,
