@@ -46,6 +46,11 @@
  *  - The caller owns all buffers; the library keeps no caller pointer after
  *    return. Device workspace is cached by the library per device and freed
  *    by ncf_release_workspace() or at process exit.
+ *  - The environment variable NCF_WORKSPACE_LIMIT_MB (MiB, read once per
+ *    process) bounds the device workspace arenas of a call or a plan: a call
+ *    that would need more returns NCF_E_NOMEM with a message before
+ *    allocating, and the library stays usable for smaller calls. Unset or
+ *    not a positive number: no bound beyond the device's memory.
  *
  * Errors
  *  - Every entry point returns NCF_OK (0) or a negative NCF_E_* code; on an
@@ -67,7 +72,7 @@ extern "C" {
 #define NCF_E_INVALID_ARG (-1) /* null pointer, n < 2, K < 0, h <= 0, non-finite input, err <= 0 */
 #define NCF_E_UNSORTED (-2)    /* times not non-decreasing */
 #define NCF_E_DEGENERATE (-3)  /* sd = 0, or lag-0 scale (ACF r(0), CCF scale product) <= 0 */
-#define NCF_E_NOMEM (-4)       /* device or host allocation failed */
+#define NCF_E_NOMEM (-4)       /* device or host allocation failed, or workspace bound reached */
 #define NCF_E_DEVICE (-5)      /* HIP runtime error, or no GPU */
 #define NCF_E_UNSUPPORTED (-6) /* option combination not implemented */
 

@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <map>
@@ -193,6 +194,22 @@ int ensure_queue(Resources& R, unsigned long long** out) {
 std::mutex g_ws_mu;
 std::map<int, Resources> g_res;  // one-shot calls, per device
 
+// Bound on the device workspace arenas of one call or plan, in bytes, from
+// the environment variable NCF_WORKSPACE_LIMIT_MB (MiB, read once; unset or
+// not a positive number: no bound). A call whose arenas would exceed it
+// fails with NCF_E_NOMEM before allocating.
+size_t workspace_limit() {
+    static const size_t lim = [] {
+        const char* e = std::getenv("NCF_WORKSPACE_LIMIT_MB");
+        if (!e || !*e) return (size_t)0;
+        char* end = nullptr;
+        const double v = std::strtod(e, &end);
+        if (end == e || !(v > 0.0) || !(v < 1e12)) return (size_t)0;
+        return (size_t)(v * 1048576.0);
+    }();
+    return lim;
+}
+
 int ensure_ws(Resources& R, int which, size_t bytes, void** out) {
     DevBuf& b = R.ws[which];
     if (R.fixed_dev) {
@@ -216,6 +233,18 @@ int ensure_ws(Resources& R, int which, size_t bytes, void** out) {
             b.cap = 0;
         }
         size_t want = R.exact ? bytes : bytes + bytes / 8 + (1 << 20);
+        if (const size_t lim = workspace_limit()) {
+            size_t others = 0;
+            for (int i = 0; i < 4; ++i)
+                if (i != which) others += R.ws[i].cap;
+            if (others > lim || bytes > lim - others) {
+                set_error("device workspace limit of %zu bytes (NCF_WORKSPACE_LIMIT_MB) "
+                          "reached: %zu bytes held, %zu more asked",
+                          lim, others, bytes);
+                return NCF_E_NOMEM;
+            }
+            want = std::min(want, lim - others);
+        }
         hipError_t e = hipMalloc(&b.ptr, want);
         if (e != hipSuccess) {
             (void)hipGetLastError();
@@ -1207,8 +1236,11 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         const int arrays = 1 + ((W.plans.empty() ? false : ((wflags & WIN_NUMER) != 0)) ? 1 : 0) +
                            (weighted ? (rect ? 2 : 1) : 0);
         const int jmax = 1024;
-        const int budget = 40 * 1024 / 8;  // doubles
-        int cap = (budget - jmax * arrays) / arrays - 8;
+        // LDS per workgroup (doubles): Gaussian items stage the window arrays
+        // and their outer samples; rectangle items stage only the window
+        // arrays and keep a smaller footprint, for more resident workgroups
+        const int budget = (rect ? 24 : 40) * 1024 / 8;
+        int cap = rect ? budget / arrays - 8 : (budget - jmax * arrays) / arrays - 8;
         cap = std::max(256, std::min(4096, cap));
         const int ntw = (int)W.plans.size();
         W.wt.assign(ntw, WinTask{});
@@ -1304,15 +1336,27 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
                 Jt *= 2;
             T.J = (int32_t)Jt;
         }
+        // j-tiles per work item: one item per tile while that leaves the
+        // launch few items; more tiles per item (one partial per group of
+        // tiles) when the launch has many
+        int64_t tiles = 0;
         for (int i = 0; i < ntw; ++i) {
             WinTask& T = W.wt[i];
             T.n_jt = (int32_t)ceil_div(T.n_out, T.J);
+            tiles += (int64_t)T.n_jt * T.n_kt;
+        }
+        const int G = (int)std::max<int64_t>(1, std::min<int64_t>(kWinGroupMax,
+                                                                  tiles / kWinItemsMin));
+        for (int i = 0; i < ntw; ++i) {
+            WinTask& T = W.wt[i];
+            T.G = G;
+            T.n_jg = (int32_t)ceil_div(T.n_jt, G);
             T.item0 = W.nitems;
             W.item0[i] = W.nitems;
             W.wk0[i] = W.total_rows;
             W.r0[i] = W.nred1;
-            W.nitems += (int64_t)T.n_jt * T.n_kt;
-            W.nred1 += (int64_t)T.n_kt * ceil_div(T.n_jt, kWinJc);
+            W.nitems += (int64_t)T.n_jg * T.n_kt;
+            W.nred1 += (int64_t)T.n_kt * ceil_div(T.n_jg, kWinJc);
             W.total_rows += T.K;
         }
         W.item0[ntw] = W.nitems;
@@ -1408,8 +1452,8 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     auto layout2 = [&](Arena& ar) {
         for (int i = 0; i < ntw; ++i) {
             WinTask& T = W1.wt[i];
-            T.part = ar.take<double>((size_t)T.n_jt * T.K * 4);
-            T.part2 = ar.take<double>((size_t)ceil_div(T.n_jt, kWinJc) * T.K * 4);
+            T.part = ar.take<double>((size_t)T.n_jg * T.K * 4);
+            T.part2 = ar.take<double>((size_t)ceil_div(T.n_jg, kWinJc) * T.K * 4);
             T.sums = ar.take<double>((size_t)T.K * 4);
         }
         // per-lag spectral results of all problems are contiguous (one readback)
@@ -1946,8 +1990,8 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         auto layout3 = [&](Arena& ar) {
             for (int i = 0; i < ntw2; ++i) {
                 WinTask& T = W2.wt[i];
-                T.part = ar.take<double>((size_t)T.n_jt * T.K * 4);
-                T.part2 = ar.take<double>((size_t)ceil_div(T.n_jt, kWinJc) * T.K * 4);
+                T.part = ar.take<double>((size_t)T.n_jg * T.K * 4);
+                T.part2 = ar.take<double>((size_t)ceil_div(T.n_jg, kWinJc) * T.K * 4);
                 T.sums = ar.take<double>((size_t)T.K * 4);
             }
         };

@@ -261,12 +261,14 @@ struct WinTask {
     int32_t K;
     int32_t J;           // outer samples per workgroup
     int32_t n_jt, n_kt;  // tiles
+    int32_t G;           // j-tiles per work item (a j-group)
+    int32_t n_jg;        // j-groups: ceil(n_jt / G)
     double h;            // bandwidth
     double W;            // window half-width: 6h (Gaussian) or h (rectangle)
-    double* part;        // [n_jt][K][4] partial sums: C, B, b, count (count as bits);
+    double* part;        // [n_jg][K][4] partial sums: C, B, b, count (count as bits);
                          // weighted rectangle: b holds the count of pairs of two
                          // nonzero weights (the window is empty when it is 0)
-    double* part2;       // [ceil(n_jt / 64)][K][4] first-level sums of part
+    double* part2;       // [ceil(n_jg / 64)][K][4] first-level sums of part
     double* sums;        // [K][4] final sums
     int64_t item0;       // first work item of this task
 };
@@ -278,7 +280,9 @@ int launch_window(const WinTask* d_tasks, const int64_t* d_item0, int ntasks, in
                   double work_units);
 int launch_window_reduce(const WinTask* d_tasks, int ntasks, int64_t total_k, const int64_t* d_k0,
                          const int64_t* d_r0, int64_t nred1, uint32_t flags, hipStream_t st);
-constexpr int kWinJc = 64;  // j-tiles per first-level reduction block
+constexpr int kWinJc = 64;          // j-groups per first-level reduction block
+constexpr int kWinGroupMax = 16;    // most j-tiles per window work item
+constexpr int kWinItemsMin = 16384; // items a launch keeps before grouping j-tiles
 
 // --------------------------------------------------- A2-A6 spectral route
 struct SpreadParams {

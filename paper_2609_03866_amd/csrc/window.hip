@@ -216,100 +216,153 @@ __device__ __forceinline__ void scan_lane(Acc& acc, const V& v, int ja, int jb, 
     }
 }
 
-// Rectangle scan over LDS: window times contiguous (t_i, +inf sentinels),
-// their prefix sums P (and PW) in parallel arrays `dp` doubles further on,
-// outer samples as records (s_j[, vo_j][, wo_j]) of QO doubles. The bounds
-// are LDS addresses into the time array, so a prefix value is read at a
-// fixed distance from the time that its bound stopped at, and counts
-// accumulate as address differences. Same predicates and the same order of
-// the numerator sums as scan_lane.
+// Rectangle scan over LDS. The window times are staged contiguously (then
+// +inf sentinels), their prefix sums P (and PW, PZ) in parallel arrays `dp`
+// doubles further on. The two bounds are LDS addresses into the time array
+// and the times at them are kept in registers, so a bound is read again only
+// after it moves; an outer sample whose window does not move costs two
+// compares. Counts accumulate as address differences and a prefix value is
+// read at a fixed distance from its bound. Same predicates and the same
+// order of the numerator sums as scan_lane. The outer samples (s_j, vo_j,
+// wo_j) are not staged: they come from global memory.
 struct AccR {
     double C, B;
     double nz;  // weighted: pairs of two nonzero weights
     int bytes;  // sum over j of (hi - lo) * 8
 };
 
-constexpr int kRectAdv = 1;  // reads past the staged times land on the 8 sentinels
+struct RectBounds {
+    const double* plo;
+    const double* phi;
+    double tl, th;  // times at the bounds
+};
 
+// bounds of the first outer sample of a run, by binary search
+__device__ __forceinline__ void rect_init(RectBounds& st, const double* win, int len, double c0,
+                                          double W) {
+    const double key = c0 - W;
+    int a = 0, b = len;
+    while (a < b) {
+        const int m = (a + b) >> 1;
+        if (win[m] < key)
+            a = m + 1;
+        else
+            b = m;
+    }
+    st.plo = win + a;
+    const double keyh = c0 + W;
+    b = len;
+    while (a < b) {
+        const int m = (a + b) >> 1;
+        if (win[m] <= keyh)
+            a = m + 1;
+        else
+            b = m;
+    }
+    st.phi = win + a;
+    st.tl = *st.plo;
+    st.th = *st.phi;
+}
+
+// One outer sample: move both bounds to its window, add its terms.
 template <bool NUMER, bool WTD>
-__device__ __forceinline__ void scan_rect(AccR& acc, int o_t, int dp, int o_o, int len, int ja,
-                                          int jb, double delta, double W) {
-    constexpr int QO = 1 + (NUMER ? 1 : 0) + (WTD ? 1 : 0);
+__device__ __forceinline__ void rect_step(AccR& acc, RectBounds& st, int dp, double s, double vo,
+                                          double wo, double delta, double W) {
     constexpr int QW = NUMER ? 2 : 1;  // PW array follows P when both exist
     constexpr int QZ = QW + 1;         // then the nonzero-weight count prefix
-    if (ja >= jb) return;
-    const double* win = g_win_lds + o_t;
-    const double* po = g_win_lds + o_o + QO * ja;
-    const double* const pend = g_win_lds + o_o + QO * jb;
-    double s = po[0];
-    double vo = NUMER ? po[1] : 0.0;
-    double wo = WTD ? po[QO - 1] : 0.0;
-    // initial bounds of the first outer sample by binary search
-    const double c0 = s + delta;
-    int lo, hi;
-    {
-        const double key = c0 - W;
-        int a = 0, b = len;
-        while (a < b) {
-            const int m = (a + b) >> 1;
-            if (win[m] < key)
-                a = m + 1;
-            else
-                b = m;
-        }
-        lo = a;
-        const double keyh = c0 + W;
-        b = len;
-        while (a < b) {
-            const int m = (a + b) >> 1;
-            if (win[m] <= keyh)
-                a = m + 1;
-            else
-                b = m;
-        }
-        hi = a;
+    const double c = s + delta;
+    const double lk = c - W;
+    const double hk = c + W;
+    // both bounds advance in one loop, one sample per round each, on the
+    // lanes where one of them moves (reads past the staged times land on the
+    // sentinels); measured faster than a loop per bound
+    bool a = st.tl < lk, b = st.th <= hk;
+    while (a || b) {
+        st.plo += a;
+        st.phi += b;
+        st.tl = *st.plo;
+        st.th = *st.phi;
+        a = st.tl < lk;
+        b = st.th <= hk;
     }
-    const double* plo = win + lo;
-    const double* phi = win + hi;
-    for (;;) {
-        // next outer record (the staged array has one padding record)
-        const double* pn = po + QO;
-        const double s_n = pn[0];
-        const double vo_n = NUMER ? pn[1] : 0.0;
-        const double wo_n = WTD ? pn[QO - 1] : 0.0;
-        const double c = s + delta;
-        const double lk = c - W;
-        const double hk = c + W;
-        // both bounds advance in one loop, kRectAdv samples per round each
-        // (measured on c2 and c5: 1 beats 2 and 3; separate loops with 2, 3,
-        // 4 or 6 are slower still); a bound that has stopped re-checks its
-        // own position and stays
-        for (;;) {
-            int a = 0, b = 0;
+    acc.bytes += (int)((const char*)st.phi - (const char*)st.plo);
+    if (NUMER) acc.C += vo * (st.phi[dp] - st.plo[dp]);
+    if (WTD) {
+        acc.B += wo * (st.phi[QW * dp] - st.plo[QW * dp]);
+        if (wo != 0.0) acc.nz += st.phi[QZ * dp] - st.plo[QZ * dp];
+    }
+}
+
+typedef const __attribute__((address_space(4))) double* cdp;
+
+__device__ __forceinline__ cdp uniform_ptr(const double* p) {
+    const uint64_t a = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    return (cdp)(((uint64_t)hi << 32) | lo);
+}
+
+// Every lane of the wave walks the same outer run [ja, jb) (one lag per
+// lane): the outer samples come through scalar loads, eight at a time.
+template <bool NUMER, bool WTD>
+__device__ __forceinline__ void scan_rect_wave(AccR& acc, const double* win, int dp, int len,
+                                               int ja, int jb, double delta, double W,
+                                               const double* gs, const double* gvo,
+                                               const double* gwo) {
+    ja = __builtin_amdgcn_readfirstlane(ja);
+    jb = __builtin_amdgcn_readfirstlane(jb);
+    if (ja >= jb) return;
+    const cdp cs = uniform_ptr(gs);
+    const cdp cvo = NUMER ? uniform_ptr(gvo) : cs;
+    const cdp cwo = WTD ? uniform_ptr(gwo) : cs;
+    RectBounds st;
+    rect_init(st, win, len, cs[ja] + delta, W);
+    int j = ja;
+    for (; j + 8 <= jb; j += 8) {
+        double sb[8], vb[8], wb[8];
 #pragma unroll
-            for (int q = 0; q < kRectAdv; ++q) {
-                a += plo[q] < lk;
-                b += phi[q] <= hk;
-            }
-            plo += a;
-            phi += b;
-            if (a < kRectAdv && b < kRectAdv) break;
+        for (int m = 0; m < 8; ++m) {
+            sb[m] = cs[j + m];
+            vb[m] = NUMER ? cvo[j + m] : 0.0;
+            wb[m] = WTD ? cwo[j + m] : 0.0;
         }
-        acc.bytes += (int)((const char*)phi - (const char*)plo);
-        if (NUMER) acc.C += vo * (phi[dp] - plo[dp]);
-        if (WTD) {
-            acc.B += wo * (phi[QW * dp] - plo[QW * dp]);
-            if (wo != 0.0) acc.nz += phi[QZ * dp] - plo[QZ * dp];
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+            rect_step<NUMER, WTD>(acc, st, dp, sb[m], vb[m], wb[m], delta, W);
+    }
+    for (; j < jb; ++j)
+        rect_step<NUMER, WTD>(acc, st, dp, cs[j], NUMER ? cvo[j] : 0.0, WTD ? cwo[j] : 0.0,
+                              delta, W);
+}
+
+// Each lane walks its own outer run (items of few lags): outer samples by
+// vector loads, the next one's in flight while the current one is scanned.
+template <bool NUMER, bool WTD>
+__device__ __forceinline__ void scan_rect_lane(AccR& acc, const double* win, int dp, int len,
+                                               int ja, int jb, double delta, double W,
+                                               gdp gs, gdp gvo, gdp gwo) {
+    if (ja >= jb) return;
+    RectBounds st;
+    rect_init(st, win, len, gs[ja] + delta, W);
+    double s = gs[ja], vo = NUMER ? gvo[ja] : 0.0, wo = WTD ? gwo[ja] : 0.0;
+    for (int j = ja; j < jb; ++j) {
+        double s_n = 0.0, vo_n = 0.0, wo_n = 0.0;
+        if (j + 1 < jb) {
+            s_n = gs[j + 1];
+            if (NUMER) vo_n = gvo[j + 1];
+            if (WTD) wo_n = gwo[j + 1];
         }
-        po = pn;
-        if (po == pend) break;
+        rect_step<NUMER, WTD>(acc, st, dp, s, vo, wo, delta, W);
         s = s_n;
         vo = vo_n;
         wo = wo_n;
     }
 }
 
-// One work item: (task, j-tile, lag-tile) -> partial sums of the tile.
+// One work item: (task, j-group, lag-tile) -> partial sums of the group. A
+// j-group is up to G consecutive j-tiles; the workgroup stages and scans them
+// in order, each lane keeping its sums across the tiles, so one partial per
+// group and lag is written.
 template <uint32_t F>
 __device__ __forceinline__ void window_item(const WinTask* __restrict__ tasks,
                                             const int64_t* __restrict__ item0, int ntasks,
@@ -330,84 +383,12 @@ __device__ __forceinline__ void window_item(const WinTask* __restrict__ tasks,
     const int ti = ntasks == 1 ? 0 : (int)wave_search<int64_t>(item0, ntasks, item, true) - 1;
     const WinTask& T = tasks[ti];
     const int64_t local = item - T.item0;
-    const int jt = (int)(local / T.n_kt);
+    const int jg = (int)(local / T.n_kt);
     const int kt = (int)(local % T.n_kt);
-    const int64_t j0 = (int64_t)jt * T.J;
-    const int64_t j1 = min(j0 + (int64_t)T.J, T.n_out);
+    const int jt_end = min(T.n_jt, (jg + 1) * T.G);
     const int k0 = kt * 64;
     const int nk = min(64, T.K - k0);
     const double W = T.W;
-
-    if (wave == 0) {
-        const double dmin = T.delta[k0];
-        const double dmax = T.delta[k0 + nk - 1];
-        const double lo_key = (T.s[j0] + dmin) - W;
-        const double hi_key = (T.s[j1 - 1] + dmax) + W;
-        int64_t tlo = wave_search<double>(T.t, T.n_win, lo_key, false);
-        int64_t thi = wave_search<double>(T.t, T.n_win, hi_key, RECT);
-        if (lane == 0) {
-            sh_rng[0] = tlo;
-            sh_rng[1] = thi;
-        }
-    }
-    __syncthreads();
-    const int64_t tlo = sh_rng[0];
-    const int64_t thi = sh_rng[1];
-    const int len = (int)(thi - tlo);
-    const int nj = (int)(j1 - j0);
-    const bool fits = (thi - tlo) <= cap && nj <= jmax;
-
-    // LDS carve-up (offsets in doubles)
-    const int o_t = 0;
-    const int o_a1 = o_t + cap + 8;
-    const int o_a2 = o_a1 + (HAS_A1 ? cap + 8 : 0);
-    const int o_s = o_a2 + (HAS_A2 ? cap + 8 : 0);
-    const int o_vo = o_s + jmax;
-    const int o_wo = o_vo + (NUMER ? jmax : 0);
-
-    const double* A1g = RECT ? T.pv : T.v;
-    const double* A2g = RECT ? T.pw : T.w;
-    const int a_len = RECT ? len + 1 : len;  // prefix arrays need the entry at hi
-    // rectangle: times, prefix arrays (each cap + 8 long: values, weights and
-    // the nonzero-weight count), then outer records (s[, vo][, wo])
-    constexpr int QW = NUMER ? 2 : 1;
-    constexpr int QR = 1 + (NUMER ? 1 : 0) + (WTD ? 2 : 0);
-    constexpr int QRO = 1 + (NUMER ? 1 : 0) + (WTD ? 1 : 0);
-    const int o_rw = 0;
-    const int dp = cap + 8;
-    const int o_ro = QR * (cap + 8);
-    const gdp gt = (gdp)T.t, gs = (gdp)T.s, gvo = (gdp)T.vo, gwo = (gdp)T.wo;
-    const gdp ga1 = (gdp)A1g, ga2 = (gdp)A2g, ga3 = (gdp)T.pz;
-    if (RECT && fits) {
-        for (int i = tid; i < len + 8; i += kThreads) {
-            double* r = g_win_lds + o_rw + i;
-            r[0] = i < len ? gt[tlo + i] : kInf;
-            if (NUMER) r[dp] = i <= len ? ga1[tlo + i] : 0.0;
-            if (WTD) {
-                r[QW * dp] = i <= len ? ga2[tlo + i] : 0.0;
-                r[(QW + 1) * dp] = i <= len ? ga3[tlo + i] : 0.0;
-            }
-        }
-        for (int i = tid; i <= nj; i += kThreads) {
-            double* r = g_win_lds + o_ro + QRO * i;
-            r[0] = i < nj ? gs[j0 + i] : 0.0;
-            if (NUMER) r[1] = i < nj ? gvo[j0 + i] : 0.0;
-            if (WTD) r[QRO - 1] = i < nj ? gwo[j0 + i] : 0.0;
-        }
-    } else if (fits) {
-        for (int i = tid; i < len + 8; i += kThreads)
-            g_win_lds[o_t + i] = i < len ? gt[tlo + i] : kInf;
-        if (HAS_A1)
-            for (int i = tid; i < a_len; i += kThreads) g_win_lds[o_a1 + i] = ga1[tlo + i];
-        if (HAS_A2)
-            for (int i = tid; i < a_len; i += kThreads) g_win_lds[o_a2 + i] = ga2[tlo + i];
-        for (int i = tid; i < nj; i += kThreads) {
-            g_win_lds[o_s + i] = gs[j0 + i];
-            if (NUMER) g_win_lds[o_vo + i] = gvo[j0 + i];
-            if (WTD) g_win_lds[o_wo + i] = gwo[j0 + i];
-        }
-    }
-    __syncthreads();
 
     // lane -> (lag, j-stream)
     int KW = 1;
@@ -418,33 +399,107 @@ __device__ __forceinline__ void window_item(const WinTask* __restrict__ tasks,
     const bool active = kl < nk;
     const int nseg = 4 * streams;
     const int seg = wave * streams + stream;
-    const int ja = (int)((int64_t)nj * seg / nseg);
-    const int jb = (int)((int64_t)nj * (seg + 1) / nseg);
     const double delta = active ? T.delta[k0 + kl] : 0.0;
     const double inv_h = 1.0 / T.h;
 
+    // LDS carve-up (offsets in doubles)
+    const int o_t = 0;
+    const int o_a1 = o_t + cap + 8;
+    const int o_a2 = o_a1 + (HAS_A1 ? cap + 8 : 0);
+    const int o_s = o_a2 + (HAS_A2 ? cap + 8 : 0);
+    const int o_vo = o_s + jmax;
+    const int o_wo = o_vo + (NUMER ? jmax : 0);
+    const double* A1g = RECT ? T.pv : T.v;
+    const double* A2g = RECT ? T.pw : T.w;
+    // rectangle: times, then the prefix arrays (each cap + 8 long: values,
+    // weights and the nonzero-weight count); the outer samples stay in global
+    // memory
+    constexpr int QW = NUMER ? 2 : 1;
+    const int dp = cap + 8;
+    const gdp gt = (gdp)T.t, gs = (gdp)T.s, gvo = (gdp)T.vo, gwo = (gdp)T.wo;
+    const gdp ga1 = (gdp)A1g, ga2 = (gdp)A2g, ga3 = (gdp)T.pz;
+
     Acc acc = {0.0, 0.0, 0.0, 0};
-    if (RECT && fits) {
-        AccR ar = {0.0, 0.0, 0.0, 0};
-        if (active) scan_rect<NUMER, WTD>(ar, o_rw, dp, o_ro, len, ja, jb, delta, W);
-        acc.C = ar.C;
-        acc.B = ar.B;
-        acc.b = ar.nz;
-        acc.n = ar.bytes / (int)sizeof(double);
-    } else if (active) {
-        if (fits) {
-            LdsView v{o_t, o_a1, o_a2, o_s, o_vo, o_wo, len};
-            scan_lane<F>(acc, v, ja, jb, delta, W, inv_h);
-        } else {
-            GlbView v{(gdp)(T.t + tlo),
-                      HAS_A1 ? (gdp)(A1g + tlo) : nullptr,
-                      HAS_A2 ? (gdp)(A2g + tlo) : nullptr,
-                      (RECT && WTD) ? (gdp)(T.pz + tlo) : nullptr,
-                      (gdp)(T.s + j0),
-                      NUMER ? (gdp)(T.vo + j0) : nullptr,
-                      WTD ? (gdp)(T.wo + j0) : nullptr,
-                      len};
-            scan_lane<F>(acc, v, ja, jb, delta, W, inv_h);
+    for (int jt = jg * T.G; jt < jt_end; ++jt) {
+        const int64_t j0 = (int64_t)jt * T.J;
+        const int64_t j1 = min(j0 + (int64_t)T.J, T.n_out);
+        if (wave == 0) {
+            const double dmin = T.delta[k0];
+            const double dmax = T.delta[k0 + nk - 1];
+            const double lo_key = (T.s[j0] + dmin) - W;
+            const double hi_key = (T.s[j1 - 1] + dmax) + W;
+            int64_t tlo = wave_search<double>(T.t, T.n_win, lo_key, false);
+            int64_t thi = wave_search<double>(T.t, T.n_win, hi_key, RECT);
+            if (lane == 0) {
+                sh_rng[0] = tlo;
+                sh_rng[1] = thi;
+            }
+        }
+        __syncthreads();  // also: every wave is done with the previous tile
+        const int64_t tlo = sh_rng[0];
+        const int64_t thi = sh_rng[1];
+        const int len = (int)(thi - tlo);
+        const int nj = (int)(j1 - j0);
+        const bool fits = (thi - tlo) <= cap && (RECT || nj <= jmax);
+        const int a_len = RECT ? len + 1 : len;  // prefix arrays need the entry at hi
+        if (RECT && fits) {
+            for (int i = tid; i < len + 8; i += kThreads) {
+                double* r = g_win_lds + i;
+                r[0] = i < len ? gt[tlo + i] : kInf;
+                if (NUMER) r[dp] = i <= len ? ga1[tlo + i] : 0.0;
+                if (WTD) {
+                    r[QW * dp] = i <= len ? ga2[tlo + i] : 0.0;
+                    r[(QW + 1) * dp] = i <= len ? ga3[tlo + i] : 0.0;
+                }
+            }
+        } else if (fits) {
+            for (int i = tid; i < len + 8; i += kThreads)
+                g_win_lds[o_t + i] = i < len ? gt[tlo + i] : kInf;
+            if (HAS_A1)
+                for (int i = tid; i < a_len; i += kThreads) g_win_lds[o_a1 + i] = ga1[tlo + i];
+            if (HAS_A2)
+                for (int i = tid; i < a_len; i += kThreads) g_win_lds[o_a2 + i] = ga2[tlo + i];
+            for (int i = tid; i < nj; i += kThreads) {
+                g_win_lds[o_s + i] = gs[j0 + i];
+                if (NUMER) g_win_lds[o_vo + i] = gvo[j0 + i];
+                if (WTD) g_win_lds[o_wo + i] = gwo[j0 + i];
+            }
+        }
+        __syncthreads();
+
+        const int ja = (int)((int64_t)nj * seg / nseg);
+        const int jb = (int)((int64_t)nj * (seg + 1) / nseg);
+        if (RECT && fits) {
+            AccR ar = {0.0, 0.0, 0.0, 0};
+            if (streams == 1) {  // one outer run per wave
+                if (active)
+                    scan_rect_wave<NUMER, WTD>(ar, g_win_lds, dp, len, ja, jb, delta, W,
+                                               T.s + j0, NUMER ? T.vo + j0 : nullptr,
+                                               WTD ? T.wo + j0 : nullptr);
+            } else if (active) {
+                scan_rect_lane<NUMER, WTD>(ar, g_win_lds, dp, len, ja, jb, delta, W, gs + j0,
+                                           NUMER ? gvo + j0 : nullptr,
+                                           WTD ? gwo + j0 : nullptr);
+            }
+            acc.C += ar.C;
+            acc.B += ar.B;
+            acc.b += ar.nz;
+            acc.n += ar.bytes / (int)sizeof(double);
+        } else if (active) {
+            if (fits) {
+                LdsView v{o_t, o_a1, o_a2, o_s, o_vo, o_wo, len};
+                scan_lane<F>(acc, v, ja, jb, delta, W, inv_h);
+            } else {
+                GlbView v{(gdp)(T.t + tlo),
+                          HAS_A1 ? (gdp)(A1g + tlo) : nullptr,
+                          HAS_A2 ? (gdp)(A2g + tlo) : nullptr,
+                          (RECT && WTD) ? (gdp)(T.pz + tlo) : nullptr,
+                          (gdp)(T.s + j0),
+                          NUMER ? (gdp)(T.vo + j0) : nullptr,
+                          WTD ? (gdp)(T.wo + j0) : nullptr,
+                          len};
+                scan_lane<F>(acc, v, ja, jb, delta, W, inv_h);
+            }
         }
     }
     __syncthreads();  // staging area is reused for the reduction
@@ -465,7 +520,7 @@ __device__ __forceinline__ void window_item(const WinTask* __restrict__ tasks,
                 b += Red[src + 2];
                 n += __double_as_longlong(Red[src + 3]);
             }
-        double* out = T.part + ((int64_t)jt * T.K + k0 + tid) * 4;
+        double* out = T.part + ((int64_t)jg * T.K + k0 + tid) * 4;
         out[0] = C;
         out[1] = B;
         out[2] = b;
@@ -521,7 +576,7 @@ k_window_reduce1(const WinTask* __restrict__ tasks, const int64_t* __restrict__ 
     const int ti = (int)wave_search<int64_t>(r0s, ntasks, item, true) - 1;
     const WinTask& T = tasks[ti];
     const int64_t local = item - r0s[ti];
-    const int n_jc = (T.n_jt + kJc - 1) / kJc;
+    const int n_jc = (T.n_jg + kJc - 1) / kJc;
     const int kt = (int)(local / n_jc);
     const int jc = (int)(local % n_jc);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -529,7 +584,7 @@ k_window_reduce1(const WinTask* __restrict__ tasks, const int64_t* __restrict__ 
     double C = 0.0, B = 0.0, b = 0.0;
     long long n = 0;
     if (k < T.K) {
-        const int jt_end = min(T.n_jt, (jc + 1) * kJc);
+        const int jt_end = min(T.n_jg, (jc + 1) * kJc);
         for (int jt = jc * kJc + wave; jt < jt_end; jt += 4) {
             const double* p = T.part + ((int64_t)jt * T.K + k) * 4;
             C += p[0];
@@ -576,7 +631,7 @@ __global__ void k_window_reduce(const WinTask* __restrict__ tasks, int ntasks,
     }
     const WinTask& T = tasks[lo];
     const int k = (int)(g - k0s[lo]);
-    const int n_jc = (T.n_jt + kJc - 1) / kJc;
+    const int n_jc = (T.n_jg + kJc - 1) / kJc;
     double C = 0.0, B = 0.0, b = 0.0;
     long long n = 0;
     for (int jc = 0; jc < n_jc; ++jc) {
@@ -631,7 +686,7 @@ int launch_window_t(const WinTask* d_tasks, const int64_t* d_item0, int ntasks, 
     constexpr bool NUMER = (F & WIN_NUMER) != 0;
     constexpr bool WTD = (F & WIN_WEIGHTED) != 0;
     size_t stage = (size_t)(cap + 8) * (1 + (NUMER ? 1 : 0) + (WTD ? (RECT ? 2 : 1) : 0)) +
-                   (size_t)(jmax + 2) * (1 + (NUMER ? 1 : 0) + (WTD ? 1 : 0));
+                   (RECT ? 0 : (size_t)(jmax + 2) * (1 + (NUMER ? 1 : 0) + (WTD ? 1 : 0)));
     size_t red = 4 * kThreads;
     size_t bytes = (stage > red ? stage : red) * sizeof(double);
     (void)RECT;
