@@ -409,6 +409,11 @@ typedef struct {
     int32_t window_tile_scale; /* log2 factor on the outer samples per workgroup */
     int32_t window_queue;      /* 1: work-queue dispatch of the window scans */
     double replay_ms;          /* autotuned: measured time of one execution */
+    int32_t lattice_grids;     /* grids whose lags are read off the folded spectrum (lags on a
+                                  lattice: Sec. "The Non-Uniform Fast Fourier Transform",
+                                  type-2 step at equispaced points) */
+    int32_t lattice_off;       /* 1: the autotuner chose inverse transform + interpolation
+                                  although the lags sit on a lattice */
 } ncf_plan_info_t;
 
 int ncf_plan_info(const ncf_plan_t* plan, ncf_plan_info_t* info);

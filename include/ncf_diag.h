@@ -47,6 +47,20 @@ int ncf_diag_type1(int64_t n, const double* t, const double* v, double t_ref, do
  * truncation half-width W (cells). */
 int ncf_diag_spread_params(double sigma, double eps, double* out);
 
+/* Grid geometry the planner picks for one Gaussian spectral problem (host
+ * only; no device is needed), Sec. "From kernel-weighted estimators to
+ * NUFFT" with the period and mode count of the type-1 / type-2 steps
+ * (eq. nufft_type1, nufft_type2). Samples span [tmin, tmax]; `lags` holds
+ * the K evaluation lags (with acf != 0 lag 0 is evaluated too); bandwidth h;
+ * precision NCF_MIXED or NCF_FP64; `lattice` != 0 allows the lag-lattice
+ * evaluation (lags read off the spectrum folded modulo P) where the lags sit
+ * on a lattice. Outputs: out_f[0] = period L, out_f[1] = spreading width s
+ * (cells); out_i[0] = cells N, out_i[1] = retained modes M, out_i[2] = P
+ * (0: inverse transform and interpolation). Returns NCF_E_INVALID_ARG for
+ * bad arguments, NCF_E_UNSUPPORTED when no grid of at most 2^31 cells fits. */
+int ncf_diag_grid(double tmin, double tmax, int64_t K, const double* lags, int acf, double h,
+                  int precision, int lattice, double* out_f, int64_t* out_i);
+
 /* ------------------------------------------------------------ profiling */
 
 /* Enable (1) or disable (0) per-kernel HIP-event timing on the stream each

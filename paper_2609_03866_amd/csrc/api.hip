@@ -367,9 +367,11 @@ struct Tune {
     int jscale = 0;      // window tiles (outer samples per workgroup) times 2^jscale
     bool queue = false;  // window scans by work-queue dispatch
     bool no_mid = false; // separate last FFT pass, product and first inverse pass
+    bool eval_interp = false;  // lags by inverse transform and interpolation even on a lattice
 };
 
 struct Job {
+    double lag_unit = 0.0;  // lattice unit of the evaluation lags (0: not on a lattice)
     bool ccf = false;
     int64_t nprob = 0;
     int kern = NCF_GAUSSIAN;
@@ -406,6 +408,7 @@ struct Job {
     // filled by run_job: what the call planned
     int64_t info_grid_cells = 0, info_window_items = 0;
     int info_grids = 0, info_window_launches = 0;
+    int info_fold_grids = 0;  // grids read off a lag lattice
 };
 
 int check_lags(const Job& J) {
@@ -432,16 +435,49 @@ bool use_spectral(const Job& J) {
 }
 
 int64_t pow2_at_least(double v) {
-    int64_t p = 1;
-    while ((double)p < v) p <<= 1;
-    return p;
+    if (!(v > 1.0)) return 1;
+    int e = 0;
+    const double m = std::frexp(v, &e);  // v = m 2^e, m in [0.5, 1)
+    const int k = m == 0.5 ? e - 1 : e;
+    return k >= 62 ? (int64_t)1 << 62 : (int64_t)1 << k;
 }
 
 // One spectral problem's geometry.
 struct SpecGeom {
     double L, t_ref, s, W;
     int64_t N, M;
+    int64_t P = 0;  // lag-lattice evaluation: L = P lattice units (0: interpolation)
 };
+
+// A unit D > 0 of which every evaluation lag (and 0) is a whole multiple, to
+// 1e-9 relative, with fewer than 2^30 units to the farthest lag: the finest
+// of gap / q, q = 1..8, over the smallest gap between distinct lags. 0 when
+// the lags are not on such a lattice (then they are read by interpolation).
+double lag_lattice_unit(const std::vector<double>& lags, bool with_zero) {
+    std::vector<double> v(lags);
+    if (with_zero) v.push_back(0.0);
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    if (v.size() < 2) return 0.0;
+    double gap = HUGE_VAL;
+    for (size_t i = 1; i < v.size(); ++i) gap = std::min(gap, v[i] - v[i - 1]);
+    if (!(gap > 0.0) || !std::isfinite(gap)) return 0.0;
+    const double far = std::max(std::fabs(v.front()), std::fabs(v.back()));
+    for (int q = 1; q <= 8; ++q) {
+        const double D = gap / q;
+        if (far / D >= 1073741824.0) break;
+        bool ok = true;
+        for (double x : v) {
+            const double u = x / D;
+            if (std::fabs(u - std::nearbyint(u)) > 1e-9 * std::max(1.0, std::fabs(u))) {
+                ok = false;
+                break;
+            }
+        }
+        if (ok) return D;
+    }
+    return 0.0;
+}
 
 int plan_grid(const Job& J, double tmin, double tmax, double maxlag, double h, SpecGeom* g) {
     const bool fp64 = J.opt.precision == NCF_FP64;
@@ -457,27 +493,38 @@ int plan_grid(const Job& J, double tmin, double tmax, double maxlag, double h, S
         Wh = h;
         fcut = 16.0 / h;
     }
-    double L = span + maxlag + Wh;
-    for (int iter = 0; iter < 8; ++iter) {
+    // modes, cells and spreading kernel for period L; the evaluated factor
+    // phihat / Psi^q (q = 3 with interpolation at the lags, 2 on a lag
+    // lattice) must decay with |m|
+    auto cells = [&](double L, double q, double sig, int64_t* Nout, int64_t* Mout,
+                     SpreadParams* spo) {
         int64_t M = (int64_t)std::ceil(fcut * L);
         int64_t N;
         if (J.opt.grid_size > 0) {
             N = J.opt.grid_size;
-            M = std::min<int64_t>(M, (int64_t)std::floor((N / sig_min - 1.0) / 2.0));
+            M = std::min<int64_t>(M, (int64_t)std::floor((N / sig - 1.0) / 2.0));
         } else {
-            N = std::max<int64_t>(4096, pow2_at_least(sig_min * (2.0 * M + 1.0)));
+            N = std::max<int64_t>(4096, pow2_at_least(sig * (2.0 * M + 1.0)));
         }
         SpreadParams sp{};
         for (;;) {
             const double sigma = (double)N / (2.0 * M + 1.0);
             sp = spread_params(sigma, eps_s);
             const double h_cells = h * (double)N / L;
-            // the folded factor phihat / Psi^3 must decay with |m|
-            if (J.kern != NCF_GAUSSIAN || h_cells >= std::sqrt(3.0) * sp.s ||
-                J.opt.grid_size > 0)
+            if (J.kern != NCF_GAUSSIAN || h_cells >= std::sqrt(q) * sp.s || J.opt.grid_size > 0)
                 break;
             N *= 2;
         }
+        *Nout = N;
+        *Mout = M;
+        *spo = sp;
+    };
+    double L = span + maxlag + Wh;
+    bool done = false;
+    for (int iter = 0; iter < 8 && !done; ++iter) {
+        int64_t M, N;
+        SpreadParams sp;
+        cells(L, 3.0, sig_min, &N, &M, &sp);
         if (N > (1LL << 31)) {
             set_error("spectral grid of %lld cells exceeds the supported maximum (2^31)",
                       (long long)N);
@@ -492,12 +539,65 @@ int plan_grid(const Job& J, double tmin, double tmax, double maxlag, double h, S
             g->s = sp.s;
             g->W = sp.W;
             g->t_ref = tmin - margin;
-            return NCF_OK;
+            g->P = 0;
+            done = true;
+        } else {
+            L = span + 2.0 * margin + cell;
         }
-        L = span + 2.0 * margin + cell;
     }
-    set_error("grid planning did not converge");
-    return NCF_E_UNSUPPORTED;
+    if (!done) {
+        set_error("grid planning did not converge");
+        return NCF_E_UNSUPPORTED;
+    }
+    // Lag lattice of unit D: with L = P D / d for a
+    // whole d, every lag is a whole number of units L / P and the lag sum is
+    // a P-point DFT of the spectrum folded modulo P. P = 2^j >= d Lmin / D,
+    // so L lies in [Lmin, 2 Lmin); over d = 1..32 the geometry with the
+    // fewest cells wins (then the smallest P), taken when it has no more
+    // cells than the interpolating one. P must divide N with 2 <= N / P <= 256
+    // (16 to 2048 folded entries per 4096-position tile).
+    // (Lmin: the interpolating period before its margin adjustment.)
+    if (J.lag_unit > 0.0 && J.kern == NCF_GAUSSIAN && J.opt.grid_size <= 0) {
+        const double Lmin = span + maxlag + Wh;
+        // L = P D / d lies in [Lmin, 2 Lmin), so the cell count at the
+        // minimum oversampling takes at most two values, N_a (that of Lmin)
+        // and 2 N_a. For a target count Nt the admissible periods are
+        // L <= L_t (the longest whose modes fit Nt); the smallest P among them
+        // comes from the smallest d that has a power of two in
+        // [d Lmin / D, d L_t / D] (P grows with d). The lattice period may
+        // take the oversampling down to 1.25 (a wider spreading kernel) where
+        // the interpolating grid keeps the default 1.5.
+        const double sig_fold = std::min(sig_min, 1.25);
+        const int64_t Na = std::max<int64_t>(
+            4096, pow2_at_least(sig_fold * (2.0 * std::ceil(fcut * Lmin) + 1.0)));
+        for (int64_t Nt = Na; Nt <= g->N && Nt <= Na * 2; Nt *= 2) {
+            const double Lt = std::floor((Nt / sig_fold - 1.0) / 2.0) / fcut;
+            int64_t P = 0;
+            double Lf = 0.0;
+            for (int d = 1; d <= 32; ++d) {
+                const double u = J.lag_unit / d;
+                const int64_t Pd = pow2_at_least(Lmin / u);
+                if (2 * Pd > Nt) break;        // larger d only makes P larger
+                if (Nt / Pd > 256) continue;   // too few folded entries per tile
+                if ((double)Pd * u <= Lt) {
+                    P = Pd;
+                    Lf = (double)Pd * u;
+                    break;
+                }
+            }
+            if (P == 0) continue;
+            int64_t M, N;
+            SpreadParams sp;
+            cells(Lf, 2.0, sig_fold, &N, &M, &sp);
+            if (N > g->N || 2 * P > N || N / P > 256) continue;
+            const double cell = Lf / (double)N;
+            const double margin = (sp.W + 2.0) * cell;
+            if (span + 2.0 * margin > Lf) continue;
+            *g = SpecGeom{Lf, tmin - margin, sp.s, sp.W, N, M, P};
+            break;
+        }
+    }
+    return NCF_OK;
 }
 
 // Per-problem statuses of a finished call (h_fstat: device statuses read
@@ -1126,6 +1226,17 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     // 30 us for its extra launches and the fallback round trip.
     // grid geometry per problem, planned once (the route choice and the
     // spectral planning below both use it)
+    // Lag lattice: Gaussian spectral problems through the fused kernel (the
+    // fold needs the product tiles in LDS) read lags that sit on a lattice off
+    // a folded spectrum instead of an inverse transform and interpolation.
+    {
+        const bool sb = spectral && !rect && J.opt.method == NCF_AUTO;
+        const bool su = sb && weighted && !J.no_b;
+        J.lag_unit = 0.0;
+        if (spectral && J.kern == NCF_GAUSSIAN && J.opt.grid_size <= 0 && !J.tune.no_mid &&
+            !J.tune.eval_interp && mid_supported(J.ccf, sb, su, fp64))
+            J.lag_unit = lag_lattice_unit(J.lags, !J.ccf);
+    }
     std::vector<SpecGeom> geom((size_t)J.nprob);
     std::vector<char> have_geom((size_t)J.nprob, 0);
     if (spectral && J.opt.method == NCF_AUTO && J.kern == NCF_GAUSSIAN &&
@@ -1155,7 +1266,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
                 break;
             }
             have_geom[p] = 1;
-            spec_s += 11.0 * (double)g.N * csz_b * (J.ccf ? 2.0 : 1.0) / 4e12 +
+            spec_s += (g.P > 0 ? 7.0 : 11.0) * (double)g.N * csz_b * (J.ccf ? 2.0 : 1.0) / 4e12 +
                       (n0 + (J.ccf ? n1 : 0.0)) * 12.0 / 4e12;
         }
         if (direct_s < spec_s) spectral = false;
@@ -1427,7 +1538,11 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     const int Keval = (int)(J.ccf ? K : K + 1);
     J.info_grids = nts;
     J.info_grid_cells = 0;
-    for (auto& sp : splans) J.info_grid_cells += sp.g.N;
+    J.info_fold_grids = 0;
+    for (auto& sp : splans) {
+        J.info_grid_cells += sp.g.N;
+        J.info_fold_grids += sp.g.P > 0 ? 1 : 0;
+    }
     J.info_window_items = W1.nitems;
     J.info_window_launches = ntw > 0 ? 1 : 0;
     const size_t csz = fp64 ? 16 : 8;
@@ -1438,7 +1553,9 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     const int nfwd = 1 + (two_grids ? 1 : 0) + (three_grids ? 1 : 0);
 
     // ------------------------------------------------ phase 2 device workspace
-    std::vector<void*> grids(nts), gridbs(nts, nullptr), gridcs(nts, nullptr);
+    std::vector<void*> grids(nts), gridbs(nts, nullptr), gridcs(nts, nullptr),
+        ybufs(nts, nullptr);
+    std::vector<double*> fparts(nts, nullptr);
     std::vector<double*> numer(nts), bspec(nts, nullptr), spart(nts, nullptr),
         bunw(nts, nullptr);
     int64_t ntiles_all = 0;
@@ -1468,6 +1585,11 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             grids[i] = ar.take<char>((size_t)splans[i].g.N * csz);
             if (two_grids) gridbs[i] = ar.take<char>((size_t)splans[i].g.N * csz);
             if (three_grids) gridcs[i] = ar.take<char>((size_t)splans[i].g.N * csz);
+            if (splans[i].g.P > 0) {
+                ybufs[i] = ar.take<char>((size_t)splans[i].g.P * csz);
+                const int64_t nmc = ceil_div(splans[i].g.N / 4096, kFoldTiles);
+                if (nmc > 1) fparts[i] = ar.take<double>((size_t)nmc * std::max(Keval, 1) * 2);
+            }
             numer[i] = numer_all + (size_t)i * std::max(Keval, 1);
             if (spec_b) bspec[i] = bspec_all + (size_t)i * std::max(Keval, 1);
             if (spec_unw) bunw[i] = bunw_all + (size_t)i * std::max(Keval, 1);
@@ -1496,7 +1618,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         int64_t *item0, *wk0, *r0;
         double* dl;
         SpecTask* st;
-        int64_t *tile0, *pos0, *sk0, *pair0;
+        int64_t *tile0, *pos0, *sk0, *pair0, *fe0;
         int32_t* smap;
         int32_t* rinfo;
         double* ev;
@@ -1562,6 +1684,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         dT.pos0 = tb.take<int64_t>(nts + 1, &hT.pos0);
         dT.pair0 = tb.take<int64_t>(nts + 1, &hT.pair0);
         dT.sk0 = tb.take<int64_t>(nts + 1, &hT.sk0);
+        dT.fe0 = tb.take<int64_t>(nts + 1, &hT.fe0);
         dT.smap = tb.take<int32_t>(nsd, &hT.smap);
         dT.rinfo = tb.take<int32_t>(6 * (size_t)nts, &hT.rinfo);
         dT.ev = tb.take<double>(Keval, &hT.ev);
@@ -1596,7 +1719,9 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
 
     // spectral tables
     std::map<int64_t, FftPlan> plans;
-    int64_t total_pos = 0, ntiles = 0, total_samp = 0, total_pairs = 0;
+    int64_t total_pos = 0, ntiles = 0, total_samp = 0, total_pairs = 0, fold_blocks = 0,
+            mid_out = 0;
+    bool fold_chunks = false;  // a lattice task sums its tiles in several chunks
     for (int q = 0; q < nsd; ++q) hT.smap[q] = -1;
     double spread_bytes = 0.0;
     std::vector<std::pair<int, int>> groups;  // (first task, count) per grid size
@@ -1643,6 +1768,16 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         if (J.ccf) hT.smap[J.set[1].sd0 + P.prob] = 2 * i + 1;
         T.lags = dT.ev;
         T.K_eval = Keval;
+        T.P = P.g.P;
+        T.ybuf = ybufs[i];
+        T.fpart = fparts[i];
+        T.nmc = T.P > 0 ? (int32_t)ceil_div(T.N / 4096, kFoldTiles) : 0;
+        fold_chunks |= T.nmc > 1;
+        if (T.P > 0) {
+            int lg = 0;
+            while ((T.N >> lg) > T.P) ++lg;  // N / P = 2^lg
+            T.lgP2 = 12 - lg;
+        }
         T.numer = numer[i];
         T.scale_part = spart[i];
         T.pos0 = total_pos;
@@ -1653,6 +1788,9 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         hT.pair0[i] = total_pairs;
         total_pairs += mid_pairs(T.N);
         hT.sk0[i] = (int64_t)i * Keval;
+        hT.fe0[i] = fold_blocks;
+        if (T.P > 0) fold_blocks += ceil_div(Keval, kFoldLags) * T.nmc;
+        mid_out += T.P > 0 ? T.P : T.N;
         if (i == 0 || splans[i].g.N != splans[i - 1].g.N)
             groups.push_back({i, 1});
         else
@@ -1699,12 +1837,16 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         }
         // inverse table: per size group, its grids then (weighted with b) the
         // b spectra in gridb
+        // (grids read off a lag lattice have no inverse transform)
         int oi = 0;
         for (auto& gq : groups) {
-            inv_groups.push_back({oi, gq.second * (spec_unw ? 2 : 1)});
-            for (int i = gq.first; i < gq.first + gq.second; ++i) hT.ginv[oi++] = grids[i];
+            const int o0 = oi;
+            for (int i = gq.first; i < gq.first + gq.second; ++i)
+                if (splans[i].g.P == 0) hT.ginv[oi++] = grids[i];
             if (spec_unw)
-                for (int i = gq.first; i < gq.first + gq.second; ++i) hT.ginv[oi++] = gridbs[i];
+                for (int i = gq.first; i < gq.first + gq.second; ++i)
+                    if (splans[i].g.P == 0) hT.ginv[oi++] = gridbs[i];
+            inv_groups.push_back({o0, oi - o0});
         }
     }
     if (nts > 0) {
@@ -1712,6 +1854,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         hT.pos0[nts] = total_pos;
         hT.pair0[nts] = total_pairs;
         hT.sk0[nts] = (int64_t)nts * Keval;
+        hT.fe0[nts] = fold_blocks;
         for (int64_t k = 0; k < K; ++k) hT.ev[k] = J.lags[k];
         if (!J.ccf) hT.ev[K] = 0.0;
     }
@@ -1877,7 +2020,9 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             const int64_t* pair0 = dT.pair0;
             const int64_t npairs = total_pairs;
             const void* wsmall = plans.begin()->second.small;
-            const double mbytes = (double)(nfwd + 1) * total_pos * csz;
+            // reads every grid it transforms, writes the product grids (or
+            // the folded spectra of the grids on a lag lattice)
+            const double mbytes = ((double)nfwd * total_pos + (double)mid_out) * csz;
             NCF_TRY(emit(J, [=](hipStream_t s) {
                 return launch_mid(stk, pair0, nts, npairs, rinfo, wsmall, ccf, spec_b, fp64, s,
                                   mbytes);
@@ -1892,11 +2037,23 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             const FftPlan fp = plans[splans[groups[q].first].g.N];
             void* const* gp = dT.ginv + inv_groups[q].first;
             const int cnt = inv_groups[q].second;
+            if (cnt == 0) continue;  // every grid of the size is on a lag lattice
             NCF_TRY(emit(J, [=](hipStream_t s) {
                 return fft_exec(fp, gp, cnt, -1, fp64, s, fuse);
             }));
         }
-        NCF_TRY(emit(J, [=](hipStream_t s) { return launch_interp(stk, nts, sk0, nkeval, fp64, s); }));
+        if (J.info_fold_grids < nts)
+            NCF_TRY(emit(J, [=](hipStream_t s) {
+                return launch_interp(stk, nts, sk0, nkeval, fp64, s);
+            }));
+        if (fold_blocks > 0) {
+            const int64_t* fe0 = dT.fe0;
+            const int64_t nfb = fold_blocks;
+            const bool fch = fold_chunks;
+            NCF_TRY(emit(J, [=](hipStream_t s) {
+                return launch_fold_eval(stk, nts, fe0, nfb, sk0, nkeval, fch, fp64, s);
+            }));
+        }
     }
 
     // ------------------------------------------------ direct fallback (spectral b)
@@ -2657,7 +2814,7 @@ struct ncf_plan_s {
     std::vector<int32_t> hstatus;          // host statuses (host-pointer plans)
     // what was planned, and how (ncf_plan_info)
     ncf::Tune tune;
-    int grids = 0, window_launches = 0;
+    int grids = 0, window_launches = 0, fold_grids = 0;
     int64_t grid_cells = 0, window_items = 0;
     int autotuned = 0, candidates = 0;
     double replay_ms = 0.0;
@@ -2755,6 +2912,7 @@ int plan_build(ncf_plan_s* P, Job& J, const double* const* tin, const double* co
     NCF_TRY(run_job(B, tdev, xdev, edev));
     P->tune = tune;
     P->grids = B.info_grids;
+    P->fold_grids = B.info_fold_grids;
     P->grid_cells = B.info_grid_cells;
     P->window_items = B.info_window_items;
     P->window_launches = B.info_window_launches;
@@ -2906,6 +3064,13 @@ int plan_create(Job& J, const double* const* tin, const double* const* ein, ncf_
             if (rc == NCF_OK && !J.regular) {  // separate last pass and product
                 Tune t = best->tune;
                 t.no_mid = true;
+                rc = attempt(t);
+            }
+            if (rc == NCF_OK && !J.regular && best->fold_grids > 0) {
+                // lags by inverse transform and interpolation although they
+                // sit on a lattice
+                Tune t = best->tune;
+                t.eval_interp = true;
                 rc = attempt(t);
             }
         }
@@ -3110,6 +3275,8 @@ int ncf_plan_info(const ncf_plan_t* P, ncf_plan_info_t* info) {
     info->window_queue = P->tune.queue ? 1 : 0;
     info->graph = P->exec ? 1 : 0;
     info->replay_ms = P->replay_ms;
+    info->lattice_grids = P->fold_grids;
+    info->lattice_off = P->tune.eval_interp ? 1 : 0;
     return NCF_OK;
 }
 
@@ -3192,6 +3359,40 @@ int ncf_diag_spread_params(double sigma, double eps, double* out) {
     SpreadParams p = spread_params(sigma, eps);
     out[0] = p.s;
     out[1] = p.W;
+    return NCF_OK;
+}
+
+int ncf_diag_grid(double tmin, double tmax, int64_t K, const double* lags, int acf, double h,
+                  int precision, int lattice, double* out_f, int64_t* out_i) {
+    clear_error();
+    if (K < 0 || (K > 0 && !lags) || !out_f || !out_i || !(h > 0.0) || !std::isfinite(h) ||
+        !(tmax >= tmin) || !std::isfinite(tmin) || !std::isfinite(tmax) ||
+        (precision != NCF_MIXED && precision != NCF_FP64)) {
+        set_error("ncf_diag_grid: invalid argument");
+        return NCF_E_INVALID_ARG;
+    }
+    Job J;
+    ncf_options_init(&J.opt);
+    J.opt.precision = precision;
+    J.kern = NCF_GAUSSIAN;
+    J.ccf = acf == 0;
+    J.lags.assign(lags, lags + K);
+    double maxlag = 0.0;
+    for (double v : J.lags) {
+        if (!std::isfinite(v)) {
+            set_error("ncf_diag_grid: non-finite lag");
+            return NCF_E_INVALID_ARG;
+        }
+        maxlag = std::max(maxlag, std::fabs(v));
+    }
+    J.lag_unit = lattice ? lag_lattice_unit(J.lags, acf != 0) : 0.0;
+    SpecGeom g;
+    NCF_TRY(plan_grid(J, tmin, tmax, maxlag, h, &g));
+    out_f[0] = g.L;
+    out_f[1] = g.s;
+    out_i[0] = g.N;
+    out_i[1] = g.M;
+    out_i[2] = g.P;
     return NCF_OK;
 }
 

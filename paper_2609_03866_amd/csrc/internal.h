@@ -326,6 +326,18 @@ struct SpecTask {
     // gridb holds the spectrum of b and bunw receives b(tau) at the lags
     void* gridc;
     double* bunw;
+    // lag-lattice evaluation (P > 0): every evaluation lag is a whole number of
+    // lattice units L / P, so the lag sum is a P-point DFT of the spectrum
+    // folded modulo P. The fused kernel folds each 4096-position tile to
+    // P2 = 4096 P / N entries, inverse-transforms them and writes them to
+    // ybuf[k_low * P2 + n2] (k_low: the tile's frequency residue mod N / 4096);
+    // the evaluation kernel finishes the sum at each lag. P = 0: the inverse
+    // transform and the interpolation at the lags.
+    int64_t P;
+    int32_t lgP2;
+    int32_t nmc;           // chunks of kFoldTiles tiles summed by separate workgroups
+    void* ybuf;
+    double* fpart;         // nmc > 1: [nmc][K_eval][2] partial lag sums of the chunks
 };
 
 // Spreading tile records: p0, p1 of set 0, p0, p1 of set 1, task index,
@@ -360,6 +372,16 @@ int launch_fallback_flags(const SpecTask* d_tasks, const double* bspec, int64_t 
                           int Krow, double beta, uint64_t* mask, hipStream_t st);
 int launch_interp(const SpecTask* d_tasks, int ntasks, const int64_t* d_k0, int64_t total_k,
                   bool fp64, hipStream_t st);
+// Lag-lattice evaluation of the tasks with P > 0: workgroup b of
+// [d_fe0[i], d_fe0[i + 1]) takes 64 evaluation lags and one chunk of
+// kFoldTiles tiles of task i (nmc chunks); tasks of several chunks add their
+// chunk sums in a second kernel (one thread per task and lag, indexed like
+// the interpolation: d_k0).
+constexpr int kFoldLags = 64;
+constexpr int kFoldTiles = 1024;
+int launch_fold_eval(const SpecTask* d_tasks, int ntasks, const int64_t* d_fe0, int64_t nblocks,
+                     const int64_t* d_k0, int64_t total_k, bool chunk_sums, bool fp64,
+                     hipStream_t st);
 
 // FFT (A4)
 struct FftPlan {

@@ -436,9 +436,13 @@ __device__ __forceinline__ double exp2_split(double y) {
 
 // The factors at signed mode m (|m| <= N/2); both zero beyond the retained
 // modes.
+// f3 is the factor of the evaluated spectrum: phihat / (L Psi^3) when the
+// lags are read by interpolation (one more Psi for the interpolating
+// kernel), phihat / (L Psi^2) = f2 when they are read off a lag lattice
+// (`fold`: no interpolation).
 template <typename R, bool CCF>
 __device__ __forceinline__ void product_factors_m(const ProductCtx<R>& X, int64_t m, double& f3,
-                                                  double& f2) {
+                                                  double& f2, bool fold = false) {
     f3 = 0.0;
     f2 = 0.0;
     if (m > X.M || m < -X.M) return;
@@ -446,16 +450,16 @@ __device__ __forceinline__ void product_factors_m(const ProductCtx<R>& X, int64_
     const double m2 = md * md;
     if (X.kern == NCF_GAUSSIAN) {
         if (sizeof(R) == 4) {
-            f3 = X.c3 * exp2_split(X.e3 * m2);
-            if (CCF) f2 = X.c2 * exp2_split(X.e2 * m2);
+            if (fold || CCF) f2 = X.c2 * exp2_split(X.e2 * m2);
+            f3 = fold ? f2 : X.c3 * exp2_split(X.e3 * m2);
         } else {
-            f3 = X.c3 * exp(X.e3 * m2);
-            if (CCF) f2 = X.c2 * exp(X.e2 * m2);
+            if (fold || CCF) f2 = X.c2 * exp(X.e2 * m2);
+            f3 = fold ? f2 : X.c3 * exp(X.e3 * m2);
         }
     } else {
         const double ker = lag_kernel_ft<R>(X.kern, md / X.L, X.h);
-        f3 = X.c3 * ker * exp(3.0 * X.psi * m2);
-        if (CCF) f2 = X.c2 * ker * exp(2.0 * X.psi * m2);
+        if (fold || CCF) f2 = X.c2 * ker * exp(2.0 * X.psi * m2);
+        f3 = fold ? f2 : X.c3 * ker * exp(3.0 * X.psi * m2);
     }
 }
 
@@ -670,6 +674,7 @@ __global__ void k_interp(const SpecTask* __restrict__ tasks, int ntasks, const i
     if (g >= total_k) return;
     const int ti = (int)find_task(k0s, ntasks, g);
     const SpecTask& T = tasks[ti];
+    if (T.P > 0) return;  // lag-lattice task: k_fold_eval
     const int k = (int)(g - k0s[ti]);
     const double tau = T.lags[k];
     const double Nd = (double)T.N;
@@ -698,6 +703,101 @@ __global__ void k_interp(const SpecTask* __restrict__ tasks, int ntasks, const i
     if (T.bunw) T.bunw[k] = accn;
 }
 
+
+// Lag-lattice evaluation, the sum over the tiles (after mid_fold): workgroup
+// b of task i takes the evaluation lags [64 c, 64 c + 64) and the tiles
+// [kFoldTiles q, kFoldTiles (q + 1)) of one chunk q (b - fe0[i] = c nmc + q).
+// Lane l of wave w sums, for lag 64 c + l at lattice point n = tau P / L (a
+// whole number for a lag on the lattice), the tiles k_low of its quarter of
+// the chunk: sum exp(-2 pi i k_low n / P) Y[k_low][n mod P2], the
+// exponential by FP64 recurrence in k_low, re-anchored every 64 terms with
+// exact integer reduction of k_low n mod P. The quarters are added in a
+// fixed order; a task of one chunk writes the result (real part: numerator
+// N(tau); imaginary part: pair count), one of several writes the chunk's
+// sum for k_fold_sum.
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_fold_eval(const SpecTask* __restrict__ tasks, int ntasks, const int64_t* __restrict__ fe0) {
+    using C2 = typename Cplx<R>::T;
+    __shared__ double red[2][4][64];
+    const int64_t blk = blockIdx.x;
+    const int ti = (int)find_task(fe0, ntasks, blk);
+    const SpecTask& T = tasks[ti];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t local = blk - fe0[ti];
+    const int nmc = T.nmc;
+    const int q = (int)(local % nmc);
+    const int k = (int)(local / nmc) * kFoldLags + lane;
+    const bool live = k < T.K_eval;
+    double ax = 0.0, ay = 0.0;
+    if (live) {
+        const int64_t P = T.P;
+        const int64_t P2 = 1LL << T.lgP2;
+        const int64_t N1 = T.N >> 12;
+        int64_t n = llround(T.lags[k] * ((double)P / T.L)) % P;
+        if (n < 0) n += P;
+        const int64_t n2 = n & (P2 - 1);
+        const int64_t c0 = (int64_t)q * kFoldTiles;
+        const int64_t c1 = c0 + kFoldTiles < N1 ? c0 + kFoldTiles : N1;
+        const int64_t quarter = (c1 - c0 + 3) / 4;
+        const int64_t m0 = c0 + wave * quarter;
+        const int64_t m1 = m0 + quarter < c1 ? m0 + quarter : c1;
+        const C2* Y = reinterpret_cast<const C2*>(T.ybuf);
+        double sr, cr;
+        sincospi(-2.0 * (double)n / (double)P, &sr, &cr);  // ratio exp(-2 pi i n / P)
+        double tc = 1.0, ts = 0.0;
+        for (int64_t m = m0; m < m1; ++m) {
+            if (((m - m0) & 63) == 0) {
+                const int64_t e = (m * n) % P;  // m n < 2^50 (N <= 2^31)
+                sincospi(-2.0 * (double)e / (double)P, &ts, &tc);
+            }
+            const C2 y = Y[m * P2 + n2];
+            ax += tc * (double)y.x - ts * (double)y.y;
+            ay += tc * (double)y.y + ts * (double)y.x;
+            const double nc = tc * cr - ts * sr;
+            ts = tc * sr + ts * cr;
+            tc = nc;
+        }
+    }
+    red[0][wave][lane] = ax;
+    red[1][wave][lane] = ay;
+    __syncthreads();
+    if (wave == 0 && live) {
+        double x = 0.0, y = 0.0;
+        for (int w = 0; w < 4; ++w) {
+            x += red[0][w][lane];
+            y += red[1][w][lane];
+        }
+        if (nmc == 1) {
+            T.numer[k] = x;
+            if (T.with_b) T.bspec[k] = y;
+        } else {
+            double* o = T.fpart + ((int64_t)q * T.K_eval + k) * 2;
+            o[0] = x;
+            o[1] = y;
+        }
+    }
+}
+
+// The chunk sums of the tasks with several chunks, in chunk order; one
+// thread per task and evaluation lag.
+__global__ void k_fold_sum(const SpecTask* __restrict__ tasks, int ntasks,
+                           const int64_t* __restrict__ k0s, int64_t total_k) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total_k) return;
+    const int ti = (int)find_task(k0s, ntasks, g);
+    const SpecTask& T = tasks[ti];
+    if (T.P <= 0 || T.nmc <= 1) return;
+    const int k = (int)(g - k0s[ti]);
+    double x = 0.0, y = 0.0;
+    for (int q = 0; q < T.nmc; ++q) {
+        const double* o = T.fpart + ((int64_t)q * T.K_eval + k) * 2;
+        x += o[0];
+        y += o[1];
+    }
+    T.numer[k] = x;
+    if (T.with_b) T.bspec[k] = y;
+}
 
 // ------------------------------------------- fused last pass + product
 
@@ -777,15 +877,96 @@ __device__ __forceinline__ void mid_math(double f3d, double f2d, bool paired, C2
 }
 
 constexpr int kMidPad = 4096 + 4096 / 16;  // one padded LDS tile (fftk::lds_pad)
+constexpr int kMidThreads = 512;            // threads of the fused kernel
 
 extern __shared__ char g_mid_lds[];
+
+// Lag-lattice evaluation, the tile part. Position r of a tile holds frequency
+// k_low + r N1 (N1 = N / 4096). With P = N1 P2 (P2 a power of two <= 4096) the
+// frequency's residue mod P is k_low + N1 (r mod P2), so the tile folds on
+// its own: F[r2] = sum_j G[r2 + P2 j]. The lag sum at lattice point n,
+// sum over the residues p of F_p exp(-2 pi i p n / P), splits with
+// p = k_low + N1 r2 into the P2-point inverse DFT of the tile's F at
+// n mod P2, times exp(-2 pi i k_low n / P), summed over the N1 tiles; this
+// function leaves Y[n2] = that inverse DFT in ybuf[k_low P2 + n2]. The DFT
+// runs as radix-2 decimation-in-time stages in place (input in bit-reversed
+// order), twiddles from the FP64 table of w_4096 rounded once. Each half of
+// the workgroup (256 threads) takes its own tile; every thread meets the
+// same barriers.
+template <typename R>
+__device__ __forceinline__ void mid_fold(const SpecTask& T, typename Cplx<R>::T* tile,
+                                         typename Cplx<R>::T* tile0, bool act, int64_t k_low,
+                                         int lt, const void* wsmall) {
+    using C2 = typename Cplx<R>::T;
+    const int lg = T.lgP2;
+    const int P2 = 1 << lg;
+    const int nf = 4096 >> lg;  // terms per folded entry
+    C2 f[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int r2 = lt + 256 * i;
+        C2 acc;
+        acc.x = (R)0;
+        acc.y = (R)0;
+        if (act && r2 < P2)
+            for (int j = 0; j < nf; ++j) acc = fftk::cadd(acc, tile[fftk::lds_pad(r2 + P2 * j)]);
+        f[i] = acc;
+    }
+    __syncthreads();  // every read of the product tile is done
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int r2 = lt + 256 * i;
+        if (act && r2 < P2) {
+            const int br = lg ? (int)(__builtin_bitreverse32((uint32_t)r2) >> (32 - lg)) : 0;
+            tile[fftk::lds_pad(br)] = f[i];
+        }
+    }
+    // twiddles exp(-2 pi i e / P2), e < P2 / 2, rounded once from the FP64
+    // table of w_4096: in LDS past the folded entries of the first tile when
+    // they fit there (P2 <= 2048), else read from the table at each stage
+    const bool lds_tab = P2 <= 2048;
+    C2* const tab = tile0 + (kMidPad - P2 / 2);
+    if (lds_tab)
+        for (int e = threadIdx.x; e < P2 / 2; e += kMidThreads) {
+            const double2 wd = fftk::gld<double2>(wsmall, (int64_t)e << (12 - lg));
+            C2 w;
+            w.x = (R)wd.x;
+            w.y = (R)(-wd.y);
+            tab[e] = w;
+        }
+    __syncthreads();
+    for (int lh = 0; lh < lg; ++lh) {  // butterflies of half-size 2^lh
+        const int hs = 1 << lh;
+        for (int b = lt; act && b < P2 / 2; b += 256) {
+            const int j = b & (hs - 1);
+            const int i0 = ((b >> lh) << (lh + 1)) | j;
+            const int i1 = i0 + hs;
+            // w = exp(-2 pi i j / 2hs) = exp(-2 pi i e / P2), e = j P2 / 2hs
+            C2 w;
+            if (lds_tab) {
+                w = tab[j << (lg - 1 - lh)];
+            } else {
+                const double2 wd = fftk::gld<double2>(wsmall, (int64_t)j << (11 - lh));
+                w.x = (R)wd.x;
+                w.y = (R)(-wd.y);
+            }
+            const C2 u = tile[fftk::lds_pad(i0)];
+            const C2 v = fftk::cmul(tile[fftk::lds_pad(i1)], w);
+            tile[fftk::lds_pad(i0)] = fftk::cadd(u, v);
+            tile[fftk::lds_pad(i1)] = fftk::csub(u, v);
+        }
+        __syncthreads();
+    }
+    if (act) {
+        C2* Y = reinterpret_cast<C2*>(T.ybuf) + k_low * P2;
+        for (int n = lt; n < P2; n += 256) Y[n] = tile[fftk::lds_pad(n)];
+    }
+}
 
 // MODE: bit 1 CCF, bit 0 pair-count channel (gridb for the CCF); as k_product
 // without the unit channel. 512 threads: the two halves transform the two
 // tiles at the same time (in a one-tile pair the second half only keeps the
 // barriers); all threads share the products.
-constexpr int kMidThreads = 512;
-
 template <typename R, int MODE>
 __global__ void __launch_bounds__(kMidThreads)
 k_mid(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pair0, int ntasks,
@@ -808,6 +989,7 @@ k_mid(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pair0, int
     int64_t tA, tB, kl, kp;
     mid_pair(blk - pair0[ti], ri, tA, tB, kl, kp);
     const bool self = tA == tB;
+    const bool fold = T.P > 0;  // lag-lattice evaluation
     C2* const Z = reinterpret_cast<C2*>(T.grid);
     C2* const U = reinterpret_cast<C2*>(T.gridb);
     const int half = threadIdx.x >> 8;  // wave-uniform
@@ -859,7 +1041,7 @@ k_mid(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pair0, int
             ub = PUB[fftk::lds_pad(rp)];
         }
         double f3, f2;
-        product_factors_m<R, CCF>(X, mode_of(kl + ((int64_t)r << lgs)), f3, f2);
+        product_factors_m<R, CCF>(X, mode_of(kl + ((int64_t)r << lgs)), f3, f2, fold);
         C2 o, oc;
         mid_math<R, CCF, WB>(f3, f2, paired, za, pairs ? zb : za, ua, ub, sacc, o, oc);
         A[fftk::lds_pad(r)] = o;
@@ -869,7 +1051,7 @@ k_mid(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pair0, int
         for (int r = threadIdx.x; r < 4096; r += kMidThreads) {
             const C2 za = Bt[fftk::lds_pad(r)];
             double f3, f2;
-            product_factors_m<R, CCF>(X, mode_of(kp + ((int64_t)r << lgs)), f3, f2);
+            product_factors_m<R, CCF>(X, mode_of(kp + ((int64_t)r << lgs)), f3, f2, fold);
             C2 o, oc;
             mid_math<R, CCF, WB>(f3, f2, false, za, za, za, za, sacc, o, oc);
             Bt[fftk::lds_pad(r)] = o;
@@ -880,18 +1062,24 @@ k_mid(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pair0, int
         const C2 za = A[fftk::lds_pad(r)];
         const C2 ua = TWO ? UA[fftk::lds_pad(r)] : za;
         double f3, f2;
-        product_factors_m<R, CCF>(X, mode_of((int64_t)r << lgs), f3, f2);
+        product_factors_m<R, CCF>(X, mode_of((int64_t)r << lgs), f3, f2, fold);
         C2 o, oc;
         mid_math<R, CCF, WB>(f3, f2, false, za, za, ua, ua, sacc, o, oc);
         A[fftk::lds_pad(r)] = o;
     }
     __syncthreads();
-    // inverse first pass of the product tiles, to HBM
-    a.sign = -1;
-    if (act)
-        fftk::run_stages_io<12, 0, 1, 12, false, true>(a, myZ, Z + myT * 4096, 0, lt);
-    else
-        fftk::run_stages_idle<12, 0, false, true>();
+    if (fold) {
+        // lag lattice: fold each product tile modulo P and inverse-transform
+        // the P2 folded entries in LDS (see mid_fold)
+        mid_fold<R>(T, myZ, A, act, half ? kp : kl, lt, wsmall);
+    } else {
+        // inverse first pass of the product tiles, to HBM
+        a.sign = -1;
+        if (act)
+            fftk::run_stages_io<12, 0, 1, 12, false, true>(a, myZ, Z + myT * 4096, 0, lt);
+        else
+            fftk::run_stages_idle<12, 0, false, true>();
+    }
     if (CCF) {  // lag-0 partial sums: the pair's in the slot of tile tA, 0 in tB's
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -1113,6 +1301,29 @@ int launch_interp(const SpecTask* d_tasks, int ntasks, const int64_t* d_k0, int6
         hipLaunchKernelGGL(k_interp<float>, dim3((unsigned)ceil_div(total_k, 128)), dim3(128), 0,
                            st, d_tasks, ntasks, d_k0, total_k);
     NCF_CHECK_LAUNCH();
+    return NCF_OK;
+}
+
+int launch_fold_eval(const SpecTask* d_tasks, int ntasks, const int64_t* d_fe0, int64_t nblocks,
+                     const int64_t* d_k0, int64_t total_k, bool chunk_sums, bool fp64,
+                     hipStream_t st) {
+    if (nblocks <= 0) return NCF_OK;
+    {
+        ProfScope p(st, "fold_eval", 0.0, "bytes");
+        if (fp64)
+            hipLaunchKernelGGL(k_fold_eval<double>, dim3((unsigned)nblocks), dim3(256), 0, st,
+                               d_tasks, ntasks, d_fe0);
+        else
+            hipLaunchKernelGGL(k_fold_eval<float>, dim3((unsigned)nblocks), dim3(256), 0, st,
+                               d_tasks, ntasks, d_fe0);
+        NCF_CHECK_LAUNCH();
+    }
+    if (chunk_sums && total_k > 0) {
+        ProfScope p(st, "fold_sum", 0.0, "bytes");
+        hipLaunchKernelGGL(k_fold_sum, dim3((unsigned)ceil_div(total_k, 128)), dim3(128), 0, st,
+                           d_tasks, ntasks, d_k0, total_k);
+        NCF_CHECK_LAUNCH();
+    }
     return NCF_OK;
 }
 

@@ -528,9 +528,9 @@ __device__ __forceinline__ void window_item(const WinTask* __restrict__ tasks,
     }
 }
 
-// Work items (series x j-tile x lag-tile) of a whole batch in one launch.
-// Flat dispatch: workgroup b runs item b (the hardware hands workgroups out
-// in order). Queue dispatch: a grid of resident workgroups pulls items from
+// Work items (series x j-group x lag-tile) of a whole batch in one launch.
+// Flat dispatch: workgroup b runs item xcd_remap(b) (the hardware hands
+// workgroups out in order, round robin over the XCDs). Queue dispatch: a grid of resident workgroups pulls items from
 // a device counter until the items run out; the last workgroup to leave
 // resets the counter pair for the next launch (no memset, so a captured
 // graph can replay it). Every item writes its own partial sums, so results
@@ -540,8 +540,11 @@ __global__ void __launch_bounds__(kThreads)
 k_window(const WinTask* __restrict__ tasks, const int64_t* __restrict__ item0, int ntasks,
          int64_t nitems, int cap, int jmax, unsigned long long* __restrict__ queue) {
     if (!queue) {
-        if ((int64_t)blockIdx.x < nitems)
-            window_item<F>(tasks, item0, ntasks, (int64_t)blockIdx.x, cap, jmax);
+        // XCD-aware order: each XCD takes a contiguous run of items, so the
+        // lag tiles of one j-group (consecutive items, the same window
+        // samples) meet in one L2
+        const int64_t item = xcd_remap(blockIdx.x, gridDim.x);
+        if (item < nitems) window_item<F>(tasks, item0, ntasks, item, cap, jmax);
         return;
     }
     __shared__ int64_t sh_item;

@@ -54,7 +54,8 @@ class PlanInfo(ctypes.Structure):
                 ("grid_cells", ctypes.c_int64), ("window_items", ctypes.c_int64),
                 ("sigma", ctypes.c_double), ("fft_split", ctypes.c_int32),
                 ("fft_tile_log2", ctypes.c_int32), ("window_tile_scale", ctypes.c_int32),
-                ("window_queue", ctypes.c_int32), ("replay_ms", ctypes.c_double)]
+                ("window_queue", ctypes.c_int32), ("replay_ms", ctypes.c_double),
+                ("lattice_grids", ctypes.c_int32), ("lattice_off", ctypes.c_int32)]
 
 
 class ProfileRecord(ctypes.Structure):
@@ -106,6 +107,8 @@ def lib():
         L.ncf_diag_type1.argtypes = [_I64, _P, _P, ctypes.c_double, ctypes.c_double, _I64, _I64,
                                      ctypes.c_int, _P]
         L.ncf_diag_spread_params.argtypes = [ctypes.c_double, ctypes.c_double, _P]
+        L.ncf_diag_grid.argtypes = [ctypes.c_double, ctypes.c_double, _I64, _P, ctypes.c_int,
+                                    ctypes.c_double, ctypes.c_int, ctypes.c_int, _P, _P]
         L.ncf_plan_acf.argtypes = [_I64, _P, _P, _P, _I64, _P, ctypes.c_int, _P, _P, _P]
         L.ncf_plan_ccf.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _I64, _P, ctypes.c_int, _P, _P,
                                    _P]
@@ -628,6 +631,18 @@ def diag_type1(t, v, t_ref, L, N, M, precision="mixed"):
                                 int(N), int(M), FP64 if precision in ("fp64", FP64) else MIXED,
                                 out.ctypes.data))
     return out[0::2] + 1j * out[1::2]
+
+
+def diag_grid(tmin, tmax, lags, h, acf=True, precision="mixed", lattice=True):
+    """ncf_diag_grid: (L, s, N, M, P) of the planner's grid for one problem."""
+    lags = np.ascontiguousarray(lags, dtype=np.float64)
+    of = np.zeros(2)
+    oi = np.zeros(3, dtype=np.int64)
+    _check(lib().ncf_diag_grid(float(tmin), float(tmax), lags.size,
+                               lags.ctypes.data, 1 if acf else 0, float(h),
+                               FP64 if precision == "fp64" else MIXED,
+                               1 if lattice else 0, of.ctypes.data, oi.ctypes.data))
+    return float(of[0]), float(of[1]), int(oi[0]), int(oi[1]), int(oi[2])
 
 
 def diag_spread_params(sigma, eps):
