@@ -1433,7 +1433,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             jneed = std::max(jneed, (int)W.wt[i].J);
         }
         // LDS: twice the estimated window range (clustering margin), rounded up
-        const int want = (int)std::min<double>(cap, round_up((int64_t)(2.0 * need) + 64, 256));
+        const int want = (int)std::min<double>(cap, round_up((int64_t)(2.0 * need) + 64, 64));
         W.cap = std::max(256, want);
         W.jmax = (int)round_up(jneed, 64);
         // items of few lags (e.g. the lag-0 scale tasks) grow within that

@@ -536,9 +536,10 @@ __device__ __forceinline__ void window_item(const WinTask* __restrict__ tasks,
 // graph can replay it). Every item writes its own partial sums, so results
 // do not depend on which workgroup ran it.
 template <uint32_t F>
-__global__ void __launch_bounds__(kThreads)
-k_window(const WinTask* __restrict__ tasks, const int64_t* __restrict__ item0, int ntasks,
-         int64_t nitems, int cap, int jmax, unsigned long long* __restrict__ queue) {
+__device__ __forceinline__ void window_dispatch(const WinTask* __restrict__ tasks,
+                                                const int64_t* __restrict__ item0, int ntasks,
+                                                int64_t nitems, int cap, int jmax,
+                                                unsigned long long* __restrict__ queue) {
     if (!queue) {
         // XCD-aware order: each XCD takes a contiguous run of items, so the
         // lag tiles of one j-group (consecutive items, the same window
@@ -563,6 +564,34 @@ k_window(const WinTask* __restrict__ tasks, const int64_t* __restrict__ item0, i
             atomicExch(queue + 1, 0ull);
         }
     }
+}
+
+template <uint32_t F>
+__global__ void __launch_bounds__(kThreads)
+k_window(const WinTask* __restrict__ tasks, const int64_t* __restrict__ item0, int ntasks,
+         int64_t nitems, int cap, int jmax, unsigned long long* __restrict__ queue) {
+    window_dispatch<F>(tasks, item0, ntasks, nitems, cap, jmax, queue);
+}
+
+// The unweighted rectangle scans, register-allocated for eight waves per
+// SIMD (scalar registers partly spilled to vector lanes): their wait on each
+// dependent LDS read is covered by more waves (c5 window_rect 25.1 ->
+// 22.8 ms). The weighted ones would spill vector registers to memory.
+template <uint32_t F>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8)))
+k_window_rect8(const WinTask* __restrict__ tasks, const int64_t* __restrict__ item0,
+               int ntasks, int64_t nitems, int cap, int jmax,
+               unsigned long long* __restrict__ queue) {
+    window_dispatch<F>(tasks, item0, ntasks, nitems, cap, jmax, queue);
+}
+
+// the kernel that runs window flags F
+template <uint32_t F>
+constexpr auto window_kernel() {
+    if constexpr (F == WIN_RECT || F == (WIN_RECT | WIN_NUMER))
+        return k_window_rect8<F>;
+    else
+        return k_window<F>;
 }
 
 // Level 1: sum the partials of up to kJc consecutive j-tiles for 64 lags
@@ -673,7 +702,7 @@ int resident_blocks(size_t bytes, int64_t* out) {
     auto it = cache.find(key);
     if (it == cache.end()) {
         int per_cu = 0, cus = 0;
-        NCF_TRY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_window<F>, kThreads,
+        NCF_TRY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, window_kernel<F>(), kThreads,
                                                                  bytes));
         NCF_TRY_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         it = cache.emplace(key, (int64_t)std::max(per_cu, 1) * std::max(cus, 1)).first;
@@ -700,7 +729,7 @@ int launch_window_t(const WinTask* d_tasks, const int64_t* d_item0, int ntasks, 
         nblocks = std::min(nitems, res);
     }
     ProfScope p(st, RECT ? "window_rect" : "window_gauss", work, "valu_ops");
-    hipLaunchKernelGGL(k_window<F>, dim3((unsigned)nblocks), dim3(kThreads), bytes, st, d_tasks,
+    hipLaunchKernelGGL(window_kernel<F>(), dim3((unsigned)nblocks), dim3(kThreads), bytes, st, d_tasks,
                        d_item0, ntasks, nitems, cap, jmax, queue);
     NCF_CHECK_LAUNCH();
     return NCF_OK;
