@@ -241,10 +241,12 @@ __device__ __forceinline__ int lds_pad(int e) { return e + (e >> 4); }
 // One Stockham stage of radix RADIX over the tile's C columns of length R.
 // Each thread owns 16 / RADIX butterflies (16 elements). Inputs come from
 // `src` (global or LDS view), outputs go to `dst`.
-// tid: the thread's index among the 2^(LGT-4) threads of the tile.
+// tid: the thread's index among the 2^(LGT-4) threads of the tile. `on`
+// false: the thread does no work and only meets the stage's barriers, which
+// lie outside the work it skips.
 template <int RADIX, bool FROM_GLOBAL, bool TO_GLOBAL, int LGR, int NS, int LGT, typename C2>
 __device__ __forceinline__ void stockham_stage(const PassArgs& a, C2* lds, C2* gbase, int64_t s0,
-                                               int tid) {
+                                               int tid, bool on = true) {
     constexpr int kThreads = 1 << (LGT - 4);  // 16 elements per thread
     constexpr int NB = 16 / RADIX;  // butterflies per thread
     constexpr int lgC = LGT - LGR;
@@ -255,7 +257,7 @@ __device__ __forceinline__ void stockham_stage(const PassArgs& a, C2* lds, C2* g
     C2 v[16];
     int jj[NB], cc[NB];
 #pragma unroll
-    for (int u = 0; u < NB; ++u) {
+    for (int u = 0; u < NB && on; ++u) {
         const int beta = tid + u * kThreads;
         const int c = beta & (C - 1);
         const int j = beta >> lgC;
@@ -297,7 +299,7 @@ __device__ __forceinline__ void stockham_stage(const PassArgs& a, C2* lds, C2* g
     // transformed in place, in LDS or in HBM)
     if (!FROM_GLOBAL || TO_GLOBAL) __syncthreads();
 #pragma unroll
-    for (int u = 0; u < NB; ++u) {
+    for (int u = 0; u < NB && on; ++u) {
         const int j = jj[u], c = cc[u];
         const int k = j & (Ns - 1);
         const int obase = (j / Ns) * Ns * RADIX + k;
@@ -345,15 +347,15 @@ __device__ __forceinline__ void run_stages(const PassArgs& a, C2* lds, C2* gbase
 // (global memory or LDS) chosen at compile time.
 template <int LGR, int ST, int NS, int LGT, bool G_IN, bool G_OUT, typename C2>
 __device__ __forceinline__ void run_stages_io(const PassArgs& a, C2* lds, C2* gbase, int64_t s0,
-                                              int tid) {
+                                              int tid, bool on = true) {
     constexpr int n16 = LGR / 4;
     constexpr int rem = LGR % 4;
     constexpr int nst = n16 + (rem ? 1 : 0);
     if constexpr (ST < nst) {
         constexpr int RX = ST < n16 ? 16 : (1 << rem);
         stockham_stage<RX, G_IN && ST == 0, G_OUT && ST == nst - 1, LGR, NS, LGT>(a, lds, gbase,
-                                                                                   s0, tid);
-        run_stages_io<LGR, ST + 1, NS * RX, LGT, G_IN, G_OUT>(a, lds, gbase, s0, tid);
+                                                                                   s0, tid, on);
+        run_stages_io<LGR, ST + 1, NS * RX, LGT, G_IN, G_OUT>(a, lds, gbase, s0, tid, on);
     }
 }
 

@@ -889,14 +889,21 @@ extern __shared__ char g_mid_lds[];
 // p = k_low + N1 r2 into the P2-point inverse DFT of the tile's F at
 // n mod P2, times exp(-2 pi i k_low n / P), summed over the N1 tiles; this
 // function leaves Y[n2] = that inverse DFT in ybuf[k_low P2 + n2]. The DFT
-// runs as radix-2 decimation-in-time stages in place (input in bit-reversed
-// order), twiddles from the FP64 table of w_4096 rounded once. Each half of
-// the workgroup (256 threads) takes its own tile; every thread meets the
-// same barriers.
+// runs as Stockham stages in LDS (radix 16, then one of 8, 4 or 2; 16
+// entries per thread, so P2 / 16 of the half's 256 threads take part) with
+// the twiddle progressions of the FFT passes. The planner keeps
+// 16 <= P2 <= 2048 (2 <= N / P <= 256). Each half of the workgroup (256
+// threads) takes its own tile; every thread meets the same barriers.
+template <int LG, typename C2>
+__device__ __forceinline__ void fold_dft(const fftk::PassArgs& a, C2* tile, bool act, int lt) {
+    // one column of 2^LG entries; threads past 2^(LG - 4) only keep the barriers
+    fftk::run_stages_io<LG, 0, 1, LG, false, false>(a, tile, tile, 0, lt,
+                                                    act && lt < (1 << (LG - 4)));
+}
+
 template <typename R>
-__device__ __forceinline__ void mid_fold(const SpecTask& T, typename Cplx<R>::T* tile,
-                                         typename Cplx<R>::T* tile0, bool act, int64_t k_low,
-                                         int lt, const void* wsmall) {
+__device__ __forceinline__ void mid_fold(const SpecTask& T, typename Cplx<R>::T* tile, bool act,
+                                         int64_t k_low, int lt, const void* wsmall) {
     using C2 = typename Cplx<R>::T;
     const int lg = T.lgP2;
     const int P2 = 1 << lg;
@@ -916,46 +923,24 @@ __device__ __forceinline__ void mid_fold(const SpecTask& T, typename Cplx<R>::T*
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const int r2 = lt + 256 * i;
-        if (act && r2 < P2) {
-            const int br = lg ? (int)(__builtin_bitreverse32((uint32_t)r2) >> (32 - lg)) : 0;
-            tile[fftk::lds_pad(br)] = f[i];
-        }
+        if (act && r2 < P2) tile[fftk::lds_pad(r2)] = f[i];
     }
-    // twiddles exp(-2 pi i e / P2), e < P2 / 2, rounded once from the FP64
-    // table of w_4096: in LDS past the folded entries of the first tile when
-    // they fit there (P2 <= 2048), else read from the table at each stage
-    const bool lds_tab = P2 <= 2048;
-    C2* const tab = tile0 + (kMidPad - P2 / 2);
-    if (lds_tab)
-        for (int e = threadIdx.x; e < P2 / 2; e += kMidThreads) {
-            const double2 wd = fftk::gld<double2>(wsmall, (int64_t)e << (12 - lg));
-            C2 w;
-            w.x = (R)wd.x;
-            w.y = (R)(-wd.y);
-            tab[e] = w;
-        }
     __syncthreads();
-    for (int lh = 0; lh < lg; ++lh) {  // butterflies of half-size 2^lh
-        const int hs = 1 << lh;
-        for (int b = lt; act && b < P2 / 2; b += 256) {
-            const int j = b & (hs - 1);
-            const int i0 = ((b >> lh) << (lh + 1)) | j;
-            const int i1 = i0 + hs;
-            // w = exp(-2 pi i j / 2hs) = exp(-2 pi i e / P2), e = j P2 / 2hs
-            C2 w;
-            if (lds_tab) {
-                w = tab[j << (lg - 1 - lh)];
-            } else {
-                const double2 wd = fftk::gld<double2>(wsmall, (int64_t)j << (11 - lh));
-                w.x = (R)wd.x;
-                w.y = (R)(-wd.y);
-            }
-            const C2 u = tile[fftk::lds_pad(i0)];
-            const C2 v = fftk::cmul(tile[fftk::lds_pad(i1)], w);
-            tile[fftk::lds_pad(i0)] = fftk::cadd(u, v);
-            tile[fftk::lds_pad(i1)] = fftk::csub(u, v);
-        }
-        __syncthreads();
+    fftk::PassArgs a{};
+    a.N = P2;
+    a.S = 1;
+    a.B = P2;
+    a.sign = -1;
+    a.wsmall = wsmall;
+    switch (lg) {  // uniform over the workgroup (one task)
+        case 4: fold_dft<4>(a, tile, act, lt); break;
+        case 5: fold_dft<5>(a, tile, act, lt); break;
+        case 6: fold_dft<6>(a, tile, act, lt); break;
+        case 7: fold_dft<7>(a, tile, act, lt); break;
+        case 8: fold_dft<8>(a, tile, act, lt); break;
+        case 9: fold_dft<9>(a, tile, act, lt); break;
+        case 10: fold_dft<10>(a, tile, act, lt); break;
+        default: fold_dft<11>(a, tile, act, lt); break;
     }
     if (act) {
         C2* Y = reinterpret_cast<C2*>(T.ybuf) + k_low * P2;
@@ -1071,7 +1056,7 @@ k_mid(const SpecTask* __restrict__ tasks, const int64_t* __restrict__ pair0, int
     if (fold) {
         // lag lattice: fold each product tile modulo P and inverse-transform
         // the P2 folded entries in LDS (see mid_fold)
-        mid_fold<R>(T, myZ, A, act, half ? kp : kl, lt, wsmall);
+        mid_fold<R>(T, myZ, act, half ? kp : kl, lt, wsmall);
     } else {
         // inverse first pass of the product tiles, to HBM
         a.sign = -1;
