@@ -228,46 +228,57 @@ __device__ __forceinline__ void scan_lane(Acc& acc, const V& v, int ja, int jb, 
 struct AccR {
     double C, B;
     double nz;  // weighted: pairs of two nonzero weights
-    int bytes;  // sum over j of (hi - lo) * 8
+    int bytes;  // sum over j of (hi - lo) * 8 S
 };
 
+// Window samples in LDS as records of S doubles: S = 2 interleaves each time
+// with its value prefix (unweighted numerator scans: one paired read fetches
+// both, the prefix at the final bounds is already in registers); S = 1 keeps
+// the times alone, the prefix arrays at dp, 2 dp, ... doubles further on.
+template <int S>
 struct RectBounds {
     const double* plo;
     const double* phi;
     double tl, th;  // times at the bounds
+    double pl, ph;  // (S = 2) value prefixes at the bounds
 };
 
 // bounds of the first outer sample of a run, by binary search
-__device__ __forceinline__ void rect_init(RectBounds& st, const double* win, int len, double c0,
+template <int S>
+__device__ __forceinline__ void rect_init(RectBounds<S>& st, const double* win, int len, double c0,
                                           double W) {
     const double key = c0 - W;
     int a = 0, b = len;
     while (a < b) {
         const int m = (a + b) >> 1;
-        if (win[m] < key)
+        if (win[S * m] < key)
             a = m + 1;
         else
             b = m;
     }
-    st.plo = win + a;
+    st.plo = win + S * a;
     const double keyh = c0 + W;
     b = len;
     while (a < b) {
         const int m = (a + b) >> 1;
-        if (win[m] <= keyh)
+        if (win[S * m] <= keyh)
             a = m + 1;
         else
             b = m;
     }
-    st.phi = win + a;
-    st.tl = *st.plo;
-    st.th = *st.phi;
+    st.phi = win + S * a;
+    st.tl = st.plo[0];
+    st.th = st.phi[0];
+    if (S == 2) {
+        st.pl = st.plo[1];
+        st.ph = st.phi[1];
+    }
 }
 
 // One outer sample: move both bounds to its window, add its terms.
-template <bool NUMER, bool WTD>
-__device__ __forceinline__ void rect_step(AccR& acc, RectBounds& st, int dp, double s, double vo,
-                                          double wo, double delta, double W) {
+template <bool NUMER, bool WTD, int S>
+__device__ __forceinline__ void rect_step(AccR& acc, RectBounds<S>& st, int dp, double s,
+                                          double vo, double wo, double delta, double W) {
     constexpr int QW = NUMER ? 2 : 1;  // PW array follows P when both exist
     constexpr int QZ = QW + 1;         // then the nonzero-weight count prefix
     const double c = s + delta;
@@ -278,15 +289,19 @@ __device__ __forceinline__ void rect_step(AccR& acc, RectBounds& st, int dp, dou
     // sentinels); measured faster than a loop per bound
     bool a = st.tl < lk, b = st.th <= hk;
     while (a || b) {
-        st.plo += a;
-        st.phi += b;
-        st.tl = *st.plo;
-        st.th = *st.phi;
+        st.plo += a ? S : 0;
+        st.phi += b ? S : 0;
+        st.tl = st.plo[0];
+        st.th = st.phi[0];
+        if (S == 2) {
+            st.pl = st.plo[1];
+            st.ph = st.phi[1];
+        }
         a = st.tl < lk;
         b = st.th <= hk;
     }
     acc.bytes += (int)((const char*)st.phi - (const char*)st.plo);
-    if (NUMER) acc.C += vo * (st.phi[dp] - st.plo[dp]);
+    if (NUMER) acc.C += vo * (S == 2 ? st.ph - st.pl : st.phi[dp] - st.plo[dp]);
     if (WTD) {
         acc.B += wo * (st.phi[QW * dp] - st.plo[QW * dp]);
         if (wo != 0.0) acc.nz += st.phi[QZ * dp] - st.plo[QZ * dp];
@@ -304,7 +319,7 @@ __device__ __forceinline__ cdp uniform_ptr(const double* p) {
 
 // Every lane of the wave walks the same outer run [ja, jb) (one lag per
 // lane): the outer samples come through scalar loads, eight at a time.
-template <bool NUMER, bool WTD>
+template <bool NUMER, bool WTD, int S>
 __device__ __forceinline__ void scan_rect_wave(AccR& acc, const double* win, int dp, int len,
                                                int ja, int jb, double delta, double W,
                                                const double* gs, const double* gvo,
@@ -315,7 +330,7 @@ __device__ __forceinline__ void scan_rect_wave(AccR& acc, const double* win, int
     const cdp cs = uniform_ptr(gs);
     const cdp cvo = NUMER ? uniform_ptr(gvo) : cs;
     const cdp cwo = WTD ? uniform_ptr(gwo) : cs;
-    RectBounds st;
+    RectBounds<S> st;
     rect_init(st, win, len, cs[ja] + delta, W);
     int j = ja;
     for (; j + 8 <= jb; j += 8) {
@@ -328,21 +343,21 @@ __device__ __forceinline__ void scan_rect_wave(AccR& acc, const double* win, int
         }
 #pragma unroll
         for (int m = 0; m < 8; ++m)
-            rect_step<NUMER, WTD>(acc, st, dp, sb[m], vb[m], wb[m], delta, W);
+            rect_step<NUMER, WTD, S>(acc, st, dp, sb[m], vb[m], wb[m], delta, W);
     }
     for (; j < jb; ++j)
-        rect_step<NUMER, WTD>(acc, st, dp, cs[j], NUMER ? cvo[j] : 0.0, WTD ? cwo[j] : 0.0,
+        rect_step<NUMER, WTD, S>(acc, st, dp, cs[j], NUMER ? cvo[j] : 0.0, WTD ? cwo[j] : 0.0,
                               delta, W);
 }
 
 // Each lane walks its own outer run (items of few lags): outer samples by
 // vector loads, the next one's in flight while the current one is scanned.
-template <bool NUMER, bool WTD>
+template <bool NUMER, bool WTD, int S>
 __device__ __forceinline__ void scan_rect_lane(AccR& acc, const double* win, int dp, int len,
                                                int ja, int jb, double delta, double W,
                                                gdp gs, gdp gvo, gdp gwo) {
     if (ja >= jb) return;
-    RectBounds st;
+    RectBounds<S> st;
     rect_init(st, win, len, gs[ja] + delta, W);
     double s = gs[ja], vo = NUMER ? gvo[ja] : 0.0, wo = WTD ? gwo[ja] : 0.0;
     for (int j = ja; j < jb; ++j) {
@@ -352,7 +367,7 @@ __device__ __forceinline__ void scan_rect_lane(AccR& acc, const double* win, int
             if (NUMER) vo_n = gvo[j + 1];
             if (WTD) wo_n = gwo[j + 1];
         }
-        rect_step<NUMER, WTD>(acc, st, dp, s, vo, wo, delta, W);
+        rect_step<NUMER, WTD, S>(acc, st, dp, s, vo, wo, delta, W);
         s = s_n;
         vo = vo_n;
         wo = wo_n;
@@ -412,10 +427,13 @@ __device__ __forceinline__ void window_item(const WinTask* __restrict__ tasks,
     const double* A1g = RECT ? T.pv : T.v;
     const double* A2g = RECT ? T.pw : T.w;
     // rectangle: times, then the prefix arrays (each cap + 8 long: values,
-    // weights and the nonzero-weight count); the outer samples stay in global
-    // memory
+    // weights and the nonzero-weight count), or with values only (no
+    // weights) each time paired with its value prefix; the outer samples
+    // stay in global memory
     constexpr int QW = NUMER ? 2 : 1;
     const int dp = cap + 8;
+    // unweighted numerator: time and value prefix interleaved (records of 2)
+    constexpr int RS = (RECT && NUMER && !WTD) ? 2 : 1;
     const gdp gt = (gdp)T.t, gs = (gdp)T.s, gvo = (gdp)T.vo, gwo = (gdp)T.wo;
     const gdp ga1 = (gdp)A1g, ga2 = (gdp)A2g, ga3 = (gdp)T.pz;
 
@@ -442,7 +460,13 @@ __device__ __forceinline__ void window_item(const WinTask* __restrict__ tasks,
         const int nj = (int)(j1 - j0);
         const bool fits = (thi - tlo) <= cap && (RECT || nj <= jmax);
         const int a_len = RECT ? len + 1 : len;  // prefix arrays need the entry at hi
-        if (RECT && fits) {
+        if (RECT && fits && RS == 2) {
+            for (int i = tid; i < len + 8; i += kThreads) {
+                double* r = g_win_lds + 2 * i;
+                r[0] = i < len ? gt[tlo + i] : kInf;
+                r[1] = i <= len ? ga1[tlo + i] : 0.0;
+            }
+        } else if (RECT && fits) {
             for (int i = tid; i < len + 8; i += kThreads) {
                 double* r = g_win_lds + i;
                 r[0] = i < len ? gt[tlo + i] : kInf;
@@ -473,18 +497,18 @@ __device__ __forceinline__ void window_item(const WinTask* __restrict__ tasks,
             AccR ar = {0.0, 0.0, 0.0, 0};
             if (streams == 1) {  // one outer run per wave
                 if (active)
-                    scan_rect_wave<NUMER, WTD>(ar, g_win_lds, dp, len, ja, jb, delta, W,
+                    scan_rect_wave<NUMER, WTD, RS>(ar, g_win_lds, dp, len, ja, jb, delta, W,
                                                T.s + j0, NUMER ? T.vo + j0 : nullptr,
                                                WTD ? T.wo + j0 : nullptr);
             } else if (active) {
-                scan_rect_lane<NUMER, WTD>(ar, g_win_lds, dp, len, ja, jb, delta, W, gs + j0,
+                scan_rect_lane<NUMER, WTD, RS>(ar, g_win_lds, dp, len, ja, jb, delta, W, gs + j0,
                                            NUMER ? gvo + j0 : nullptr,
                                            WTD ? gwo + j0 : nullptr);
             }
             acc.C += ar.C;
             acc.B += ar.B;
             acc.b += ar.nz;
-            acc.n += ar.bytes / (int)sizeof(double);
+            acc.n += ar.bytes / (int)(RS * sizeof(double));
         } else if (active) {
             if (fits) {
                 LdsView v{o_t, o_a1, o_a2, o_s, o_vo, o_wo, len};
