@@ -1001,40 +1001,204 @@ int promote_fp64(Job& J, const std::vector<int64_t>& probs, int32_t* h_fstat,
     return rc;
 }
 
-int run_job(Job& J, const double* const* tin, const double* const* xin,
-            const double* const* ein) {
-    const bool fp64 = J.opt.precision == NCF_FP64;
-    bool spectral = use_spectral(J);  // may turn to the window route after phase 1
-    const bool rect = J.kern == NCF_RECTANGLE;
-    const int nsets = J.ccf ? 2 : 1;
-    bool weighted = false;
+// The state and steps of one call of the irregular-sampling estimators
+// (run_job). A window task of one window launch (the main pass, or the
+// fallback pass of the spectral pair counts):
+struct WinPlan {
+    int wi_set, wo_set;  // window set, outer set (series index = problem)
+    int64_t prob;
+    int role;            // 0 main, 1 self x, 2 self y, 3 fallback
+    std::vector<double> dl;  // sorted lag offsets of this task
+};
+// Window tasks of one launch: tile sizes, LDS size, work items.
+struct WinLaunch {
+    std::vector<WinPlan> plans;
+    std::vector<WinTask> wt;
+    std::vector<int64_t> item0, wk0, r0;
+    int64_t nitems = 0, total_rows = 0, nred1 = 0;
+    int cap = 256, jmax = 64;
+    double work = 0.0;
+};
+
+// A spectral problem and its grid geometry.
+struct SpecPlan {
+    int64_t prob;
+    SpecGeom g;
+};
+
+struct Phase2Tables {  // phase-2 tables (device views, host staging)
+    WinTask* wt;
+    int64_t *item0, *wk0, *r0;
+    double* dl;
+    SpecTask* st;
+    int64_t *tile0, *pos0, *sk0, *pair0, *fe0;
+    int32_t* smap;
+    int32_t* rinfo;
+    double* ev;
+    void** gfwd;
+    void** ginv;
+    int32_t* rowk;   // evaluation index of each window row (-1: none)
+    uint64_t* mask;  // fallback flags, written on the device and read back
+};
+
+struct Phase3Tables {  // phase-3 tables
+    int32_t* status;  // first: right after the flag masks when merged
+    double* rmin;     // smallest lag-0 scale per problem (comes back with the statuses)
+    WinTask* wt;
+    int64_t *item0, *wk0, *r0;
+    double* dl;
+    int32_t* fbrow;
+    int32_t* perm;
+    NormTask* nt;
+    IoBlock* io;
+};
+
+// The steps of one call, in order (run): the moments and the standardization
+// (A1), the route choice and the lag rows, the window tasks (A7), the grid
+// geometry of the spectral problems (A2), the device workspace, the phase-2
+// tables and their upload, the launches of the window scan and of the
+// spectral route (A3-A6), the fallback flags of the spectral pair counts,
+// then phase 3 (fallback window scans, normalization A8, outputs) and the
+// statuses. State that crosses steps lives in the members; every window
+// launch checks its tasks' input arrays in check_win.
+class CallRun {
+   public:
+    CallRun(Job& job, const double* const* t, const double* const* x, const double* const* e)
+        : J(job), tin(t), xin(x), ein(e), R(*job.res) {}
+    int run();
+
+   private:
+    void init_flags();
+    int moments();
+    int plan_route();
+    void plan_window(WinLaunch& W);
+    int check_win(const WinLaunch& W, uint32_t f) const;
+    void plan_windows();
+    int plan_spectral();
+    int alloc_phase2();
+    void take2(Tables& tb);
+    void take3(Tables& tb, int ntw2, size_t ndl2, bool any_fb);
+    int tables_phase2();
+    void fill3(int ntw2, bool any_fb);
+    int record_window();
+    int record_spectral();
+    int record_flags();
+    void read_flags();
+    int launch3(int ntw2, bool with_masks);
+    int separate3();
+    int done();
+    const SeriesStat& stat_of(int si, int64_t s) const { return stats[J.set[si].sd0 + s]; }
+
+    Job& J;
+    const double* const* tin;
+    const double* const* xin;
+    const double* const* ein;
+    Resources& R;
+    // route and arrays (init_flags)
+    bool fp64 = false, spectral = false, rect = false, weighted = false;
+    int nsets = 1;
+    std::vector<char> short_p;  // problems with a series too short for the spectral route
+    bool any_short = false, numer_in_window = false, need_v32 = false, need_v64 = false,
+         need_prefix = false, v32_needed = false, v64_needed = false;
+    // phase 1
+    std::vector<SeriesDesc> sdesc;
+    std::vector<Chunk> chunks;
+    int nsd = 0, nch = 0;
+    double *d_cpart = nullptr, *d_ctot = nullptr, *d_lagc = nullptr;
+    SeriesStat* d_stats = nullptr;
+    Chunk* d_ch = nullptr;
+    MomentsArgs ma{};
+    std::vector<SeriesStat> stats;
+    std::vector<int> pstat;
+    // route choice, lag rows, window flags
+    int64_t K = 0;
+    double maxlag = 0.0;
+    std::vector<SpecGeom> geom;
+    std::vector<char> have_geom, direct_p;
+    bool any_direct = false, spec_b = false, spec_w = false, spec_unw = false;
+    double beta = 0.1;
+    std::vector<std::pair<double, int>> rows;
+    int Krow = 0;
+    std::vector<double> delta;
+    std::vector<int32_t> perm;
+    int row0 = -1;
+    uint32_t wflags = 0;
+    // window launches: main pass, fallback pass
+    WinLaunch W1, W2;
+    int ntw = 0;
+    // spectral problems and their device arrays
+    std::vector<SpecPlan> splans;
+    int nts = 0, Keval = 0;
+    size_t csz = 8;
+    bool two_grids = false, three_grids = false;
+    int nfwd = 1;
+    std::vector<void*> grids, gridbs, gridcs, ybufs;
+    std::vector<double*> fparts, numer, bspec, spart, bunw;
+    int64_t ntiles_all = 0;
+    bool bounds_pass = false;
+    int64_t* d_rng = nullptr;
+    double *d_c = nullptr, *d_b = nullptr;
+    int64_t* d_cnt = nullptr;
+    // tables
+    Phase2Tables dT{}, hT{};
+    Phase3Tables dU{}, hU{};
+    int fwords = 1;
+    bool flag_pass = false, speculate = false, merge3 = false, combine = false;
+    size_t ndl = 0;
+    Tables t2;
+    Staging* stg2 = nullptr;
+    std::map<int64_t, FftPlan> plans;
+    int64_t total_pos = 0, ntiles = 0, total_samp = 0, total_pairs = 0, fold_blocks = 0,
+            mid_out = 0;
+    bool fold_chunks = false;
+    double spread_bytes = 0.0;
+    std::vector<std::pair<int, int>> groups, fwd_groups, inv_groups;
+    std::vector<int> spec_of;
+    std::vector<std::vector<int>> flagged;
+    unsigned long long* qbase = nullptr;
+    int32_t* h_fstat = nullptr;
+    double* h_rmin = nullptr;
+};
+
+// Route flags and the derived arrays the call needs.
+void CallRun::init_flags() {
+    fp64 = J.opt.precision == NCF_FP64;
+    spectral = use_spectral(J);  // may turn to the window route after phase 1
+    rect = J.kern == NCF_RECTANGLE;
+    nsets = J.ccf ? 2 : 1;
+    weighted = false;
     for (int si = 0; si < nsets; ++si) weighted |= (ein[si] != nullptr);
     // problems with a series shorter than kMinSpectralSamples take the direct
     // window sums on every route (the spectral route makes no accuracy claim
     // for them); the lengths are known from the offsets
-    std::vector<char> short_p((size_t)J.nprob, 0);
-    bool any_short = false;
+    short_p.assign((size_t)J.nprob, 0);
+    any_short = false;
     for (int64_t p = 0; p < J.nprob; ++p) {
         for (int si = 0; si < nsets; ++si)
             if (J.set[si].offs[p + 1] - J.set[si].offs[p] < kMinSpectralSamples) short_p[p] = 1;
         any_short |= short_p[p] != 0;
     }
-    const bool numer_in_window = !spectral;  // C from the window scan
-    const bool need_v32 = spectral && !fp64;
+    numer_in_window = !spectral;  // C from the window scan
+    need_v32 = spectral && !fp64;
     // FP64 values: FP64 spreading, and every Gaussian window pass (its direct
     // numerator backs up the spectral one at lags with few pairs), and the
     // rectangle window numerator of the direct problems
-    const bool need_v64 = (spectral && fp64) || numer_in_window || !rect || any_short;
+    need_v64 = (spectral && fp64) || numer_in_window || !rect || any_short;
     // prefix sums for the rectangle window pass: values (numerator in the
     // window), weights and the nonzero-weight count (weighted calls)
-    const bool need_prefix = rect && !J.regular;
-    const bool v32_needed = need_v32 && !J.regular;
-    const bool v64_needed = need_v64 || J.regular;
+    need_prefix = rect && !J.regular;
+    v32_needed = need_v32 && !J.regular;
+    v64_needed = need_v64 || J.regular;
+}
 
+// Phase 1 (A1): per-chunk moments of every series, the statistics and the
+// per-problem statuses back on the host, then the standardization (and the
+// prefix sums) of all series in one launch.
+int CallRun::moments() {
     // ------------------------------------------------ phase 1: A1 moments
     // chunks of every series of every set, one launch for all of them
-    std::vector<SeriesDesc> sdesc;
-    std::vector<Chunk> chunks;
+    sdesc.clear();
+    chunks.clear();
     for (int si = 0; si < nsets; ++si) {
         SeriesSet& S = J.set[si];
         S.sd0 = (int)sdesc.size();
@@ -1052,13 +1216,13 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             sdesc.push_back(d);
         }
     }
-    const int nsd = (int)sdesc.size();
-    const int nch = (int)chunks.size();
+    nsd = (int)sdesc.size();
+    nch = (int)chunks.size();
 
     // device workspace of phase 1: inputs (host mode), derived arrays, partials
     const bool lags_with_stats = J.lags_dev && !J.rec;
-    auto layout1 = [&](Arena& ar, double** d_cpart, double** d_ctot, SeriesStat** d_stats,
-                       double** d_lagc) {
+    auto layout1 = [&](Arena& ar, double** o_cpart, double** o_ctot, SeriesStat** o_stats,
+                       double** o_lagc) {
         for (int si = 0; si < nsets; ++si) {
             SeriesSet& S = J.set[si];
             if (J.dev_ptrs) {
@@ -1081,19 +1245,16 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             S.pw = (need_prefix && weighted) ? ar.take<double>(S.ntot + S.nser) : nullptr;
             S.pz = (need_prefix && weighted) ? ar.take<double>(S.ntot + S.nser) : nullptr;
         }
-        *d_cpart = ar.take<double>(4 * (size_t)nch);
-        *d_ctot = ar.take<double>(3 * (size_t)nch);
-        *d_stats = ar.take<SeriesStat>(nsd);
+        *o_cpart = ar.take<double>(4 * (size_t)nch);
+        *o_ctot = ar.take<double>(3 * (size_t)nch);
+        *o_stats = ar.take<SeriesStat>(nsd);
         // device lags of a one-shot call: copied next to the statistics by
         // the moments launch, so one readback brings both (recorded launches
         // must not keep the caller's lag pointer: they copy them apart)
-        *d_lagc = ar.take<double>(lags_with_stats ? J.K : 0);
+        *o_lagc = ar.take<double>(lags_with_stats ? J.K : 0);
     };
-    double *d_cpart, *d_ctot, *d_lagc;
-    SeriesStat* d_stats;
     Arena a1;
     layout1(a1, &d_cpart, &d_ctot, &d_stats, &d_lagc);
-    Resources& R = *J.res;
     void* ws1 = nullptr;
     NCF_TRY(ensure_ws(R, 0, a1.off + 256, &ws1));
     a1 = Arena{(char*)ws1, 0};
@@ -1152,7 +1313,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     IoBlock* h_io1;
     SeriesStat* h_stats;
     SeriesDesc* d_sd = t1.take<SeriesDesc>(nsd, &h_sd);
-    Chunk* d_ch = t1.take<Chunk>(nch, &h_ch);
+    d_ch = t1.take<Chunk>(nch, &h_ch);
     IoBlock* d_io1 = t1.take<IoBlock>(1, &h_io1);
     // host landing area of the statistics (and of the lag copy behind them,
     // laid out as on the device)
@@ -1168,7 +1329,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     for (int si = 0; si < nsets; ++si) h_io1->x[si] = J.set[si].x;
     const size_t up1 = (size_t)((char*)h_stats - stg1->h);
     NCF_TRY_HIP(hipMemcpyAsync(stg1->d, stg1->h, up1, hipMemcpyHostToDevice, J.st));
-    MomentsArgs ma{};
+    ma = MomentsArgs{};
     ma.series = d_sd;
     ma.chunks = d_ch;
     ma.nseries = nsd;
@@ -1183,7 +1344,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         ma.lag_dst = d_lagc;
         ma.nlag = J.K;
     }
-    NCF_TRY(emit(J, [ma](hipStream_t s) { return launch_moments(ma, s); }));
+    NCF_TRY(emit(J, [m = ma](hipStream_t s) { return launch_moments(m, s); }));
     NCF_TRY_HIP(hipMemcpyAsync(h_span, d_stats, stat_span, hipMemcpyDeviceToHost, J.st));
     if (J.lags_dev && !lags_with_stats)
         NCF_TRY_HIP(hipMemcpyAsync(h_lags, J.lags_dev, sizeof(double) * J.K,
@@ -1194,13 +1355,10 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         J.lags_dev = nullptr;
         NCF_TRY(check_lags(J));
     }
-    std::vector<SeriesStat> stats(h_stats, h_stats + nsd);
-    auto stat_of = [&](int si, int64_t s) -> const SeriesStat& {
-        return stats[J.set[si].sd0 + s];
-    };
+    stats.assign(h_stats, h_stats + nsd);
 
     // per-problem status from its series
-    std::vector<int> pstat(J.nprob, NCF_OK);
+    pstat.assign(J.nprob, NCF_OK);
     for (int64_t p = 0; p < J.nprob; ++p) {
         for (int si = 0; si < nsets; ++si) {
             int s = stat_of(si, p).status;
@@ -1211,12 +1369,16 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     }
 
     // standardization (+ prefix sums), all series in one launch
-    NCF_TRY(emit(J, [ma](hipStream_t s) { return launch_standardize(ma, s); }));
-    if (J.regular) return run_regular(J, sdesc, stats, pstat, d_stats);
+    NCF_TRY(emit(J, [m = ma](hipStream_t s) { return launch_standardize(m, s); }));
+    return NCF_OK;
+}
 
+// Route choice (the K* crossover of NCF_AUTO), the sorted lag rows of the
+// window scans and the window flags.
+int CallRun::plan_route() {
     // ------------------------------------------------ phase 2 planning (host)
-    const int64_t K = J.K;
-    double maxlag = 0.0;
+    K = J.K;
+    maxlag = 0.0;
     for (double v : J.lags) maxlag = std::max(maxlag, std::fabs(v));
     // NCF_AUTO, Gaussian: the real-space route (direct window sums) when its
     // work is below the spectral pipeline's, the paper's K* crossover
@@ -1237,11 +1399,11 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             !J.tune.eval_interp && mid_supported(J.ccf, sb, su, fp64))
             J.lag_unit = lag_lattice_unit(J.lags, !J.ccf);
     }
-    std::vector<SpecGeom> geom((size_t)J.nprob);
-    std::vector<char> have_geom((size_t)J.nprob, 0);
+    geom.assign((size_t)J.nprob, SpecGeom{});
+    have_geom.assign((size_t)J.nprob, 0);
     if (spectral && J.opt.method == NCF_AUTO && J.kern == NCF_GAUSSIAN &&
         !(J.opt.flags & NCF_SPECTRAL_ALWAYS)) {
-        const double rows = (double)(J.ccf ? K : K + 1);
+        const double nrows = (double)(J.ccf ? K : K + 1);
         const double rate = fp64 ? 2e12 : 5e12;
         const double csz_b = fp64 ? 16.0 : 8.0;
         double direct_s = 0.0, spec_s = 30e-6;
@@ -1252,7 +1414,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             const double n1 = J.ccf ? (double)(J.set[1].offs[p + 1] - J.set[1].offs[p]) : n0;
             const double dens = (n0 - 1.0) / std::max(s0.tmax - s0.tmin, 1e-300);
             const double pts = dens * 12.0 * J.h[p];
-            const double windows = n1 * rows + (J.ccf ? n0 + n1 : 0.0);
+            const double windows = n1 * nrows + (J.ccf ? n0 + n1 : 0.0);
             direct_s += windows * (8.0 + 8.0 * pts) / rate;
             double tmin = s0.tmin, tmax = s0.tmax;
             if (J.ccf) {
@@ -1272,8 +1434,8 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         if (direct_s < spec_s) spectral = false;
     }
     // per problem: the direct window sums (no spectral grid)
-    std::vector<char> direct_p((size_t)J.nprob, 0);
-    bool any_direct = false;
+    direct_p.assign((size_t)J.nprob, 0);
+    any_direct = false;
     for (int64_t p = 0; p < J.nprob; ++p) {
         direct_p[p] = (!spectral || short_p[p]) ? 1 : 0;
         any_direct |= direct_p[p] != 0;
@@ -1284,17 +1446,17 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     // Weighted calls: the pair-count channel carries the weights and yields
     // B; one more channel with unit weights yields the unweighted b, unless
     // the caller does not read b (then b is reported equal to B).
-    const bool spec_b = spectral && !rect && J.opt.method == NCF_AUTO;
-    const bool spec_w = spec_b && weighted;
-    const bool spec_unw = spec_w && !J.no_b;
+    spec_b = spectral && !rect && J.opt.method == NCF_AUTO;
+    spec_w = spec_b && weighted;
+    spec_unw = spec_w && !J.no_b;
     // Mixed: the FP32 transforms leave |dN|, |db| ~ 7e-7 b_ref on every lag, so
     // |dc| ~ 2 * 7e-7 b_ref / b stays below 1e-5 for b >= 0.1 b_ref. FP64: the
     // limit is the 6h truncation of the window scan, whose effect is
     // relatively large where a lag has few pairs.
-    const double beta = fp64 ? 1e-2 : 0.1;
+    beta = fp64 ? 1e-2 : 0.1;
     // window lag rows: sorted offsets delta = eps * tau (ACF: plus lag 0)
     const double epsv = J.ccf ? -1.0 : 1.0;
-    std::vector<std::pair<double, int>> rows;
+    rows.clear();
     for (int64_t k = 0; k < K; ++k) rows.push_back({epsv * J.lags[k], (int)k});
     bool have0 = false;
     for (double v : J.lags) have0 |= (v == 0.0);
@@ -1303,10 +1465,10 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
                      [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
                          return a.first < b.first;
                      });
-    const int Krow = (int)rows.size();
-    std::vector<double> delta(std::max(Krow, 1), 0.0);
-    std::vector<int32_t> perm(std::max<int64_t>(K, 1), 0);
-    int row0 = -1;
+    Krow = (int)rows.size();
+    delta.assign(std::max(Krow, 1), 0.0);
+    perm.assign(std::max<int64_t>(K, 1), 0);
+    row0 = -1;
     for (int r = 0; r < Krow; ++r) {
         delta[r] = rows[r].first;
         if (rows[r].second >= 0) perm[rows[r].second] = r;
@@ -1316,184 +1478,174 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     // window flags: the rectangle numerator is always the prefix form; the
     // Gaussian window pass also sums the direct numerator (its weights are
     // already computed), used where the window b is small
-    uint32_t wflags = 0;
+    wflags = 0;
     if (rect) wflags |= WIN_RECT;
     if (!rect || numer_in_window) wflags |= WIN_NUMER;
     if (weighted) wflags |= WIN_WEIGHTED;
     if (fp64 && !rect) wflags |= WIN_EXP64;
-    const bool wnumer = (wflags & WIN_NUMER) != 0;
 
     // the rectangle window numerator is needed only by the direct problems
     if (rect && !numer_in_window && !any_direct) wflags &= ~(uint32_t)WIN_NUMER;
+    return NCF_OK;
+}
 
-    struct WinPlan {
-        int wi_set, wo_set;  // window set, outer set (series index = problem)
-        int64_t prob;
-        int role;            // 0 main, 1 self x, 2 self y, 3 fallback
-        std::vector<double> dl;  // sorted lag offsets of this task
-    };
-    // Plan window tasks: tile sizes, LDS size, work items.
-    struct WinLaunch {
-        std::vector<WinPlan> plans;
-        std::vector<WinTask> wt;
-        std::vector<int64_t> item0, wk0, r0;
-        int64_t nitems = 0, total_rows = 0, nred1 = 0;
-        int cap = 256, jmax = 64;
-        double work = 0.0;
-    };
-    auto plan_window = [&](WinLaunch& W) {
-        // staged window arrays: times, values (or their prefix), weights (or
-        // their prefix and, rectangle, the nonzero-weight count prefix)
-        const int arrays = 1 + ((W.plans.empty() ? false : ((wflags & WIN_NUMER) != 0)) ? 1 : 0) +
-                           (weighted ? (rect ? 2 : 1) : 0);
-        const int jmax = 1024;
-        // LDS per workgroup (doubles): Gaussian items stage the window arrays
-        // and their outer samples; rectangle items stage only the window
-        // arrays and keep a smaller footprint, for more resident workgroups
-        const int budget = (rect ? 24 : 40) * 1024 / 8;
-        int cap = rect ? budget / arrays - 8 : (budget - jmax * arrays) / arrays - 8;
-        cap = std::max(256, std::min(4096, cap));
-        const int ntw = (int)W.plans.size();
-        W.wt.assign(ntw, WinTask{});
-        W.item0.assign(ntw + 1, 0);
-        W.wk0.assign(ntw + 1, 0);
-        W.r0.assign(ntw + 1, 0);
-        std::vector<std::array<double, 3>> dens(ntw);  // window / outer density, extent
-        for (int i = 0; i < ntw; ++i) {
-            const WinPlan& P = W.plans[i];
-            const SeriesSet& SW = J.set[P.wi_set];
-            const SeriesSet& SO = J.set[P.wo_set];
-            const SeriesDesc& dw = sdesc[SW.sd0 + P.prob];
-            const SeriesDesc& dO = sdesc[SO.sd0 + P.prob];
-            const SeriesStat& sw = stat_of(P.wi_set, P.prob);
-            const SeriesStat& so = stat_of(P.wo_set, P.prob);
-            const double h = J.h[P.prob];
-            WinTask T{};
-            T.t = dw.t;
-            T.n_win = dw.n;
-            T.s = dO.t;
-            T.n_out = dO.n;
-            if (wflags & WIN_NUMER) {
-                if (rect)
-                    T.pv = dw.pv;
-                else
-                    T.v = dw.v64;
-                T.vo = dO.v64;
+// Tile sizes, LDS size and work items of the window tasks in W.
+void CallRun::plan_window(WinLaunch& W) {
+    // staged window arrays: times, values (or their prefix), weights (or
+    // their prefix and, rectangle, the nonzero-weight count prefix)
+    const int arrays = 1 + ((W.plans.empty() ? false : ((wflags & WIN_NUMER) != 0)) ? 1 : 0) +
+                       (weighted ? (rect ? 2 : 1) : 0);
+    const int jmax = 1024;
+    // LDS per workgroup (doubles): Gaussian items stage the window arrays
+    // and their outer samples; rectangle items stage only the window
+    // arrays and keep a smaller footprint, for more resident workgroups
+    const int budget = (rect ? 24 : 40) * 1024 / 8;
+    int cap = rect ? budget / arrays - 8 : (budget - jmax * arrays) / arrays - 8;
+    cap = std::max(256, std::min(4096, cap));
+    const int ntask = (int)W.plans.size();
+    W.wt.assign(ntask, WinTask{});
+    W.item0.assign(ntask + 1, 0);
+    W.wk0.assign(ntask + 1, 0);
+    W.r0.assign(ntask + 1, 0);
+    std::vector<std::array<double, 3>> dens(ntask);  // window / outer density, extent
+    for (int i = 0; i < ntask; ++i) {
+        const WinPlan& P = W.plans[i];
+        const SeriesSet& SW = J.set[P.wi_set];
+        const SeriesSet& SO = J.set[P.wo_set];
+        const SeriesDesc& dw = sdesc[SW.sd0 + P.prob];
+        const SeriesDesc& dO = sdesc[SO.sd0 + P.prob];
+        const SeriesStat& sw = stat_of(P.wi_set, P.prob);
+        const SeriesStat& so = stat_of(P.wo_set, P.prob);
+        const double h = J.h[P.prob];
+        WinTask T{};
+        T.t = dw.t;
+        T.n_win = dw.n;
+        T.s = dO.t;
+        T.n_out = dO.n;
+        if (wflags & WIN_NUMER) {
+            if (rect)
+                T.pv = dw.pv;
+            else
+                T.v = dw.v64;
+            T.vo = dO.v64;
+        }
+        if (weighted) {
+            if (rect) {
+                T.pw = dw.pw;
+                T.pz = dw.pz;
+            } else {
+                T.w = dw.w64;
             }
-            if (weighted) {
-                if (rect) {
-                    T.pw = dw.pw;
-                    T.pz = dw.pz;
-                } else {
-                    T.w = dw.w64;
-                }
-                T.wo = dO.w64;
-            }
-            T.K = (int32_t)P.dl.size();
-            T.h = h;
-            T.W = rect ? h : 6.0 * h;
-            double lext = 0.0;
-            for (size_t r = 0; r < P.dl.size(); r += 64) {
-                const size_t r1 = std::min(P.dl.size(), r + 64) - 1;
-                lext = std::max(lext, P.dl[r1] - P.dl[r]);
-            }
-            const double span_w = std::max(sw.tmax - sw.tmin, 1e-300);
-            const double span_o = std::max(so.tmax - so.tmin, 1e-300);
-            const double dens_w = (double)(dw.n - 1) / span_w;
-            const double dens_o = (double)(dO.n - 1) / span_o;
-            const int n_kt = (int)ceil_div(T.K, 64);
-            const double ext = lext + 2.0 * T.W;
-            auto est = [&](int64_t j) { return dens_w * ((double)j / dens_o + ext) + 2.0; };
-            // outer samples per workgroup: as many as keep the window range in
-            // LDS (half the capacity, for clustering) while leaving at least
-            // 2048 work items (eight per CU) when the problem is big enough
-            int64_t Jt = 64;
-            while (Jt * 2 <= jmax && est(Jt * 2) <= 0.5 * cap &&
-                   (double)dO.n * n_kt / (double)(Jt * 2) >= 2048.0)
-                Jt *= 2;
-            while (Jt > 16 && est(Jt) > 0.5 * cap) Jt /= 2;
-            if (J.tune.jscale > 0) Jt = std::min<int64_t>(Jt << J.tune.jscale, jmax);
-            if (J.tune.jscale < 0) Jt = std::max<int64_t>(Jt >> -J.tune.jscale, 16);
-            T.J = (int32_t)Jt;
-            T.n_kt = n_kt;
-            dens[i] = {dens_w, dens_o, ext};
-            // algorithmic work: per (j, k) window, searches + per-point weight ops
-            const double pts = rect ? 0.0 : dens_w * 2.0 * T.W;
-            W.work += (double)dO.n * T.K * (8.0 + (rect ? 4.0 : 8.0 * pts));
-            W.wt[i] = T;
+            T.wo = dO.w64;
         }
-        // the launch has one LDS size, set by the largest footprint
-        double need = 0.0;
-        int jneed = 16;
-        auto est_of = [&](int i, int64_t j) {
-            return dens[i][0] * ((double)j / dens[i][1] + dens[i][2]) + 2.0;
-        };
-        for (int i = 0; i < ntw; ++i) {
-            need = std::max(need, est_of(i, W.wt[i].J));
-            jneed = std::max(jneed, (int)W.wt[i].J);
+        T.K = (int32_t)P.dl.size();
+        T.h = h;
+        T.W = rect ? h : 6.0 * h;
+        double lext = 0.0;
+        for (size_t r = 0; r < P.dl.size(); r += 64) {
+            const size_t r1 = std::min(P.dl.size(), r + 64) - 1;
+            lext = std::max(lext, P.dl[r1] - P.dl[r]);
         }
-        // LDS: twice the estimated window range (clustering margin), rounded up
-        const int want = (int)std::min<double>(cap, round_up((int64_t)(2.0 * need) + 64, 64));
-        W.cap = std::max(256, want);
-        W.jmax = (int)round_up(jneed, 64);
-        // items of few lags (e.g. the lag-0 scale tasks) grow within that
-        // footprint until they hold ~8192 windows: a workgroup's searches and
-        // staging cost the same for any size
-        for (int i = 0; i < ntw; ++i) {
-            WinTask& T = W.wt[i];
-            const int64_t kin = std::min<int64_t>(T.K, 64);
-            int64_t Jt = T.J;
-            while (Jt * 2 <= W.jmax && est_of(i, Jt * 2) <= 0.5 * W.cap && Jt * 2 * kin <= 8192)
-                Jt *= 2;
-            T.J = (int32_t)Jt;
-        }
-        // j-tiles per work item: one item per tile while that leaves the
-        // launch few items; more tiles per item (one partial per group of
-        // tiles) when the launch has many
-        int64_t tiles = 0;
-        for (int i = 0; i < ntw; ++i) {
-            WinTask& T = W.wt[i];
-            T.n_jt = (int32_t)ceil_div(T.n_out, T.J);
-            tiles += (int64_t)T.n_jt * T.n_kt;
-        }
-        const int G = (int)std::max<int64_t>(1, std::min<int64_t>(kWinGroupMax,
-                                                                  tiles / kWinItemsMin));
-        for (int i = 0; i < ntw; ++i) {
-            WinTask& T = W.wt[i];
-            T.G = G;
-            T.n_jg = (int32_t)ceil_div(T.n_jt, G);
-            T.item0 = W.nitems;
-            W.item0[i] = W.nitems;
-            W.wk0[i] = W.total_rows;
-            W.r0[i] = W.nred1;
-            W.nitems += (int64_t)T.n_jg * T.n_kt;
-            W.nred1 += (int64_t)T.n_kt * ceil_div(T.n_jg, kWinJc);
-            W.total_rows += T.K;
-        }
-        W.item0[ntw] = W.nitems;
-        W.wk0[ntw] = W.total_rows;
-        W.r0[ntw] = W.nred1;
+        const double span_w = std::max(sw.tmax - sw.tmin, 1e-300);
+        const double span_o = std::max(so.tmax - so.tmin, 1e-300);
+        const double dens_w = (double)(dw.n - 1) / span_w;
+        const double dens_o = (double)(dO.n - 1) / span_o;
+        const int n_kt = (int)ceil_div(T.K, 64);
+        const double ext = lext + 2.0 * T.W;
+        auto est = [&](int64_t j) { return dens_w * ((double)j / dens_o + ext) + 2.0; };
+        // outer samples per workgroup: as many as keep the window range in
+        // LDS (half the capacity, for clustering) while leaving at least
+        // 2048 work items (eight per CU) when the problem is big enough
+        int64_t Jt = 64;
+        while (Jt * 2 <= jmax && est(Jt * 2) <= 0.5 * cap &&
+               (double)dO.n * n_kt / (double)(Jt * 2) >= 2048.0)
+            Jt *= 2;
+        while (Jt > 16 && est(Jt) > 0.5 * cap) Jt /= 2;
+        if (J.tune.jscale > 0) Jt = std::min<int64_t>(Jt << J.tune.jscale, jmax);
+        if (J.tune.jscale < 0) Jt = std::max<int64_t>(Jt >> -J.tune.jscale, 16);
+        T.J = (int32_t)Jt;
+        T.n_kt = n_kt;
+        dens[i] = {dens_w, dens_o, ext};
+        // algorithmic work: per (j, k) window, searches + per-point weight ops
+        const double pts = rect ? 0.0 : dens_w * 2.0 * T.W;
+        W.work += (double)dO.n * T.K * (8.0 + (rect ? 4.0 : 8.0 * pts));
+        W.wt[i] = T;
+    }
+    // the launch has one LDS size, set by the largest footprint
+    double need = 0.0;
+    int jneed = 16;
+    auto est_of = [&](int i, int64_t j) {
+        return dens[i][0] * ((double)j / dens[i][1] + dens[i][2]) + 2.0;
     };
+    for (int i = 0; i < ntask; ++i) {
+        need = std::max(need, est_of(i, W.wt[i].J));
+        jneed = std::max(jneed, (int)W.wt[i].J);
+    }
+    // LDS: twice the estimated window range (clustering margin), rounded up
+    const int want = (int)std::min<double>(cap, round_up((int64_t)(2.0 * need) + 64, 64));
+    W.cap = std::max(256, want);
+    W.jmax = (int)round_up(jneed, 64);
+    // items of few lags (e.g. the lag-0 scale tasks) grow within that
+    // footprint until they hold ~8192 windows: a workgroup's searches and
+    // staging cost the same for any size
+    for (int i = 0; i < ntask; ++i) {
+        WinTask& T = W.wt[i];
+        const int64_t kin = std::min<int64_t>(T.K, 64);
+        int64_t Jt = T.J;
+        while (Jt * 2 <= W.jmax && est_of(i, Jt * 2) <= 0.5 * W.cap && Jt * 2 * kin <= 8192)
+            Jt *= 2;
+        T.J = (int32_t)Jt;
+    }
+    // j-tiles per work item: one item per tile while that leaves the
+    // launch few items; more tiles per item (one partial per group of
+    // tiles) when the launch has many
+    int64_t tiles = 0;
+    for (int i = 0; i < ntask; ++i) {
+        WinTask& T = W.wt[i];
+        T.n_jt = (int32_t)ceil_div(T.n_out, T.J);
+        tiles += (int64_t)T.n_jt * T.n_kt;
+    }
+    const int G = (int)std::max<int64_t>(1, std::min<int64_t>(kWinGroupMax,
+                                                              tiles / kWinItemsMin));
+    for (int i = 0; i < ntask; ++i) {
+        WinTask& T = W.wt[i];
+        T.G = G;
+        T.n_jg = (int32_t)ceil_div(T.n_jt, G);
+        T.item0 = W.nitems;
+        W.item0[i] = W.nitems;
+        W.wk0[i] = W.total_rows;
+        W.r0[i] = W.nred1;
+        W.nitems += (int64_t)T.n_jg * T.n_kt;
+        W.nred1 += (int64_t)T.n_kt * ceil_div(T.n_jg, kWinJc);
+        W.total_rows += T.K;
+    }
+    W.item0[ntask] = W.nitems;
+    W.wk0[ntask] = W.total_rows;
+    W.r0[ntask] = W.nred1;
+}
 
-    // every array that a window pass reads must exist: checked on the host
-    // before the launch, since a missing one would be read on the device
-    auto check_win = [&](const WinLaunch& W, uint32_t f) -> int {
-        const bool numer = (f & WIN_NUMER) != 0, wtd = (f & WIN_WEIGHTED) != 0;
-        for (const WinTask& T : W.wt) {
-            bool ok = T.t != nullptr && T.s != nullptr;
-            if (numer) ok = ok && (rect ? T.pv != nullptr : T.v != nullptr) && T.vo != nullptr;
-            if (wtd)
-                ok = ok && (rect ? (T.pw != nullptr && T.pz != nullptr) : T.w != nullptr) &&
-                     T.wo != nullptr;
-            if (!ok) {
-                set_error("window pass: a task lacks one of its input arrays");
-                return NCF_E_INVALID_ARG;
-            }
+// every array that a window pass reads must exist: checked on the host
+// before the launch, since a missing one would be read on the device
+int CallRun::check_win(const WinLaunch& W, uint32_t f) const {
+    const bool need_num = (f & WIN_NUMER) != 0, wtd = (f & WIN_WEIGHTED) != 0;
+    for (const WinTask& T : W.wt) {
+        bool ok = T.t != nullptr && T.s != nullptr;
+        if (need_num) ok = ok && (rect ? T.pv != nullptr : T.v != nullptr) && T.vo != nullptr;
+        if (wtd)
+            ok = ok && (rect ? (T.pw != nullptr && T.pz != nullptr) : T.w != nullptr) &&
+                 T.wo != nullptr;
+        if (!ok) {
+            set_error("window pass: a task lacks one of its input arrays");
+            return NCF_E_INVALID_ARG;
         }
-        return NCF_OK;
-    };
+    }
+    return NCF_OK;
+}
 
-    WinLaunch W1;
+// The main window launch: every problem that the spectral route does not
+// take whole (its numerator and pair counts, or the CCF lag-0 scales).
+void CallRun::plan_windows() {
+    W1 = WinLaunch{};
     for (int64_t p = 0; p < J.nprob; ++p) {
         if (pstat[p] != NCF_OK || (spec_b && !direct_p[p])) continue;
         if (!J.ccf) {
@@ -1506,15 +1658,13 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     }
     if (Krow == 0) delta.assign(1, 0.0);
     plan_window(W1);
-    const int ntw = (int)W1.plans.size();
-    (void)wnumer;
+    ntw = (int)W1.plans.size();
+}
 
-    // spectral problems, sorted by grid size so grids of one size are contiguous
-    struct SpecPlan {
-        int64_t prob;
-        SpecGeom g;
-    };
-    std::vector<SpecPlan> splans;
+// Spectral problems (A2), sorted by grid size so grids of one size are
+// contiguous, and the grids each needs.
+int CallRun::plan_spectral() {
+    splans.clear();
     if (spectral) {
         for (int64_t p = 0; p < J.nprob; ++p) {
             if (pstat[p] != NCF_OK || direct_p[p]) continue;
@@ -1534,8 +1684,8 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         std::stable_sort(splans.begin(), splans.end(),
                          [](const SpecPlan& a, const SpecPlan& b) { return a.g.N < b.g.N; });
     }
-    const int nts = (int)splans.size();
-    const int Keval = (int)(J.ccf ? K : K + 1);
+    nts = (int)splans.size();
+    Keval = (int)(J.ccf ? K : K + 1);
     J.info_grids = nts;
     J.info_grid_cells = 0;
     J.info_fold_grids = 0;
@@ -1545,27 +1695,35 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     }
     J.info_window_items = W1.nitems;
     J.info_window_launches = ntw > 0 ? 1 : 0;
-    const size_t csz = fp64 ? 16 : 8;
+    csz = fp64 ? 16 : 8;
     // second grid: the CCF pair-count channels, or the ACF unit channel of a
     // weighted call; third grid: the CCF unit channels of a weighted call
-    const bool two_grids = (spec_b && J.ccf) || spec_unw;
-    const bool three_grids = spec_unw && J.ccf;
-    const int nfwd = 1 + (two_grids ? 1 : 0) + (three_grids ? 1 : 0);
+    two_grids = (spec_b && J.ccf) || spec_unw;
+    three_grids = spec_unw && J.ccf;
+    nfwd = 1 + (two_grids ? 1 : 0) + (three_grids ? 1 : 0);
+    return NCF_OK;
+}
 
-    // ------------------------------------------------ phase 2 device workspace
-    std::vector<void*> grids(nts), gridbs(nts, nullptr), gridcs(nts, nullptr),
-        ybufs(nts, nullptr);
-    std::vector<double*> fparts(nts, nullptr);
-    std::vector<double*> numer(nts), bspec(nts, nullptr), spart(nts, nullptr),
-        bunw(nts, nullptr);
-    int64_t ntiles_all = 0;
+// Phase-2 device workspace: window partials and sums, grids, per-lag
+// spectral results, spreading-tile ranges and (host-pointer calls) outputs.
+int CallRun::alloc_phase2() {
+    grids.assign(nts, nullptr);
+    gridbs.assign(nts, nullptr);
+    gridcs.assign(nts, nullptr);
+    ybufs.assign(nts, nullptr);
+    fparts.assign(nts, nullptr);
+    numer.assign(nts, nullptr);
+    bspec.assign(nts, nullptr);
+    spart.assign(nts, nullptr);
+    bunw.assign(nts, nullptr);
+    ntiles_all = 0;
     for (int i = 0; i < nts; ++i) ntiles_all += splans[i].g.N / 4096;
     // sample ranges of the spreading tiles: one pass over the samples when
     // there are many tiles; with a few, each spreading workgroup searches
-    const bool bounds_pass = ntiles_all > 4096;
-    int64_t* d_rng = nullptr;  // [tiles][4] sample ranges of every spreading tile
-    double *d_c = nullptr, *d_b = nullptr;
-    int64_t* d_cnt = nullptr;
+    bounds_pass = ntiles_all > 4096;
+    d_rng = nullptr;  // [tiles][4] sample ranges of every spreading tile
+    d_c = d_b = nullptr;
+    d_cnt = nullptr;
     auto layout2 = [&](Arena& ar) {
         for (int i = 0; i < ntw; ++i) {
             WinTask& T = W1.wt[i];
@@ -1611,24 +1769,54 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     NCF_TRY(ensure_ws(R, 1, a2.off + 256, &ws2));
     a2 = Arena{(char*)ws2, 0};
     layout2(a2);
+    return NCF_OK;
+}
 
-    // ------------------------------------------------ phase 2 tables
-    struct T2 {
-        WinTask* wt;
-        int64_t *item0, *wk0, *r0;
-        double* dl;
-        SpecTask* st;
-        int64_t *tile0, *pos0, *sk0, *pair0, *fe0;
-        int32_t* smap;
-        int32_t* rinfo;
-        double* ev;
-        void** gfwd;
-        void** ginv;
-        int32_t* rowk;   // evaluation index of each window row (-1: none)
-        uint64_t* mask;  // fallback flags, written on the device and read back
-    } dT{}, hT{};
-    const int fwords = (int)ceil_div(std::max(Krow, 1), 64);
-    const bool flag_pass = spec_b && nts > 0 && K > 0;
+// Layout of the phase-3 tables in tb (ntw2 fallback window tasks).
+void CallRun::take3(Tables& tb, int ntw2, size_t ndl2, bool any_fb) {
+    dU.status = tb.take<int32_t>(J.nprob, &hU.status);
+    dU.rmin = tb.take<double>(J.nprob, &hU.rmin);
+    dU.wt = tb.take<WinTask>(ntw2, &hU.wt);
+    dU.item0 = tb.take<int64_t>(ntw2 + 1, &hU.item0);
+    dU.wk0 = tb.take<int64_t>(ntw2 + 1, &hU.wk0);
+    dU.r0 = tb.take<int64_t>(ntw2 + 1, &hU.r0);
+    dU.dl = tb.take<double>(ndl2, &hU.dl);
+    // fallback rows: K entries per problem with fallback lags
+    dU.fbrow = tb.take<int32_t>(any_fb ? (size_t)ntw2 * K : 1, &hU.fbrow);
+    dU.perm = tb.take<int32_t>(K, &hU.perm);
+    dU.nt = tb.take<NormTask>(J.nprob, &hU.nt);
+    dU.io = tb.take<IoBlock>(1, &hU.io);
+}
+
+// Layout of the phase-2 tables in tb (with phase 3 behind them when merged).
+void CallRun::take2(Tables& tb) {
+    dT.wt = tb.take<WinTask>(ntw, &hT.wt);
+    dT.item0 = tb.take<int64_t>(ntw + 1, &hT.item0);
+    dT.wk0 = tb.take<int64_t>(ntw + 1, &hT.wk0);
+    dT.r0 = tb.take<int64_t>(ntw + 1, &hT.r0);
+    dT.dl = tb.take<double>(ndl, &hT.dl);
+    dT.st = tb.take<SpecTask>(nts, &hT.st);
+    dT.tile0 = tb.take<int64_t>(nts + 1, &hT.tile0);
+    dT.pos0 = tb.take<int64_t>(nts + 1, &hT.pos0);
+    dT.pair0 = tb.take<int64_t>(nts + 1, &hT.pair0);
+    dT.sk0 = tb.take<int64_t>(nts + 1, &hT.sk0);
+    dT.fe0 = tb.take<int64_t>(nts + 1, &hT.fe0);
+    dT.smap = tb.take<int32_t>(nsd, &hT.smap);
+    dT.rinfo = tb.take<int32_t>(6 * (size_t)nts, &hT.rinfo);
+    dT.ev = tb.take<double>(Keval, &hT.ev);
+    dT.gfwd = tb.take<void*>(3 * (size_t)nts, &hT.gfwd);
+    dT.ginv = tb.take<void*>(2 * (size_t)nts, &hT.ginv);
+    dT.rowk = tb.take<int32_t>(flag_pass ? Krow : 0, &hT.rowk);
+    dT.mask = tb.take<uint64_t>(flag_pass ? (size_t)nts * fwords : 0, &hT.mask);
+    if (merge3) take3(tb, 0, 0, false);  // phase 3 without fallback lags
+}
+
+// Phase-2 tables: window tasks and their lag offsets, spectral tasks, FFT
+// plans and grid groups, the fallback-flag rows; phase 3 travels with them
+// when it does not wait for the flags. One upload.
+int CallRun::tables_phase2() {
+    fwords = (int)ceil_div(std::max(Krow, 1), 64);
+    flag_pass = spec_b && nts > 0 && K > 0;
     // Phase 3 (fallback window scans, normalization, outputs). For the
     // spectral pair counts of a one-shot call it is first enqueued
     // speculatively with no fallback lags, behind the fallback flags: when no
@@ -1643,60 +1831,14 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     // masks and the statuses, adjacent in the staging, come back in one copy
     // (combine).
     constexpr int64_t kSpeculateMaxProblems = 8;
-    const bool speculate = flag_pass && !J.rec && J.nprob <= kSpeculateMaxProblems;
-    const bool merge3 = !flag_pass || speculate;
-    const bool combine = speculate && !J.io_fixed;
-    struct T3 {
-        int32_t* status;  // first: right after the flag masks when merged
-        double* rmin;     // smallest lag-0 scale per problem (comes back with the statuses)
-        WinTask* wt;
-        int64_t *item0, *wk0, *r0;
-        double* dl;
-        int32_t* fbrow;
-        int32_t* perm;
-        NormTask* nt;
-        IoBlock* io;
-    } dU{}, hU{};
-    auto take3 = [&](Tables& tb, int ntw2, size_t ndl2, bool any_fb) {
-        dU.status = tb.take<int32_t>(J.nprob, &hU.status);
-        dU.rmin = tb.take<double>(J.nprob, &hU.rmin);
-        dU.wt = tb.take<WinTask>(ntw2, &hU.wt);
-        dU.item0 = tb.take<int64_t>(ntw2 + 1, &hU.item0);
-        dU.wk0 = tb.take<int64_t>(ntw2 + 1, &hU.wk0);
-        dU.r0 = tb.take<int64_t>(ntw2 + 1, &hU.r0);
-        dU.dl = tb.take<double>(ndl2, &hU.dl);
-        // fallback rows: K entries per problem with fallback lags
-        dU.fbrow = tb.take<int32_t>(any_fb ? (size_t)ntw2 * K : 1, &hU.fbrow);
-        dU.perm = tb.take<int32_t>(K, &hU.perm);
-        dU.nt = tb.take<NormTask>(J.nprob, &hU.nt);
-        dU.io = tb.take<IoBlock>(1, &hU.io);
-    };
-    size_t ndl = 0;
+    speculate = flag_pass && !J.rec && J.nprob <= kSpeculateMaxProblems;
+    merge3 = !flag_pass || speculate;
+    combine = speculate && !J.io_fixed;
+    ndl = 0;
     for (auto& P : W1.plans) ndl += P.dl.size();
-    auto take2 = [&](Tables& tb) {
-        dT.wt = tb.take<WinTask>(ntw, &hT.wt);
-        dT.item0 = tb.take<int64_t>(ntw + 1, &hT.item0);
-        dT.wk0 = tb.take<int64_t>(ntw + 1, &hT.wk0);
-        dT.r0 = tb.take<int64_t>(ntw + 1, &hT.r0);
-        dT.dl = tb.take<double>(ndl, &hT.dl);
-        dT.st = tb.take<SpecTask>(nts, &hT.st);
-        dT.tile0 = tb.take<int64_t>(nts + 1, &hT.tile0);
-        dT.pos0 = tb.take<int64_t>(nts + 1, &hT.pos0);
-        dT.pair0 = tb.take<int64_t>(nts + 1, &hT.pair0);
-        dT.sk0 = tb.take<int64_t>(nts + 1, &hT.sk0);
-        dT.fe0 = tb.take<int64_t>(nts + 1, &hT.fe0);
-        dT.smap = tb.take<int32_t>(nsd, &hT.smap);
-        dT.rinfo = tb.take<int32_t>(6 * (size_t)nts, &hT.rinfo);
-        dT.ev = tb.take<double>(Keval, &hT.ev);
-        dT.gfwd = tb.take<void*>(3 * (size_t)nts, &hT.gfwd);
-        dT.ginv = tb.take<void*>(2 * (size_t)nts, &hT.ginv);
-        dT.rowk = tb.take<int32_t>(flag_pass ? Krow : 0, &hT.rowk);
-        dT.mask = tb.take<uint64_t>(flag_pass ? (size_t)nts * fwords : 0, &hT.mask);
-        if (merge3) take3(tb, 0, 0, false);  // phase 3 without fallback lags
-    };
-    Tables t2;
+    t2 = Tables{};
     take2(t2);
-    Staging* stg2 = nullptr;
+    stg2 = nullptr;
     NCF_TRY(ensure_stage(R, 1, t2.off, &stg2));
     t2 = Tables{stg2->h, stg2->d, 0};
     take2(t2);
@@ -1718,13 +1860,12 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     }
 
     // spectral tables
-    std::map<int64_t, FftPlan> plans;
-    int64_t total_pos = 0, ntiles = 0, total_samp = 0, total_pairs = 0, fold_blocks = 0,
-            mid_out = 0;
-    bool fold_chunks = false;  // a lattice task sums its tiles in several chunks
+    plans.clear();
+    total_pos = ntiles = total_samp = total_pairs = fold_blocks = mid_out = 0;
+    fold_chunks = false;  // a lattice task sums its tiles in several chunks
     for (int q = 0; q < nsd; ++q) hT.smap[q] = -1;
-    double spread_bytes = 0.0;
-    std::vector<std::pair<int, int>> groups;  // (first task, count) per grid size
+    spread_bytes = 0.0;
+    groups.clear();  // (first task, count) per grid size
     for (int i = 0; i < nts; ++i) {
         const SpecPlan& P = splans[i];
         const SeriesDesc& d0 = sdesc[J.set[0].sd0 + P.prob];
@@ -1824,7 +1965,8 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     // forward table: per size group, its grids, then its second grids (CCF
     // pair-count channels, or the ACF unit channels of a weighted call), then
     // its third grids (CCF unit channels of a weighted call)
-    std::vector<std::pair<int, int>> fwd_groups, inv_groups;
+    fwd_groups.clear();
+    inv_groups.clear();
     {
         int o = 0;
         for (auto& gq : groups) {
@@ -1863,128 +2005,141 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     // lags whose spectral pair count is below beta times the reference
     // (b(0) for the ACF, sqrt(B_xx(0) B_yy(0)) for the CCF) are summed
     // directly: their spectral value is dominated by rounding noise
-    std::vector<int> spec_of(J.nprob, -1);
+    spec_of.assign(J.nprob, -1);
     for (int i = 0; i < nts; ++i) spec_of[splans[i].prob] = i;
-    std::vector<std::vector<int>> flagged(J.nprob);  // requested lag indices
-    WinLaunch W2;
-    // phase-3 tables (laid out in dU / hU): the fallback window tasks of W2
-    // (ntw2 of them), the normalization tasks, statuses and the I/O block
-    auto fill3 = [&](int ntw2, bool any_fb) {
-        std::vector<int> fb_task(J.nprob, -1);
-        {
-            size_t o = 0;
-            for (int i = 0; i < ntw2; ++i) {
-                std::memcpy(hU.dl + o, W2.plans[i].dl.data(), sizeof(double) * W2.plans[i].dl.size());
-                W2.wt[i].delta = dU.dl + o;
-                o += W2.plans[i].dl.size();
-                fb_task[W2.plans[i].prob] = i;
-            }
-            if (ntw2) {
-                std::memcpy(hU.wt, W2.wt.data(), sizeof(WinTask) * ntw2);
-                std::memcpy(hU.item0, W2.item0.data(), sizeof(int64_t) * (ntw2 + 1));
-                std::memcpy(hU.wk0, W2.wk0.data(), sizeof(int64_t) * (ntw2 + 1));
-                std::memcpy(hU.r0, W2.r0.data(), sizeof(int64_t) * (ntw2 + 1));
-            }
-            if (any_fb) {
-                for (int64_t i = 0; i < (int64_t)ntw2 * K; ++i) hU.fbrow[i] = -1;
-                // flagged lags are in sorted-row order; their fallback row is their rank
-                for (int i = 0; i < ntw2; ++i) {
-                    const int64_t p = W2.plans[i].prob;
-                    for (size_t q = 0; q < flagged[p].size(); ++q)
-                        hU.fbrow[(int64_t)i * K + flagged[p][q]] = (int32_t)q;
-                }
-            }
-        }
-        // normalization tables
-        std::memcpy(hU.perm, perm.data(), sizeof(int32_t) * K);
-        {
-            std::vector<int> main_t(J.nprob, -1), selfx(J.nprob, -1), selfy(J.nprob, -1);
-            for (int i = 0; i < ntw; ++i) {
-                const WinPlan& P = W1.plans[i];
-                (P.role == 0 ? main_t : P.role == 1 ? selfx : selfy)[P.prob] = i;
-            }
-            for (int64_t p = 0; p < J.nprob; ++p) {
-                const bool sp = spectral && !direct_p[p];
-                NormTask T{};
-                T.ccf = J.ccf ? 1 : 0;
-                T.K = (int32_t)K;
-                T.perm = dU.perm;
-                T.row0 = row0;
-                T.spectral = sp ? 1 : 0;
-                T.spec_b = (spec_b && sp) ? 1 : 0;
-                // mixed-precision Gaussian: the lag-0 scale decides whether the
-                // problem is evaluated again in FP64 (one-shot calls) or, in a
-                // plan execution, reported as unsupported
-                const bool promotable = !fp64 && !rect;
-                const bool fixed_launches = J.rec != nullptr || J.no_alloc;
-                T.guard = (promotable && fixed_launches) ? 1 : 0;
-                T.rmin = (promotable && !fixed_launches) ? dU.rmin + p : nullptr;
-                T.weighted = weighted ? 1 : 0;
-                T.is_rect = rect ? 1 : 0;
-                T.beta = beta;
-                T.out_off = p * K;
-                T.index = p;
-                T.st0 = d_stats + J.set[0].sd0 + p;
-                T.st1 = J.ccf ? d_stats + J.set[1].sd0 + p : nullptr;
-                hU.status[p] = pstat[p];
-                if (pstat[p] == NCF_OK) {
-                    if (main_t[p] >= 0) T.wsums = W1.wt[main_t[p]].sums;
-                    if (J.ccf && selfx[p] >= 0) {
-                        T.self_x = W1.wt[selfx[p]].sums;
-                        T.self_y = W1.wt[selfy[p]].sums;
-                    }
-                    if (sp) {
-                        const int i = spec_of[p];
-                        T.numer = numer[i];
-                        T.bspec = bspec[i];
-                        T.bunw = bunw[i];
-                        T.scale_part = spart[i];
-                        T.nscale_part = splans[i].g.N / 4096;
-                    }
-                    if (fb_task[p] >= 0) {
-                        T.fb_row = dU.fbrow + (int64_t)fb_task[p] * K;
-                        T.fb_sums = W2.wt[fb_task[p]].sums;
-                    }
-                } else {
-                    T.skip = 1;  // outputs: c = NaN, b = 0, count = 0
-                    T.skip_status = pstat[p];
-                }
-                hU.nt[p] = T;
-            }
-        }
-        // caller arrays of the normalization (one-shot calls)
-        hU.io->x[0] = J.set[0].x;
-        hU.io->x[1] = J.ccf ? J.set[1].x : nullptr;
-        hU.io->c = d_c;
-        hU.io->b = d_b;
-        hU.io->count = d_cnt;
-        hU.io->status = dU.status;
-    };
+    flagged.assign(J.nprob, std::vector<int>());  // requested lag indices
+    W2 = WinLaunch{};
     if (merge3) fill3(0, false);
     NCF_TRY_HIP(hipMemcpyAsync(stg2->d, stg2->h, t2.off, hipMemcpyHostToDevice, J.st));
+    return NCF_OK;
+}
 
+// phase-3 tables (laid out in dU / hU): the fallback window tasks of W2
+// (ntw2 of them), the normalization tasks, statuses and the I/O block
+void CallRun::fill3(int ntw2, bool any_fb) {
+    std::vector<int> fb_task(J.nprob, -1);
+    {
+        size_t o = 0;
+        for (int i = 0; i < ntw2; ++i) {
+            std::memcpy(hU.dl + o, W2.plans[i].dl.data(), sizeof(double) * W2.plans[i].dl.size());
+            W2.wt[i].delta = dU.dl + o;
+            o += W2.plans[i].dl.size();
+            fb_task[W2.plans[i].prob] = i;
+        }
+        if (ntw2) {
+            std::memcpy(hU.wt, W2.wt.data(), sizeof(WinTask) * ntw2);
+            std::memcpy(hU.item0, W2.item0.data(), sizeof(int64_t) * (ntw2 + 1));
+            std::memcpy(hU.wk0, W2.wk0.data(), sizeof(int64_t) * (ntw2 + 1));
+            std::memcpy(hU.r0, W2.r0.data(), sizeof(int64_t) * (ntw2 + 1));
+        }
+        if (any_fb) {
+            for (int64_t i = 0; i < (int64_t)ntw2 * K; ++i) hU.fbrow[i] = -1;
+            // flagged lags are in sorted-row order; their fallback row is their rank
+            for (int i = 0; i < ntw2; ++i) {
+                const int64_t p = W2.plans[i].prob;
+                for (size_t q = 0; q < flagged[p].size(); ++q)
+                    hU.fbrow[(int64_t)i * K + flagged[p][q]] = (int32_t)q;
+            }
+        }
+    }
+    // normalization tables
+    std::memcpy(hU.perm, perm.data(), sizeof(int32_t) * K);
+    {
+        std::vector<int> main_t(J.nprob, -1), selfx(J.nprob, -1), selfy(J.nprob, -1);
+        for (int i = 0; i < ntw; ++i) {
+            const WinPlan& P = W1.plans[i];
+            (P.role == 0 ? main_t : P.role == 1 ? selfx : selfy)[P.prob] = i;
+        }
+        for (int64_t p = 0; p < J.nprob; ++p) {
+            const bool sp = spectral && !direct_p[p];
+            NormTask T{};
+            T.ccf = J.ccf ? 1 : 0;
+            T.K = (int32_t)K;
+            T.perm = dU.perm;
+            T.row0 = row0;
+            T.spectral = sp ? 1 : 0;
+            T.spec_b = (spec_b && sp) ? 1 : 0;
+            // mixed-precision Gaussian: the lag-0 scale decides whether the
+            // problem is evaluated again in FP64 (one-shot calls) or, in a
+            // plan execution, reported as unsupported
+            const bool promotable = !fp64 && !rect;
+            const bool fixed_launches = J.rec != nullptr || J.no_alloc;
+            T.guard = (promotable && fixed_launches) ? 1 : 0;
+            T.rmin = (promotable && !fixed_launches) ? dU.rmin + p : nullptr;
+            T.weighted = weighted ? 1 : 0;
+            T.is_rect = rect ? 1 : 0;
+            T.beta = beta;
+            T.out_off = p * K;
+            T.index = p;
+            T.st0 = d_stats + J.set[0].sd0 + p;
+            T.st1 = J.ccf ? d_stats + J.set[1].sd0 + p : nullptr;
+            hU.status[p] = pstat[p];
+            if (pstat[p] == NCF_OK) {
+                if (main_t[p] >= 0) T.wsums = W1.wt[main_t[p]].sums;
+                if (J.ccf && selfx[p] >= 0) {
+                    T.self_x = W1.wt[selfx[p]].sums;
+                    T.self_y = W1.wt[selfy[p]].sums;
+                }
+                if (sp) {
+                    const int i = spec_of[p];
+                    T.numer = numer[i];
+                    T.bspec = bspec[i];
+                    T.bunw = bunw[i];
+                    T.scale_part = spart[i];
+                    T.nscale_part = splans[i].g.N / 4096;
+                }
+                if (fb_task[p] >= 0) {
+                    T.fb_row = dU.fbrow + (int64_t)fb_task[p] * K;
+                    T.fb_sums = W2.wt[fb_task[p]].sums;
+                }
+            } else {
+                T.skip = 1;  // outputs: c = NaN, b = 0, count = 0
+                T.skip_status = pstat[p];
+            }
+            hU.nt[p] = T;
+        }
+    }
+    // caller arrays of the normalization (one-shot calls)
+    hU.io->x[0] = J.set[0].x;
+    hU.io->x[1] = J.ccf ? J.set[1].x : nullptr;
+    hU.io->c = d_c;
+    hU.io->b = d_b;
+    hU.io->count = d_cnt;
+    hU.io->status = dU.status;
+}
+
+// A7: the main window launch and its reduction.
+int CallRun::record_window() {
     // ------------------------------------------------ A7 window scan
     // work-queue dispatch of the window scans (scheduling option)
-    unsigned long long* qbase = nullptr;
+    qbase = nullptr;
     if ((J.opt.flags & NCF_WINDOW_QUEUE) || J.tune.queue) NCF_TRY(ensure_queue(R, &qbase));
+    // the launch lambdas capture copies only: recorded launches (plans) are
+    // replayed after this object is gone
     {
         const WinTask* wt = dT.wt;
         const int64_t *it0 = dT.item0, *wk0 = dT.wk0, *r0 = dT.r0;
-        const int64_t nitems = W1.nitems, rows = W1.total_rows, nred1 = W1.nred1;
-        const int cap = W1.cap, jmax = W1.jmax;
+        const int64_t nitems = W1.nitems, nrows = W1.total_rows, nred1 = W1.nred1;
+        const int cap = W1.cap, jmax = W1.jmax, nt = ntw;
         const double work = W1.work;
+        const uint32_t wf = wflags;
         unsigned long long* q = qbase;
-        if (ntw > 0) {
-            NCF_TRY(check_win(W1, wflags));
+        if (nt > 0) {
+            NCF_TRY(check_win(W1, wf));
             NCF_TRY(emit(J, [=](hipStream_t s) {
-                return launch_window(wt, it0, ntw, nitems, wflags, cap, jmax, q, s, work);
+                return launch_window(wt, it0, nt, nitems, wf, cap, jmax, q, s, work);
             }));
             NCF_TRY(emit(J, [=](hipStream_t s) {
-                return launch_window_reduce(wt, ntw, rows, wk0, r0, nred1, wflags, s);
+                return launch_window_reduce(wt, nt, nrows, wk0, r0, nred1, wf, s);
             }));
         }
     }
+    return NCF_OK;
+}
 
+// A2-A6: tile ranges, spreading, forward passes, the fused middle (or the
+// product), inverse passes, and the evaluation at the lags.
+int CallRun::record_spectral() {
     // ------------------------------------------------ A2-A6 spectral route
     if (nts > 0) {
         const SpecTask* stk = dT.st;
@@ -1997,13 +2152,18 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
         const int64_t* rec_all = d_rng;
         const Chunk* dch = d_ch;
         const double tb_bytes = 8.0 * (double)total_samp;
+        // the launch lambdas capture copies only (see record_window)
+        const int nc = nch, nt = nts;
+        const int64_t ntl = ntiles, tpos = total_pos;
+        const bool sb = spec_b, sw = spec_w, su = spec_unw, f64 = fp64;
+        const double sbytes = spread_bytes;
         if (bounds_pass)
             NCF_TRY(emit(J, [=](hipStream_t s) {
-                return launch_tile_bounds(stk, dch, nch, smap, s, tb_bytes);
+                return launch_tile_bounds(stk, dch, nc, smap, s, tb_bytes);
             }));
         NCF_TRY(emit(J, [=](hipStream_t s) {
-            return launch_spread(stk, tile0, nts, ntiles, rec_all, 4096, ccf, spec_b, spec_w,
-                                 spec_unw, fp64, s, spread_bytes);
+            return launch_spread(stk, tile0, nt, ntl, rec_all, 4096, ccf, sb, sw, su, f64, s,
+                                 sbytes);
         }));
         // the forward last pass, the product and the inverse first pass run
         // fused over tile pairs where the mode fits the LDS of one workgroup
@@ -2013,7 +2173,7 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             void* const* gp = dT.gfwd + fwd_groups[q].first;
             const int cnt = fwd_groups[q].second;
             NCF_TRY(emit(J, [=](hipStream_t s) {
-                return fft_exec(fp, gp, cnt, +1, fp64, s, fuse);
+                return fft_exec(fp, gp, cnt, +1, f64, s, fuse);
             }));
         }
         if (fuse) {
@@ -2024,13 +2184,12 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             // the folded spectra of the grids on a lag lattice)
             const double mbytes = ((double)nfwd * total_pos + (double)mid_out) * csz;
             NCF_TRY(emit(J, [=](hipStream_t s) {
-                return launch_mid(stk, pair0, nts, npairs, rinfo, wsmall, ccf, spec_b, fp64, s,
+                return launch_mid(stk, pair0, nt, npairs, rinfo, wsmall, ccf, sb, f64, s,
                                   mbytes);
             }));
         } else {
             NCF_TRY(emit(J, [=](hipStream_t s) {
-                return launch_product(stk, pos0, nts, total_pos, rinfo, ccf, spec_b, spec_unw,
-                                      fp64, s, pbytes);
+                return launch_product(stk, pos0, nt, tpos, rinfo, ccf, sb, su, f64, s, pbytes);
             }));
         }
         for (size_t q = 0; q < groups.size(); ++q) {
@@ -2039,26 +2198,30 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             const int cnt = inv_groups[q].second;
             if (cnt == 0) continue;  // every grid of the size is on a lag lattice
             NCF_TRY(emit(J, [=](hipStream_t s) {
-                return fft_exec(fp, gp, cnt, -1, fp64, s, fuse);
+                return fft_exec(fp, gp, cnt, -1, f64, s, fuse);
             }));
         }
         if (J.info_fold_grids < nts)
             NCF_TRY(emit(J, [=](hipStream_t s) {
-                return launch_interp(stk, nts, sk0, nkeval, fp64, s);
+                return launch_interp(stk, nt, sk0, nkeval, f64, s);
             }));
         if (fold_blocks > 0) {
             const int64_t* fe0 = dT.fe0;
             const int64_t nfb = fold_blocks;
             const bool fch = fold_chunks;
             NCF_TRY(emit(J, [=](hipStream_t s) {
-                return launch_fold_eval(stk, nts, fe0, nfb, sk0, nkeval, fch, fp64, s);
+                return launch_fold_eval(stk, nt, fe0, nfb, sk0, nkeval, fch, f64, s);
             }));
         }
     }
+    return NCF_OK;
+}
 
+// Fallback flags of the spectral pair counts.
+int CallRun::record_flags() {
     // ------------------------------------------------ direct fallback (spectral b)
-    int32_t* h_fstat = nullptr;
-    double* h_rmin = nullptr;
+    h_fstat = nullptr;
+    h_rmin = nullptr;
     if (flag_pass) {
         // flags computed on the device from the spectral b values (contiguous
         // over the problems); only the bit masks come back
@@ -2069,127 +2232,149 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             NCF_TRY_HIP(hipMemcpyAsync(hT.mask, dT.mask, sizeof(uint64_t) * (size_t)nts * fwords,
                                        hipMemcpyDeviceToHost, J.st));
     }
-    auto read_flags = [&]() {
-        for (int i = 0; i < nts; ++i) {
-            const int64_t p = splans[i].prob;
-            const uint64_t* mw = hT.mask + (size_t)i * fwords;
-            std::vector<double> dl;
-            for (int w = 0; w < fwords; ++w)
-                for (uint64_t m = mw[w]; m; m &= m - 1) {
-                    const int r = w * 64 + __builtin_ctzll(m);
-                    flagged[p].push_back(rows[r].second);
-                    dl.push_back(delta[r]);
-                }
-            if (!dl.empty())
-                W2.plans.push_back({0, J.ccf ? 1 : 0, p, 3, std::move(dl)});
-        }
-    };
-    // phase-3 launches on the tables in dU: the fallback window scans, the
-    // normalization, and the copies of the statuses (with the flag masks in
-    // front when with_masks) and of host-memory outputs
-    auto launch3 = [&](int ntw2, bool with_masks) -> int {
-        const uint32_t wflags2 = (fp64 ? (uint32_t)WIN_EXP64 : 0u) | (uint32_t)WIN_NUMER |
-                                 (weighted ? (uint32_t)WIN_WEIGHTED : 0u);
-        if (ntw2 > 0) {
-            const WinTask* wt = dU.wt;
-            const int64_t *it0 = dU.item0, *wk0 = dU.wk0, *r0 = dU.r0;
-            const int64_t nitems = W2.nitems, rows = W2.total_rows, nred1 = W2.nred1;
-            const int cap = W2.cap, jmax = W2.jmax;
-            const double work = W2.work;
-            unsigned long long* q = qbase ? qbase + 2 : nullptr;
-            NCF_TRY(check_win(W2, wflags2));
-            NCF_TRY(emit(J, [=](hipStream_t s) {
-                return launch_window(wt, it0, ntw2, nitems, wflags2, cap, jmax, q, s, work);
-            }));
-            NCF_TRY(emit(J, [=](hipStream_t s) {
-                return launch_window_reduce(wt, ntw2, rows, wk0, r0, nred1, wflags2, s);
-            }));
-        }
+    return NCF_OK;
+}
 
-        // ------------------------------------------------ A8 normalization, outputs
-        {
-            const NormTask* nt = dU.nt;
-            const int np = (int)J.nprob;
-            const IoBlock* io = J.io_fixed ? J.io_fixed : dU.io;
-            NCF_TRY(emit(J, [=](hipStream_t s) { return launch_normalize(nt, np, io, s); }));
-        }
-        h_fstat = hU.status;  // pinned
-        // written by promotable tasks only
-        h_rmin = (J.rec || J.no_alloc || fp64 || rect) ? nullptr : hU.rmin;
-        if (with_masks) {
-            const size_t bytes =
-                (size_t)((const char*)(dU.rmin + J.nprob) - (const char*)dT.mask);
-            NCF_TRY_HIP(hipMemcpyAsync(hT.mask, dT.mask, bytes, hipMemcpyDeviceToHost, J.st));
-        } else if (J.io_fixed) {
-            NCF_TRY_HIP(hipMemcpyAsync(h_fstat, J.io_status, sizeof(int32_t) * J.nprob,
-                                       hipMemcpyDeviceToHost, J.st));
-        } else {
-            // statuses and the lag-0 scales behind them
-            const size_t bytes = (size_t)((const char*)(dU.rmin + J.nprob) -
-                                          (const char*)dU.status);
-            NCF_TRY_HIP(hipMemcpyAsync(h_fstat, dU.status, bytes, hipMemcpyDeviceToHost, J.st));
-        }
-        if (!J.dev_ptrs && K > 0) {
-            NCF_TRY_HIP(hipMemcpyAsync(J.c, d_c, sizeof(double) * J.nprob * K, hipMemcpyDeviceToHost,
-                                       J.st));
-            NCF_TRY_HIP(hipMemcpyAsync(J.b, d_b, sizeof(double) * J.nprob * K, hipMemcpyDeviceToHost,
-                                       J.st));
-            if (J.count)
-                NCF_TRY_HIP(hipMemcpyAsync(J.count, d_cnt, sizeof(int64_t) * J.nprob * K,
-                                           hipMemcpyDeviceToHost, J.st));
-        }
-        return NCF_OK;
-    };
-    // phase 3 with its own tables and upload (the fallback tasks of W2)
-    auto separate3 = [&]() -> int {
-        const int ntw2 = (int)W2.plans.size();
-        // fallback workspace and the output tables
-        auto layout3 = [&](Arena& ar) {
-            for (int i = 0; i < ntw2; ++i) {
-                WinTask& T = W2.wt[i];
-                T.part = ar.take<double>((size_t)T.n_jg * T.K * 4);
-                T.part2 = ar.take<double>((size_t)ceil_div(T.n_jg, kWinJc) * T.K * 4);
-                T.sums = ar.take<double>((size_t)T.K * 4);
+// Flagged lags of each spectral problem -> fallback window tasks in W2.
+void CallRun::read_flags() {
+    for (int i = 0; i < nts; ++i) {
+        const int64_t p = splans[i].prob;
+        const uint64_t* mw = hT.mask + (size_t)i * fwords;
+        std::vector<double> dl;
+        for (int w = 0; w < fwords; ++w)
+            for (uint64_t m = mw[w]; m; m &= m - 1) {
+                const int r = w * 64 + __builtin_ctzll(m);
+                flagged[p].push_back(rows[r].second);
+                dl.push_back(delta[r]);
             }
-        };
-        Arena a3;
+        if (!dl.empty())
+            W2.plans.push_back({0, J.ccf ? 1 : 0, p, 3, std::move(dl)});
+    }
+}
+
+// phase-3 launches on the tables in dU: the fallback window scans, the
+// normalization, and the copies of the statuses (with the flag masks in
+// front when with_masks) and of host-memory outputs
+int CallRun::launch3(int ntw2, bool with_masks) {
+    const uint32_t wflags2 = (fp64 ? (uint32_t)WIN_EXP64 : 0u) | (uint32_t)WIN_NUMER |
+                             (weighted ? (uint32_t)WIN_WEIGHTED : 0u);
+    if (ntw2 > 0) {
+        const WinTask* wt = dU.wt;
+        const int64_t *it0 = dU.item0, *wk0 = dU.wk0, *r0 = dU.r0;
+        const int64_t nitems = W2.nitems, nrows = W2.total_rows, nred1 = W2.nred1;
+        const int cap = W2.cap, jmax = W2.jmax;
+        const double work = W2.work;
+        unsigned long long* q = qbase ? qbase + 2 : nullptr;
+        NCF_TRY(check_win(W2, wflags2));
+        NCF_TRY(emit(J, [=](hipStream_t s) {
+            return launch_window(wt, it0, ntw2, nitems, wflags2, cap, jmax, q, s, work);
+        }));
+        NCF_TRY(emit(J, [=](hipStream_t s) {
+            return launch_window_reduce(wt, ntw2, nrows, wk0, r0, nred1, wflags2, s);
+        }));
+    }
+
+    // ------------------------------------------------ A8 normalization, outputs
+    {
+        const NormTask* nt = dU.nt;
+        const int np = (int)J.nprob;
+        const IoBlock* io = J.io_fixed ? J.io_fixed : dU.io;
+        NCF_TRY(emit(J, [=](hipStream_t s) { return launch_normalize(nt, np, io, s); }));
+    }
+    h_fstat = hU.status;  // pinned
+    // written by promotable tasks only
+    h_rmin = (J.rec || J.no_alloc || fp64 || rect) ? nullptr : hU.rmin;
+    if (with_masks) {
+        const size_t bytes =
+            (size_t)((const char*)(dU.rmin + J.nprob) - (const char*)dT.mask);
+        NCF_TRY_HIP(hipMemcpyAsync(hT.mask, dT.mask, bytes, hipMemcpyDeviceToHost, J.st));
+    } else if (J.io_fixed) {
+        NCF_TRY_HIP(hipMemcpyAsync(h_fstat, J.io_status, sizeof(int32_t) * J.nprob,
+                                   hipMemcpyDeviceToHost, J.st));
+    } else {
+        // statuses and the lag-0 scales behind them
+        const size_t bytes = (size_t)((const char*)(dU.rmin + J.nprob) -
+                                      (const char*)dU.status);
+        NCF_TRY_HIP(hipMemcpyAsync(h_fstat, dU.status, bytes, hipMemcpyDeviceToHost, J.st));
+    }
+    if (!J.dev_ptrs && K > 0) {
+        NCF_TRY_HIP(hipMemcpyAsync(J.c, d_c, sizeof(double) * J.nprob * K, hipMemcpyDeviceToHost,
+                                   J.st));
+        NCF_TRY_HIP(hipMemcpyAsync(J.b, d_b, sizeof(double) * J.nprob * K, hipMemcpyDeviceToHost,
+                                   J.st));
+        if (J.count)
+            NCF_TRY_HIP(hipMemcpyAsync(J.count, d_cnt, sizeof(int64_t) * J.nprob * K,
+                                       hipMemcpyDeviceToHost, J.st));
+    }
+    return NCF_OK;
+}
+
+// Phase 3 with its own tables and upload (the fallback tasks of W2).
+int CallRun::separate3() {
+    const int ntw2 = (int)W2.plans.size();
+    // fallback workspace and the output tables
+    auto layout3 = [&](Arena& ar) {
+        for (int i = 0; i < ntw2; ++i) {
+            WinTask& T = W2.wt[i];
+            T.part = ar.take<double>((size_t)T.n_jg * T.K * 4);
+            T.part2 = ar.take<double>((size_t)ceil_div(T.n_jg, kWinJc) * T.K * 4);
+            T.sums = ar.take<double>((size_t)T.K * 4);
+        }
+    };
+    Arena a3;
+    layout3(a3);
+    if (ntw2 > 0) {
+        void* ws3 = nullptr;
+        NCF_TRY(ensure_ws(R, 2, a3.off + 256, &ws3));
+        a3 = Arena{(char*)ws3, 0};
         layout3(a3);
-        if (ntw2 > 0) {
-            void* ws3 = nullptr;
-            NCF_TRY(ensure_ws(R, 2, a3.off + 256, &ws3));
-            a3 = Arena{(char*)ws3, 0};
-            layout3(a3);
-        }
-        size_t ndl2 = 0;
-        for (auto& P : W2.plans) ndl2 += P.dl.size();
-        const bool any_fb = ntw2 > 0;
-        Tables t3;
-        take3(t3, ntw2, ndl2, any_fb);
-        Staging* stg3 = nullptr;
-        NCF_TRY(ensure_stage(R, 2, t3.off, &stg3));
-        t3 = Tables{stg3->h, stg3->d, 0};
-        take3(t3, ntw2, ndl2, any_fb);
-        fill3(ntw2, any_fb);
-        NCF_TRY_HIP(hipMemcpyAsync(stg3->d, stg3->h, t3.off, hipMemcpyHostToDevice, J.st));
-        return launch3(ntw2, false);
-    };
-    auto done = [&]() -> int {
-        NCF_TRY_HIP(hipStreamSynchronize(J.st));
-        if (g_prof_on) {
-            std::lock_guard<std::mutex> lock(g_prof_mu);
-            prof_flush_locked();
-        }
-        if (h_rmin && !J.plan_build) {
-            // problems whose lag-0 scale is small in mixed precision: again in FP64
-            std::vector<int64_t> again;
-            for (int64_t p = 0; p < J.nprob; ++p)
-                if ((h_fstat[p] == NCF_OK || h_fstat[p] == NCF_E_DEGENERATE) &&
-                    h_rmin[p] < kPromoteScale)
-                    again.push_back(p);
-            if (!again.empty()) NCF_TRY(promote_fp64(J, again, h_fstat, stats));
-        }
-        return finish_status(J, pstat, h_fstat);
-    };
+    }
+    size_t ndl2 = 0;
+    for (auto& P : W2.plans) ndl2 += P.dl.size();
+    const bool any_fb = ntw2 > 0;
+    Tables t3;
+    take3(t3, ntw2, ndl2, any_fb);
+    Staging* stg3 = nullptr;
+    NCF_TRY(ensure_stage(R, 2, t3.off, &stg3));
+    t3 = Tables{stg3->h, stg3->d, 0};
+    take3(t3, ntw2, ndl2, any_fb);
+    fill3(ntw2, any_fb);
+    NCF_TRY_HIP(hipMemcpyAsync(stg3->d, stg3->h, t3.off, hipMemcpyHostToDevice, J.st));
+    return launch3(ntw2, false);
+}
+
+// Wait for the call, re-evaluate problems of small lag-0 scale in FP64,
+// report the statuses.
+int CallRun::done() {
+    NCF_TRY_HIP(hipStreamSynchronize(J.st));
+    if (g_prof_on) {
+        std::lock_guard<std::mutex> lock(g_prof_mu);
+        prof_flush_locked();
+    }
+    if (h_rmin && !J.plan_build) {
+        // problems whose lag-0 scale is small in mixed precision: again in FP64
+        std::vector<int64_t> again;
+        for (int64_t p = 0; p < J.nprob; ++p)
+            if ((h_fstat[p] == NCF_OK || h_fstat[p] == NCF_E_DEGENERATE) &&
+                h_rmin[p] < kPromoteScale)
+                again.push_back(p);
+        if (!again.empty()) NCF_TRY(promote_fp64(J, again, h_fstat, stats));
+    }
+    return finish_status(J, pstat, h_fstat);
+}
+
+int CallRun::run() {
+    init_flags();
+    NCF_TRY(moments());
+    if (J.regular) return run_regular(J, sdesc, stats, pstat, d_stats);
+    NCF_TRY(plan_route());
+    plan_windows();
+    NCF_TRY(plan_spectral());
+    NCF_TRY(alloc_phase2());
+    NCF_TRY(tables_phase2());
+    NCF_TRY(record_window());
+    NCF_TRY(record_spectral());
+    NCF_TRY(record_flags());
     if (!flag_pass) {  // tables uploaded with phase 2
         NCF_TRY(launch3(0, false));
         return done();
@@ -2208,6 +2393,12 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
     J.info_window_launches += W2.plans.empty() ? 0 : 1;
     NCF_TRY(separate3());
     return done();
+}
+
+int run_job(Job& J, const double* const* tin, const double* const* xin,
+            const double* const* ein) {
+    CallRun run(J, tin, xin, ein);
+    return run.run();
 }
 
 // ---------------------------------------------------------- entry helpers
