@@ -37,7 +37,7 @@ def _lattice_grids(d, lags, **kw):
 
 def _check_b(b, ob, precision):
     if precision == "mixed":  # spectral pair count: relative to the largest
-        np.testing.assert_allclose(b, ob, rtol=0, atol=1e-5 * np.max(ob))
+        np.testing.assert_allclose(b, ob, rtol=0, atol=2e-6 * np.max(ob))
     else:
         np.testing.assert_allclose(b, ob, rtol=2e-8, atol=0)
 

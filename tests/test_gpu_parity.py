@@ -72,7 +72,7 @@ def _check(c, b, n, oc, ob, on, kernel, ctol, btol):
 
 
 MODES = [
-    ("mixed", "auto", 1e-5, ("ref", 1e-5)),
+    ("mixed", "auto", 1e-5, ("ref", 2e-6)),
     ("fp64", "auto", 5e-8, 2e-8),
     ("fp64", "direct", 1e-11, 1e-12),
     ("mixed", "direct", 1e-5, 1e-6),
@@ -139,14 +139,14 @@ def test_weighted_mode_matches_oracle():
     for kern in ("gaussian", "rectangle"):
         st, oc, ob, on = O.acf(t, x, lags, kern, 0.5, err=e)
         assert st == 0
-        for prec, ctol, btol in (("mixed", 1e-5, ("ref", 1e-5)), ("fp64", 5e-8, 2e-8)):
+        for prec, ctol, btol in (("mixed", 1e-5, ("ref", 2e-6)), ("fp64", 5e-8, 2e-8)):
             c, b, n, _ = ncf.acf(t, x, lags, kern, 0.5, err=e, precision=prec)
             if kern == "rectangle":
                 ctol = 1e-9
             _check(c, b, n, oc, ob, on, kern, ctol, btol)
 
 
-@pytest.mark.parametrize("prec,ctol,btol", [("mixed", 1e-5, ("ref", 1e-5)),
+@pytest.mark.parametrize("prec,ctol,btol", [("mixed", 1e-5, ("ref", 2e-6)),
                                             ("fp64", 5e-8, 2e-8)])
 @pytest.mark.parametrize("which", ["both", "x", "y"])
 def test_weighted_ccf_gaussian(which, prec, ctol, btol):
@@ -172,7 +172,7 @@ def test_weighted_batch_gaussian():
         sl = slice(offs[i], offs[i + 1])
         s_, oc, ob, on = O.acf(t[sl], x[sl], lags, "gaussian", d["h"][i], err=e[sl])
         assert s_ == 0
-        _check(c[i], b[i], n[i], oc, ob, on, "gaussian", 1e-5, ("ref", 1e-5))
+        _check(c[i], b[i], n[i], oc, ob, on, "gaussian", 1e-5, ("ref", 2e-6))
 
 
 def test_status_codes_on_gpu():
@@ -310,11 +310,15 @@ def test_fft_against_numpy(p, prec):
     x = rng.normal(size=N) + 1j * rng.normal(size=N)
     want_p = np.fft.ifft(x) * N  # sum x exp(+2 pi i n k / N)
     want_m = np.fft.fft(x)       # sum x exp(-2 pi i n k / N)
-    tol = 2e-6 if prec == "mixed" else 1e-13
+    # relative L2 error, and every element against the RMS of the output (a
+    # wrong twiddle or index shows in a few elements before the norm)
+    tol, tol_el = (5e-7, 4e-6) if prec == "mixed" else (1e-14, 5e-14)
     for sign, want in ((+1, want_p), (-1, want_m)):
         got = ncf.diag_fft(x, sign, prec)
         rel = np.linalg.norm(got - want) / np.linalg.norm(want)
         assert rel < tol, (sign, rel)
+        el = np.max(np.abs(got - want)) / (np.linalg.norm(want) / np.sqrt(N))
+        assert el < tol_el, (sign, el)
 
 
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
@@ -328,6 +332,8 @@ def test_type1_against_direct_dft(prec):
     want = np.exp(2j * np.pi * np.outer(m, t) / L) @ v
     rel = np.linalg.norm(got - want) / np.linalg.norm(want)
     assert rel < (2e-6 if prec == "mixed" else 1e-11), rel
+    el = np.max(np.abs(got - want)) / (np.linalg.norm(want) / np.sqrt(want.size))
+    assert el < (3e-5 if prec == "mixed" else 3e-10), el
 
 
 # ------------------------------------------- full-size, bench configuration
@@ -371,7 +377,7 @@ def test_c3_full_size_sampled_lags():
     ("rectangle", "fp64", "direct", 1e-9, 0),
     ("gaussian", "mixed", "direct", 1e-5, 1e-6),
     ("gaussian", "fp64", "direct", 1e-11, 1e-12),
-    ("gaussian", "mixed", "auto", 1e-5, ("ref", 1e-5)),
+    ("gaussian", "mixed", "auto", 1e-5, ("ref", 2e-6)),
 ])
 def test_ccf_weights_on_one_side(side, kernel, prec, method, ctol, btol):
     # errors on one series only: the other takes unit weights in the pair

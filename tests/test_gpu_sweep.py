@@ -134,7 +134,7 @@ def _tols(kernel, prec, method, spec_always, oc, on, r_min, n_min, n0):
     if kernel == "rectangle":
         return 1e-9 + 1e-15 * (1.0 + oc) / g, None
     if prec == "mixed":
-        btol = ("ref", 1e-5) if method == "auto" else 1e-6
+        btol = ("ref", 2e-6) if method == "auto" else 1e-6
         return np.full(oc.shape, 1e-5), btol
     nsum = max(int(np.max(on)) if np.size(on) else 0, n0)
     if method == "direct":
