@@ -414,6 +414,10 @@ typedef struct {
                                   type-2 step at equispaced points) */
     int32_t lattice_off;       /* 1: the autotuner chose inverse transform + interpolation
                                   although the lags sit on a lattice */
+    int32_t tune_cached;       /* 1: NCF_PLAN_AUTOTUNE took its settings from the autotune
+                                  cache (file named by the NCF_AUTOTUNE_CACHE environment
+                                  variable, one JSON record per line; a plan tuned anew
+                                  appends its record there) instead of timing candidates */
 } ncf_plan_info_t;
 
 int ncf_plan_info(const ncf_plan_t* plan, ncf_plan_info_t* info);

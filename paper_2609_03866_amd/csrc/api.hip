@@ -14,6 +14,7 @@
 // launch covers thousands of uneven series.
 #include <algorithm>
 #include <array>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -34,6 +35,14 @@ namespace ncf {
 
 namespace {
 thread_local std::string g_err;
+}
+
+// Verbosity of the call log on stderr, from NCF_LOG (0 when unset): 1, one
+// line per call (route, grids, window work, fallback lags, statuses, host
+// time) and per plan build; 2, also every autotuner candidate.
+int log_level() {
+    const char* v = std::getenv("NCF_LOG");
+    return v ? std::atoi(v) : 0;
 }
 
 void set_error(const char* fmt, ...) {
@@ -907,7 +916,19 @@ int run_regular(Job& J, const std::vector<SeriesDesc>& sdesc,
         std::lock_guard<std::mutex> lock(g_prof_mu);
         prof_flush_locked();
     }
-    return finish_status(J, pstat, h_fstat);
+    const int rc = finish_status(J, pstat, h_fstat);
+    if (log_level() > 0) {
+        int64_t nbad = 0;
+        for (int64_t p = 0; p < J.nprob; ++p) nbad += h_fstat && h_fstat[p] != NCF_OK;
+        std::fprintf(stderr,
+                     "ncf: %s%s n=%lld K=%lld %s regular route=lattice grids=%d cells=%lld "
+                     "failed=%lld rc=%d\n",
+                     J.plan_build ? "plan-build " : "", J.ccf ? "ccf" : "acf",
+                     (long long)J.nprob, (long long)J.K,
+                     J.kern == NCF_RECTANGLE ? "rectangle" : "gaussian", J.info_grids,
+                     (long long)J.info_grid_cells, (long long)nbad, rc);
+    }
+    return rc;
 }
 
 int run_job(Job& J, const double* const* tin, const double* const* xin,
@@ -1158,6 +1179,8 @@ class CallRun {
     unsigned long long* qbase = nullptr;
     int32_t* h_fstat = nullptr;
     double* h_rmin = nullptr;
+    std::chrono::steady_clock::time_point t_start = std::chrono::steady_clock::now();
+    void log_call(int rc) const;
 };
 
 // Route flags and the derived arrays the call needs.
@@ -2360,7 +2383,31 @@ int CallRun::done() {
                 again.push_back(p);
         if (!again.empty()) NCF_TRY(promote_fp64(J, again, h_fstat, stats));
     }
-    return finish_status(J, pstat, h_fstat);
+    const int rc = finish_status(J, pstat, h_fstat);
+    if (log_level() > 0) log_call(rc);
+    return rc;
+}
+
+// One NCF_LOG line for a finished call.
+void CallRun::log_call(int rc) const {
+    int64_t ndirect = 0, nbad = 0;
+    for (int64_t p = 0; p < J.nprob; ++p) {
+        ndirect += direct_p.empty() ? 0 : direct_p[p];
+        nbad += h_fstat && h_fstat[p] != NCF_OK;
+    }
+    const double ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start)
+            .count();
+    std::fprintf(stderr,
+                 "ncf: %s%s n=%lld K=%lld %s %s%s route=%s direct_problems=%lld grids=%d "
+                 "cells=%lld lattice_grids=%d window_items=%lld window_launches=%d "
+                 "fallback_rows=%lld failed=%lld rc=%d host_ms=%.3f\n",
+                 J.plan_build ? "plan-build " : "", J.ccf ? "ccf" : "acf", (long long)J.nprob,
+                 (long long)J.K, rect ? "rectangle" : "gaussian", fp64 ? "fp64" : "mixed",
+                 weighted ? " weighted" : "", spectral ? "spectral" : "direct",
+                 (long long)ndirect, J.info_grids, (long long)J.info_grid_cells,
+                 J.info_fold_grids, (long long)J.info_window_items, J.info_window_launches,
+                 (long long)W2.total_rows, (long long)nbad, rc, ms);
 }
 
 int CallRun::run() {
@@ -3008,6 +3055,7 @@ struct ncf_plan_s {
     int grids = 0, window_launches = 0, fold_grids = 0;
     int64_t grid_cells = 0, window_items = 0;
     int autotuned = 0, candidates = 0;
+    int tune_cached = 0;  // autotuned settings read from the autotune cache
     double replay_ms = 0.0;
 };
 
@@ -3177,6 +3225,102 @@ int plan_time(ncf_plan_s* P, double* dummy, int reps, double* ms) {
     return rc;
 }
 
+// ------------------------------------------------------------ autotune cache
+// The autotuner's choice persists in the text file that NCF_AUTOTUNE_CACHE
+// names: one JSON record per line, {"key": "...", "sigma": ..., ...}, keyed
+// by the device (architecture, compute units) and the call's shape: kind,
+// kernel, precision, method, flags, weights, options, and power-of-two
+// buckets of the problem count, total samples, lag count and the first
+// problem's h. The settings change speed only (results differ at the
+// rounding level), so calls of one bucket share them. The last record of a
+// key wins; a line that does not parse, or holds a value out of range, is
+// skipped. Appends are serialized within the process.
+std::mutex g_tune_mu;
+
+std::string tune_key(const Job& J, int device, bool weighted) {
+    hipDeviceProp_t prop{};
+    char arch[64] = "unknown";
+    int cus = 0;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        std::snprintf(arch, sizeof(arch), "%s", prop.gcnArchName);
+        cus = prop.multiProcessorCount;
+    }
+    for (char* c = arch; *c; ++c)
+        if (*c == '"' || *c == '\\') *c = '_';
+    auto lg2 = [](double v) { return v > 0.0 ? (int)std::floor(std::log2(v)) : -999; };
+    const int64_t ntot = J.set[0].ntot + (J.ccf ? J.set[1].ntot : 0);
+    const unsigned fl = J.opt.flags & (NCF_SPECTRAL_ALWAYS | NCF_WINDOW_QUEUE | NCF_PLAN_NO_GRAPH |
+                                       NCF_DEVICE_POINTERS);
+    char buf[320];
+    std::snprintf(buf, sizeof(buf),
+                  "%s/%dcu %s %s %s prec%d method%d flags%u w%d tol%.3g sigma%.3g grid%lld "
+                  "n%d N%d K%d h%d",
+                  arch, cus, J.ccf ? "ccf" : "acf", J.regular ? "regular" : "irregular",
+                  J.kern == NCF_RECTANGLE ? "rect" : "gauss", (int)J.opt.precision,
+                  (int)J.opt.method, fl, weighted ? 1 : 0, J.opt.tol, J.opt.sigma,
+                  (long long)J.opt.grid_size, lg2((double)J.nprob), lg2((double)ntot),
+                  lg2((double)J.K + 1.0), lg2(J.h.empty() ? 0.0 : J.h[0]));
+    return buf;
+}
+
+bool tune_cache_find(const char* path, const std::string& key, Tune* out) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    static const char* const names[8] = {"sigma", "fft_split", "fft_tile_log2",
+                                         "window_tile_scale", "window_queue", "no_mid",
+                                         "eval_interp", "replay_ms"};
+    const std::string kq = "\"key\": \"" + key + "\"";
+    char line[2048];
+    bool found = false;
+    while (std::fgets(line, sizeof(line), f)) {
+        if (!std::strstr(line, kq.c_str())) continue;
+        double v[8];
+        bool ok = true;
+        for (int i = 0; i < 8 && ok; ++i) {
+            char pat[48];
+            std::snprintf(pat, sizeof(pat), "\"%s\": ", names[i]);
+            const char* q = std::strstr(line, pat);
+            char* end = nullptr;
+            if (q) v[i] = std::strtod(q + std::strlen(pat), &end);
+            ok = q && end != q + std::strlen(pat) && std::isfinite(v[i]);
+        }
+        if (!ok) continue;
+        ok = (v[0] == 0.0 || (v[0] >= 1.25 && v[0] <= 2.0)) && (v[1] >= 0 && v[1] <= 2) &&
+             (v[2] == 0 || v[2] == 12 || v[2] == 13) && (v[3] >= -2 && v[3] <= 2) &&
+             (v[4] == 0 || v[4] == 1) && (v[5] == 0 || v[5] == 1) && (v[6] == 0 || v[6] == 1);
+        if (!ok) continue;
+        Tune t;
+        t.sigma = v[0];
+        t.fft.split = (int)v[1];
+        t.fft.lgt_strided = (int)v[2];
+        t.jscale = (int)v[3];
+        t.queue = v[4] != 0.0;
+        t.no_mid = v[5] != 0.0;
+        t.eval_interp = v[6] != 0.0;
+        *out = t;
+        found = true;
+    }
+    std::fclose(f);
+    return found;
+}
+
+void tune_cache_store(const char* path, const std::string& key, const Tune& t, double ms) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    FILE* f = std::fopen(path, "a");
+    if (!f) {
+        if (log_level() > 0) std::fprintf(stderr, "ncf: autotune cache %s: cannot append\n", path);
+        return;
+    }
+    std::fprintf(f,
+                 "{\"key\": \"%s\", \"sigma\": %.17g, \"fft_split\": %d, \"fft_tile_log2\": %d, "
+                 "\"window_tile_scale\": %d, \"window_queue\": %d, \"no_mid\": %d, "
+                 "\"eval_interp\": %d, \"replay_ms\": %.6g}\n",
+                 key.c_str(), t.sigma, t.fft.split, t.fft.lgt_strided, t.jscale, t.queue ? 1 : 0,
+                 t.no_mid ? 1 : 0, t.eval_interp ? 1 : 0, ms);
+    std::fclose(f);
+}
+
 // Build a plan; with NCF_PLAN_AUTOTUNE, build and time candidate settings by
 // coordinate descent from the defaults (minimum oversampling, FFT radix split
 // and strided tile, window tile scale, window dispatch) and keep the fastest.
@@ -3195,6 +3339,33 @@ int plan_create(Job& J, const double* const* tin, const double* const* ein, ncf_
         }
     } guard{dummy};
     NCF_TRY(launch_fill_alternating(dummy, nmax, J.st));
+
+    // autotune cache: a plan whose key is there takes the recorded settings
+    const char* cpath =
+        (J.opt.flags & NCF_PLAN_AUTOTUNE) ? std::getenv("NCF_AUTOTUNE_CACHE") : nullptr;
+    if (cpath && !*cpath) cpath = nullptr;
+    std::string ckey;
+    if (cpath) {
+        int dev = 0;
+        NCF_TRY_HIP(hipGetDevice(&dev));
+        ckey = tune_key(J, dev, ein[0] != nullptr || (J.ccf && ein[1] != nullptr));
+        Tune ct;
+        if (tune_cache_find(cpath, ckey, &ct)) {
+            ncf_plan_s* P = new ncf_plan_s;
+            const int r = plan_build(P, J, tin, ein, ct, dummy);
+            if (r == NCF_OK) {
+                P->autotuned = 1;
+                P->tune_cached = 1;
+                if (log_level() > 0)
+                    std::fprintf(stderr, "ncf: plan settings from the autotune cache [%s]\n",
+                                 ckey.c_str());
+                *out = P;
+                return NCF_OK;
+            }
+            plan_free(P);  // e.g. a grid that no longer fits: tune again
+            clear_error();
+        }
+    }
 
     ncf_plan_s* best = new ncf_plan_s;
     int rc = plan_build(best, J, tin, ein, Tune{}, dummy);
@@ -3222,6 +3393,13 @@ int plan_create(Job& J, const double* const* tin, const double* const* ein, ncf_
                 return r == NCF_E_DEVICE ? r : NCF_OK;
             }
             ++ncand;
+            if (log_level() > 1)
+                std::fprintf(stderr,
+                             "ncf: autotune candidate sigma=%g fft_split=%d fft_tile_log2=%d "
+                             "window_tile_scale=%d window_queue=%d no_mid=%d eval_interp=%d: "
+                             "%.3f ms (best %.3f ms)\n",
+                             t.sigma, t.fft.split, t.fft.lgt_strided, t.jscale, t.queue ? 1 : 0,
+                             t.no_mid ? 1 : 0, t.eval_interp ? 1 : 0, tp, tb);
             if (tp < 0.97 * tb) {
                 plan_free(best);
                 best = P;
@@ -3285,6 +3463,10 @@ int plan_create(Job& J, const double* const* tin, const double* const* ein, ncf_
         best->autotuned = 1;
         best->candidates = ncand;
         best->replay_ms = tb;
+        if (cpath) tune_cache_store(cpath, ckey, best->tune, tb);
+        if (log_level() > 0)
+            std::fprintf(stderr, "ncf: plan autotuned over %d candidates: %.3f ms per execution\n",
+                         ncand, tb);
     }
     *out = best;
     return NCF_OK;
@@ -3468,6 +3650,7 @@ int ncf_plan_info(const ncf_plan_t* P, ncf_plan_info_t* info) {
     info->replay_ms = P->replay_ms;
     info->lattice_grids = P->fold_grids;
     info->lattice_off = P->tune.eval_interp ? 1 : 0;
+    info->tune_cached = P->tune_cached;
     return NCF_OK;
 }
 

@@ -55,7 +55,8 @@ class PlanInfo(ctypes.Structure):
                 ("sigma", ctypes.c_double), ("fft_split", ctypes.c_int32),
                 ("fft_tile_log2", ctypes.c_int32), ("window_tile_scale", ctypes.c_int32),
                 ("window_queue", ctypes.c_int32), ("replay_ms", ctypes.c_double),
-                ("lattice_grids", ctypes.c_int32), ("lattice_off", ctypes.c_int32)]
+                ("lattice_grids", ctypes.c_int32), ("lattice_off", ctypes.c_int32),
+                ("tune_cached", ctypes.c_int32)]
 
 
 class ProfileRecord(ctypes.Structure):

@@ -291,3 +291,92 @@ def test_autotuned_plans_match_oracle_and_default_plan(kind):
     finally:
         pa.close()
         pd.close()
+
+
+def test_autotune_cache(tmp_path, monkeypatch):
+    # NCF_AUTOTUNE_CACHE names a file of JSON records (one per line): a tuned
+    # plan appends its settings; a later plan of the same key takes them
+    # without timing candidates and runs the same kernels (bitwise equal
+    # outputs); lines that do not parse or hold values out of range are skipped
+    import json
+
+    path = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("NCF_AUTOTUNE_CACHE", str(path))
+    d = synth.small("c4", seed=41)
+    args = (d["offs"], d["t"], d["lags"], "gaussian", d["h"])
+    keys = ("sigma", "fft_split", "fft_tile_log2", "window_tile_scale", "window_queue",
+            "lattice_off")
+    print("case: c4-small autotuned plan through the autotune cache", flush=True)
+    p1 = ncf.plan_acf(*args, autotune=True)
+    try:
+        i1 = p1.info()
+        assert i1["autotuned"] == 1 and i1["tune_cached"] == 0 and i1["candidates"] >= 2
+        r1 = p1.execute(d["x"])[:4]
+    finally:
+        p1.close()
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1
+    rec = json.loads(lines[0])
+    assert set(rec) == {"key", "sigma", "fft_split", "fft_tile_log2", "window_tile_scale",
+                        "window_queue", "no_mid", "eval_interp", "replay_ms"}
+    p2 = ncf.plan_acf(*args, autotune=True)
+    try:
+        i2 = p2.info()
+        assert i2["autotuned"] == 1 and i2["tune_cached"] == 1 and i2["candidates"] == 0
+        assert all(i2[k] == i1[k] for k in keys)
+        r2 = p2.execute(d["x"])[:4]
+    finally:
+        p2.close()
+    for a, b in zip(r1, r2):
+        assert np.asarray(a).tobytes() == np.asarray(b).tobytes()
+    assert len(path.read_text().splitlines()) == 1  # nothing appended
+    # another key (other lags) is tuned anew and appended
+    p3 = ncf.plan_acf(d["offs"], d["t"], d["lags"][:8], "gaussian", d["h"], autotune=True)
+    try:
+        assert p3.info()["tune_cached"] == 0
+    finally:
+        p3.close()
+    assert len(path.read_text().splitlines()) == 2
+    # a broken line and an out-of-range record of the first key are skipped:
+    # the first plan's key is tuned again
+    bad = dict(rec, sigma=7.0)
+    path.write_text("not json at all\n" + json.dumps(bad) + "\n")
+    p4 = ncf.plan_acf(*args, autotune=True)
+    try:
+        assert p4.info()["tune_cached"] == 0
+    finally:
+        p4.close()
+    assert len(path.read_text().splitlines()) == 3
+
+
+def test_call_log(tmp_path):
+    # NCF_LOG=1: one line per call on stderr (route, grids, window work,
+    # fallback rows, statuses, host time); 2 adds the autotune candidates
+    import subprocess
+    import sys
+
+    code = (
+        "import numpy as np\n"
+        "from paper_2609_03866_amd import ncf, synth\n"
+        "d = synth.small('c2', seed=3)\n"
+        "ncf.acf(d['t'], d['x'], d['lags'], 'gaussian', d['h'], spectral_always=True)\n"
+        "ncf.ccf(d['t'], d['x'], d['s'], d['y'], d['lags'], 'rectangle', d['h'])\n"
+        "e = synth.small('c4', seed=5)\n"
+        "p = ncf.plan_acf(e['offs'], e['t'], e['lags'], 'gaussian', e['h'], autotune=True)\n"
+        "p.close()\n")
+    import os
+    env = dict(os.environ, NCF_LOG="2")
+    env.pop("NCF_AUTOTUNE_CACHE", None)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    print("case: NCF_LOG=2 in a child process", flush=True)
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True,
+                       text=True, timeout=240)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [ln for ln in r.stderr.splitlines() if ln.startswith("ncf: ")]
+    assert any(ln.startswith("ncf: acf n=1 ") and "route=spectral" in ln and "rc=0" in ln
+               for ln in lines), lines
+    assert any(ln.startswith("ncf: ccf n=1 ") and "rectangle" in ln and "route=direct" in ln
+               for ln in lines), lines
+    assert any(ln.startswith("ncf: plan-build acf n=") for ln in lines), lines
+    assert any(ln.startswith("ncf: autotune candidate ") for ln in lines), lines
+    assert any(ln.startswith("ncf: plan autotuned over ") for ln in lines), lines
