@@ -207,21 +207,58 @@ __device__ __forceinline__ double wave_scan(double v) {
     return v;
 }
 
+// Chunk-local inclusive prefix sums of x (x[k]: sample tid + k kThreads of
+// the chunk), in place; returns the chunk total. The samples pass through
+// LDS so that each thread holds a run of kPer consecutive samples and adds
+// them in order; the run totals take one wave scan, and each run adds the
+// totals of the preceding waves (in wave order) and of the preceding runs of
+// its wave: one scan per run instead of one per row of samples. buf holds
+// one chunk with a pad slot per run (kMomentChunk + kMomentChunk / kPer).
+__device__ __forceinline__ double chunk_scan(double (&x)[kPer], double* buf, double* wsum) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    auto pad = [](int e) { return e + e / kPer; };
+    __syncthreads();  // buf and wsum may still be read by a previous scan
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) buf[pad(tid + k * kThreads)] = x[k];
+    __syncthreads();
+    double r[kPer];
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) r[m] = buf[pad(tid * kPer + m)];
+#pragma unroll
+    for (int m = 1; m < kPer; ++m) r[m] += r[m - 1];
+    const double incl = wave_scan(r[kPer - 1]);
+    const double before = __shfl_up(incl, 1);  // runs of the wave before this one
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    double carry = 0.0, total = 0.0;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) {
+        if (q < wave) carry += wsum[q];
+        total += wsum[q];
+    }
+    if (lane > 0) carry += before;
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) buf[pad(tid * kPer + m)] = carry + r[m];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) x[k] = buf[pad(tid + k * kThreads)];
+    return total;
+}
+
 // Standardize one chunk and write the chunk-local inclusive prefix sums.
 // A thread holds the samples tid + k * kThreads (k < kPer) of its chunk: all
-// loads are issued before any store, and the prefix of sample (k, wave, lane)
-// is the carry of the preceding rows k, plus the totals of the preceding
-// waves of row k, plus the lane's inclusive wave scan (one barrier).
+// loads are issued before any store; the prefix sums come from chunk_scan.
 __global__ void __launch_bounds__(kThreads)
 k_standardize(MomentsArgs a) {
-    __shared__ double shv[3][kPer][kWaves];
+    __shared__ double sbuf[kMomentChunk + kMomentChunk / kPer];
+    __shared__ double swsum[kWaves];
     const Chunk ch = a.chunks[blockIdx.x];
     const SeriesDesc sd = a.series[ch.series];
     const SeriesStat st = a.stats[ch.series];
     const gptr<const double> X = gbl(a.io->x[sd.set] + sd.xoff);
     const gptr<const double> er = gbl(sd.err);
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
     const bool ok = st.status == NCF_OK;
     const double mean = st.mean;
     const double inv_sd = ok ? 1.0 / st.sd : 0.0;
@@ -274,48 +311,22 @@ k_standardize(MomentsArgs a) {
     double z[kPer];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) z[k] = w[k] != 0.0 ? 1.0 : 0.0;
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) v[k] = wave_scan(v[k]);
-    if (scan_w)
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) w[k] = wave_scan(w[k]);
-    if (scan_z)
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) z[k] = wave_scan(z[k]);
-    if (lane == 63)
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            shv[0][k][wave] = v[k];
-            shv[1][k][wave] = w[k];
-            shv[2][k][wave] = z[k];
-        }
-    __syncthreads();
-    double carry_v = 0.0, carry_w = 0.0, carry_z = 0.0;
+    const double tv = chunk_scan(v, sbuf, swsum);
+    const double tw = scan_w ? chunk_scan(w, sbuf, swsum) : 0.0;
+    const double tz = scan_z ? chunk_scan(z, sbuf, swsum) : 0.0;
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
         const int64_t i = ch.begin + tid + (int64_t)k * kThreads;
-        double ov = carry_v, ow = carry_w, oz = carry_z;
-        for (int q = 0; q < wave; ++q) {
-            ov += shv[0][k][q];
-            ow += shv[1][k][q];
-            oz += shv[2][k][q];
-        }
         if (i < ch.end) {
-            gbl(sd.pv)[i + 1] = ov + v[k];
-            if (sd.pw) gbl(sd.pw)[i + 1] = ow + w[k];
-            if (sd.pz) gbl(sd.pz)[i + 1] = oz + z[k];
-        }
-#pragma unroll
-        for (int q = 0; q < kWaves; ++q) {
-            carry_v += shv[0][k][q];
-            carry_w += shv[1][k][q];
-            carry_z += shv[2][k][q];
+            gbl(sd.pv)[i + 1] = v[k];
+            if (scan_w) gbl(sd.pw)[i + 1] = w[k];
+            if (scan_z) gbl(sd.pz)[i + 1] = z[k];
         }
     }
     if (tid == 0) {
-        a.chunk_tot[3 * (int64_t)blockIdx.x] = carry_v;
-        a.chunk_tot[3 * (int64_t)blockIdx.x + 1] = carry_w;
-        a.chunk_tot[3 * (int64_t)blockIdx.x + 2] = carry_z;
+        a.chunk_tot[3 * (int64_t)blockIdx.x] = tv;
+        a.chunk_tot[3 * (int64_t)blockIdx.x + 1] = tw;
+        a.chunk_tot[3 * (int64_t)blockIdx.x + 2] = tz;
         if (ch.begin == 0) {
             sd.pv[0] = 0.0;
             if (sd.pw) sd.pw[0] = 0.0;
