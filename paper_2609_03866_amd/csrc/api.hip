@@ -14,7 +14,9 @@
 // launch covers thousands of uneven series.
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <chrono>
+#include <condition_variable>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -22,8 +24,11 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "internal.h"
@@ -55,6 +60,88 @@ void set_error(const char* fmt, ...) {
 }
 
 void clear_error() { g_err.clear(); }
+
+// ------------------------------------------------------- host worker pool
+// The per-problem planning loops of large batches (grid geometry, window
+// task tiling) run on a few host threads: workers created on first use and
+// kept for the process (never joined: they only ever wait on the pool's
+// condition variable), one job at a time; a call that finds the pool busy
+// (another host thread's call) runs its loop alone. f(i) for i in [0, n)
+// must touch only its own outputs.
+class HostPool {
+   public:
+    static HostPool& get() {
+        static HostPool* pool = new HostPool();  // never destroyed (see above)
+        return *pool;
+    }
+    template <typename F>
+    void run(int64_t n, const F& f) {
+        constexpr int64_t kMinItems = 1024;  // below this the hand-off costs more
+        std::unique_lock<std::mutex> busy(job_mu_, std::try_to_lock);
+        if (n < kMinItems || nthreads_ == 0 || !busy.owns_lock()) {
+            for (int64_t i = 0; i < n; ++i) f(i);
+            return;
+        }
+        std::function<void(int64_t)> fn = [&f](int64_t i) { f(i); };
+        const int64_t nblk = (int64_t)(nthreads_ + 1) * 4;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            job_ = &fn;
+            n_ = n;
+            nblk_ = nblk;
+            next_.store(0);
+            left_ = nthreads_;
+            ++gen_;
+        }
+        cv_.notify_all();
+        work();
+        std::unique_lock<std::mutex> lk(mu_);
+        done_cv_.wait(lk, [&] { return left_ == 0; });
+        job_ = nullptr;
+    }
+
+   private:
+    HostPool() {
+        const unsigned hw = std::thread::hardware_concurrency();
+        nthreads_ = (int)std::min(7u, hw > 1 ? hw - 1 : 0u);
+        for (int i = 0; i < nthreads_; ++i) std::thread([this] { loop(); }).detach();
+    }
+    void work() {  // blocks of the current job until none is left
+        for (;;) {
+            const int64_t b = next_.fetch_add(1);
+            if (b >= nblk_) return;
+            const int64_t i0 = n_ * b / nblk_, i1 = n_ * (b + 1) / nblk_;
+            for (int64_t i = i0; i < i1; ++i) (*job_)(i);
+        }
+    }
+    void loop() {
+        uint64_t seen = 0;
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                cv_.wait(lk, [&] { return gen_ != seen; });
+                seen = gen_;
+            }
+            work();
+            std::lock_guard<std::mutex> lk(mu_);
+            if (--left_ == 0) done_cv_.notify_one();
+        }
+    }
+    int nthreads_ = 0;
+    std::mutex job_mu_;  // one job at a time
+    std::mutex mu_;
+    std::condition_variable cv_, done_cv_;
+    const std::function<void(int64_t)>* job_ = nullptr;
+    int64_t n_ = 0, nblk_ = 0;
+    std::atomic<int64_t> next_{0};
+    int left_ = 0;
+    uint64_t gen_ = 0;
+};
+
+template <typename F>
+void host_parallel_for(int64_t n, const F& f) {
+    HostPool::get().run(n, f);
+}
 
 // --------------------------------------------------------------- profiling
 
@@ -442,6 +529,9 @@ bool use_spectral(const Job& J) {
     if (J.kern == NCF_GAUSSIAN) return true;
     return J.opt.method == NCF_SPECTRAL;  // rectangle: diagnostic only
 }
+
+// log2 of a power of two (0 to 63)
+int ilog2_exact(int64_t n) { return n > 0 ? 63 - __builtin_clzll((unsigned long long)n) : 0; }
 
 int64_t pow2_at_least(double v) {
     if (!(v > 1.0)) return 1;
@@ -1029,8 +1119,31 @@ struct WinPlan {
     int wi_set, wo_set;  // window set, outer set (series index = problem)
     int64_t prob;
     int role;            // 0 main, 1 self x, 2 self y, 3 fallback
-    std::vector<double> dl;  // sorted lag offsets of this task
+    // sorted lag offsets of this task (tasks with the same offsets share one
+    // list, and one copy of it in the tables)
+    std::shared_ptr<const std::vector<double>> dl;
 };
+
+// Offsets of the distinct lag-offset lists of a launch's tasks in one table
+// (first[i]: task i is the first holder of its list); returns the length.
+size_t dl_layout(const std::vector<WinPlan>& plans, std::vector<size_t>* off,
+                 std::vector<char>* first) {
+    off->assign(plans.size(), 0);
+    first->assign(plans.size(), 0);
+    std::unordered_map<const std::vector<double>*, size_t> seen;
+    seen.reserve(plans.size());
+    size_t n = 0;
+    for (size_t i = 0; i < plans.size(); ++i) {
+        auto it = seen.find(plans[i].dl.get());
+        if (it == seen.end()) {
+            it = seen.emplace(plans[i].dl.get(), n).first;
+            n += plans[i].dl->size();
+            (*first)[i] = 1;
+        }
+        (*off)[i] = it->second;
+    }
+    return n;
+}
 // Window tasks of one launch: tile sizes, LDS size, work items.
 struct WinLaunch {
     std::vector<WinPlan> plans;
@@ -1176,11 +1289,26 @@ class CallRun {
     std::vector<std::pair<int, int>> groups, fwd_groups, inv_groups;
     std::vector<int> spec_of;
     std::vector<std::vector<int>> flagged;
+    std::vector<size_t> dl2_off;  // fallback tasks' lag offsets in the phase-3 table
+    std::vector<char> dl2_first;
     unsigned long long* qbase = nullptr;
     int32_t* h_fstat = nullptr;
     double* h_rmin = nullptr;
     std::chrono::steady_clock::time_point t_start = std::chrono::steady_clock::now();
     void log_call(int rc) const;
+    // NCF_LOG >= 3: host time of each step, in the call's log line
+    int log = 0;
+    std::chrono::steady_clock::time_point t_mark = t_start;
+    std::string steps;
+    void mark(const char* name) {
+        if (log < 3) return;
+        const auto now = std::chrono::steady_clock::now();
+        char b[64];
+        std::snprintf(b, sizeof(b), " %s=%.3f", name,
+                      std::chrono::duration<double, std::milli>(now - t_mark).count());
+        steps += b;
+        t_mark = now;
+    }
 };
 
 // Route flags and the derived arrays the call needs.
@@ -1430,6 +1558,18 @@ int CallRun::plan_route() {
         const double rate = fp64 ? 2e12 : 5e12;
         const double csz_b = fp64 ? 16.0 : 8.0;
         double direct_s = 0.0, spec_s = 30e-6;
+        // grid geometry of every problem (independent: host threads for
+        // large batches), then the costs in problem order
+        std::vector<int> grc((size_t)J.nprob, NCF_OK);
+        host_parallel_for(J.nprob, [&](int64_t p) {
+            if (pstat[p] != NCF_OK) return;
+            double tmin = stat_of(0, p).tmin, tmax = stat_of(0, p).tmax;
+            if (J.ccf) {
+                tmin = std::min(tmin, stat_of(1, p).tmin);
+                tmax = std::max(tmax, stat_of(1, p).tmax);
+            }
+            grc[p] = plan_grid(J, tmin, tmax, maxlag, J.h[p], &geom[p]);
+        });
         for (int64_t p = 0; p < J.nprob; ++p) {
             if (pstat[p] != NCF_OK) continue;
             const SeriesStat& s0 = stat_of(0, p);
@@ -1439,13 +1579,8 @@ int CallRun::plan_route() {
             const double pts = dens * 12.0 * J.h[p];
             const double windows = n1 * nrows + (J.ccf ? n0 + n1 : 0.0);
             direct_s += windows * (8.0 + 8.0 * pts) / rate;
-            double tmin = s0.tmin, tmax = s0.tmax;
-            if (J.ccf) {
-                tmin = std::min(tmin, stat_of(1, p).tmin);
-                tmax = std::max(tmax, stat_of(1, p).tmax);
-            }
-            SpecGeom& g = geom[p];
-            if (plan_grid(J, tmin, tmax, maxlag, J.h[p], &g) != NCF_OK) {
+            const SpecGeom& g = geom[p];
+            if (grc[p] != NCF_OK) {
                 clear_error();
                 direct_s = 0.0;  // no grid fits: the window route
                 break;
@@ -1561,13 +1696,14 @@ void CallRun::plan_window(WinLaunch& W) {
             }
             T.wo = dO.w64;
         }
-        T.K = (int32_t)P.dl.size();
+        const std::vector<double>& dl = *P.dl;
+        T.K = (int32_t)dl.size();
         T.h = h;
         T.W = rect ? h : 6.0 * h;
         double lext = 0.0;
-        for (size_t r = 0; r < P.dl.size(); r += 64) {
-            const size_t r1 = std::min(P.dl.size(), r + 64) - 1;
-            lext = std::max(lext, P.dl[r1] - P.dl[r]);
+        for (size_t r = 0; r < dl.size(); r += 64) {
+            const size_t r1 = std::min(dl.size(), r + 64) - 1;
+            lext = std::max(lext, dl[r1] - dl[r]);
         }
         const double span_w = std::max(sw.tmax - sw.tmin, 1e-300);
         const double span_o = std::max(so.tmax - so.tmin, 1e-300);
@@ -1669,14 +1805,16 @@ int CallRun::check_win(const WinLaunch& W, uint32_t f) const {
 // take whole (its numerator and pair counts, or the CCF lag-0 scales).
 void CallRun::plan_windows() {
     W1 = WinLaunch{};
+    const auto dall = std::make_shared<const std::vector<double>>(delta);
+    const auto dzero = std::make_shared<const std::vector<double>>(1, 0.0);
     for (int64_t p = 0; p < J.nprob; ++p) {
         if (pstat[p] != NCF_OK || (spec_b && !direct_p[p])) continue;
         if (!J.ccf) {
-            W1.plans.push_back({0, 0, p, 0, delta});
+            W1.plans.push_back({0, 0, p, 0, dall});
         } else {
-            if (Krow > 0) W1.plans.push_back({0, 1, p, 0, delta});
-            W1.plans.push_back({0, 0, p, 1, {0.0}});
-            W1.plans.push_back({1, 1, p, 2, {0.0}});
+            if (Krow > 0) W1.plans.push_back({0, 1, p, 0, dall});
+            W1.plans.push_back({0, 0, p, 1, dzero});
+            W1.plans.push_back({1, 1, p, 2, dzero});
         }
     }
     if (Krow == 0) delta.assign(1, 0.0);
@@ -1689,23 +1827,42 @@ void CallRun::plan_windows() {
 int CallRun::plan_spectral() {
     splans.clear();
     if (spectral) {
+        auto range = [&](int64_t p, double* tmin, double* tmax) {
+            *tmin = stat_of(0, p).tmin;
+            *tmax = stat_of(0, p).tmax;
+            if (J.ccf) {
+                *tmin = std::min(*tmin, stat_of(1, p).tmin);
+                *tmax = std::max(*tmax, stat_of(1, p).tmax);
+            }
+        };
+        // geometry of the problems the route choice did not plan (host
+        // threads for large batches)
+        std::vector<int> grc((size_t)J.nprob, NCF_OK);
+        host_parallel_for(J.nprob, [&](int64_t p) {
+            if (pstat[p] != NCF_OK || direct_p[p] || have_geom[p]) return;
+            double tmin, tmax;
+            range(p, &tmin, &tmax);
+            grc[p] = plan_grid(J, tmin, tmax, maxlag, J.h[p], &geom[p]);
+        });
+        // problems by grid size, stable (counting sort on log2 N)
+        int64_t cnt[65] = {0};
         for (int64_t p = 0; p < J.nprob; ++p) {
             if (pstat[p] != NCF_OK || direct_p[p]) continue;
-            double tmin = stat_of(0, p).tmin, tmax = stat_of(0, p).tmax;
-            if (J.ccf) {
-                tmin = std::min(tmin, stat_of(1, p).tmin);
-                tmax = std::max(tmax, stat_of(1, p).tmax);
+            if (grc[p] != NCF_OK) {
+                // the first failure in problem order; planned again here so
+                // that its message is this thread's
+                double tmin, tmax;
+                range(p, &tmin, &tmax);
+                NCF_TRY(plan_grid(J, tmin, tmax, maxlag, J.h[p], &geom[p]));
             }
-            SpecPlan sp;
-            sp.prob = p;
-            if (have_geom[p])
-                sp.g = geom[p];
-            else
-                NCF_TRY(plan_grid(J, tmin, tmax, maxlag, J.h[p], &sp.g));
-            splans.push_back(sp);
+            cnt[1 + ilog2_exact(geom[p].N)]++;
         }
-        std::stable_sort(splans.begin(), splans.end(),
-                         [](const SpecPlan& a, const SpecPlan& b) { return a.g.N < b.g.N; });
+        for (int b = 1; b < 65; ++b) cnt[b] += cnt[b - 1];
+        splans.resize((size_t)cnt[64]);
+        for (int64_t p = 0; p < J.nprob; ++p) {
+            if (pstat[p] != NCF_OK || direct_p[p]) continue;
+            splans[(size_t)cnt[ilog2_exact(geom[p].N)]++] = SpecPlan{p, geom[p]};
+        }
     }
     nts = (int)splans.size();
     Keval = (int)(J.ccf ? K : K + 1);
@@ -1858,7 +2015,9 @@ int CallRun::tables_phase2() {
     merge3 = !flag_pass || speculate;
     combine = speculate && !J.io_fixed;
     ndl = 0;
-    for (auto& P : W1.plans) ndl += P.dl.size();
+    std::vector<size_t> dl_off;
+    std::vector<char> dl_first;
+    ndl = dl_layout(W1.plans, &dl_off, &dl_first);
     t2 = Tables{};
     take2(t2);
     stg2 = nullptr;
@@ -1868,11 +2027,11 @@ int CallRun::tables_phase2() {
 
     // window tables: each task's sorted lag offsets
     {
-        size_t o = 0;
         for (int i = 0; i < ntw; ++i) {
-            std::memcpy(hT.dl + o, W1.plans[i].dl.data(), sizeof(double) * W1.plans[i].dl.size());
-            W1.wt[i].delta = dT.dl + o;
-            o += W1.plans[i].dl.size();
+            if (dl_first[i])
+                std::memcpy(hT.dl + dl_off[i], W1.plans[i].dl->data(),
+                            sizeof(double) * W1.plans[i].dl->size());
+            W1.wt[i].delta = dT.dl + dl_off[i];
         }
     }
     if (ntw) {
@@ -2042,11 +2201,11 @@ int CallRun::tables_phase2() {
 void CallRun::fill3(int ntw2, bool any_fb) {
     std::vector<int> fb_task(J.nprob, -1);
     {
-        size_t o = 0;
         for (int i = 0; i < ntw2; ++i) {
-            std::memcpy(hU.dl + o, W2.plans[i].dl.data(), sizeof(double) * W2.plans[i].dl.size());
-            W2.wt[i].delta = dU.dl + o;
-            o += W2.plans[i].dl.size();
+            if (dl2_first[i])
+                std::memcpy(hU.dl + dl2_off[i], W2.plans[i].dl->data(),
+                            sizeof(double) * W2.plans[i].dl->size());
+            W2.wt[i].delta = dU.dl + dl2_off[i];
             fb_task[W2.plans[i].prob] = i;
         }
         if (ntw2) {
@@ -2271,7 +2430,8 @@ void CallRun::read_flags() {
                 dl.push_back(delta[r]);
             }
         if (!dl.empty())
-            W2.plans.push_back({0, J.ccf ? 1 : 0, p, 3, std::move(dl)});
+            W2.plans.push_back(
+                {0, J.ccf ? 1 : 0, p, 3, std::make_shared<const std::vector<double>>(std::move(dl))});
     }
 }
 
@@ -2352,8 +2512,7 @@ int CallRun::separate3() {
         a3 = Arena{(char*)ws3, 0};
         layout3(a3);
     }
-    size_t ndl2 = 0;
-    for (auto& P : W2.plans) ndl2 += P.dl.size();
+    const size_t ndl2 = dl_layout(W2.plans, &dl2_off, &dl2_first);
     const bool any_fb = ntw2 > 0;
     Tables t3;
     take3(t3, ntw2, ndl2, any_fb);
@@ -2383,8 +2542,9 @@ int CallRun::done() {
                 again.push_back(p);
         if (!again.empty()) NCF_TRY(promote_fp64(J, again, h_fstat, stats));
     }
+    mark("wait_end");
     const int rc = finish_status(J, pstat, h_fstat);
-    if (log_level() > 0) log_call(rc);
+    if (log > 0) log_call(rc);
     return rc;
 }
 
@@ -2401,27 +2561,36 @@ void CallRun::log_call(int rc) const {
     std::fprintf(stderr,
                  "ncf: %s%s n=%lld K=%lld %s %s%s route=%s direct_problems=%lld grids=%d "
                  "cells=%lld lattice_grids=%d window_items=%lld window_launches=%d "
-                 "fallback_rows=%lld failed=%lld rc=%d host_ms=%.3f\n",
+                 "fallback_rows=%lld failed=%lld rc=%d host_ms=%.3f%s%s\n",
                  J.plan_build ? "plan-build " : "", J.ccf ? "ccf" : "acf", (long long)J.nprob,
                  (long long)J.K, rect ? "rectangle" : "gaussian", fp64 ? "fp64" : "mixed",
                  weighted ? " weighted" : "", spectral ? "spectral" : "direct",
                  (long long)ndirect, J.info_grids, (long long)J.info_grid_cells,
                  J.info_fold_grids, (long long)J.info_window_items, J.info_window_launches,
-                 (long long)W2.total_rows, (long long)nbad, rc, ms);
+                 (long long)W2.total_rows, (long long)nbad, rc, ms, steps.empty() ? "" : " steps:",
+                 steps.c_str());
 }
 
 int CallRun::run() {
+    log = log_level();
     init_flags();
     NCF_TRY(moments());
+    mark("moments");
     if (J.regular) return run_regular(J, sdesc, stats, pstat, d_stats);
     NCF_TRY(plan_route());
+    mark("route");
     plan_windows();
+    mark("windows");
     NCF_TRY(plan_spectral());
+    mark("spectral");
     NCF_TRY(alloc_phase2());
+    mark("alloc");
     NCF_TRY(tables_phase2());
+    mark("tables");
     NCF_TRY(record_window());
     NCF_TRY(record_spectral());
     NCF_TRY(record_flags());
+    mark("launch");
     if (!flag_pass) {  // tables uploaded with phase 2
         NCF_TRY(launch3(0, false));
         return done();
@@ -2429,16 +2598,20 @@ int CallRun::run() {
     if (speculate) {
         NCF_TRY(launch3(0, combine));
         NCF_TRY_HIP(hipStreamSynchronize(J.st));
+        mark("wait_flags");
         read_flags();
         if (W2.plans.empty()) return done();
     } else {
         NCF_TRY_HIP(hipStreamSynchronize(J.st));
+        mark("wait_flags");
         read_flags();
     }
     if (!W2.plans.empty()) plan_window(W2);
     J.info_window_items += W2.nitems;
     J.info_window_launches += W2.plans.empty() ? 0 : 1;
+    mark("fallback_plan");
     NCF_TRY(separate3());
+    mark("phase3");
     return done();
 }
 
