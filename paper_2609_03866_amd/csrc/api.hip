@@ -31,6 +31,8 @@
 #include <unordered_map>
 #include <vector>
 
+#include <unistd.h>
+
 #include "internal.h"
 #include "ncf_diag.h"
 
@@ -66,8 +68,9 @@ void clear_error() { g_err.clear(); }
 // task tiling) run on a few host threads: workers created on first use and
 // kept for the process (never joined: they only ever wait on the pool's
 // condition variable), one job at a time; a call that finds the pool busy
-// (another host thread's call) runs its loop alone. f(i) for i in [0, n)
-// must touch only its own outputs.
+// (another host thread's call, or a loop nested in a job) runs its loop
+// alone, and so does a forked child, which has no workers. f(i) for i in
+// [0, n) must touch only its own outputs and must not throw.
 class HostPool {
    public:
     static HostPool& get() {
@@ -78,7 +81,7 @@ class HostPool {
     void run(int64_t n, const F& f) {
         constexpr int64_t kMinItems = 1024;  // below this the hand-off costs more
         std::unique_lock<std::mutex> busy(job_mu_, std::try_to_lock);
-        if (n < kMinItems || nthreads_ == 0 || !busy.owns_lock()) {
+        if (n < kMinItems || nthreads_ == 0 || !busy.owns_lock() || getpid() != pid_) {
             for (int64_t i = 0; i < n; ++i) f(i);
             return;
         }
@@ -101,7 +104,7 @@ class HostPool {
     }
 
    private:
-    HostPool() {
+    HostPool() : pid_(getpid()) {
         const unsigned hw = std::thread::hardware_concurrency();
         nthreads_ = (int)std::min(7u, hw > 1 ? hw - 1 : 0u);
         for (int i = 0; i < nthreads_; ++i) std::thread([this] { loop(); }).detach();
@@ -127,6 +130,7 @@ class HostPool {
             if (--left_ == 0) done_cv_.notify_one();
         }
     }
+    pid_t pid_;  // the process whose threads these are
     int nthreads_ = 0;
     std::mutex job_mu_;  // one job at a time
     std::mutex mu_;
