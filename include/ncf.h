@@ -51,6 +51,12 @@
  *    that would need more returns NCF_E_NOMEM with a message before
  *    allocating, and the library stays usable for smaller calls. Unset or
  *    not a positive number: no bound beyond the device's memory.
+ *  - NCF_LOG (read at each call): 1 prints one line per call and per plan
+ *    build on stderr (kind, sizes, kernel, precision, route, grids, window
+ *    work, fallback lags, failed problems, status, host time); 2 adds each
+ *    autotuner candidate; 3 the host time of each planning step.
+ *  - NCF_AUTOTUNE_CACHE names the autotune cache file (see
+ *    ncf_plan_info_t.tune_cached).
  *
  * Errors
  *  - Every entry point returns NCF_OK (0) or a negative NCF_E_* code; on an
