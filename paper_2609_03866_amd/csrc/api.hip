@@ -1700,6 +1700,8 @@ void CallRun::plan_window(WinLaunch& W) {
             }
             T.wo = dO.w64;
         }
+        // chunk offsets of the window series' (chunk-local) prefix sums
+        if (rect) T.poff = d_ctot + 3 * (int64_t)dw.chunk0;
         const std::vector<double>& dl = *P.dl;
         T.K = (int32_t)dl.size();
         T.h = h;
@@ -1792,7 +1794,7 @@ void CallRun::plan_window(WinLaunch& W) {
 int CallRun::check_win(const WinLaunch& W, uint32_t f) const {
     const bool need_num = (f & WIN_NUMER) != 0, wtd = (f & WIN_WEIGHTED) != 0;
     for (const WinTask& T : W.wt) {
-        bool ok = T.t != nullptr && T.s != nullptr;
+        bool ok = T.t != nullptr && T.s != nullptr && (!rect || T.poff != nullptr);
         if (need_num) ok = ok && (rect ? T.pv != nullptr : T.v != nullptr) && T.vo != nullptr;
         if (wtd)
             ok = ok && (rect ? (T.pw != nullptr && T.pz != nullptr) : T.w != nullptr) &&

@@ -207,7 +207,10 @@ struct MomentsArgs {
     const Chunk* chunks;
     int32_t nseries, nchunks;
     double* chunk_part;      // 4 doubles per chunk: sw, mean, M2, flags
-    double* chunk_tot;       // 3 doubles per chunk (v, w, nonzero-weight count) totals for the prefix pass
+    double* chunk_tot;       // 3 doubles per chunk (v, w, nonzero-weight count): chunk totals,
+                             // then (chunk-offset pass) the exclusive sums of the preceding
+                             // chunks of the series, which readers of the chunk-local prefix
+                             // sums add
     SeriesStat* stats;       // nseries
     const IoBlock* io;       // value arrays
     int32_t prefix;          // any series has prefix outputs
@@ -251,6 +254,10 @@ struct WinTask {
     const double* pv;    // prefix of v (n_win + 1) or null
     const double* pw;    // prefix of w (n_win + 1) or null
     const double* pz;    // prefix count of nonzero weights (n_win + 1), weighted rectangle
+    // prefix sums above are chunk-local (kMomentChunk samples): entry j >= 1
+    // adds poff[3 c + q] (q = 0 values, 1 weights, 2 counts) of chunk
+    // c = (j - 1) / kMomentChunk, the exclusive sum of the preceding chunks
+    const double* poff;
     int64_t n_win;
     // outer array (series 2 of a CCF)
     const double* s;

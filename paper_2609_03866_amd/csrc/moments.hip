@@ -8,8 +8,10 @@
 // combines the chunks in order (pairwise update of mean and M2), so the
 // result is deterministic and does not suffer from the cancellation of a
 // one-pass sum of squares. The same chunks then write the standardized
-// values and, for the rectangle kernel, the FP64 prefix sums used by the
-// window scan (Algorithm "CorrSum, rectangle").
+// values and, for the rectangle kernel, the chunk-local FP64 prefix sums
+// used by the window scan (Algorithm "CorrSum, rectangle"), which adds the
+// chunk offsets (the exclusive sums of the preceding chunks) as it reads
+// them.
 #include "internal.h"
 
 namespace ncf {
@@ -388,42 +390,6 @@ k_chunk_offsets(MomentsArgs a) {
     }
 }
 
-// Add the chunk's offset to its prefix sums (a chunk holds at most kPer
-// samples per thread): loads first, then stores.
-__global__ void __launch_bounds__(kThreads)
-k_prefix_add(MomentsArgs a) {
-    const Chunk ch = a.chunks[blockIdx.x];
-    const SeriesDesc sd = a.series[ch.series];
-    if (!sd.pv) return;
-    if (ch.begin == 0) return;  // first chunk: offset 0
-    const double ov = a.chunk_tot[3 * (int64_t)blockIdx.x];
-    const double ow = a.chunk_tot[3 * (int64_t)blockIdx.x + 1];
-    const double oz = a.chunk_tot[3 * (int64_t)blockIdx.x + 2];
-    const gptr<double> pv = gbl(sd.pv), pw = gbl(sd.pw), pz = gbl(sd.pz);
-    double v[kPer], w[kPer], z[kPer];
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-        const int64_t i = ch.begin + threadIdx.x + (int64_t)k * kThreads;
-        v[k] = 0.0;
-        w[k] = 0.0;
-        z[k] = 0.0;
-        if (i < ch.end) {
-            v[k] = pv[i + 1];
-            if (sd.pw) w[k] = pw[i + 1];
-            if (sd.pz) z[k] = pz[i + 1];
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-        const int64_t i = ch.begin + threadIdx.x + (int64_t)k * kThreads;
-        if (i < ch.end) {
-            pv[i + 1] = v[k] + ov;
-            if (sd.pw) pw[i + 1] = w[k] + ow;
-            if (sd.pz) pz[i + 1] = z[k] + oz;
-        }
-    }
-}
-
 __global__ void __launch_bounds__(kThreads)
 k_fill_alternating(double* __restrict__ p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -461,10 +427,10 @@ int launch_standardize(const MomentsArgs& a, hipStream_t st) {
         hipLaunchKernelGGL(k_standardize, dim3(a.nchunks), dim3(kThreads), 0, st, a);
         NCF_CHECK_LAUNCH();
     }
+    // the prefix sums stay chunk-local: their reader (the window scan) adds
+    // the chunk offsets computed here
     if (a.prefix) {
         hipLaunchKernelGGL(k_chunk_offsets, dim3(a.nseries), dim3(kThreads), 0, st, a);
-        NCF_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_prefix_add, dim3(a.nchunks), dim3(kThreads), 0, st, a);
         NCF_CHECK_LAUNCH();
     }
     return NCF_OK;

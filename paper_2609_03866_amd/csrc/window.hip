@@ -35,28 +35,6 @@ namespace {
 
 constexpr int kThreads = 256;
 
-__device__ __forceinline__ int lower_idx(const double* a, int lo, int hi, double key) {
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (a[mid] < key)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
-__device__ __forceinline__ int upper_idx(const double* a, int lo, int hi, double key) {
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (a[mid] <= key)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
 struct Acc {
     double C, B, b;
     int64_t n;
@@ -95,6 +73,27 @@ struct GlbView {
     __device__ __forceinline__ double S(int j) const { return s[j]; }
     __device__ __forceinline__ double VO(int j) const { return vo[j]; }
     __device__ __forceinline__ double WO(int j) const { return wo[j]; }
+};
+
+// Offset of chunk-local prefix entry j (q: 0 values, 1 weights, 2 counts).
+__device__ __forceinline__ double prefix_off(gdp poff, int64_t j, int q) {
+    return j > 0 ? poff[3 * ((j - 1) / kMomentChunk) + q] : 0.0;
+}
+
+// The same view of a rectangle task whose prefix arrays start at prefix
+// entry base: each read adds its chunk offset.
+struct GlbPrefixView : GlbView {
+    gdp poff;
+    int64_t base;
+    __device__ __forceinline__ double A1(int i) const {
+        return a1[i] + prefix_off(poff, base + i, 0);
+    }
+    __device__ __forceinline__ double A2(int i) const {
+        return a2[i] + prefix_off(poff, base + i, 1);
+    }
+    __device__ __forceinline__ double A3(int i) const {
+        return a3[i] + prefix_off(poff, base + i, 2);
+    }
 };
 
 template <typename V>
@@ -435,7 +434,7 @@ __device__ __forceinline__ void window_item(const WinTask* __restrict__ tasks,
     // unweighted numerator: time and value prefix interleaved (records of 2)
     constexpr int RS = (RECT && NUMER && !WTD) ? 2 : 1;
     const gdp gt = (gdp)T.t, gs = (gdp)T.s, gvo = (gdp)T.vo, gwo = (gdp)T.wo;
-    const gdp ga1 = (gdp)A1g, ga2 = (gdp)A2g, ga3 = (gdp)T.pz;
+    const gdp ga1 = (gdp)A1g, ga2 = (gdp)A2g, ga3 = (gdp)T.pz, gpo = (gdp)T.poff;
 
     Acc acc = {0.0, 0.0, 0.0, 0};
     for (int jt = jg * T.G; jt < jt_end; ++jt) {
@@ -464,16 +463,17 @@ __device__ __forceinline__ void window_item(const WinTask* __restrict__ tasks,
             for (int i = tid; i < len + 8; i += kThreads) {
                 double* r = g_win_lds + 2 * i;
                 r[0] = i < len ? gt[tlo + i] : kInf;
-                r[1] = i <= len ? ga1[tlo + i] : 0.0;
+                r[1] = i <= len ? ga1[tlo + i] + prefix_off(gpo, tlo + i, 0) : 0.0;
             }
         } else if (RECT && fits) {
             for (int i = tid; i < len + 8; i += kThreads) {
                 double* r = g_win_lds + i;
                 r[0] = i < len ? gt[tlo + i] : kInf;
-                if (NUMER) r[dp] = i <= len ? ga1[tlo + i] : 0.0;
+                if (NUMER) r[dp] = i <= len ? ga1[tlo + i] + prefix_off(gpo, tlo + i, 0) : 0.0;
                 if (WTD) {
-                    r[QW * dp] = i <= len ? ga2[tlo + i] : 0.0;
-                    r[(QW + 1) * dp] = i <= len ? ga3[tlo + i] : 0.0;
+                    r[QW * dp] = i <= len ? ga2[tlo + i] + prefix_off(gpo, tlo + i, 1) : 0.0;
+                    r[(QW + 1) * dp] =
+                        i <= len ? ga3[tlo + i] + prefix_off(gpo, tlo + i, 2) : 0.0;
                 }
             }
         } else if (fits) {
@@ -514,15 +514,20 @@ __device__ __forceinline__ void window_item(const WinTask* __restrict__ tasks,
                 LdsView v{o_t, o_a1, o_a2, o_s, o_vo, o_wo, len};
                 scan_lane<F>(acc, v, ja, jb, delta, W, inv_h);
             } else {
-                GlbView v{(gdp)(T.t + tlo),
-                          HAS_A1 ? (gdp)(A1g + tlo) : nullptr,
-                          HAS_A2 ? (gdp)(A2g + tlo) : nullptr,
-                          (RECT && WTD) ? (gdp)(T.pz + tlo) : nullptr,
-                          (gdp)(T.s + j0),
-                          NUMER ? (gdp)(T.vo + j0) : nullptr,
-                          WTD ? (gdp)(T.wo + j0) : nullptr,
-                          len};
-                scan_lane<F>(acc, v, ja, jb, delta, W, inv_h);
+                const GlbView g{(gdp)(T.t + tlo),
+                                HAS_A1 ? (gdp)(A1g + tlo) : nullptr,
+                                HAS_A2 ? (gdp)(A2g + tlo) : nullptr,
+                                (RECT && WTD) ? (gdp)(T.pz + tlo) : nullptr,
+                                (gdp)(T.s + j0),
+                                NUMER ? (gdp)(T.vo + j0) : nullptr,
+                                WTD ? (gdp)(T.wo + j0) : nullptr,
+                                len};
+                if constexpr (RECT) {  // chunk-local prefix sums: offsets on read
+                    const GlbPrefixView v{g, gpo, tlo};
+                    scan_lane<F>(acc, v, ja, jb, delta, W, inv_h);
+                } else {
+                    scan_lane<F>(acc, g, ja, jb, delta, W, inv_h);
+                }
             }
         }
     }
