@@ -394,3 +394,29 @@ def test_ccf_weights_on_one_side(side, kernel, prec, method, ctol, btol):
                          precision=prec, method=method)
     assert s == 0
     _check(c, b, n, oc, ob, on, kernel, ctol, btol)
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_rectangle_dense_burst_global_window_path(weighted):
+    # a burst of 4,000 samples within one day in a 7,000-sample series: the
+    # windows of the outer samples near it hold more samples than the LDS
+    # stage, so the scan reads the window arrays from global memory, and the
+    # burst spans several prefix chunks (2,048 samples each) whose offsets
+    # are added on that path too; exact counts against the oracle
+    rng = np.random.default_rng(77)
+    t = np.sort(np.concatenate([rng.uniform(0.0, 1000.0, 3000), rng.uniform(500.0, 501.0, 4000)]))
+    s = np.sort(rng.uniform(0.0, 1000.0, 2000))
+    x = rng.standard_normal(t.size)
+    y = rng.standard_normal(s.size)
+    lags = np.linspace(-20.0, 20.0, 81)
+    ex = 10.0 ** rng.uniform(-1.5, 0.0, t.size) if weighted else None
+    ey = 10.0 ** rng.uniform(-1.5, 0.0, s.size) if weighted else None
+    print(f"case: rectangle burst CCF/ACF, weighted={weighted}", flush=True)
+    st, oc, ob, on = O.ccf(t, x, s, y, lags, "rectangle", 0.5, ex=ex, ey=ey)
+    assert st == 0
+    c, b, n, _ = ncf.ccf(t, x, s, y, lags, "rectangle", 0.5, ex=ex, ey=ey)
+    _check(c, b, n, oc, ob, on, "rectangle", 1e-9, 0)
+    st, oc, ob, on = O.acf(t, x, lags[40:], "rectangle", 0.5, err=ex)
+    assert st == 0
+    c, b, n, _ = ncf.acf(t, x, lags[40:], "rectangle", 0.5, err=ex)
+    _check(c, b, n, oc, ob, on, "rectangle", 1e-9, 0)
