@@ -239,22 +239,25 @@ __device__ __forceinline__ void dft_r(C2* a, int sign) {
 __device__ __forceinline__ int lds_pad(int e) { return e + (e >> 4); }
 
 // One Stockham stage of radix RADIX over the tile's C columns of length R.
-// Each thread owns 16 / RADIX butterflies (16 elements). Inputs come from
-// `src` (global or LDS view), outputs go to `dst`.
-// tid: the thread's index among the 2^(LGT-4) threads of the tile. `on`
+// Each thread owns EPT / RADIX butterflies (EPT elements, 16 unless a
+// caller asks for fewer). Inputs come from `src` (global or LDS view),
+// outputs go to `dst`.
+// tid: the thread's index among the 2^LGT / EPT threads of the tile. `on`
 // false: the thread does no work and only meets the stage's barriers, which
 // lie outside the work it skips.
-template <int RADIX, bool FROM_GLOBAL, bool TO_GLOBAL, int LGR, int NS, int LGT, typename C2>
+template <int RADIX, bool FROM_GLOBAL, bool TO_GLOBAL, int LGR, int NS, int LGT, int EPT = 16,
+          typename C2>
 __device__ __forceinline__ void stockham_stage(const PassArgs& a, C2* lds, C2* gbase, int64_t s0,
                                                int tid, bool on = true) {
-    constexpr int kThreads = 1 << (LGT - 4);  // 16 elements per thread
-    constexpr int NB = 16 / RADIX;  // butterflies per thread
+    static_assert(RADIX <= EPT && EPT <= 16, "a thread holds whole butterflies");
+    constexpr int kThreads = (1 << LGT) / EPT;  // EPT elements per thread
+    constexpr int NB = EPT / RADIX;             // butterflies per thread
     constexpr int lgC = LGT - LGR;
     constexpr int R = 1 << LGR;
     constexpr int C = 1 << lgC;
     constexpr int Rr = R / RADIX;
     constexpr int Ns = NS;
-    C2 v[16];
+    C2 v[EPT];
     int jj[NB], cc[NB];
 #pragma unroll
     for (int u = 0; u < NB && on; ++u) {
@@ -344,18 +347,20 @@ __device__ __forceinline__ void run_stages(const PassArgs& a, C2* lds, C2* gbase
 
 // Stages of one tile column of length 2^LGR, as run_stages, with the source
 // of the first stage (global memory or LDS) and the destination of the last
-// (global memory or LDS) chosen at compile time.
-template <int LGR, int ST, int NS, int LGT, bool G_IN, bool G_OUT, typename C2>
+// (global memory or LDS) chosen at compile time; EPT elements per thread
+// (radix-EPT stages, then one for the remainder).
+template <int LGR, int ST, int NS, int LGT, bool G_IN, bool G_OUT, int EPT = 16, typename C2>
 __device__ __forceinline__ void run_stages_io(const PassArgs& a, C2* lds, C2* gbase, int64_t s0,
                                               int tid, bool on = true) {
-    constexpr int n16 = LGR / 4;
-    constexpr int rem = LGR % 4;
-    constexpr int nst = n16 + (rem ? 1 : 0);
+    constexpr int lgE = __builtin_ctz(EPT);
+    constexpr int nbig = LGR / lgE;
+    constexpr int rem = LGR % lgE;
+    constexpr int nst = nbig + (rem ? 1 : 0);
     if constexpr (ST < nst) {
-        constexpr int RX = ST < n16 ? 16 : (1 << rem);
-        stockham_stage<RX, G_IN && ST == 0, G_OUT && ST == nst - 1, LGR, NS, LGT>(a, lds, gbase,
-                                                                                   s0, tid, on);
-        run_stages_io<LGR, ST + 1, NS * RX, LGT, G_IN, G_OUT>(a, lds, gbase, s0, tid, on);
+        constexpr int RX = ST < nbig ? EPT : (1 << rem);
+        stockham_stage<RX, G_IN && ST == 0, G_OUT && ST == nst - 1, LGR, NS, LGT, EPT>(
+            a, lds, gbase, s0, tid, on);
+        run_stages_io<LGR, ST + 1, NS * RX, LGT, G_IN, G_OUT, EPT>(a, lds, gbase, s0, tid, on);
     }
 }
 

@@ -61,18 +61,6 @@ __device__ __forceinline__ int64_t find_task(const int64_t* starts, int ntasks, 
     return lo;
 }
 
-__device__ __forceinline__ int64_t lower_bound_d(const double* a, int64_t n, double key) {
-    int64_t lo = 0, hi = n;
-    while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (a[mid] < key)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
 // Sample index ranges [p0, p1) that reach each spreading tile, from one
 // coalesced pass over the sorted samples instead of a search per tile. With
 // u_i the FP64 grid coordinate of sample i, tile g (cells [gT, gT + T)) needs
@@ -889,16 +877,18 @@ extern __shared__ char g_mid_lds[];
 // p = k_low + N1 r2 into the P2-point inverse DFT of the tile's F at
 // n mod P2, times exp(-2 pi i k_low n / P), summed over the N1 tiles; this
 // function leaves Y[n2] = that inverse DFT in ybuf[k_low P2 + n2]. The DFT
-// runs as Stockham stages in LDS (radix 16, then one of 8, 4 or 2; 16
-// entries per thread, so P2 / 16 of the half's 256 threads take part) with
-// the twiddle progressions of the FFT passes. The planner keeps
-// 16 <= P2 <= 2048 (2 <= N / P <= 256). Each half of the workgroup (256
-// threads) takes its own tile; every thread meets the same barriers.
+// runs as Stockham stages in LDS with the twiddle progressions of the FFT
+// passes: 8 entries per thread for P2 = 2048 (radix 8, 8, 8, 4 over all 256
+// threads of the half), 4 below (radix-4 stages, then one of 2; P2 / 4
+// threads). The planner keeps 16 <= P2 <= 2048 (2 <= N / P <= 256). Each
+// half of the workgroup (256 threads) takes its own tile; every thread
+// meets the same barriers.
 template <int LG, typename C2>
 __device__ __forceinline__ void fold_dft(const fftk::PassArgs& a, C2* tile, bool act, int lt) {
-    // one column of 2^LG entries; threads past 2^(LG - 4) only keep the barriers
-    fftk::run_stages_io<LG, 0, 1, LG, false, false>(a, tile, tile, 0, lt,
-                                                    act && lt < (1 << (LG - 4)));
+    // one column of 2^LG entries; threads past 2^LG / EPT only keep the barriers
+    constexpr int EPT = LG >= 11 ? 8 : 4;
+    fftk::run_stages_io<LG, 0, 1, LG, false, false, EPT>(a, tile, tile, 0, lt,
+                                                         act && lt < (1 << LG) / EPT);
 }
 
 template <typename R>
