@@ -436,25 +436,30 @@ __device__ __forceinline__ void window_item(const WinTask* __restrict__ tasks,
     const gdp gt = (gdp)T.t, gs = (gdp)T.s, gvo = (gdp)T.vo, gwo = (gdp)T.wo;
     const gdp ga1 = (gdp)A1g, ga2 = (gdp)A2g, ga3 = (gdp)T.pz, gpo = (gdp)T.poff;
 
+    // window range [tlo, thi) of j-tile jt for this item's lags, into slot
+    // sl of sh_rng: wave 0 searches the low end, wave 1 the high end
+    auto search_tile = [&](int jt_s, int sl) {
+        const int64_t a0 = (int64_t)jt_s * T.J;
+        const int64_t a1 = min(a0 + (int64_t)T.J, T.n_out);
+        if (wave == 0) {
+            const double lo_key = (T.s[a0] + T.delta[k0]) - W;
+            const int64_t r = wave_search<double>(T.t, T.n_win, lo_key, false);
+            if (lane == 0) sh_rng[2 * sl] = r;
+        } else if (wave == 1) {
+            const double hi_key = (T.s[a1 - 1] + T.delta[k0 + nk - 1]) + W;
+            const int64_t r = wave_search<double>(T.t, T.n_win, hi_key, RECT);
+            if (lane == 0) sh_rng[2 * sl + 1] = r;
+        }
+    };
     Acc acc = {0.0, 0.0, 0.0, 0};
+    search_tile(jg * T.G, 0);
     for (int jt = jg * T.G; jt < jt_end; ++jt) {
+        const int sl = (jt - jg * T.G) & 1;
         const int64_t j0 = (int64_t)jt * T.J;
         const int64_t j1 = min(j0 + (int64_t)T.J, T.n_out);
-        if (wave == 0) {
-            const double dmin = T.delta[k0];
-            const double dmax = T.delta[k0 + nk - 1];
-            const double lo_key = (T.s[j0] + dmin) - W;
-            const double hi_key = (T.s[j1 - 1] + dmax) + W;
-            int64_t tlo = wave_search<double>(T.t, T.n_win, lo_key, false);
-            int64_t thi = wave_search<double>(T.t, T.n_win, hi_key, RECT);
-            if (lane == 0) {
-                sh_rng[0] = tlo;
-                sh_rng[1] = thi;
-            }
-        }
-        __syncthreads();  // also: every wave is done with the previous tile
-        const int64_t tlo = sh_rng[0];
-        const int64_t thi = sh_rng[1];
+        __syncthreads();  // the tile's range is in slot sl; every wave is done with the previous tile
+        const int64_t tlo = sh_rng[2 * sl];
+        const int64_t thi = sh_rng[2 * sl + 1];
         const int len = (int)(thi - tlo);
         const int nj = (int)(j1 - j0);
         const bool fits = (thi - tlo) <= cap && (RECT || nj <= jmax);
@@ -490,6 +495,9 @@ __device__ __forceinline__ void window_item(const WinTask* __restrict__ tasks,
             }
         }
         __syncthreads();
+        // the next tile's range, searched while this one is scanned (its
+        // slot was last read before the barrier above)
+        if (jt + 1 < jt_end) search_tile(jt + 1, sl ^ 1);
 
         const int ja = (int)((int64_t)nj * seg / nseg);
         const int jb = (int)((int64_t)nj * (seg + 1) / nseg);
