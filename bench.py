@@ -272,6 +272,30 @@ def counts_equal(gpu_n, orc_ns, pick=None):
     return bool(all(np.array_equal(g[i], orc_ns[i]) for i in range(len(orc_ns))))
 
 
+def measure_copy_bandwidth(torch):
+    """HBM bandwidth of a plain device copy on this GPU (1 GiB read + 1 GiB
+    written per copy, best of 5, HIP events), to set beside the published
+    8 TB/s that the roofline uses as its peak."""
+    n = 256 * 1024 * 1024  # float32 elements: 1 GiB
+    src = torch.ones(n, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(5):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    nbytes = 2 * 4 * n
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"GB_per_s": nbytes / best / 1e9, "bytes_per_copy": nbytes,
+            "frac_of_published": nbytes / best / HBM_PEAK}
+
+
 def measured_traffic(workload, kernel):
     """HBM bytes per dispatch of `kernel` from the committed rocprofv3 counter
     summary (calibrated FETCH_SIZE + WRITE_SIZE), or None when no summary
@@ -338,6 +362,8 @@ def main():
             cal_dst.copy_(cal_src)
         torch.cuda.synchronize()
         del cal_src, cal_dst
+    copy_bw = measure_copy_bandwidth(torch)
+    log(f"[bench] device copy: {copy_bw['GB_per_s']:.0f} GB/s (read + write)")
     log(f"[bench] generating workload {args.workload}")
     host = make_workload(args.workload)
     devs = [to_dev(d) for d in host]
@@ -572,6 +598,7 @@ def main():
         "plan_replay": plan_rep,
         "accuracy_vs_oracle": acc,
         "roofline": roof,
+        "hbm_copy_measured": copy_bw,
         "kernels": kernels,
         "cpu_baseline": cpu,
     }
