@@ -1029,90 +1029,168 @@ int run_job(Job& J, const double* const* tin, const double* const* xin,
             const double* const* ein);
 
 // Problems of a finished mixed-precision call whose smallest lag-0 scale is
-// below kPromoteScale are evaluated again in FP64 (same method, one problem
-// per call on the call's stream), and their outputs and statuses replace
-// the mixed ones. They run in a workspace of their own: the call's arenas
-// still hold their inputs (device copies in host-pointer mode, replicate
-// series of the resampling calls).
+// below kPromoteScale are evaluated again in FP64 (same estimator), and
+// their outputs and statuses replace the mixed ones. Each problem takes the
+// direct window sums (the real-space estimator itself) unless their work
+// (windows x (8 + 8 x samples per window) lane-ops) would take more than
+// about 10 ms; then the call's method in FP64. The problems of each choice
+// run as one batch call on the call's stream: their series are gathered
+// into a workspace of their own (the call's arenas still hold the inputs:
+// device copies in host-pointer mode, replicate series of the resampling
+// calls), and the batch's rows are scattered back into the outputs.
+int promote_batch(Job& J, const std::vector<int64_t>& probs, int method, int32_t* h_fstat);
+
 int promote_fp64(Job& J, const std::vector<int64_t>& probs, int32_t* h_fstat,
                  const std::vector<SeriesStat>& stats) {
-    const int nsets = J.ccf ? 2 : 1;
     const int64_t K = J.K;
-    Resources R2;
-    R2.exact = true;
-    double* dout = nullptr;
-    if (hipMalloc((void**)&dout, sizeof(double) * 2 * (size_t)std::max<int64_t>(K, 1)) !=
-        hipSuccess) {
+    std::vector<int64_t> direct, other;
+    for (int64_t p : probs) {
+        const SeriesStat& sw = stats[J.set[0].sd0 + p];
+        const int so = J.ccf ? 1 : 0;
+        const double nw = (double)(J.set[0].offs[p + 1] - J.set[0].offs[p]);
+        const double no = (double)(J.set[so].offs[p + 1] - J.set[so].offs[p]);
+        const double dens = (nw - 1.0) / std::max(sw.tmax - sw.tmin, 1e-300);
+        const double pts = std::min(dens * 12.0 * J.h[p], nw);
+        const double windows = no * (double)(K + 1) + (J.ccf ? nw + no : 0.0);
+        (windows * (8.0 + 8.0 * pts) <= 2e10 ? direct : other).push_back(p);
+    }
+    if (!direct.empty()) NCF_TRY(promote_batch(J, direct, NCF_DIRECT, h_fstat));
+    if (!other.empty()) NCF_TRY(promote_batch(J, other, J.opt.method, h_fstat));
+    return NCF_OK;
+}
+
+int promote_batch(Job& J, const std::vector<int64_t>& probs, int method, int32_t* h_fstat) {
+    const int nsets = J.ccf ? 2 : 1;
+    const int64_t K = J.K, nb = (int64_t)probs.size();
+    const int64_t Kr = std::max<int64_t>(K, 1);
+    // workspace: segment tables (per set: values, then times; outputs), the
+    // gathered series (per set: t, x and err when present), the batch outputs
+    std::vector<CopySeg> segs;
+    segs.reserve((size_t)(2 * nsets + 1) * nb);
+    int64_t nser[2] = {0, 0};
+    size_t seg0[2][2] = {{0, 0}, {0, 0}};
+    for (int si = 0; si < nsets; ++si) {
+        const SeriesSet& S = J.set[si];
+        for (int part = 0; part < 2; ++part) {  // 0: values and errors, 1: times
+            seg0[si][part] = segs.size();
+            int64_t at = 0;
+            for (int64_t p : probs) {
+                const int64_t o = S.offs[p], n = S.offs[p + 1] - o;
+                segs.push_back({part == 1 && S.shared_t ? 0 : o, at, n});
+                at += n;
+            }
+            nser[si] = at;
+        }
+    }
+    const size_t segout = segs.size();
+    for (int64_t i = 0; i < nb; ++i) segs.push_back({i * Kr, probs[i] * K, K});
+    size_t bytes = sizeof(CopySeg) * segs.size();
+    bytes = (bytes + 255) & ~(size_t)255;
+    const size_t data0 = bytes;
+    for (int si = 0; si < nsets; ++si)
+        bytes += sizeof(double) * (size_t)nser[si] * (J.set[si].err ? 3 : 2);
+    const size_t out0 = bytes;
+    bytes += sizeof(double) * 2 * (size_t)(nb * Kr);
+    char* ws = nullptr;
+    if (hipMalloc((void**)&ws, bytes) != hipSuccess) {
         (void)hipGetLastError();
         set_error("workspace allocation for the FP64 re-evaluation failed");
         return NCF_E_NOMEM;
     }
-    int rc = NCF_OK;
-    for (int64_t p : probs) {
-        Job P;
-        P.ccf = J.ccf;
-        P.nprob = 1;
-        P.kern = J.kern;
-        P.h.assign(1, J.h[p]);
-        P.lags = J.lags;
-        P.K = K;
-        P.c = dout;
-        P.b = dout + std::max<int64_t>(K, 1);
-        P.count = nullptr;
-        int pst = NCF_OK;
-        P.status = &pst;
-        P.opt = J.opt;
-        P.opt.precision = NCF_FP64;
-        // the direct window sums (the real-space estimator itself) unless
-        // their work (windows x (8 + 8 x samples per window) lane-ops) would
-        // take more than about 10 ms; then the call's method in FP64
-        {
-            const SeriesStat& sw = stats[J.set[0].sd0 + p];
-            const int so = J.ccf ? 1 : 0;
-            const double nw = (double)(J.set[0].offs[p + 1] - J.set[0].offs[p]);
-            const double no = (double)(J.set[so].offs[p + 1] - J.set[so].offs[p]);
-            const double dens = (nw - 1.0) / std::max(sw.tmax - sw.tmin, 1e-300);
-            const double pts = std::min(dens * 12.0 * J.h[p], nw);
-            const double windows = no * (double)(K + 1) + (J.ccf ? nw + no : 0.0);
-            if (windows * (8.0 + 8.0 * pts) <= 2e10) P.opt.method = NCF_DIRECT;
+    std::unique_ptr<char, void (*)(char*)> ws_guard(ws, [](char* q) { (void)hipFree(q); });
+    CopySeg* d_segs = (CopySeg*)ws;
+    NCF_TRY_HIP(hipMemcpyAsync(d_segs, segs.data(), sizeof(CopySeg) * segs.size(),
+                               hipMemcpyHostToDevice, J.st));
+    Job P;
+    P.ccf = J.ccf;
+    P.nprob = nb;
+    P.kern = J.kern;
+    P.h.resize((size_t)nb);
+    for (int64_t i = 0; i < nb; ++i) P.h[(size_t)i] = J.h[probs[(size_t)i]];
+    P.lags = J.lags;
+    P.K = K;
+    P.c = (double*)(ws + out0);
+    P.b = P.c + nb * Kr;
+    P.count = nullptr;
+    // a status left at kUnset after the call means the call itself failed
+    constexpr int kUnset = 1;
+    std::vector<int> pst((size_t)nb, kUnset);
+    P.status = pst.data();
+    P.opt = J.opt;
+    P.opt.precision = NCF_FP64;
+    P.opt.method = method;
+    P.opt.flags = (J.opt.flags & (NCF_SPECTRAL_ALWAYS | NCF_WINDOW_QUEUE)) | NCF_DEVICE_POINTERS;
+    P.dev_ptrs = true;
+    P.st = J.st;
+    Resources R2;
+    R2.exact = true;
+    P.res = &R2;
+    P.no_b = J.no_b;
+    const double* tin[2] = {nullptr, nullptr};
+    const double* xin[2] = {nullptr, nullptr};
+    const double* ein[2] = {nullptr, nullptr};
+    double* at = (double*)(ws + data0);
+    for (int si = 0; si < nsets; ++si) {
+        const SeriesSet& S = J.set[si];
+        const int64_t n = nser[si];
+        double* gt = at;
+        double* gx = gt + n;
+        double* ge = S.err ? gx + n : nullptr;
+        at += n * (S.err ? 3 : 2);
+        const double* sv[3] = {S.x, S.err, nullptr};
+        double* dv[3] = {gx, ge, nullptr};
+        NCF_TRY(launch_copy_segments(d_segs + seg0[si][0], nb, sv, dv, J.st));
+        const double* st3[3] = {S.t, nullptr, nullptr};
+        double* dt3[3] = {gt, nullptr, nullptr};
+        NCF_TRY(launch_copy_segments(d_segs + seg0[si][1], nb, st3, dt3, J.st));
+        SeriesSet& Q = P.set[si];
+        Q.ntot = n;
+        Q.nser = (int)nb;
+        Q.offs.resize((size_t)nb + 1);
+        Q.offs[0] = 0;
+        for (int64_t i = 0; i < nb; ++i)
+            Q.offs[(size_t)i + 1] = Q.offs[(size_t)i] + segs[seg0[si][0] + (size_t)i].len;
+        Q.wmode = S.wmode;
+        tin[si] = gt;
+        xin[si] = gx;
+        ein[si] = ge;
+    }
+    int rc = run_job(P, tin, xin, ein);
+    for (int v : pst)
+        if (v == kUnset) {  // the batch call failed before reporting statuses
+            (void)hipStreamSynchronize(J.st);
+            free_resources(R2);
+            return rc != NCF_OK ? rc : NCF_E_DEVICE;
         }
-        P.opt.flags = (J.opt.flags & (NCF_SPECTRAL_ALWAYS | NCF_WINDOW_QUEUE)) | NCF_DEVICE_POINTERS;
-        P.dev_ptrs = true;
-        P.st = J.st;
-        P.res = &R2;
-        P.no_b = J.no_b;
-        const double* tin[2] = {nullptr, nullptr};
-        const double* xin[2] = {nullptr, nullptr};
-        const double* ein[2] = {nullptr, nullptr};
-        for (int si = 0; si < nsets; ++si) {
-            const SeriesSet& S = J.set[si];
-            const int64_t o = S.offs[p], n = S.offs[p + 1] - o;
-            SeriesSet& Q = P.set[si];
-            Q.ntot = n;
-            Q.nser = 1;
-            Q.offs = {0, n};
-            Q.wmode = S.wmode;
-            tin[si] = S.shared_t ? S.t : S.t + o;
-            xin[si] = S.x + o;
-            ein[si] = S.err ? S.err + o : nullptr;
-        }
-        rc = run_job(P, tin, xin, ein);
-        if (rc != NCF_OK && pst == NCF_OK) break;  // a call failure, not a series status
-        rc = NCF_OK;
-        h_fstat[p] = pst;
-        if (K > 0) {
-            const hipMemcpyKind kind = J.dev_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-            if (hipMemcpyAsync(J.c + p * K, P.c, sizeof(double) * K, kind, J.st) != hipSuccess ||
-                hipMemcpyAsync(J.b + p * K, P.b, sizeof(double) * K, kind, J.st) != hipSuccess) {
+    rc = NCF_OK;
+    for (int64_t i = 0; i < nb; ++i) h_fstat[probs[(size_t)i]] = pst[(size_t)i];
+    if (K > 0) {
+        if (J.dev_ptrs) {
+            const double* so[3] = {P.c, J.b ? P.b : nullptr, nullptr};
+            double* dso[3] = {J.c, J.b, nullptr};
+            rc = launch_copy_segments(d_segs + segout, nb, so, dso, J.st);
+        } else {
+            std::vector<double> hout((size_t)(2 * nb * Kr));
+            if (hipMemcpyAsync(hout.data(), P.c, sizeof(double) * hout.size(),
+                               hipMemcpyDeviceToHost, J.st) != hipSuccess ||
+                hipStreamSynchronize(J.st) != hipSuccess) {
                 set_error("copy of the FP64 re-evaluation failed");
                 rc = NCF_E_DEVICE;
-                break;
+            } else {
+                for (int64_t i = 0; i < nb; ++i) {
+                    const int64_t p = probs[(size_t)i];
+                    std::memcpy(J.c + p * K, hout.data() + i * Kr, sizeof(double) * K);
+                    if (J.b)
+                        std::memcpy(J.b + p * K, hout.data() + (nb + i) * Kr, sizeof(double) * K);
+                }
             }
         }
     }
-    (void)hipStreamSynchronize(J.st);
+    if (hipStreamSynchronize(J.st) != hipSuccess && rc == NCF_OK) {
+        set_error("FP64 re-evaluation failed on the device");
+        rc = NCF_E_DEVICE;
+    }
     free_resources(R2);
-    (void)hipFree(dout);
     return rc;
 }
 

@@ -224,6 +224,15 @@ int launch_moments(const MomentsArgs& a, hipStream_t st);
 int launch_standardize(const MomentsArgs& a, hipStream_t st);
 // Fill p[0..n) with alternating +1, -1 (finite values of unit variance).
 int launch_fill_alternating(double* p, int64_t n, hipStream_t st);
+// One segment of a gather or scatter: len values from src + src_off to
+// dst + dst_off.
+struct CopySeg {
+    int64_t src_off, dst_off, len;
+};
+// Copy the segments (device table, nseg entries) of up to three arrays that
+// share them: s[a] -> d[a] for every a whose s[a] is not null.
+int launch_copy_segments(const CopySeg* d_segs, int64_t nseg, const double* const s[3],
+                         double* const d[3], hipStream_t st);
 
 // --------------------------------------------------- replicate statistics
 // Replicate r of a series of n samples: values x + sigma z_r (z_r: R x n,

@@ -396,7 +396,30 @@ k_fill_alternating(double* __restrict__ p, int64_t n) {
     if (i < n) p[i] = (i & 1) ? -1.0 : 1.0;
 }
 
+// One workgroup per segment; up to three arrays share the segment table.
+__global__ void __launch_bounds__(kThreads)
+k_copy_segments(const CopySeg* __restrict__ segs, const double* __restrict__ s0,
+                double* __restrict__ d0, const double* __restrict__ s1, double* __restrict__ d1,
+                const double* __restrict__ s2, double* __restrict__ d2) {
+    const CopySeg g = segs[blockIdx.x];
+    for (int64_t i = threadIdx.x; i < g.len; i += kThreads) {
+        if (s0) d0[g.dst_off + i] = s0[g.src_off + i];
+        if (s1) d1[g.dst_off + i] = s1[g.src_off + i];
+        if (s2) d2[g.dst_off + i] = s2[g.src_off + i];
+    }
+}
+
 }  // namespace
+
+int launch_copy_segments(const CopySeg* d_segs, int64_t nseg, const double* const s[3],
+                         double* const d[3], hipStream_t st) {
+    if (nseg <= 0 || (!s[0] && !s[1] && !s[2])) return NCF_OK;
+    if (nseg > INT32_MAX) return NCF_E_INVALID_ARG;
+    hipLaunchKernelGGL(k_copy_segments, dim3((unsigned)nseg), dim3(kThreads), 0, st, d_segs,
+                       s[0], d[0], s[1], d[1], s[2], d[2]);
+    NCF_CHECK_LAUNCH();
+    return NCF_OK;
+}
 
 int launch_fill_alternating(double* p, int64_t n, hipStream_t st) {
     if (n <= 0) return NCF_OK;
