@@ -1013,7 +1013,8 @@ int run_regular(Job& J, const std::vector<SeriesDesc>& sdesc,
     const int rc = finish_status(J, pstat, h_fstat);
     if (log_level() > 0) {
         int64_t nbad = 0;
-        for (int64_t p = 0; p < J.nprob; ++p) nbad += h_fstat && h_fstat[p] != NCF_OK;
+        for (int64_t p = 0; p < J.nprob; ++p)
+            nbad += J.plan_build ? pstat[p] != NCF_OK : (h_fstat && h_fstat[p] != NCF_OK);
         std::fprintf(stderr,
                      "ncf: %s%s n=%lld K=%lld %s regular route=lattice grids=%d cells=%lld "
                      "failed=%lld rc=%d\n",
@@ -1287,6 +1288,7 @@ class CallRun {
     void init_flags();
     int moments();
     int plan_route();
+    bool weights_fall_back(int64_t p) const;
     void plan_window(WinLaunch& W);
     int check_win(const WinLaunch& W, uint32_t f) const;
     void plan_windows();
@@ -1331,6 +1333,7 @@ class CallRun {
     double maxlag = 0.0;
     std::vector<SpecGeom> geom;
     std::vector<char> have_geom, direct_p;
+    std::vector<char> fb_direct;  // weighted problems sent to the direct sums (every lag falls back)
     bool any_direct = false, spec_b = false, spec_w = false, spec_unw = false;
     double beta = 0.1;
     std::vector<std::pair<double, int>> rows;
@@ -1478,7 +1481,7 @@ int CallRun::moments() {
             S.pw = (need_prefix && weighted) ? ar.take<double>(S.ntot + S.nser) : nullptr;
             S.pz = (need_prefix && weighted) ? ar.take<double>(S.ntot + S.nser) : nullptr;
         }
-        *o_cpart = ar.take<double>(4 * (size_t)nch);
+        *o_cpart = ar.take<double>(kChunkPart * (size_t)nch);
         *o_ctot = ar.take<double>(3 * (size_t)nch);
         *o_stats = ar.take<SeriesStat>(nsd);
         // device lags of a one-shot call: copied next to the statistics by
@@ -1608,6 +1611,34 @@ int CallRun::moments() {
 
 // Route choice (the K* crossover of NCF_AUTO), the sorted lag rows of the
 // window scans and the window flags.
+// Weighted Gaussian problem of the spectral route: would every lag fall back
+// to the direct window sums? The spectral weighted pair sums B serve the lags
+// with B(tau) >= beta B_ref (B_ref: B(0), CCF sqrt(B_xx(0) B_yy(0))). B(0)
+// holds the self-pairs, sum w^2, which weights spread over decades make
+// dominant. With the samples spread evenly over their span T, a sample's
+// neighbours at any lag carry weight sw / T per unit time, so B(tau) is at
+// most about sw_x sw_y h sqrt(2 pi) / T and B(0) is sum w^2 + sw^2 h
+// sqrt(2 pi) / T. The estimate leaves out two factors that lower the tested
+// B(tau) further (the overlap 1 - |tau| / T of the spans, and for the ACF
+// the lag-0 scale min(1, r(0)) that the test applies) and one that raises
+// it (samples clustered in seasons or bursts put more pairs at small lags);
+// measured on light curves with errors over four decades, problems whose
+// estimate lay between a quarter of the threshold and the threshold still
+// sent 94-97 % of their lags to the fallback.
+bool CallRun::weights_fall_back(int64_t p) const {
+    const double beta_p = fp64 ? 1e-2 : 0.1;  // the fallback threshold below
+    const double kint = J.h[p] * 2.5066282746310002;  // integral of the kernel
+    const SeriesStat& a = stat_of(0, p);
+    const SeriesStat& b = stat_of(J.ccf ? 1 : 0, p);
+    const double ta = std::max(a.tmax - a.tmin, 1e-300);
+    const double tb = std::max(b.tmax - b.tmin, 1e-300);
+    const double b0a = a.sw2 + a.sw * a.sw * kint / ta;
+    const double b0b = b.sw2 + b.sw * b.sw * kint / tb;
+    const double bref = std::sqrt(b0a * b0b);
+    const double btau = a.sw * b.sw * kint / std::max(ta, tb);
+    return bref > 0.0 && btau < beta_p * bref;
+}
+
 int CallRun::plan_route() {
     // ------------------------------------------------ phase 2 planning (host)
     K = J.K;
@@ -1634,6 +1665,7 @@ int CallRun::plan_route() {
     }
     geom.assign((size_t)J.nprob, SpecGeom{});
     have_geom.assign((size_t)J.nprob, 0);
+    fb_direct.assign((size_t)J.nprob, 0);
     if (spectral && J.opt.method == NCF_AUTO && J.kern == NCF_GAUSSIAN &&
         !(J.opt.flags & NCF_SPECTRAL_ALWAYS)) {
         const double nrows = (double)(J.ccf ? K : K + 1);
@@ -1660,7 +1692,8 @@ int CallRun::plan_route() {
             const double dens = (n0 - 1.0) / std::max(s0.tmax - s0.tmin, 1e-300);
             const double pts = dens * 12.0 * J.h[p];
             const double windows = n1 * nrows + (J.ccf ? n0 + n1 : 0.0);
-            direct_s += windows * (8.0 + 8.0 * pts) / rate;
+            const double dcost = windows * (8.0 + 8.0 * pts) / rate;
+            direct_s += dcost;
             const SpecGeom& g = geom[p];
             if (grc[p] != NCF_OK) {
                 clear_error();
@@ -1668,6 +1701,11 @@ int CallRun::plan_route() {
                 break;
             }
             have_geom[p] = 1;
+            if (weighted && weights_fall_back(p)) {
+                fb_direct[p] = 1;
+                spec_s += dcost;
+                continue;
+            }
             spec_s += (g.P > 0 ? 7.0 : 11.0) * (double)g.N * csz_b * (J.ccf ? 2.0 : 1.0) / 4e12 +
                       (n0 + (J.ccf ? n1 : 0.0)) * 12.0 / 4e12;
         }
@@ -1677,7 +1715,7 @@ int CallRun::plan_route() {
     direct_p.assign((size_t)J.nprob, 0);
     any_direct = false;
     for (int64_t p = 0; p < J.nprob; ++p) {
-        direct_p[p] = (!spectral || short_p[p]) ? 1 : 0;
+        direct_p[p] = (!spectral || short_p[p] || fb_direct[p]) ? 1 : 0;
         any_direct |= direct_p[p] != 0;
     }
     // Gaussian default: numerator and pair count both by the spectral route
@@ -2634,10 +2672,12 @@ int CallRun::done() {
 
 // One NCF_LOG line for a finished call.
 void CallRun::log_call(int rc) const {
+    // a plan build reports the statuses of the host checks (its device pass
+    // ran on placeholder values)
     int64_t ndirect = 0, nbad = 0;
     for (int64_t p = 0; p < J.nprob; ++p) {
         ndirect += direct_p.empty() ? 0 : direct_p[p];
-        nbad += h_fstat && h_fstat[p] != NCF_OK;
+        nbad += J.plan_build ? pstat[p] != NCF_OK : (h_fstat && h_fstat[p] != NCF_OK);
     }
     const double ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start)

@@ -188,6 +188,7 @@ constexpr double kPromoteScale = 0.1;
 // against the lag-0 pair sums, is far above its usual size.
 constexpr int64_t kMinSpectralSamples = 32;
 constexpr int64_t kMomentChunk = 2048;  // samples per moments chunk (8 per thread)
+constexpr int kChunkPart = 5;           // partial moments per chunk (MomentsArgs)
 
 struct Chunk {
     int64_t begin, end;  // sample range [begin, end) within the series
@@ -197,6 +198,7 @@ struct Chunk {
 
 struct SeriesStat {
     double mean, sd, sw;  // weighted mean, sd (ddof 0), sum of weights
+    double sw2;           // sum of squared weights
     double tmin, tmax;
     int32_t status;       // NCF_OK or a negative NCF_E_* code
     int32_t pad;
@@ -206,7 +208,7 @@ struct MomentsArgs {
     const SeriesDesc* series;
     const Chunk* chunks;
     int32_t nseries, nchunks;
-    double* chunk_part;      // 4 doubles per chunk: sw, mean, M2, flags
+    double* chunk_part;      // kChunkPart doubles per chunk: sw, mean, M2, flags, sum w^2
     double* chunk_tot;       // 3 doubles per chunk (v, w, nonzero-weight count): chunk totals,
                              // then (chunk-offset pass) the exclusive sums of the preceding
                              // chunks of the series, which readers of the chunk-local prefix

@@ -64,7 +64,7 @@ k_chunk_moments(MomentsArgs a) {
     // the thread's samples stay in registers for the second pass
     double xs[kPer], ws[kPer];
     int bad = 0, unsorted = 0;
-    double acc[2] = {0.0, 0.0};  // sum w, sum w x
+    double acc[3] = {0.0, 0.0, 0.0};  // sum w, sum w x, sum w^2
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
         const int64_t i = ch.begin + tid + (int64_t)k * kThreads;
@@ -89,13 +89,14 @@ k_chunk_moments(MomentsArgs a) {
             ws[k] = wi;
             acc[0] += wi;
             acc[1] += wi * xi;
+            acc[2] += wi * wi;
         }
     }
     int fl = bad | (unsorted << 1);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) fl |= __shfl_xor(fl, off);
     if ((tid & 63) == 0) shf[tid >> 6] = fl;
-    block_sum<2>(acc, sh);
+    block_sum<3>(acc, sh);
     const double mean = acc[1] / acc[0];
     double m2[1] = {0.0};
 #pragma unroll
@@ -107,11 +108,12 @@ k_chunk_moments(MomentsArgs a) {
     if (tid == 0) {
         int f = 0;
         for (int w = 0; w < kWaves; ++w) f |= shf[w];
-        double* p = a.chunk_part + 4 * (int64_t)blockIdx.x;
+        double* p = a.chunk_part + kChunkPart * (int64_t)blockIdx.x;
         p[0] = acc[0];
         p[1] = mean;
         p[2] = m2[0];
         p[3] = (double)f;
+        p[4] = acc[2];
     }
 }
 
@@ -137,7 +139,7 @@ __device__ __forceinline__ void merge_moments(double& sw, double& mean, double& 
 // wave (shuffles) and over the waves in order.
 __global__ void __launch_bounds__(kThreads)
 k_series_finalize(MomentsArgs a) {
-    __shared__ double sh[3][kWaves];
+    __shared__ double sh[4][kWaves];
     __shared__ int shf[kWaves];
     const int s = blockIdx.x;
     const int tid = threadIdx.x;
@@ -145,29 +147,32 @@ k_series_finalize(MomentsArgs a) {
         for (int64_t i = tid; i < a.nlag; i += kThreads) gbl(a.lag_dst)[i] = gbl(a.lag_src)[i];
     const int lane = tid & 63, wave = tid >> 6;
     const SeriesDesc sd = a.series[s];
-    double sw = 0.0, mean = 0.0, m2 = 0.0;
+    double sw = 0.0, mean = 0.0, m2 = 0.0, sw2 = 0.0;
     int fl = 0;
     const int per = (sd.nchunk + kThreads - 1) / kThreads;
     const int c0 = tid * per, c1 = min(sd.nchunk, c0 + per);
     for (int c = c0; c < c1; ++c) {
-        const double* p = a.chunk_part + 4 * (int64_t)(sd.chunk0 + c);
+        const double* p = a.chunk_part + kChunkPart * (int64_t)(sd.chunk0 + c);
         merge_moments(sw, mean, m2, p[0], p[1], p[2]);
         fl |= (int)p[3];
+        sw2 += p[4];
     }
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
         const double w1 = __shfl_down(sw, off), m1 = __shfl_down(mean, off),
-                     q1 = __shfl_down(m2, off);
+                     q1 = __shfl_down(m2, off), s1 = __shfl_down(sw2, off);
         const int f1 = __shfl_down(fl, off);
         if ((lane & (2 * off - 1)) == 0) {  // left operand of this level
             merge_moments(sw, mean, m2, w1, m1, q1);
             fl |= f1;
+            sw2 += s1;
         }
     }
     if (lane == 0) {
         sh[0][wave] = sw;
         sh[1][wave] = mean;
         sh[2][wave] = m2;
+        sh[3][wave] = sw2;
         shf[wave] = fl;
     }
     __syncthreads();
@@ -175,10 +180,12 @@ k_series_finalize(MomentsArgs a) {
     sw = sh[0][0];
     mean = sh[1][0];
     m2 = sh[2][0];
+    sw2 = sh[3][0];
     fl = shf[0];
     for (int w = 1; w < kWaves; ++w) {
         merge_moments(sw, mean, m2, sh[0][w], sh[1][w], sh[2][w]);
         fl |= shf[w];
+        sw2 += sh[3][w];
     }
     SeriesStat st;
     st.status = NCF_OK;
@@ -187,6 +194,7 @@ k_series_finalize(MomentsArgs a) {
     st.mean = mean;
     st.sd = sdv;
     st.sw = sw;
+    st.sw2 = sw2;
     st.tmin = sd.t[0];
     st.tmax = sd.t[sd.n - 1];
     if (sd.n < 2 || (fl & 1))

@@ -40,3 +40,37 @@ def test_large_ccf_takes_the_spectral_route():
     st, oc, ob, on = O.ccf(d["t"], d["x"], d["s"], d["y"], d["lags"][::20], "gaussian", d["h"])
     c, b, n, _ = ncf.ccf(d["t"], d["x"], d["s"], d["y"], d["lags"][::20], "gaussian", d["h"])
     assert np.max(np.abs(c - oc)) <= 1e-5
+
+
+def _batch_route(d, err, **kw):
+    plan = ncf.plan_acf(d["offs"], d["t"], d["lags"], "gaussian", d["h"], err=err, **kw)
+    try:
+        return plan.info()["spectral_grids"]
+    finally:
+        plan.close()
+
+
+def test_weights_over_decades_take_the_window_sums():
+    # errors 0.01 x 10^(N(0, 0.5)): weights 1/err^2 over about four decades,
+    # whose self-pairs dominate the weighted lag-0 sum B(0); B(tau) < 0.1
+    # B(0) at every lag sends the spectral B of such curves to the direct
+    # window sums, so they take them from the start. Narrow errors (a factor
+    # 4 in weight) keep the spectral route.
+    d = synth.c4(seed=41, n_series=32, nmin=2000, nmax=12_000, K=256, with_err=True)
+    nser = d["offs"].size - 1
+    wide = d["err_values"]
+    narrow = np.random.default_rng(42).uniform(0.5, 1.0, wide.size)
+    print(f"case: c4 batch of {nser} curves, K=256, wide and narrow error spreads", flush=True)
+    assert _batch_route(d, narrow) == nser
+    assert _batch_route(d, wide) == 0
+    assert _batch_route(d, wide, spectral_always=True) == nser
+    c, b, n, st, rc = ncf.acf_batch(d["offs"], d["t"], d["x"], d["lags"], "gaussian", d["h"],
+                                    err=wide)
+    assert rc == 0
+    for i in (0, nser // 2, nser - 1):
+        a, e = d["offs"][i], d["offs"][i + 1]
+        ost, oc, ob, _ = O.acf(d["t"][a:e], d["x"][a:e], d["lags"], "gaussian", d["h"][i],
+                               err=wide[a:e])
+        assert ost == st[i] == 0
+        assert np.max(np.abs(c[i] - oc)) <= 1e-5, f"curve {i}"
+        np.testing.assert_allclose(b[i], ob, rtol=1e-6, err_msg=f"curve {i}")
