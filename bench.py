@@ -362,8 +362,10 @@ def main():
             cal_dst.copy_(cal_src)
         torch.cuda.synchronize()
         del cal_src, cal_dst
-    copy_bw = measure_copy_bandwidth(torch)
-    log(f"[bench] device copy: {copy_bw['GB_per_s']:.0f} GB/s (read + write)")
+    # a counter-calibration run holds only the known-size copies above
+    copy_bw = None if args.calibrate else measure_copy_bandwidth(torch)
+    if copy_bw:
+        log(f"[bench] device copy: {copy_bw['GB_per_s']:.0f} GB/s (read + write)")
     log(f"[bench] generating workload {args.workload}")
     host = make_workload(args.workload)
     devs = [to_dev(d) for d in host]
