@@ -189,6 +189,7 @@ constexpr double kPromoteScale = 0.1;
 constexpr int64_t kMinSpectralSamples = 32;
 constexpr int64_t kMomentChunk = 2048;  // samples per moments chunk (8 per thread)
 constexpr int kChunkPart = 5;           // partial moments per chunk (MomentsArgs)
+constexpr int64_t kQueueAutoItems = 100000;  // Gaussian window launches this large pull items from a queue
 
 struct Chunk {
     int64_t begin, end;  // sample range [begin, end) within the series
