@@ -125,7 +125,9 @@ typedef enum { NCF_AUTO = 0, NCF_SPECTRAL = 1, NCF_DIRECT = 2 } ncf_method_t;
 #define NCF_PLAN_NO_GRAPH 0x2u
 /* Scheduling: run the window scans as persistent workgroups that pull
  * (series, outer-sample tile, lag tile) work items from a device queue,
- * instead of one workgroup per item. Results are identical. */
+ * instead of one workgroup per item. Results are identical. Gaussian
+ * window scans of 100,000 items or more use the queue without the flag
+ * (except in the allocation-free entry point). */
 #define NCF_WINDOW_QUEUE 0x4u
 /* Plans only: build and time candidate scheduling settings (minimum grid
  * oversampling, FFT radix split and strided-pass tile, window tile scale,
